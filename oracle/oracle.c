@@ -1,0 +1,289 @@
+/* CPU oracle for batch-dynamic SpGEMM -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain C, built with -O2 -ffp-contract=off -fno-fast-math so that every
+ * fp64 product and sum is one IEEE-754 rounding, with no fused multiply-add.
+ * Loaded only by the tests, the smoke check and the benchmark's CPU-baseline
+ * leg; it shares no code with the GPU library.
+ *
+ * Readings of the paper that this file fixes (Section numbers of arXiv
+ * 2202.08808):
+ *  - absent entries equal the semiring's additive neutral element and present
+ *    entries stay present whatever their value (Section 3);
+ *  - SET on a present entry overwrites it, on an absent one inserts it (the
+ *    "merge" procedure, Section 4.1); DELETE removes a present entry and is a
+ *    no-op on an absent one ("mask", Section 4.1); ADD folds x into a present
+ *    entry with the semiring's addition and inserts x where absent (algebraic
+ *    update, Section 4.1 and Section 5);
+ *  - a batch is the sequence of its updates applied in batch order, so
+ *    repeated keys resolve last-one-wins with later ADDs folded on top;
+ *  - a row is "changed" when its stored set of (column, value bits) differs;
+ *  - C' = A' B' over the semiring (Section 5, problem statement): c_ij is
+ *    present iff some k has both a_ik and b_kj present, and its value is the
+ *    semiring sum over those k, taken in ascending k, of a_ik (x) b_kj;
+ *  - (min,+) on fp32: (x) is the rounded fp32 sum; (+) is the minimum with
+ *    -0 ordered below +0; (+,x) on int64 wraps around (two's complement).
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int orc_value_size(int semiring) {
+  switch (semiring) {
+    case ORC_PLUS_TIMES_I64: return 8;
+    case ORC_MIN_PLUS_F32: return 4;
+    case ORC_PLUS_TIMES_F64: return 8;
+    default: return 0;
+  }
+}
+
+/* ---- semiring arithmetic (Section 3: semirings, neutral element) ---- */
+
+static float mp_add(float a, float b) {
+  if (a < b) return a;
+  if (b < a) return b;
+  return signbit(a) ? a : b; /* equal: prefer -0 over +0, else either */
+}
+
+/* dst <- x (+) y */
+static void sr_add(int sr, void* dst, const void* x, const void* y) {
+  if (sr == ORC_PLUS_TIMES_I64) {
+    uint64_t a, b, r;
+    memcpy(&a, x, 8); memcpy(&b, y, 8);
+    r = a + b;
+    memcpy(dst, &r, 8);
+  } else if (sr == ORC_MIN_PLUS_F32) {
+    float a, b, r;
+    memcpy(&a, x, 4); memcpy(&b, y, 4);
+    r = mp_add(a, b);
+    memcpy(dst, &r, 4);
+  } else {
+    double a, b, r;
+    memcpy(&a, x, 8); memcpy(&b, y, 8);
+    r = a + b;
+    memcpy(dst, &r, 8);
+  }
+}
+
+/* dst <- x (x) y */
+static void sr_mul(int sr, void* dst, const void* x, const void* y) {
+  if (sr == ORC_PLUS_TIMES_I64) {
+    uint64_t a, b, r;
+    memcpy(&a, x, 8); memcpy(&b, y, 8);
+    r = a * b;
+    memcpy(dst, &r, 8);
+  } else if (sr == ORC_MIN_PLUS_F32) {
+    float a, b, r;
+    memcpy(&a, x, 4); memcpy(&b, y, 4);
+    r = a + b;
+    memcpy(dst, &r, 4);
+  } else {
+    double a, b, r;
+    memcpy(&a, x, 8); memcpy(&b, y, 8);
+    r = a * b;
+    memcpy(dst, &r, 8);
+  }
+}
+
+/* ---- updates (Section 4.1) ---- */
+
+/* first position in cols[0..len) whose column is >= c */
+static int64_t lower_bound(const int32_t* cols, int64_t len, int32_t c) {
+  int64_t lo = 0, hi = len;
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (cols[mid] < c) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+int64_t orc_apply(int sr, int32_t nrows, int32_t ncols,
+                  const int64_t* rp, const int32_t* ci, const void* v,
+                  const int32_t* brow, const int32_t* bcol, const void* bval,
+                  const uint8_t* bop, int64_t b,
+                  int64_t* orp, int32_t* oci, void* ov, uint8_t* changed) {
+  const int vs = orc_value_size(sr);
+  if (vs == 0 || nrows < 0 || ncols < 0 || b < 0) return -1;
+  for (int64_t t = 0; t < b; ++t) {
+    if (brow[t] < 0 || brow[t] >= nrows || bcol[t] < 0 || bcol[t] >= ncols) return -1;
+    if (bop[t] > ORC_OP_ADD) return -1;
+  }
+  /* The updates of one row, in batch order: rows do not interact, so applying
+   * each row's updates in their batch order is the sequential application. */
+  int64_t* first = (int64_t*)calloc((size_t)nrows + 1, sizeof(int64_t));
+  int64_t* order = (int64_t*)malloc(sizeof(int64_t) * (size_t)(b > 0 ? b : 1));
+  for (int64_t t = 0; t < b; ++t) first[brow[t] + 1]++;
+  for (int32_t i = 0; i < nrows; ++i) first[i + 1] += first[i];
+  {
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)nrows + 1));
+    memcpy(fill, first, sizeof(int64_t) * ((size_t)nrows + 1));
+    for (int64_t t = 0; t < b; ++t) order[fill[brow[t]]++] = t;
+    free(fill);
+  }
+  const char* vin = (const char*)v;
+  const char* bv = (const char*)bval;
+  char* vout = (char*)ov;
+  int64_t maxrow = 0;
+  for (int32_t i = 0; i < nrows; ++i) {
+    int64_t need = rp[i + 1] - rp[i] + (first[i + 1] - first[i]);
+    if (need > maxrow) maxrow = need;
+  }
+  int32_t* wc = (int32_t*)malloc(sizeof(int32_t) * (size_t)(maxrow > 0 ? maxrow : 1));
+  char* wv = (char*)malloc((size_t)vs * (size_t)(maxrow > 0 ? maxrow : 1));
+  int64_t out = 0;
+  orp[0] = 0;
+  for (int32_t i = 0; i < nrows; ++i) {
+    int64_t len0 = rp[i + 1] - rp[i];
+    int64_t len = len0;
+    memcpy(wc, ci + rp[i], sizeof(int32_t) * (size_t)len);
+    memcpy(wv, vin + (size_t)vs * (size_t)rp[i], (size_t)vs * (size_t)len);
+    for (int64_t u = first[i]; u < first[i + 1]; ++u) {
+      int64_t t = order[u];
+      int32_t c = bcol[t];
+      const char* x = bv + (size_t)vs * (size_t)t;
+      int64_t pos = lower_bound(wc, len, c);
+      int present = pos < len && wc[pos] == c;
+      if (bop[t] == ORC_OP_DELETE) {
+        if (present) {
+          memmove(wc + pos, wc + pos + 1, sizeof(int32_t) * (size_t)(len - pos - 1));
+          memmove(wv + (size_t)vs * pos, wv + (size_t)vs * (pos + 1), (size_t)vs * (size_t)(len - pos - 1));
+          --len;
+        }
+      } else if (present) {
+        if (bop[t] == ORC_OP_SET) memcpy(wv + (size_t)vs * pos, x, (size_t)vs);
+        else sr_add(sr, wv + (size_t)vs * pos, wv + (size_t)vs * pos, x);
+      } else { /* SET or ADD on an absent entry inserts x */
+        memmove(wc + pos + 1, wc + pos, sizeof(int32_t) * (size_t)(len - pos));
+        memmove(wv + (size_t)vs * (pos + 1), wv + (size_t)vs * pos, (size_t)vs * (size_t)(len - pos));
+        wc[pos] = c;
+        memcpy(wv + (size_t)vs * pos, x, (size_t)vs);
+        ++len;
+      }
+    }
+    if (changed) {
+      int diff = len != len0;
+      if (!diff) diff = memcmp(wc, ci + rp[i], sizeof(int32_t) * (size_t)len) != 0;
+      if (!diff) diff = memcmp(wv, vin + (size_t)vs * (size_t)rp[i], (size_t)vs * (size_t)len) != 0;
+      changed[i] = (uint8_t)diff;
+    }
+    memcpy(oci + out, wc, sizeof(int32_t) * (size_t)len);
+    memcpy(vout + (size_t)vs * (size_t)out, wv, (size_t)vs * (size_t)len);
+    out += len;
+    orp[i + 1] = out;
+  }
+  free(wc); free(wv); free(order); free(first);
+  return out;
+}
+
+/* ---- Gustavson product (Section 5 problem statement; Section 6.1) ---- */
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+typedef struct {
+  int64_t* mark;   /* mark[j] == q  <=>  column j already touched for output row q */
+  char* acc;       /* dense accumulator, one value per column */
+  int32_t* touched;
+} spa_t;
+
+static int spa_init(spa_t* s, int32_t ncols, int vs) {
+  size_t n = (size_t)(ncols > 0 ? ncols : 1);
+  s->mark = (int64_t*)malloc(sizeof(int64_t) * n);
+  s->acc = (char*)malloc((size_t)vs * n);
+  s->touched = (int32_t*)malloc(sizeof(int32_t) * n);
+  if (!s->mark || !s->acc || !s->touched) return -1;
+  for (size_t j = 0; j < n; ++j) s->mark[j] = -1;
+  return 0;
+}
+
+static void spa_free(spa_t* s) { free(s->mark); free(s->acc); free(s->touched); }
+
+/* Accumulate output row q (= row i of A times B) into the SPA; returns the
+ * number of touched columns, sorted ascending in s->touched. */
+static int64_t gustavson_row(int sr, int vs, int64_t q, int32_t i,
+                             const int64_t* arp, const int32_t* aci, const char* av,
+                             const int64_t* brp, const int32_t* bci, const char* bv,
+                             spa_t* s) {
+  int64_t nt = 0;
+  char p[8];
+  for (int64_t ea = arp[i]; ea < arp[i + 1]; ++ea) {     /* ascending k */
+    int32_t k = aci[ea];
+    const char* a = av + (size_t)vs * (size_t)ea;
+    for (int64_t eb = brp[k]; eb < brp[k + 1]; ++eb) {   /* ascending j */
+      int32_t j = bci[eb];
+      char* slot = s->acc + (size_t)vs * (size_t)j;
+      sr_mul(sr, p, a, bv + (size_t)vs * (size_t)eb);
+      if (s->mark[j] != q) {
+        s->mark[j] = q;
+        memcpy(slot, p, (size_t)vs);
+        s->touched[nt++] = j;
+      } else {
+        sr_add(sr, slot, slot, p);
+      }
+    }
+  }
+  qsort(s->touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+  return nt;
+}
+
+int orc_spgemm(int sr, int32_t nrows, int32_t ninner, int32_t ncols,
+               const int64_t* arp, const int32_t* aci, const void* av,
+               const int64_t* brp, const int32_t* bci, const void* bv,
+               const int32_t* rows, int32_t nq,
+               int64_t* crp, int32_t* cci, void* cv, int nthreads) {
+  const int vs = orc_value_size(sr);
+  (void)ninner;
+  if (vs == 0 || nrows < 0 || ncols < 0) return -1;
+  const int64_t nout = rows ? nq : nrows;
+  if (rows)
+    for (int32_t q = 0; q < nq; ++q)
+      if (rows[q] < 0 || rows[q] >= nrows) return -1;
+  const int numeric = (cci != NULL || cv != NULL);
+  int bad = 0;
+#ifdef _OPENMP
+  if (nthreads < 1) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+#endif
+  {
+    spa_t s;
+    if (spa_init(&s, ncols, vs) != 0) {
+#ifdef _OPENMP
+#pragma omp atomic write
+#endif
+      bad = 1;
+    } else {
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 64)
+#endif
+      for (int64_t q = 0; q < nout; ++q) {
+        int32_t i = rows ? rows[q] : (int32_t)q;
+        int64_t nt = gustavson_row(sr, vs, q, i, arp, aci, (const char*)av, brp, bci,
+                                   (const char*)bv, &s);
+        if (!numeric) {
+          crp[q + 1] = nt;
+        } else {
+          int64_t o = crp[q];
+          for (int64_t t = 0; t < nt; ++t) {
+            int32_t j = s.touched[t];
+            cci[o + t] = j;
+            memcpy((char*)cv + (size_t)vs * (size_t)(o + t), s.acc + (size_t)vs * (size_t)j,
+                   (size_t)vs);
+          }
+        }
+      }
+    }
+    spa_free(&s);
+  }
+  if (bad) return -1;
+  if (!numeric) {
+    crp[0] = 0;
+    for (int64_t q = 0; q < nout; ++q) crp[q + 1] += crp[q];
+  }
+  return 0;
+}
