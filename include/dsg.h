@@ -1,0 +1,223 @@
+/* dsg -- batch-dynamic sparse matrix-matrix multiplication on AMD MI355X (gfx950).
+ *
+ * The library keeps the product C = A B of sparse matrices current while
+ * batches of entry insertions, deletions and value changes are applied to A
+ * and B, recomputing only the rows of C that the changes can reach.  It
+ * follows the problem statement of "Fast Dynamic Updates and Dynamic SpGEMM
+ * on MPI-Distributed Graphs" (van der Grinten et al., arXiv 2202.08808):
+ *   - Section 3:   matrices over a semiring; an absent entry equals the
+ *                  semiring's additive neutral element; a present entry is a
+ *                  structural non-zero whatever its value;
+ *   - Section 4.1: updates are (i, j, x) tuples applied by "merge"
+ *                  (insert/overwrite), "mask" (delete) or algebraic addition;
+ *   - Section 5:   given C = A B and the updated operands A', B', compute
+ *                  C' = A' B'; C' can differ from C only in rows holding a
+ *                  non-zero of C* = A* B' + A B* (Eq. 1 and the discussion of
+ *                  general updates), where A*, B* mark the changed entries.
+ *
+ * All numeric work runs in HIP kernels on one GPU.  Objects live in device
+ * memory (HBM).  Every call is ordered on the context's HIP stream.
+ *
+ * Conventions
+ *   Status:     every function returns a dsg_status; no exceptions cross the
+ *               boundary.  On failure no object is modified (arguments are
+ *               validated before any mutation) and dsg_last_error() holds a
+ *               message.
+ *   Ownership:  input arrays are borrowed for the duration of the call.  The
+ *               library owns matrices and products until *_destroy.  Views
+ *               (dsg_rows) point into library memory and stay valid until the
+ *               next call that mutates that product.
+ *   Host/device pointers: input arrays are host pointers unless the call's
+ *               flags contain DSG_INPUT_DEVICE, in which case they are device
+ *               pointers readable on the context's device.
+ *   Threading:  a context and its objects may be used by one host thread at a
+ *               time.
+ *   Indices:    int32 row and column indices, 0-based; int64 offsets.
+ */
+#ifndef DSG_H
+#define DSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSG_OK = 0,
+  DSG_E_ARG = 1,         /* null pointer, bad size, bad op code or flag */
+  DSG_E_RANGE = 2,       /* an index outside [0, nrows) x [0, ncols) */
+  DSG_E_OOM = 3,         /* device allocation failed or the memory budget is exceeded */
+  DSG_E_DEVICE = 4,      /* a HIP call failed */
+  DSG_E_STATE = 5,       /* semiring/shape mismatch, or object still referenced */
+  DSG_E_UNSUPPORTED = 6
+} dsg_status;
+
+/* Semirings (Section 3).  The semiring fixes the value type:
+ *   DSG_PLUS_TIMES_I64: (+, x) over int64, two's-complement wrap-around;
+ *   DSG_MIN_PLUS_F32:   (min, +) over fp32, +inf neutral, -0 ordered below +0;
+ *   DSG_PLUS_TIMES_F64: (+, x) over fp64, each product and sum rounded once
+ *                       (no fused multiply-add). */
+typedef enum {
+  DSG_PLUS_TIMES_I64 = 0,
+  DSG_MIN_PLUS_F32 = 1,
+  DSG_PLUS_TIMES_F64 = 2
+} dsg_semiring;
+
+/* Update operations (Section 4.1). */
+typedef enum {
+  DSG_OP_SET = 0,     /* "merge": overwrite if present, else insert */
+  DSG_OP_DELETE = 1,  /* "mask": remove if present, else no-op */
+  DSG_OP_ADD = 2      /* algebraic: a <- a (+) x if present, else insert x */
+} dsg_op;
+
+/* flags */
+#define DSG_INPUT_DEVICE 0x1u     /* input arrays are device pointers */
+#define DSG_SYNC 0x2u             /* return only after the device work has finished */
+#define DSG_REPORT_AFFECTED 0x4u  /* dsg_prod_update: report every recomputed row, skip the comparison with the old row */
+
+typedef struct dsg_ctx dsg_ctx;
+typedef struct dsg_mat dsg_mat;
+typedef struct dsg_prod dsg_prod;
+
+/* A set of rows of a product, as device views into the product's storage.
+ * Row rows[q] has row_len[rows[q]] entries at positions
+ * row_off[rows[q]] .. +row_len[rows[q]]-1 of col[] and val[] (val holds the
+ * semiring's value type).  Entries inside a row are in no particular order.
+ * rows[] is ascending.  All pointers are device pointers. */
+typedef struct {
+  int32_t n;
+  const int32_t* rows;
+  const int64_t* row_off;
+  const int32_t* row_len;
+  const int32_t* col;
+  const void* val;
+} dsg_rows;
+
+/* ---- context ---- */
+
+/* Create a context on HIP device `device`.  hip_stream is a hipStream_t to
+ * order all work on (NULL: the library creates its own).  mem_budget caps the
+ * device bytes the context may hold (0: no cap); exceeding it gives
+ * DSG_E_OOM. */
+dsg_status dsg_ctx_create(int device, void* hip_stream, size_t mem_budget, dsg_ctx** out);
+/* Destroy a context.  DSG_E_STATE while it still owns matrices or products. */
+dsg_status dsg_ctx_destroy(dsg_ctx* ctx);
+/* Message describing the last failure on this context (never NULL). */
+const char* dsg_last_error(const dsg_ctx* ctx);
+/* Block until all work queued on the context's stream has finished. */
+dsg_status dsg_ctx_synchronize(dsg_ctx* ctx);
+/* Device bytes currently held by the context. */
+dsg_status dsg_ctx_memory(const dsg_ctx* ctx, size_t* bytes);
+/* Turn per-kernel timing with HIP events on (1) or off (0); turning it on
+ * clears the record.  dsg_ctx_timing_report writes a JSON object
+ * {"kernels": {name: {"launches": n, "ms": total, "bytes": algorithmic
+ * bytes}}} into buf (NUL-terminated, truncated to cap) after synchronising. */
+dsg_status dsg_ctx_set_timing(dsg_ctx* ctx, int on);
+dsg_status dsg_ctx_timing_report(dsg_ctx* ctx, char* buf, size_t cap);
+
+/* Row-kernel tuning: output-row-size thresholds of the accumulator bins.
+ * Results never depend on these settings. */
+typedef struct {
+  int32_t group_ub[8];     /* bin b (lane-group hash in LDS) takes rows with ub <= group_ub[b];
+                              ascending, each at most the bin's capacity (32<<b); 0 disables bin b */
+  int32_t dense_max_passes;/* rows above the group bins use the chunked dense LDS accumulator when
+                              it needs at most this many column passes, else a global-memory hash */
+  int32_t force_bin;       /* -1: automatic; 0..7 group bin; 8 dense; 9 global hash (for tests;
+                              a group bin is only used for rows that fit it) */
+} dsg_tuning;
+dsg_status dsg_ctx_get_tuning(const dsg_ctx* ctx, dsg_tuning* t);
+dsg_status dsg_ctx_set_tuning(dsg_ctx* ctx, const dsg_tuning* t);
+
+/* ---- dynamic matrices (Section 4: dynamic storage with O(1) updates) ---- */
+
+/* Create an nrows x ncols dynamic matrix from CSR arrays (row_ptr[nrows+1],
+ * col[nnz], val[nnz] of the semiring's value type), each row free of
+ * duplicate columns, in any column order.  row_ptr == NULL creates an empty
+ * matrix.  flags: DSG_INPUT_DEVICE.  Errors: DSG_E_ARG (sizes, duplicates,
+ * non-monotone row_ptr), DSG_E_RANGE (column index), DSG_E_OOM. */
+dsg_status dsg_mat_create(dsg_ctx* ctx, int32_t nrows, int32_t ncols, dsg_semiring sr,
+                          const int64_t* row_ptr, const int32_t* col, const void* val,
+                          uint32_t flags, dsg_mat** out);
+
+/* Apply a batch of n updates (Section 4.1) with the semantics of applying
+ * them one after the other in batch order: for repeated (i, j) the last
+ * SET/DELETE wins and later ADDs fold on top.  rows/cols/vals/ops are arrays
+ * of n entries (vals of the value type; ignored for DELETE).  Rows whose
+ * stored content changes are logged for the next dsg_prod_update of every
+ * product using the matrix.  flags: DSG_INPUT_DEVICE, DSG_SYNC.
+ * Errors (nothing applied): DSG_E_ARG (bad op), DSG_E_RANGE (index),
+ * DSG_E_OOM. */
+dsg_status dsg_mat_apply(dsg_mat* m, const int32_t* rows, const int32_t* cols, const void* vals,
+                         const uint8_t* ops, int64_t n, uint32_t flags);
+
+dsg_status dsg_mat_nnz(dsg_mat* m, int64_t* nnz);
+dsg_status dsg_mat_shape(const dsg_mat* m, int32_t* nrows, int32_t* ncols, dsg_semiring* sr);
+
+/* Copy the matrix to host CSR arrays in canonical form (rows sorted by
+ * column).  row_ptr has nrows+1 entries; col/val have room for cap entries.
+ * *nnz_out receives nnz; with col == NULL only *nnz_out (and row_ptr if not
+ * NULL) is written.  DSG_E_ARG if cap < nnz. */
+dsg_status dsg_mat_export(dsg_mat* m, int64_t* row_ptr, int32_t* col, void* val, int64_t cap,
+                          int64_t* nnz_out);
+
+/* Destroy a matrix.  DSG_E_STATE while a product uses it. */
+dsg_status dsg_mat_destroy(dsg_mat* m);
+
+/* ---- products (Section 5) ---- */
+
+/* Create the product C = A B (B may be A) and compute it from scratch with
+ * the row kernels.  DSG_E_STATE on semiring mismatch or ncols(A) != nrows(B).
+ * The product keeps a structure-only transpose index of A current. */
+dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod** out);
+
+/* Recompute every row of C from the current A and B (the static baseline),
+ * consuming the pending changes.  flags: DSG_SYNC. */
+dsg_status dsg_prod_recompute_static(dsg_prod* p, uint32_t flags);
+
+/* Dynamic multiply: bring C up to date with all changes applied to A and B
+ * since the previous update, recomputing only the affected rows: the changed
+ * rows of A and every row i with A'[i,k] present for a changed row k of B.
+ * *changed receives the rows whose stored content differs from before the
+ * call (with DSG_REPORT_AFFECTED: every recomputed row).  Synchronises with
+ * the device to learn the row count. */
+dsg_status dsg_prod_update(dsg_prod* p, uint32_t flags, dsg_rows* changed);
+
+/* Views of nq rows of C (rows: host int32 array, or device with
+ * DSG_INPUT_DEVICE; any order, repeats allowed; out->rows lists them as
+ * given).  DSG_E_RANGE for a bad row. */
+dsg_status dsg_prod_rows(dsg_prod* p, const int32_t* rows, int32_t nq, uint32_t flags,
+                         dsg_rows* out);
+
+/* Copy the rows of a view (from dsg_prod_update or dsg_prod_rows on this
+ * product, still valid) to host CSR arrays in view order, each row sorted by
+ * column: row_ptr[v->n + 1], col/val with room for cap entries.  With col ==
+ * NULL only *nnz_out and row_ptr are written.  DSG_E_ARG if cap < nnz. */
+dsg_status dsg_rows_export(dsg_prod* p, const dsg_rows* v, int64_t* row_ptr, int32_t* col, void* val,
+                           int64_t cap, int64_t* nnz_out);
+
+dsg_status dsg_prod_nnz(dsg_prod* p, int64_t* nnz);
+/* Canonical host CSR of C, as dsg_mat_export. */
+dsg_status dsg_prod_export(dsg_prod* p, int64_t* row_ptr, int32_t* col, void* val, int64_t cap,
+                           int64_t* nnz_out);
+
+/* Statistics of the last dsg_prod_update / recompute. */
+typedef struct {
+  int64_t affected_rows;
+  int64_t changed_rows;
+  int64_t a_entries;    /* sum over recomputed rows of nnz(A'[i,:]) */
+  int64_t flops;        /* sum of semiring multiplications */
+  int64_t nnz_new;      /* entries of the recomputed rows after the update */
+  int64_t nnz_old;      /* entries of those rows before it */
+  int64_t bin_rows[10]; /* rows per accumulator bin (8 group bins, dense, global hash) */
+  int64_t bin_flops[10];
+} dsg_update_stats;
+dsg_status dsg_prod_stats(const dsg_prod* p, dsg_update_stats* s);
+
+dsg_status dsg_prod_destroy(dsg_prod* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,703 @@
+// C ABI of the dsg library: argument checks, host/device marshalling, error
+// mapping.  All numeric work happens in the HIP kernels of the other files.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+
+#include "internal.h"
+
+struct dsg_ctx {
+  Ctx c;
+};
+struct dsg_mat {
+  DMat* m;
+  dsg_ctx* owner;
+  bool alive;
+};
+struct dsg_prod {
+  DProd* p;
+  dsg_ctx* owner;
+  dsg_mat* A;
+  dsg_mat* B;
+};
+
+// ---------------------------------------------------------------------------
+// context services used by the rest of the library
+// ---------------------------------------------------------------------------
+
+void* ctx_alloc(Ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 1;
+  if (c->budget && c->held + bytes > c->budget)
+    throw DsgError{DSG_E_OOM, "memory budget exceeded (" + std::to_string(c->held + bytes) + " > " +
+                                  std::to_string(c->budget) + " bytes)"};
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw DsgError{DSG_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  c->held += bytes;
+  return p;
+}
+
+void ctx_free(Ctx* c, void* p, size_t bytes) {
+  if (!p) return;
+  if (bytes == 0) bytes = 1;
+  (void)hipFree(p);
+  c->held -= std::min(c->held, bytes);
+}
+
+static void* grow_scratch(Ctx* c, void*& buf, size_t& have, size_t bytes) {
+  if (bytes <= have) return buf;
+  DSG_HIP(hipStreamSynchronize(c->stream));
+  ctx_free(c, buf, have);
+  buf = nullptr;
+  have = 0;
+  size_t nb = bytes + bytes / 4 + (1 << 20);
+  buf = ctx_alloc(c, nb);
+  have = nb;
+  return buf;
+}
+
+void* ctx_scratch(Ctx* c, size_t bytes) { return grow_scratch(c, c->scratch, c->scratch_bytes, bytes); }
+void* ctx_scratch2(Ctx* c, size_t bytes) { return grow_scratch(c, c->scratch2, c->scratch2_bytes, bytes); }
+
+void ctx_sync(Ctx* c) { DSG_HIP(hipStreamSynchronize(c->stream)); }
+
+void ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop) {
+  KernelTiming t;
+  t.name = name;
+  t.bytes = bytes;
+  DSG_HIP(hipEventCreate(&t.start));
+  DSG_HIP(hipEventCreate(&t.stop));
+  DSG_HIP(hipEventRecord(t.start, c->stream));
+  *start = t.start;
+  *stop = t.stop;
+  c->timings.push_back(t);
+}
+
+void ctx_timing_end(Ctx* c, hipEvent_t stop) { DSG_HIP(hipEventRecord(stop, c->stream)); }
+
+static void clear_timings(Ctx* c) {
+  for (auto& t : c->timings) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  c->timings.clear();
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+
+static thread_local std::string g_create_error;
+
+static dsg_status fail(dsg_ctx* ctx, dsg_status code, const std::string& msg) {
+  if (ctx) ctx->c.last_error = msg;
+  else g_create_error = msg;
+  return code;
+}
+
+#define API_BEGIN(ctxp) \
+  dsg_ctx* ctx__ = (ctxp); \
+  try {
+#define API_END                                                   \
+  }                                                               \
+  catch (const DsgError& e) {                                     \
+    return fail(ctx__, e.code, e.msg);                            \
+  }                                                               \
+  catch (const std::bad_alloc&) {                                 \
+    return fail(ctx__, DSG_E_OOM, "host allocation failed");      \
+  }                                                               \
+  catch (...) {                                                   \
+    return fail(ctx__, DSG_E_DEVICE, "unexpected internal error"); \
+  }                                                               \
+  return DSG_OK;
+
+static int value_size(int sr) { return sr == DSG_MIN_PLUS_F32 ? 4 : 8; }
+
+static void set_device(dsg_ctx* ctx) { DSG_HIP(hipSetDevice(ctx->c.device)); }
+
+// device copy of a host array (or a device alias when flags say so)
+struct DevArray {
+  Ctx* c = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  bool owned = false;
+  DevArray() = default;
+  DevArray(const DevArray&) = delete;
+  ~DevArray() {
+    if (owned && c) ctx_free(c, p, bytes);
+  }
+  void host(Ctx* cc, const void* src, size_t b) {
+    c = cc;
+    bytes = b;
+    p = ctx_alloc(c, b ? b : 1);
+    owned = true;
+    if (b) DSG_HIP(hipMemcpyAsync(p, src, b, hipMemcpyHostToDevice, c->stream));
+  }
+  void device(const void* src) { p = const_cast<void*>(src); }
+};
+
+static void default_tuning(dsg_tuning* t) {
+  for (int b = 0; b < 8; ++b) t->group_ub[b] = 32 << b;
+  t->dense_max_passes = 4;
+  t->force_bin = -1;
+}
+
+// host-side check of a CSR: row_ptr monotone from 0, columns in range, no
+// repeated column inside a row
+static dsg_status check_csr(int32_t nrows, int32_t ncols, const int64_t* rp, const int32_t* ci,
+                            std::string& msg) {
+  if (rp[0] != 0) {
+    msg = "row_ptr[0] must be 0";
+    return DSG_E_ARG;
+  }
+  std::vector<int32_t> mark((size_t)std::max(ncols, 1), -1);
+  for (int32_t i = 0; i < nrows; ++i) {
+    if (rp[i + 1] < rp[i]) {
+      msg = "row_ptr is not monotone at row " + std::to_string(i);
+      return DSG_E_ARG;
+    }
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      int32_t j = ci[e];
+      if (j < 0 || j >= ncols) {
+        msg = "column index out of range in row " + std::to_string(i);
+        return DSG_E_RANGE;
+      }
+      if (mark[j] == i) {
+        msg = "repeated column " + std::to_string(j) + " in row " + std::to_string(i);
+        return DSG_E_ARG;
+      }
+      mark[j] = i;
+    }
+  }
+  return DSG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+extern "C" dsg_status dsg_ctx_create(int device, void* hip_stream, size_t mem_budget, dsg_ctx** out) {
+  if (!out) return fail(nullptr, DSG_E_ARG, "out is NULL");
+  *out = nullptr;
+  dsg_ctx* ctx = nullptr;
+  try {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+      (void)hipGetLastError();
+      return fail(nullptr, DSG_E_DEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= count) return fail(nullptr, DSG_E_ARG, "bad device index");
+    DSG_HIP(hipSetDevice(device));
+    ctx = new dsg_ctx();
+    Ctx& c = ctx->c;
+    c.device = device;
+    c.budget = mem_budget;
+    default_tuning(&c.tuning);
+    if (hip_stream) {
+      c.stream = (hipStream_t)hip_stream;
+    } else {
+      DSG_HIP(hipStreamCreate(&c.stream));
+      c.own_stream = true;
+    }
+    DSG_HIP(hipHostMalloc(&c.pinned, 4096, hipHostMallocDefault));
+  } catch (const DsgError& e) {
+    if (ctx) {
+      if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
+      delete ctx;
+    }
+    return fail(nullptr, e.code, e.msg);
+  } catch (...) {
+    delete ctx;
+    return fail(nullptr, DSG_E_DEVICE, "context creation failed");
+  }
+  *out = ctx;
+  return DSG_OK;
+}
+
+extern "C" dsg_status dsg_ctx_destroy(dsg_ctx* ctx) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  Ctx& c = ctx->c;
+  if (c.objects > 0) return fail(ctx, DSG_E_STATE, "context still owns matrices or products");
+  (void)hipSetDevice(c.device);
+  (void)hipStreamSynchronize(c.stream);
+  clear_timings(&c);
+  ctx_free(&c, c.scratch, c.scratch_bytes);
+  ctx_free(&c, c.scratch2, c.scratch2_bytes);
+  if (c.pinned) (void)hipHostFree(c.pinned);
+  if (c.own_stream) (void)hipStreamDestroy(c.stream);
+  delete ctx;
+  return DSG_OK;
+}
+
+extern "C" const char* dsg_last_error(const dsg_ctx* ctx) {
+  return ctx ? ctx->c.last_error.c_str() : g_create_error.c_str();
+}
+
+extern "C" dsg_status dsg_ctx_synchronize(dsg_ctx* ctx) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  API_BEGIN(ctx)
+  set_device(ctx);
+  ctx_sync(&ctx->c);
+  API_END
+}
+
+extern "C" dsg_status dsg_ctx_memory(const dsg_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return fail(const_cast<dsg_ctx*>(ctx), DSG_E_ARG, "NULL argument");
+  *bytes = ctx->c.held;
+  return DSG_OK;
+}
+
+extern "C" dsg_status dsg_ctx_set_timing(dsg_ctx* ctx, int on) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  API_BEGIN(ctx)
+  set_device(ctx);
+  ctx_sync(&ctx->c);
+  clear_timings(&ctx->c);
+  ctx->c.timing = on != 0;
+  API_END
+}
+
+extern "C" dsg_status dsg_ctx_timing_report(dsg_ctx* ctx, char* buf, size_t cap) {
+  if (!ctx || !buf || cap == 0) return fail(ctx, DSG_E_ARG, "NULL argument");
+  API_BEGIN(ctx)
+  set_device(ctx);
+  ctx_sync(&ctx->c);
+  struct Agg {
+    long n = 0;
+    double ms = 0, bytes = 0;
+  };
+  std::map<std::string, Agg> agg;
+  for (auto& t : ctx->c.timings) {
+    float ms = 0;
+    DSG_HIP(hipEventElapsedTime(&ms, t.start, t.stop));
+    Agg& a = agg[t.name];
+    a.n++;
+    a.ms += ms;
+    a.bytes += t.bytes;
+  }
+  std::string s = "{\"kernels\": {";
+  bool first = true;
+  for (auto& kv : agg) {
+    char tmp[256];
+    snprintf(tmp, sizeof tmp, "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.1f}", first ? "" : ", ",
+             kv.first.c_str(), kv.second.n, kv.second.ms, kv.second.bytes);
+    s += tmp;
+    first = false;
+  }
+  s += "}}";
+  size_t n = std::min(cap - 1, s.size());
+  memcpy(buf, s.data(), n);
+  buf[n] = 0;
+  API_END
+}
+
+extern "C" dsg_status dsg_ctx_get_tuning(const dsg_ctx* ctx, dsg_tuning* t) {
+  if (!ctx || !t) return fail(const_cast<dsg_ctx*>(ctx), DSG_E_ARG, "NULL argument");
+  *t = ctx->c.tuning;
+  return DSG_OK;
+}
+
+extern "C" dsg_status dsg_ctx_set_tuning(dsg_ctx* ctx, const dsg_tuning* t) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  if (!t) {
+    default_tuning(&ctx->c.tuning);
+    return DSG_OK;
+  }
+  int prev = 0;
+  for (int b = 0; b < 8; ++b) {
+    if (t->group_ub[b] < 0 || t->group_ub[b] > (32 << b))
+      return fail(ctx, DSG_E_ARG, "group_ub[" + std::to_string(b) + "] outside [0, " + std::to_string(32 << b) + "]");
+    if (t->group_ub[b] && t->group_ub[b] < prev) return fail(ctx, DSG_E_ARG, "group_ub must ascend");
+    if (t->group_ub[b]) prev = t->group_ub[b];
+  }
+  if (t->dense_max_passes < 0) return fail(ctx, DSG_E_ARG, "dense_max_passes < 0");
+  if (t->force_bin < -1 || t->force_bin > 9) return fail(ctx, DSG_E_ARG, "force_bin outside [-1, 9]");
+  ctx->c.tuning = *t;
+  return DSG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// matrices
+// ---------------------------------------------------------------------------
+
+extern "C" dsg_status dsg_mat_create(dsg_ctx* ctx, int32_t nrows, int32_t ncols, dsg_semiring sr,
+                                     const int64_t* row_ptr, const int32_t* col, const void* val, uint32_t flags,
+                                     dsg_mat** out) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  if (!out) return fail(ctx, DSG_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (nrows < 0 || ncols < 0) return fail(ctx, DSG_E_ARG, "negative shape");
+  if (sr < DSG_PLUS_TIMES_I64 || sr > DSG_PLUS_TIMES_F64) return fail(ctx, DSG_E_ARG, "unknown semiring");
+  if (flags & ~(uint32_t)(DSG_INPUT_DEVICE | DSG_SYNC)) return fail(ctx, DSG_E_ARG, "unknown flag");
+  API_BEGIN(ctx)
+  set_device(ctx);
+  Ctx* c = &ctx->c;
+  const int vs = value_size(sr);
+  DevArray drp, dci, dv;
+  std::vector<int64_t> hrp;
+  std::vector<int32_t> hci;
+  std::vector<char> hv;
+  const int64_t* rp_h = row_ptr;
+  const int32_t* ci_h = col;
+  if (row_ptr) {
+    if (flags & DSG_INPUT_DEVICE) {
+      hrp.resize((size_t)nrows + 1);
+      DSG_HIP(hipMemcpy(hrp.data(), row_ptr, hrp.size() * 8, hipMemcpyDeviceToHost));
+      rp_h = hrp.data();
+    }
+    int64_t nnz = rp_h[nrows];
+    if (nnz < 0) throw DsgError{DSG_E_ARG, "negative nnz"};
+    if (nnz > 0 && (!col || !val)) throw DsgError{DSG_E_ARG, "col/val NULL with nnz > 0"};
+    if (flags & DSG_INPUT_DEVICE) {
+      hci.resize((size_t)nnz);
+      if (nnz) DSG_HIP(hipMemcpy(hci.data(), col, (size_t)nnz * 4, hipMemcpyDeviceToHost));
+      ci_h = hci.data();
+    }
+    std::string msg;
+    dsg_status st = check_csr(nrows, ncols, rp_h, ci_h, msg);
+    if (st != DSG_OK) throw DsgError{st, msg};
+    if (flags & DSG_INPUT_DEVICE) {
+      drp.device(row_ptr);
+      dci.device(col);
+      dv.device(val);
+    } else {
+      drp.host(c, row_ptr, ((size_t)nrows + 1) * 8);
+      dci.host(c, col, (size_t)nnz * 4);
+      dv.host(c, val, (size_t)nnz * vs);
+    }
+  }
+  DMat* m = mat_create(c, nrows, ncols, (int)sr, row_ptr ? (const int64_t*)drp.p : nullptr,
+                       (const int32_t*)dci.p, dv.p);
+  ctx_sync(c);
+  *out = new dsg_mat{m, ctx, true};
+  API_END
+}
+
+extern "C" dsg_status dsg_mat_apply(dsg_mat* mh, const int32_t* rows, const int32_t* cols, const void* vals,
+                                    const uint8_t* ops, int64_t n, uint32_t flags) {
+  if (!mh || !mh->alive) return fail(nullptr, DSG_E_ARG, "matrix is NULL or destroyed");
+  dsg_ctx* ctx = mh->owner;
+  if (n < 0) return fail(ctx, DSG_E_ARG, "negative batch size");
+  if (n > 0 && (!rows || !cols || !vals || !ops)) return fail(ctx, DSG_E_ARG, "NULL batch array");
+  if (n > (int64_t)0x7fffffff) return fail(ctx, DSG_E_ARG, "batch larger than 2^31-1");
+  if (flags & ~(uint32_t)(DSG_INPUT_DEVICE | DSG_SYNC)) return fail(ctx, DSG_E_ARG, "unknown flag");
+  API_BEGIN(ctx)
+  set_device(ctx);
+  DMat* m = mh->m;
+  Ctx* c = &ctx->c;
+  if (n == 0) return DSG_OK;
+  DevArray dr, dcol, dval, dop;
+  if (flags & DSG_INPUT_DEVICE) {
+    dsg_status st = validate_batch_device(m, rows, cols, ops, n);
+    if (st == DSG_E_RANGE) throw DsgError{st, "update index out of range"};
+    if (st != DSG_OK) throw DsgError{st, "unknown update op code"};
+    dr.device(rows);
+    dcol.device(cols);
+    dval.device(vals);
+    dop.device(ops);
+  } else {
+    for (int64_t t = 0; t < n; ++t) {
+      if (rows[t] < 0 || rows[t] >= m->nrows || cols[t] < 0 || cols[t] >= m->ncols)
+        throw DsgError{DSG_E_RANGE, "update " + std::to_string(t) + " index out of range"};
+      if (ops[t] > DSG_OP_ADD) throw DsgError{DSG_E_ARG, "update " + std::to_string(t) + " unknown op"};
+    }
+    dr.host(c, rows, (size_t)n * 4);
+    dcol.host(c, cols, (size_t)n * 4);
+    dval.host(c, vals, (size_t)n * value_size(m->sr));
+    dop.host(c, ops, (size_t)n);
+  }
+  mat_apply_device(m, (const int32_t*)dr.p, (const int32_t*)dcol.p, dval.p, (const uint8_t*)dop.p, n);
+  if ((flags & DSG_SYNC) || !(flags & DSG_INPUT_DEVICE)) ctx_sync(c);
+  API_END
+}
+
+extern "C" dsg_status dsg_mat_nnz(dsg_mat* mh, int64_t* nnz) {
+  if (!mh || !mh->alive || !nnz) return fail(mh ? mh->owner : nullptr, DSG_E_ARG, "NULL argument");
+  API_BEGIN(mh->owner)
+  set_device(ctx__);
+  *nnz = mat_nnz(mh->m);
+  API_END
+}
+
+extern "C" dsg_status dsg_mat_shape(const dsg_mat* mh, int32_t* nrows, int32_t* ncols, dsg_semiring* sr) {
+  if (!mh || !mh->alive) return fail(nullptr, DSG_E_ARG, "matrix is NULL or destroyed");
+  if (nrows) *nrows = mh->m->nrows;
+  if (ncols) *ncols = mh->m->ncols;
+  if (sr) *sr = (dsg_semiring)mh->m->sr;
+  return DSG_OK;
+}
+
+static void export_impl(DMat* m, int64_t* row_ptr, int32_t* col, void* val, int64_t cap, int64_t* nnz_out) {
+  Ctx* c = m->ctx;
+  const int32_t n = m->nrows;
+  DevArray drp;
+  drp.c = c;
+  drp.bytes = ((size_t)n + 1) * 8;
+  drp.p = ctx_alloc(c, drp.bytes);
+  drp.owned = true;
+  mat_export_device(m, (int64_t*)drp.p, nullptr, nullptr, nullptr, c->stream);
+  int64_t nnz = 0;
+  DSG_HIP(hipMemcpy(&nnz, (int64_t*)drp.p + n, 8, hipMemcpyDeviceToHost));
+  *nnz_out = nnz;
+  if (row_ptr) DSG_HIP(hipMemcpy(row_ptr, drp.p, drp.bytes, hipMemcpyDeviceToHost));
+  if (!col) return;
+  if (cap < nnz) throw DsgError{DSG_E_ARG, "capacity " + std::to_string(cap) + " < nnz " + std::to_string(nnz)};
+  if (nnz == 0) return;
+  const int vs = m->vsz ? m->vsz : 4;
+  DevArray dc, dv;
+  dc.c = dv.c = c;
+  dc.bytes = (size_t)nnz * 4;
+  dv.bytes = (size_t)nnz * vs;
+  dc.p = ctx_alloc(c, dc.bytes);
+  dc.owned = true;
+  dv.p = ctx_alloc(c, dv.bytes);
+  dv.owned = true;
+  mat_export_device(m, (int64_t*)drp.p, (int32_t*)dc.p, dv.p, nullptr, c->stream);
+  ctx_sync(c);
+  DSG_HIP(hipMemcpy(col, dc.p, dc.bytes, hipMemcpyDeviceToHost));
+  if (val && m->vsz) DSG_HIP(hipMemcpy(val, dv.p, dv.bytes, hipMemcpyDeviceToHost));
+}
+
+extern "C" dsg_status dsg_mat_export(dsg_mat* mh, int64_t* row_ptr, int32_t* col, void* val, int64_t cap,
+                                     int64_t* nnz_out) {
+  if (!mh || !mh->alive || !nnz_out) return fail(mh ? mh->owner : nullptr, DSG_E_ARG, "NULL argument");
+  if (col && !val) return fail(mh->owner, DSG_E_ARG, "val is NULL");
+  API_BEGIN(mh->owner)
+  set_device(ctx__);
+  export_impl(mh->m, row_ptr, col, val, cap, nnz_out);
+  API_END
+}
+
+extern "C" dsg_status dsg_mat_destroy(dsg_mat* mh) {
+  if (!mh || !mh->alive) return fail(nullptr, DSG_E_ARG, "matrix is NULL or destroyed");
+  dsg_ctx* ctx = mh->owner;
+  if (mh->m->refs > 0) return fail(ctx, DSG_E_STATE, "matrix is used by a product");
+  API_BEGIN(ctx)
+  set_device(ctx);
+  ctx_sync(&ctx->c);
+  mat_destroy(mh->m);
+  mh->m = nullptr;
+  mh->alive = false;
+  delete mh;
+  API_END
+}
+
+// ---------------------------------------------------------------------------
+// products
+// ---------------------------------------------------------------------------
+
+static void fill_rows(DProd* p, const int32_t* rows, int32_t n, dsg_rows* out) {
+  out->n = n;
+  out->rows = rows;
+  out->row_off = p->C->row_off;
+  out->row_len = p->C->row_len;
+  out->col = p->C->col;
+  out->val = p->C->val;
+}
+
+extern "C" dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod** out) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  if (!out || !A || !B || !A->alive || !B->alive) return fail(ctx, DSG_E_ARG, "NULL or destroyed argument");
+  *out = nullptr;
+  if (A->owner != ctx || B->owner != ctx) return fail(ctx, DSG_E_STATE, "operands belong to another context");
+  if (A->m->sr != B->m->sr) return fail(ctx, DSG_E_STATE, "semiring mismatch");
+  if (A->m->ncols != B->m->nrows) return fail(ctx, DSG_E_STATE, "shape mismatch: ncols(A) != nrows(B)");
+  API_BEGIN(ctx)
+  set_device(ctx);
+  DProd* p = prod_create(&ctx->c, A->m, B->m);
+  *out = new dsg_prod{p, ctx, A, B};
+  API_END
+}
+
+extern "C" dsg_status dsg_prod_recompute_static(dsg_prod* ph, uint32_t flags) {
+  if (!ph) return fail(nullptr, DSG_E_ARG, "product is NULL");
+  if (flags & ~(uint32_t)DSG_SYNC) return fail(ph->owner, DSG_E_ARG, "unknown flag");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  prod_run(ph->p, 1, true);
+  API_END
+}
+
+extern "C" dsg_status dsg_prod_update(dsg_prod* ph, uint32_t flags, dsg_rows* changed) {
+  if (!ph) return fail(nullptr, DSG_E_ARG, "product is NULL");
+  if (flags & ~(uint32_t)(DSG_SYNC | DSG_REPORT_AFFECTED)) return fail(ph->owner, DSG_E_ARG, "unknown flag");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  int32_t n = prod_run(ph->p, 0, (flags & DSG_REPORT_AFFECTED) != 0);
+  if (changed) fill_rows(ph->p, ph->p->changed_rows, n, changed);
+  API_END
+}
+
+__global__ static void k_check_rows(const int32_t* rows, int32_t n, int32_t nrows, int* bad) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n && (rows[t] < 0 || rows[t] >= nrows)) atomicOr(bad, 1);
+}
+
+extern "C" dsg_status dsg_prod_rows(dsg_prod* ph, const int32_t* rows, int32_t nq, uint32_t flags,
+                                    dsg_rows* out) {
+  if (!ph || !out) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
+  if (nq < 0 || (nq > 0 && !rows)) return fail(ph->owner, DSG_E_ARG, "bad row list");
+  if (flags & ~(uint32_t)(DSG_INPUT_DEVICE | DSG_SYNC)) return fail(ph->owner, DSG_E_ARG, "unknown flag");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  DProd* p = ph->p;
+  Ctx* c = p->ctx;
+  const int32_t nrows = p->C->nrows;
+  if (nq > p->query_cap) {
+    if (p->query_rows) ctx_free(c, p->query_rows, (size_t)p->query_cap * 4);
+    p->query_rows = nullptr;
+    p->query_cap = 0;
+    int64_t cap = std::max<int64_t>(nq, 1024);
+    p->query_rows = (int32_t*)ctx_alloc(c, (size_t)cap * 4);
+    p->query_cap = cap;
+  }
+  if (flags & DSG_INPUT_DEVICE) {
+    if (nq > 0) {
+      int* bad = (int*)ctx_scratch(c, 64);
+      DSG_HIP(hipMemsetAsync(bad, 0, 4, c->stream));
+      hipLaunchKernelGGL(k_check_rows, dim3((nq + 255) / 256), dim3(256), 0, c->stream, rows, nq, nrows, bad);
+      int* h = (int*)c->pinned;
+      DSG_HIP(hipMemcpyAsync(h, bad, 4, hipMemcpyDeviceToHost, c->stream));
+      DSG_HIP(hipStreamSynchronize(c->stream));
+      if (h[0]) throw DsgError{DSG_E_RANGE, "row index out of range"};
+      DSG_HIP(hipMemcpyAsync(p->query_rows, rows, (size_t)nq * 4, hipMemcpyDeviceToDevice, c->stream));
+    }
+  } else {
+    for (int32_t t = 0; t < nq; ++t)
+      if (rows[t] < 0 || rows[t] >= nrows) throw DsgError{DSG_E_RANGE, "row index out of range"};
+    if (nq > 0) DSG_HIP(hipMemcpyAsync(p->query_rows, rows, (size_t)nq * 4, hipMemcpyHostToDevice, c->stream));
+  }
+  if (flags & DSG_SYNC || !(flags & DSG_INPUT_DEVICE)) ctx_sync(c);
+  fill_rows(p, p->query_rows, nq, out);
+  API_END
+}
+
+__global__ static void k_view_lens(const int32_t* rows, int32_t n, const int32_t* row_len, int64_t* lens) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) lens[q] = row_len[rows[q]];
+}
+
+// one wavefront per view row: gather its entries into a compact buffer
+template <int VSZ>
+__global__ __launch_bounds__(256) static void k_view_gather(const int32_t* rows, int32_t n, const int64_t* off,
+                                                            const int32_t* len, const int32_t* col,
+                                                            const char* val, const int64_t* rp, int32_t* ocol,
+                                                            char* oval) {
+  int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int lane = threadIdx.x & 63;
+  if (q >= n) return;
+  int32_t i = rows[q];
+  int64_t o = off[i], d = rp[q];
+  for (int32_t t = lane; t < len[i]; t += 64) {
+    ocol[d + t] = col[o + t];
+    for (int b = 0; b < VSZ; ++b) oval[(d + t) * VSZ + b] = val[(o + t) * VSZ + b];
+  }
+}
+
+extern "C" dsg_status dsg_rows_export(dsg_prod* ph, const dsg_rows* v, int64_t* row_ptr, int32_t* col,
+                                      void* val, int64_t cap, int64_t* nnz_out) {
+  if (!ph || !v || !nnz_out) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
+  if (col && !val) return fail(ph->owner, DSG_E_ARG, "val is NULL");
+  if (v->n < 0 || (v->n > 0 && !v->rows)) return fail(ph->owner, DSG_E_ARG, "bad view");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  DProd* p = ph->p;
+  Ctx* c = p->ctx;
+  DMat* C = p->C;
+  const int32_t n = v->n;
+  const int vs = C->vsz;
+  const size_t sb = scan_scratch_bytes(n) + 64;
+  DevArray lens, rp, scr;
+  lens.c = rp.c = scr.c = c;
+  lens.bytes = (size_t)(n + 1) * 8;
+  rp.bytes = (size_t)(n + 1) * 8;
+  scr.bytes = sb;
+  lens.p = ctx_alloc(c, lens.bytes); lens.owned = true;
+  rp.p = ctx_alloc(c, rp.bytes); rp.owned = true;
+  scr.p = ctx_alloc(c, scr.bytes); scr.owned = true;
+  if (n > 0)
+    hipLaunchKernelGGL(k_view_lens, dim3((n + 255) / 256), dim3(256), 0, c->stream, v->rows, n, C->row_len,
+                       (int64_t*)lens.p);
+  exclusive_scan_i64((const int64_t*)lens.p, (int64_t*)rp.p, n, (int64_t*)rp.p + n, scr.p, c->stream);
+  std::vector<int64_t> hrp((size_t)n + 1);
+  DSG_HIP(hipMemcpyAsync(hrp.data(), rp.p, hrp.size() * 8, hipMemcpyDeviceToHost, c->stream));
+  ctx_sync(c);
+  const int64_t nnz = hrp[n];
+  *nnz_out = nnz;
+  if (row_ptr) memcpy(row_ptr, hrp.data(), hrp.size() * 8);
+  if (!col) return DSG_OK;
+  if (cap < nnz) throw DsgError{DSG_E_ARG, "capacity < nnz"};
+  if (nnz == 0) return DSG_OK;
+  DevArray dc, dv;
+  dc.c = dv.c = c;
+  dc.bytes = (size_t)nnz * 4;
+  dv.bytes = (size_t)nnz * vs;
+  dc.p = ctx_alloc(c, dc.bytes); dc.owned = true;
+  dv.p = ctx_alloc(c, dv.bytes); dv.owned = true;
+  unsigned nb = (unsigned)(((int64_t)n * 64 + 255) / 256);
+  if (vs == 8)
+    hipLaunchKernelGGL(k_view_gather<8>, dim3(nb), dim3(256), 0, c->stream, v->rows, n, C->row_off, C->row_len,
+                       C->col, (const char*)C->val, (const int64_t*)rp.p, (int32_t*)dc.p, (char*)dv.p);
+  else
+    hipLaunchKernelGGL(k_view_gather<4>, dim3(nb), dim3(256), 0, c->stream, v->rows, n, C->row_off, C->row_len,
+                       C->col, (const char*)C->val, (const int64_t*)rp.p, (int32_t*)dc.p, (char*)dv.p);
+  std::vector<int32_t> hc((size_t)nnz);
+  std::vector<char> hv((size_t)nnz * vs);
+  DSG_HIP(hipMemcpyAsync(hc.data(), dc.p, dc.bytes, hipMemcpyDeviceToHost, c->stream));
+  DSG_HIP(hipMemcpyAsync(hv.data(), dv.p, dv.bytes, hipMemcpyDeviceToHost, c->stream));
+  ctx_sync(c);
+  // canonical order inside each row
+  std::vector<int64_t> perm;
+  char* ov = (char*)val;
+  for (int32_t q = 0; q < n; ++q) {
+    int64_t a = hrp[q], b = hrp[q + 1];
+    perm.resize((size_t)(b - a));
+    for (int64_t e = a; e < b; ++e) perm[(size_t)(e - a)] = e;
+    std::sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return hc[(size_t)x] < hc[(size_t)y]; });
+    for (int64_t e = a; e < b; ++e) {
+      int64_t src = perm[(size_t)(e - a)];
+      col[e] = hc[(size_t)src];
+      memcpy(ov + (size_t)e * vs, hv.data() + (size_t)src * vs, (size_t)vs);
+    }
+  }
+  API_END
+}
+
+extern "C" dsg_status dsg_prod_nnz(dsg_prod* ph, int64_t* nnz) {
+  if (!ph || !nnz) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  *nnz = mat_nnz(ph->p->C);
+  API_END
+}
+
+extern "C" dsg_status dsg_prod_export(dsg_prod* ph, int64_t* row_ptr, int32_t* col, void* val, int64_t cap,
+                                      int64_t* nnz_out) {
+  if (!ph || !nnz_out) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
+  if (col && !val) return fail(ph->owner, DSG_E_ARG, "val is NULL");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  export_impl(ph->p->C, row_ptr, col, val, cap, nnz_out);
+  API_END
+}
+
+extern "C" dsg_status dsg_prod_stats(const dsg_prod* ph, dsg_update_stats* s) {
+  if (!ph || !s) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
+  *s = ph->p->stats;
+  return DSG_OK;
+}
+
+extern "C" dsg_status dsg_prod_destroy(dsg_prod* ph) {
+  if (!ph) return fail(nullptr, DSG_E_ARG, "product is NULL");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  ctx_sync(&ctx__->c);
+  prod_destroy(ph->p);
+  delete ph;
+  API_END
+}

@@ -1,0 +1,550 @@
+// Batch ingest: apply (i, j, x) updates to a device dynamic matrix.
+//
+// Semantics (Section 4.1): SET replaces or inserts ("merge"), DELETE removes a
+// present entry ("mask"), ADD folds x in with the semiring addition or
+// inserts it.  A batch means its updates applied one after the other in batch
+// order.
+//
+// Pipeline, all on the device:
+//   1. key = (row << colbits) | col, stable LSD radix sort of (key, index);
+//   2. segment heads -> unique keys and unique rows (the doubly compressed,
+//      hypersparse shape the paper gives update matrices, Section 4);
+//   3. fold each key's run in batch order: the last SET/DELETE is the base,
+//      the ADDs after it are folded on top when the row is visited;
+//   4. plan: one wavefront per touched row streams the row once, matches its
+//      slots against the row's sorted unique updates by binary search, and
+//      decides each update's outcome (insert / delete / overwrite / no-op);
+//      rows that outgrow their slack request new space;
+//   5. the host reserves pool space for the requested moves (one small
+//      device-to-host read), then
+//   6. commit: in place (holes left by deletions are filled by insertions
+//      first, then by entries moved down from the row's tail) or into fresh
+//      space; changed rows get the matrix's new epoch, and every structural
+//      change is emitted for the transpose index, which is updated by the
+//      same pipeline.
+#include "internal.h"
+#include "kernel_common.h"
+
+namespace {
+
+constexpr uint8_t K_KEEP = 0, K_SET = 1, K_DEL = 2;
+constexpr uint8_t C_NOP = 0, C_INS = 1, C_DEL = 2, C_OVR = 3;
+
+int bits_for(int64_t n) {
+  int b = 0;
+  while ((int64_t(1) << b) < n) ++b;
+  return b;
+}
+
+unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// structure-only matrices (transpose index) carry no values
+struct SemNone {
+  using V = uint32_t;
+  __device__ static V add(V a, V) { return a; }
+};
+template <int SR>
+struct SemOf {
+  using S = Sem<SR>;
+};
+template <>
+struct SemOf<-1> {
+  using S = SemNone;
+};
+
+__global__ void k_batch_keys(const int32_t* rows, const int32_t* cols, int64_t n, int cbits, uint64_t* keys,
+                             uint32_t* idx) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    keys[t] = ((uint64_t)(uint32_t)rows[t] << cbits) | (uint64_t)(uint32_t)cols[t];
+    idx[t] = (uint32_t)t;
+  }
+}
+
+__global__ void k_heads(const uint64_t* keys, int64_t n, int cbits, uint64_t sentinel, int64_t* kh,
+                        int64_t* rh) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  uint64_t k = keys[t];
+  bool valid = k != sentinel;
+  bool newk = valid && (t == 0 || keys[t - 1] != k);
+  bool newr = valid && (t == 0 || (keys[t - 1] >> cbits) != (k >> cbits));
+  kh[t] = newk ? 1 : 0;
+  rh[t] = newr ? 1 : 0;
+}
+
+struct Uniq {
+  uint64_t* key;
+  uint8_t* kind;
+  uint64_t* val;  // raw value bits of the base (SET) value
+  int32_t* add_start;
+  int32_t* add_cnt;
+  int32_t* slot;
+  uint8_t* code;
+  uint64_t* fin;  // raw bits of the final value
+  int32_t* urow;
+  int32_t* row_first;
+  int32_t* plen;
+  int32_t* pcap;
+  uint8_t* pchg;
+  int32_t* holes;
+  int32_t* mv_src;
+  int32_t* mv_u;
+};
+
+template <int VSZ>
+__device__ inline uint64_t load_raw(const void* p, int64_t i) {
+  if constexpr (VSZ == 8) return ((const uint64_t*)p)[i];
+  if constexpr (VSZ == 4) return ((const uint32_t*)p)[i];
+  return 0;
+}
+template <int VSZ>
+__device__ inline void store_raw(void* p, int64_t i, uint64_t v) {
+  if constexpr (VSZ == 8) ((uint64_t*)p)[i] = v;
+  if constexpr (VSZ == 4) ((uint32_t*)p)[i] = (uint32_t)v;
+}
+
+template <class V>
+__device__ inline V from_raw(uint64_t r) {
+  if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, r);
+  else return __builtin_bit_cast(V, (uint32_t)r);
+}
+template <class V>
+__device__ inline uint64_t to_raw(V v) {
+  if constexpr (sizeof(V) == 8) return __builtin_bit_cast(uint64_t, v);
+  else return (uint64_t)__builtin_bit_cast(uint32_t, v);
+}
+
+// fold each unique key's run (in batch order, since the sort is stable)
+template <int VSZ>
+__global__ void k_fold(const uint64_t* keys, const uint32_t* idx, int64_t n, int cbits, const uint8_t* ops,
+                       const void* vals, const int64_t* kh, const int64_t* ukpos, const int64_t* rh,
+                       const int64_t* urpos, const int64_t* d_nU, const int64_t* d_nR, Uniq U) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) U.row_first[*d_nR] = (int32_t)*d_nU;
+  if (t >= n || !kh[t]) return;
+  uint64_t k = keys[t];
+  int64_t u = ukpos[t];
+  int64_t last = -1, e = t;
+  while (e < n && keys[e] == k) {
+    if (ops[idx[e]] != DSG_OP_ADD) last = e;
+    ++e;
+  }
+  U.key[u] = k;
+  if (last < 0) {
+    U.kind[u] = K_KEEP;
+    U.val[u] = 0;
+    U.add_start[u] = (int32_t)t;
+    U.add_cnt[u] = (int32_t)(e - t);
+  } else {
+    bool del = ops[idx[last]] == DSG_OP_DELETE;
+    U.kind[u] = del ? K_DEL : K_SET;
+    U.val[u] = del ? 0 : load_raw<VSZ>(vals, idx[last]);
+    U.add_start[u] = (int32_t)(last + 1);
+    U.add_cnt[u] = (int32_t)(e - last - 1);
+  }
+  if (rh[t]) {
+    int64_t r = urpos[t];
+    U.urow[r] = (int32_t)(k >> cbits);
+    U.row_first[r] = (int32_t)u;
+  }
+}
+
+// position of column c among the unique updates [u0, u1) of a row, or -1
+__device__ inline int32_t find_update(const uint64_t* ukey, int32_t u0, int32_t u1, uint64_t cmask, int32_t c) {
+  int32_t lo = u0, hi = u1;
+  while (lo < hi) {
+    int32_t mid = (lo + hi) >> 1;
+    int32_t mc = (int32_t)(ukey[mid] & cmask);
+    if (mc < c) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < u1 && (int32_t)(ukey[lo] & cmask) == c) ? lo : -1;
+}
+
+template <int SR, int VSZ>
+__global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint64_t cmask, const uint32_t* idx,
+                                              const void* vals, Uniq U, unsigned long long* demand) {
+  using S = typename SemOf<SR>::S;
+  using V = typename S::V;
+  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r >= *d_nR) return;
+  const int32_t i = U.urow[r];
+  const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+  const int64_t off = m.row_off[i];
+  const int32_t len = m.row_len[i], cap = m.row_cap[i];
+  for (int32_t u = u0 + lane; u < u1; u += 64) U.slot[u] = -1;
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  for (int32_t s = lane; s < len; s += 64) {
+    int32_t u = find_update(U.key, u0, u1, cmask, m.col[off + s]);
+    if (u >= 0) U.slot[u] = s;
+  }
+  __threadfence_block();
+  __builtin_amdgcn_wave_barrier();
+  int32_t n_del = 0, n_ins = 0, n_ovr = 0;
+  for (int32_t base = u0; base < u1; base += 64) {
+    int32_t u = base + lane;
+    uint8_t code = C_NOP;
+    if (u < u1) {
+      int32_t s = U.slot[u];
+      bool present = s >= 0;
+      uint64_t old = present ? load_raw<VSZ>(m.val, off + s) : 0;
+      uint64_t v = old;
+      bool ex = present;
+      uint8_t kind = U.kind[u];
+      if (kind == K_SET) {
+        ex = true;
+        v = U.val[u];
+      } else if (kind == K_DEL) {
+        ex = false;
+      }
+      int32_t a0 = U.add_start[u], a1 = a0 + U.add_cnt[u];
+      for (int32_t q = a0; q < a1; ++q) {
+        uint64_t x = load_raw<VSZ>(vals, idx[q]);
+        if (ex) v = to_raw<V>(S::add(from_raw<V>(v), from_raw<V>(x)));
+        else v = x;
+        ex = true;
+      }
+      if (present) code = ex ? ((VSZ && v != old) ? C_OVR : C_NOP) : C_DEL;
+      else code = ex ? C_INS : C_NOP;
+      U.code[u] = code;
+      U.fin[u] = v;
+    }
+    n_del += __popcll(__ballot(code == C_DEL));
+    n_ins += __popcll(__ballot(code == C_INS));
+    n_ovr += __popcll(__ballot(code == C_OVR));
+  }
+  if (lane == 0) {
+    int32_t nl = len - n_del + n_ins;
+    bool chg = (n_del + n_ins + n_ovr) > 0;
+    bool reloc = nl > cap;
+    U.plen[r] = nl;
+    U.pchg[r] = chg ? 1 : 0;
+    U.pcap[r] = reloc ? slack_cap(nl) : 0;
+    if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
+  }
+}
+
+template <int SR, int VSZ>
+__global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uint64_t cmask, int cbits,
+                                                Uniq U, uint32_t epoch, int tbits, uint64_t* dkey,
+                                                uint8_t* dop, unsigned long long* d_ndelta, int* err) {
+  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (r >= *d_nR) return;
+  if (!U.pchg[r]) return;
+  const int32_t i = U.urow[r];
+  const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+  const int64_t off = m.row_off[i];
+  const int32_t len = m.row_len[i];
+  const int32_t nl = U.plen[r];
+  const int32_t ncap = U.pcap[r];
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  if (ncap == 0) {
+    // ---- in place ----
+    int32_t H = 0, Mc = 0;
+    for (int32_t base = 0; base < len; base += 64) {
+      int32_t s = base + lane;
+      bool act = s < len;
+      bool deleted = false;
+      int32_t u = -1;
+      if (act) {
+        u = find_update(U.key, u0, u1, cmask, m.col[off + s]);
+        if (u >= 0) {
+          uint8_t code = U.code[u];
+          deleted = code == C_DEL;
+          if (code == C_OVR && s < nl) store_raw<VSZ>(m.val, off + s, U.fin[u]);
+        }
+      }
+      bool hole = act && deleted && s < nl;
+      bool mover = act && !deleted && s >= nl;
+      uint64_t hb = __ballot(hole), mb = __ballot(mover);
+      if (hole) U.holes[u0 + H + __popcll(hb & lt)] = s;
+      if (mover) {
+        int32_t k = u0 + Mc + __popcll(mb & lt);
+        U.mv_src[k] = s;
+        U.mv_u[k] = u;
+      }
+      H += __popcll(hb);
+      Mc += __popcll(mb);
+    }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t q = lane; q < Mc; q += 64) {
+      int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q], mu = U.mv_u[u0 + q];
+      m.col[off + dst] = m.col[off + src];
+      uint64_t v = (mu >= 0 && U.code[mu] == C_OVR) ? U.fin[mu] : load_raw<VSZ>(m.val, off + src);
+      store_raw<VSZ>(m.val, off + dst, v);
+    }
+    int32_t k = 0;
+    for (int32_t base = u0; base < u1; base += 64) {
+      int32_t u = base + lane;
+      bool ins = u < u1 && U.code[u] == C_INS;
+      uint64_t ib = __ballot(ins);
+      if (ins) {
+        int32_t mm = Mc + k + __popcll(ib & lt);
+        int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
+        m.col[off + dst] = (int32_t)(U.key[u] & cmask);
+        store_raw<VSZ>(m.val, off + dst, U.fin[u]);
+      }
+      k += __popcll(ib);
+    }
+  } else {
+    // ---- move the row to fresh space ----
+    unsigned long long no = 0;
+    if (lane == 0) no = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
+    no = __shfl(no, 0, 64);
+    if ((int64_t)no + ncap > m.pool_cap) {
+      if (lane == 0) atomicOr(err, 1);
+      return;
+    }
+    int32_t kept = 0;
+    for (int32_t base = 0; base < len; base += 64) {
+      int32_t s = base + lane;
+      bool act = s < len;
+      bool keep = false;
+      int32_t u = -1;
+      int32_t c = 0;
+      if (act) {
+        c = m.col[off + s];
+        u = find_update(U.key, u0, u1, cmask, c);
+        keep = !(u >= 0 && U.code[u] == C_DEL);
+      }
+      uint64_t kb = __ballot(keep);
+      if (keep) {
+        int64_t dst = (int64_t)no + kept + __popcll(kb & lt);
+        m.col[dst] = c;
+        uint64_t v = (u >= 0 && U.code[u] == C_OVR) ? U.fin[u] : load_raw<VSZ>(m.val, off + s);
+        store_raw<VSZ>(m.val, dst, v);
+      }
+      kept += __popcll(kb);
+    }
+    for (int32_t base = u0; base < u1; base += 64) {
+      int32_t u = base + lane;
+      bool ins = u < u1 && U.code[u] == C_INS;
+      uint64_t ib = __ballot(ins);
+      if (ins) {
+        int64_t dst = (int64_t)no + kept + __popcll(ib & lt);
+        m.col[dst] = (int32_t)(U.key[u] & cmask);
+        store_raw<VSZ>(m.val, dst, U.fin[u]);
+      }
+      kept += __popcll(ib);
+    }
+    if (lane == 0) {
+      m.row_off[i] = (int64_t)no;
+      m.row_cap[i] = ncap;
+    }
+  }
+  if (lane == 0) {
+    m.row_len[i] = nl;
+    m.row_epoch[i] = epoch;
+  }
+  // structural changes for the transpose index: key (col << tbits) | row
+  if (dkey) {
+    for (int32_t base = u0; base < u1; base += 64) {
+      int32_t u = base + lane;
+      uint8_t code = u < u1 ? U.code[u] : C_NOP;
+      bool emit = code == C_INS || code == C_DEL;
+      uint64_t eb = __ballot(emit);
+      unsigned long long pos = 0;
+      if (lane == 0 && eb) pos = atomicAdd(d_ndelta, (unsigned long long)__popcll(eb));
+      pos = __shfl(pos, 0, 64);
+      if (emit) {
+        int64_t q = (int64_t)pos + __popcll(eb & lt);
+        uint64_t j = U.key[u] & cmask;
+        dkey[q] = (j << tbits) | (uint64_t)(uint32_t)i;
+        dop[q] = code == C_INS ? DSG_OP_SET : DSG_OP_DELETE;
+      }
+    }
+  }
+}
+
+__global__ void k_delta_keys(const uint64_t* dkey, const unsigned long long* d_nd, uint64_t sentinel,
+                             uint64_t* keys, uint32_t* idx, int64_t n) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    keys[t] = t < (int64_t)*d_nd ? dkey[t] : sentinel;
+    idx[t] = (uint32_t)t;
+  }
+}
+
+__global__ void k_validate(const int32_t* rows, const int32_t* cols, const uint8_t* ops, int64_t n,
+                           int32_t nrows, int32_t ncols, int* flags) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  if (rows[t] < 0 || rows[t] >= nrows || cols[t] < 0 || cols[t] >= ncols) atomicOr(flags, 1);
+  if (ops[t] > DSG_OP_ADD) atomicOr(flags, 2);
+}
+
+struct Work {
+  uint64_t* keys;
+  uint32_t* idx;
+  void* radix;
+  int64_t* kh;
+  int64_t* rh;
+  int64_t* ukpos;
+  int64_t* urpos;
+  int64_t* nU;
+  int64_t* nR;
+  void* scan;
+  Uniq U;
+  unsigned long long* demand;
+  unsigned long long* ndelta;
+  int* err;
+  uint64_t* dkey;
+  uint8_t* dop;
+};
+
+size_t work_bytes(int64_t n, bool deltas) {
+  size_t N = (size_t)(n > 0 ? n : 1);
+  return Carve::need({N * 8, N * 4, radix_scratch_bytes(n), N * 8, N * 8, N * 8, N * 8, 64, 64,
+                      scan_scratch_bytes(n), N * 8, N, N * 8, N * 4, N * 4, N * 4, N, N * 8, N * 4,
+                      (N + 1) * 4, N * 4, N * 4, N, N * 4, N * 4, N * 4, 64, 64, 64,
+                      deltas ? N * 8 : 0, deltas ? N : 0});
+}
+
+Work carve_work(void* base, int64_t n, bool deltas) {
+  size_t N = (size_t)(n > 0 ? n : 1);
+  Carve cv(base, work_bytes(n, deltas));
+  Work w;
+  w.keys = cv.take<uint64_t>(N);
+  w.idx = cv.take<uint32_t>(N);
+  w.radix = cv.take<char>(radix_scratch_bytes(n));
+  w.kh = cv.take<int64_t>(N);
+  w.rh = cv.take<int64_t>(N);
+  w.ukpos = cv.take<int64_t>(N);
+  w.urpos = cv.take<int64_t>(N);
+  w.nU = cv.take<int64_t>(8);
+  w.nR = cv.take<int64_t>(8);
+  w.scan = cv.take<char>(scan_scratch_bytes(n));
+  w.U.key = cv.take<uint64_t>(N);
+  w.U.kind = cv.take<uint8_t>(N);
+  w.U.val = cv.take<uint64_t>(N);
+  w.U.add_start = cv.take<int32_t>(N);
+  w.U.add_cnt = cv.take<int32_t>(N);
+  w.U.slot = cv.take<int32_t>(N);
+  w.U.code = cv.take<uint8_t>(N);
+  w.U.fin = cv.take<uint64_t>(N);
+  w.U.urow = cv.take<int32_t>(N);
+  w.U.row_first = cv.take<int32_t>(N + 1);
+  w.U.plen = cv.take<int32_t>(N);
+  w.U.pcap = cv.take<int32_t>(N);
+  w.U.pchg = cv.take<uint8_t>(N);
+  w.U.holes = cv.take<int32_t>(N);
+  w.U.mv_src = cv.take<int32_t>(N);
+  w.U.mv_u = cv.take<int32_t>(N);
+  w.demand = cv.take<unsigned long long>(8);
+  w.ndelta = cv.take<unsigned long long>(8);
+  w.err = cv.take<int>(16);
+  w.dkey = deltas ? cv.take<uint64_t>(N) : nullptr;
+  w.dop = deltas ? cv.take<uint8_t>(N) : nullptr;
+  return w;
+}
+
+template <int SR, int VSZ>
+void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, const void* vals,
+                        uint32_t epoch, int tbits) {
+  Ctx* c = m->ctx;
+  hipStream_t s = c->stream;
+  unsigned nb = blocks_for(n * 64, 256);
+  hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
+                     w.demand);
+  // the one host round trip: how much pool space moved rows need
+  unsigned long long* h = (unsigned long long*)c->pinned;
+  DSG_HIP(hipMemcpyAsync(h, w.demand, 8, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  int64_t demand = (int64_t)h[0];
+  if (demand > 0) {
+    mat_reserve(m, demand);
+    m->h_top_ub += demand;
+  }
+  hipLaunchKernelGGL((k_commit<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, cbits, w.U, epoch,
+                     tbits, w.dkey, w.dop, w.ndelta, w.err);
+}
+
+// Steps 2-6 on keys/idx already filled (n entries, sentinel-padded allowed).
+void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint8_t* ops,
+              const void* vals) {
+  Ctx* c = m->ctx;
+  hipStream_t s = c->stream;
+  int cbits = bits_for(m->ncols);
+  uint64_t sentinel = 1ull << key_bits;
+  uint64_t cmask = (1ull << cbits) - 1;
+  radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s);
+  unsigned nb = blocks_for(n, 256);
+  hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, s, w.keys, n, cbits, sentinel, w.kh, w.rh);
+  exclusive_scan_i64(w.kh, w.ukpos, n, w.nU, w.scan, s);
+  exclusive_scan_i64(w.rh, w.urpos, n, w.nR, w.scan, s);
+  DSG_HIP(hipMemsetAsync(w.demand, 0, 8, s));
+  DSG_HIP(hipMemsetAsync(w.ndelta, 0, 8, s));
+  DSG_HIP(hipMemsetAsync(w.err, 0, 4, s));
+  int vsz = m->vsz;
+  if (vsz == 8)
+    hipLaunchKernelGGL(k_fold<8>, dim3(nb), dim3(256), 0, s, w.keys, w.idx, n, cbits, ops, vals, w.kh,
+                       w.ukpos, w.rh, w.urpos, w.nU, w.nR, w.U);
+  else if (vsz == 4)
+    hipLaunchKernelGGL(k_fold<4>, dim3(nb), dim3(256), 0, s, w.keys, w.idx, n, cbits, ops, vals, w.kh,
+                       w.ukpos, w.rh, w.urpos, w.nU, w.nR, w.U);
+  else
+    hipLaunchKernelGGL(k_fold<0>, dim3(nb), dim3(256), 0, s, w.keys, w.idx, n, cbits, ops, vals, w.kh,
+                       w.ukpos, w.rh, w.urpos, w.nU, w.nR, w.U);
+  uint32_t epoch = ++m->epoch;
+  int tbits = bits_for(m->nrows);
+  switch (m->sr) {
+    case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, epoch, tbits); break;
+    case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, epoch, tbits); break;
+    case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, epoch, tbits); break;
+    default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, epoch, tbits); break;
+  }
+  DSG_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const uint8_t* d_ops,
+                                 int64_t n) {
+  if (n == 0) return DSG_OK;
+  Ctx* c = m->ctx;
+  int* flags = (int*)ctx_scratch(c, 64);
+  DSG_HIP(hipMemsetAsync(flags, 0, 4, c->stream));
+  hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, d_rows, d_cols, d_ops, n,
+                     m->nrows, m->ncols, flags);
+  int* h = (int*)c->pinned;
+  DSG_HIP(hipMemcpyAsync(h, flags, 4, hipMemcpyDeviceToHost, c->stream));
+  DSG_HIP(hipStreamSynchronize(c->stream));
+  if (h[0] & 1) return DSG_E_RANGE;
+  if (h[0] & 2) return DSG_E_ARG;
+  return DSG_OK;
+}
+
+void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
+                      const uint8_t* d_ops, int64_t n) {
+  if (n == 0) return;
+  Ctx* c = m->ctx;
+  hipStream_t s = c->stream;
+  bool deltas = m->tidx != nullptr;
+  Work w = carve_work(ctx_scratch(c, work_bytes(n, deltas)), n, deltas);
+  int cbits = bits_for(m->ncols);
+  int kbits = cbits + bits_for(m->nrows);
+  unsigned nb = blocks_for(n, 256);
+  hipLaunchKernelGGL(k_batch_keys, dim3(nb), dim3(256), 0, s, d_rows, d_cols, n, cbits, w.keys, w.idx);
+  run_core(m, w, n, kbits, false, d_ops, d_vals);
+  if (deltas) {
+    DMat* t = m->tidx;
+    Work wt = carve_work(ctx_scratch2(c, work_bytes(n, false)), n, false);
+    int tk = bits_for(t->ncols) + bits_for(t->nrows);
+    // the emitted deltas occupy [0, ndelta); the rest of the n slots hold the sentinel
+    hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, w.ndelta, 1ull << tk, wt.keys,
+                       wt.idx, n);
+    run_core(t, wt, n, tk, true, w.dop, nullptr);
+    DSG_HIP(hipMemcpyAsync((int*)c->pinned + 1, wt.err, 4, hipMemcpyDeviceToHost, s));
+  }
+  // a failed move (pool exhausted) would leave the batch half applied: report it loudly
+  int* h = (int*)c->pinned;
+  h[1] = 0;
+  DSG_HIP(hipMemcpyAsync(h, w.err, 4, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  DSG_REQUIRE(h[0] == 0 && h[1] == 0, DSG_E_DEVICE, "internal: pool overflow while applying a batch");
+}

@@ -1,0 +1,203 @@
+// Internal declarations of the dsg library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dsg.h"
+
+// ---------------------------------------------------------------------------
+// host-side error plumbing
+// ---------------------------------------------------------------------------
+
+struct DsgError {
+  dsg_status code;
+  std::string msg;
+};
+
+#define DSG_HIP(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw DsgError{DSG_E_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)};  \
+  } while (0)
+
+#define DSG_REQUIRE(cond, code, text)                     \
+  do {                                                    \
+    if (!(cond)) throw DsgError{(code), std::string(text)}; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// storage
+// ---------------------------------------------------------------------------
+
+// Slack row capacity for a row of `len` entries: room to grow without moving.
+__host__ __device__ inline int32_t slack_cap(int32_t len) {
+  int32_t extra = len >> 3;
+  return len + (extra < 4 ? 4 : extra);
+}
+
+struct Ctx;
+
+// Device-resident dynamic matrix: every row owns a slot range
+// [row_off[i], row_off[i] + row_cap[i]) of the column/value pools and uses its
+// first row_len[i] slots, in no particular column order.  Rows that outgrow
+// their capacity move to fresh space taken from the pool top.
+struct DMat {
+  Ctx* ctx = nullptr;
+  int32_t nrows = 0, ncols = 0;
+  int sr = 0;          // semiring id; -1 for a structure-only matrix
+  int vsz = 0;         // bytes per value (0: structure only)
+  int64_t* row_off = nullptr;
+  int32_t* row_len = nullptr;
+  int32_t* row_cap = nullptr;
+  uint32_t* row_epoch = nullptr;  // epoch of the last change of each row
+  int32_t* col = nullptr;
+  void* val = nullptr;
+  int64_t pool_cap = 0;           // slots in col/val
+  int64_t* d_top = nullptr;       // device: first free slot
+  int64_t h_top_ub = 0;           // host: upper bound of *d_top
+  uint32_t epoch = 1;             // bumped by every apply that changes something
+  DMat* tidx = nullptr;           // structure-only transpose index (rows = columns of this)
+  int refs = 0;                   // products using this matrix
+  bool counted = false;           // registered in ctx->objects
+};
+
+// Per-kernel timing record.
+struct KernelTiming {
+  std::string name;
+  hipEvent_t start, stop;
+  double bytes;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0;
+  size_t held = 0;
+  std::string last_error = "";
+  int objects = 0;
+  dsg_tuning tuning;
+  bool timing = false;
+  std::vector<KernelTiming> timings;
+  std::vector<hipEvent_t> event_pool;
+  // pinned host staging block for small device->host reads
+  void* pinned = nullptr;
+  // reusable device scratch, grown on demand
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  void* scratch2 = nullptr;
+  size_t scratch2_bytes = 0;
+};
+
+void* ctx_alloc(Ctx* c, size_t bytes);
+void ctx_free(Ctx* c, void* p, size_t bytes);
+void* ctx_scratch(Ctx* c, size_t bytes);   // contents undefined; valid until the next call
+void* ctx_scratch2(Ctx* c, size_t bytes);
+void ctx_sync(Ctx* c);
+void ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop);
+void ctx_timing_end(Ctx* c, hipEvent_t stop);
+
+// Bump allocator for device scratch carved out of one allocation.
+struct Carve {
+  char* base;
+  size_t off = 0, cap;
+  Carve(void* b, size_t c) : base((char*)b), cap(c) {}
+  template <class T>
+  T* take(size_t n) {
+    size_t a = (off + 255) & ~size_t(255);
+    T* p = (T*)(base + a);
+    off = a + n * sizeof(T);
+    if (off > cap) throw DsgError{DSG_E_OOM, "internal scratch overflow"};
+    return p;
+  }
+  static size_t need(std::initializer_list<size_t> bytes) {
+    size_t s = 0;
+    for (size_t b : bytes) s += (b + 255) & ~size_t(255);
+    return s + 256;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// primitives (prims.hip)
+// ---------------------------------------------------------------------------
+
+// Exclusive scan of n int64 values (in place allowed); total written to
+// *d_total (device) if not null.  Scratch: scan_scratch_bytes(n).
+size_t scan_scratch_bytes(int64_t n);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* d_total, void* scratch,
+                        hipStream_t s);
+// Exclusive scan of int32 counts into int64 offsets.
+void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* d_total,
+                               void* scratch, hipStream_t s);
+
+// Indices i < n with flags[i] != 0, ascending, into out; count into *d_count.
+size_t compact_scratch_bytes(int64_t n);
+void compact_flags(const uint8_t* flags, int64_t n, int32_t* out, int32_t* d_count, void* scratch,
+                   hipStream_t s);
+// Entries list[q], q < *d_n, with flags[q] != 0, in order, into out; count into *d_count.
+void compact_list_by_flags(const int32_t* list, const uint8_t* flags, const int32_t* d_n, int64_t n_max,
+                           int32_t* out, int32_t* d_count, void* scratch, hipStream_t s);
+
+// Stable LSD radix sort of (key, value) pairs on the low key_bits bits.
+size_t radix_scratch_bytes(int64_t n);
+// Sorts keys/vals in place (using the scratch as ping-pong buffers).
+void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, void* scratch,
+                      hipStream_t s);
+
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+void iota_i32(int32_t* p, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// matrices (matrix.hip) and updates (ingest.hip)
+// ---------------------------------------------------------------------------
+
+DMat* mat_create(Ctx* c, int32_t nrows, int32_t ncols, int sr, const int64_t* d_row_ptr,
+                 const int32_t* d_col, const void* d_val);  // device CSR or null
+void mat_destroy(DMat* m);
+// Make sure `extra` more slots can be taken from the pool top; may compact.
+void mat_reserve(DMat* m, int64_t extra);
+void mat_compact(DMat* m, int64_t extra);
+int64_t mat_nnz(DMat* m);
+// Canonical (column-sorted) CSR copy on the device: row_ptr[nrows+1], col, val.
+void mat_export_device(DMat* m, int64_t* d_row_ptr, int32_t* d_col, void* d_val, void* scratch,
+                       hipStream_t s);
+// Build the structure-only transpose index of m.
+void mat_build_transpose(DMat* m);
+
+// Apply a device-resident batch (validated).  Returns nothing; updates epochs.
+void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
+                      const uint8_t* d_ops, int64_t n);
+// Device validation of a batch: returns dsg_status.
+dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols,
+                                 const uint8_t* d_ops, int64_t n);
+
+// ---------------------------------------------------------------------------
+// products (spgemm.hip)
+// ---------------------------------------------------------------------------
+
+struct DProd {
+  Ctx* ctx = nullptr;
+  DMat* A = nullptr;
+  DMat* B = nullptr;
+  DMat* C = nullptr;
+  uint32_t syncA = 0, syncB = 0;
+  int32_t* changed_rows = nullptr;  // device list of the last update's reported rows
+  int64_t changed_cap = 0;
+  int32_t* query_rows = nullptr;
+  int64_t query_cap = 0;
+  void* arena = nullptr;                     // per-row staging / global hash tables
+  size_t arena_bytes = 0;
+  unsigned long long* arena_top = nullptr;   // device bump pointer into the arena
+  dsg_update_stats stats{};
+};
+
+DProd* prod_create(Ctx* c, DMat* A, DMat* B);
+void prod_destroy(DProd* p);
+// mode 0: dynamic update; 1: recompute every row (static); with report_affected.
+int32_t prod_run(DProd* p, int mode, bool report_affected);

@@ -1,0 +1,307 @@
+// Device primitives: scans, flag compaction, stable LSD radix sort.
+//
+// Block-level scans use 64-wide wavefront shuffles plus one LDS slot per
+// wave.  Radix sort ranks keys inside a tile with a wavefront multi-split
+// (8 ballots build the set of lanes holding the same digit), which keeps the
+// sort stable without per-digit loops.
+#include "internal.h"
+#include "kernel_common.h"
+
+namespace {
+
+constexpr int SCAN_NT = 1024;
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_NT * SCAN_ITEMS;
+
+template <class T>
+__device__ T block_exclusive_scan(T v, T* lds, T& total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  T x = wave_inclusive_scan(v);
+  if (lane == 63) lds[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    T s = lane < nw ? lds[lane] : T(0);
+    s = wave_inclusive_scan(s);
+    if (lane < nw) lds[lane] = s;
+  }
+  __syncthreads();
+  T base = w > 0 ? lds[w - 1] : T(0);
+  total = lds[nw - 1];
+  __syncthreads();
+  return base + x - v;
+}
+
+template <class In>
+__global__ __launch_bounds__(SCAN_NT) void k_tile_sums(const In* in, int64_t n, int64_t* sums) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int64_t s = 0;
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    if (i < n) s += (int64_t)in[i];
+  }
+  int64_t total;
+  block_exclusive_scan<int64_t>(s, lds, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// single block: exclusive scan of sums[0..m) in place, grand total to *total
+__global__ __launch_bounds__(SCAN_NT) void k_scan_sums(int64_t* sums, int64_t m, int64_t* total) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < m; base += SCAN_NT) {
+    int64_t i = base + threadIdx.x;
+    int64_t v = i < m ? sums[i] : 0;
+    int64_t t;
+    int64_t ex = block_exclusive_scan<int64_t>(v, lds, t);
+    if (i < m) sums[i] = carry + ex;
+    carry += t;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <class In>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const In* in, int64_t* out, int64_t n,
+                                                        const int64_t* sums) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int64_t v[SCAN_ITEMS];
+  int64_t s = 0;
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    v[t] = i < n ? (int64_t)in[i] : 0;
+    s += v[t];
+  }
+  int64_t total;
+  int64_t run = sums[blockIdx.x] + block_exclusive_scan<int64_t>(s, lds, total);
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    if (i < n) out[i] = run;
+    run += v[t];
+  }
+}
+
+template <class In>
+void scan_impl(const In* in, int64_t* out, int64_t n, int64_t* d_total, void* scratch, hipStream_t s) {
+  int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (tiles == 0) tiles = 1;
+  int64_t* sums = (int64_t*)scratch;
+  hipLaunchKernelGGL(k_tile_sums<In>, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, in, n, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, s, sums, tiles, d_total);
+  hipLaunchKernelGGL(k_scan_apply<In>, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, in, out, n, sums);
+}
+
+// ---- flag compaction ----
+
+__global__ __launch_bounds__(SCAN_NT) void k_flag_counts(const uint8_t* flags, int64_t n, int64_t* sums,
+                                                         const int32_t* d_n) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  if (d_n) n = *d_n;
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int64_t c = 0;
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    if (i < n && flags[i]) ++c;
+  }
+  int64_t total;
+  block_exclusive_scan<int64_t>(c, lds, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_NT) void k_flag_write(const uint8_t* flags, const int32_t* list,
+                                                        int64_t n, const int64_t* sums, int32_t* out,
+                                                        const int32_t* d_n) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  if (d_n) n = *d_n;
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  uint8_t f[SCAN_ITEMS];
+  int64_t c = 0;
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    f[t] = (i < n && flags[i]) ? 1 : 0;
+    c += f[t];
+  }
+  int64_t total;
+  int64_t pos = sums[blockIdx.x] + block_exclusive_scan<int64_t>(c, lds, total);
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    if (f[t]) out[pos++] = list ? list[i] : (int32_t)i;
+  }
+}
+
+__global__ void k_store_count(const int64_t* total, int32_t* d_count) { *d_count = (int32_t)*total; }
+
+// ---- radix sort ----
+
+constexpr int RS_NT = 256;
+constexpr int RS_WAVES = RS_NT / 64;
+constexpr int RS_ITEMS = 8;
+constexpr int RS_TILE = RS_NT * RS_ITEMS;
+
+__global__ __launch_bounds__(RS_NT) void k_rs_hist(const uint64_t* keys, int64_t n, int shift,
+                                                    int64_t* counts, int64_t ntiles) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int t = 0; t < RS_ITEMS; ++t) {
+    int64_t i = base + t * RS_NT + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const uint32_t* vin,
+                                                       uint64_t* kout, uint32_t* vout, int64_t n,
+                                                       int shift, const int64_t* offs, int64_t ntiles) {
+  __shared__ int32_t wcount[RS_WAVES][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int d = threadIdx.x; d < RS_WAVES * 256; d += RS_NT) (&wcount[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t seg = (int64_t)blockIdx.x * RS_TILE + (int64_t)w * (64 * RS_ITEMS);
+  uint64_t k[RS_ITEMS];
+  uint32_t v[RS_ITEMS];
+  int32_t rank[RS_ITEMS];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    int64_t i = seg + r * 64 + lane;
+    bool act = i < n;
+    k[r] = act ? kin[i] : 0;
+    v[r] = act ? vin[i] : 0;
+    uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+    uint64_t peers = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      bool bit = (d >> b) & 1u;
+      uint64_t m = __ballot(act && bit);
+      peers &= bit ? m : ~m;
+    }
+    int before = __popcll(peers & lt);
+    int32_t base = act ? wcount[w][d] : 0;
+    __builtin_amdgcn_wave_barrier();
+    if (act && before == 0) wcount[w][d] = base + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    rank[r] = base + before;
+  }
+  __syncthreads();
+  {
+    int d = threadIdx.x;  // RS_NT == 256 digits
+    int32_t run = 0;
+    for (int ww = 0; ww < RS_WAVES; ++ww) {
+      int32_t c = wcount[ww][d];
+      wcount[ww][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    int64_t i = seg + r * 64 + lane;
+    if (i < n) {
+      uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+      int64_t pos = offs[(int64_t)d * ntiles + blockIdx.x] + wcount[w][d] + rank[r];
+      kout[pos] = k[r];
+      vout[pos] = v[r];
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_iota_i32(int32_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (int32_t)i;
+}
+
+}  // namespace
+
+size_t scan_scratch_bytes(int64_t n) {
+  int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE + 1;
+  return (size_t)tiles * sizeof(int64_t) + 256;
+}
+
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* d_total, void* scratch,
+                        hipStream_t s) {
+  scan_impl<int64_t>(in, out, n, d_total, scratch, s);
+}
+
+void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* d_total,
+                               void* scratch, hipStream_t s) {
+  scan_impl<int32_t>(in, out, n, d_total, scratch, s);
+}
+
+size_t compact_scratch_bytes(int64_t n) { return scan_scratch_bytes(n) + 256; }
+
+void compact_flags(const uint8_t* flags, int64_t n, int32_t* out, int32_t* d_count, void* scratch,
+                   hipStream_t s) {
+  int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  if (tiles == 0) tiles = 1;
+  int64_t* sums = (int64_t*)scratch;
+  int64_t* total = sums + tiles + 1;
+  hipLaunchKernelGGL(k_flag_counts, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, flags, n, sums,
+                     (const int32_t*)nullptr);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, s, sums, tiles, total);
+  hipLaunchKernelGGL(k_flag_write, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, flags,
+                     (const int32_t*)nullptr, n, sums, out, (const int32_t*)nullptr);
+  hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, total, d_count);
+}
+
+void compact_list_by_flags(const int32_t* list, const uint8_t* flags, const int32_t* d_n, int64_t n_max,
+                           int32_t* out, int32_t* d_count, void* scratch, hipStream_t s) {
+  int64_t tiles = (n_max + SCAN_TILE - 1) / SCAN_TILE;
+  if (tiles == 0) tiles = 1;
+  int64_t* sums = (int64_t*)scratch;
+  int64_t* total = sums + tiles + 1;
+  hipLaunchKernelGGL(k_flag_counts, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, flags, n_max, sums, d_n);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, s, sums, tiles, total);
+  hipLaunchKernelGGL(k_flag_write, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, flags, list, n_max, sums,
+                     out, d_n);
+  hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, total, d_count);
+}
+
+size_t radix_scratch_bytes(int64_t n) {
+  int64_t ntiles = (n + RS_TILE - 1) / RS_TILE + 1;
+  return Carve::need({(size_t)n * 8, (size_t)n * 4, (size_t)(256 * ntiles) * 8,
+                      scan_scratch_bytes(256 * ntiles)});
+}
+
+void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, void* scratch,
+                      hipStream_t s) {
+  if (n <= 1 || key_bits <= 0) return;
+  int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+  Carve cv(scratch, radix_scratch_bytes(n));
+  uint64_t* k2 = cv.take<uint64_t>(n);
+  uint32_t* v2 = cv.take<uint32_t>(n);
+  int64_t* counts = cv.take<int64_t>(256 * ntiles + 1);
+  void* sscr = cv.take<char>(scan_scratch_bytes(256 * ntiles));
+  uint64_t* ka = keys;
+  uint32_t* va = vals;
+  uint64_t* kb = k2;
+  uint32_t* vb = v2;
+  int passes = (key_bits + 7) / 8;
+  for (int p = 0; p < passes; ++p) {
+    int shift = 8 * p;
+    hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, n, shift, counts, ntiles);
+    exclusive_scan_i64(counts, counts, 256 * ntiles, nullptr, sscr, s);
+    hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, va, kb, vb, n, shift,
+                       counts, ntiles);
+    uint64_t* tk = ka; ka = kb; kb = tk;
+    uint32_t* tv = va; va = vb; vb = tv;
+  }
+  if (ka != keys) {
+    DSG_HIP(hipMemcpyAsync(keys, ka, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    DSG_HIP(hipMemcpyAsync(vals, va, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+}
+
+void iota_i32(int32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_iota_i32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+}

@@ -1,0 +1,1181 @@
+// Dynamic and static products: affected-row discovery, row analysis and
+// binning, binned row-wise Gustavson recompute, merge into the dynamic C.
+//
+// What is computed (Section 5): C' = A' B' over the semiring.  C' can differ
+// from C only in entries where C* = A* B' + A B* (Eq. 1) is non-zero, where
+// A*, B* mark the changed entries (for general updates only their structure
+// matters, and deletions count as changed entries).  Rows of C* are the
+// changed rows of A plus every row i with A[i,k] present for a changed row
+// k of B; since rows of A outside the changed set are equal in A and A',
+// the post-update transpose index finds them.  Each such row is recomputed
+// in full with Gustavson's row-wise algorithm (Section 6.1), then compared
+// with the stored row and written back only if it differs.
+//
+// Accumulators, by an upper bound ub_i = min(flops_i, ncols) of the output
+// row length:
+//   bins 0-7  a lane group of G = 8<<b lanes per row with an LDS hash table of
+//             8G slots (load <= 1/2);
+//   bin 8     one 1024-lane workgroup per row with a dense LDS accumulator
+//             over column chunks (one pass per chunk);
+//   bin 9     one workgroup per row with a hash table in device memory.
+// Semiring additions that are exactly associative (int64 wrap-around, fp32
+// min) combine with LDS/global atomics in any order.  fp64 sums take the
+// A-row entries one k at a time in ascending k (lanes cover the columns of
+// B[k,:], which are distinct), so every c_ij is summed in ascending k.
+#include "internal.h"
+#include "kernel_common.h"
+
+namespace {
+
+unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+constexpr int NBINS = 10;
+constexpr int BIN_DENSE = 8;
+constexpr int BIN_GLOBAL = 9;
+constexpr int NSTAT = 7;  // rows, a_entries, flops, nnz_new, nnz_old, old_read, written
+constexpr int DENSE_WG = 1024;
+constexpr int DENSE_ACHUNK = 512;
+
+template <int VSZ>
+constexpr int dense_cols() {
+  return VSZ == 8 ? 16384 : 32768;
+}
+
+struct RowArgs {
+  // A (left operand), B (right operand), C (result)
+  const int64_t* a_off;
+  const int32_t* a_len;
+  const int32_t* a_col;
+  const void* a_val;
+  const int64_t* b_off;
+  const int32_t* b_len;
+  const int32_t* b_col;
+  const void* b_val;
+  int64_t* c_off;
+  int32_t* c_len;
+  int32_t* c_cap;
+  int32_t* c_col;
+  void* c_val;
+  int64_t* c_top;
+  int64_t c_pool_cap;
+  int32_t ncols;
+  const int32_t* aff;   // affected rows, indexed by q
+  int32_t* ub;          // per q
+  uint8_t* chg;         // per q: row reported
+  unsigned long long* stats;  // [NBINS][NSTAT]
+  char* arena;
+  unsigned long long* arena_top;
+  int64_t arena_cap;
+  int force_write;      // 1: write every recomputed row, no comparison
+  int* err;
+};
+
+__device__ inline void stat_add(unsigned long long* st, int bin, int f, long long v) {
+  if (v) atomicAdd(&st[bin * NSTAT + f], (unsigned long long)v);
+}
+
+// ---------------------------------------------------------------------------
+// lane-group primitives: G <= 64 lanes inside one wavefront, or G == blockDim
+// ---------------------------------------------------------------------------
+
+template <int G>
+struct Grp {
+  static constexpr bool sub = G <= 64;
+  int lane;   // lane in group
+  int goff;   // offset of the group inside its wavefront (sub-wave groups)
+  __device__ Grp() {
+    lane = threadIdx.x % G;
+    goff = (threadIdx.x & 63) & ~(G < 64 ? G - 1 : 63);
+  }
+  __device__ void sync() const {
+    if constexpr (sub) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+      __syncthreads();
+    }
+  }
+  __device__ uint64_t gmask(uint64_t ballot) const {
+    if constexpr (G >= 64) return ballot;
+    else return (ballot >> goff) & ((1ull << G) - 1);
+  }
+  // exclusive rank of pred among group lanes, and the group's total
+  __device__ int rank(bool pred, int& total, int* wscr) const {
+    uint64_t b = __ballot(pred);
+    if constexpr (sub) {
+      uint64_t m = gmask(b);
+      total = __popcll(m);
+      return __popcll(m & ((1ull << lane) - 1));
+    } else {
+      const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = G / 64;
+      if (l == 0) wscr[w] = __popcll(b);
+      __syncthreads();
+      int before = 0, tot = 0;
+      for (int x = 0; x < nw; ++x) {
+        int c = wscr[x];
+        if (x < w) before += c;
+        tot += c;
+      }
+      __syncthreads();
+      total = tot;
+      uint64_t lt = l ? (~0ull >> (64 - l)) : 0ull;
+      return before + __popcll(b & lt);
+    }
+  }
+  __device__ bool any(bool pred, int* wscr) const {
+    int t;
+    rank(pred, t, wscr);
+    return t > 0;
+  }
+  // inclusive scan of int32 over the group
+  __device__ int32_t scan(int32_t x, int32_t& total, int* wscr) const {
+    if constexpr (sub) {
+#pragma unroll
+      for (int d = 1; d < G; d <<= 1) {
+        int32_t y = __shfl_up(x, d, G);
+        if (lane >= d) x += y;
+      }
+      total = __shfl(x, G - 1, G);
+      return x;
+    } else {
+      const int w = threadIdx.x >> 6, l = threadIdx.x & 63, nw = G / 64;
+      x = wave_inclusive_scan(x);
+      if (l == 63) wscr[w] = x;
+      __syncthreads();
+      int32_t before = 0, tot = 0;
+      for (int q = 0; q < nw; ++q) {
+        int32_t c = wscr[q];
+        if (q < w) before += c;
+        tot += c;
+      }
+      __syncthreads();
+      total = tot;
+      return x + before;
+    }
+  }
+  __device__ int64_t bcast64(int64_t v, int src, int64_t* slot) const {
+    if constexpr (sub) {
+      return __shfl(v, src, G);
+    } else {
+      if (lane == src) *slot = v;
+      __syncthreads();
+      int64_t r = *slot;
+      __syncthreads();
+      return r;
+    }
+  }
+};
+
+// largest t in [0, cnt) with pre[t] <= f  (pre non-decreasing, pre[0] = 0)
+__device__ inline int find_seg(const int32_t* pre, int cnt, int32_t f) {
+  int lo = 0, hi = cnt - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= f) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class V>
+__device__ inline V ldv(const void* p, int64_t i) {
+  return ((const V*)p)[i];
+}
+
+// ---------------------------------------------------------------------------
+// LDS open-addressing hash (linear probing), keys -1 = empty
+// ---------------------------------------------------------------------------
+
+template <int SLOTS>
+__device__ inline int hash_insert(int32_t* keys, int32_t c, bool& fresh) {
+  uint32_t h = hash_col(c) >> (32 - __builtin_ctz(SLOTS));
+  for (int p = 0; p < SLOTS; ++p) {
+    int32_t k = keys[h];
+    if (k == c) {
+      fresh = false;
+      return (int)h;
+    }
+    if (k == -1) {
+      int32_t old = atomicCAS(&keys[h], -1, c);
+      if (old == -1) {
+        fresh = true;
+        return (int)h;
+      }
+      if (old == c) {
+        fresh = false;
+        return (int)h;
+      }
+    }
+    h = (h + 1) & (SLOTS - 1);
+  }
+  fresh = false;
+  return -1;
+}
+
+template <int SLOTS>
+__device__ inline int hash_find(const int32_t* keys, int32_t c) {
+  uint32_t h = hash_col(c) >> (32 - __builtin_ctz(SLOTS));
+  for (int p = 0; p < SLOTS; ++p) {
+    int32_t k = keys[h];
+    if (k == c) return (int)h;
+    if (k == -1) return -1;
+    h = (h + 1) & (SLOTS - 1);
+  }
+  return -1;
+}
+
+// Take `ncap` slots of C's pool (lane `0` of the group asks, all get it).
+template <int G>
+__device__ inline int64_t take_pool(const RowArgs& R, int32_t ncap, const Grp<G>& grp, int64_t* slot) {
+  int64_t no = 0;
+  if (grp.lane == 0) no = (int64_t)atomicAdd((unsigned long long*)R.c_top, (unsigned long long)ncap);
+  no = grp.bcast64(no, 0, slot);
+  if (no + ncap > R.c_pool_cap) {
+    if (grp.lane == 0) atomicOr(R.err, 1);
+    return -1;
+  }
+  return no;
+}
+
+// ---------------------------------------------------------------------------
+// bins 0-7: lane group per row, LDS hash
+// ---------------------------------------------------------------------------
+
+template <int SR, int G, int WG>
+__global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* list, int32_t count, int bin) {
+  using S = Sem<SR>;
+  using V = typename S::V;
+  using Acc = typename S::Acc;
+  constexpr int SLOTS = 8 * G;
+  constexpr int GPB = WG / G;
+  __shared__ int32_t hk[GPB][SLOTS];
+  __shared__ Acc hv[GPB][SLOTS];
+  __shared__ int32_t ck[GPB][G];
+  __shared__ V ca[GPB][G];
+  __shared__ int64_t cb[GPB][G];
+  __shared__ int32_t cp[GPB][G + 1];
+  __shared__ int32_t so[GPB][S::order_free ? 1 : G];
+  __shared__ int wscr[16];
+  __shared__ int64_t bslot;
+
+  const Grp<G> grp;
+  const int g = threadIdx.x / G;
+  const int lane = grp.lane;
+  const int64_t qi = (int64_t)blockIdx.x * GPB + g;
+  if (qi >= count) return;  // whole group (whole block when GPB == 1)
+  const int32_t q = list[qi];
+  const int32_t i = R.aff[q];
+  int32_t* keys = hk[g];
+  Acc* vals = hv[g];
+
+  for (int s = lane; s < SLOTS; s += G) {
+    keys[s] = -1;
+    if constexpr (S::order_free) vals[s] = S::identity();
+  }
+  grp.sync();
+
+  const int64_t aoff = R.a_off[i];
+  const int32_t d = R.a_len[i];
+  int64_t flops = 0;
+  bool overflow = false;
+  for (int32_t cbase = 0; cbase < d; cbase += G) {
+    const int32_t t = cbase + lane;
+    const int cnt = min(G, d - cbase);
+    int32_t k = 0, len = 0;
+    V a = V(0);
+    int64_t boff = 0;
+    if (t < d) {
+      k = R.a_col[aoff + t];
+      a = ldv<V>(R.a_val, aoff + t);
+      len = R.b_len[k];
+      boff = R.b_off[k];
+    }
+    int32_t tot;
+    int32_t incl = grp.scan(len, tot, wscr);
+    ck[g][lane] = k;
+    ca[g][lane] = a;
+    cb[g][lane] = boff;
+    cp[g][lane + 1] = incl;
+    if (lane == 0) cp[g][0] = 0;
+    flops += tot;
+    grp.sync();
+    if constexpr (S::order_free) {
+      for (int32_t fb = 0; fb < tot; fb += G) {
+        int32_t f = fb + lane;
+        if (f < tot) {
+          int ts = find_seg(cp[g], cnt, f);
+          int64_t pos = cb[g][ts] + (f - cp[g][ts]);
+          int32_t j = R.b_col[pos];
+          Acc p = S::mul(ca[g][ts], ldv<V>(R.b_val, pos));
+          bool fresh;
+          int h = hash_insert<SLOTS>(keys, j, fresh);
+          if (h >= 0) S::atomic_combine(&vals[h], p);
+          else overflow = true;
+        }
+      }
+    } else {
+      // ascending k inside the chunk (the whole row when d <= G)
+      if (t < d) {
+        int r = 0;
+        for (int x = 0; x < cnt; ++x) r += ck[g][x] < k;
+        so[g][r] = lane;
+      }
+      grp.sync();
+      for (int x = 0; x < cnt; ++x) {
+        const int ts = so[g][x];
+        const int32_t blen = cp[g][ts + 1] - cp[g][ts];
+        const int64_t bo = cb[g][ts];
+        const V av = ca[g][ts];
+        for (int32_t e = lane; e < blen; e += G) {
+          int32_t j = R.b_col[bo + e];
+          Acc p = S::mul(av, ldv<V>(R.b_val, bo + e));
+          bool fresh;
+          int h = hash_insert<SLOTS>(keys, j, fresh);
+          if (h >= 0) vals[h] = fresh ? p : __dadd_rn(vals[h], p);
+          else overflow = true;
+        }
+        grp.sync();
+      }
+    }
+    grp.sync();
+  }
+  if (grp.any(overflow, wscr)) {
+    if (lane == 0) atomicOr(R.err, 2);
+    return;
+  }
+
+  // new row length
+  int32_t nnew = 0;
+  for (int sb = 0; sb < SLOTS; sb += G) {
+    int tot;
+    grp.rank(keys[sb + lane] != -1, tot, wscr);
+    nnew += tot;
+  }
+  const int64_t ooff = R.c_off[i];
+  const int32_t olen = R.c_len[i];
+  bool changed = R.force_write || nnew != olen;
+  int64_t old_read = 0;
+  if (!changed) {
+    old_read = olen;
+    for (int32_t ob = 0; ob < olen; ob += G) {
+      int32_t e = ob + lane;
+      bool bad = false;
+      if (e < olen) {
+        int h = hash_find<SLOTS>(keys, R.c_col[ooff + e]);
+        bad = h < 0 || !same_bits(vals[h], S::to_acc(ldv<V>(R.c_val, ooff + e)));
+      }
+      if (grp.any(bad, wscr)) {
+        changed = true;
+        break;
+      }
+    }
+  }
+  if (changed) {
+    int64_t dest = ooff;
+    int32_t ncap = 0;
+    if (nnew > R.c_cap[i]) {
+      ncap = slack_cap(nnew);
+      dest = take_pool<G>(R, ncap, grp, &bslot);
+      if (dest < 0) return;
+    }
+    int32_t w = 0;
+    for (int sb = 0; sb < SLOTS; sb += G) {
+      const int s = sb + lane;
+      const int32_t key = keys[s];
+      int tot;
+      int r = grp.rank(key != -1, tot, wscr);
+      if (key != -1) {
+        R.c_col[dest + w + r] = key;
+        ((V*)R.c_val)[dest + w + r] = S::from_acc(vals[s]);
+      }
+      w += tot;
+    }
+    if (lane == 0) {
+      R.c_len[i] = nnew;
+      if (ncap) {
+        R.c_off[i] = dest;
+        R.c_cap[i] = ncap;
+      }
+    }
+  }
+  if (lane == 0) {
+    R.chg[q] = changed ? 1 : 0;
+    stat_add(R.stats, bin, 0, 1);
+    stat_add(R.stats, bin, 1, d);
+    stat_add(R.stats, bin, 2, flops);
+    stat_add(R.stats, bin, 3, nnew);
+    stat_add(R.stats, bin, 4, olen);
+    stat_add(R.stats, bin, 5, old_read);
+    stat_add(R.stats, bin, 6, changed ? nnew : 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// A-row chunk staging shared by the workgroup-per-row kernels (bins 8, 9)
+// ---------------------------------------------------------------------------
+
+template <class V>
+struct AChunk {
+  int32_t k[DENSE_ACHUNK];
+  V a[DENSE_ACHUNK];
+  int64_t b[DENSE_ACHUNK];
+  int32_t pre[DENSE_ACHUNK + 1];
+  int32_t so[DENSE_ACHUNK];
+};
+
+// Stage A entries [cbase, cbase+cnt) and prefix sums of their B-row lengths.
+// Returns the chunk's flop count.  Whole-workgroup call.
+template <class V>
+__device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d, int32_t cbase, AChunk<V>& ch,
+                                      const Grp<DENSE_WG>& grp, int* wscr, bool sort_k) {
+  const int lane = grp.lane;
+  const int32_t t = cbase + lane;
+  const bool act = lane < DENSE_ACHUNK && t < d;
+  int32_t k = 0, len = 0;
+  V a = V(0);
+  int64_t boff = 0;
+  if (act) {
+    k = R.a_col[aoff + t];
+    a = ldv<V>(R.a_val, aoff + t);
+    len = R.b_len[k];
+    boff = R.b_off[k];
+  }
+  int32_t tot;
+  int32_t incl = grp.scan(len, tot, wscr);
+  if (lane < DENSE_ACHUNK) {
+    ch.k[lane] = k;
+    ch.a[lane] = a;
+    ch.b[lane] = boff;
+    ch.pre[lane + 1] = incl;
+  }
+  if (lane == 0) ch.pre[0] = 0;
+  grp.sync();
+  if (sort_k) {
+    const int cnt = min(DENSE_ACHUNK, d - cbase);
+    if (act) {
+      int r = 0;
+      for (int x = 0; x < cnt; ++x) r += ch.k[x] < k;
+      ch.so[r] = lane;
+    }
+    grp.sync();
+  }
+  return tot;
+}
+
+// ---------------------------------------------------------------------------
+// bin 8: dense LDS accumulator over column chunks, one workgroup per row
+// ---------------------------------------------------------------------------
+
+template <int SR>
+__global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_t* list, int32_t count) {
+  using S = Sem<SR>;
+  using V = typename S::V;
+  using Acc = typename S::Acc;
+  constexpr int CH = dense_cols<sizeof(V)>();
+  constexpr int PER = CH / DENSE_WG;  // columns per thread in the compaction
+  __shared__ Acc acc[CH];
+  __shared__ uint32_t bits[CH / 32];
+  __shared__ AChunk<V> ch;
+  __shared__ int wscr[16];
+  __shared__ int64_t bslot;
+  const Grp<DENSE_WG> grp;
+  const int tid = threadIdx.x;
+  if ((int64_t)blockIdx.x >= count) return;
+  const int32_t q = list[blockIdx.x];
+  const int32_t i = R.aff[q];
+  const int64_t aoff = R.a_off[i];
+  const int32_t d = R.a_len[i];
+  const int32_t ub = R.ub[q];
+  const int64_t ooff = R.c_off[i];
+  const int32_t olen = R.c_len[i];
+  const int32_t stage_n = min(ub, R.ncols);
+  const size_t stage_bytes = (((size_t)stage_n * (4 + sizeof(V))) + 255) & ~size_t(255);
+  int64_t sbase = 0;
+  if (tid == 0) sbase = (int64_t)atomicAdd(R.arena_top, (unsigned long long)stage_bytes);
+  sbase = grp.bcast64(sbase, 0, &bslot);
+  if (sbase + (int64_t)stage_bytes > R.arena_cap) {
+    if (tid == 0) atomicOr(R.err, 4);
+    return;
+  }
+  int32_t* scol = (int32_t*)(R.arena + sbase);
+  V* sval = (V*)(R.arena + sbase + (size_t)stage_n * 4);
+
+  bool changed = R.force_write;
+  int32_t nnew = 0;
+  int64_t flops = 0;
+  int64_t old_read = 0;
+  const int passes = (R.ncols + CH - 1) / CH;
+  for (int pc = 0; pc < passes; ++pc) {
+    const int32_t c0 = pc * CH;
+    const int32_t c1 = min(c0 + CH, R.ncols);
+    for (int x = tid; x < CH; x += DENSE_WG) acc[x] = S::identity();
+    for (int x = tid; x < CH / 32; x += DENSE_WG) bits[x] = 0u;
+    grp.sync();
+    for (int32_t cbase = 0; cbase < d; cbase += DENSE_ACHUNK) {
+      const int cnt = min(DENSE_ACHUNK, d - cbase);
+      int32_t tot = stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, !S::order_free);
+      if (pc == 0) flops += tot;
+      if constexpr (S::order_free) {
+        for (int32_t fb = 0; fb < tot; fb += DENSE_WG) {
+          int32_t f = fb + tid;
+          if (f < tot) {
+            int ts = find_seg(ch.pre, cnt, f);
+            int64_t pos = ch.b[ts] + (f - ch.pre[ts]);
+            int32_t j = R.b_col[pos];
+            if (j >= c0 && j < c1) {
+              int x = j - c0;
+              S::atomic_combine(&acc[x], S::mul(ch.a[ts], ldv<V>(R.b_val, pos)));
+              atomicOr(&bits[x >> 5], 1u << (x & 31));
+            }
+          }
+        }
+      } else {
+        for (int y = 0; y < cnt; ++y) {
+          const int ts = ch.so[y];
+          const int32_t blen = ch.pre[ts + 1] - ch.pre[ts];
+          const int64_t bo = ch.b[ts];
+          const V av = ch.a[ts];
+          for (int32_t e = tid; e < blen; e += DENSE_WG) {
+            int32_t j = R.b_col[bo + e];
+            if (j >= c0 && j < c1) {
+              int x = j - c0;
+              Acc p = S::mul(av, ldv<V>(R.b_val, bo + e));
+              uint32_t m = 1u << (x & 31);
+              uint32_t was = atomicOr(&bits[x >> 5], m);
+              acc[x] = (was & m) ? __dadd_rn(acc[x], p) : p;
+            }
+          }
+          grp.sync();
+        }
+      }
+      grp.sync();
+    }
+    // compaction of this column chunk, ascending column order
+    int32_t mine = 0;
+    const int x0 = tid * PER;
+    for (int x = x0; x < x0 + PER; x += 32) {
+      uint32_t w = bits[x >> 5];
+      if constexpr (PER < 32) w = (w >> (x & 31)) & ((1u << (PER & 31)) - 1);
+      mine += __popc(w);
+    }
+    int32_t ctot;
+    int32_t excl = grp.scan(mine, ctot, wscr) - mine;
+    int32_t o = nnew + excl;
+    for (int x = x0; x < x0 + PER; ++x) {
+      if ((bits[x >> 5] >> (x & 31)) & 1u) {
+        if (o < stage_n) {
+          scol[o] = c0 + x;
+          sval[o] = S::from_acc(acc[x]);
+        }
+        ++o;
+      }
+    }
+    // compare the old entries that fall into this chunk
+    if (!changed) {
+      int32_t in_chunk = 0;
+      bool bad = false;
+      for (int32_t e = tid; e < olen; e += DENSE_WG) {
+        int32_t c = R.c_col[ooff + e];
+        if (c >= c0 && c < c1) {
+          ++in_chunk;
+          int x = c - c0;
+          bool have = (bits[x >> 5] >> (x & 31)) & 1u;
+          bad |= !have || !same_bits(acc[x], S::to_acc(ldv<V>(R.c_val, ooff + e)));
+        }
+      }
+      int32_t itot;
+      grp.scan(in_chunk, itot, wscr);
+      if (grp.any(bad, wscr) || itot != ctot) changed = true;
+      old_read = olen;
+    }
+    nnew += ctot;
+    grp.sync();
+  }
+  if (nnew > stage_n) {
+    if (tid == 0) atomicOr(R.err, 8);
+    return;
+  }
+  if (changed) {
+    int64_t dest = ooff;
+    int32_t ncap = 0;
+    if (nnew > R.c_cap[i]) {
+      ncap = slack_cap(nnew);
+      dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
+      if (dest < 0) return;
+    }
+    for (int32_t e = tid; e < nnew; e += DENSE_WG) {
+      R.c_col[dest + e] = scol[e];
+      ((V*)R.c_val)[dest + e] = sval[e];
+    }
+    if (tid == 0) {
+      R.c_len[i] = nnew;
+      if (ncap) {
+        R.c_off[i] = dest;
+        R.c_cap[i] = ncap;
+      }
+    }
+  }
+  if (tid == 0) {
+    R.chg[q] = changed ? 1 : 0;
+    stat_add(R.stats, BIN_DENSE, 0, 1);
+    stat_add(R.stats, BIN_DENSE, 1, d);
+    stat_add(R.stats, BIN_DENSE, 2, flops);
+    stat_add(R.stats, BIN_DENSE, 3, nnew);
+    stat_add(R.stats, BIN_DENSE, 4, olen);
+    stat_add(R.stats, BIN_DENSE, 5, old_read);
+    stat_add(R.stats, BIN_DENSE, 6, changed ? nnew : 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// bin 9: hash table in device memory, one workgroup per row
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ inline T aload(const T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline int64_t global_slots(int32_t ub) {
+  int64_t s = 2048;
+  while (s < 2 * (int64_t)ub) s <<= 1;
+  return s;
+}
+
+__device__ inline int64_t ghash_insert(int32_t* keys, int64_t slots, int32_t c, bool& fresh) {
+  int64_t h = (int64_t)(hash_col(c) & (uint32_t)(slots - 1));
+  for (int64_t p = 0; p < slots; ++p) {
+    int32_t k = aload(&keys[h]);
+    if (k == c) {
+      fresh = false;
+      return h;
+    }
+    if (k == -1) {
+      int32_t old = atomicCAS(&keys[h], -1, c);
+      if (old == -1) {
+        fresh = true;
+        return h;
+      }
+      if (old == c) {
+        fresh = false;
+        return h;
+      }
+    }
+    h = (h + 1) & (slots - 1);
+  }
+  fresh = false;
+  return -1;
+}
+
+__device__ inline int64_t ghash_find(const int32_t* keys, int64_t slots, int32_t c) {
+  int64_t h = (int64_t)(hash_col(c) & (uint32_t)(slots - 1));
+  for (int64_t p = 0; p < slots; ++p) {
+    int32_t k = aload(&keys[h]);
+    if (k == c) return h;
+    if (k == -1) return -1;
+    h = (h + 1) & (slots - 1);
+  }
+  return -1;
+}
+
+template <int SR>
+__global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32_t* list, int32_t count) {
+  using S = Sem<SR>;
+  using V = typename S::V;
+  using Acc = typename S::Acc;
+  __shared__ AChunk<V> ch;
+  __shared__ int wscr[16];
+  __shared__ int64_t bslot;
+  const Grp<DENSE_WG> grp;
+  const int tid = threadIdx.x;
+  if ((int64_t)blockIdx.x >= count) return;
+  const int32_t q = list[blockIdx.x];
+  const int32_t i = R.aff[q];
+  const int64_t aoff = R.a_off[i];
+  const int32_t d = R.a_len[i];
+  const int64_t slots = global_slots(R.ub[q]);
+  const size_t tbytes = ((size_t)slots * (4 + sizeof(Acc)) + 255) & ~size_t(255);
+  int64_t tb = 0;
+  if (tid == 0) tb = (int64_t)atomicAdd(R.arena_top, (unsigned long long)tbytes);
+  tb = grp.bcast64(tb, 0, &bslot);
+  if (tb + (int64_t)tbytes > R.arena_cap) {
+    if (tid == 0) atomicOr(R.err, 4);
+    return;
+  }
+  int32_t* keys = (int32_t*)(R.arena + tb);
+  Acc* vals = (Acc*)(R.arena + tb + (size_t)slots * 4);
+  for (int64_t s = tid; s < slots; s += DENSE_WG) {
+    __hip_atomic_store(&keys[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&vals[s], S::identity(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __threadfence();
+  grp.sync();
+  int64_t flops = 0;
+  bool overflow = false;
+  for (int32_t cbase = 0; cbase < d; cbase += DENSE_ACHUNK) {
+    const int cnt = min(DENSE_ACHUNK, d - cbase);
+    int32_t tot = stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, !S::order_free);
+    flops += tot;
+    if constexpr (S::order_free) {
+      for (int32_t fb = 0; fb < tot; fb += DENSE_WG) {
+        int32_t f = fb + tid;
+        if (f < tot) {
+          int ts = find_seg(ch.pre, cnt, f);
+          int64_t pos = ch.b[ts] + (f - ch.pre[ts]);
+          bool fresh;
+          int64_t h = ghash_insert(keys, slots, R.b_col[pos], fresh);
+          if (h >= 0) S::atomic_combine(&vals[h], S::mul(ch.a[ts], ldv<V>(R.b_val, pos)));
+          else overflow = true;
+        }
+      }
+    } else {
+      for (int y = 0; y < cnt; ++y) {
+        const int ts = ch.so[y];
+        const int32_t blen = ch.pre[ts + 1] - ch.pre[ts];
+        const int64_t bo = ch.b[ts];
+        const V av = ch.a[ts];
+        for (int32_t e = tid; e < blen; e += DENSE_WG) {
+          Acc p = S::mul(av, ldv<V>(R.b_val, bo + e));
+          bool fresh;
+          int64_t h = ghash_insert(keys, slots, R.b_col[bo + e], fresh);
+          if (h < 0) {
+            overflow = true;
+          } else if (fresh) {
+            __hip_atomic_store(&vals[h], p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            Acc cur = aload(&vals[h]);
+            __hip_atomic_store(&vals[h], __dadd_rn(cur, p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+        __threadfence();
+        grp.sync();
+      }
+    }
+    __threadfence();
+    grp.sync();
+  }
+  if (grp.any(overflow, wscr)) {
+    if (tid == 0) atomicOr(R.err, 2);
+    return;
+  }
+  int32_t nnew = 0;
+  for (int64_t sb = 0; sb < slots; sb += DENSE_WG) {
+    int tot;
+    grp.rank(aload(&keys[sb + tid]) != -1, tot, wscr);
+    nnew += tot;
+  }
+  const int64_t ooff = R.c_off[i];
+  const int32_t olen = R.c_len[i];
+  bool changed = R.force_write || nnew != olen;
+  int64_t old_read = 0;
+  if (!changed) {
+    old_read = olen;
+    for (int32_t ob = 0; ob < olen; ob += DENSE_WG) {
+      int32_t e = ob + tid;
+      bool bad = false;
+      if (e < olen) {
+        int64_t h = ghash_find(keys, slots, R.c_col[ooff + e]);
+        bad = h < 0 || !same_bits(aload(&vals[h]), S::to_acc(ldv<V>(R.c_val, ooff + e)));
+      }
+      if (grp.any(bad, wscr)) {
+        changed = true;
+        break;
+      }
+    }
+  }
+  if (changed) {
+    int64_t dest = ooff;
+    int32_t ncap = 0;
+    if (nnew > R.c_cap[i]) {
+      ncap = slack_cap(nnew);
+      dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
+      if (dest < 0) return;
+    }
+    int32_t w = 0;
+    for (int64_t sb = 0; sb < slots; sb += DENSE_WG) {
+      const int64_t s = sb + tid;
+      const int32_t key = aload(&keys[s]);
+      int tot;
+      int r = grp.rank(key != -1, tot, wscr);
+      if (key != -1) {
+        R.c_col[dest + w + r] = key;
+        ((V*)R.c_val)[dest + w + r] = S::from_acc(aload(&vals[s]));
+      }
+      w += tot;
+    }
+    if (tid == 0) {
+      R.c_len[i] = nnew;
+      if (ncap) {
+        R.c_off[i] = dest;
+        R.c_cap[i] = ncap;
+      }
+    }
+  }
+  if (tid == 0) {
+    R.chg[q] = changed ? 1 : 0;
+    stat_add(R.stats, BIN_GLOBAL, 0, 1);
+    stat_add(R.stats, BIN_GLOBAL, 1, d);
+    stat_add(R.stats, BIN_GLOBAL, 2, flops);
+    stat_add(R.stats, BIN_GLOBAL, 3, nnew);
+    stat_add(R.stats, BIN_GLOBAL, 4, olen);
+    stat_add(R.stats, BIN_GLOBAL, 5, old_read);
+    stat_add(R.stats, BIN_GLOBAL, 6, changed ? nnew : 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// discovery and analysis
+// ---------------------------------------------------------------------------
+
+__global__ void k_mark_changed(int32_t n, const uint32_t* epoch, uint32_t since, uint8_t* flags) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = epoch[i] > since ? 1 : 0;
+}
+
+// one wavefront per changed row k of B: flag every row i with A'[i,k] present
+__global__ __launch_bounds__(256) void k_scatter_dB(const int32_t* dB, const int32_t* d_nB,
+                                                    const int64_t* t_off, const int32_t* t_len,
+                                                    const int32_t* t_col, uint8_t* aff) {
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  const int32_t nB = *d_nB;
+  for (int64_t x = wv; x < nB; x += nw) {
+    int32_t k = dB[x];
+    int64_t o = t_off[k];
+    int32_t l = t_len[k];
+    for (int32_t e = lane; e < l; e += 64) aff[t_col[o + e]] = 1;
+  }
+}
+
+struct Tun {
+  int32_t group_ub[8];
+  int32_t dense_passes;  // passes the dense bin needs for this product
+  int32_t dense_max_passes;
+  int32_t force_bin;
+  int32_t fp64;
+};
+
+struct Plan {
+  int32_t count;         // affected rows
+  int32_t pad;
+  unsigned long long bin_count[NBINS];
+  unsigned long long c_demand;
+  unsigned long long arena_demand;
+};
+
+__device__ inline int pick_bin(int32_t ub, int32_t d, const Tun& T) {
+  if (T.force_bin >= BIN_DENSE) return T.force_bin;
+  int first = 0;
+  if (T.fp64) {  // the lane group must hold the whole A row to sum in ascending k
+    while (first < 8 && (8 << first) < d) ++first;
+  }
+  if (T.force_bin >= 0) first = max(first, T.force_bin);
+  for (int b = first; b < 8; ++b)
+    if (T.group_ub[b] > 0 && ub <= T.group_ub[b] && ub <= (32 << b)) return b;
+  return T.dense_passes <= T.dense_max_passes ? BIN_DENSE : BIN_GLOBAL;
+}
+
+// 16 lanes per affected row: flops, ub, bin; empty output rows are finished here
+__global__ __launch_bounds__(256) void k_analyze(RowArgs R, const int32_t* d_count, Tun T, Plan* plan,
+                                                 int32_t* bins, int32_t bin_stride) {
+  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+  const int l = threadIdx.x & 15;
+  if (q >= *d_count) return;
+  const int32_t i = R.aff[q];
+  const int64_t aoff = R.a_off[i];
+  const int32_t d = R.a_len[i];
+  int64_t f = 0;
+  for (int32_t t = l; t < d; t += 16) f += R.b_len[R.a_col[aoff + t]];
+  for (int s = 8; s > 0; s >>= 1) f += __shfl_xor(f, s, 16);
+  if (l != 0) return;
+  const int32_t ub = (int32_t)min(f, (int64_t)R.ncols);
+  R.ub[q] = ub;
+  if (ub == 0) {
+    const int32_t olen = R.c_len[i];
+    bool changed = R.force_write || olen != 0;
+    R.c_len[i] = 0;
+    R.chg[q] = changed ? 1 : 0;
+    stat_add(R.stats, 0, 0, 1);
+    stat_add(R.stats, 0, 1, d);
+    stat_add(R.stats, 0, 4, olen);
+    return;
+  }
+  const int b = pick_bin(ub, d, T);
+  unsigned long long pos = atomicAdd(&plan->bin_count[b], 1ull);
+  bins[(int64_t)b * bin_stride + (int64_t)pos] = (int32_t)q;
+  if (ub > R.c_cap[i]) atomicAdd(&plan->c_demand, (unsigned long long)slack_cap(ub));
+  if (b == BIN_DENSE) {
+    size_t sb = ((size_t)min(ub, R.ncols) * (4 + (T.fp64 ? 8 : 8)) + 255) & ~size_t(255);
+    atomicAdd(&plan->arena_demand, (unsigned long long)sb);
+  } else if (b == BIN_GLOBAL) {
+    int64_t slots = global_slots(ub);
+    atomicAdd(&plan->arena_demand, (unsigned long long)(((size_t)slots * 12 + 255) & ~size_t(255)));
+  }
+}
+
+__global__ void k_set_count(int32_t* d, int32_t v) { *d = v; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+namespace {
+
+int dense_passes_for(int vsz, int32_t ncols) {
+  int ch = vsz == 8 ? dense_cols<8>() : dense_cols<4>();
+  return (ncols + ch - 1) / ch;
+}
+
+template <int SR>
+void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, const Plan& plan,
+                 std::vector<std::pair<int, size_t>>& timed) {
+  hipStream_t s = c->stream;
+  static const char* names[NBINS] = {"rows_g8", "rows_g16", "rows_g32", "rows_g64", "rows_g128",
+                                     "rows_g256", "rows_g512", "rows_g1024", "rows_dense", "rows_global"};
+  for (int b = 0; b < NBINS; ++b) {
+    int32_t cnt = (int32_t)plan.bin_count[b];
+    if (cnt == 0) continue;
+    const int32_t* list = bins + (int64_t)b * stride;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+      ctx_timing_begin(c, names[b], 0.0, &e0, &e1);
+      timed.push_back({b, c->timings.size() - 1});
+    }
+    switch (b) {
+#define GROUP_CASE(B, G, WG)                                                                          \
+  case B:                                                                                             \
+    hipLaunchKernelGGL((k_rows_group<SR, G, WG>), dim3(blocks_for(cnt, WG / G)), dim3(WG), 0, s, R,   \
+                       list, cnt, B);                                                                 \
+    break;
+      GROUP_CASE(0, 8, 256)
+      GROUP_CASE(1, 16, 256)
+      GROUP_CASE(2, 32, 256)
+      GROUP_CASE(3, 64, 256)
+      GROUP_CASE(4, 128, 128)
+      GROUP_CASE(5, 256, 256)
+      GROUP_CASE(6, 512, 512)
+      GROUP_CASE(7, 1024, 1024)
+#undef GROUP_CASE
+      case BIN_DENSE:
+        hipLaunchKernelGGL((k_rows_dense<SR>), dim3(cnt), dim3(DENSE_WG), 0, s, R, list, cnt);
+        break;
+      case BIN_GLOBAL:
+        hipLaunchKernelGGL((k_rows_global<SR>), dim3(cnt), dim3(DENSE_WG), 0, s, R, list, cnt);
+        break;
+    }
+    if (c->timing) ctx_timing_end(c, e1);
+  }
+  DSG_HIP(hipGetLastError());
+}
+
+struct ProdWork {
+  uint8_t* aff_flags;
+  uint8_t* b_flags;
+  int32_t* aff;
+  int32_t* d_count;
+  int32_t* dB;
+  int32_t* d_nB;
+  int32_t* ub;
+  uint8_t* chg;
+  int32_t* bins;
+  Plan* plan;
+  unsigned long long* stats;
+  int* err;
+  int32_t* d_nchg;
+  void* cscr;
+};
+
+}  // namespace
+
+DProd* prod_create(Ctx* c, DMat* A, DMat* B) {
+  DProd* p = new DProd();
+  p->ctx = c;
+  p->A = A;
+  p->B = B;
+  try {
+    mat_build_transpose(A);
+    p->C = mat_create(c, A->nrows, B->ncols, A->sr, nullptr, nullptr, nullptr);
+  } catch (...) {
+    delete p;
+    throw;
+  }
+  A->refs++;
+  B->refs++;
+  try {
+    prod_run(p, 1, true);
+  } catch (...) {
+    prod_destroy(p);
+    throw;
+  }
+  return p;
+}
+
+void prod_destroy(DProd* p) {
+  if (!p) return;
+  Ctx* c = p->ctx;
+  if (p->changed_rows) ctx_free(c, p->changed_rows, (size_t)p->changed_cap * 4);
+  if (p->query_rows) ctx_free(c, p->query_rows, (size_t)p->query_cap * 4);
+  if (p->arena) ctx_free(c, p->arena, p->arena_bytes);
+  if (p->C) mat_destroy(p->C);
+  if (p->A) p->A->refs--;
+  if (p->B) p->B->refs--;
+  delete p;
+}
+
+int32_t prod_run(DProd* p, int mode, bool report_affected) {
+  Ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  DMat* A = p->A;
+  DMat* B = p->B;
+  DMat* C = p->C;
+  const int32_t n = A->nrows;
+  const int64_t N = n > 0 ? n : 1;
+  const int64_t nB = B->nrows > 0 ? B->nrows : 1;
+  const size_t need = Carve::need({(size_t)N, (size_t)nB, (size_t)N * 4, 64, (size_t)nB * 4, 64, (size_t)N * 4, (size_t)N,
+                                   (size_t)N * 4 * NBINS, sizeof(Plan) + 64, NBINS * NSTAT * 8 + 64, 64,
+                                   64, compact_scratch_bytes(std::max(N, nB)) + 64});
+  Carve cv(ctx_scratch(c, need), need);
+  ProdWork w;
+  w.aff_flags = cv.take<uint8_t>(N);
+  w.b_flags = cv.take<uint8_t>(nB);
+  w.aff = cv.take<int32_t>(N);
+  w.d_count = cv.take<int32_t>(16);
+  w.dB = cv.take<int32_t>(nB);
+  w.d_nB = cv.take<int32_t>(16);
+  w.ub = cv.take<int32_t>(N);
+  w.chg = cv.take<uint8_t>(N);
+  w.bins = cv.take<int32_t>(N * NBINS);
+  w.plan = cv.take<Plan>(1);
+  w.stats = cv.take<unsigned long long>(NBINS * NSTAT);
+  w.err = cv.take<int>(16);
+  w.d_nchg = cv.take<int32_t>(16);
+  w.cscr = cv.take<char>(compact_scratch_bytes(std::max(N, nB)) + 64);
+
+  DSG_HIP(hipMemsetAsync(w.plan, 0, sizeof(Plan), s));
+  DSG_HIP(hipMemsetAsync(w.stats, 0, NBINS * NSTAT * 8, s));
+  DSG_HIP(hipMemsetAsync(w.err, 0, 4, s));
+  // ---- affected rows ----
+  if (mode == 1) {
+    iota_i32(w.aff, n, s);
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, w.d_count, n);
+  } else if (n > 0) {
+    hipLaunchKernelGGL(k_mark_changed, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->row_epoch, p->syncA,
+                       w.aff_flags);
+    if (B->nrows > 0) {
+      // changed rows of B
+      hipLaunchKernelGGL(k_mark_changed, dim3(blocks_for(B->nrows, 256)), dim3(256), 0, s, B->nrows,
+                         B->row_epoch, p->syncB, w.b_flags);
+      compact_flags(w.b_flags, B->nrows, w.dB, w.d_nB, w.cscr, s);
+      DMat* T = A->tidx;
+      unsigned nbk = (unsigned)std::min<int64_t>(blocks_for((int64_t)B->nrows * 64, 256), 8192);
+      hipLaunchKernelGGL(k_scatter_dB, dim3(nbk), dim3(256), 0, s, w.dB, w.d_nB, T->row_off, T->row_len, T->col,
+                         w.aff_flags);
+    }
+    compact_flags(w.aff_flags, n, w.aff, w.d_count, w.cscr, s);
+  } else {
+    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, w.d_count, 0);
+  }
+
+  RowArgs R;
+  R.a_off = A->row_off; R.a_len = A->row_len; R.a_col = A->col; R.a_val = A->val;
+  R.b_off = B->row_off; R.b_len = B->row_len; R.b_col = B->col; R.b_val = B->val;
+  R.c_off = C->row_off; R.c_len = C->row_len; R.c_cap = C->row_cap; R.c_col = C->col; R.c_val = C->val;
+  R.c_top = C->d_top; R.c_pool_cap = C->pool_cap;
+  R.ncols = B->ncols;
+  R.aff = w.aff; R.ub = w.ub; R.chg = w.chg; R.stats = w.stats;
+  R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
+  R.force_write = (mode == 1 || report_affected) ? 1 : 0;
+  R.err = w.err;
+
+  Tun T;
+  const dsg_tuning& tu = c->tuning;
+  for (int b = 0; b < 8; ++b) T.group_ub[b] = tu.group_ub[b];
+  T.dense_passes = dense_passes_for(C->vsz, B->ncols);
+  T.dense_max_passes = tu.dense_max_passes;
+  T.force_bin = tu.force_bin;
+  T.fp64 = A->sr == 2 ? 1 : 0;
+  if (n > 0) {
+    hipLaunchKernelGGL(k_analyze, dim3(blocks_for((int64_t)n * 16, 256)), dim3(256), 0, s, R, w.d_count, T,
+                       w.plan, w.bins, n);
+  }
+  // ---- host round trip 1: bin sizes and space needs ----
+  Plan* hp = (Plan*)c->pinned;
+  DSG_HIP(hipMemcpyAsync(hp, w.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipMemcpyAsync(&hp->count, w.d_count, 4, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  Plan plan = *hp;
+  if (plan.c_demand > 0) {
+    mat_reserve(C, (int64_t)plan.c_demand);
+    C->h_top_ub += (int64_t)plan.c_demand;
+  }
+  if (plan.arena_demand > 0) {
+    if (plan.arena_demand > p->arena_bytes) {
+      if (p->arena) ctx_free(c, p->arena, p->arena_bytes);
+      p->arena = nullptr;
+      size_t nb = plan.arena_demand + plan.arena_demand / 4 + 4096;
+      p->arena = ctx_alloc(c, nb);
+      p->arena_bytes = nb;
+    }
+    if (!p->arena_top) p->arena_top = (unsigned long long*)ctx_alloc(c, 64);
+    DSG_HIP(hipMemsetAsync(p->arena_top, 0, 8, s));
+  }
+  R.c_col = C->col; R.c_val = C->val; R.c_off = C->row_off; R.c_top = C->d_top; R.c_pool_cap = C->pool_cap;
+  R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
+
+  std::vector<std::pair<int, size_t>> timed;
+  switch (A->sr) {
+    case 0: launch_bins<0>(c, R, w.bins, n, plan, timed); break;
+    case 1: launch_bins<1>(c, R, w.bins, n, plan, timed); break;
+    default: launch_bins<2>(c, R, w.bins, n, plan, timed); break;
+  }
+  // ---- reported rows ----
+  if ((int64_t)plan.count > p->changed_cap) {
+    if (p->changed_rows) ctx_free(c, p->changed_rows, (size_t)p->changed_cap * 4);
+    p->changed_rows = nullptr;
+    p->changed_cap = std::max<int64_t>(plan.count, 1024);
+    p->changed_rows = (int32_t*)ctx_alloc(c, (size_t)p->changed_cap * 4);
+  }
+  compact_list_by_flags(w.aff, w.chg, w.d_count, std::max<int32_t>(plan.count, 1), p->changed_rows, w.d_nchg,
+                        w.cscr, s);
+  // ---- host round trip 2: row count, statistics, errors ----
+  struct Tail {
+    int32_t nchg;
+    int32_t err;
+    unsigned long long stats[NBINS * NSTAT];
+  };
+  Tail* ht = (Tail*)c->pinned;
+  DSG_HIP(hipMemcpyAsync(&ht->nchg, w.d_nchg, 4, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipMemcpyAsync(&ht->err, w.err, 4, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipMemcpyAsync(ht->stats, w.stats, sizeof(ht->stats), hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  Tail tail = *ht;
+  DSG_REQUIRE(tail.err == 0, DSG_E_DEVICE,
+              "internal: row kernel reported error code " + std::to_string(tail.err));
+  p->syncA = A->epoch;
+  p->syncB = B->epoch;
+  dsg_update_stats& st = p->stats;
+  st = dsg_update_stats{};
+  st.affected_rows = plan.count;
+  st.changed_rows = tail.nchg;
+  const double sz = 4.0 + (double)C->vsz;
+  for (int b = 0; b < NBINS; ++b) {
+    const unsigned long long* x = tail.stats + b * NSTAT;
+    st.bin_rows[b] = (int64_t)x[0];
+    st.bin_flops[b] = (int64_t)x[2];
+    st.a_entries += (int64_t)x[1];
+    st.flops += (int64_t)x[2];
+    st.nnz_new += (int64_t)x[3];
+    st.nnz_old += (int64_t)x[4];
+  }
+  for (auto& tb : timed) {
+    const unsigned long long* x = tail.stats + tb.first * NSTAT;
+    // A row, B row lookups (offset + length), B entries, old C row when compared, new C row when written
+    c->timings[tb.second].bytes = sz * (double)x[1] + 12.0 * (double)x[1] + sz * (double)x[2] +
+                                  sz * (double)x[5] + sz * (double)x[6];
+  }
+  return tail.nchg;
+}

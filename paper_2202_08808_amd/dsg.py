@@ -1,0 +1,328 @@
+"""Thin Python binding of ``libdsg.so`` (declared in ``include/dsg.h``).
+
+Argument marshalling only: every step of the update and multiply path runs in
+the library's HIP kernels.  Arrays may be numpy arrays (host memory) or torch
+tensors on the GPU (device memory, passed with DSG_INPUT_DEVICE).  The
+library is required: importing this module fails loudly if it is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdsg.so")
+
+OK, E_ARG, E_RANGE, E_OOM, E_DEVICE, E_STATE, E_UNSUPPORTED = range(7)
+PLUS_TIMES_I64, MIN_PLUS_F32, PLUS_TIMES_F64 = 0, 1, 2
+OP_SET, OP_DELETE, OP_ADD = 0, 1, 2
+INPUT_DEVICE, SYNC, REPORT_AFFECTED = 0x1, 0x2, 0x4
+DTYPE = {PLUS_TIMES_I64: np.int64, MIN_PLUS_F32: np.float32, PLUS_TIMES_F64: np.float64}
+NAMES = {OK: "DSG_OK", E_ARG: "DSG_E_ARG", E_RANGE: "DSG_E_RANGE", E_OOM: "DSG_E_OOM",
+         E_DEVICE: "DSG_E_DEVICE", E_STATE: "DSG_E_STATE", E_UNSUPPORTED: "DSG_E_UNSUPPORTED"}
+
+P = ctypes.c_void_p
+
+
+class DsgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Rows(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("rows", P), ("row_off", P), ("row_len", P), ("col", P),
+                ("val", P)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("group_ub", ctypes.c_int32 * 8), ("dense_max_passes", ctypes.c_int32),
+                ("force_bin", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("affected_rows", ctypes.c_int64), ("changed_rows", ctypes.c_int64),
+                ("a_entries", ctypes.c_int64), ("flops", ctypes.c_int64),
+                ("nnz_new", ctypes.c_int64), ("nnz_old", ctypes.c_int64),
+                ("bin_rows", ctypes.c_int64 * 10), ("bin_flops", ctypes.c_int64 * 10)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("bin_")}
+        d["bin_rows"] = list(self.bin_rows)
+        d["bin_flops"] = list(self.bin_flops)
+        return d
+
+
+SIGNATURES = {
+    "dsg_ctx_create": [ctypes.c_int, P, ctypes.c_size_t, P],
+    "dsg_ctx_destroy": [P],
+    "dsg_ctx_synchronize": [P],
+    "dsg_ctx_memory": [P, P],
+    "dsg_ctx_set_timing": [P, ctypes.c_int],
+    "dsg_ctx_timing_report": [P, ctypes.c_char_p, ctypes.c_size_t],
+    "dsg_ctx_get_tuning": [P, P],
+    "dsg_ctx_set_tuning": [P, P],
+    "dsg_mat_create": [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, ctypes.c_uint32, P],
+    "dsg_mat_apply": [P, P, P, P, P, ctypes.c_int64, ctypes.c_uint32],
+    "dsg_mat_nnz": [P, P],
+    "dsg_mat_shape": [P, P, P, P],
+    "dsg_mat_export": [P, P, P, P, ctypes.c_int64, P],
+    "dsg_mat_destroy": [P],
+    "dsg_prod_create_static": [P, P, P, P],
+    "dsg_prod_recompute_static": [P, ctypes.c_uint32],
+    "dsg_prod_update": [P, ctypes.c_uint32, P],
+    "dsg_prod_rows": [P, P, ctypes.c_int32, ctypes.c_uint32, P],
+    "dsg_rows_export": [P, P, P, P, P, ctypes.c_int64, P],
+    "dsg_prod_nnz": [P, P],
+    "dsg_prod_export": [P, P, P, P, ctypes.c_int64, P],
+    "dsg_prod_stats": [P, P],
+    "dsg_prod_destroy": [P],
+}
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+                          " (the GPU path has no fallback)")
+    L = ctypes.CDLL(path)
+    for name, args in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.dsg_last_error.argtypes = [P]
+    L.dsg_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_L: Optional[ctypes.CDLL] = None
+
+
+def lib() -> ctypes.CDLL:
+    global _L
+    if _L is None:
+        _L = load()
+    return _L
+
+
+def _ptr(a):
+    """(pointer, is_device) of a numpy array or a torch tensor."""
+    if a is None:
+        return None, False
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be contiguous")
+        return a.ctypes.data_as(P), False
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return P(a.data_ptr()), bool(a.is_cuda)
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None, budget: int = 0):
+        """stream: a torch.cuda.Stream (or None for the library's own)."""
+        self.L = lib()
+        h = P()
+        s = None if stream is None else P(stream.cuda_stream)
+        self._check(self.L.dsg_ctx_create(device, s, budget, ctypes.byref(h)), None)
+        self.h = h
+
+    def _check(self, st, h="self"):
+        if st != OK:
+            hh = self.h if h == "self" else h
+            msg = self.L.dsg_last_error(hh)
+            raise DsgError(st, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._check(self.L.dsg_ctx_destroy(self.h))
+            self.h = None
+
+    def synchronize(self):
+        self._check(self.L.dsg_ctx_synchronize(self.h))
+
+    def memory(self) -> int:
+        v = ctypes.c_size_t()
+        self._check(self.L.dsg_ctx_memory(self.h, ctypes.byref(v)))
+        return v.value
+
+    def set_timing(self, on: bool):
+        self._check(self.L.dsg_ctx_set_timing(self.h, 1 if on else 0))
+
+    def timing_report(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self.L.dsg_ctx_timing_report(self.h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def get_tuning(self) -> Tuning:
+        t = Tuning()
+        self._check(self.L.dsg_ctx_get_tuning(self.h, ctypes.byref(t)))
+        return t
+
+    def set_tuning(self, t: Optional[Tuning]):
+        self._check(self.L.dsg_ctx_set_tuning(self.h, None if t is None else ctypes.byref(t)))
+
+
+class Matrix:
+    def __init__(self, ctx: Context, nrows: int, ncols: int, semiring: int, row_ptr=None, col=None, val=None):
+        self.ctx, self.L = ctx, ctx.L
+        self.nrows, self.ncols, self.semiring = int(nrows), int(ncols), int(semiring)
+        h = P()
+        flags = 0
+        prp, dev = _ptr(row_ptr)
+        pci, _ = _ptr(col)
+        pv, _ = _ptr(val)
+        if dev:
+            flags |= INPUT_DEVICE
+        ctx._check(self.L.dsg_mat_create(ctx.h, self.nrows, self.ncols, self.semiring, prp, pci, pv, flags,
+                                         ctypes.byref(h)))
+        self.h = h
+
+    @classmethod
+    def from_csr(cls, ctx: Context, csr, semiring: int):
+        return cls(ctx, csr.nrows, csr.ncols, semiring, np.ascontiguousarray(csr.row_ptr, np.int64),
+                   np.ascontiguousarray(csr.col, np.int32),
+                   np.ascontiguousarray(csr.val, DTYPE[semiring]))
+
+    def apply(self, rows, cols, vals, ops, sync: bool = False):
+        n = int(rows.shape[0])
+        pr, dev = _ptr(rows)
+        pc, _ = _ptr(cols)
+        pv, _ = _ptr(vals)
+        po, _ = _ptr(ops)
+        flags = (INPUT_DEVICE if dev else 0) | (SYNC if sync else 0)
+        self.ctx._check(self.L.dsg_mat_apply(self.h, pr, pc, pv, po, n, flags))
+
+    def apply_batch(self, b, sync: bool = False):
+        self.apply(b.rows, b.cols, b.vals, b.ops, sync)
+
+    def nnz(self) -> int:
+        v = ctypes.c_int64()
+        self.ctx._check(self.L.dsg_mat_nnz(self.h, ctypes.byref(v)))
+        return v.value
+
+    def export(self):
+        return _export(self.ctx, self.L.dsg_mat_export, self.h, self.nrows, self.ncols, self.semiring)
+
+    def destroy(self):
+        if self.h:
+            self.ctx._check(self.L.dsg_mat_destroy(self.h))
+            self.h = None
+
+
+class Csr:
+    def __init__(self, nrows, ncols, row_ptr, col, val):
+        self.nrows, self.ncols = nrows, ncols
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+
+    @property
+    def nnz(self):
+        return int(self.row_ptr[-1])
+
+
+def _export(ctx, fn, h, nrows, ncols, semiring):
+    nnz = ctypes.c_int64()
+    rp = np.zeros(nrows + 1, np.int64)
+    ctx._check(fn(h, rp.ctypes.data_as(P), None, None, 0, ctypes.byref(nnz)))
+    col = np.zeros(max(nnz.value, 1), np.int32)
+    val = np.zeros(max(nnz.value, 1), DTYPE[semiring])
+    ctx._check(fn(h, rp.ctypes.data_as(P), col.ctypes.data_as(P), val.ctypes.data_as(P), col.size,
+                  ctypes.byref(nnz)))
+    return Csr(nrows, ncols, rp, col[:nnz.value], val[:nnz.value])
+
+
+class RowSet:
+    """Device views returned by Product.update / Product.rows."""
+
+    def __init__(self, prod: "Product", v: Rows):
+        self.prod, self.v = prod, v
+
+    @property
+    def n(self) -> int:
+        return int(self.v.n)
+
+    def to_host(self):
+        """(rows, row_ptr, col, val) with each row sorted by column."""
+        p = self.prod
+        L = p.L
+        nnz = ctypes.c_int64()
+        rp = np.zeros(self.n + 1, np.int64)
+        p.ctx._check(L.dsg_rows_export(p.h, ctypes.byref(self.v), rp.ctypes.data_as(P), None, None, 0,
+                                       ctypes.byref(nnz)))
+        col = np.zeros(max(nnz.value, 1), np.int32)
+        val = np.zeros(max(nnz.value, 1), DTYPE[p.semiring])
+        p.ctx._check(L.dsg_rows_export(p.h, ctypes.byref(self.v), rp.ctypes.data_as(P), col.ctypes.data_as(P),
+                                       val.ctypes.data_as(P), col.size, ctypes.byref(nnz)))
+        return self.row_ids(), rp, col[:nnz.value], val[:nnz.value]
+
+    def row_ids(self) -> np.ndarray:
+        """The view's row list, copied from device memory."""
+        out = np.zeros(self.n, np.int32)
+        if self.n:
+            self.prod.ctx.synchronize()
+            st = _hip().hipMemcpy(out.ctypes.data_as(P), self.v.rows, self.n * 4, 2)  # device to host
+            if st != 0:
+                raise DsgError(E_DEVICE, f"hipMemcpy failed ({st})")
+        return out
+
+
+_HIP = None
+
+
+def _hip():
+    global _HIP
+    if _HIP is None:
+        _HIP = ctypes.CDLL("libamdhip64.so")
+        _HIP.hipMemcpy.argtypes = [P, P, ctypes.c_size_t, ctypes.c_int]
+        _HIP.hipMemcpy.restype = ctypes.c_int
+    return _HIP
+
+
+class Product:
+    def __init__(self, ctx: Context, A: Matrix, B: Matrix):
+        self.ctx, self.L = ctx, ctx.L
+        self.A, self.B = A, B
+        self.semiring = A.semiring
+        self.nrows, self.ncols = A.nrows, B.ncols
+        h = P()
+        ctx._check(self.L.dsg_prod_create_static(ctx.h, A.h, B.h, ctypes.byref(h)))
+        self.h = h
+
+    def update(self, report_affected: bool = False) -> RowSet:
+        v = Rows()
+        self.ctx._check(self.L.dsg_prod_update(self.h, REPORT_AFFECTED if report_affected else 0,
+                                               ctypes.byref(v)))
+        return RowSet(self, v)
+
+    def recompute_static(self):
+        self.ctx._check(self.L.dsg_prod_recompute_static(self.h, 0))
+
+    def rows(self, rows) -> RowSet:
+        v = Rows()
+        pr, dev = _ptr(rows)
+        n = int(rows.shape[0])
+        self.ctx._check(self.L.dsg_prod_rows(self.h, pr, n, INPUT_DEVICE if dev else 0, ctypes.byref(v)))
+        return RowSet(self, v)
+
+    def nnz(self) -> int:
+        v = ctypes.c_int64()
+        self.ctx._check(self.L.dsg_prod_nnz(self.h, ctypes.byref(v)))
+        return v.value
+
+    def export(self):
+        return _export(self.ctx, self.L.dsg_prod_export, self.h, self.nrows, self.ncols, self.semiring)
+
+    def stats(self) -> dict:
+        s = Stats()
+        self.ctx._check(self.L.dsg_prod_stats(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def destroy(self):
+        if self.h:
+            self.ctx._check(self.L.dsg_prod_destroy(self.h))
+            self.h = None

@@ -1,0 +1,52 @@
+"""The C ABI library loads and exports every function that include/dsg.h
+declares; calls fail cleanly without a GPU.  No device work here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2202_08808_amd import dsg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "dsg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dsg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ["dsg_ctx_create", "dsg_mat_create", "dsg_mat_apply", "dsg_prod_create_static",
+                 "dsg_prod_update", "dsg_prod_recompute_static", "dsg_prod_rows", "dsg_mat_export"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(dsg.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    assert set(declared_functions()) <= set(dsg.SIGNATURES) | {"dsg_last_error"}
+
+
+def test_null_arguments_are_rejected():
+    L = dsg.lib()
+    assert L.dsg_ctx_create(0, None, 0, None) == dsg.E_ARG
+    assert L.dsg_ctx_destroy(None) == dsg.E_ARG
+    assert L.dsg_mat_apply(None, None, None, None, None, 0, 0) == dsg.E_ARG
+    assert L.dsg_prod_update(None, 0, None) == dsg.E_ARG
+    assert L.dsg_last_error(None)
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd") and os.access("/dev/kfd", os.R_OK),
+                    reason="a GPU is present")
+def test_no_device_reports_device_error():
+    L = dsg.lib()
+    h = ctypes.c_void_p()
+    assert L.dsg_ctx_create(0, None, 0, ctypes.byref(h)) == dsg.E_DEVICE
+    assert b"device" in L.dsg_last_error(None)
