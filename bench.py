@@ -1,0 +1,227 @@
+"""Benchmark of batch-dynamic SpGEMM on one MI355X.
+
+One step = the whole hot path over one update batch: ingest the batch into
+the dynamic operand (sort, fold, apply, transpose index), find the affected
+rows, recompute them with the binned row kernels, and merge them into C.
+Batches are uploaded to HBM before the timed region.
+
+Prints one JSON line (metric: dynamic-SpGEMM updates/s) with the speedup over
+a static recompute on the same GPU, the p99 batch latency, the roofline of
+the dominant row kernel (algorithmic bytes / measured time, HIP events on the
+library's stream) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_workload(name: str, batch: int, count: int):
+    from paper_2202_08808_amd import inputs as I
+    if name == "rmat16":
+        return I.workload_rmat16_minplus(batch=batch, n_batches=count)
+    if name == "rmat12":
+        return I.workload_rmat12_i64(n_batches=count, batch=batch)
+    if name == "stencil":
+        return I.workload_stencil_f64(n_batches=count)
+    if name == "er":
+        return I.workload_er_minplus(n_batches=count, batch=batch)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, n_batches: int, budget_s: float = 20.0):
+    """The oracle as it stands: apply the batch, recompute C' = A'B' from
+    scratch; timed on this host's cores, on a bounded number of batches."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    A = oracle.Csr.of(w.A)
+    B = None if w.B is None else oracle.Csr.of(w.B)
+    done = 0
+    updates = 0
+    t0 = time.perf_counter()
+    for t in range(n_batches):
+        b = w.batches_A[t]
+        A, _ = oracle.apply(w.semiring, A, b.rows, b.cols, b.vals, b.ops)
+        updates += len(b)
+        if B is not None:
+            bb = w.batches_B[t]
+            B, _ = oracle.apply(w.semiring, B, bb.rows, bb.cols, bb.vals, bb.ops)
+            updates += len(bb)
+        oracle.spgemm(w.semiring, A, A if B is None else B, nthreads=threads)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": updates / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{done} batch(es) of the same workload: sequential apply + full static "
+                      f"recompute of C' ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat12", "stencil", "er"])
+    ap.add_argument("--batch", type=int, default=10000)
+    ap.add_argument("--static-reps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy a buffer of this many MiB device to device three times (reference "
+                         "dispatches for the HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the whole problem lives on one "
+              "MI355X and this build has no multi-GPU path", file=sys.stderr)
+        raise SystemExit(2)
+
+    import torch
+    from paper_2202_08808_amd import dsg
+    from paper_2202_08808_amd import inputs as I
+
+    K, W = args.steps, args.warmup
+    if args.calibrate_copy:
+        x = torch.ones(args.calibrate_copy << 20, dtype=torch.uint8, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: 3 x {args.calibrate_copy} MiB device to device")
+        del x, y
+    t0 = time.perf_counter()
+    w = make_workload(args.workload, args.batch, K + W)
+    log(f"[bench] workload {w.name}: n={w.A.nrows} nnz(A)={w.A.nnz} batches={K + W} "
+        f"({time.perf_counter() - t0:.1f}s to generate)")
+    sr = w.semiring
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    ctx = dsg.Context(0, stream=stream)
+    A = dsg.Matrix.from_csr(ctx, w.A, sr)
+    B = A if w.B is None else dsg.Matrix.from_csr(ctx, w.B, sr)
+    t0 = time.perf_counter()
+    P = dsg.Product(ctx, A, B)
+    ctx.synchronize()
+    log(f"[bench] initial product: nnz(C)={P.nnz()} in {time.perf_counter() - t0:.2f}s")
+
+    def dev_batch(b):
+        return (torch.from_numpy(b.rows).to(dev), torch.from_numpy(b.cols).to(dev),
+                torch.from_numpy(np.ascontiguousarray(b.vals)).to(dev), torch.from_numpy(b.ops).to(dev))
+    batches = [(dev_batch(w.batches_A[t]), dev_batch(w.batches_B[t]) if w.B is not None else None)
+               for t in range(K + W)]
+    per_step_updates = len(w.batches_A[0]) + (len(w.batches_B[0]) if w.B is not None else 0)
+    torch.cuda.synchronize()
+
+    def step(t):
+        ba, bb = batches[t]
+        A.apply(*ba)
+        if bb is not None:
+            B.apply(*bb)
+        return P.update()
+
+    for t in range(W):
+        step(t)
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+
+    ctx.set_timing(True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    stops = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+    affected = changed = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        starts[k].record(stream)
+        rs = step(W + k)
+        stops[k].record(stream)
+        st = P.stats()
+        affected += st["affected_rows"]
+        changed += rs.n
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    report = ctx.timing_report()
+    ctx.set_timing(False)
+    lat = np.array([starts[k].elapsed_time(stops[k]) for k in range(K)])
+    log(f"[bench] timed {K} steps in {wall:.3f}s; per-step ms: {np.round(lat, 3).tolist()}")
+
+    # static recompute on the same GPU, same kernels, full C written
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(args.static_reps):
+        t1 = time.perf_counter()
+        P.recompute_static()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    t_static = float(np.median(ts))
+    log(f"[bench] static recompute: {np.round(np.array(ts) * 1e3, 3).tolist()} ms")
+
+    ms_per_step = wall / K * 1e3
+    kern = report["kernels"]
+    dom_name = max(kern, key=lambda k: kern[k]["ms"]) if kern else None
+    roof = None
+    if dom_name:
+        d = kern[dom_name]
+        gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                "launches": d["launches"], "avg_launch_ms": round(d["ms"] / max(d["launches"], 1), 4),
+                "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline ...")
+        cpu = cpu_baseline(w, K + W)
+        log(f"[bench] CPU oracle: {cpu['value']:.1f} updates/s on {cpu['cores']} threads")
+    out = {
+        "metric": "dynamic SpGEMM updates/s",
+        "value": round(per_step_updates * K / wall, 2),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "int64", 1: "f32", 2: "f64"}[sr],
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.A.nrows, "nnz_A": w.A.nnz,
+                   "nnz_B": None if w.B is None else w.B.nnz, "nnz_C": P.nnz(),
+                   "updates_per_batch": per_step_updates, "mix_insert_delete_change": "50/25/25"
+                   if args.workload in ("rmat16", "er") else None, "parallelism": "single-gpu"},
+        "speedup_vs_static_gpu_recompute": round(t_static * 1e3 / ms_per_step, 4),
+        "static_recompute_ms": round(t_static * 1e3, 4),
+        "p99_batch_latency_ms": round(float(np.percentile(lat, 99)), 4),
+        "p50_batch_latency_ms": round(float(np.percentile(lat, 50)), 4),
+        "affected_rows_per_batch": affected / K,
+        "changed_rows_per_batch": changed / K,
+        "recomputed_rows_per_s": round(affected / wall, 1),
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 4),
+                        "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else None}
+                    for k, v in kern.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    P.destroy()
+    if B is not A:
+        B.destroy()
+    A.destroy()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

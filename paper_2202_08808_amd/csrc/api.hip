@@ -197,6 +197,9 @@ extern "C" dsg_status dsg_ctx_create(int device, void* hip_stream, size_t mem_bu
     Ctx& c = ctx->c;
     c.device = device;
     c.budget = mem_budget;
+    int cus = 0;
+    DSG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    c.num_cus = cus > 0 ? cus : 1;
     default_tuning(&c.tuning);
     if (hip_stream) {
       c.stream = (hipStream_t)hip_stream;

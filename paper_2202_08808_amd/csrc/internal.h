@@ -82,6 +82,7 @@ struct Ctx {
   size_t held = 0;
   std::string last_error = "";
   int objects = 0;
+  int num_cus = 256;  // compute units of the device
   dsg_tuning tuning;
   bool timing = false;
   std::vector<KernelTiming> timings;

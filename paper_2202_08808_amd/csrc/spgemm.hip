@@ -33,7 +33,9 @@ constexpr int NBINS = 10;
 constexpr int BIN_DENSE = 8;
 constexpr int BIN_GLOBAL = 9;
 constexpr int NSTAT = 7;  // rows, a_entries, flops, nnz_new, nnz_old, old_read, written
-constexpr int DENSE_WG = 1024;
+// Workgroup of the one-row-per-workgroup bins: 8 wavefronts, so each lane
+// may hold 256 VGPRs and keep several gathers in flight.
+constexpr int DENSE_WG = 512;
 constexpr int DENSE_ACHUNK = 512;
 
 template <int VSZ>
@@ -68,10 +70,27 @@ struct RowArgs {
   int64_t arena_cap;
   int force_write;      // 1: write every recomputed row, no comparison
   int* err;
+  struct RowStat* rstat;  // per q
+  uint8_t* binof;         // per q
+  int32_t* flq;           // per q: flops (clamped to int32)
+  unsigned int* dense_next;  // row counter of the persistent dense kernel
 };
 
-__device__ inline void stat_add(unsigned long long* st, int bin, int f, long long v) {
-  if (v) atomicAdd(&st[bin * NSTAT + f], (unsigned long long)v);
+// Per-row work record, summed per bin by k_reduce_stats.
+struct RowStat {
+  int32_t d, flops, nnew, olen, old_read, written;
+};
+
+__device__ inline void row_stat(const RowArgs& R, int32_t q, int32_t d, int64_t flops, int32_t nnew,
+                                int32_t olen, int64_t old_read, int32_t written) {
+  RowStat s;
+  s.d = d;
+  s.flops = (int32_t)flops;
+  s.nnew = nnew;
+  s.olen = olen;
+  s.old_read = (int32_t)old_read;
+  s.written = written;
+  R.rstat[q] = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -401,13 +420,7 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
   }
   if (lane == 0) {
     R.chg[q] = changed ? 1 : 0;
-    stat_add(R.stats, bin, 0, 1);
-    stat_add(R.stats, bin, 1, d);
-    stat_add(R.stats, bin, 2, flops);
-    stat_add(R.stats, bin, 3, nnew);
-    stat_add(R.stats, bin, 4, olen);
-    stat_add(R.stats, bin, 5, old_read);
-    stat_add(R.stats, bin, 6, changed ? nnew : 0);
+    row_stat(R, q, d, flops, nnew, olen, old_read, changed ? nnew : 0);
   }
 }
 
@@ -423,6 +436,51 @@ struct AChunk {
   int32_t pre[DENSE_ACHUNK + 1];
   int32_t so[DENSE_ACHUNK];
 };
+
+// Entries of a staged chunk split by B-row length.  Long rows are cut into
+// 64-entry tiles that the wavefronts share (each tile is one coalesced
+// wavefront load, and one hub row cannot stall a single wavefront); short
+// rows are flattened over the workgroup with a binary search in their own
+// prefix sums.
+constexpr int LONG_ROW = 64;
+struct ChunkSplit {
+  int32_t lidx[DENSE_ACHUNK];
+  int32_t tpre[DENSE_ACHUNK + 1];  // tile prefix over long entries
+  int32_t sidx[DENSE_ACHUNK];
+  int32_t spre[DENSE_ACHUNK + 1];  // flop prefix over short entries
+  int32_t nlong, nshort;
+};
+
+template <class V>
+__device__ inline void split_chunk(const AChunk<V>& ch, int cnt, ChunkSplit& sp, const Grp<DENSE_WG>& grp,
+                                   int* wscr) {
+  const int lane = grp.lane;
+  const bool act = lane < cnt;
+  const int32_t len = act ? ch.pre[lane + 1] - ch.pre[lane] : 0;
+  const bool lng = act && len >= LONG_ROW;
+  const bool sht = act && len > 0 && len < LONG_ROW;
+  int nl, ns;
+  const int rl = grp.rank(lng, nl, wscr);
+  const int rs = grp.rank(sht, ns, wscr);
+  int32_t stot, ttot;
+  const int32_t sincl = grp.scan(sht ? len : 0, stot, wscr);
+  const int32_t tincl = grp.scan(lng ? (len + 63) >> 6 : 0, ttot, wscr);
+  if (lng) {
+    sp.lidx[rl] = lane;
+    sp.tpre[rl + 1] = tincl;
+  }
+  if (sht) {
+    sp.sidx[rs] = lane;
+    sp.spre[rs + 1] = sincl;
+  }
+  if (lane == 0) {
+    sp.spre[0] = 0;
+    sp.tpre[0] = 0;
+    sp.nlong = nl;
+    sp.nshort = ns;
+  }
+  grp.sync();
+}
 
 // Stage A entries [cbase, cbase+cnt) and prefix sums of their B-row lengths.
 // Returns the chunk's flop count.  Whole-workgroup call.
@@ -473,16 +531,26 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   using V = typename S::V;
   using Acc = typename S::Acc;
   constexpr int CH = dense_cols<sizeof(V)>();
-  constexpr int PER = CH / DENSE_WG;  // columns per thread in the compaction
+  // (min,+): an untouched slot still holds the identity key, so no bitmap is
+  // needed; (+,x) needs one because 0 is a legitimate sum.
+  constexpr bool kBits = SR != 1;
   __shared__ Acc acc[CH];
-  __shared__ uint32_t bits[CH / 32];
+  __shared__ uint32_t bits[kBits ? CH / 32 : 1];
   __shared__ AChunk<V> ch;
+  __shared__ ChunkSplit sp;
   __shared__ int wscr[16];
   __shared__ int64_t bslot;
+  __shared__ int32_t next_row;
   const Grp<DENSE_WG> grp;
   const int tid = threadIdx.x;
-  if ((int64_t)blockIdx.x >= count) return;
-  const int32_t q = list[blockIdx.x];
+  // persistent: rows are taken in list order (longest first) from a counter
+  for (;;) {
+  if (tid == 0) next_row = (int32_t)atomicAdd(R.dense_next, 1u);
+  grp.sync();
+  const int32_t qi = next_row;
+  grp.sync();
+  if (qi >= count) break;
+  const int32_t q = list[qi];
   const int32_t i = R.aff[q];
   const int64_t aoff = R.a_off[i];
   const int32_t d = R.a_len[i];
@@ -496,7 +564,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   sbase = grp.bcast64(sbase, 0, &bslot);
   if (sbase + (int64_t)stage_bytes > R.arena_cap) {
     if (tid == 0) atomicOr(R.err, 4);
-    return;
+    break;
   }
   int32_t* scol = (int32_t*)(R.arena + sbase);
   V* sval = (V*)(R.arena + sbase + (size_t)stage_n * 4);
@@ -510,24 +578,101 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     const int32_t c0 = pc * CH;
     const int32_t c1 = min(c0 + CH, R.ncols);
     for (int x = tid; x < CH; x += DENSE_WG) acc[x] = S::identity();
-    for (int x = tid; x < CH / 32; x += DENSE_WG) bits[x] = 0u;
+    if constexpr (kBits)
+      for (int x = tid; x < CH / 32; x += DENSE_WG) bits[x] = 0u;
     grp.sync();
+    // MLP rounds of UNR independent flops per lane: all loads first, then the
+    // LDS updates, so each lane keeps UNR gathers in flight
+    constexpr int UNR = 8;
+    auto accumulate_round = [&](const int64_t* pos, const V* av, const bool* ok) {
+      int32_t j[UNR];
+      V bv[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        j[u] = ok[u] ? R.b_col[pos[u]] : -1;
+        bv[u] = ok[u] ? ldv<V>(R.b_val, pos[u]) : V(0);
+      }
+      if constexpr (S::order_free) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          if (j[u] >= c0 && j[u] < c1) {
+            const int x = j[u] - c0;
+            S::atomic_combine(&acc[x], S::mul(av[u], bv[u]));
+            if constexpr (kBits) atomicOr(&bits[x >> 5], 1u << (x & 31));
+          }
+        }
+      }
+    };
     for (int32_t cbase = 0; cbase < d; cbase += DENSE_ACHUNK) {
       const int cnt = min(DENSE_ACHUNK, d - cbase);
       int32_t tot = stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, !S::order_free);
       if (pc == 0) flops += tot;
       if constexpr (S::order_free) {
-        for (int32_t fb = 0; fb < tot; fb += DENSE_WG) {
-          int32_t f = fb + tid;
-          if (f < tot) {
-            int ts = find_seg(ch.pre, cnt, f);
-            int64_t pos = ch.b[ts] + (f - ch.pre[ts]);
-            int32_t j = R.b_col[pos];
-            if (j >= c0 && j < c1) {
-              int x = j - c0;
-              S::atomic_combine(&acc[x], S::mul(ch.a[ts], ldv<V>(R.b_val, pos)));
-              atomicOr(&bits[x >> 5], 1u << (x & 31));
+        split_chunk<V>(ch, cnt, sp, grp, wscr);
+        // long B rows as 64-entry tiles, UNR tiles per wavefront per round
+        const int wv = tid >> 6, ln = tid & 63;
+        const int nl = sp.nlong;
+        const int ntiles = sp.tpre[nl];
+        for (int tb = wv * UNR; tb < ntiles; tb += (DENSE_WG / 64) * UNR) {
+          int64_t pos[UNR];
+          V av[UNR];
+          bool ok[UNR];
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            const int tile = tb + u;
+            ok[u] = false;
+            pos[u] = 0;
+            av[u] = V(0);
+            if (tile < ntiles) {
+              const int e = find_seg(sp.tpre, nl, tile);
+              const int t = sp.lidx[e];
+              const int32_t x = ((tile - sp.tpre[e]) << 6) + ln;
+              if (x < ch.pre[t + 1] - ch.pre[t]) {
+                ok[u] = true;
+                pos[u] = ch.b[t] + x;
+                av[u] = ch.a[t];
+              }
             }
+          }
+          accumulate_round(pos, av, ok);
+        }
+        // short B rows: 8-lane sub-groups, each streaming 4 rows at once (no
+        // search; 4 gathers in flight per lane)
+        const int ns = sp.nshort;
+        constexpr int NSG = DENSE_WG / 8;
+        const int sg = tid >> 3, l8 = tid & 7;
+        for (int eb = sg; eb < ns; eb += 4 * NSG) {
+          int64_t bo[4];
+          int32_t bl[4];
+          V ba[4];
+          int32_t mx = 0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int e = eb + u * NSG;
+            bl[u] = 0;
+            bo[u] = 0;
+            ba[u] = V(0);
+            if (e < ns) {
+              const int t = sp.sidx[e];
+              bo[u] = ch.b[t];
+              bl[u] = ch.pre[t + 1] - ch.pre[t];
+              ba[u] = ch.a[t];
+              mx = max(mx, bl[u]);
+            }
+          }
+          for (int32_t x = l8; x < mx; x += 16) {
+            int64_t pos[UNR];
+            V av[UNR];
+            bool ok[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+              const int r = u & 3;
+              const int32_t xx = x + (u >> 2) * 8;
+              ok[u] = xx < bl[r];
+              pos[u] = bo[r] + xx;
+              av[u] = ba[r];
+            }
+            accumulate_round(pos, av, ok);
           }
         }
       } else {
@@ -551,25 +696,41 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       }
       grp.sync();
     }
-    // compaction of this column chunk, ascending column order
+    // compaction of this column chunk in ascending column order: wavefront w
+    // owns columns [w*SEG, (w+1)*SEG) and walks them 64 at a time, so LDS reads
+    // are bank-conflict free and staging writes are coalesced
+    auto touched = [&](int x) -> bool {
+      if constexpr (kBits) return (bits[x >> 5] >> (x & 31)) & 1u;
+      else return acc[x] != S::identity();
+    };
+    constexpr int NWV = DENSE_WG / 64;
+    constexpr int SEG = CH / NWV;
+    const int cwv = tid >> 6, cln = tid & 63;
+    const uint64_t clt = cln ? (~0ull >> (64 - cln)) : 0ull;
     int32_t mine = 0;
-    const int x0 = tid * PER;
-    for (int x = x0; x < x0 + PER; x += 32) {
-      uint32_t w = bits[x >> 5];
-      if constexpr (PER < 32) w = (w >> (x & 31)) & ((1u << (PER & 31)) - 1);
-      mine += __popc(w);
+    for (int r = 0; r < SEG; r += 64) mine += __popcll(__ballot(touched(cwv * SEG + r + cln)));
+    if (cln == 0) wscr[cwv] = mine;
+    grp.sync();
+    int32_t before = 0, ctot = 0;
+    for (int x = 0; x < NWV; ++x) {
+      const int32_t c = wscr[x];
+      if (x < cwv) before += c;
+      ctot += c;
     }
-    int32_t ctot;
-    int32_t excl = grp.scan(mine, ctot, wscr) - mine;
-    int32_t o = nnew + excl;
-    for (int x = x0; x < x0 + PER; ++x) {
-      if ((bits[x >> 5] >> (x & 31)) & 1u) {
-        if (o < stage_n) {
-          scol[o] = c0 + x;
-          sval[o] = S::from_acc(acc[x]);
+    grp.sync();
+    int32_t o = nnew + before;
+    for (int r = 0; r < SEG; r += 64) {
+      const int x = cwv * SEG + r + cln;
+      const bool tch = touched(x);
+      const uint64_t b = __ballot(tch);
+      if (tch) {
+        const int32_t pos = o + __popcll(b & clt);
+        if (pos < stage_n) {
+          scol[pos] = c0 + x;
+          sval[pos] = S::from_acc(acc[x]);
         }
-        ++o;
       }
+      o += __popcll(b);
     }
     // compare the old entries that fall into this chunk
     if (!changed) {
@@ -580,8 +741,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
         if (c >= c0 && c < c1) {
           ++in_chunk;
           int x = c - c0;
-          bool have = (bits[x >> 5] >> (x & 31)) & 1u;
-          bad |= !have || !same_bits(acc[x], S::to_acc(ldv<V>(R.c_val, ooff + e)));
+          bad |= !touched(x) || !same_bits(acc[x], S::to_acc(ldv<V>(R.c_val, ooff + e)));
         }
       }
       int32_t itot;
@@ -594,7 +754,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   }
   if (nnew > stage_n) {
     if (tid == 0) atomicOr(R.err, 8);
-    return;
+    break;
   }
   if (changed) {
     int64_t dest = ooff;
@@ -602,7 +762,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     if (nnew > R.c_cap[i]) {
       ncap = slack_cap(nnew);
       dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
-      if (dest < 0) return;
+      if (dest < 0) break;
     }
     for (int32_t e = tid; e < nnew; e += DENSE_WG) {
       R.c_col[dest + e] = scol[e];
@@ -618,14 +778,9 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   }
   if (tid == 0) {
     R.chg[q] = changed ? 1 : 0;
-    stat_add(R.stats, BIN_DENSE, 0, 1);
-    stat_add(R.stats, BIN_DENSE, 1, d);
-    stat_add(R.stats, BIN_DENSE, 2, flops);
-    stat_add(R.stats, BIN_DENSE, 3, nnew);
-    stat_add(R.stats, BIN_DENSE, 4, olen);
-    stat_add(R.stats, BIN_DENSE, 5, old_read);
-    stat_add(R.stats, BIN_DENSE, 6, changed ? nnew : 0);
+    row_stat(R, q, d, flops, nnew, olen, old_read, changed ? nnew : 0);
   }
+  }  // rows
 }
 
 // ---------------------------------------------------------------------------
@@ -814,13 +969,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
   }
   if (tid == 0) {
     R.chg[q] = changed ? 1 : 0;
-    stat_add(R.stats, BIN_GLOBAL, 0, 1);
-    stat_add(R.stats, BIN_GLOBAL, 1, d);
-    stat_add(R.stats, BIN_GLOBAL, 2, flops);
-    stat_add(R.stats, BIN_GLOBAL, 3, nnew);
-    stat_add(R.stats, BIN_GLOBAL, 4, olen);
-    stat_add(R.stats, BIN_GLOBAL, 5, old_read);
-    stat_add(R.stats, BIN_GLOBAL, 6, changed ? nnew : 0);
+    row_stat(R, q, d, flops, nnew, olen, old_read, changed ? nnew : 0);
   }
 }
 
@@ -863,7 +1012,21 @@ struct Plan {
   unsigned long long bin_count[NBINS];
   unsigned long long c_demand;
   unsigned long long arena_demand;
+  unsigned int dense_next;
+  unsigned int pad2;
 };
+
+// longest rows first: key = (2^20 - 1) - min(flops, 2^20 - 1)
+constexpr int FLOP_KEY_BITS = 20;
+__global__ void k_flop_keys(const int32_t* list, int32_t n, const int32_t* flq, uint64_t* keys, uint32_t* vals) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    const int32_t q = list[t];
+    const int32_t f = min(flq[q], (1 << FLOP_KEY_BITS) - 1);
+    keys[t] = (uint64_t)(((1 << FLOP_KEY_BITS) - 1) - f);
+    vals[t] = (uint32_t)q;
+  }
+}
 
 __device__ inline int pick_bin(int32_t ub, int32_t d, const Tun& T) {
   if (T.force_bin >= BIN_DENSE) return T.force_bin;
@@ -878,8 +1041,7 @@ __device__ inline int pick_bin(int32_t ub, int32_t d, const Tun& T) {
 }
 
 // 16 lanes per affected row: flops, ub, bin; empty output rows are finished here
-__global__ __launch_bounds__(256) void k_analyze(RowArgs R, const int32_t* d_count, Tun T, Plan* plan,
-                                                 int32_t* bins, int32_t bin_stride) {
+__global__ __launch_bounds__(256) void k_analyze(RowArgs R, const int32_t* d_count, Tun T) {
   const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
   const int l = threadIdx.x & 15;
   if (q >= *d_count) return;
@@ -892,27 +1054,76 @@ __global__ __launch_bounds__(256) void k_analyze(RowArgs R, const int32_t* d_cou
   if (l != 0) return;
   const int32_t ub = (int32_t)min(f, (int64_t)R.ncols);
   R.ub[q] = ub;
+  R.flq[q] = (int32_t)min(f, (int64_t)0x7fffffff);
   if (ub == 0) {
     const int32_t olen = R.c_len[i];
     bool changed = R.force_write || olen != 0;
     R.c_len[i] = 0;
     R.chg[q] = changed ? 1 : 0;
-    stat_add(R.stats, 0, 0, 1);
-    stat_add(R.stats, 0, 1, d);
-    stat_add(R.stats, 0, 4, olen);
+    R.binof[q] = 0;
+    row_stat(R, q, d, 0, 0, olen, 0, 0);
     return;
   }
-  const int b = pick_bin(ub, d, T);
-  unsigned long long pos = atomicAdd(&plan->bin_count[b], 1ull);
-  bins[(int64_t)b * bin_stride + (int64_t)pos] = (int32_t)q;
-  if (ub > R.c_cap[i]) atomicAdd(&plan->c_demand, (unsigned long long)slack_cap(ub));
-  if (b == BIN_DENSE) {
-    size_t sb = ((size_t)min(ub, R.ncols) * (4 + (T.fp64 ? 8 : 8)) + 255) & ~size_t(255);
-    atomicAdd(&plan->arena_demand, (unsigned long long)sb);
-  } else if (b == BIN_GLOBAL) {
-    int64_t slots = global_slots(ub);
-    atomicAdd(&plan->arena_demand, (unsigned long long)(((size_t)slots * 12 + 255) & ~size_t(255)));
+  R.binof[q] = (uint8_t)pick_bin(ub, d, T);
+}
+
+// Bin lists and space needs, aggregated per workgroup: one global atomic per
+// bin and per counter and workgroup, not one per row.
+constexpr int SCATTER_NT = 1024;
+__global__ __launch_bounds__(SCATTER_NT) void k_bin_scatter(RowArgs R, const int32_t* d_count, Plan* plan,
+                                                            int32_t* bins, int32_t bin_stride) {
+  __shared__ int32_t cnt[NBINS];
+  __shared__ unsigned long long base[NBINS];
+  __shared__ unsigned long long dem[2];
+  const int tid = threadIdx.x;
+  if (tid < NBINS) cnt[tid] = 0;
+  if (tid < 2) dem[tid] = 0;
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * SCATTER_NT + tid;
+  int b = -1, local = 0;
+  if (q < *d_count) {
+    const int32_t ub = R.ub[q];
+    if (ub > 0) {
+      b = R.binof[q];
+      local = atomicAdd(&cnt[b], 1);
+      const int32_t i = R.aff[q];
+      if (ub > R.c_cap[i]) atomicAdd(&dem[0], (unsigned long long)slack_cap(ub));
+      if (b == BIN_DENSE) {
+        atomicAdd(&dem[1], (unsigned long long)(((size_t)min(ub, R.ncols) * 12 + 255) & ~size_t(255)));
+      } else if (b == BIN_GLOBAL) {
+        atomicAdd(&dem[1], (unsigned long long)(((size_t)global_slots(ub) * 12 + 255) & ~size_t(255)));
+      }
+    }
   }
+  __syncthreads();
+  if (tid < NBINS) base[tid] = cnt[tid] ? atomicAdd(&plan->bin_count[tid], (unsigned long long)cnt[tid]) : 0;
+  if (tid == NBINS && dem[0]) atomicAdd(&plan->c_demand, dem[0]);
+  if (tid == NBINS + 1 && dem[1]) atomicAdd(&plan->arena_demand, dem[1]);
+  __syncthreads();
+  if (b >= 0) bins[(int64_t)b * bin_stride + (int64_t)(base[b] + local)] = (int32_t)q;
+}
+
+// Sum the per-row records into per-bin totals.
+__global__ __launch_bounds__(256) void k_reduce_stats(const RowStat* rs, const uint8_t* binof,
+                                                      const int32_t* d_count, unsigned long long* stats) {
+  __shared__ unsigned long long acc[NBINS * NSTAT];
+  for (int x = threadIdx.x; x < NBINS * NSTAT; x += blockDim.x) acc[x] = 0;
+  __syncthreads();
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < *d_count) {
+    const RowStat s = rs[q];
+    unsigned long long* a = acc + binof[q] * NSTAT;
+    atomicAdd(&a[0], 1ull);
+    if (s.d) atomicAdd(&a[1], (unsigned long long)s.d);
+    if (s.flops) atomicAdd(&a[2], (unsigned long long)s.flops);
+    if (s.nnew) atomicAdd(&a[3], (unsigned long long)s.nnew);
+    if (s.olen) atomicAdd(&a[4], (unsigned long long)s.olen);
+    if (s.old_read) atomicAdd(&a[5], (unsigned long long)s.old_read);
+    if (s.written) atomicAdd(&a[6], (unsigned long long)s.written);
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < NBINS * NSTAT; x += blockDim.x)
+    if (acc[x]) atomicAdd(&stats[x], acc[x]);
 }
 
 __global__ void k_set_count(int32_t* d, int32_t v) { *d = v; }
@@ -960,9 +1171,13 @@ void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, 
       GROUP_CASE(6, 512, 512)
       GROUP_CASE(7, 1024, 1024)
 #undef GROUP_CASE
-      case BIN_DENSE:
-        hipLaunchKernelGGL((k_rows_dense<SR>), dim3(cnt), dim3(DENSE_WG), 0, s, R, list, cnt);
+      case BIN_DENSE: {
+        // persistent workgroups, one per CU (the kernel holds ~150 KB of LDS),
+        // taking rows longest first
+        unsigned grid = (unsigned)std::min<int64_t>(cnt, (int64_t)c->num_cus);
+        hipLaunchKernelGGL((k_rows_dense<SR>), dim3(grid), dim3(DENSE_WG), 0, s, R, list, cnt);
         break;
+      }
       case BIN_GLOBAL:
         hipLaunchKernelGGL((k_rows_global<SR>), dim3(cnt), dim3(DENSE_WG), 0, s, R, list, cnt);
         break;
@@ -984,6 +1199,9 @@ struct ProdWork {
   int32_t* bins;
   Plan* plan;
   unsigned long long* stats;
+  RowStat* rstat;
+  uint8_t* binof;
+  int32_t* flq;
   int* err;
   int32_t* d_nchg;
   void* cscr;
@@ -1036,8 +1254,9 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   const int64_t N = n > 0 ? n : 1;
   const int64_t nB = B->nrows > 0 ? B->nrows : 1;
   const size_t need = Carve::need({(size_t)N, (size_t)nB, (size_t)N * 4, 64, (size_t)nB * 4, 64, (size_t)N * 4, (size_t)N,
-                                   (size_t)N * 4 * NBINS, sizeof(Plan) + 64, NBINS * NSTAT * 8 + 64, 64,
-                                   64, compact_scratch_bytes(std::max(N, nB)) + 64});
+                                   (size_t)N * 4 * NBINS, sizeof(Plan) + 64, NBINS * NSTAT * 8 + 64,
+                                   (size_t)N * sizeof(RowStat), (size_t)N, (size_t)N * 4, 64, 64,
+                                   compact_scratch_bytes(std::max(N, nB)) + 64});
   Carve cv(ctx_scratch(c, need), need);
   ProdWork w;
   w.aff_flags = cv.take<uint8_t>(N);
@@ -1051,6 +1270,9 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   w.bins = cv.take<int32_t>(N * NBINS);
   w.plan = cv.take<Plan>(1);
   w.stats = cv.take<unsigned long long>(NBINS * NSTAT);
+  w.rstat = cv.take<RowStat>(N);
+  w.binof = cv.take<uint8_t>(N);
+  w.flq = cv.take<int32_t>(N);
   w.err = cv.take<int>(16);
   w.d_nchg = cv.take<int32_t>(16);
   w.cscr = cv.take<char>(compact_scratch_bytes(std::max(N, nB)) + 64);
@@ -1090,6 +1312,10 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
   R.force_write = (mode == 1 || report_affected) ? 1 : 0;
   R.err = w.err;
+  R.rstat = w.rstat;
+  R.binof = w.binof;
+  R.flq = w.flq;
+  R.dense_next = &w.plan->dense_next;
 
   Tun T;
   const dsg_tuning& tu = c->tuning;
@@ -1099,7 +1325,8 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   T.force_bin = tu.force_bin;
   T.fp64 = A->sr == 2 ? 1 : 0;
   if (n > 0) {
-    hipLaunchKernelGGL(k_analyze, dim3(blocks_for((int64_t)n * 16, 256)), dim3(256), 0, s, R, w.d_count, T,
+    hipLaunchKernelGGL(k_analyze, dim3(blocks_for((int64_t)n * 16, 256)), dim3(256), 0, s, R, w.d_count, T);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n, SCATTER_NT)), dim3(SCATTER_NT), 0, s, R, w.d_count,
                        w.plan, w.bins, n);
   }
   // ---- host round trip 1: bin sizes and space needs ----
@@ -1126,6 +1353,20 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   R.c_col = C->col; R.c_val = C->val; R.c_off = C->row_off; R.c_top = C->d_top; R.c_pool_cap = C->pool_cap;
   R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
 
+  // the dense bin runs persistent workgroups: hand them the longest rows first
+  const int64_t ndense = (int64_t)plan.bin_count[BIN_DENSE];
+  if (ndense > 1) {
+    int32_t* dl = w.bins + (int64_t)BIN_DENSE * n;
+    const size_t nb = Carve::need({(size_t)ndense * 8, (size_t)ndense * 4, radix_scratch_bytes(ndense)});
+    Carve dc(ctx_scratch2(c, nb), nb);
+    uint64_t* keys = dc.take<uint64_t>(ndense);
+    uint32_t* vals = dc.take<uint32_t>(ndense);
+    void* rs = dc.take<char>(radix_scratch_bytes(ndense));
+    hipLaunchKernelGGL(k_flop_keys, dim3(blocks_for(ndense, 256)), dim3(256), 0, s, dl, (int32_t)ndense, w.flq,
+                       keys, vals);
+    radix_sort_pairs(keys, vals, ndense, FLOP_KEY_BITS, rs, s);
+    DSG_HIP(hipMemcpyAsync(dl, vals, (size_t)ndense * 4, hipMemcpyDeviceToDevice, s));
+  }
   std::vector<std::pair<int, size_t>> timed;
   switch (A->sr) {
     case 0: launch_bins<0>(c, R, w.bins, n, plan, timed); break;
@@ -1141,6 +1382,9 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   }
   compact_list_by_flags(w.aff, w.chg, w.d_count, std::max<int32_t>(plan.count, 1), p->changed_rows, w.d_nchg,
                         w.cscr, s);
+  if (plan.count > 0)
+    hipLaunchKernelGGL(k_reduce_stats, dim3(blocks_for(plan.count, 256)), dim3(256), 0, s, w.rstat, w.binof,
+                       w.d_count, w.stats);
   // ---- host round trip 2: row count, statistics, errors ----
   struct Tail {
     int32_t nchg;
