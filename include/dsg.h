@@ -128,6 +128,8 @@ typedef struct {
                               a group bin is only used for rows that fit it) */
 } dsg_tuning;
 dsg_status dsg_ctx_get_tuning(const dsg_ctx* ctx, dsg_tuning* t);
+/* t == NULL restores the defaults.  DSG_E_ARG for thresholds outside the
+ * bins' capacities, a descending order, or force_bin outside [-1, 9]. */
 dsg_status dsg_ctx_set_tuning(dsg_ctx* ctx, const dsg_tuning* t);
 
 /* ---- dynamic matrices (Section 4: dynamic storage with O(1) updates) ---- */
@@ -215,7 +217,60 @@ typedef struct {
 } dsg_update_stats;
 dsg_status dsg_prod_stats(const dsg_prod* p, dsg_update_stats* s);
 
+/* Autotuner: time `reps` full recomputes of C (same kernels as updates, all
+ * rows) under each of a fixed set of candidate tunings (accumulator-bin
+ * thresholds and the dense-versus-global-hash switch), keep the fastest as
+ * the context's tuning and return it in *best with its median time in
+ * *best_ms.  report (may be NULL) receives a JSON array of every candidate
+ * and its time.  C is recomputed by every trial and ends equal to A·B;
+ * pending changes of A and B are consumed as by dsg_prod_recompute_static. */
+dsg_status dsg_prod_autotune(dsg_prod* p, int32_t reps, dsg_tuning* best, double* best_ms, char* report,
+                             size_t cap);
+
+/* DSG_E_STATE while a batched executor uses the product. */
 dsg_status dsg_prod_destroy(dsg_prod* p);
+
+/* ---- batched form: many independent products in one hipGraph replay ---- */
+
+typedef struct dsg_batch dsg_batch;
+
+/* The updates of one matrix inside a batched run: device arrays laid out as
+ * for dsg_mat_apply with DSG_INPUT_DEVICE. */
+typedef struct {
+  dsg_mat* mat;
+  const int32_t* rows;
+  const int32_t* cols;
+  const void* vals;
+  const uint8_t* ops;
+  int64_t n;
+} dsg_update_set;
+
+/* Create a batched executor over nprod products of ctx.  The products must
+ * not share operands (each instance is independent); they and their
+ * operands stay alive until dsg_batch_destroy.  DSG_E_STATE otherwise. */
+dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int32_t nprod, dsg_batch** out);
+
+/* Apply nsets update sets (each to a distinct operand of one of the batch's
+ * products) and bring every product up to date: the same C, row contents and
+ * reported rows as dsg_mat_apply on each set followed by dsg_prod_update on
+ * each product.  All products' chains (ingest, discovery, row recompute,
+ * merge) are one hipGraph replay, with one host round trip before it
+ * (validation of every set) and one after it (results).  The graph is
+ * captured on the first run and replayed while the set arrays, their sizes
+ * and the storage of every object stay the same (a run with other arrays or
+ * after storage grew captures again).  A product whose update needs more C
+ * or staging space than was set aside is completed by the plain path after
+ * the replay, with the same result.  changed_counts (host, nprod entries)
+ * receives each product's reported row count; dsg_batch_rows gives the rows.
+ * Errors: DSG_E_RANGE / DSG_E_ARG for a bad set (nothing is applied). */
+dsg_status dsg_batch_run(dsg_batch* b, const dsg_update_set* sets, int32_t nsets, uint32_t flags,
+                         int32_t* changed_counts);
+/* Views of the rows product i reported in the last run (valid until the next
+ * run or mutating call on that product). */
+dsg_status dsg_batch_rows(dsg_batch* b, int32_t i, dsg_rows* out);
+/* Graph captures, replays, and products completed by the plain path so far. */
+dsg_status dsg_batch_info(const dsg_batch* b, int64_t* captures, int64_t* replays, int64_t* deferred);
+dsg_status dsg_batch_destroy(dsg_batch* b);
 
 #ifdef __cplusplus
 }

@@ -695,8 +695,170 @@ extern "C" dsg_status dsg_prod_stats(const dsg_prod* ph, dsg_update_stats* s) {
   return DSG_OK;
 }
 
+// Candidate tunings: bin thresholds at full or half capacity, small bins on
+// or off, and the pass limit of the dense accumulator.
+static std::vector<dsg_tuning> tuning_candidates() {
+  std::vector<dsg_tuning> out;
+  for (int half = 0; half < 2; ++half)
+    for (int skip_small = 0; skip_small < 2; ++skip_small)
+      for (int passes : {1, 2, 4, 8}) {
+        dsg_tuning t;
+        for (int b = 0; b < 8; ++b) t.group_ub[b] = half ? (16 << b) : (32 << b);
+        if (skip_small) t.group_ub[0] = t.group_ub[1] = 0;
+        t.dense_max_passes = passes;
+        t.force_bin = -1;
+        out.push_back(t);
+      }
+  return out;
+}
+
+extern "C" dsg_status dsg_prod_autotune(dsg_prod* ph, int32_t reps, dsg_tuning* best, double* best_ms,
+                                        char* report, size_t cap) {
+  if (!ph || !best || !best_ms) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
+  if (reps < 1 || reps > 100) return fail(ph->owner, DSG_E_ARG, "reps outside [1, 100]");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  Ctx* c = &ctx__->c;
+  const dsg_tuning saved = c->tuning;
+  hipEvent_t e0, e1;
+  DSG_HIP(hipEventCreate(&e0));
+  DSG_HIP(hipEventCreate(&e1));
+  std::string js = "[";
+  double best_t = 1e300;
+  dsg_tuning best_tu = saved;
+  const bool timing = c->timing;
+  c->timing = false;
+  try {
+    for (const dsg_tuning& t : tuning_candidates()) {
+      c->tuning = t;
+      prod_run(ph->p, 1, true);  // warm: sizes the pools and the arena for this setting
+      std::vector<float> ms;
+      for (int r = 0; r < reps; ++r) {
+        DSG_HIP(hipEventRecord(e0, c->stream));
+        prod_run(ph->p, 1, true);
+        DSG_HIP(hipEventRecord(e1, c->stream));
+        DSG_HIP(hipEventSynchronize(e1));
+        float x = 0;
+        DSG_HIP(hipEventElapsedTime(&x, e0, e1));
+        ms.push_back(x);
+      }
+      std::sort(ms.begin(), ms.end());
+      const double med = ms[ms.size() / 2];
+      char tmp[256];
+      snprintf(tmp, sizeof tmp, "%s{\"group_ub\": [%d,%d,%d,%d,%d,%d,%d,%d], \"dense_max_passes\": %d, \"ms\": %.4f}",
+               js.size() > 1 ? ", " : "", t.group_ub[0], t.group_ub[1], t.group_ub[2], t.group_ub[3],
+               t.group_ub[4], t.group_ub[5], t.group_ub[6], t.group_ub[7], t.dense_max_passes, med);
+      js += tmp;
+      if (med < best_t) {
+        best_t = med;
+        best_tu = t;
+      }
+    }
+  } catch (...) {
+    c->tuning = saved;
+    c->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  js += "]";
+  c->timing = timing;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tuning = best_tu;
+  *best = best_tu;
+  *best_ms = best_t;
+  if (report && cap) {
+    size_t n = std::min(cap - 1, js.size());
+    memcpy(report, js.data(), n);
+    report[n] = 0;
+  }
+  API_END
+}
+
+struct dsg_batch {
+  DBatch* b;
+  dsg_ctx* owner;
+  std::vector<dsg_prod*> prods;
+  std::vector<int32_t> counts;
+};
+
+extern "C" dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int32_t nprod, dsg_batch** out) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  if (!out || (nprod > 0 && !prods) || nprod < 0) return fail(ctx, DSG_E_ARG, "bad arguments");
+  *out = nullptr;
+  std::vector<DMat*> seen;
+  for (int32_t i = 0; i < nprod; ++i) {
+    if (!prods[i] || prods[i]->owner != ctx) return fail(ctx, DSG_E_STATE, "product of another context");
+    for (DMat* m : {prods[i]->p->A, prods[i]->p->B}) {
+      if (std::find(seen.begin(), seen.end(), m) != seen.end() && !(m == prods[i]->p->B && m == prods[i]->p->A))
+        return fail(ctx, DSG_E_STATE, "products of a batch must not share operands");
+      seen.push_back(m);
+    }
+  }
+  API_BEGIN(ctx)
+  set_device(ctx);
+  std::vector<DProd*> ps;
+  for (int32_t i = 0; i < nprod; ++i) ps.push_back(prods[i]->p);
+  DBatch* b = batch_create(&ctx->c, ps);
+  dsg_batch* h = new dsg_batch();
+  h->b = b;
+  h->owner = ctx;
+  h->prods.assign(prods, prods + nprod);
+  h->counts.assign((size_t)nprod, 0);
+  *out = h;
+  API_END
+}
+
+extern "C" dsg_status dsg_batch_run(dsg_batch* bh, const dsg_update_set* sets, int32_t nsets, uint32_t flags,
+                                    int32_t* changed_counts) {
+  if (!bh) return fail(nullptr, DSG_E_ARG, "batch is NULL");
+  if (nsets < 0 || (nsets > 0 && !sets)) return fail(bh->owner, DSG_E_ARG, "bad set list");
+  if (flags & ~(uint32_t)DSG_SYNC) return fail(bh->owner, DSG_E_ARG, "unknown flag");
+  std::vector<DBatchSet> ss;
+  for (int32_t k = 0; k < nsets; ++k) {
+    const dsg_update_set& s = sets[k];
+    if (!s.mat || !s.mat->alive || s.mat->owner != bh->owner) return fail(bh->owner, DSG_E_ARG, "bad matrix in set");
+    if (s.n < 0 || (s.n > 0 && (!s.rows || !s.cols || !s.vals || !s.ops)))
+      return fail(bh->owner, DSG_E_ARG, "bad set arrays");
+    ss.push_back(DBatchSet{s.mat->m, s.rows, s.cols, s.vals, s.ops, s.n});
+  }
+  API_BEGIN(bh->owner)
+  set_device(ctx__);
+  dsg_status st = batch_run(bh->b, ss, bh->counts);
+  if (st == DSG_E_RANGE) throw DsgError{st, "update index out of range in a set"};
+  if (st != DSG_OK) throw DsgError{st, "unknown update op code in a set"};
+  if (changed_counts)
+    for (size_t j = 0; j < bh->counts.size(); ++j) changed_counts[j] = bh->counts[j];
+  API_END
+}
+
+extern "C" dsg_status dsg_batch_rows(dsg_batch* bh, int32_t i, dsg_rows* out) {
+  if (!bh || !out) return fail(bh ? bh->owner : nullptr, DSG_E_ARG, "NULL argument");
+  if (i < 0 || i >= (int32_t)bh->prods.size()) return fail(bh->owner, DSG_E_ARG, "product index out of range");
+  DProd* p = batch_prod(bh->b, i);
+  fill_rows(p, p->changed_rows, bh->counts[(size_t)i], out);
+  return DSG_OK;
+}
+
+extern "C" dsg_status dsg_batch_info(const dsg_batch* bh, int64_t* captures, int64_t* replays, int64_t* deferred) {
+  if (!bh) return fail(nullptr, DSG_E_ARG, "batch is NULL");
+  batch_info(bh->b, captures, replays, deferred);
+  return DSG_OK;
+}
+
+extern "C" dsg_status dsg_batch_destroy(dsg_batch* bh) {
+  if (!bh) return fail(nullptr, DSG_E_ARG, "batch is NULL");
+  API_BEGIN(bh->owner)
+  set_device(ctx__);
+  batch_destroy(bh->b);
+  delete bh;
+  API_END
+}
+
 extern "C" dsg_status dsg_prod_destroy(dsg_prod* ph) {
   if (!ph) return fail(nullptr, DSG_E_ARG, "product is NULL");
+  if (ph->p->refs > 0) return fail(ph->owner, DSG_E_STATE, "product is used by a batched executor or server");
   API_BEGIN(ph->owner)
   set_device(ctx__);
   ctx_sync(&ctx__->c);

@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
 
 template <int SR, int VSZ>
 __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uint64_t cmask, int cbits,
-                                                Uniq U, uint32_t epoch, int tbits, uint64_t* dkey,
+                                                Uniq U, const uint32_t* d_epoch, int tbits, uint64_t* dkey,
                                                 uint8_t* dop, unsigned long long* d_ndelta, int* err) {
   const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
   }
   if (lane == 0) {
     m.row_len[i] = nl;
-    m.row_epoch[i] = epoch;
+    m.row_epoch[i] = *d_epoch;
   }
   // structural changes for the transpose index: key (col << tbits) | row
   if (dkey) {
@@ -443,30 +443,40 @@ Work carve_work(void* base, int64_t n, bool deltas) {
   return w;
 }
 
+__global__ void k_bump_epoch(uint32_t* e) { *e += 1; }
+__global__ void k_zero_counters(unsigned long long* a, unsigned long long* b, int* c) {
+  *a = 0;
+  *b = 0;
+  *c = 0;
+}
+
 template <int SR, int VSZ>
-void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, const void* vals,
-                        uint32_t epoch, int tbits) {
+void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, const void* vals, int tbits,
+                        bool graph) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   unsigned nb = blocks_for(n * 64, 256);
   hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
                      w.demand);
-  // the one host round trip: how much pool space moved rows need
-  unsigned long long* h = (unsigned long long*)c->pinned;
-  DSG_HIP(hipMemcpyAsync(h, w.demand, 8, hipMemcpyDeviceToHost, s));
-  DSG_HIP(hipStreamSynchronize(s));
-  int64_t demand = (int64_t)h[0];
-  if (demand > 0) {
-    mat_reserve(m, demand);
-    m->h_top_ub += demand;
+  if (!graph) {
+    // the one host round trip: how much pool space moved rows need
+    unsigned long long* h = (unsigned long long*)c->pinned;
+    DSG_HIP(hipMemcpyAsync(h, w.demand, 8, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipStreamSynchronize(s));
+    int64_t demand = (int64_t)h[0];
+    if (demand > 0) {
+      mat_reserve(m, demand);
+      m->h_top_ub += demand;
+    }
   }
-  hipLaunchKernelGGL((k_commit<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, cbits, w.U, epoch,
-                     tbits, w.dkey, w.dop, w.ndelta, w.err);
+  // (graph mode: the caller reserved the worst case, see apply_headroom)
+  hipLaunchKernelGGL((k_commit<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, cbits, w.U,
+                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.ndelta, w.err);
 }
 
 // Steps 2-6 on keys/idx already filled (n entries, sentinel-padded allowed).
-void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint8_t* ops,
-              const void* vals) {
+void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint8_t* ops, const void* vals,
+              bool graph) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   int cbits = bits_for(m->ncols);
@@ -477,9 +487,8 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
   hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, s, w.keys, n, cbits, sentinel, w.kh, w.rh);
   exclusive_scan_i64(w.kh, w.ukpos, n, w.nU, w.scan, s);
   exclusive_scan_i64(w.rh, w.urpos, n, w.nR, w.scan, s);
-  DSG_HIP(hipMemsetAsync(w.demand, 0, 8, s));
-  DSG_HIP(hipMemsetAsync(w.ndelta, 0, 8, s));
-  DSG_HIP(hipMemsetAsync(w.err, 0, 4, s));
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(1), 0, s, w.demand, w.ndelta, w.err);
+  hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, m->d_epoch);
   int vsz = m->vsz;
   if (vsz == 8)
     hipLaunchKernelGGL(k_fold<8>, dim3(nb), dim3(256), 0, s, w.keys, w.idx, n, cbits, ops, vals, w.kh,
@@ -490,18 +499,62 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
   else
     hipLaunchKernelGGL(k_fold<0>, dim3(nb), dim3(256), 0, s, w.keys, w.idx, n, cbits, ops, vals, w.kh,
                        w.ukpos, w.rh, w.urpos, w.nU, w.nR, w.U);
-  uint32_t epoch = ++m->epoch;
   int tbits = bits_for(m->nrows);
   switch (m->sr) {
-    case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, epoch, tbits); break;
-    case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, epoch, tbits); break;
-    case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, epoch, tbits); break;
-    default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, epoch, tbits); break;
+    case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph); break;
+    case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph); break;
+    case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph); break;
+    default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph); break;
   }
   DSG_HIP(hipGetLastError());
 }
 
+// Everything of mat_apply_device without host round trips, on caller-owned
+// workspaces (capturable in a graph).  Error flags stay on the device.
+void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
+                    const uint8_t* d_ops, int64_t n, Work& w, Work* wt, bool graph) {
+  hipStream_t s = m->ctx->stream;
+  int cbits = bits_for(m->ncols);
+  int kbits = cbits + bits_for(m->nrows);
+  unsigned nb = blocks_for(n, 256);
+  hipLaunchKernelGGL(k_batch_keys, dim3(nb), dim3(256), 0, s, d_rows, d_cols, n, cbits, w.keys, w.idx);
+  run_core(m, w, n, kbits, false, d_ops, d_vals, graph);
+  if (m->tidx) {
+    DMat* t = m->tidx;
+    int tk = bits_for(t->ncols) + bits_for(t->nrows);
+    // the emitted deltas occupy [0, ndelta); the rest of the n slots hold the sentinel
+    hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, w.ndelta, 1ull << tk, wt->keys,
+                       wt->idx, n);
+    run_core(t, *wt, n, tk, true, w.dop, nullptr, graph);
+  }
+}
+
 }  // namespace
+
+size_t apply_work_bytes(int64_t n, bool deltas) { return work_bytes(n, deltas); }
+
+int* apply_err_ptr(void* work, int64_t n, bool deltas) { return carve_work(work, n, deltas).err; }
+
+int64_t apply_headroom(const DMat* m, int64_t n) {
+  // moved rows take at most slack_cap(len + inserts) each: <= 9/8 (nnz + n) + 4 per row
+  return m->h_top_ub + m->h_top_ub / 8 + 6 * n + 64;
+}
+
+void mat_apply_graph(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
+                     const uint8_t* d_ops, int64_t n, void* work_main, void* work_tidx) {
+  if (n == 0) return;
+  Work w = carve_work(work_main, n, m->tidx != nullptr);
+  Work wt;
+  if (m->tidx) wt = carve_work(work_tidx, n, false);
+  apply_pipeline(m, d_rows, d_cols, d_vals, d_ops, n, w, m->tidx ? &wt : nullptr, true);
+}
+
+void validate_batch_async(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const uint8_t* d_ops, int64_t n,
+                          int* d_flag) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, m->ctx->stream, d_rows, d_cols, d_ops, n,
+                     m->nrows, m->ncols, d_flag);
+}
 
 dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const uint8_t* d_ops,
                                  int64_t n) {
@@ -526,24 +579,13 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   hipStream_t s = c->stream;
   bool deltas = m->tidx != nullptr;
   Work w = carve_work(ctx_scratch(c, work_bytes(n, deltas)), n, deltas);
-  int cbits = bits_for(m->ncols);
-  int kbits = cbits + bits_for(m->nrows);
-  unsigned nb = blocks_for(n, 256);
-  hipLaunchKernelGGL(k_batch_keys, dim3(nb), dim3(256), 0, s, d_rows, d_cols, n, cbits, w.keys, w.idx);
-  run_core(m, w, n, kbits, false, d_ops, d_vals);
-  if (deltas) {
-    DMat* t = m->tidx;
-    Work wt = carve_work(ctx_scratch2(c, work_bytes(n, false)), n, false);
-    int tk = bits_for(t->ncols) + bits_for(t->nrows);
-    // the emitted deltas occupy [0, ndelta); the rest of the n slots hold the sentinel
-    hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, w.ndelta, 1ull << tk, wt.keys,
-                       wt.idx, n);
-    run_core(t, wt, n, tk, true, w.dop, nullptr);
-    DSG_HIP(hipMemcpyAsync((int*)c->pinned + 1, wt.err, 4, hipMemcpyDeviceToHost, s));
-  }
-  // a failed move (pool exhausted) would leave the batch half applied: report it loudly
+  Work wt;
+  if (deltas) wt = carve_work(ctx_scratch2(c, work_bytes(n, false)), n, false);
+  apply_pipeline(m, d_rows, d_cols, d_vals, d_ops, n, w, deltas ? &wt : nullptr, false);
   int* h = (int*)c->pinned;
   h[1] = 0;
+  if (deltas) DSG_HIP(hipMemcpyAsync(h + 1, wt.err, 4, hipMemcpyDeviceToHost, s));
+  // a failed move (pool exhausted) would leave the batch half applied: report it loudly
   DSG_HIP(hipMemcpyAsync(h, w.err, 4, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(h[0] == 0 && h[1] == 0, DSG_E_DEVICE, "internal: pool overflow while applying a batch");

@@ -59,9 +59,10 @@ struct DMat {
   int32_t* col = nullptr;
   void* val = nullptr;
   int64_t pool_cap = 0;           // slots in col/val
-  int64_t* d_top = nullptr;       // device: first free slot
+  int64_t* d_top = nullptr;       // device: first free slot (16-byte block: top, epoch)
+  uint32_t* d_epoch = nullptr;    // device: bumped by every apply (lives in the d_top block)
   int64_t h_top_ub = 0;           // host: upper bound of *d_top
-  uint32_t epoch = 1;             // bumped by every apply that changes something
+  uint64_t version = 0;           // bumped whenever the pools are reallocated
   DMat* tidx = nullptr;           // structure-only transpose index (rows = columns of this)
   int refs = 0;                   // products using this matrix
   bool counted = false;           // registered in ctx->objects
@@ -174,6 +175,15 @@ void mat_build_transpose(DMat* m);
 // Apply a device-resident batch (validated).  Returns nothing; updates epochs.
 void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
                       const uint8_t* d_ops, int64_t n);
+// Graph-capturable apply (no host round trips) on caller-owned workspaces of
+// apply_work_bytes(n, ...) bytes (work_tidx only when m->tidx).  The caller
+// must have reserved apply_headroom(m, n) free pool slots in m and in
+// m->tidx; error flags stay on the device (apply_err_ptr).
+size_t apply_work_bytes(int64_t n, bool deltas);
+int* apply_err_ptr(void* work, int64_t n, bool deltas);
+int64_t apply_headroom(const DMat* m, int64_t n);
+void mat_apply_graph(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
+                     const uint8_t* d_ops, int64_t n, void* work_main, void* work_tidx);
 // Device validation of a batch: returns dsg_status.
 dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols,
                                  const uint8_t* d_ops, int64_t n);
@@ -187,7 +197,7 @@ struct DProd {
   DMat* A = nullptr;
   DMat* B = nullptr;
   DMat* C = nullptr;
-  uint32_t syncA = 0, syncB = 0;
+  uint32_t* d_sync = nullptr;      // device [2]: epochs of A and B that C reflects
   int32_t* changed_rows = nullptr;  // device list of the last update's reported rows
   int64_t changed_cap = 0;
   int32_t* query_rows = nullptr;
@@ -196,9 +206,46 @@ struct DProd {
   size_t arena_bytes = 0;
   unsigned long long* arena_top = nullptr;   // device bump pointer into the arena
   dsg_update_stats stats{};
+  int64_t last_c_demand = 0;      // C pool and arena needs of the last plain-path run
+  int64_t last_arena_demand = 0;
+  int refs = 0;                   // batched executors and servers using this product
 };
 
 DProd* prod_create(Ctx* c, DMat* A, DMat* B);
 void prod_destroy(DProd* p);
 // mode 0: dynamic update; 1: recompute every row (static); with report_affected.
 int32_t prod_run(DProd* p, int mode, bool report_affected);
+
+// Graph-capturable dynamic update (no host round trips) on a caller-owned
+// workspace of prod_graph_work_bytes(p) bytes.  prod_prepare_graph must have
+// reserved C and arena space first; if the update needs more, the device
+// sets *d_defer and writes nothing, and the caller runs prod_run instead.
+// d_out[0..5] receives: reported rows, affected rows, error flags, deferred,
+// C space asked, arena bytes asked.
+size_t prod_graph_work_bytes(const DProd* p);
+void prod_prepare_graph(DProd* p, int64_t c_headroom, size_t arena_bytes);
+void prod_update_graph(DProd* p, void* work, int* d_defer, int64_t* d_out);
+
+// asynchronous validation of a device batch: ORs 1 (range) / 2 (op) into *d_flag
+void validate_batch_async(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const uint8_t* d_ops, int64_t n,
+                          int* d_flag);
+
+// ---------------------------------------------------------------------------
+// batched form (batch.hip)
+// ---------------------------------------------------------------------------
+
+struct DBatchSet {
+  DMat* m;
+  const int32_t* rows;
+  const int32_t* cols;
+  const void* vals;
+  const uint8_t* ops;
+  int64_t n;
+};
+struct DBatch;
+DBatch* batch_create(Ctx* c, const std::vector<DProd*>& prods);
+void batch_destroy(DBatch* b);
+// returns DSG_OK, or DSG_E_RANGE / DSG_E_ARG for a bad set (nothing applied)
+dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<int32_t>& counts);
+DProd* batch_prod(DBatch* b, int i);
+void batch_info(const DBatch* b, int64_t* captures, int64_t* replays, int64_t* deferred);

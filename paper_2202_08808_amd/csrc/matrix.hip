@@ -166,7 +166,13 @@ DMat* mat_create(Ctx* c, int32_t nrows, int32_t ncols, int sr, const int64_t* d_
     m->row_len = (int32_t*)ctx_alloc(c, n * 4);
     m->row_cap = (int32_t*)ctx_alloc(c, n * 4);
     m->row_epoch = (uint32_t*)ctx_alloc(c, n * 4);
-    m->d_top = (int64_t*)ctx_alloc(c, 8);
+    m->d_top = (int64_t*)ctx_alloc(c, 16);
+    m->d_epoch = (uint32_t*)(m->d_top + 1);
+    {
+      const uint32_t one = 1;
+      DSG_HIP(hipMemcpyAsync(m->d_epoch, &one, 4, hipMemcpyHostToDevice, s));
+      DSG_HIP(hipStreamSynchronize(s));
+    }
     hipLaunchKernelGGL(k_zero_rows, dim3(blocks_for(nrows, 256) + 1), dim3(256), 0, s, nrows, m->row_len,
                        m->row_cap, m->row_off, m->row_epoch);
     int64_t total = 0;
@@ -213,7 +219,7 @@ void mat_destroy(DMat* m) {
   ctx_free(c, m->row_len, n * 4);
   ctx_free(c, m->row_cap, n * 4);
   ctx_free(c, m->row_epoch, n * 4);
-  ctx_free(c, m->d_top, 8);
+  ctx_free(c, m->d_top, 16);
   ctx_free(c, m->col, (size_t)m->pool_cap * 4);
   if (m->val) ctx_free(c, m->val, (size_t)m->pool_cap * m->vsz);
   if (m->counted) c->objects--;
@@ -268,6 +274,7 @@ void mat_compact(DMat* m, int64_t extra) {
     m->col = ncol;
     m->val = nval;
     m->pool_cap = cap;
+    m->version++;
     set_top(m, total);
   } catch (...) {
     ctx_free(c, new_off, nn * 8);
@@ -363,6 +370,7 @@ void mat_build_transpose(DMat* m) {
       ctx_free(c, t->col, (size_t)t->pool_cap * 4);
       t->col = nullptr;
       t->pool_cap = total + total / 4 + 1024;
+      t->version++;
       t->col = (int32_t*)ctx_alloc(c, (size_t)t->pool_cap * 4);
       DSG_HIP(hipMemsetAsync(t->row_len, 0, (size_t)nt * 4, s));
       hipLaunchKernelGGL(k_fill_transpose, dim3(nb), dim3(256), 0, s, m->nrows, m->row_off, m->row_len,

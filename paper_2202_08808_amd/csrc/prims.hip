@@ -206,6 +206,14 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const
   }
 }
 
+__global__ void k_copy_pairs(const uint64_t* ks, const uint32_t* vs, uint64_t* kd, uint32_t* vd, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    kd[i] = ks[i];
+    vd[i] = vs[i];
+  }
+}
+
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -290,10 +298,8 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, v
     uint64_t* tk = ka; ka = kb; kb = tk;
     uint32_t* tv = va; va = vb; vb = tv;
   }
-  if (ka != keys) {
-    DSG_HIP(hipMemcpyAsync(keys, ka, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-    DSG_HIP(hipMemcpyAsync(vals, va, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
-  }
+  if (ka != keys)  // a kernel rather than a copy, so the sort stays capturable
+    hipLaunchKernelGGL(k_copy_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ka, va, keys, vals, n);
 }
 
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {

@@ -74,6 +74,7 @@ struct RowArgs {
   uint8_t* binof;         // per q
   int32_t* flq;           // per q: flops (clamped to int32)
   unsigned int* dense_next;  // row counter of the persistent dense kernel
+  const int* defer;          // non-null and set: skip this product (graph mode)
 };
 
 // Per-row work record, summed per bin by k_reduce_stats.
@@ -262,7 +263,8 @@ __device__ inline int64_t take_pool(const RowArgs& R, int32_t ncap, const Grp<G>
 // ---------------------------------------------------------------------------
 
 template <int SR, int G, int WG>
-__global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* list, int32_t count, int bin) {
+__global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* list, const unsigned long long* d_cnt,
+                                                   int bin) {
   using S = Sem<SR>;
   using V = typename S::V;
   using Acc = typename S::Acc;
@@ -281,12 +283,16 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
   const Grp<G> grp;
   const int g = threadIdx.x / G;
   const int lane = grp.lane;
-  const int64_t qi = (int64_t)blockIdx.x * GPB + g;
-  if (qi >= count) return;  // whole group (whole block when GPB == 1)
-  const int32_t q = list[qi];
-  const int32_t i = R.aff[q];
+  if (R.defer && *R.defer) return;
+  const int64_t count = (int64_t)*d_cnt;
   int32_t* keys = hk[g];
   Acc* vals = hv[g];
+  // rows qi = group, group + all groups of the grid, ... (one pass when the
+  // grid covers the bin; persistent when it does not)
+  for (int64_t qi = (int64_t)blockIdx.x * GPB + g; qi < count; qi += (int64_t)gridDim.x * GPB) {
+  grp.sync();  // the previous row's readers are done with the table
+  const int32_t q = list[qi];
+  const int32_t i = R.aff[q];
 
   for (int s = lane; s < SLOTS; s += G) {
     keys[s] = -1;
@@ -361,7 +367,7 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
   }
   if (grp.any(overflow, wscr)) {
     if (lane == 0) atomicOr(R.err, 2);
-    return;
+    continue;
   }
 
   // new row length
@@ -396,7 +402,7 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
     if (nnew > R.c_cap[i]) {
       ncap = slack_cap(nnew);
       dest = take_pool<G>(R, ncap, grp, &bslot);
-      if (dest < 0) return;
+      if (dest < 0) continue;
     }
     int32_t w = 0;
     for (int sb = 0; sb < SLOTS; sb += G) {
@@ -422,6 +428,7 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
     R.chg[q] = changed ? 1 : 0;
     row_stat(R, q, d, flops, nnew, olen, old_read, changed ? nnew : 0);
   }
+  }  // rows
 }
 
 // ---------------------------------------------------------------------------
@@ -526,7 +533,8 @@ __device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d,
 // ---------------------------------------------------------------------------
 
 template <int SR>
-__global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_t* list, int32_t count) {
+__global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_t* list,
+                                                         const unsigned long long* d_cnt) {
   using S = Sem<SR>;
   using V = typename S::V;
   using Acc = typename S::Acc;
@@ -543,6 +551,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   __shared__ int32_t next_row;
   const Grp<DENSE_WG> grp;
   const int tid = threadIdx.x;
+  if (R.defer && *R.defer) return;
+  const int64_t count = (int64_t)*d_cnt;
   // persistent: rows are taken in list order (longest first) from a counter
   for (;;) {
   if (tid == 0) next_row = (int32_t)atomicAdd(R.dense_next, 1u);
@@ -835,7 +845,8 @@ __device__ inline int64_t ghash_find(const int32_t* keys, int64_t slots, int32_t
 }
 
 template <int SR>
-__global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32_t* list, int32_t count) {
+__global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32_t* list,
+                                                          const unsigned long long* d_cnt) {
   using S = Sem<SR>;
   using V = typename S::V;
   using Acc = typename S::Acc;
@@ -844,8 +855,11 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
   __shared__ int64_t bslot;
   const Grp<DENSE_WG> grp;
   const int tid = threadIdx.x;
-  if ((int64_t)blockIdx.x >= count) return;
-  const int32_t q = list[blockIdx.x];
+  if (R.defer && *R.defer) return;
+  const int64_t count = (int64_t)*d_cnt;
+  for (int64_t qi = blockIdx.x; qi < count; qi += gridDim.x) {
+  grp.sync();
+  const int32_t q = list[qi];
   const int32_t i = R.aff[q];
   const int64_t aoff = R.a_off[i];
   const int32_t d = R.a_len[i];
@@ -856,7 +870,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
   tb = grp.bcast64(tb, 0, &bslot);
   if (tb + (int64_t)tbytes > R.arena_cap) {
     if (tid == 0) atomicOr(R.err, 4);
-    return;
+    break;
   }
   int32_t* keys = (int32_t*)(R.arena + tb);
   Acc* vals = (Acc*)(R.arena + tb + (size_t)slots * 4);
@@ -912,7 +926,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
   }
   if (grp.any(overflow, wscr)) {
     if (tid == 0) atomicOr(R.err, 2);
-    return;
+    continue;
   }
   int32_t nnew = 0;
   for (int64_t sb = 0; sb < slots; sb += DENSE_WG) {
@@ -945,7 +959,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
     if (nnew > R.c_cap[i]) {
       ncap = slack_cap(nnew);
       dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
-      if (dest < 0) return;
+      if (dest < 0) continue;
     }
     int32_t w = 0;
     for (int64_t sb = 0; sb < slots; sb += DENSE_WG) {
@@ -971,15 +985,16 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
     R.chg[q] = changed ? 1 : 0;
     row_stat(R, q, d, flops, nnew, olen, old_read, changed ? nnew : 0);
   }
+  }  // rows
 }
 
 // ---------------------------------------------------------------------------
 // discovery and analysis
 // ---------------------------------------------------------------------------
 
-__global__ void k_mark_changed(int32_t n, const uint32_t* epoch, uint32_t since, uint8_t* flags) {
+__global__ void k_mark_changed(int32_t n, const uint32_t* epoch, const uint32_t* since, uint8_t* flags) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) flags[i] = epoch[i] > since ? 1 : 0;
+  if (i < n) flags[i] = epoch[i] > *since ? 1 : 0;
 }
 
 // one wavefront per changed row k of B: flag every row i with A'[i,k] present
@@ -1055,15 +1070,8 @@ __global__ __launch_bounds__(256) void k_analyze(RowArgs R, const int32_t* d_cou
   const int32_t ub = (int32_t)min(f, (int64_t)R.ncols);
   R.ub[q] = ub;
   R.flq[q] = (int32_t)min(f, (int64_t)0x7fffffff);
-  if (ub == 0) {
-    const int32_t olen = R.c_len[i];
-    bool changed = R.force_write || olen != 0;
-    R.c_len[i] = 0;
-    R.chg[q] = changed ? 1 : 0;
-    R.binof[q] = 0;
-    row_stat(R, q, d, 0, 0, olen, 0, 0);
-    return;
-  }
+  // (rows with an empty new row go to the smallest bin like any other: nothing
+  // is written before the row kernels run)
   R.binof[q] = (uint8_t)pick_bin(ub, d, T);
 }
 
@@ -1083,16 +1091,14 @@ __global__ __launch_bounds__(SCATTER_NT) void k_bin_scatter(RowArgs R, const int
   int b = -1, local = 0;
   if (q < *d_count) {
     const int32_t ub = R.ub[q];
-    if (ub > 0) {
-      b = R.binof[q];
-      local = atomicAdd(&cnt[b], 1);
-      const int32_t i = R.aff[q];
-      if (ub > R.c_cap[i]) atomicAdd(&dem[0], (unsigned long long)slack_cap(ub));
-      if (b == BIN_DENSE) {
-        atomicAdd(&dem[1], (unsigned long long)(((size_t)min(ub, R.ncols) * 12 + 255) & ~size_t(255)));
-      } else if (b == BIN_GLOBAL) {
-        atomicAdd(&dem[1], (unsigned long long)(((size_t)global_slots(ub) * 12 + 255) & ~size_t(255)));
-      }
+    b = R.binof[q];
+    local = atomicAdd(&cnt[b], 1);
+    const int32_t i = R.aff[q];
+    if (ub > R.c_cap[i]) atomicAdd(&dem[0], (unsigned long long)slack_cap(ub));
+    if (b == BIN_DENSE) {
+      atomicAdd(&dem[1], (unsigned long long)(((size_t)min(ub, R.ncols) * 12 + 255) & ~size_t(255)));
+    } else if (b == BIN_GLOBAL) {
+      atomicAdd(&dem[1], (unsigned long long)(((size_t)global_slots(ub) * 12 + 255) & ~size_t(255)));
     }
   }
   __syncthreads();
@@ -1128,6 +1134,37 @@ __global__ __launch_bounds__(256) void k_reduce_stats(const RowStat* rs, const u
 
 __global__ void k_set_count(int32_t* d, int32_t v) { *d = v; }
 
+// zero fills that a captured graph may hold (graphs here carry no memset nodes)
+__global__ void k_zero_words(unsigned long long* p, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
+}
+
+__global__ void k_set_sync(uint32_t* sync, const uint32_t* ea, const uint32_t* eb, const int* defer) {
+  if (defer && *defer) return;
+  sync[0] = *ea;
+  sync[1] = *eb;
+}
+
+// Graph mode: defer this product's update -- before anything is written --
+// when its C pool or its arena cannot hold what the analysis asks for; the
+// host then runs it through the plain path.
+__global__ void k_guard(const Plan* plan, const int64_t* c_top, int64_t c_pool_cap, int64_t arena_cap,
+                        int* defer) {
+  const bool short_c = (int64_t)plan->c_demand > c_pool_cap - *c_top;
+  const bool short_a = (int64_t)plan->arena_demand > arena_cap;
+  *defer = (short_c || short_a) ? 1 : 0;
+}
+
+__global__ void k_publish(const int32_t* nchg, const int32_t* naff, const int* err, const int* defer,
+                          const Plan* plan, int64_t* out) {
+  out[0] = *nchg;
+  out[1] = *naff;
+  out[2] = *err;
+  out[3] = defer ? *defer : 0;
+  out[4] = (int64_t)plan->c_demand;
+  out[5] = (int64_t)plan->arena_demand;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1141,27 +1178,35 @@ int dense_passes_for(int vsz, int32_t ncols) {
   return (ncols + ch - 1) / ch;
 }
 
+const char* kBinNames[NBINS] = {"rows_g8",   "rows_g16",  "rows_g32",   "rows_g64",   "rows_g128",
+                                "rows_g256", "rows_g512", "rows_g1024", "rows_dense", "rows_global"};
+
+// Launch every non-empty bin.  plan == nullptr (graph mode): bin sizes are
+// only on the device, so every bin is launched with a persistent grid that
+// reads its count from d_counts.
 template <int SR>
-void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, const Plan& plan,
-                 std::vector<std::pair<int, size_t>>& timed) {
+void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, const unsigned long long* d_counts,
+                 const Plan* plan, int64_t nrows, std::vector<std::pair<int, size_t>>& timed) {
   hipStream_t s = c->stream;
-  static const char* names[NBINS] = {"rows_g8", "rows_g16", "rows_g32", "rows_g64", "rows_g128",
-                                     "rows_g256", "rows_g512", "rows_g1024", "rows_dense", "rows_global"};
+  const int64_t cus = c->num_cus;
   for (int b = 0; b < NBINS; ++b) {
-    int32_t cnt = (int32_t)plan.bin_count[b];
+    const int64_t cnt = plan ? (int64_t)plan->bin_count[b] : nrows;
     if (cnt == 0) continue;
     const int32_t* list = bins + (int64_t)b * stride;
+    const unsigned long long* dc = d_counts + b;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
-      ctx_timing_begin(c, names[b], 0.0, &e0, &e1);
+    if (c->timing && plan) {
+      ctx_timing_begin(c, kBinNames[b], 0.0, &e0, &e1);
       timed.push_back({b, c->timings.size() - 1});
     }
     switch (b) {
-#define GROUP_CASE(B, G, WG)                                                                          \
-  case B:                                                                                             \
-    hipLaunchKernelGGL((k_rows_group<SR, G, WG>), dim3(blocks_for(cnt, WG / G)), dim3(WG), 0, s, R,   \
-                       list, cnt, B);                                                                 \
-    break;
+#define GROUP_CASE(B, G, WG)                                                                              \
+  case B: {                                                                                               \
+    const int64_t blocks = plan ? (int64_t)blocks_for(cnt, WG / G)                                        \
+                                : std::min<int64_t>(blocks_for(cnt, WG / G), cus * (2048 / WG));          \
+    hipLaunchKernelGGL((k_rows_group<SR, G, WG>), dim3((unsigned)blocks), dim3(WG), 0, s, R, list, dc, B); \
+    break;                                                                                                \
+  }
       GROUP_CASE(0, 8, 256)
       GROUP_CASE(1, 16, 256)
       GROUP_CASE(2, 32, 256)
@@ -1172,17 +1217,18 @@ void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, 
       GROUP_CASE(7, 1024, 1024)
 #undef GROUP_CASE
       case BIN_DENSE: {
-        // persistent workgroups, one per CU (the kernel holds ~150 KB of LDS),
-        // taking rows longest first
-        unsigned grid = (unsigned)std::min<int64_t>(cnt, (int64_t)c->num_cus);
-        hipLaunchKernelGGL((k_rows_dense<SR>), dim3(grid), dim3(DENSE_WG), 0, s, R, list, cnt);
+        // persistent workgroups, one per CU (each holds ~150 KB of LDS)
+        const unsigned grid = (unsigned)std::min<int64_t>(cnt, cus);
+        hipLaunchKernelGGL((k_rows_dense<SR>), dim3(grid), dim3(DENSE_WG), 0, s, R, list, dc);
         break;
       }
-      case BIN_GLOBAL:
-        hipLaunchKernelGGL((k_rows_global<SR>), dim3(cnt), dim3(DENSE_WG), 0, s, R, list, cnt);
+      case BIN_GLOBAL: {
+        const unsigned grid = (unsigned)(plan ? cnt : std::min<int64_t>(cnt, cus * 2));
+        hipLaunchKernelGGL((k_rows_global<SR>), dim3(grid), dim3(DENSE_WG), 0, s, R, list, dc);
         break;
+      }
     }
-    if (c->timing) ctx_timing_end(c, e1);
+    if (c->timing && plan) ctx_timing_end(c, e1);
   }
   DSG_HIP(hipGetLastError());
 }
@@ -1207,57 +1253,14 @@ struct ProdWork {
   void* cscr;
 };
 
-}  // namespace
-
-DProd* prod_create(Ctx* c, DMat* A, DMat* B) {
-  DProd* p = new DProd();
-  p->ctx = c;
-  p->A = A;
-  p->B = B;
-  try {
-    mat_build_transpose(A);
-    p->C = mat_create(c, A->nrows, B->ncols, A->sr, nullptr, nullptr, nullptr);
-  } catch (...) {
-    delete p;
-    throw;
-  }
-  A->refs++;
-  B->refs++;
-  try {
-    prod_run(p, 1, true);
-  } catch (...) {
-    prod_destroy(p);
-    throw;
-  }
-  return p;
+size_t work_bytes_for(int64_t N, int64_t nB) {
+  return Carve::need({(size_t)N, (size_t)nB, (size_t)N * 4, 64, (size_t)nB * 4, 64, (size_t)N * 4, (size_t)N,
+                      (size_t)N * 4 * NBINS, sizeof(Plan) + 64, NBINS * NSTAT * 8 + 64, (size_t)N * sizeof(RowStat),
+                      (size_t)N, (size_t)N * 4, 64, 64, compact_scratch_bytes(std::max(N, nB)) + 64});
 }
 
-void prod_destroy(DProd* p) {
-  if (!p) return;
-  Ctx* c = p->ctx;
-  if (p->changed_rows) ctx_free(c, p->changed_rows, (size_t)p->changed_cap * 4);
-  if (p->query_rows) ctx_free(c, p->query_rows, (size_t)p->query_cap * 4);
-  if (p->arena) ctx_free(c, p->arena, p->arena_bytes);
-  if (p->C) mat_destroy(p->C);
-  if (p->A) p->A->refs--;
-  if (p->B) p->B->refs--;
-  delete p;
-}
-
-int32_t prod_run(DProd* p, int mode, bool report_affected) {
-  Ctx* c = p->ctx;
-  hipStream_t s = c->stream;
-  DMat* A = p->A;
-  DMat* B = p->B;
-  DMat* C = p->C;
-  const int32_t n = A->nrows;
-  const int64_t N = n > 0 ? n : 1;
-  const int64_t nB = B->nrows > 0 ? B->nrows : 1;
-  const size_t need = Carve::need({(size_t)N, (size_t)nB, (size_t)N * 4, 64, (size_t)nB * 4, 64, (size_t)N * 4, (size_t)N,
-                                   (size_t)N * 4 * NBINS, sizeof(Plan) + 64, NBINS * NSTAT * 8 + 64,
-                                   (size_t)N * sizeof(RowStat), (size_t)N, (size_t)N * 4, 64, 64,
-                                   compact_scratch_bytes(std::max(N, nB)) + 64});
-  Carve cv(ctx_scratch(c, need), need);
+ProdWork carve_prod(void* base, int64_t N, int64_t nB) {
+  Carve cv(base, work_bytes_for(N, nB));
   ProdWork w;
   w.aff_flags = cv.take<uint8_t>(N);
   w.b_flags = cv.take<uint8_t>(nB);
@@ -1276,21 +1279,59 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   w.err = cv.take<int>(16);
   w.d_nchg = cv.take<int32_t>(16);
   w.cscr = cv.take<char>(compact_scratch_bytes(std::max(N, nB)) + 64);
+  return w;
+}
 
-  DSG_HIP(hipMemsetAsync(w.plan, 0, sizeof(Plan), s));
-  DSG_HIP(hipMemsetAsync(w.stats, 0, NBINS * NSTAT * 8, s));
-  DSG_HIP(hipMemsetAsync(w.err, 0, 4, s));
+void ensure_changed_cap(DProd* p, int64_t need) {
+  if (need <= p->changed_cap) return;
+  Ctx* c = p->ctx;
+  if (p->changed_rows) ctx_free(c, p->changed_rows, (size_t)p->changed_cap * 4);
+  p->changed_rows = nullptr;
+  p->changed_cap = 0;
+  const int64_t cap = std::max<int64_t>(need, 1024);
+  p->changed_rows = (int32_t*)ctx_alloc(c, (size_t)cap * 4);
+  p->changed_cap = cap;
+}
+
+void ensure_arena(DProd* p, size_t bytes) {
+  Ctx* c = p->ctx;
+  if (!p->arena_top) p->arena_top = (unsigned long long*)ctx_alloc(c, 64);
+  if (bytes <= p->arena_bytes) return;
+  if (p->arena) ctx_free(c, p->arena, p->arena_bytes);
+  p->arena = nullptr;
+  p->arena_bytes = 0;
+  const size_t nb = bytes + bytes / 4 + 4096;
+  p->arena = ctx_alloc(c, nb);
+  p->arena_bytes = nb;
+}
+
+// One product update (mode 0) or full recompute (mode 1).  Plain mode reads
+// the bin sizes and space needs back after the analysis and the results at
+// the end.  Graph mode (d_defer != nullptr) makes no host round trip: the
+// caller has reserved C and arena space, the device guard defers the product
+// if that is not enough, and k_publish leaves the results in d_out.
+int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, int* d_defer, int64_t* d_out) {
+  Ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  const bool graph = d_defer != nullptr;
+  DMat* A = p->A;
+  DMat* B = p->B;
+  DMat* C = p->C;
+  const int32_t n = A->nrows;
+
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (unsigned long long*)w.plan, (int)(sizeof(Plan) / 8));
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, w.stats, NBINS * NSTAT);
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, (unsigned long long*)w.err, 1);
   // ---- affected rows ----
   if (mode == 1) {
     iota_i32(w.aff, n, s);
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, w.d_count, n);
   } else if (n > 0) {
-    hipLaunchKernelGGL(k_mark_changed, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->row_epoch, p->syncA,
-                       w.aff_flags);
+    hipLaunchKernelGGL(k_mark_changed, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, A->row_epoch,
+                       (const uint32_t*)p->d_sync, w.aff_flags);
     if (B->nrows > 0) {
-      // changed rows of B
-      hipLaunchKernelGGL(k_mark_changed, dim3(blocks_for(B->nrows, 256)), dim3(256), 0, s, B->nrows,
-                         B->row_epoch, p->syncB, w.b_flags);
+      hipLaunchKernelGGL(k_mark_changed, dim3(blocks_for(B->nrows, 256)), dim3(256), 0, s, B->nrows, B->row_epoch,
+                         (const uint32_t*)p->d_sync + 1, w.b_flags);
       compact_flags(w.b_flags, B->nrows, w.dB, w.d_nB, w.cscr, s);
       DMat* T = A->tidx;
       unsigned nbk = (unsigned)std::min<int64_t>(blocks_for((int64_t)B->nrows * 64, 256), 8192);
@@ -1316,6 +1357,7 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   R.binof = w.binof;
   R.flq = w.flq;
   R.dense_next = &w.plan->dense_next;
+  R.defer = d_defer;
 
   Tun T;
   const dsg_tuning& tu = c->tuning;
@@ -1329,62 +1371,66 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
     hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n, SCATTER_NT)), dim3(SCATTER_NT), 0, s, R, w.d_count,
                        w.plan, w.bins, n);
   }
-  // ---- host round trip 1: bin sizes and space needs ----
-  Plan* hp = (Plan*)c->pinned;
-  DSG_HIP(hipMemcpyAsync(hp, w.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
-  DSG_HIP(hipMemcpyAsync(&hp->count, w.d_count, 4, hipMemcpyDeviceToHost, s));
-  DSG_HIP(hipStreamSynchronize(s));
-  Plan plan = *hp;
-  if (plan.c_demand > 0) {
-    mat_reserve(C, (int64_t)plan.c_demand);
-    C->h_top_ub += (int64_t)plan.c_demand;
-  }
-  if (plan.arena_demand > 0) {
-    if (plan.arena_demand > p->arena_bytes) {
-      if (p->arena) ctx_free(c, p->arena, p->arena_bytes);
-      p->arena = nullptr;
-      size_t nb = plan.arena_demand + plan.arena_demand / 4 + 4096;
-      p->arena = ctx_alloc(c, nb);
-      p->arena_bytes = nb;
+  Plan plan{};
+  if (graph) {
+    hipLaunchKernelGGL(k_guard, dim3(1), dim3(1), 0, s, (const Plan*)w.plan, (const int64_t*)C->d_top,
+                       C->pool_cap, (int64_t)p->arena_bytes, d_defer);
+    if (p->arena_top)
+      hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, p->arena_top, 1);
+  } else {
+    // ---- host round trip 1: bin sizes and space needs ----
+    Plan* hp = (Plan*)c->pinned;
+    DSG_HIP(hipMemcpyAsync(hp, w.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipMemcpyAsync(&hp->count, w.d_count, 4, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipStreamSynchronize(s));
+    plan = *hp;
+    if (plan.c_demand > 0) {
+      mat_reserve(C, (int64_t)plan.c_demand);
+      C->h_top_ub += (int64_t)plan.c_demand;
     }
-    if (!p->arena_top) p->arena_top = (unsigned long long*)ctx_alloc(c, 64);
-    DSG_HIP(hipMemsetAsync(p->arena_top, 0, 8, s));
-  }
-  R.c_col = C->col; R.c_val = C->val; R.c_off = C->row_off; R.c_top = C->d_top; R.c_pool_cap = C->pool_cap;
-  R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
-
-  // the dense bin runs persistent workgroups: hand them the longest rows first
-  const int64_t ndense = (int64_t)plan.bin_count[BIN_DENSE];
-  if (ndense > 1) {
-    int32_t* dl = w.bins + (int64_t)BIN_DENSE * n;
-    const size_t nb = Carve::need({(size_t)ndense * 8, (size_t)ndense * 4, radix_scratch_bytes(ndense)});
-    Carve dc(ctx_scratch2(c, nb), nb);
-    uint64_t* keys = dc.take<uint64_t>(ndense);
-    uint32_t* vals = dc.take<uint32_t>(ndense);
-    void* rs = dc.take<char>(radix_scratch_bytes(ndense));
-    hipLaunchKernelGGL(k_flop_keys, dim3(blocks_for(ndense, 256)), dim3(256), 0, s, dl, (int32_t)ndense, w.flq,
-                       keys, vals);
-    radix_sort_pairs(keys, vals, ndense, FLOP_KEY_BITS, rs, s);
-    DSG_HIP(hipMemcpyAsync(dl, vals, (size_t)ndense * 4, hipMemcpyDeviceToDevice, s));
+    if (plan.arena_demand > 0) {
+      ensure_arena(p, plan.arena_demand);
+      DSG_HIP(hipMemsetAsync(p->arena_top, 0, 8, s));
+    }
+    ensure_changed_cap(p, plan.count);
+    R.c_col = C->col; R.c_val = C->val; R.c_off = C->row_off; R.c_top = C->d_top; R.c_pool_cap = C->pool_cap;
+    R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
+    // the dense bin runs persistent workgroups: hand them the longest rows first
+    const int64_t ndense = (int64_t)plan.bin_count[BIN_DENSE];
+    if (ndense > 1) {
+      int32_t* dl = w.bins + (int64_t)BIN_DENSE * n;
+      const size_t nb = Carve::need({(size_t)ndense * 8, (size_t)ndense * 4, radix_scratch_bytes(ndense)});
+      Carve dc(ctx_scratch2(c, nb), nb);
+      uint64_t* keys = dc.take<uint64_t>(ndense);
+      uint32_t* vals = dc.take<uint32_t>(ndense);
+      void* rs = dc.take<char>(radix_scratch_bytes(ndense));
+      hipLaunchKernelGGL(k_flop_keys, dim3(blocks_for(ndense, 256)), dim3(256), 0, s, dl, (int32_t)ndense, w.flq,
+                         keys, vals);
+      radix_sort_pairs(keys, vals, ndense, FLOP_KEY_BITS, rs, s);
+      DSG_HIP(hipMemcpyAsync(dl, vals, (size_t)ndense * 4, hipMemcpyDeviceToDevice, s));
+    }
   }
   std::vector<std::pair<int, size_t>> timed;
+  const Plan* hplan = graph ? nullptr : &plan;
   switch (A->sr) {
-    case 0: launch_bins<0>(c, R, w.bins, n, plan, timed); break;
-    case 1: launch_bins<1>(c, R, w.bins, n, plan, timed); break;
-    default: launch_bins<2>(c, R, w.bins, n, plan, timed); break;
+    case 0: launch_bins<0>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
+    case 1: launch_bins<1>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
+    default: launch_bins<2>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
   }
-  // ---- reported rows ----
-  if ((int64_t)plan.count > p->changed_cap) {
-    if (p->changed_rows) ctx_free(c, p->changed_rows, (size_t)p->changed_cap * 4);
-    p->changed_rows = nullptr;
-    p->changed_cap = std::max<int64_t>(plan.count, 1024);
-    p->changed_rows = (int32_t*)ctx_alloc(c, (size_t)p->changed_cap * 4);
+  // ---- reported rows and statistics ----
+  const int64_t nmax = graph ? std::max<int32_t>(n, 1) : std::max<int32_t>(plan.count, 1);
+  compact_list_by_flags(w.aff, w.chg, w.d_count, nmax, p->changed_rows, w.d_nchg, w.cscr, s);
+  if (nmax > 0)
+    hipLaunchKernelGGL(k_reduce_stats, dim3(blocks_for(nmax, 256)), dim3(256), 0, s, w.rstat, w.binof, w.d_count,
+                       w.stats);
+  hipLaunchKernelGGL(k_set_sync, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)A->d_epoch,
+                     (const uint32_t*)B->d_epoch, (const int*)d_defer);
+  if (graph) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, (const int32_t*)w.d_nchg, (const int32_t*)w.d_count,
+                       (const int*)w.err, (const int*)d_defer, (const Plan*)w.plan, d_out);
+    DSG_HIP(hipGetLastError());
+    return 0;
   }
-  compact_list_by_flags(w.aff, w.chg, w.d_count, std::max<int32_t>(plan.count, 1), p->changed_rows, w.d_nchg,
-                        w.cscr, s);
-  if (plan.count > 0)
-    hipLaunchKernelGGL(k_reduce_stats, dim3(blocks_for(plan.count, 256)), dim3(256), 0, s, w.rstat, w.binof,
-                       w.d_count, w.stats);
   // ---- host round trip 2: row count, statistics, errors ----
   struct Tail {
     int32_t nchg;
@@ -1397,10 +1443,7 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   DSG_HIP(hipMemcpyAsync(ht->stats, w.stats, sizeof(ht->stats), hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));
   Tail tail = *ht;
-  DSG_REQUIRE(tail.err == 0, DSG_E_DEVICE,
-              "internal: row kernel reported error code " + std::to_string(tail.err));
-  p->syncA = A->epoch;
-  p->syncB = B->epoch;
+  DSG_REQUIRE(tail.err == 0, DSG_E_DEVICE, "internal: row kernel reported error code " + std::to_string(tail.err));
   dsg_update_stats& st = p->stats;
   st = dsg_update_stats{};
   st.affected_rows = plan.count;
@@ -1415,11 +1458,80 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
     st.nnz_new += (int64_t)x[3];
     st.nnz_old += (int64_t)x[4];
   }
+  p->last_c_demand = (int64_t)plan.c_demand;
+  p->last_arena_demand = (int64_t)plan.arena_demand;
   for (auto& tb : timed) {
     const unsigned long long* x = tail.stats + tb.first * NSTAT;
     // A row, B row lookups (offset + length), B entries, old C row when compared, new C row when written
-    c->timings[tb.second].bytes = sz * (double)x[1] + 12.0 * (double)x[1] + sz * (double)x[2] +
-                                  sz * (double)x[5] + sz * (double)x[6];
+    c->timings[tb.second].bytes =
+        sz * (double)x[1] + 12.0 * (double)x[1] + sz * (double)x[2] + sz * (double)x[5] + sz * (double)x[6];
   }
   return tail.nchg;
+}
+
+}  // namespace
+
+DProd* prod_create(Ctx* c, DMat* A, DMat* B) {
+  DProd* p = new DProd();
+  p->ctx = c;
+  p->A = A;
+  p->B = B;
+  try {
+    mat_build_transpose(A);
+    p->C = mat_create(c, A->nrows, B->ncols, A->sr, nullptr, nullptr, nullptr);
+    p->d_sync = (uint32_t*)ctx_alloc(c, 16);
+  } catch (...) {
+    if (p->C) mat_destroy(p->C);
+    delete p;
+    throw;
+  }
+  A->refs++;
+  B->refs++;
+  try {
+    prod_run(p, 1, true);
+  } catch (...) {
+    prod_destroy(p);
+    throw;
+  }
+  return p;
+}
+
+void prod_destroy(DProd* p) {
+  if (!p) return;
+  Ctx* c = p->ctx;
+  if (p->changed_rows) ctx_free(c, p->changed_rows, (size_t)p->changed_cap * 4);
+  if (p->query_rows) ctx_free(c, p->query_rows, (size_t)p->query_cap * 4);
+  if (p->arena) ctx_free(c, p->arena, p->arena_bytes);
+  if (p->arena_top) ctx_free(c, p->arena_top, 64);
+  if (p->d_sync) ctx_free(c, p->d_sync, 16);
+  if (p->C) mat_destroy(p->C);
+  if (p->A) p->A->refs--;
+  if (p->B) p->B->refs--;
+  delete p;
+}
+
+int32_t prod_run(DProd* p, int mode, bool report_affected) {
+  const int64_t N = std::max<int32_t>(p->A->nrows, 1);
+  const int64_t nB = std::max<int32_t>(p->B->nrows, 1);
+  ensure_changed_cap(p, 0);
+  const size_t need = work_bytes_for(N, nB);
+  ProdWork w = carve_prod(ctx_scratch(p->ctx, need), N, nB);
+  return prod_sequence(p, mode, report_affected, w, nullptr, nullptr);
+}
+
+size_t prod_graph_work_bytes(const DProd* p) {
+  return work_bytes_for(std::max<int32_t>(p->A->nrows, 1), std::max<int32_t>(p->B->nrows, 1));
+}
+
+void prod_update_graph(DProd* p, void* work, int* d_defer, int64_t* d_out) {
+  const int64_t N = std::max<int32_t>(p->A->nrows, 1);
+  const int64_t nB = std::max<int32_t>(p->B->nrows, 1);
+  ProdWork w = carve_prod(work, N, nB);
+  prod_sequence(p, 0, false, w, d_defer, d_out);
+}
+
+void prod_prepare_graph(DProd* p, int64_t c_headroom, size_t arena_bytes) {
+  ensure_changed_cap(p, std::max<int32_t>(p->A->nrows, 1));
+  ensure_arena(p, arena_bytes);
+  mat_reserve(p->C, c_headroom);
 }

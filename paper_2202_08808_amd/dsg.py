@@ -80,14 +80,32 @@ SIGNATURES = {
     "dsg_prod_nnz": [P, P],
     "dsg_prod_export": [P, P, P, P, ctypes.c_int64, P],
     "dsg_prod_stats": [P, P],
+    "dsg_prod_autotune": [P, ctypes.c_int32, P, P, ctypes.c_char_p, ctypes.c_size_t],
     "dsg_prod_destroy": [P],
+    "dsg_batch_create": [P, P, ctypes.c_int32, P],
+    "dsg_batch_run": [P, P, ctypes.c_int32, ctypes.c_uint32, P],
+    "dsg_batch_rows": [P, ctypes.c_int32, P],
+    "dsg_batch_info": [P, P, P, P],
+    "dsg_batch_destroy": [P],
 }
+
+
+class UpdateSet(ctypes.Structure):
+    _fields_ = [("mat", P), ("rows", P), ("cols", P), ("vals", P), ("ops", P), ("n", ctypes.c_int64)]
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
                           " (the GPU path has no fallback)")
+    # PyTorch-ROCm ships its own HIP runtime under the same soname as the
+    # system one.  Loading torch first makes the library bind to that copy, so
+    # the process holds one HIP runtime and torch's buffers and streams are
+    # usable by the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     for name, args in SIGNATURES.items():
         fn = getattr(L, name)
@@ -274,6 +292,14 @@ class RowSet:
 _HIP = None
 
 
+def _arch() -> str:
+    try:
+        import torch
+        return str(torch.cuda.get_device_properties(0).gcnArchName).split(":")[0]
+    except Exception:
+        return "unknown"
+
+
 def _hip():
     global _HIP
     if _HIP is None:
@@ -322,7 +348,82 @@ class Product:
         self.ctx._check(self.L.dsg_prod_stats(self.h, ctypes.byref(s)))
         return s.as_dict()
 
+    def autotune(self, reps: int = 3, cache_path: Optional[str] = None) -> dict:
+        """Pick the row-kernel tuning for this product (timed trials in the
+        library).  With cache_path, results are stored in a JSON file keyed by
+        (device arch, semiring, shape, nnz(A) and nnz(C) to two significant
+        digits) and reused without trials."""
+        key = json.dumps([_arch(), self.semiring, self.nrows, self.ncols,
+                          float(f"{self.A.nnz():.2g}"), float(f"{self.nnz():.2g}")])
+        cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                cache = json.load(f)
+        if key in cache:
+            t = Tuning()
+            ent = cache[key]
+            for b in range(8):
+                t.group_ub[b] = ent["group_ub"][b]
+            t.dense_max_passes = ent["dense_max_passes"]
+            t.force_bin = -1
+            self.ctx.set_tuning(t)
+            return dict(ent, cached=True)
+        best = Tuning()
+        ms = ctypes.c_double()
+        buf = ctypes.create_string_buffer(1 << 16)
+        self.ctx._check(self.L.dsg_prod_autotune(self.h, reps, ctypes.byref(best), ctypes.byref(ms), buf,
+                                                 len(buf)))
+        ent = {"group_ub": list(best.group_ub), "dense_max_passes": best.dense_max_passes,
+               "ms": ms.value, "trials": json.loads(buf.value.decode())}
+        if cache_path:
+            cache[key] = {k: v for k, v in ent.items() if k != "trials"}
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1)
+        return dict(ent, cached=False)
+
     def destroy(self):
         if self.h:
             self.ctx._check(self.L.dsg_prod_destroy(self.h))
+            self.h = None
+
+
+class Batch:
+    """Batched executor: many independent products, one hipGraph replay per run."""
+
+    def __init__(self, ctx: Context, prods):
+        self.ctx, self.L = ctx, ctx.L
+        self.prods = list(prods)
+        arr = (P * max(len(self.prods), 1))(*[p.h for p in self.prods])
+        h = P()
+        ctx._check(self.L.dsg_batch_create(ctx.h, arr, len(self.prods), ctypes.byref(h)))
+        self.h = h
+
+    def run(self, sets):
+        """sets: list of (Matrix, rows, cols, vals, ops) with device tensors.
+        Returns the reported-row count of every product."""
+        arr = (UpdateSet * max(len(sets), 1))()
+        for k, (m, rows, cols, vals, ops) in enumerate(sets):
+            arr[k].mat = m.h
+            arr[k].rows = _ptr(rows)[0]
+            arr[k].cols = _ptr(cols)[0]
+            arr[k].vals = _ptr(vals)[0]
+            arr[k].ops = _ptr(ops)[0]
+            arr[k].n = int(rows.shape[0])
+        counts = (ctypes.c_int32 * max(len(self.prods), 1))()
+        self.ctx._check(self.L.dsg_batch_run(self.h, arr, len(sets), 0, counts))
+        return [int(counts[i]) for i in range(len(self.prods))]
+
+    def rows(self, i: int) -> RowSet:
+        v = Rows()
+        self.ctx._check(self.L.dsg_batch_rows(self.h, i, ctypes.byref(v)))
+        return RowSet(self.prods[i], v)
+
+    def info(self) -> dict:
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self.ctx._check(self.L.dsg_batch_info(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"captures": a.value, "replays": b.value, "deferred": c.value}
+
+    def destroy(self):
+        if self.h:
+            self.ctx._check(self.L.dsg_batch_destroy(self.h))
             self.h = None

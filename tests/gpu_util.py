@@ -67,8 +67,9 @@ def changed_rows(before, after):
     pb = np.nonzero(~diff[rid_b])[0]
     pa = np.nonzero(~diff[rid_a])[0]
     assert pb.size == pa.size
-    vb = np.ascontiguousarray(before.val).view(np.uint8).reshape(before.val.size, -1)
-    va = np.ascontiguousarray(after.val).view(np.uint8).reshape(after.val.size, -1)
+    isz = np.asarray(before.val).dtype.itemsize
+    vb = np.ascontiguousarray(before.val).view(np.uint8).reshape(before.val.size, isz)
+    va = np.ascontiguousarray(after.val).view(np.uint8).reshape(after.val.size, isz)
     ne = (before.col[pb] != after.col[pa]) | (vb[pb] != va[pa]).any(axis=1)
     diff[rid_b[pb[ne]]] = True
     return np.nonzero(diff)[0].astype(np.int32)

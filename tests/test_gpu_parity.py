@@ -262,6 +262,28 @@ def test_report_affected_superset(ctx):
     destroy(P, Am)
 
 
+def test_autotune_keeps_results(tuned, tmp_path):
+    """The autotuner's trials and its chosen tuning never change C; a second
+    call with the cache file reuses the choice without trials."""
+    ctx = tuned
+    say("autotune")
+    sr = I.MIN_PLUS_F32
+    A = I.rmat_csr(11, 16, sr, stream=55, lo=1, hi=100)
+    Am, _, P = gpu_product(ctx, sr, A)
+    cache = str(tmp_path / "tune.json")
+    r1 = P.autotune(reps=1, cache_path=cache)
+    assert not r1["cached"] and len(r1["trials"]) >= 8
+    check_product(sr, P, A, A, "after autotune")
+    r2 = P.autotune(reps=1, cache_path=cache)
+    assert r2["cached"] and r2["group_ub"] == r1["group_ub"]
+    b = I.disjoint_batches(A, sr, [500], stream=56, value_lo=1, value_hi=100)[0]
+    Am.apply_batch(b)
+    P.update()
+    a, _ = oracle.apply(sr, oracle.Csr.of(A), b.rows, b.cols, b.vals, b.ops)
+    assert_same_csr(sr, P.export(), oracle.spgemm(sr, a, a, nthreads=THREADS), "update after autotune")
+    destroy(P, Am)
+
+
 def test_config1_rmat12_int64(ctx):
     """R-MAT scale 12, edge factor 8, int64 plus-times, one batch of 100
     insertions: dynamic C' equals the oracle's static recompute."""
