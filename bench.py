@@ -72,12 +72,114 @@ def cpu_baseline(w, n_batches: int, budget_s: float = 20.0):
                       f"recompute of C' ({dt:.1f} s)"}
 
 
+def bench_batched(args):
+    """Batched form: independent R-MAT instances (scale ~ U{10..16}, edge
+    factor ~ U{4,8,16,32}, int64 plus-times and min-plus alternating, one
+    batch of size floor(10^U(1,4)) each per round, mix 50/25/25).  Two equal
+    copies of every instance: one brought up to date by the plain
+    per-instance loop (apply + update), one by one batched graph replay; both
+    timed over the same rounds, both outside the timed region fed from
+    device-resident batches."""
+    import torch
+    from paper_2202_08808_amd import dsg
+    from paper_2202_08808_amd import inputs as I
+
+    K, W = args.steps, args.warmup
+    desc = I.batched_instances(args.instances, max_scale=args.max_scale)
+    ctx = dsg.Context(0, stream=torch.cuda.current_stream())
+    plain, batched, rounds = [], [], []
+    t0 = time.perf_counter()
+    total_updates = 0
+    for t, (scale, ef, sr, b) in enumerate(desc):
+        lo, hi = (1, 9) if sr == I.PLUS_TIMES_I64 else (1, 100)
+        A = I.rmat_csr(scale, ef, sr, stream=1000 + t, lo=lo, hi=hi)
+        try:
+            bs = I.disjoint_batches(A, sr, [b] * (K + W), stream=2000 + t, value_lo=lo, value_hi=hi)
+        except ValueError:
+            # too few entries for pairwise-distinct deletes/changes over all rounds:
+            # uniform positions, 75% SET (insert or change) and 25% DELETE
+            rng = I.rng_for(2000 + t, 1)
+            bs = [I.random_batch(A.nrows, A.ncols, sr, b, rng, op_probs=(0.75, 0.25, 0.0), value_lo=lo,
+                                 value_hi=hi) for _ in range(K + W)]
+        a1 = dsg.Matrix.from_csr(ctx, A, sr)
+        a2 = dsg.Matrix.from_csr(ctx, A, sr)
+        plain.append((a1, dsg.Product(ctx, a1, a1)))
+        batched.append((a2, dsg.Product(ctx, a2, a2)))
+        rounds.append([[torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (q.rows, q.cols, q.vals, q.ops)]
+                       for q in bs])
+        total_updates += b
+    log(f"[bench] {len(desc)} instances, {total_updates} updates per round, set up in "
+        f"{time.perf_counter() - t0:.1f}s")
+    B = dsg.Batch(ctx, [p for _, p in batched])
+    bufs = [[x.clone() for x in rounds[t][0]] for t in range(len(desc))]
+
+    def fill(r):
+        for t in range(len(desc)):
+            for x, y in zip(bufs[t], rounds[t][r]):
+                x.copy_(y)
+        torch.cuda.synchronize()
+
+    t_plain, t_batch = [], []
+    for r in range(W + K):
+        fill(r)
+        # plain loop: apply + update, instance after instance
+        t1 = time.perf_counter()
+        for t, (a, p) in enumerate(plain):
+            a.apply(*bufs[t])
+            p.update()
+        torch.cuda.synchronize()
+        dt_plain = time.perf_counter() - t1
+        # batched: every instance in one graph replay
+        t1 = time.perf_counter()
+        counts = B.run([(batched[t][0], *bufs[t]) for t in range(len(desc))])
+        torch.cuda.synchronize()
+        dt_batch = time.perf_counter() - t1
+        if r >= W:
+            t_plain.append(dt_plain)
+            t_batch.append(dt_batch)
+        log(f"[bench] round {r}: plain loop {dt_plain * 1e3:.2f} ms, batched {dt_batch * 1e3:.2f} ms, "
+            f"{sum(counts)} rows reported")
+    # the two copies must agree (spot check: every instance's row count)
+    for t in range(len(desc)):
+        assert plain[t][1].nnz() == batched[t][1].nnz(), f"instance {t} differs"
+    info = B.info()
+    tp, tb = float(np.sum(t_plain)), float(np.sum(t_batch))
+    out = {
+        "metric": "batched dynamic SpGEMM updates/s",
+        "value": round(total_updates * K / tb, 2),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(tb / K * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64+f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched_{len(desc)}_rmat_instances", "instances": len(desc),
+                   "scales": [d[0] for d in desc], "edge_factors": [d[1] for d in desc],
+                   "batch_sizes": [d[3] for d in desc], "updates_per_round": total_updates},
+        "plain_loop_ms_per_round": round(tp / K * 1e3, 4),
+        "speedup_vs_plain_loop": round(tp / tb, 4),
+        "graph": info,
+    }
+    B.destroy()
+    for a, p in plain + batched:
+        p.destroy()
+        a.destroy()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat12", "stencil", "er"])
+    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat12", "stencil", "er", "batched"])
+    ap.add_argument("--instances", type=int, default=64, help="batched workload: number of instances")
+    ap.add_argument("--max-scale", type=int, default=16, help="batched workload: largest R-MAT scale")
     ap.add_argument("--batch", type=int, default=10000)
     ap.add_argument("--static-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -89,6 +191,8 @@ def main():
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the whole problem lives on one "
               "MI355X and this build has no multi-GPU path", file=sys.stderr)
         raise SystemExit(2)
+    if args.workload == "batched":
+        return bench_batched(args)
 
     import torch
     from paper_2202_08808_amd import dsg

@@ -5,10 +5,9 @@
 // is captured on a stream of its own, forked from and joined to the
 // context's stream, so independent instances overlap on the device.  The
 // chains make no host round trip: operand pools hold the worst-case room a
-// set can take (apply_headroom), C and the staging arena hold the room the
-// previous round needed plus a margin, and a device guard defers a product
-// whose update asks for more -- before anything of C is written -- to the
-// plain path after the replay.  The graph is captured on the first run and
+// set can take (apply_headroom); rows of C that find no room in C or in the
+// staging arena write nothing and are recomputed after the replay, once the
+// room has grown by exactly what they asked for.  The graph is captured on the first run and
 // replayed while every pointer and size it baked in is unchanged.
 #include <algorithm>
 
@@ -49,7 +48,6 @@ struct DBatch {
   std::vector<size_t> aw_bytes, awt_bytes;
   std::vector<void*> pw;
   std::vector<size_t> pw_bytes;
-  int* d_defer = nullptr;
   int64_t* d_out = nullptr;
   int64_t* d_tops = nullptr;
   int64_t** d_top_ptrs = nullptr;
@@ -83,7 +81,6 @@ DBatch* batch_create(Ctx* c, const std::vector<DProd*>& prods) {
         if (m && std::find(b->mats.begin(), b->mats.end(), m) == b->mats.end()) b->mats.push_back(m);
     }
     const size_t np = prods.size() ? prods.size() : 1;
-    b->d_defer = (int*)ctx_alloc(c, np * 4);
     b->d_out = (int64_t*)ctx_alloc(c, np * OUT_WORDS * 8);
     b->d_tops = (int64_t*)ctx_alloc(c, b->mats.size() * 8 + 8);
     b->d_top_ptrs = (int64_t**)ctx_alloc(c, b->mats.size() * 8 + 8);
@@ -113,7 +110,6 @@ void batch_destroy(DBatch* b) {
   free_ws(c, b->awt, b->awt_bytes);
   free_ws(c, b->pw, b->pw_bytes);
   const size_t np = b->prods.size() ? b->prods.size() : 1;
-  ctx_free(c, b->d_defer, np * 4);
   ctx_free(c, b->d_out, np * OUT_WORDS * 8);
   ctx_free(c, b->d_tops, b->mats.size() * 8 + 8);
   ctx_free(c, b->d_top_ptrs, b->mats.size() * 8 + 8);
@@ -187,8 +183,9 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   }
   for (size_t j = 0; j < np; ++j) {
     DProd* p = b->prods[j];
-    const int64_t c_room = std::max<int64_t>(p->last_c_demand + p->last_c_demand / 4, p->C->h_top_ub / 4) + 4096;
-    const size_t arena = (size_t)std::max<int64_t>(p->last_arena_demand + p->last_arena_demand / 4, 1 << 20);
+    // modest room: rows that need more are completed after the replay
+    const int64_t c_room = p->C->h_top_ub / 8 + 4096;
+    const size_t arena = std::max<size_t>(p->arena_bytes, (size_t)1 << 20);
     prod_prepare_graph(p, c_room, arena);
     ensure_ws(c, b->pw, b->pw_bytes, j, prod_graph_work_bytes(p), ws_changed);
   }
@@ -241,7 +238,7 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
           }
           slot = 7;
         }
-        prod_update_graph(b->prods[j], b->pw[j], b->d_defer + j, b->d_out + j * OUT_WORDS);
+        prod_update_graph(b->prods[j], b->pw[j], b->d_out + j * OUT_WORDS);
         DSG_HIP(hipEventRecord(b->ev_join[j], sj));
       }
       c->stream = main;
@@ -275,13 +272,10 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     DSG_REQUIRE(o[2] == 0 && o[6] == 0 && o[7] == 0, DSG_E_DEVICE,
                 "internal: device error flags " + std::to_string(o[2]) + "/" + std::to_string(o[6]) + "/" +
                     std::to_string(o[7]) + " in batched product " + std::to_string(j));
-    DProd* p = b->prods[j];
-    p->last_c_demand = std::max<int64_t>(p->last_c_demand, o[4]);
-    p->last_arena_demand = std::max<int64_t>(p->last_arena_demand, o[5]);
     if (o[3]) {
-      // this product needed more room than reserved: nothing of C was written,
-      // so the plain path (which reserves exactly) completes it
-      counts[j] = prod_run(p, 0, false);
+      // some rows found no room (they wrote nothing): grow C / the arena by
+      // exactly what they asked for and recompute them
+      counts[j] = prod_finish_graph(b->prods[j], b->pw[j]);
       b->deferred++;
     } else {
       counts[j] = (int32_t)o[0];

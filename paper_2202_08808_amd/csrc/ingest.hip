@@ -444,6 +444,7 @@ Work carve_work(void* base, int64_t n, bool deltas) {
 }
 
 __global__ void k_bump_epoch(uint32_t* e) { *e += 1; }
+__global__ void k_zero_u64(unsigned long long* a) { *a = 0; }
 __global__ void k_zero_counters(unsigned long long* a, unsigned long long* b, int* c) {
   *a = 0;
   *b = 0;
@@ -461,12 +462,23 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
   if (!graph) {
     // the one host round trip: how much pool space moved rows need
     unsigned long long* h = (unsigned long long*)c->pinned;
-    DSG_HIP(hipMemcpyAsync(h, w.demand, 8, hipMemcpyDeviceToHost, s));
-    DSG_HIP(hipStreamSynchronize(s));
-    int64_t demand = (int64_t)h[0];
-    if (demand > 0) {
+    for (;;) {
+      DSG_HIP(hipMemcpyAsync(h, w.demand, 8, hipMemcpyDeviceToHost, s));
+      DSG_HIP(hipStreamSynchronize(s));
+      const int64_t demand = (int64_t)h[0];
+      if (demand == 0) break;
+      const uint64_t version = m->version;
       mat_reserve(m, demand);
-      m->h_top_ub += demand;
+      if (m->version == version) {
+        m->h_top_ub += demand;
+        break;
+      }
+      // the pool was compacted, which reset every row's capacity to the slack
+      // of its length: a row planned to grow in place may no longer fit, so
+      // plan again against the new capacities
+      hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, w.demand);
+      hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
+                         w.demand);
     }
   }
   // (graph mode: the caller reserved the worst case, see apply_headroom)

@@ -217,14 +217,17 @@ void prod_destroy(DProd* p);
 int32_t prod_run(DProd* p, int mode, bool report_affected);
 
 // Graph-capturable dynamic update (no host round trips) on a caller-owned
-// workspace of prod_graph_work_bytes(p) bytes.  prod_prepare_graph must have
-// reserved C and arena space first; if the update needs more, the device
-// sets *d_defer and writes nothing, and the caller runs prod_run instead.
-// d_out[0..5] receives: reported rows, affected rows, error flags, deferred,
-// C space asked, arena bytes asked.
+// workspace of prod_graph_work_bytes(p) bytes, after prod_prepare_graph set
+// room aside.  Rows that find no room in C or the staging arena write
+// nothing and are flagged; d_out[0..5] receives: reported rows, affected
+// rows, error flags, rows waiting for room (0/1), C slots and arena bytes
+// they need.  When d_out[3] is set, prod_finish_graph (plain, with host
+// round trips) grows the room, recomputes those rows and returns the final
+// reported-row count.
 size_t prod_graph_work_bytes(const DProd* p);
 void prod_prepare_graph(DProd* p, int64_t c_headroom, size_t arena_bytes);
-void prod_update_graph(DProd* p, void* work, int* d_defer, int64_t* d_out);
+void prod_update_graph(DProd* p, void* work, int64_t* d_out);
+int32_t prod_finish_graph(DProd* p, void* work);
 
 // asynchronous validation of a device batch: ORs 1 (range) / 2 (op) into *d_flag
 void validate_batch_async(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const uint8_t* d_ops, int64_t n,

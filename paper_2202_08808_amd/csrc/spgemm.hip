@@ -74,7 +74,10 @@ struct RowArgs {
   uint8_t* binof;         // per q
   int32_t* flq;           // per q: flops (clamped to int32)
   unsigned int* dense_next;  // row counter of the persistent dense kernel
-  const int* defer;          // non-null and set: skip this product (graph mode)
+  const int* defer;          // non-null and set: skip this product
+  uint8_t* retry;            // per q: row could not be placed, recompute it
+  unsigned long long* c_short;      // C slots the flagged rows need
+  unsigned long long* arena_short;  // arena bytes the flagged rows need
 };
 
 // Per-row work record, summed per bin by k_reduce_stats.
@@ -251,11 +254,17 @@ __device__ inline int64_t take_pool(const RowArgs& R, int32_t ncap, const Grp<G>
   int64_t no = 0;
   if (grp.lane == 0) no = (int64_t)atomicAdd((unsigned long long*)R.c_top, (unsigned long long)ncap);
   no = grp.bcast64(no, 0, slot);
-  if (no + ncap > R.c_pool_cap) {
-    if (grp.lane == 0) atomicOr(R.err, 1);
-    return -1;
-  }
-  return no;
+  return no + ncap > R.c_pool_cap ? -1 : no;
+}
+
+// Row q could not be placed (C pool or staging arena full): nothing of it was
+// written.  Record the exact room it needs; the host grows the space and
+// recomputes the flagged rows.
+__device__ inline void mark_retry(const RowArgs& R, int32_t q, unsigned long long* counter,
+                                  unsigned long long need) {
+  R.retry[q] = 1;
+  R.chg[q] = 0;
+  atomicAdd(counter, need);
 }
 
 // ---------------------------------------------------------------------------
@@ -402,7 +411,10 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
     if (nnew > R.c_cap[i]) {
       ncap = slack_cap(nnew);
       dest = take_pool<G>(R, ncap, grp, &bslot);
-      if (dest < 0) continue;
+      if (dest < 0) {
+        if (lane == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
+        continue;
+      }
     }
     int32_t w = 0;
     for (int sb = 0; sb < SLOTS; sb += G) {
@@ -573,8 +585,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   if (tid == 0) sbase = (int64_t)atomicAdd(R.arena_top, (unsigned long long)stage_bytes);
   sbase = grp.bcast64(sbase, 0, &bslot);
   if (sbase + (int64_t)stage_bytes > R.arena_cap) {
-    if (tid == 0) atomicOr(R.err, 4);
-    break;
+    if (tid == 0) mark_retry(R, q, R.arena_short, (unsigned long long)stage_bytes);
+    continue;
   }
   int32_t* scol = (int32_t*)(R.arena + sbase);
   V* sval = (V*)(R.arena + sbase + (size_t)stage_n * 4);
@@ -772,7 +784,10 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     if (nnew > R.c_cap[i]) {
       ncap = slack_cap(nnew);
       dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
-      if (dest < 0) break;
+      if (dest < 0) {
+        if (tid == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
+        continue;
+      }
     }
     for (int32_t e = tid; e < nnew; e += DENSE_WG) {
       R.c_col[dest + e] = scol[e];
@@ -869,8 +884,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
   if (tid == 0) tb = (int64_t)atomicAdd(R.arena_top, (unsigned long long)tbytes);
   tb = grp.bcast64(tb, 0, &bslot);
   if (tb + (int64_t)tbytes > R.arena_cap) {
-    if (tid == 0) atomicOr(R.err, 4);
-    break;
+    if (tid == 0) mark_retry(R, q, R.arena_short, (unsigned long long)tbytes);
+    continue;
   }
   int32_t* keys = (int32_t*)(R.arena + tb);
   Acc* vals = (Acc*)(R.arena + tb + (size_t)slots * 4);
@@ -959,7 +974,10 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
     if (nnew > R.c_cap[i]) {
       ncap = slack_cap(nnew);
       dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
-      if (dest < 0) continue;
+      if (dest < 0) {
+        if (tid == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
+        continue;
+      }
     }
     int32_t w = 0;
     for (int64_t sb = 0; sb < slots; sb += DENSE_WG) {
@@ -1025,10 +1043,12 @@ struct Plan {
   int32_t count;         // affected rows
   int32_t pad;
   unsigned long long bin_count[NBINS];
-  unsigned long long c_demand;
-  unsigned long long arena_demand;
+  unsigned long long c_demand;      // upper bound of C slots moved rows may take
+  unsigned long long arena_demand;  // upper bound of staging bytes
   unsigned int dense_next;
   unsigned int pad2;
+  unsigned long long c_short;       // exact C slots that rows flagged for retry need
+  unsigned long long arena_short;   // exact arena bytes they need
 };
 
 // longest rows first: key = (2^20 - 1) - min(flops, 2^20 - 1)
@@ -1079,7 +1099,8 @@ __global__ __launch_bounds__(256) void k_analyze(RowArgs R, const int32_t* d_cou
 // bin and per counter and workgroup, not one per row.
 constexpr int SCATTER_NT = 1024;
 __global__ __launch_bounds__(SCATTER_NT) void k_bin_scatter(RowArgs R, const int32_t* d_count, Plan* plan,
-                                                            int32_t* bins, int32_t bin_stride) {
+                                                            int32_t* bins, int32_t bin_stride,
+                                                            const uint8_t* filter) {
   __shared__ int32_t cnt[NBINS];
   __shared__ unsigned long long base[NBINS];
   __shared__ unsigned long long dem[2];
@@ -1089,7 +1110,7 @@ __global__ __launch_bounds__(SCATTER_NT) void k_bin_scatter(RowArgs R, const int
   __syncthreads();
   const int64_t q = (int64_t)blockIdx.x * SCATTER_NT + tid;
   int b = -1, local = 0;
-  if (q < *d_count) {
+  if (q < *d_count && (!filter || filter[q])) {
     const int32_t ub = R.ub[q];
     b = R.binof[q];
     local = atomicAdd(&cnt[b], 1);
@@ -1139,30 +1160,46 @@ __global__ void k_zero_words(unsigned long long* p, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0ull;
 }
 
-__global__ void k_set_sync(uint32_t* sync, const uint32_t* ea, const uint32_t* eb, const int* defer) {
-  if (defer && *defer) return;
+__global__ void k_zero_bytes(uint8_t* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// rows flagged for retry become the filter of the next pass; flags reset
+__global__ void k_take_retry(uint8_t* retry, uint8_t* filter, const int32_t* d_count) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < *d_count) {
+    filter[q] = retry[q];
+    retry[q] = 0;
+  }
+}
+
+// a retry pass starts with empty bins and shortfalls
+__global__ void k_reset_bins(Plan* plan) {
+  const int t = threadIdx.x;
+  if (t < NBINS) plan->bin_count[t] = 0;
+  if (t == 0) {
+    plan->c_short = 0;
+    plan->arena_short = 0;
+    plan->dense_next = 0;
+  }
+}
+
+// C now reflects the operands' current epochs -- unless rows still wait for room
+__global__ void k_set_sync(uint32_t* sync, const uint32_t* ea, const uint32_t* eb, const Plan* plan) {
+  if (plan->c_short || plan->arena_short) return;
   sync[0] = *ea;
   sync[1] = *eb;
 }
 
-// Graph mode: defer this product's update -- before anything is written --
-// when its C pool or its arena cannot hold what the analysis asks for; the
-// host then runs it through the plain path.
-__global__ void k_guard(const Plan* plan, const int64_t* c_top, int64_t c_pool_cap, int64_t arena_cap,
-                        int* defer) {
-  const bool short_c = (int64_t)plan->c_demand > c_pool_cap - *c_top;
-  const bool short_a = (int64_t)plan->arena_demand > arena_cap;
-  *defer = (short_c || short_a) ? 1 : 0;
-}
-
-__global__ void k_publish(const int32_t* nchg, const int32_t* naff, const int* err, const int* defer,
-                          const Plan* plan, int64_t* out) {
+__global__ void k_publish(const int32_t* nchg, const int32_t* naff, const int* err, const Plan* plan,
+                          int64_t* out) {
   out[0] = *nchg;
   out[1] = *naff;
   out[2] = *err;
-  out[3] = defer ? *defer : 0;
-  out[4] = (int64_t)plan->c_demand;
-  out[5] = (int64_t)plan->arena_demand;
+  out[3] = (plan->c_short || plan->arena_short) ? 1 : 0;
+  out[4] = (int64_t)plan->c_short;
+  out[5] = (int64_t)plan->arena_short;
 }
 
 }  // namespace
@@ -1248,6 +1285,8 @@ struct ProdWork {
   RowStat* rstat;
   uint8_t* binof;
   int32_t* flq;
+  uint8_t* retry;
+  uint8_t* filter;
   int* err;
   int32_t* d_nchg;
   void* cscr;
@@ -1256,7 +1295,8 @@ struct ProdWork {
 size_t work_bytes_for(int64_t N, int64_t nB) {
   return Carve::need({(size_t)N, (size_t)nB, (size_t)N * 4, 64, (size_t)nB * 4, 64, (size_t)N * 4, (size_t)N,
                       (size_t)N * 4 * NBINS, sizeof(Plan) + 64, NBINS * NSTAT * 8 + 64, (size_t)N * sizeof(RowStat),
-                      (size_t)N, (size_t)N * 4, 64, 64, compact_scratch_bytes(std::max(N, nB)) + 64});
+                      (size_t)N, (size_t)N * 4, (size_t)N, (size_t)N, 64, 64,
+                      compact_scratch_bytes(std::max(N, nB)) + 64});
 }
 
 ProdWork carve_prod(void* base, int64_t N, int64_t nB) {
@@ -1276,6 +1316,8 @@ ProdWork carve_prod(void* base, int64_t N, int64_t nB) {
   w.rstat = cv.take<RowStat>(N);
   w.binof = cv.take<uint8_t>(N);
   w.flq = cv.take<int32_t>(N);
+  w.retry = cv.take<uint8_t>(N);
+  w.filter = cv.take<uint8_t>(N);
   w.err = cv.take<int>(16);
   w.d_nchg = cv.take<int32_t>(16);
   w.cscr = cv.take<char>(compact_scratch_bytes(std::max(N, nB)) + 64);
@@ -1305,24 +1347,42 @@ void ensure_arena(DProd* p, size_t bytes) {
   p->arena_bytes = nb;
 }
 
-// One product update (mode 0) or full recompute (mode 1).  Plain mode reads
-// the bin sizes and space needs back after the analysis and the results at
-// the end.  Graph mode (d_defer != nullptr) makes no host round trip: the
-// caller has reserved C and arena space, the device guard defers the product
-// if that is not enough, and k_publish leaves the results in d_out.
-int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, int* d_defer, int64_t* d_out) {
-  Ctx* c = p->ctx;
-  hipStream_t s = c->stream;
-  const bool graph = d_defer != nullptr;
+RowArgs row_args(DProd* p, ProdWork& w, int mode, bool report_affected) {
   DMat* A = p->A;
   DMat* B = p->B;
   DMat* C = p->C;
-  const int32_t n = A->nrows;
+  RowArgs R;
+  R.a_off = A->row_off; R.a_len = A->row_len; R.a_col = A->col; R.a_val = A->val;
+  R.b_off = B->row_off; R.b_len = B->row_len; R.b_col = B->col; R.b_val = B->val;
+  R.c_off = C->row_off; R.c_len = C->row_len; R.c_cap = C->row_cap; R.c_col = C->col; R.c_val = C->val;
+  R.c_top = C->d_top; R.c_pool_cap = C->pool_cap;
+  R.ncols = B->ncols;
+  R.aff = w.aff; R.ub = w.ub; R.chg = w.chg; R.stats = w.stats;
+  R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
+  R.force_write = (mode == 1 || report_affected) ? 1 : 0;
+  R.err = w.err;
+  R.rstat = w.rstat;
+  R.binof = w.binof;
+  R.flq = w.flq;
+  R.dense_next = &w.plan->dense_next;
+  R.defer = nullptr;
+  R.retry = w.retry;
+  R.c_short = &w.plan->c_short;
+  R.arena_short = &w.plan->arena_short;
+  return R;
+}
 
+// Discovery, analysis and binning (no host round trip).
+void launch_front(DProd* p, int mode, ProdWork& w, const RowArgs& R) {
+  Ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  DMat* A = p->A;
+  DMat* B = p->B;
+  const int32_t n = A->nrows;
   hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, (unsigned long long*)w.plan, (int)(sizeof(Plan) / 8));
   hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, w.stats, NBINS * NSTAT);
   hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, (unsigned long long*)w.err, 1);
-  // ---- affected rows ----
+  if (n > 0) hipLaunchKernelGGL(k_zero_bytes, dim3(blocks_for(n, 256)), dim3(256), 0, s, w.retry, (int64_t)n);
   if (mode == 1) {
     iota_i32(w.aff, n, s);
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, w.d_count, n);
@@ -1342,96 +1402,117 @@ int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, int
   } else {
     hipLaunchKernelGGL(k_set_count, dim3(1), dim3(1), 0, s, w.d_count, 0);
   }
-
-  RowArgs R;
-  R.a_off = A->row_off; R.a_len = A->row_len; R.a_col = A->col; R.a_val = A->val;
-  R.b_off = B->row_off; R.b_len = B->row_len; R.b_col = B->col; R.b_val = B->val;
-  R.c_off = C->row_off; R.c_len = C->row_len; R.c_cap = C->row_cap; R.c_col = C->col; R.c_val = C->val;
-  R.c_top = C->d_top; R.c_pool_cap = C->pool_cap;
-  R.ncols = B->ncols;
-  R.aff = w.aff; R.ub = w.ub; R.chg = w.chg; R.stats = w.stats;
-  R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
-  R.force_write = (mode == 1 || report_affected) ? 1 : 0;
-  R.err = w.err;
-  R.rstat = w.rstat;
-  R.binof = w.binof;
-  R.flq = w.flq;
-  R.dense_next = &w.plan->dense_next;
-  R.defer = d_defer;
-
   Tun T;
   const dsg_tuning& tu = c->tuning;
   for (int b = 0; b < 8; ++b) T.group_ub[b] = tu.group_ub[b];
-  T.dense_passes = dense_passes_for(C->vsz, B->ncols);
+  T.dense_passes = dense_passes_for(p->C->vsz, B->ncols);
   T.dense_max_passes = tu.dense_max_passes;
   T.force_bin = tu.force_bin;
   T.fp64 = A->sr == 2 ? 1 : 0;
   if (n > 0) {
     hipLaunchKernelGGL(k_analyze, dim3(blocks_for((int64_t)n * 16, 256)), dim3(256), 0, s, R, w.d_count, T);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n, SCATTER_NT)), dim3(SCATTER_NT), 0, s, R, w.d_count,
-                       w.plan, w.bins, n);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n, SCATTER_NT)), dim3(SCATTER_NT), 0, s, R, w.d_count, w.plan,
+                       w.bins, n, (const uint8_t*)nullptr);
   }
-  Plan plan{};
-  if (graph) {
-    hipLaunchKernelGGL(k_guard, dim3(1), dim3(1), 0, s, (const Plan*)w.plan, (const int64_t*)C->d_top,
-                       C->pool_cap, (int64_t)p->arena_bytes, d_defer);
-    if (p->arena_top)
-      hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, s, p->arena_top, 1);
-  } else {
-    // ---- host round trip 1: bin sizes and space needs ----
-    Plan* hp = (Plan*)c->pinned;
-    DSG_HIP(hipMemcpyAsync(hp, w.plan, sizeof(Plan), hipMemcpyDeviceToHost, s));
-    DSG_HIP(hipMemcpyAsync(&hp->count, w.d_count, 4, hipMemcpyDeviceToHost, s));
-    DSG_HIP(hipStreamSynchronize(s));
-    plan = *hp;
-    if (plan.c_demand > 0) {
-      mat_reserve(C, (int64_t)plan.c_demand);
-      C->h_top_ub += (int64_t)plan.c_demand;
-    }
-    if (plan.arena_demand > 0) {
-      ensure_arena(p, plan.arena_demand);
-      DSG_HIP(hipMemsetAsync(p->arena_top, 0, 8, s));
-    }
-    ensure_changed_cap(p, plan.count);
-    R.c_col = C->col; R.c_val = C->val; R.c_off = C->row_off; R.c_top = C->d_top; R.c_pool_cap = C->pool_cap;
-    R.arena = (char*)p->arena; R.arena_top = p->arena_top; R.arena_cap = (int64_t)p->arena_bytes;
-    // the dense bin runs persistent workgroups: hand them the longest rows first
-    const int64_t ndense = (int64_t)plan.bin_count[BIN_DENSE];
-    if (ndense > 1) {
-      int32_t* dl = w.bins + (int64_t)BIN_DENSE * n;
-      const size_t nb = Carve::need({(size_t)ndense * 8, (size_t)ndense * 4, radix_scratch_bytes(ndense)});
-      Carve dc(ctx_scratch2(c, nb), nb);
-      uint64_t* keys = dc.take<uint64_t>(ndense);
-      uint32_t* vals = dc.take<uint32_t>(ndense);
-      void* rs = dc.take<char>(radix_scratch_bytes(ndense));
-      hipLaunchKernelGGL(k_flop_keys, dim3(blocks_for(ndense, 256)), dim3(256), 0, s, dl, (int32_t)ndense, w.flq,
-                         keys, vals);
-      radix_sort_pairs(keys, vals, ndense, FLOP_KEY_BITS, rs, s);
-      DSG_HIP(hipMemcpyAsync(dl, vals, (size_t)ndense * 4, hipMemcpyDeviceToDevice, s));
-    }
-  }
-  std::vector<std::pair<int, size_t>> timed;
-  const Plan* hplan = graph ? nullptr : &plan;
-  switch (A->sr) {
+}
+
+void launch_rows(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
+                 std::vector<std::pair<int, size_t>>& timed) {
+  Ctx* c = p->ctx;
+  const int32_t n = p->A->nrows;
+  if (p->arena_top) hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, c->stream, p->arena_top, 1);
+  switch (p->A->sr) {
     case 0: launch_bins<0>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
     case 1: launch_bins<1>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
     default: launch_bins<2>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
   }
-  // ---- reported rows and statistics ----
-  const int64_t nmax = graph ? std::max<int32_t>(n, 1) : std::max<int32_t>(plan.count, 1);
+}
+
+// reported rows, statistics, sync epochs (no host round trip)
+void launch_tail(DProd* p, ProdWork& w, int64_t nmax) {
+  hipStream_t s = p->ctx->stream;
   compact_list_by_flags(w.aff, w.chg, w.d_count, nmax, p->changed_rows, w.d_nchg, w.cscr, s);
-  if (nmax > 0)
-    hipLaunchKernelGGL(k_reduce_stats, dim3(blocks_for(nmax, 256)), dim3(256), 0, s, w.rstat, w.binof, w.d_count,
-                       w.stats);
-  hipLaunchKernelGGL(k_set_sync, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)A->d_epoch,
-                     (const uint32_t*)B->d_epoch, (const int*)d_defer);
-  if (graph) {
-    hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, (const int32_t*)w.d_nchg, (const int32_t*)w.d_count,
-                       (const int*)w.err, (const int*)d_defer, (const Plan*)w.plan, d_out);
-    DSG_HIP(hipGetLastError());
-    return 0;
+  hipLaunchKernelGGL(k_reduce_stats, dim3(blocks_for(nmax, 256)), dim3(256), 0, s, w.rstat, w.binof, w.d_count,
+                     w.stats);
+  hipLaunchKernelGGL(k_set_sync, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)p->A->d_epoch,
+                     (const uint32_t*)p->B->d_epoch, (const Plan*)w.plan);
+}
+
+// Read the plan back; also refresh the host's view of C's pool top, which the
+// row kernels advance on the device.
+Plan read_plan(Ctx* c, ProdWork& w, DMat* C) {
+  Plan* hp = (Plan*)c->pinned;
+  int64_t* htop = (int64_t*)((char*)c->pinned + 2048);
+  DSG_HIP(hipMemcpyAsync(hp, w.plan, sizeof(Plan), hipMemcpyDeviceToHost, c->stream));
+  DSG_HIP(hipMemcpyAsync(&hp->count, w.d_count, 4, hipMemcpyDeviceToHost, c->stream));
+  DSG_HIP(hipMemcpyAsync(htop, C->d_top, 8, hipMemcpyDeviceToHost, c->stream));
+  DSG_HIP(hipStreamSynchronize(c->stream));
+  C->h_top_ub = *htop;
+  return *hp;
+}
+
+// Recompute the rows flagged for retry after growing C and the arena by
+// exactly what they asked for.  Returns the plan of the last pass.
+Plan retry_rows(DProd* p, ProdWork& w, int mode, bool report_affected, Plan plan,
+                std::vector<std::pair<int, size_t>>& timed) {
+  Ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  const int32_t n = p->A->nrows;
+  for (int pass = 0; (plan.c_short || plan.arena_short) && pass < 8; ++pass) {
+    if (plan.c_short) {
+      mat_reserve(p->C, (int64_t)(plan.c_short + plan.c_short / 4));
+      p->C->h_top_ub += (int64_t)plan.c_short;
+    }
+    if (plan.arena_short) ensure_arena(p, plan.arena_short);
+    RowArgs R = row_args(p, w, mode, report_affected);
+    hipLaunchKernelGGL(k_take_retry, dim3(blocks_for(std::max<int32_t>(n, 1), 256)), dim3(256), 0, s, w.retry,
+                       w.filter, (const int32_t*)w.d_count);
+    hipLaunchKernelGGL(k_reset_bins, dim3(1), dim3(64), 0, s, w.plan);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(std::max<int32_t>(n, 1), SCATTER_NT)), dim3(SCATTER_NT), 0, s,
+                       R, w.d_count, w.plan, w.bins, n, (const uint8_t*)w.filter);
+    Plan bins = read_plan(c, w, p->C);
+    launch_rows(p, R, w, &bins, timed);
+    plan = read_plan(c, w, p->C);
   }
-  // ---- host round trip 2: row count, statistics, errors ----
+  DSG_REQUIRE(!plan.c_short && !plan.arena_short, DSG_E_OOM, "rows still without room after growing C");
+  return plan;
+}
+
+// Plain mode: one product update (mode 0) or full recompute (mode 1), with
+// host round trips after the analysis (bin sizes) and at the end (results).
+int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w) {
+  Ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  DMat* C = p->C;
+  const int32_t n = p->A->nrows;
+  RowArgs R = row_args(p, w, mode, report_affected);
+  launch_front(p, mode, w, R);
+  Plan plan = read_plan(c, w, p->C);
+  // room: C grows only by what rows that do not fit ask for (retry below);
+  // the arena keeps the largest size used so far, up to the analysis bound
+  if (plan.arena_demand > p->arena_bytes) ensure_arena(p, std::min<size_t>(plan.arena_demand, std::max<size_t>(p->arena_bytes * 2, (size_t)64 << 20)));
+  ensure_changed_cap(p, plan.count);
+  R = row_args(p, w, mode, report_affected);
+  // the dense bin runs persistent workgroups: hand them the longest rows first
+  const int64_t ndense = (int64_t)plan.bin_count[BIN_DENSE];
+  if (ndense > 1) {
+    int32_t* dl = w.bins + (int64_t)BIN_DENSE * n;
+    const size_t nb = Carve::need({(size_t)ndense * 8, (size_t)ndense * 4, radix_scratch_bytes(ndense)});
+    Carve dc(ctx_scratch2(c, nb), nb);
+    uint64_t* keys = dc.take<uint64_t>(ndense);
+    uint32_t* vals = dc.take<uint32_t>(ndense);
+    void* rs = dc.take<char>(radix_scratch_bytes(ndense));
+    hipLaunchKernelGGL(k_flop_keys, dim3(blocks_for(ndense, 256)), dim3(256), 0, s, dl, (int32_t)ndense, w.flq, keys,
+                       vals);
+    radix_sort_pairs(keys, vals, ndense, FLOP_KEY_BITS, rs, s);
+    DSG_HIP(hipMemcpyAsync(dl, vals, (size_t)ndense * 4, hipMemcpyDeviceToDevice, s));
+  }
+  std::vector<std::pair<int, size_t>> timed;
+  launch_rows(p, R, w, &plan, timed);
+  Plan after = read_plan(c, w, p->C);
+  if (after.c_short || after.arena_short) after = retry_rows(p, w, mode, report_affected, after, timed);
+  launch_tail(p, w, std::max<int32_t>(plan.count, 1));
+  // ---- results, statistics, errors ----
   struct Tail {
     int32_t nchg;
     int32_t err;
@@ -1516,22 +1597,44 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   ensure_changed_cap(p, 0);
   const size_t need = work_bytes_for(N, nB);
   ProdWork w = carve_prod(ctx_scratch(p->ctx, need), N, nB);
-  return prod_sequence(p, mode, report_affected, w, nullptr, nullptr);
+  return prod_sequence(p, mode, report_affected, w);
 }
 
 size_t prod_graph_work_bytes(const DProd* p) {
   return work_bytes_for(std::max<int32_t>(p->A->nrows, 1), std::max<int32_t>(p->B->nrows, 1));
 }
 
-void prod_update_graph(DProd* p, void* work, int* d_defer, int64_t* d_out) {
-  const int64_t N = std::max<int32_t>(p->A->nrows, 1);
-  const int64_t nB = std::max<int32_t>(p->B->nrows, 1);
-  ProdWork w = carve_prod(work, N, nB);
-  prod_sequence(p, 0, false, w, d_defer, d_out);
-}
-
 void prod_prepare_graph(DProd* p, int64_t c_headroom, size_t arena_bytes) {
   ensure_changed_cap(p, std::max<int32_t>(p->A->nrows, 1));
   ensure_arena(p, arena_bytes);
   mat_reserve(p->C, c_headroom);
+}
+
+void prod_update_graph(DProd* p, void* work, int64_t* d_out) {
+  const int64_t N = std::max<int32_t>(p->A->nrows, 1);
+  const int64_t nB = std::max<int32_t>(p->B->nrows, 1);
+  ProdWork w = carve_prod(work, N, nB);
+  RowArgs R = row_args(p, w, 0, false);
+  launch_front(p, 0, w, R);
+  std::vector<std::pair<int, size_t>> none;
+  launch_rows(p, R, w, nullptr, none);
+  launch_tail(p, w, N);
+  hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, p->ctx->stream, (const int32_t*)w.d_nchg,
+                     (const int32_t*)w.d_count, (const int*)w.err, (const Plan*)w.plan, d_out);
+  DSG_HIP(hipGetLastError());
+}
+
+int32_t prod_finish_graph(DProd* p, void* work) {
+  Ctx* c = p->ctx;
+  const int64_t N = std::max<int32_t>(p->A->nrows, 1);
+  const int64_t nB = std::max<int32_t>(p->B->nrows, 1);
+  ProdWork w = carve_prod(work, N, nB);
+  Plan plan = read_plan(c, w, p->C);
+  std::vector<std::pair<int, size_t>> none;
+  retry_rows(p, w, 0, false, plan, none);
+  launch_tail(p, w, N);
+  int32_t* h = (int32_t*)c->pinned;
+  DSG_HIP(hipMemcpyAsync(h, w.d_nchg, 4, hipMemcpyDeviceToHost, c->stream));
+  DSG_HIP(hipStreamSynchronize(c->stream));
+  return h[0];
 }

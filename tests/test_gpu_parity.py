@@ -130,6 +130,44 @@ def test_apply_matches_oracle(ctx, sr):
 
 
 @pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+@pytest.mark.parametrize("with_product", [False, True], ids=["matrix", "product"])
+def test_apply_growth_across_compaction(ctx, sr, with_product):
+    """A row that shrank keeps its old capacity; a later batch grows it again
+    (in place by that capacity) while another row's move forces a pool
+    compaction, which trims every capacity to the slack of its length.  The
+    grown row must not spill into its neighbours."""
+    say(f"apply growth across compaction {SR_ID[sr]} {with_product}")
+    rng = np.random.default_rng(31 + sr)
+    n = nc = 2048
+    keys = np.concatenate([np.arange(40), (np.arange(1, 64)[:, None] * nc + np.array([[7, 9]])).ravel()])
+    keys = np.sort(keys.astype(np.int64))
+    A = I.csr_from_keys(n, nc, keys, I.draw_values(sr, keys.size, rng, 1, 9))
+    Am = dsg.Matrix.from_csr(ctx, A, sr)
+    P = dsg.Product(ctx, Am, Am) if with_product else None
+    cur = oracle.Csr.of(A)
+    # 1: row 0 shrinks from 40 to 4 entries
+    dels = np.arange(4, 40, dtype=np.int32)
+    b1 = I.Batch(np.zeros(dels.size, np.int32), dels, I.draw_values(sr, dels.size, rng, 1, 9),
+                 np.full(dels.size, I.OP_DELETE, np.uint8))
+    # 2: row 0 grows to 34 entries; rows 1 and 2 to 2002 each (moves larger
+    # than the free part of the pool)
+    r = np.concatenate([np.zeros(30, np.int32), np.full(2000, 1, np.int32), np.full(2000, 2, np.int32)])
+    c = np.concatenate([np.arange(100, 130), np.arange(20, 2020), np.arange(20, 2020)]).astype(np.int32)
+    b2 = I.Batch(r, c, I.draw_values(sr, r.size, rng, 1, 9), np.full(r.size, I.OP_SET, np.uint8))
+    for t, b in enumerate((b1, b2)):
+        Am.apply_batch(b)
+        cur, _ = oracle.apply(sr, cur, b.rows, b.cols, b.vals, b.ops)
+        assert_same_csr(sr, Am.export(), cur, f"after batch {t}")
+        if P is not None:
+            P.update()
+            want = oracle.spgemm(sr, cur, cur, nthreads=THREADS)
+            assert_same_csr(sr, P.export(), want, f"product after batch {t}", A=cur, B=cur)
+    if P is not None:
+        P.destroy()
+    destroy(Am)
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
 @pytest.mark.parametrize("square", [True, False], ids=["AxA", "AxB"])
 def test_dynamic_sequence(ctx, sr, square):
     """D1 (dynamic result = static recompute of the updated operands) and D5
