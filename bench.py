@@ -172,15 +172,149 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serve(args):
+    """Served form on the Erdos-Renyi n=2^21, mean degree 8, min-plus product
+    (C = A*A resident in HBM).  One Poisson trace per offered load (a
+    multiple of the measured synchronous capacity): update batches of
+    floor(10**X) entries, X ~ N(3, 0.67) on [1, 5], mix 50/25/25, and queries
+    of 1..1024 random rows, half and half.  The same trace is run by the
+    plain synchronous path (one request at a time: apply + update, or row
+    query) and by the server (continuous batching); both from host arrays,
+    latency = completion - scheduled arrival."""
+    import torch
+    from paper_2202_08808_amd import dsg
+    from paper_2202_08808_amd import inputs as I
+
+    n = 1 << args.serve_scale
+    t0 = time.perf_counter()
+    keys = I.er_keys(n, 8 * n, I.rng_for(501, 0))
+    A = I.csr_from_keys(n, n, keys, I.draw_values(I.MIN_PLUS_F32, keys.size, I.rng_for(501, 1), 1, 100))
+    sr = I.MIN_PLUS_F32
+    log(f"[serve] ER n={n} nnz={A.nnz} ({time.perf_counter() - t0:.1f}s)")
+    ctx = dsg.Context(0, stream=torch.cuda.current_stream())
+
+    def fresh():
+        m = dsg.Matrix.from_csr(ctx, A, sr)
+        return m, dsg.Product(ctx, m, m)
+
+    def wait_until(t):
+        while True:
+            d = t - time.perf_counter()
+            if d <= 0:
+                return
+            time.sleep(min(d, 2e-4) if d > 2e-4 else 0)
+
+    def run_sync(trace):
+        m, P = fresh()
+        torch.cuda.synchronize()
+        lat_u, lat_q, entries = [], [], 0
+        start = time.perf_counter() + 0.05
+        last = start
+        for r in trace:
+            target = start + r.t
+            wait_until(target)
+            if r.kind == "update":
+                m.apply_batch(r.batch)
+                P.update()
+                entries += len(r.batch.ops)
+            else:
+                P.rows(r.rows).to_host()
+            last = time.perf_counter()
+            (lat_u if r.kind == "update" else lat_q).append((last - target) * 1e3)
+        busy = last - (start + trace[0].t)
+        P.destroy()
+        m.destroy()
+        return {"update_p50_ms": float(np.percentile(lat_u, 50)), "update_p99_ms": float(np.percentile(lat_u, 99)),
+                "query_p50_ms": float(np.percentile(lat_q, 50)), "query_p99_ms": float(np.percentile(lat_q, 99)),
+                "updates_per_s": entries / busy, "busy_s": busy}
+
+    def run_served(trace):
+        m, P = fresh()
+        torch.cuda.synchronize()
+        S = dsg.Server(ctx, P, mem_budget=args.serve_budget << 20)
+        tickets, late = [], []
+        start = time.perf_counter() + 0.05
+        for r in trace:
+            target = start + r.t
+            wait_until(target)
+            late.append((time.perf_counter() - target) * 1e3)
+            tickets.append(S.submit_batch(m, r.batch) if r.kind == "update" else S.submit_query(r.rows))
+        S.drain()
+        res = [S.poll(t) for t in tickets]
+        st = S.stats()
+        S.destroy()
+        P.destroy()
+        m.destroy()
+        assert all(x["status"] == dsg.OK for x in res)
+        lat_u = [x["latency_ms"] + lt for x, lt in zip(res, late) if x["kind"] == 0]
+        lat_q = [x["latency_ms"] + lt for x, lt in zip(res, late) if x["kind"] == 1]
+        return {"update_p50_ms": float(np.percentile(lat_u, 50)), "update_p99_ms": float(np.percentile(lat_u, 99)),
+                "query_p50_ms": float(np.percentile(lat_q, 50)), "query_p99_ms": float(np.percentile(lat_q, 99)),
+                "updates_per_s": st["updates_per_s"], "busy_s": st["busy_ms"] * 1e-3,
+                "update_groups": st["update_groups"], "update_requests": st["update_requests"],
+                "query_groups": st["query_groups"], "query_requests": st["query_requests"],
+                "peak_inflight_MiB": round(st["peak_inflight_bytes"] / 2**20, 1),
+                "max_submit_lateness_ms": float(np.max(late))}
+
+    # synchronous capacity: a calibration trace served back to back
+    cal = I.serve_trace(A, sr, args.serve_calib, 1e9, stream=611)
+    c = run_sync(cal)
+    capacity = args.serve_calib / c["busy_s"]
+    log(f"[serve] synchronous capacity ~{capacity:.0f} requests/s ({c['updates_per_s']:.0f} updates/s back to back)")
+    loads = []
+    for load in args.serve_loads:
+        rate = load * capacity
+        t0 = time.perf_counter()
+        trace = I.serve_trace(A, sr, args.serve_requests, rate, stream=621)
+        log(f"[serve] load {load}: {len(trace)} requests at {rate:.0f}/s over {trace[-1].t:.1f}s "
+            f"(trace in {time.perf_counter() - t0:.1f}s)")
+        sy = run_sync(trace)
+        log(f"[serve]   synchronous: {json.dumps({k: round(v, 3) for k, v in sy.items()})}")
+        sv = run_served(trace)
+        log(f"[serve]   served:      {json.dumps({k: round(v, 3) for k, v in sv.items()})}")
+        loads.append({"load": load, "rate_per_s": round(rate, 1), "synchronous": sy, "served": sv})
+    top = loads[-1]
+    out = {
+        "metric": "served dynamic SpGEMM updates/s",
+        "value": round(top["served"]["updates_per_s"], 2),
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": args.serve_requests,
+        "warmup": args.serve_calib,
+        "ms_per_step": round(top["served"]["busy_s"] * 1e3 / args.serve_requests, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"er{n}_d8_min_plus_f32_serving", "n": n, "nnz_A": A.nnz,
+                   "requests": args.serve_requests, "query_fraction": 0.5,
+                   "batch_size": "floor(10**X), X~N(3,0.67) on [1,5]", "query_rows": "U{1..1024}",
+                   "mem_budget_MiB": args.serve_budget},
+        "synchronous_capacity_req_per_s": round(capacity, 1),
+        "speedup_vs_synchronous": round(top["served"]["updates_per_s"] / top["synchronous"]["updates_per_s"], 4),
+        "p99_batch_latency_ms": round(top["served"]["update_p99_ms"], 4),
+        "loads": loads,
+    }
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat12", "stencil", "er", "batched"])
+    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat12", "stencil", "er", "batched", "serve"])
     ap.add_argument("--instances", type=int, default=64, help="batched workload: number of instances")
     ap.add_argument("--max-scale", type=int, default=16, help="batched workload: largest R-MAT scale")
     ap.add_argument("--batch", type=int, default=10000)
+    ap.add_argument("--serve-scale", type=int, default=21, help="serve workload: log2 of the ER rows")
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-calib", type=int, default=300)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.9, 1.5],
+                    help="offered loads as multiples of the synchronous capacity")
+    ap.add_argument("--serve-budget", type=int, default=4096, help="serve workload: memory budget in MiB")
     ap.add_argument("--static-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -193,6 +327,8 @@ def main():
         raise SystemExit(2)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "serve":
+        return bench_serve(args)
 
     import torch
     from paper_2202_08808_amd import dsg

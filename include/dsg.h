@@ -258,9 +258,10 @@ dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int32_t nprod,
  * (validation of every set) and one after it (results).  The graph is
  * captured on the first run and replayed while the set arrays, their sizes
  * and the storage of every object stay the same (a run with other arrays or
- * after storage grew captures again).  A product whose update needs more C
- * or staging space than was set aside is completed by the plain path after
- * the replay, with the same result.  changed_counts (host, nprod entries)
+ * after storage grew captures again).  Rows of C that find no room in C's
+ * pool or in the staging space set aside write nothing during the replay;
+ * after it, the room grows by exactly what they asked for and only those rows
+ * are recomputed, with the same result.  changed_counts (host, nprod entries)
  * receives each product's reported row count; dsg_batch_rows gives the rows.
  * Errors: DSG_E_RANGE / DSG_E_ARG for a bad set (nothing is applied). */
 dsg_status dsg_batch_run(dsg_batch* b, const dsg_update_set* sets, int32_t nsets, uint32_t flags,
@@ -268,9 +269,90 @@ dsg_status dsg_batch_run(dsg_batch* b, const dsg_update_set* sets, int32_t nsets
 /* Views of the rows product i reported in the last run (valid until the next
  * run or mutating call on that product). */
 dsg_status dsg_batch_rows(dsg_batch* b, int32_t i, dsg_rows* out);
-/* Graph captures, replays, and products completed by the plain path so far. */
-dsg_status dsg_batch_info(const dsg_batch* b, int64_t* captures, int64_t* replays, int64_t* deferred);
+/* Counters and host-clock time totals of the runs so far. */
+typedef struct {
+  int64_t captures;   /* graph captures (first run, or after arrays or storage changed) */
+  int64_t replays;
+  int64_t deferred;   /* products with rows completed after the replay */
+  double prepare_ms;  /* validation round trip and room reservation */
+  double capture_ms;  /* capture and instantiation */
+  double replay_ms;   /* launch until the results were read back */
+  double finish_ms;   /* completion of rows that waited for room */
+} dsg_batch_stats;
+dsg_status dsg_batch_info(const dsg_batch* b, dsg_batch_stats* out);
 dsg_status dsg_batch_destroy(dsg_batch* b);
+
+/* ---- served form: a request loop over resident A, B and C ----
+ *
+ * A server owns a product (and its context) from dsg_server_create to
+ * dsg_server_destroy and answers requests in arrival order, so every result
+ * is the one the requests would get one at a time, in that order: an update
+ * request is dsg_mat_apply of its entries followed by dsg_prod_update; a
+ * query sees every update submitted before it and none submitted after it.
+ * Inside, requests that arrive while others are on the device are admitted
+ * as staging slots and memory free up (continuous batching): consecutive
+ * update requests are merged into one batch in arrival order (the batch
+ * semantics of dsg_mat_apply -- entries take effect in order -- make the
+ * merged batch equal to the sequence), consecutive queries are answered by
+ * one gather, and the host-to-device copy of the next group overlaps the
+ * device work of the current one.  Memory admission: a group is admitted when
+ * its estimated staging and workspace bytes fit the budget next to the groups
+ * in flight (a group larger than the whole budget is admitted alone).
+ * While a server lives, other calls on its context, matrices and products
+ * return DSG_E_STATE; the server calls are thread safe. */
+typedef struct dsg_server dsg_server;
+typedef struct {
+  size_t mem_budget;       /* bytes for in-flight groups; 0: 4 GiB */
+  int64_t max_coalesce;    /* most update entries merged into one batch; 0: 1 << 20 */
+  int32_t max_query_rows;  /* most rows gathered for one query group; 0: 65536 */
+  int32_t slots;           /* groups staged or running at once, 1..8; 0: 2 */
+} dsg_server_cfg;
+
+#define DSG_PENDING (-1)
+typedef struct {
+  int32_t status;          /* DSG_PENDING, DSG_OK, or the error that ended the request */
+  int32_t kind;            /* 0: update, 1: query */
+  double latency_ms;       /* submission to completion (host clock) */
+  int64_t group;           /* sequence number of the group that carried it */
+  int32_t group_requests;  /* requests merged into that group */
+  int32_t changed_rows;    /* update: rows of C the group changed */
+  int32_t nq;              /* query: rows asked for */
+  int64_t nnz;             /* query: entries of the answer */
+} dsg_server_result;
+
+typedef struct {
+  int64_t update_requests, query_requests, update_entries;
+  int64_t update_groups, query_groups;
+  double update_p50_ms, update_p99_ms, update_mean_ms;
+  double query_p50_ms, query_p99_ms, query_mean_ms;
+  double busy_ms;           /* first submission to last completion */
+  double updates_per_s;     /* update entries / busy_ms */
+  size_t peak_inflight_bytes;
+} dsg_server_stats;
+
+/* cfg may be NULL (defaults).  The product must not be in a batched executor. */
+dsg_status dsg_server_create(dsg_ctx* ctx, dsg_prod* p, const dsg_server_cfg* cfg, dsg_server** out);
+/* Host arrays, as for dsg_mat_apply; copied before the call returns.  mat is
+ * the product's A or B.  Bad indices or op codes: DSG_E_RANGE / DSG_E_ARG and
+ * nothing is queued. */
+dsg_status dsg_server_submit_update(dsg_server* s, dsg_mat* mat, const int32_t* rows, const int32_t* cols,
+                                    const void* vals, const uint8_t* ops, int64_t n, uint64_t* ticket);
+/* Host row ids (copied; repeats allowed).  DSG_E_RANGE for a bad row id. */
+dsg_status dsg_server_submit_query(dsg_server* s, const int32_t* rows, int32_t nq, uint64_t* ticket);
+/* State of a request; wait != 0 blocks until it completes. */
+dsg_status dsg_server_poll(dsg_server* s, uint64_t ticket, int32_t wait, dsg_server_result* out);
+/* Answer of a completed query: row_ptr[nq + 1] and, when col is not NULL, the
+ * entries of each asked row sorted by column (cap entries of room; DSG_E_ARG
+ * if fewer than the answer holds).  *nnz_out receives the entry count. */
+dsg_status dsg_server_query_result(dsg_server* s, uint64_t ticket, int64_t* row_ptr, int32_t* col, void* val,
+                                   int64_t cap, int64_t* nnz_out);
+/* Forget a completed request (its answer is freed). */
+dsg_status dsg_server_release(dsg_server* s, uint64_t ticket);
+/* Block until every submitted request has completed. */
+dsg_status dsg_server_drain(dsg_server* s);
+dsg_status dsg_server_stats_get(dsg_server* s, dsg_server_stats* out);
+/* Drains, stops the server and returns the context to the caller. */
+dsg_status dsg_server_destroy(dsg_server* s);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,7 @@ struct dsg_prod {
 
 void* ctx_alloc(Ctx* c, size_t bytes) {
   if (bytes == 0) bytes = 1;
+  std::lock_guard<std::mutex> lk(c->alloc_mu);
   if (c->budget && c->held + bytes > c->budget)
     throw DsgError{DSG_E_OOM, "memory budget exceeded (" + std::to_string(c->held + bytes) + " > " +
                                   std::to_string(c->budget) + " bytes)"};
@@ -45,6 +46,7 @@ void* ctx_alloc(Ctx* c, size_t bytes) {
 void ctx_free(Ctx* c, void* p, size_t bytes) {
   if (!p) return;
   if (bytes == 0) bytes = 1;
+  std::lock_guard<std::mutex> lk(c->alloc_mu);
   (void)hipFree(p);
   c->held -= std::min(c->held, bytes);
 }
@@ -100,8 +102,9 @@ static dsg_status fail(dsg_ctx* ctx, dsg_status code, const std::string& msg) {
   return code;
 }
 
-#define API_BEGIN(ctxp) \
-  dsg_ctx* ctx__ = (ctxp); \
+#define API_BEGIN(ctxp)                                                            \
+  dsg_ctx* ctx__ = (ctxp);                                                         \
+  if (ctx__ && ctx__->c.served) return fail(ctx__, DSG_E_STATE, "context is served"); \
   try {
 #define API_END                                                   \
   }                                                               \
@@ -580,28 +583,6 @@ extern "C" dsg_status dsg_prod_rows(dsg_prod* ph, const int32_t* rows, int32_t n
   API_END
 }
 
-__global__ static void k_view_lens(const int32_t* rows, int32_t n, const int32_t* row_len, int64_t* lens) {
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) lens[q] = row_len[rows[q]];
-}
-
-// one wavefront per view row: gather its entries into a compact buffer
-template <int VSZ>
-__global__ __launch_bounds__(256) static void k_view_gather(const int32_t* rows, int32_t n, const int64_t* off,
-                                                            const int32_t* len, const int32_t* col,
-                                                            const char* val, const int64_t* rp, int32_t* ocol,
-                                                            char* oval) {
-  int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  int lane = threadIdx.x & 63;
-  if (q >= n) return;
-  int32_t i = rows[q];
-  int64_t o = off[i], d = rp[q];
-  for (int32_t t = lane; t < len[i]; t += 64) {
-    ocol[d + t] = col[o + t];
-    for (int b = 0; b < VSZ; ++b) oval[(d + t) * VSZ + b] = val[(o + t) * VSZ + b];
-  }
-}
-
 extern "C" dsg_status dsg_rows_export(dsg_prod* ph, const dsg_rows* v, int64_t* row_ptr, int32_t* col,
                                       void* val, int64_t cap, int64_t* nnz_out) {
   if (!ph || !v || !nnz_out) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
@@ -611,63 +592,23 @@ extern "C" dsg_status dsg_rows_export(dsg_prod* ph, const dsg_rows* v, int64_t* 
   set_device(ctx__);
   DProd* p = ph->p;
   Ctx* c = p->ctx;
-  DMat* C = p->C;
-  const int32_t n = v->n;
-  const int vs = C->vsz;
-  const size_t sb = scan_scratch_bytes(n) + 64;
-  DevArray lens, rp, scr;
-  lens.c = rp.c = scr.c = c;
-  lens.bytes = (size_t)(n + 1) * 8;
-  rp.bytes = (size_t)(n + 1) * 8;
-  scr.bytes = sb;
-  lens.p = ctx_alloc(c, lens.bytes); lens.owned = true;
-  rp.p = ctx_alloc(c, rp.bytes); rp.owned = true;
-  scr.p = ctx_alloc(c, scr.bytes); scr.owned = true;
-  if (n > 0)
-    hipLaunchKernelGGL(k_view_lens, dim3((n + 255) / 256), dim3(256), 0, c->stream, v->rows, n, C->row_len,
-                       (int64_t*)lens.p);
-  exclusive_scan_i64((const int64_t*)lens.p, (int64_t*)rp.p, n, (int64_t*)rp.p + n, scr.p, c->stream);
-  std::vector<int64_t> hrp((size_t)n + 1);
-  DSG_HIP(hipMemcpyAsync(hrp.data(), rp.p, hrp.size() * 8, hipMemcpyDeviceToHost, c->stream));
-  ctx_sync(c);
-  const int64_t nnz = hrp[n];
+  GatherBufs g;
+  RowsHost h;
+  try {
+    mat_gather_rows(p->C, v->rows, v->n, g, h, c->stream, col != nullptr);
+  } catch (...) {
+    gather_bufs_free(c, g);
+    throw;
+  }
+  gather_bufs_free(c, g);
+  const int64_t nnz = h.row_ptr[(size_t)v->n];
   *nnz_out = nnz;
-  if (row_ptr) memcpy(row_ptr, hrp.data(), hrp.size() * 8);
+  if (row_ptr) memcpy(row_ptr, h.row_ptr.data(), h.row_ptr.size() * 8);
   if (!col) return DSG_OK;
   if (cap < nnz) throw DsgError{DSG_E_ARG, "capacity < nnz"};
   if (nnz == 0) return DSG_OK;
-  DevArray dc, dv;
-  dc.c = dv.c = c;
-  dc.bytes = (size_t)nnz * 4;
-  dv.bytes = (size_t)nnz * vs;
-  dc.p = ctx_alloc(c, dc.bytes); dc.owned = true;
-  dv.p = ctx_alloc(c, dv.bytes); dv.owned = true;
-  unsigned nb = (unsigned)(((int64_t)n * 64 + 255) / 256);
-  if (vs == 8)
-    hipLaunchKernelGGL(k_view_gather<8>, dim3(nb), dim3(256), 0, c->stream, v->rows, n, C->row_off, C->row_len,
-                       C->col, (const char*)C->val, (const int64_t*)rp.p, (int32_t*)dc.p, (char*)dv.p);
-  else
-    hipLaunchKernelGGL(k_view_gather<4>, dim3(nb), dim3(256), 0, c->stream, v->rows, n, C->row_off, C->row_len,
-                       C->col, (const char*)C->val, (const int64_t*)rp.p, (int32_t*)dc.p, (char*)dv.p);
-  std::vector<int32_t> hc((size_t)nnz);
-  std::vector<char> hv((size_t)nnz * vs);
-  DSG_HIP(hipMemcpyAsync(hc.data(), dc.p, dc.bytes, hipMemcpyDeviceToHost, c->stream));
-  DSG_HIP(hipMemcpyAsync(hv.data(), dv.p, dv.bytes, hipMemcpyDeviceToHost, c->stream));
-  ctx_sync(c);
-  // canonical order inside each row
-  std::vector<int64_t> perm;
-  char* ov = (char*)val;
-  for (int32_t q = 0; q < n; ++q) {
-    int64_t a = hrp[q], b = hrp[q + 1];
-    perm.resize((size_t)(b - a));
-    for (int64_t e = a; e < b; ++e) perm[(size_t)(e - a)] = e;
-    std::sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return hc[(size_t)x] < hc[(size_t)y]; });
-    for (int64_t e = a; e < b; ++e) {
-      int64_t src = perm[(size_t)(e - a)];
-      col[e] = hc[(size_t)src];
-      memcpy(ov + (size_t)e * vs, hv.data() + (size_t)src * vs, (size_t)vs);
-    }
-  }
+  memcpy(col, h.col.data(), (size_t)nnz * 4);
+  memcpy(val, h.val.data(), h.val.size());
   API_END
 }
 
@@ -841,9 +782,9 @@ extern "C" dsg_status dsg_batch_rows(dsg_batch* bh, int32_t i, dsg_rows* out) {
   return DSG_OK;
 }
 
-extern "C" dsg_status dsg_batch_info(const dsg_batch* bh, int64_t* captures, int64_t* replays, int64_t* deferred) {
-  if (!bh) return fail(nullptr, DSG_E_ARG, "batch is NULL");
-  batch_info(bh->b, captures, replays, deferred);
+extern "C" dsg_status dsg_batch_info(const dsg_batch* bh, dsg_batch_stats* out) {
+  if (!bh || !out) return fail(nullptr, DSG_E_ARG, "batch or output is NULL");
+  batch_info(bh->b, out);
   return DSG_OK;
 }
 
@@ -864,5 +805,100 @@ extern "C" dsg_status dsg_prod_destroy(dsg_prod* ph) {
   ctx_sync(&ctx__->c);
   prod_destroy(ph->p);
   delete ph;
+  API_END
+}
+
+// ---------------------------------------------------------------------------
+// served form
+// ---------------------------------------------------------------------------
+
+struct dsg_server {
+  DServer* s;
+  dsg_ctx* owner;
+  dsg_prod* prod;
+};
+
+// Server calls may come from several client threads: their failures go to the
+// calling thread's message (dsg_last_error(NULL)), not to the context.
+#define SERVER_BEGIN(sh)                                        \
+  if (!(sh)) return fail(nullptr, DSG_E_ARG, "server is NULL"); \
+  dsg_ctx* ctx__ = nullptr;                                     \
+  try {
+
+extern "C" dsg_status dsg_server_create(dsg_ctx* ctx, dsg_prod* ph, const dsg_server_cfg* cfg, dsg_server** out) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  if (!ph || !out) return fail(ctx, DSG_E_ARG, "NULL argument");
+  if (ph->owner != ctx) return fail(ctx, DSG_E_STATE, "product of another context");
+  if (cfg && (cfg->slots < 0 || cfg->slots > 8)) return fail(ctx, DSG_E_ARG, "slots must be 0..8");
+  *out = nullptr;
+  API_BEGIN(ctx)
+  set_device(ctx);
+  if (ph->p->refs > 0) throw DsgError{DSG_E_STATE, "product is used by a batched executor or server"};
+  DServer* s = server_create(&ctx->c, ph->p, cfg);
+  dsg_server* h = new dsg_server();
+  h->s = s;
+  h->owner = ctx;
+  h->prod = ph;
+  ctx->c.served = true;
+  *out = h;
+  API_END
+}
+
+extern "C" dsg_status dsg_server_submit_update(dsg_server* sh, dsg_mat* mh, const int32_t* rows, const int32_t* cols,
+                                               const void* vals, const uint8_t* ops, int64_t n, uint64_t* ticket) {
+  SERVER_BEGIN(sh)
+  if (!mh || !ticket || n < 0 || (n > 0 && (!rows || !cols || !ops || (mh->m->vsz && !vals))))
+    throw DsgError{DSG_E_ARG, "bad arguments"};
+  *ticket = server_submit_update(sh->s, mh->m, rows, cols, vals, ops, n);
+  API_END
+}
+
+extern "C" dsg_status dsg_server_submit_query(dsg_server* sh, const int32_t* rows, int32_t nq, uint64_t* ticket) {
+  SERVER_BEGIN(sh)
+  if (!ticket || nq < 0 || (nq > 0 && !rows)) throw DsgError{DSG_E_ARG, "bad arguments"};
+  *ticket = server_submit_query(sh->s, rows, nq);
+  API_END
+}
+
+extern "C" dsg_status dsg_server_poll(dsg_server* sh, uint64_t ticket, int32_t wait, dsg_server_result* out) {
+  SERVER_BEGIN(sh)
+  if (!out) throw DsgError{DSG_E_ARG, "out is NULL"};
+  server_poll(sh->s, ticket, wait != 0, out);
+  API_END
+}
+
+extern "C" dsg_status dsg_server_query_result(dsg_server* sh, uint64_t ticket, int64_t* row_ptr, int32_t* col,
+                                              void* val, int64_t cap, int64_t* nnz_out) {
+  SERVER_BEGIN(sh)
+  if (!nnz_out || (col && !val)) throw DsgError{DSG_E_ARG, "bad arguments"};
+  server_query_result(sh->s, ticket, row_ptr, col, val, cap, nnz_out);
+  API_END
+}
+
+extern "C" dsg_status dsg_server_release(dsg_server* sh, uint64_t ticket) {
+  SERVER_BEGIN(sh)
+  server_release(sh->s, ticket);
+  API_END
+}
+
+extern "C" dsg_status dsg_server_drain(dsg_server* sh) {
+  SERVER_BEGIN(sh)
+  server_drain(sh->s);
+  API_END
+}
+
+extern "C" dsg_status dsg_server_stats_get(dsg_server* sh, dsg_server_stats* out) {
+  SERVER_BEGIN(sh)
+  if (!out) throw DsgError{DSG_E_ARG, "out is NULL"};
+  server_stats(sh->s, out);
+  API_END
+}
+
+extern "C" dsg_status dsg_server_destroy(dsg_server* sh) {
+  SERVER_BEGIN(sh)
+  dsg_ctx* ctx = sh->owner;
+  server_destroy(sh->s);
+  ctx->c.served = false;
+  delete sh;
   API_END
 }

@@ -10,6 +10,7 @@
 // room has grown by exactly what they asked for.  The graph is captured on the first run and
 // replayed while every pointer and size it baked in is unchanged.
 #include <algorithm>
+#include <chrono>
 
 #include "internal.h"
 
@@ -56,7 +57,12 @@ struct DBatch {
   hipEvent_t ev_fork = nullptr;
   std::vector<hipEvent_t> ev_join;
   int64_t captures = 0, replays = 0, deferred = 0;
+  double prepare_ms = 0, capture_ms = 0, replay_ms = 0, finish_ms = 0;
 };
+
+static double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
 
 static void free_ws(Ctx* c, std::vector<void*>& v, std::vector<size_t>& b) {
   for (size_t i = 0; i < v.size(); ++i) ctx_free(c, v[i], b[i]);
@@ -124,10 +130,14 @@ void batch_destroy(DBatch* b) {
 
 DProd* batch_prod(DBatch* b, int i) { return b->prods[(size_t)i]; }
 
-void batch_info(const DBatch* b, int64_t* captures, int64_t* replays, int64_t* deferred) {
-  if (captures) *captures = b->captures;
-  if (replays) *replays = b->replays;
-  if (deferred) *deferred = b->deferred;
+void batch_info(const DBatch* b, dsg_batch_stats* out) {
+  out->captures = b->captures;
+  out->replays = b->replays;
+  out->deferred = b->deferred;
+  out->prepare_ms = b->prepare_ms;
+  out->capture_ms = b->capture_ms;
+  out->replay_ms = b->replay_ms;
+  out->finish_ms = b->finish_ms;
 }
 
 static void ensure_ws(Ctx* c, std::vector<void*>& v, std::vector<size_t>& have, size_t i, size_t bytes,
@@ -150,6 +160,7 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   const hipStream_t main = c->stream;
   const size_t np = b->prods.size();
   counts.assign(np, 0);
+  auto t0 = std::chrono::steady_clock::now();
   // which product each set belongs to (sets name operands of one product)
   std::vector<int> owner(sets.size(), -1);
   for (size_t k = 0; k < sets.size(); ++k) {
@@ -181,13 +192,17 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     ensure_ws(c, b->aw, b->aw_bytes, k, apply_work_bytes(sets[k].n, m->tidx != nullptr), ws_changed);
     ensure_ws(c, b->awt, b->awt_bytes, k, apply_work_bytes(sets[k].n, false), ws_changed);
   }
+  std::vector<int64_t> c_top_before(np);
   for (size_t j = 0; j < np; ++j) {
     DProd* p = b->prods[j];
-    // modest room: rows that need more are completed after the replay
-    const int64_t c_room = p->C->h_top_ub / 8 + 4096;
+    // room for C: an eighth of its pool or twice what the last run took,
+    // whichever is more; rows that need still more are completed after the
+    // replay
+    const int64_t c_room = std::max<int64_t>(p->C->h_top_ub / 8, 2 * p->last_c_growth) + 4096;
     const size_t arena = std::max<size_t>(p->arena_bytes, (size_t)1 << 20);
     prod_prepare_graph(p, c_room, arena);
     ensure_ws(c, b->pw, b->pw_bytes, j, prod_graph_work_bytes(p), ws_changed);
+    c_top_before[j] = p->C->h_top_ub;
   }
   // ---- the signature of what a graph bakes in ----
   std::vector<uintptr_t> sig;
@@ -210,7 +225,9 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   for (int x = 0; x < 8; ++x) sig.push_back((uintptr_t)t.group_ub[x]);
   sig.push_back((uintptr_t)t.dense_max_passes);
   sig.push_back((uintptr_t)(t.force_bin + 1));
+  b->prepare_ms += ms_since(t0);
   if (!b->exec || sig != b->signature) {
+    t0 = std::chrono::steady_clock::now();
     drop_graph(b);
     // device table of the pool tops the graph reports back
     std::vector<int64_t*> tops;
@@ -258,8 +275,10 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     DSG_HIP(e);
     b->signature = sig;
     b->captures++;
+    b->capture_ms += ms_since(t0);
   }
   // ---- one replay for every product ----
+  t0 = std::chrono::steady_clock::now();
   DSG_HIP(hipGraphLaunch(b->exec, main));
   b->replays++;
   std::vector<int64_t> out(np * OUT_WORDS), tops(b->mats.size());
@@ -267,19 +286,26 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   DSG_HIP(hipMemcpyAsync(tops.data(), b->d_tops, tops.size() * 8, hipMemcpyDeviceToHost, main));
   DSG_HIP(hipStreamSynchronize(main));
   for (size_t i = 0; i < b->mats.size(); ++i) b->mats[i]->h_top_ub = tops[i];
+  b->replay_ms += ms_since(t0);
+  t0 = std::chrono::steady_clock::now();
   for (size_t j = 0; j < np; ++j) {
     const int64_t* o = &out[j * OUT_WORDS];
     DSG_REQUIRE(o[2] == 0 && o[6] == 0 && o[7] == 0, DSG_E_DEVICE,
                 "internal: device error flags " + std::to_string(o[2]) + "/" + std::to_string(o[6]) + "/" +
                     std::to_string(o[7]) + " in batched product " + std::to_string(j));
+    DProd* p = b->prods[j];
+    // slots taken (a pool top that ran past the end also counts what the
+    // rows without room asked for)
+    p->last_c_growth = std::max<int64_t>(0, p->C->h_top_ub - c_top_before[j]) + o[4];
     if (o[3]) {
       // some rows found no room (they wrote nothing): grow C / the arena by
       // exactly what they asked for and recompute them
-      counts[j] = prod_finish_graph(b->prods[j], b->pw[j]);
+      counts[j] = prod_finish_graph(p, b->pw[j]);
       b->deferred++;
     } else {
       counts[j] = (int32_t)o[0];
     }
   }
+  b->finish_ms += ms_since(t0);
   return DSG_OK;
 }

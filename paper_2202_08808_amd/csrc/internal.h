@@ -5,6 +5,7 @@
 
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -81,7 +82,9 @@ struct Ctx {
   bool own_stream = false;
   size_t budget = 0;
   size_t held = 0;
+  std::mutex alloc_mu;  // ctx_alloc / ctx_free may run on a server's threads
   std::string last_error = "";
+  bool served = false;  // owned by a server thread: the ABI refuses other calls
   int objects = 0;
   int num_cus = 256;  // compute units of the device
   dsg_tuning tuning;
@@ -172,6 +175,31 @@ void mat_export_device(DMat* m, int64_t* d_row_ptr, int32_t* d_col, void* d_val,
 // Build the structure-only transpose index of m.
 void mat_build_transpose(DMat* m);
 
+// Listed rows of a matrix, copied to the host with each row sorted by column.
+struct RowsHost {
+  std::vector<int64_t> row_ptr;  // n + 1
+  std::vector<int32_t> col;
+  std::vector<char> val;         // vsz bytes per entry
+};
+// Reusable device buffers of mat_gather_rows (grown on demand).
+struct GatherBufs {
+  void* lens = nullptr;
+  size_t lens_bytes = 0;
+  void* rp = nullptr;
+  size_t rp_bytes = 0;
+  void* scan = nullptr;
+  size_t scan_bytes = 0;
+  void* col = nullptr;
+  size_t col_bytes = 0;
+  void* val = nullptr;
+  size_t val_bytes = 0;
+};
+// d_rows: n valid row ids on the device.  Synchronizes stream s.  With
+// entries false only the row pointers are filled.
+void mat_gather_rows(DMat* m, const int32_t* d_rows, int32_t n, GatherBufs& g, RowsHost& out, hipStream_t s,
+                     bool entries = true);
+void gather_bufs_free(Ctx* c, GatherBufs& g);
+
 // Apply a device-resident batch (validated).  Returns nothing; updates epochs.
 void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
                       const uint8_t* d_ops, int64_t n);
@@ -208,6 +236,7 @@ struct DProd {
   dsg_update_stats stats{};
   int64_t last_c_demand = 0;      // C pool and arena needs of the last plain-path run
   int64_t last_arena_demand = 0;
+  int64_t last_c_growth = 0;      // C pool slots the last batched run took
   int refs = 0;                   // batched executors and servers using this product
 };
 
@@ -251,4 +280,21 @@ void batch_destroy(DBatch* b);
 // returns DSG_OK, or DSG_E_RANGE / DSG_E_ARG for a bad set (nothing applied)
 dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<int32_t>& counts);
 DProd* batch_prod(DBatch* b, int i);
-void batch_info(const DBatch* b, int64_t* captures, int64_t* replays, int64_t* deferred);
+
+// ---------------------------------------------------------------------------
+// served form (server.hip)
+// ---------------------------------------------------------------------------
+
+struct DServer;
+DServer* server_create(Ctx* c, DProd* p, const dsg_server_cfg* cfg);
+void server_destroy(DServer* s);  // drains first
+uint64_t server_submit_update(DServer* s, DMat* m, const int32_t* rows, const int32_t* cols, const void* vals,
+                              const uint8_t* ops, int64_t n);
+uint64_t server_submit_query(DServer* s, const int32_t* rows, int32_t nq);
+void server_poll(DServer* s, uint64_t ticket, bool wait, dsg_server_result* out);
+void server_query_result(DServer* s, uint64_t ticket, int64_t* row_ptr, int32_t* col, void* val, int64_t cap,
+                         int64_t* nnz_out);
+void server_release(DServer* s, uint64_t ticket);
+void server_drain(DServer* s);
+void server_stats(DServer* s, dsg_server_stats* out);
+void batch_info(const DBatch* b, dsg_batch_stats* out);

@@ -7,6 +7,9 @@
 // wavefront streams a whole row once and matches it against that row's
 // updates; no per-row hash table is kept.  Rows keep slack capacity so that
 // most insertions need no move.
+#include <algorithm>
+#include <cstring>
+
 #include "internal.h"
 #include "kernel_common.h"
 
@@ -383,4 +386,104 @@ void mat_build_transpose(DMat* m) {
     throw;
   }
   m->tidx = t;
+}
+
+// ---------------------------------------------------------------------------
+// row gather: listed rows of a matrix, canonical, into host memory
+// ---------------------------------------------------------------------------
+
+namespace {
+
+__global__ void k_gather_lens(const int32_t* rows, int32_t n, const int32_t* row_len, int64_t* lens) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) lens[q] = row_len[rows[q]];
+}
+
+// one wavefront per listed row: its entries into a compact buffer
+template <int VSZ>
+__global__ __launch_bounds__(256) void k_gather_rows(const int32_t* rows, int32_t n, const int64_t* off,
+                                                     const int32_t* len, const int32_t* col, const char* val,
+                                                     const int64_t* rp, int32_t* ocol, char* oval) {
+  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (q >= n) return;
+  const int32_t i = rows[q];
+  const int64_t o = off[i], d = rp[q];
+  for (int32_t t = lane; t < len[i]; t += 64) {
+    ocol[d + t] = col[o + t];
+    if constexpr (VSZ == 8) ((uint64_t*)oval)[d + t] = ((const uint64_t*)val)[o + t];
+    else if constexpr (VSZ == 4) ((uint32_t*)oval)[d + t] = ((const uint32_t*)val)[o + t];
+  }
+}
+
+void ensure_buf(Ctx* c, void*& p, size_t& have, size_t bytes) {
+  if (bytes <= have) return;
+  ctx_free(c, p, have);
+  p = nullptr;
+  have = 0;
+  const size_t nb = bytes + bytes / 2 + 4096;
+  p = ctx_alloc(c, nb);
+  have = nb;
+}
+
+}  // namespace
+
+void gather_bufs_free(Ctx* c, GatherBufs& g) {
+  ctx_free(c, g.lens, g.lens_bytes);
+  ctx_free(c, g.rp, g.rp_bytes);
+  ctx_free(c, g.scan, g.scan_bytes);
+  ctx_free(c, g.col, g.col_bytes);
+  ctx_free(c, g.val, g.val_bytes);
+  g = GatherBufs{};
+}
+
+void mat_gather_rows(DMat* m, const int32_t* d_rows, int32_t n, GatherBufs& g, RowsHost& out, hipStream_t s,
+                     bool entries) {
+  Ctx* c = m->ctx;
+  const int vs = m->vsz;
+  ensure_buf(c, g.lens, g.lens_bytes, (size_t)(n + 1) * 8);
+  ensure_buf(c, g.rp, g.rp_bytes, (size_t)(n + 1) * 8);
+  ensure_buf(c, g.scan, g.scan_bytes, scan_scratch_bytes(n) + 64);
+  if (n > 0)
+    hipLaunchKernelGGL(k_gather_lens, dim3(blocks_for(n, 256)), dim3(256), 0, s, d_rows, n, m->row_len,
+                       (int64_t*)g.lens);
+  exclusive_scan_i64((const int64_t*)g.lens, (int64_t*)g.rp, n, (int64_t*)g.rp + n, g.scan, s);
+  out.row_ptr.assign((size_t)n + 1, 0);
+  DSG_HIP(hipMemcpyAsync(out.row_ptr.data(), g.rp, out.row_ptr.size() * 8, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  const int64_t nnz = out.row_ptr[(size_t)n];
+  if (!entries) return;
+  out.col.resize((size_t)nnz);
+  out.val.resize((size_t)nnz * vs);
+  if (nnz == 0) return;
+  ensure_buf(c, g.col, g.col_bytes, (size_t)nnz * 4);
+  ensure_buf(c, g.val, g.val_bytes, (size_t)nnz * (vs ? vs : 1));
+  const unsigned nb = (unsigned)blocks_for((int64_t)n * 64, 256);
+  if (vs == 8)
+    hipLaunchKernelGGL(k_gather_rows<8>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
+                       (const char*)m->val, (const int64_t*)g.rp, (int32_t*)g.col, (char*)g.val);
+  else if (vs == 4)
+    hipLaunchKernelGGL(k_gather_rows<4>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
+                       (const char*)m->val, (const int64_t*)g.rp, (int32_t*)g.col, (char*)g.val);
+  else
+    hipLaunchKernelGGL(k_gather_rows<0>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
+                       (const char*)m->val, (const int64_t*)g.rp, (int32_t*)g.col, (char*)g.val);
+  std::vector<int32_t> hc((size_t)nnz);
+  std::vector<char> hv((size_t)nnz * vs);
+  DSG_HIP(hipMemcpyAsync(hc.data(), g.col, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));
+  if (vs) DSG_HIP(hipMemcpyAsync(hv.data(), g.val, (size_t)nnz * vs, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  // rows are stored in no particular column order: sort each one
+  std::vector<int64_t> perm;
+  for (int32_t q = 0; q < n; ++q) {
+    const int64_t a = out.row_ptr[(size_t)q], b = out.row_ptr[(size_t)q + 1];
+    perm.resize((size_t)(b - a));
+    for (int64_t e = a; e < b; ++e) perm[(size_t)(e - a)] = e;
+    std::sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return hc[(size_t)x] < hc[(size_t)y]; });
+    for (int64_t e = a; e < b; ++e) {
+      const int64_t src = perm[(size_t)(e - a)];
+      out.col[(size_t)e] = hc[(size_t)src];
+      if (vs) memcpy(out.val.data() + (size_t)e * vs, hv.data() + (size_t)src * vs, (size_t)vs);
+    }
+  }
 }

@@ -57,6 +57,35 @@ class Stats(ctypes.Structure):
         return d
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("captures", ctypes.c_int64), ("replays", ctypes.c_int64), ("deferred", ctypes.c_int64),
+                ("prepare_ms", ctypes.c_double), ("capture_ms", ctypes.c_double),
+                ("replay_ms", ctypes.c_double), ("finish_ms", ctypes.c_double)]
+
+
+class ServerCfg(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_size_t), ("max_coalesce", ctypes.c_int64),
+                ("max_query_rows", ctypes.c_int32), ("slots", ctypes.c_int32)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("kind", ctypes.c_int32), ("latency_ms", ctypes.c_double),
+                ("group", ctypes.c_int64), ("group_requests", ctypes.c_int32), ("changed_rows", ctypes.c_int32),
+                ("nq", ctypes.c_int32), ("nnz", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("update_requests", ctypes.c_int64), ("query_requests", ctypes.c_int64),
+                ("update_entries", ctypes.c_int64), ("update_groups", ctypes.c_int64),
+                ("query_groups", ctypes.c_int64), ("update_p50_ms", ctypes.c_double),
+                ("update_p99_ms", ctypes.c_double), ("update_mean_ms", ctypes.c_double),
+                ("query_p50_ms", ctypes.c_double), ("query_p99_ms", ctypes.c_double),
+                ("query_mean_ms", ctypes.c_double), ("busy_ms", ctypes.c_double),
+                ("updates_per_s", ctypes.c_double), ("peak_inflight_bytes", ctypes.c_size_t)]
+
+
+PENDING = -1
+
 SIGNATURES = {
     "dsg_ctx_create": [ctypes.c_int, P, ctypes.c_size_t, P],
     "dsg_ctx_destroy": [P],
@@ -85,8 +114,17 @@ SIGNATURES = {
     "dsg_batch_create": [P, P, ctypes.c_int32, P],
     "dsg_batch_run": [P, P, ctypes.c_int32, ctypes.c_uint32, P],
     "dsg_batch_rows": [P, ctypes.c_int32, P],
-    "dsg_batch_info": [P, P, P, P],
+    "dsg_batch_info": [P, P],
     "dsg_batch_destroy": [P],
+    "dsg_server_create": [P, P, P, P],
+    "dsg_server_submit_update": [P, P, P, P, P, P, ctypes.c_int64, P],
+    "dsg_server_submit_query": [P, P, ctypes.c_int32, P],
+    "dsg_server_poll": [P, ctypes.c_uint64, ctypes.c_int32, P],
+    "dsg_server_query_result": [P, ctypes.c_uint64, P, P, P, ctypes.c_int64, P],
+    "dsg_server_release": [P, ctypes.c_uint64],
+    "dsg_server_drain": [P],
+    "dsg_server_stats_get": [P, P],
+    "dsg_server_destroy": [P],
 }
 
 
@@ -419,11 +457,82 @@ class Batch:
         return RowSet(self.prods[i], v)
 
     def info(self) -> dict:
-        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        self.ctx._check(self.L.dsg_batch_info(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-        return {"captures": a.value, "replays": b.value, "deferred": c.value}
+        st = BatchStats()
+        self.ctx._check(self.L.dsg_batch_info(self.h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in BatchStats._fields_}
 
     def destroy(self):
         if self.h:
             self.ctx._check(self.L.dsg_batch_destroy(self.h))
+            self.h = None
+
+
+class Server:
+    """Served form: a request loop (library threads) over a product's
+    resident operands and result.  Requests are host arrays; results are
+    polled by ticket.  While the server lives, the context is its own."""
+
+    def __init__(self, ctx: Context, prod: Product, mem_budget: int = 0, max_coalesce: int = 0,
+                 max_query_rows: int = 0, slots: int = 0):
+        self.ctx, self.L, self.prod = ctx, ctx.L, prod
+        cfg = ServerCfg(mem_budget, max_coalesce, max_query_rows, slots)
+        h = P()
+        ctx._check(self.L.dsg_server_create(ctx.h, prod.h, ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+
+    def _check(self, st):
+        self.ctx._check(st, h=None)
+
+    def submit_update(self, mat: Matrix, rows, cols, vals, ops) -> int:
+        rows = np.ascontiguousarray(rows, np.int32)
+        cols = np.ascontiguousarray(cols, np.int32)
+        vals = np.ascontiguousarray(vals, DTYPE[mat.semiring])
+        ops = np.ascontiguousarray(ops, np.uint8)
+        t = ctypes.c_uint64()
+        self._check(self.L.dsg_server_submit_update(self.h, mat.h, rows.ctypes.data_as(P), cols.ctypes.data_as(P),
+                                                    vals.ctypes.data_as(P), ops.ctypes.data_as(P), rows.size,
+                                                    ctypes.byref(t)))
+        return t.value
+
+    def submit_batch(self, mat: Matrix, b) -> int:
+        return self.submit_update(mat, b.rows, b.cols, b.vals, b.ops)
+
+    def submit_query(self, rows) -> int:
+        rows = np.ascontiguousarray(rows, np.int32)
+        t = ctypes.c_uint64()
+        self._check(self.L.dsg_server_submit_query(self.h, rows.ctypes.data_as(P), rows.size, ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = False) -> dict:
+        r = ServerResult()
+        self._check(self.L.dsg_server_poll(self.h, ticket, 1 if wait else 0, ctypes.byref(r)))
+        return {name: getattr(r, name) for name, _ in ServerResult._fields_}
+
+    def query_result(self, ticket: int) -> Csr:
+        info = self.poll(ticket, wait=True)
+        if info["status"] != OK:
+            raise DsgError(info["status"], "query failed")
+        nq = info["nq"]
+        nnz = ctypes.c_int64()
+        rp = np.zeros(nq + 1, np.int64)
+        col = np.zeros(max(info["nnz"], 1), np.int32)
+        val = np.zeros(max(info["nnz"], 1), DTYPE[self.prod.semiring])
+        self._check(self.L.dsg_server_query_result(self.h, ticket, rp.ctypes.data_as(P), col.ctypes.data_as(P),
+                                                   val.ctypes.data_as(P), col.size, ctypes.byref(nnz)))
+        return Csr(nq, self.prod.ncols, rp, col[:nnz.value], val[:nnz.value])
+
+    def release(self, ticket: int):
+        self._check(self.L.dsg_server_release(self.h, ticket))
+
+    def drain(self):
+        self._check(self.L.dsg_server_drain(self.h))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._check(self.L.dsg_server_stats_get(self.h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def destroy(self):
+        if self.h:
+            self._check(self.L.dsg_server_destroy(self.h))
             self.h = None

@@ -342,3 +342,41 @@ def batched_instances(count: int = 64, stream: int = 401, max_scale: int = 16):
         b = int(math.floor(10 ** rng.uniform(1, 4)))
         out.append((scale, ef, sr, b))
     return out
+
+
+@dataclasses.dataclass
+class Request:
+    """One request of a serving trace."""
+    t: float                        # arrival time in seconds from the start
+    kind: str                       # "update" or "query"
+    batch: Optional[Batch] = None   # update entries
+    rows: Optional[np.ndarray] = None  # query rows (int32, distinct)
+
+
+def serve_trace(base: Csr, semiring: int, n_requests: int, rate: float, stream: int = 601,
+                query_frac: float = 0.5, size_mu: float = 3.0, size_sigma: float = 0.67,
+                size_lo: float = 1.0, size_hi: float = 5.0, max_query_rows: int = 1024,
+                value_lo: int = 1, value_hi: int = 100) -> List[Request]:
+    """Poisson arrivals at ``rate`` requests/s.  A request is a query with
+    probability ``query_frac`` (1..max_query_rows distinct uniform rows), else
+    an update batch of floor(10**X) entries, X ~ N(size_mu, size_sigma)
+    truncated to [size_lo, size_hi], mix 50/25/25, positions disjoint over the
+    whole trace (see disjoint_batches)."""
+    rng = rng_for(stream, 0)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    is_query = rng.random(n_requests) < query_frac
+    n_upd = int((~is_query).sum())
+    x = np.clip(rng.normal(size_mu, size_sigma, n_upd), size_lo, size_hi)
+    sizes = np.floor(10.0 ** x).astype(np.int64)
+    batches = disjoint_batches(base, semiring, sizes, stream=stream + 1, value_lo=value_lo, value_hi=value_hi)
+    qn = rng.integers(1, max_query_rows + 1, n_requests - n_upd)
+    out, u, q = [], 0, 0
+    for k in range(n_requests):
+        if is_query[k]:
+            rows = np.sort(rng.choice(base.nrows, min(int(qn[q]), base.nrows), replace=False)).astype(np.int32)
+            out.append(Request(float(t[k]), "query", rows=rows))
+            q += 1
+        else:
+            out.append(Request(float(t[k]), "update", batch=batches[u]))
+            u += 1
+    return out
