@@ -580,22 +580,28 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   const int64_t ooff = R.c_off[i];
   const int32_t olen = R.c_len[i];
   const int32_t stage_n = min(ub, R.ncols);
-  const size_t stage_bytes = (((size_t)stage_n * (4 + sizeof(V))) + 255) & ~size_t(255);
-  int64_t sbase = 0;
-  if (tid == 0) sbase = (int64_t)atomicAdd(R.arena_top, (unsigned long long)stage_bytes);
-  sbase = grp.bcast64(sbase, 0, &bslot);
-  if (sbase + (int64_t)stage_bytes > R.arena_cap) {
-    if (tid == 0) mark_retry(R, q, R.arena_short, (unsigned long long)stage_bytes);
-    continue;
+  const int passes = (R.ncols + CH - 1) / CH;
+  // staging space holds the chunks before the last one (none for a one-pass row)
+  int32_t* scol = nullptr;
+  V* sval = nullptr;
+  if (passes > 1) {
+    const size_t stage_bytes = (((size_t)stage_n * (4 + sizeof(V))) + 255) & ~size_t(255);
+    int64_t sbase = 0;
+    if (tid == 0) sbase = (int64_t)atomicAdd(R.arena_top, (unsigned long long)stage_bytes);
+    sbase = grp.bcast64(sbase, 0, &bslot);
+    if (sbase + (int64_t)stage_bytes > R.arena_cap) {
+      if (tid == 0) mark_retry(R, q, R.arena_short, (unsigned long long)stage_bytes);
+      continue;
+    }
+    scol = (int32_t*)(R.arena + sbase);
+    sval = (V*)(R.arena + sbase + (size_t)stage_n * 4);
   }
-  int32_t* scol = (int32_t*)(R.arena + sbase);
-  V* sval = (V*)(R.arena + sbase + (size_t)stage_n * 4);
 
   bool changed = R.force_write;
+  bool fault = false, parked = false;
   int32_t nnew = 0;
   int64_t flops = 0;
   int64_t old_read = 0;
-  const int passes = (R.ncols + CH - 1) / CH;
   for (int pc = 0; pc < passes; ++pc) {
     const int32_t c0 = pc * CH;
     const int32_t c1 = min(c0 + CH, R.ncols);
@@ -718,9 +724,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       }
       grp.sync();
     }
-    // compaction of this column chunk in ascending column order: wavefront w
-    // owns columns [w*SEG, (w+1)*SEG) and walks them 64 at a time, so LDS reads
-    // are bank-conflict free and staging writes are coalesced
+    // counts of this column chunk: wavefront w owns columns [w*SEG, (w+1)*SEG)
+    // and walks them 64 at a time (bank-conflict-free LDS reads)
     auto touched = [&](int x) -> bool {
       if constexpr (kBits) return (bits[x >> 5] >> (x & 31)) & 1u;
       else return acc[x] != S::identity();
@@ -740,30 +745,26 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       ctot += c;
     }
     grp.sync();
-    int32_t o = nnew + before;
-    for (int r = 0; r < SEG; r += 64) {
-      const int x = cwv * SEG + r + cln;
-      const bool tch = touched(x);
-      const uint64_t b = __ballot(tch);
-      if (tch) {
-        const int32_t pos = o + __popcll(b & clt);
-        if (pos < stage_n) {
-          scol[pos] = c0 + x;
-          sval[pos] = S::from_acc(acc[x]);
-        }
-      }
-      o += __popcll(b);
-    }
-    // compare the old entries that fall into this chunk
+    // compare the old entries that fall into this chunk (4 loads in flight per lane)
     if (!changed) {
       int32_t in_chunk = 0;
       bool bad = false;
-      for (int32_t e = tid; e < olen; e += DENSE_WG) {
-        int32_t c = R.c_col[ooff + e];
-        if (c >= c0 && c < c1) {
-          ++in_chunk;
-          int x = c - c0;
-          bad |= !touched(x) || !same_bits(acc[x], S::to_acc(ldv<V>(R.c_val, ooff + e)));
+      for (int32_t e0 = tid; e0 < olen; e0 += 4 * DENSE_WG) {
+        int32_t oc[4];
+        V ov[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t e = e0 + u * DENSE_WG;
+          oc[u] = e < olen ? R.c_col[ooff + e] : -1;
+          ov[u] = e < olen ? ldv<V>(R.c_val, ooff + e) : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (oc[u] >= c0 && oc[u] < c1) {
+            ++in_chunk;
+            const int x = oc[u] - c0;
+            bad |= !touched(x) || !same_bits(acc[x], S::to_acc(ov[u]));
+          }
         }
       }
       int32_t itot;
@@ -771,36 +772,82 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       if (grp.any(bad, wscr) || itot != ctot) changed = true;
       old_read = olen;
     }
+    // the chunk's entries in ascending column order, to out[base + ...]
+    auto emit = [&](int32_t* ocol, V* oval, int64_t base, int32_t limit) {
+      int32_t o = before;
+      for (int r = 0; r < SEG; r += 64) {
+        const int x = cwv * SEG + r + cln;
+        const bool tch = touched(x);
+        const uint64_t b = __ballot(tch);
+        if (tch) {
+          const int32_t pos = o + __popcll(b & clt);
+          if (base + pos < limit) {
+            ocol[base + pos] = c0 + x;
+            oval[base + pos] = S::from_acc(acc[x]);
+          }
+        }
+        o += __popcll(b);
+      }
+    };
+    if (pc + 1 < passes) {
+      // not the last chunk: park its entries in the staging space
+      emit(scol, sval, nnew, stage_n);
+      nnew += ctot;
+      grp.sync();
+      continue;
+    }
+    // last chunk: the row length is known, so the row goes straight to C
     nnew += ctot;
+    if (nnew > stage_n) {
+      if (tid == 0) atomicOr(R.err, 8);
+      fault = true;
+      break;
+    }
+    if (changed) {
+      int64_t dest = ooff;
+      int32_t ncap = 0;
+      if (nnew > R.c_cap[i]) {
+        ncap = slack_cap(nnew);
+        dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
+        if (dest < 0) {
+          if (tid == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
+          parked = true;
+          break;
+        }
+      }
+      // earlier chunks from the staging space (4 loads in flight per lane)
+      const int32_t staged = nnew - ctot;
+      for (int32_t e0 = tid; e0 < staged; e0 += 4 * DENSE_WG) {
+        int32_t sc[4];
+        V sv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t e = e0 + u * DENSE_WG;
+          sc[u] = e < staged ? scol[e] : 0;
+          sv[u] = e < staged ? sval[e] : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t e = e0 + u * DENSE_WG;
+          if (e < staged) {
+            R.c_col[dest + e] = sc[u];
+            ((V*)R.c_val)[dest + e] = sv[u];
+          }
+        }
+      }
+      emit(R.c_col + dest, (V*)R.c_val + dest, staged, nnew);
+      if (tid == 0) {
+        R.c_len[i] = nnew;
+        if (ncap) {
+          R.c_off[i] = dest;
+          R.c_cap[i] = ncap;
+        }
+      }
+    }
     grp.sync();
   }
-  if (nnew > stage_n) {
-    if (tid == 0) atomicOr(R.err, 8);
-    break;
-  }
-  if (changed) {
-    int64_t dest = ooff;
-    int32_t ncap = 0;
-    if (nnew > R.c_cap[i]) {
-      ncap = slack_cap(nnew);
-      dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
-      if (dest < 0) {
-        if (tid == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
-        continue;
-      }
-    }
-    for (int32_t e = tid; e < nnew; e += DENSE_WG) {
-      R.c_col[dest + e] = scol[e];
-      ((V*)R.c_val)[dest + e] = sval[e];
-    }
-    if (tid == 0) {
-      R.c_len[i] = nnew;
-      if (ncap) {
-        R.c_off[i] = dest;
-        R.c_cap[i] = ncap;
-      }
-    }
-  }
+  if (fault) break;
+  if (parked) continue;
   if (tid == 0) {
     R.chg[q] = changed ? 1 : 0;
     row_stat(R, q, d, flops, nnew, olen, old_read, changed ? nnew : 0);
