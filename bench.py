@@ -328,6 +328,59 @@ def bench_serve(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_sweep(args):
+    """Per batch size on the default workload: ms per step of the row path,
+    of the entry-granular path, and of a static recompute, same GPU."""
+    import torch
+    from paper_2202_08808_amd import dsg
+    from paper_2202_08808_amd import inputs as I
+    out = []
+    for b in args.sweep:
+        w = make_workload(args.workload, b, args.steps + args.warmup)
+        dev = torch.device("cuda:0")
+        batches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (q.rows, q.cols, q.vals, q.ops))
+                   for q in w.batches_A]
+        rec = {"batch": b}
+        for path in ("row", "entry"):
+            ctx = dsg.Context(0, stream=torch.cuda.current_stream(dev))
+            t = ctx.get_tuning()
+            t.update_path = 1 if path == "row" else 2
+            ctx.set_tuning(t)
+            A = dsg.Matrix.from_csr(ctx, w.A, w.semiring)
+            P = dsg.Product(ctx, A, A)
+            ts = []
+            for k in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                A.apply(*batches[k])
+                P.update()
+                torch.cuda.synchronize()
+                if k >= args.warmup:
+                    ts.append(time.perf_counter() - t0)
+            st = P.stats()
+            rec[path + "_ms"] = round(float(np.median(ts)) * 1e3, 4)
+            if path == "entry":
+                rec["entry_taken"] = bool(st["path"] == 1)
+                rec["lost_per_batch"] = st["lost"]
+                rec["terms_per_batch"] = st["terms"]
+                ts = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    P.recompute_static()
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                rec["static_ms"] = round(float(np.median(ts)) * 1e3, 4)
+            P.destroy()
+            A.destroy()
+            ctx.close()
+        rec["speedup_row"] = round(rec["static_ms"] / rec["row_ms"], 3)
+        rec["speedup_entry"] = round(rec["static_ms"] / rec["entry_ms"], 3)
+        log(f"[sweep] {json.dumps(rec)}")
+        out.append(rec)
+    print(json.dumps({"workload": args.workload, "sweep": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +390,8 @@ def main():
     ap.add_argument("--instances", type=int, default=64, help="batched workload: number of instances")
     ap.add_argument("--max-scale", type=int, default=16, help="batched workload: largest R-MAT scale")
     ap.add_argument("--batch", type=int, default=10000)
+    ap.add_argument("--sweep", type=int, nargs="*", default=None,
+                    help="time the row and entry-granular paths and a static recompute at these batch sizes")
     ap.add_argument("--serve-scale", type=int, default=21, help="serve workload: log2 of the ER rows")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-calib", type=int, default=300)
@@ -357,6 +412,8 @@ def main():
         return bench_batched(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.sweep:
+        return bench_sweep(args)
 
     import torch
     from paper_2202_08808_amd import dsg

@@ -126,6 +126,10 @@ typedef struct {
                               it needs at most this many column passes, else a global-memory hash */
   int32_t force_bin;       /* -1: automatic; 0..7 group bin; 8 dense; 9 global hash (for tests;
                               a group bin is only used for rows that fit it) */
+  int32_t update_path;     /* dynamic updates of C = A*A over (min,+) or int64 (+,x):
+                              0 automatic (entry-granular while the changed products are few
+                              next to nnz(C), else whole affected rows); 1 always whole rows;
+                              2 entry-granular whenever it applies.  Same results every way. */
 } dsg_tuning;
 dsg_status dsg_ctx_get_tuning(const dsg_ctx* ctx, dsg_tuning* t);
 /* t == NULL restores the defaults.  DSG_E_ARG for thresholds outside the
@@ -214,6 +218,12 @@ typedef struct {
   int64_t nnz_old;      /* entries of those rows before it */
   int64_t bin_rows[10]; /* rows per accumulator bin (8 group bins, dense, global hash) */
   int64_t bin_flops[10];
+  int32_t path;         /* 0: affected rows recomputed; 1: entry-granular */
+  int32_t pad;
+  int64_t terms;        /* entry-granular: changed products a_ik * b_kj enumerated */
+  int64_t entries;      /* entry-granular: entries of C with changed products */
+  int64_t lost;         /* entry-granular: entries recomputed because their best term got worse
+                           (min-plus) or lost a contributor (plus-times) */
 } dsg_update_stats;
 dsg_status dsg_prod_stats(const dsg_prod* p, dsg_update_stats* s);
 

@@ -148,6 +148,7 @@ static void default_tuning(dsg_tuning* t) {
   for (int b = 0; b < 8; ++b) t->group_ub[b] = 32 << b;
   t->dense_max_passes = 4;
   t->force_bin = -1;
+  t->update_path = 0;
 }
 
 // host-side check of a CSR: row_ptr monotone from 0, columns in range, no
@@ -323,6 +324,7 @@ extern "C" dsg_status dsg_ctx_set_tuning(dsg_ctx* ctx, const dsg_tuning* t) {
   }
   if (t->dense_max_passes < 0) return fail(ctx, DSG_E_ARG, "dense_max_passes < 0");
   if (t->force_bin < -1 || t->force_bin > 9) return fail(ctx, DSG_E_ARG, "force_bin outside [-1, 9]");
+  if (t->update_path < 0 || t->update_path > 2) return fail(ctx, DSG_E_ARG, "update_path outside [0, 2]");
   ctx->c.tuning = *t;
   return DSG_OK;
 }
@@ -648,6 +650,7 @@ static std::vector<dsg_tuning> tuning_candidates() {
         if (skip_small) t.group_ub[0] = t.group_ub[1] = 0;
         t.dense_max_passes = passes;
         t.force_bin = -1;
+        t.update_path = 0;
         out.push_back(t);
       }
   return out;

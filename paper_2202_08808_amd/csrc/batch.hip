@@ -286,6 +286,9 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   DSG_HIP(hipMemcpyAsync(tops.data(), b->d_tops, tops.size() * 8, hipMemcpyDeviceToHost, main));
   DSG_HIP(hipStreamSynchronize(main));
   for (size_t i = 0; i < b->mats.size(); ++i) b->mats[i]->h_top_ub = tops[i];
+  // these applies keep no log: the entry-granular update does not follow them
+  for (const DBatchSet& st : sets)
+    if (st.n > 0) st.m->apply_seq++;
   b->replay_ms += ms_since(t0);
   t0 = std::chrono::steady_clock::now();
   for (size_t j = 0; j < np; ++j) {
@@ -305,6 +308,8 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     } else {
       counts[j] = (int32_t)o[0];
     }
+    p->a_seq = p->A->apply_seq;
+    p->b_seq = p->B->apply_seq;
   }
   b->finish_ms += ms_since(t0);
   return DSG_OK;

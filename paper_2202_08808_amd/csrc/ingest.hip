@@ -22,13 +22,17 @@
 //      space; changed rows get the matrix's new epoch, and every structural
 //      change is emitted for the transpose index, which is updated by the
 //      same pipeline.
+#include <algorithm>
+
 #include "internal.h"
 #include "kernel_common.h"
 
 namespace {
 
 constexpr uint8_t K_KEEP = 0, K_SET = 1, K_DEL = 2;
-constexpr uint8_t C_NOP = 0, C_INS = 1, C_DEL = 2, C_OVR = 3;
+constexpr uint8_t OP_GUARD_ONLY = 3;  // internal op of mat_apply_sorted_add: no value
+constexpr int PLAN_LDS = 1024;        // update columns of a row held in LDS by the plan
+constexpr uint8_t C_NOP = UPD_NOP, C_INS = UPD_INS, C_DEL = UPD_DEL, C_OVR = UPD_OVR, C_LOST = UPD_LOST;
 
 int bits_for(int64_t n) {
   int b = 0;
@@ -82,11 +86,13 @@ struct Uniq {
   int32_t* slot;
   uint8_t* code;
   uint64_t* fin;  // raw bits of the final value
+  uint64_t* old;  // raw bits of the value before (0 when absent)
   int32_t* urow;
   int32_t* row_first;
   int32_t* plen;
   int32_t* pcap;
   uint8_t* pchg;
+  uint8_t* pdel;  // the row loses entries (decided by the plan)
   int32_t* holes;
   int32_t* mv_src;
   int32_t* mv_u;
@@ -131,7 +137,13 @@ __global__ void k_fold(const uint64_t* keys, const uint32_t* idx, int64_t n, int
     ++e;
   }
   U.key[u] = k;
-  if (last < 0) {
+  if (ops[idx[t]] == OP_GUARD_ONLY) {
+    // a key that only carries a guard (unique keys of a sorted ADD input)
+    U.kind[u] = K_KEEP;
+    U.val[u] = 0;
+    U.add_start[u] = (int32_t)t;
+    U.add_cnt[u] = 0;
+  } else if (last < 0) {
     U.kind[u] = K_KEEP;
     U.val[u] = 0;
     U.add_start[u] = (int32_t)t;
@@ -162,56 +174,144 @@ __device__ inline int32_t find_update(const uint64_t* ukey, int32_t u0, int32_t 
   return (lo < u1 && (int32_t)(ukey[lo] & cmask) == c) ? lo : -1;
 }
 
+// Optional guard of an update (sorted ADD updates of a product, see
+// mat_apply_sorted_add): entries it marks are listed as lost, not changed.
+struct Guard {
+  const uint64_t* key = nullptr;  // ordered key of the guarded value, per unique update
+  const uint8_t* flag = nullptr;  // 2: guarded by key; 4: always lost when present
+  uint64_t* lost_key = nullptr;
+  int32_t* lost_slot = nullptr;
+  unsigned long long* nlost = nullptr;
+  int64_t cap = 0;
+};
+
+// The outcome of unique update u of a row whose slot (or -1) the plan found:
+// fold its chain onto the stored value, record code / final / previous
+// value, and apply the guard (listed as lost: lost_slot set).
 template <int SR, int VSZ>
-__global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint64_t cmask, const uint32_t* idx,
-                                              const void* vals, Uniq U, unsigned long long* demand) {
+__device__ inline uint8_t plan_update(const DMat& m, int64_t off, const uint32_t* idx, const void* vals,
+                                      const Uniq& U, const Guard& G, int32_t u, int32_t& lost_slot) {
   using S = typename SemOf<SR>::S;
   using V = typename S::V;
+  const int32_t s = U.slot[u];
+  const bool present = s >= 0;
+  const uint64_t old = present ? load_raw<VSZ>(m.val, off + s) : 0;
+  uint64_t v = old;
+  bool ex = present;
+  const uint8_t kind = U.kind[u];
+  if (kind == K_SET) {
+    ex = true;
+    v = U.val[u];
+  } else if (kind == K_DEL) {
+    ex = false;
+  }
+  const int32_t a0 = U.add_start[u], a1 = a0 + U.add_cnt[u];
+  for (int32_t q = a0; q < a1; ++q) {
+    const uint64_t x = load_raw<VSZ>(vals, idx[q]);
+    if (ex) v = to_raw<V>(S::add(from_raw<V>(v), from_raw<V>(x)));
+    else v = x;
+    ex = true;
+  }
+  uint8_t code;
+  if (present) code = ex ? ((VSZ && v != old) ? C_OVR : C_NOP) : C_DEL;
+  else code = ex ? C_INS : C_NOP;
+  if constexpr (VSZ > 0) {
+    if (G.flag && present) {
+      const uint8_t gf = G.flag[u];
+      bool lost = (gf & 4) != 0;
+      if (gf & 2) {
+        // (min,+): the stored value came from a term that got worse and
+        // nothing new beats or ties it
+        const uint32_t kc = f32_key(__uint_as_float((uint32_t)old));
+        const bool beats = a1 > a0 && f32_key(__uint_as_float((uint32_t)load_raw<VSZ>(vals, idx[a0]))) <= kc;
+        lost = lost || ((uint64_t)kc == G.key[u] && !beats);
+      }
+      if (lost) {
+        code = C_LOST;
+        v = old;
+        lost_slot = s;
+      }
+    }
+  }
+  U.code[u] = code;
+  U.fin[u] = v;
+  U.old[u] = present ? old : 0;
+  return code;
+}
+
+// list this wavefront's lost entries with one atomic (all lanes call it)
+__device__ inline void emit_lost(const Uniq& U, const Guard& G, int32_t u, uint8_t code, int32_t lost_slot,
+                                 int lane) {
+  if (!G.flag) return;
+  const bool l = code == C_LOST;
+  const uint64_t lb = __ballot(l);
+  if (!lb) return;
+  unsigned long long p0 = 0;
+  if (lane == 0) p0 = atomicAdd(G.nlost, (unsigned long long)__popcll(lb));
+  p0 = __shfl(p0, 0, 64);
+  if (l) {
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    const unsigned long long p = p0 + __popcll(lb & lt);
+    if ((int64_t)p < G.cap) {
+      G.lost_key[p] = U.key[u];
+      G.lost_slot[p] = lost_slot;
+    }
+  }
+}
+
+template <int SR, int VSZ>
+__global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint64_t cmask, const uint32_t* idx,
+                                              const void* vals, Uniq U, unsigned long long* demand, Guard G) {
+  // the row's update columns (sorted) in LDS, per wavefront, when they fit
+  __shared__ int32_t lcol[4][PLAN_LDS];
   const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (r >= *d_nR) return;
+  int32_t* lk = lcol[(threadIdx.x >> 6) & 3];
   const int32_t i = U.urow[r];
   const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+  const int32_t nu = u1 - u0;
+  if (nu > PLAN_LDS) return;  // a heavy row: k_plan_heavy
+  const bool in_lds = true;
   const int64_t off = m.row_off[i];
   const int32_t len = m.row_len[i], cap = m.row_cap[i];
-  for (int32_t u = u0 + lane; u < u1; u += 64) U.slot[u] = -1;
+  for (int32_t u = u0 + lane; u < u1; u += 64) {
+    U.slot[u] = -1;
+    if (in_lds) lk[u - u0] = (int32_t)(U.key[u] & cmask);
+  }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
-  for (int32_t s = lane; s < len; s += 64) {
-    int32_t u = find_update(U.key, u0, u1, cmask, m.col[off + s]);
-    if (u >= 0) U.slot[u] = s;
+  // stream the row once (4 loads in flight per lane) and find each slot's update
+  for (int32_t s0 = lane; s0 < len; s0 += 256) {
+    int32_t cc[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) cc[v] = s0 + v * 64 < len ? m.col[off + s0 + v * 64] : -1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (cc[v] < 0) continue;
+      int32_t u;
+      if (in_lds) {
+        int32_t lo = 0, hi = nu;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (lk[mid] < cc[v]) lo = mid + 1;
+          else hi = mid;
+        }
+        u = (lo < nu && lk[lo] == cc[v]) ? u0 + lo : -1;
+      } else {
+        u = find_update(U.key, u0, u1, cmask, cc[v]);
+      }
+      if (u >= 0) U.slot[u] = s0 + v * 64;
+    }
   }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
   int32_t n_del = 0, n_ins = 0, n_ovr = 0;
   for (int32_t base = u0; base < u1; base += 64) {
-    int32_t u = base + lane;
-    uint8_t code = C_NOP;
-    if (u < u1) {
-      int32_t s = U.slot[u];
-      bool present = s >= 0;
-      uint64_t old = present ? load_raw<VSZ>(m.val, off + s) : 0;
-      uint64_t v = old;
-      bool ex = present;
-      uint8_t kind = U.kind[u];
-      if (kind == K_SET) {
-        ex = true;
-        v = U.val[u];
-      } else if (kind == K_DEL) {
-        ex = false;
-      }
-      int32_t a0 = U.add_start[u], a1 = a0 + U.add_cnt[u];
-      for (int32_t q = a0; q < a1; ++q) {
-        uint64_t x = load_raw<VSZ>(vals, idx[q]);
-        if (ex) v = to_raw<V>(S::add(from_raw<V>(v), from_raw<V>(x)));
-        else v = x;
-        ex = true;
-      }
-      if (present) code = ex ? ((VSZ && v != old) ? C_OVR : C_NOP) : C_DEL;
-      else code = ex ? C_INS : C_NOP;
-      U.code[u] = code;
-      U.fin[u] = v;
-    }
+    const int32_t u = base + lane;
+    int32_t lost_slot = -1;
+    const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u, lost_slot) : C_NOP;
+    emit_lost(U, G, u, code, lost_slot, lane);
     n_del += __popcll(__ballot(code == C_DEL));
     n_ins += __popcll(__ballot(code == C_INS));
     n_ovr += __popcll(__ballot(code == C_OVR));
@@ -222,6 +322,7 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
     bool reloc = nl > cap;
     U.plen[r] = nl;
     U.pchg[r] = chg ? 1 : 0;
+    U.pdel[r] = n_del > 0 ? 1 : 0;
     U.pcap[r] = reloc ? slack_cap(nl) : 0;
     if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
   }
@@ -230,7 +331,8 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
 template <int SR, int VSZ>
 __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uint64_t cmask, int cbits,
                                                 Uniq U, const uint32_t* d_epoch, int tbits, uint64_t* dkey,
-                                                uint8_t* dop, unsigned long long* d_ndelta, int* err) {
+                                                uint8_t* dop, void* dval, unsigned long long* d_ndelta,
+                                                int64_t dcap, int* err) {
   const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
   if (r >= *d_nR) return;
@@ -242,7 +344,63 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
   const int32_t nl = U.plen[r];
   const int32_t ncap = U.pcap[r];
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  if (ncap == 0) {
+  // rows that lose no entry take the ordered paths; the heavy ones of those
+  // belong to k_commit_heavy (which runs after this kernel and must not see
+  // the rows handled here: it goes by the plan, not by the row's length)
+  const bool nodel = !U.pdel[r];
+  if (nodel && u1 - u0 > PLAN_LDS) return;
+  if (nodel) {
+    // ---- nothing deleted: the entries keep their order (moved as a block
+    // when the row outgrows its space), overwrites go to the planned slots,
+    // inserts after the row's entries ----
+    int64_t dest = off;
+    if (ncap) {
+      unsigned long long no = 0;
+      if (lane == 0) no = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
+      no = __shfl(no, 0, 64);
+      if ((int64_t)no + ncap > m.pool_cap) {
+        if (lane == 0) atomicOr(err, 1);
+        return;
+      }
+      dest = (int64_t)no;
+      for (int32_t s0 = lane; s0 < len; s0 += 256) {
+        int32_t cc[4];
+        uint64_t vv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int32_t t = s0 + v * 64;
+          cc[v] = t < len ? m.col[off + t] : 0;
+          vv[v] = t < len ? load_raw<VSZ>(m.val, off + t) : 0;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int32_t t = s0 + v * 64;
+          if (t < len) {
+            m.col[dest + t] = cc[v];
+            store_raw<VSZ>(m.val, dest + t, vv[v]);
+          }
+        }
+      }
+    }
+    int32_t k = 0;
+    for (int32_t base = u0; base < u1; base += 64) {
+      const int32_t u = base + lane;
+      const uint8_t code = u < u1 ? U.code[u] : C_NOP;
+      if (code == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
+      const bool ins = code == C_INS;
+      const uint64_t ib = __ballot(ins);
+      if (ins) {
+        const int64_t dst = dest + len + k + __popcll(ib & lt);
+        m.col[dst] = (int32_t)(U.key[u] & cmask);
+        store_raw<VSZ>(m.val, dst, U.fin[u]);
+      }
+      k += __popcll(ib);
+    }
+    if (ncap && lane == 0) {
+      m.row_off[i] = dest;
+      m.row_cap[i] = ncap;
+    }
+  } else if (ncap == 0) {
     // ---- in place ----
     int32_t H = 0, Mc = 0;
     for (int32_t base = 0; base < len; base += 64) {
@@ -341,23 +499,206 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
     m.row_len[i] = nl;
     m.row_epoch[i] = *d_epoch;
   }
-  // structural changes for the transpose index: key (col << tbits) | row
+  // changes for the transpose index: key (col << tbits) | row, with the value
   if (dkey) {
     for (int32_t base = u0; base < u1; base += 64) {
       int32_t u = base + lane;
       uint8_t code = u < u1 ? U.code[u] : C_NOP;
-      bool emit = code == C_INS || code == C_DEL;
+      bool emit = code == C_INS || code == C_DEL || code == C_OVR;
       uint64_t eb = __ballot(emit);
       unsigned long long pos = 0;
       if (lane == 0 && eb) pos = atomicAdd(d_ndelta, (unsigned long long)__popcll(eb));
       pos = __shfl(pos, 0, 64);
       if (emit) {
         int64_t q = (int64_t)pos + __popcll(eb & lt);
+        if (q >= dcap) {  // more changes than updates: an internal error, never written past the list
+          atomicOr(err, 4);
+          continue;
+        }
         uint64_t j = U.key[u] & cmask;
         dkey[q] = (j << tbits) | (uint64_t)(uint32_t)i;
-        dop[q] = code == C_INS ? DSG_OP_SET : DSG_OP_DELETE;
+        dop[q] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
+        store_raw<VSZ>(dval, q, U.fin[u]);
       }
     }
+  }
+}
+
+// Heavy rows (more than PLAN_LDS updates): one 512-lane workgroup per row,
+// rows taken in turn by a persistent grid.  The row's update columns go into
+// an LDS hash (in runs of HEAVY_SLOTS/2 updates when there are more), the row
+// is streamed once per run, and the outcomes are decided by all 8 waves.
+constexpr int HEAVY_WG = 512;
+constexpr int HEAVY_SLOTS = 16384;
+
+template <int SR, int VSZ>
+__global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* d_nR, uint64_t cmask,
+                                                         const uint32_t* idx, const void* vals, Uniq U,
+                                                         unsigned long long* demand, Guard G) {
+  __shared__ int32_t hk[HEAVY_SLOTS];
+  __shared__ int32_t hu[HEAVY_SLOTS];
+  __shared__ int32_t cnt[3];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t nR = *d_nR;
+  for (int64_t r = blockIdx.x; r < nR; r += gridDim.x) {
+    const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+    if (u1 - u0 <= PLAN_LDS) continue;
+    const int32_t i = U.urow[r];
+    const int64_t off = m.row_off[i];
+    const int32_t len = m.row_len[i], cap = m.row_cap[i];
+    for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) U.slot[u] = -1;
+    if (tid < 3) cnt[tid] = 0;
+    for (int32_t c0 = u0; c0 < u1; c0 += HEAVY_SLOTS / 2) {
+      const int32_t c1 = min(u1, c0 + HEAVY_SLOTS / 2);
+      for (int x = tid; x < HEAVY_SLOTS; x += HEAVY_WG) hk[x] = -1;
+      __syncthreads();
+      for (int32_t u = c0 + tid; u < c1; u += HEAVY_WG) {
+        const int32_t col = (int32_t)(U.key[u] & cmask);
+        uint32_t h = hash_col(col) & (HEAVY_SLOTS - 1);
+        while (atomicCAS(&hk[h], -1, col) != -1) h = (h + 1) & (HEAVY_SLOTS - 1);
+        hu[h] = u;
+      }
+      __syncthreads();
+      for (int32_t s0 = tid; s0 < len; s0 += 4 * HEAVY_WG) {
+        int32_t cc[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cc[v] = s0 + v * HEAVY_WG < len ? m.col[off + s0 + v * HEAVY_WG] : -1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (cc[v] < 0) continue;
+          uint32_t h = hash_col(cc[v]) & (HEAVY_SLOTS - 1);
+          for (;;) {
+            const int32_t x = hk[h];
+            if (x == cc[v]) {
+              U.slot[hu[h]] = s0 + v * HEAVY_WG;
+              break;
+            }
+            if (x == -1) break;
+            h = (h + 1) & (HEAVY_SLOTS - 1);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    int32_t nd = 0, ni = 0, no = 0;
+    for (int32_t base = u0 + wv * 64; base < u1; base += HEAVY_WG) {
+      const int32_t u = base + lane;
+      int32_t lost_slot = -1;
+      const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u, lost_slot) : C_NOP;
+      emit_lost(U, G, u, code, lost_slot, lane);
+      nd += __popcll(__ballot(code == C_DEL));
+      ni += __popcll(__ballot(code == C_INS));
+      no += __popcll(__ballot(code == C_OVR));
+    }
+    if (lane == 0) {
+      atomicAdd(&cnt[0], nd);
+      atomicAdd(&cnt[1], ni);
+      atomicAdd(&cnt[2], no);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int32_t nl = len - cnt[0] + cnt[1];
+      const bool chg = (cnt[0] + cnt[1] + cnt[2]) > 0;
+      const bool reloc = nl > cap;
+      U.plen[r] = nl;
+      U.pchg[r] = chg ? 1 : 0;
+      U.pdel[r] = cnt[0] > 0 ? 1 : 0;
+      U.pcap[r] = reloc ? slack_cap(nl) : 0;
+      if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
+    }
+    __syncthreads();
+  }
+}
+
+// Commit of heavy rows without deletions (k_commit takes heavy rows with
+// deletions): move as a block if needed, overwrite at the planned slots,
+// append the inserts, emit the transpose changes.
+template <int SR, int VSZ>
+__global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t* d_nR, uint64_t cmask, Uniq U,
+                                                           const uint32_t* d_epoch, int tbits, uint64_t* dkey,
+                                                           uint8_t* dop, void* dval, unsigned long long* d_ndelta,
+                                                           int64_t dcap, int* err) {
+  __shared__ int32_t wc[HEAVY_WG / 64];
+  __shared__ unsigned long long dest_s;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t nR = *d_nR;
+  for (int64_t r = blockIdx.x; r < nR; r += gridDim.x) {
+    const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+    if (u1 - u0 <= PLAN_LDS || !U.pchg[r]) continue;
+    const int32_t i = U.urow[r];
+    const int64_t off = m.row_off[i];
+    const int32_t len = m.row_len[i];
+    const int32_t nl = U.plen[r];
+    const int32_t ncap = U.pcap[r];
+    if (U.pdel[r]) continue;  // the row loses entries: k_commit did it
+    int64_t dest = off;
+    if (ncap) {
+      if (tid == 0) dest_s = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
+      __syncthreads();
+      if ((int64_t)dest_s + ncap > m.pool_cap) {
+        if (tid == 0) atomicOr(err, 1);
+        __syncthreads();
+        continue;
+      }
+      dest = (int64_t)dest_s;
+      for (int32_t t = tid; t < len; t += HEAVY_WG) {
+        m.col[dest + t] = m.col[off + t];
+        store_raw<VSZ>(m.val, dest + t, load_raw<VSZ>(m.val, off + t));
+      }
+      __syncthreads();
+    }
+    for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG)
+      if (U.code[u] == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
+    // inserts after the row's entries, in update order
+    int32_t k = 0;
+    for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+      const int32_t u = base + tid;
+      const bool ins = u < u1 && U.code[u] == C_INS;
+      const uint64_t ib = __ballot(ins);
+      if (lane == 0) wc[wv] = __popcll(ib);
+      __syncthreads();
+      int32_t before = 0, tot = 0;
+      for (int x = 0; x < HEAVY_WG / 64; ++x) {
+        if (x < wv) before += wc[x];
+        tot += wc[x];
+      }
+      if (ins) {
+        const int64_t dst = dest + len + k + before + __popcll(ib & lt);
+        m.col[dst] = (int32_t)(U.key[u] & cmask);
+        store_raw<VSZ>(m.val, dst, U.fin[u]);
+      }
+      k += tot;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      m.row_len[i] = nl;
+      m.row_epoch[i] = *d_epoch;
+      if (ncap) {
+        m.row_off[i] = dest;
+        m.row_cap[i] = ncap;
+      }
+    }
+    if (dkey) {
+      for (int32_t base = u0 + wv * 64; base < u1; base += HEAVY_WG) {
+        const int32_t u = base + lane;
+        const uint8_t code = u < u1 ? U.code[u] : C_NOP;
+        const bool emit = code == C_INS || code == C_DEL || code == C_OVR;
+        const uint64_t eb = __ballot(emit);
+        unsigned long long pos = 0;
+        if (lane == 0 && eb) pos = atomicAdd(d_ndelta, (unsigned long long)__popcll(eb));
+        pos = __shfl(pos, 0, 64);
+        if (emit && (int64_t)pos + __popcll(eb & lt) >= dcap) atomicOr(err, 4);
+        if (emit && (int64_t)pos + __popcll(eb & lt) < dcap) {
+          const int64_t q = (int64_t)pos + __popcll(eb & lt);
+          const uint64_t j = U.key[u] & cmask;
+          dkey[q] = (j << tbits) | (uint64_t)(uint32_t)i;
+          dop[q] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
+          store_raw<VSZ>(dval, q, U.fin[u]);
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -395,6 +736,8 @@ struct Work {
   int* err;
   uint64_t* dkey;
   uint8_t* dop;
+  void* dval;
+  uint8_t* allops;  // presorted ADD input: one ADD op per entry
 };
 
 size_t work_bytes(int64_t n, bool deltas) {
@@ -402,7 +745,7 @@ size_t work_bytes(int64_t n, bool deltas) {
   return Carve::need({N * 8, N * 4, radix_scratch_bytes(n), N * 8, N * 8, N * 8, N * 8, 64, 64,
                       scan_scratch_bytes(n), N * 8, N, N * 8, N * 4, N * 4, N * 4, N, N * 8, N * 4,
                       (N + 1) * 4, N * 4, N * 4, N, N * 4, N * 4, N * 4, 64, 64, 64,
-                      deltas ? N * 8 : 0, deltas ? N : 0});
+                      deltas ? N * 8 : 0, deltas ? N : 0, deltas ? N * 8 : 0, N * 8, N, N});
 }
 
 Work carve_work(void* base, int64_t n, bool deltas) {
@@ -440,6 +783,10 @@ Work carve_work(void* base, int64_t n, bool deltas) {
   w.err = cv.take<int>(16);
   w.dkey = deltas ? cv.take<uint64_t>(N) : nullptr;
   w.dop = deltas ? cv.take<uint8_t>(N) : nullptr;
+  w.dval = deltas ? (void*)cv.take<uint64_t>(N) : nullptr;
+  w.U.old = cv.take<uint64_t>(N);
+  w.allops = cv.take<uint8_t>(N);
+  w.U.pdel = cv.take<uint8_t>(N);
   return w;
 }
 
@@ -453,12 +800,15 @@ __global__ void k_zero_counters(unsigned long long* a, unsigned long long* b, in
 
 template <int SR, int VSZ>
 void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, const void* vals, int tbits,
-                        bool graph) {
+                        bool graph, const Guard& G) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   unsigned nb = blocks_for(n * 64, 256);
+  const unsigned nh = (unsigned)std::max(1, c->num_cus);
   hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
-                     w.demand);
+                     w.demand, G);
+  hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nh), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
+                     w.demand, G);
   if (!graph) {
     // the one host round trip: how much pool space moved rows need
     unsigned long long* h = (unsigned long long*)c->pinned;
@@ -477,24 +827,29 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
       // of its length: a row planned to grow in place may no longer fit, so
       // plan again against the new capacities
       hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, w.demand);
+      if (G.nlost) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, G.nlost);
       hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
-                         w.demand);
+                         w.demand, G);
+      hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nh), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals,
+                         w.U, w.demand, G);
     }
   }
   // (graph mode: the caller reserved the worst case, see apply_headroom)
   hipLaunchKernelGGL((k_commit<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, cbits, w.U,
-                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.ndelta, w.err);
+                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, w.ndelta, n, w.err);
+  hipLaunchKernelGGL((k_commit_heavy<SR, VSZ>), dim3(nh), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.U,
+                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, w.ndelta, n, w.err);
 }
 
 // Steps 2-6 on keys/idx already filled (n entries, sentinel-padded allowed).
 void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint8_t* ops, const void* vals,
-              bool graph) {
+              bool graph, bool presorted = false, const Guard& G = Guard()) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   int cbits = bits_for(m->ncols);
   uint64_t sentinel = 1ull << key_bits;
   uint64_t cmask = (1ull << cbits) - 1;
-  radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s);
+  if (!presorted) radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s);
   unsigned nb = blocks_for(n, 256);
   hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, s, w.keys, n, cbits, sentinel, w.kh, w.rh);
   exclusive_scan_i64(w.kh, w.ukpos, n, w.nU, w.scan, s);
@@ -513,10 +868,10 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
                        w.ukpos, w.rh, w.urpos, w.nU, w.nR, w.U);
   int tbits = bits_for(m->nrows);
   switch (m->sr) {
-    case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph); break;
-    case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph); break;
-    case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph); break;
-    default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph); break;
+    case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
+    case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
+    case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
+    default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
   }
   DSG_HIP(hipGetLastError());
 }
@@ -537,11 +892,79 @@ void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const
     // the emitted deltas occupy [0, ndelta); the rest of the n slots hold the sentinel
     hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, w.ndelta, 1ull << tk, wt->keys,
                        wt->idx, n);
-    run_core(t, *wt, n, tk, true, w.dop, nullptr, graph);
+    run_core(t, *wt, n, tk, true, w.dop, t->vsz ? w.dval : nullptr, graph);
+  }
+}
+
+// Keep the unique keys of this apply with their values before and after and
+// their outcomes: the entry-granular product update reads them.
+void keep_log(DMat* m, Work& w, int64_t n) {
+  Ctx* c = m->ctx;
+  hipStream_t s = c->stream;
+  if (m->log_cap < n) {
+    ctx_free(c, m->log_key, (size_t)m->log_cap * 8);
+    ctx_free(c, m->log_old, (size_t)m->log_cap * 8);
+    ctx_free(c, m->log_new, (size_t)m->log_cap * 8);
+    ctx_free(c, m->log_code, (size_t)m->log_cap);
+    m->log_key = m->log_old = m->log_new = nullptr;
+    m->log_code = nullptr;
+    m->log_cap = 0;
+    const int64_t cap = std::max<int64_t>(n + n / 2, 1024);
+    m->log_key = (uint64_t*)ctx_alloc(c, (size_t)cap * 8);
+    m->log_old = (uint64_t*)ctx_alloc(c, (size_t)cap * 8);
+    m->log_new = (uint64_t*)ctx_alloc(c, (size_t)cap * 8);
+    m->log_code = (uint8_t*)ctx_alloc(c, (size_t)cap);
+    m->log_cap = cap;
+  }
+  if (!m->d_log_n) m->d_log_n = (int64_t*)ctx_alloc(c, 64);
+  DSG_HIP(hipMemcpyAsync(m->log_key, w.U.key, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+  DSG_HIP(hipMemcpyAsync(m->log_old, w.U.old, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+  DSG_HIP(hipMemcpyAsync(m->log_new, w.U.fin, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+  DSG_HIP(hipMemcpyAsync(m->log_code, w.U.code, (size_t)n, hipMemcpyDeviceToDevice, s));
+  DSG_HIP(hipMemcpyAsync(m->d_log_n, w.nU, 8, hipMemcpyDeviceToDevice, s));
+}
+
+__global__ void k_ops_from_flags(const uint8_t* flag, int64_t n, uint8_t* ops, const uint64_t* keys,
+                                 uint64_t* wkeys, uint32_t* idx) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    ops[t] = (flag[t] & 1) ? DSG_OP_ADD : OP_GUARD_ONLY;
+    wkeys[t] = keys[t];
+    idx[t] = (uint32_t)t;
   }
 }
 
 }  // namespace
+
+int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, const uint64_t* guard,
+                             const uint8_t* flag, int64_t n, uint64_t* lost_key, int32_t* lost_slot,
+                             int64_t lost_cap, unsigned long long* d_nlost) {
+  DSG_REQUIRE(!m->tidx, DSG_E_STATE, "internal: sorted ADD apply on a matrix with a transpose");
+  Ctx* c = m->ctx;
+  hipStream_t s = c->stream;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_nlost);
+  if (n == 0) return 0;
+  Work w = carve_work(ctx_scratch(c, work_bytes(n, false)), n, false);
+  hipLaunchKernelGGL(k_ops_from_flags, dim3(blocks_for(n, 256)), dim3(256), 0, s, flag, n, w.allops, keys, w.keys,
+                     w.idx);
+  Guard G;
+  G.key = guard;
+  G.flag = flag;
+  G.lost_key = lost_key;
+  G.lost_slot = lost_slot;
+  G.nlost = d_nlost;
+  G.cap = lost_cap;
+  const int kbits = bits_for(m->ncols) + bits_for(m->nrows);
+  run_core(m, w, n, kbits, false, w.allops, vals, false, true, G);
+  unsigned long long* h = (unsigned long long*)c->pinned;
+  int* he = (int*)((char*)c->pinned + 64);
+  DSG_HIP(hipMemcpyAsync(h, d_nlost, 8, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipMemcpyAsync(he, w.err, 4, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  DSG_REQUIRE(he[0] == 0, DSG_E_DEVICE, "internal: pool overflow while applying product updates");
+  DSG_REQUIRE((int64_t)h[0] <= lost_cap, DSG_E_DEVICE, "internal: lost-entry list overflow");
+  return (int64_t)h[0];
+}
 
 size_t apply_work_bytes(int64_t n, bool deltas) { return work_bytes(n, deltas); }
 
@@ -594,6 +1017,7 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   Work wt;
   if (deltas) wt = carve_work(ctx_scratch2(c, work_bytes(n, false)), n, false);
   apply_pipeline(m, d_rows, d_cols, d_vals, d_ops, n, w, deltas ? &wt : nullptr, false);
+  keep_log(m, w, n);
   int* h = (int*)c->pinned;
   h[1] = 0;
   if (deltas) DSG_HIP(hipMemcpyAsync(h + 1, wt.err, 4, hipMemcpyDeviceToHost, s));
@@ -601,4 +1025,6 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   DSG_HIP(hipMemcpyAsync(h, w.err, 4, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(h[0] == 0 && h[1] == 0, DSG_E_DEVICE, "internal: pool overflow while applying a batch");
+  m->apply_seq++;
+  m->log_seq = m->apply_seq;
 }

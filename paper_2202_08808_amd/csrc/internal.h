@@ -44,6 +44,9 @@ __host__ __device__ inline int32_t slack_cap(int32_t len) {
 
 struct Ctx;
 
+// Outcome of one unique update key when it is applied to a row.
+enum : uint8_t { UPD_NOP = 0, UPD_INS = 1, UPD_DEL = 2, UPD_OVR = 3, UPD_LOST = 4 };
+
 // Device-resident dynamic matrix: every row owns a slot range
 // [row_off[i], row_off[i] + row_cap[i]) of the column/value pools and uses its
 // first row_len[i] slots, in no particular column order.  Rows that outgrow
@@ -64,9 +67,19 @@ struct DMat {
   uint32_t* d_epoch = nullptr;    // device: bumped by every apply (lives in the d_top block)
   int64_t h_top_ub = 0;           // host: upper bound of *d_top
   uint64_t version = 0;           // bumped whenever the pools are reallocated
-  DMat* tidx = nullptr;           // structure-only transpose index (rows = columns of this)
+  DMat* tidx = nullptr;           // transpose (rows = columns of this), same values
   int refs = 0;                   // products using this matrix
   bool counted = false;           // registered in ctx->objects
+  // log of the last plain apply: every unique key it touched, in key order,
+  // with the stored value before and after and the outcome (UPD_*)
+  uint64_t* log_key = nullptr;
+  uint64_t* log_old = nullptr;
+  uint64_t* log_new = nullptr;
+  uint8_t* log_code = nullptr;
+  int64_t* d_log_n = nullptr;     // device: entries in the log
+  int64_t log_cap = 0;
+  uint64_t apply_seq = 0;         // applies so far
+  uint64_t log_seq = 0;           // the apply whose log is held (0: none)
 };
 
 // Per-kernel timing record.
@@ -212,6 +225,16 @@ int* apply_err_ptr(void* work, int64_t n, bool deltas);
 int64_t apply_headroom(const DMat* m, int64_t n);
 void mat_apply_graph(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
                      const uint8_t* d_ops, int64_t n, void* work_main, void* work_tidx);
+// Apply n unique keys (row << colbits | col), sorted ascending, to m as ADD
+// updates: vals[u] is folded in with the semiring addition when flag[u] & 1
+// (else the key only carries a guard).  An entry present in m is left
+// unchanged and listed as lost -- (key, row-relative slot), at most lost_cap,
+// count in *d_nlost -- when flag[u] & 4, or when flag[u] & 2 and its stored
+// value has the ordered key guard[u] while vals[u] (if any) is strictly
+// larger.  Returns the number of lost entries.  m must have no transpose.
+int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, const uint64_t* guard,
+                             const uint8_t* flag, int64_t n, uint64_t* lost_key, int32_t* lost_slot,
+                             int64_t lost_cap, unsigned long long* d_nlost);
 // Device validation of a batch: returns dsg_status.
 dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols,
                                  const uint8_t* d_ops, int64_t n);
@@ -237,6 +260,11 @@ struct DProd {
   int64_t last_c_demand = 0;      // C pool and arena needs of the last plain-path run
   int64_t last_arena_demand = 0;
   int64_t last_c_growth = 0;      // C pool slots the last batched run took
+  uint64_t a_seq = 0, b_seq = 0;  // applies of A and B that C reflects
+  void* ews = nullptr;            // workspace of the entry-granular path
+  size_t ews_bytes = 0;
+  void* srt = nullptr;            // column-sorted copy of A (entry-granular path)
+  size_t srt_bytes = 0;
   int refs = 0;                   // batched executors and servers using this product
 };
 
@@ -244,6 +272,11 @@ DProd* prod_create(Ctx* c, DMat* A, DMat* B);
 void prod_destroy(DProd* p);
 // mode 0: dynamic update; 1: recompute every row (static); with report_affected.
 int32_t prod_run(DProd* p, int mode, bool report_affected);
+
+// Entry-granular dynamic update (entry.hip): for C = A*A over (min,+) or
+// int64 (+,x) when C reflects every apply but the last and A holds that
+// apply's log.  Returns false (nothing done) when it does not apply.
+bool prod_entry_update(DProd* p, int32_t* nchg);
 
 // Graph-capturable dynamic update (no host round trips) on a caller-owned
 // workspace of prod_graph_work_bytes(p) bytes, after prod_prepare_graph set

@@ -124,9 +124,10 @@ __global__ __launch_bounds__(256) void k_col_counts(int32_t n, const int64_t* of
   for (int32_t t = lane; t < len[i]; t += 64) atomicAdd(&cnt[col[o + t]], 1);
 }
 
+template <int VSZ>
 __global__ __launch_bounds__(256) void k_fill_transpose(int32_t n, const int64_t* off, const int32_t* len,
-                                                        const int32_t* col, const int64_t* toff,
-                                                        int32_t* tlen, int32_t* tcol) {
+                                                        const int32_t* col, const char* val, const int64_t* toff,
+                                                        int32_t* tlen, int32_t* tcol, char* tval) {
   int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   int lane = threadIdx.x & 63;
   if (i >= n) return;
@@ -135,6 +136,8 @@ __global__ __launch_bounds__(256) void k_fill_transpose(int32_t n, const int64_t
     int32_t j = col[o + t];
     int32_t p = atomicAdd(&tlen[j], 1);
     tcol[toff[j] + p] = (int32_t)i;
+    if constexpr (VSZ == 8) ((uint64_t*)tval)[toff[j] + p] = ((const uint64_t*)val)[o + t];
+    else if constexpr (VSZ == 4) ((uint32_t*)tval)[toff[j] + p] = ((const uint32_t*)val)[o + t];
   }
 }
 
@@ -225,6 +228,11 @@ void mat_destroy(DMat* m) {
   ctx_free(c, m->d_top, 16);
   ctx_free(c, m->col, (size_t)m->pool_cap * 4);
   if (m->val) ctx_free(c, m->val, (size_t)m->pool_cap * m->vsz);
+  ctx_free(c, m->log_key, (size_t)m->log_cap * 8);
+  ctx_free(c, m->log_old, (size_t)m->log_cap * 8);
+  ctx_free(c, m->log_new, (size_t)m->log_cap * 8);
+  ctx_free(c, m->log_code, (size_t)m->log_cap);
+  ctx_free(c, m->d_log_n, 64);
   if (m->counted) c->objects--;
   delete m;
 }
@@ -356,7 +364,8 @@ void mat_build_transpose(DMat* m) {
   if (m->tidx) return;
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
-  DMat* t = mat_create(c, m->ncols, m->nrows, -1, nullptr, nullptr, nullptr);
+  // the transpose carries the values too: columns of m with their entries
+  DMat* t = mat_create(c, m->ncols, m->nrows, m->sr, nullptr, nullptr, nullptr);
   try {
     int32_t nt = t->nrows;
     if (nt > 0 && m->nrows > 0) {
@@ -371,13 +380,23 @@ void mat_build_transpose(DMat* m) {
       exclusive_scan_i32_to_i64(t->row_cap, t->row_off, nt, d_total, scr, s);
       int64_t total = read_i64(c, d_total);
       ctx_free(c, t->col, (size_t)t->pool_cap * 4);
+      if (t->val) ctx_free(c, t->val, (size_t)t->pool_cap * t->vsz);
       t->col = nullptr;
+      t->val = nullptr;
       t->pool_cap = total + total / 4 + 1024;
       t->version++;
       t->col = (int32_t*)ctx_alloc(c, (size_t)t->pool_cap * 4);
+      if (t->vsz) t->val = ctx_alloc(c, (size_t)t->pool_cap * t->vsz);
       DSG_HIP(hipMemsetAsync(t->row_len, 0, (size_t)nt * 4, s));
-      hipLaunchKernelGGL(k_fill_transpose, dim3(nb), dim3(256), 0, s, m->nrows, m->row_off, m->row_len,
-                         m->col, t->row_off, t->row_len, t->col);
+      if (t->vsz == 8)
+        hipLaunchKernelGGL(k_fill_transpose<8>, dim3(nb), dim3(256), 0, s, m->nrows, m->row_off, m->row_len,
+                           m->col, (const char*)m->val, t->row_off, t->row_len, t->col, (char*)t->val);
+      else if (t->vsz == 4)
+        hipLaunchKernelGGL(k_fill_transpose<4>, dim3(nb), dim3(256), 0, s, m->nrows, m->row_off, m->row_len,
+                           m->col, (const char*)m->val, t->row_off, t->row_len, t->col, (char*)t->val);
+      else
+        hipLaunchKernelGGL(k_fill_transpose<0>, dim3(nb), dim3(256), 0, s, m->nrows, m->row_off, m->row_len,
+                           m->col, (const char*)m->val, t->row_off, t->row_len, t->col, (char*)t->val);
       set_top(t, total);
       DSG_HIP(hipGetLastError());
     }

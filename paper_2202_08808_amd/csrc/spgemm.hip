@@ -1615,6 +1615,8 @@ DProd* prod_create(Ctx* c, DMat* A, DMat* B) {
   }
   A->refs++;
   B->refs++;
+  p->a_seq = A->apply_seq;
+  p->b_seq = B->apply_seq;
   try {
     prod_run(p, 1, true);
   } catch (...) {
@@ -1632,6 +1634,8 @@ void prod_destroy(DProd* p) {
   if (p->arena) ctx_free(c, p->arena, p->arena_bytes);
   if (p->arena_top) ctx_free(c, p->arena_top, 64);
   if (p->d_sync) ctx_free(c, p->d_sync, 16);
+  if (p->ews) ctx_free(c, p->ews, p->ews_bytes);
+  if (p->srt) ctx_free(c, p->srt, p->srt_bytes);
   if (p->C) mat_destroy(p->C);
   if (p->A) p->A->refs--;
   if (p->B) p->B->refs--;
@@ -1639,12 +1643,21 @@ void prod_destroy(DProd* p) {
 }
 
 int32_t prod_run(DProd* p, int mode, bool report_affected) {
+  int32_t nchg = 0;
+  if (mode == 0 && !report_affected && prod_entry_update(p, &nchg)) {
+    p->a_seq = p->A->apply_seq;
+    p->b_seq = p->B->apply_seq;
+    return nchg;
+  }
   const int64_t N = std::max<int32_t>(p->A->nrows, 1);
   const int64_t nB = std::max<int32_t>(p->B->nrows, 1);
   ensure_changed_cap(p, 0);
   const size_t need = work_bytes_for(N, nB);
   ProdWork w = carve_prod(ctx_scratch(p->ctx, need), N, nB);
-  return prod_sequence(p, mode, report_affected, w);
+  nchg = prod_sequence(p, mode, report_affected, w);
+  p->a_seq = p->A->apply_seq;
+  p->b_seq = p->B->apply_seq;
+  return nchg;
 }
 
 size_t prod_graph_work_bytes(const DProd* p) {

@@ -41,17 +41,19 @@ class Rows(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("group_ub", ctypes.c_int32 * 8), ("dense_max_passes", ctypes.c_int32),
-                ("force_bin", ctypes.c_int32)]
+                ("force_bin", ctypes.c_int32), ("update_path", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("affected_rows", ctypes.c_int64), ("changed_rows", ctypes.c_int64),
                 ("a_entries", ctypes.c_int64), ("flops", ctypes.c_int64),
                 ("nnz_new", ctypes.c_int64), ("nnz_old", ctypes.c_int64),
-                ("bin_rows", ctypes.c_int64 * 10), ("bin_flops", ctypes.c_int64 * 10)]
+                ("bin_rows", ctypes.c_int64 * 10), ("bin_flops", ctypes.c_int64 * 10),
+                ("path", ctypes.c_int32), ("pad", ctypes.c_int32), ("terms", ctypes.c_int64),
+                ("entries", ctypes.c_int64), ("lost", ctypes.c_int64)]
 
     def as_dict(self):
-        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("bin_")}
+        d = {k: getattr(self, k) for k, _ in self._fields_ if not k.startswith("bin_") and k != "pad"}
         d["bin_rows"] = list(self.bin_rows)
         d["bin_flops"] = list(self.bin_flops)
         return d
@@ -404,6 +406,7 @@ class Product:
                 t.group_ub[b] = ent["group_ub"][b]
             t.dense_max_passes = ent["dense_max_passes"]
             t.force_bin = -1
+            t.update_path = 0
             self.ctx.set_tuning(t)
             return dict(ent, cached=True)
         best = Tuning()

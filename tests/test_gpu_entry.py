@@ -1,0 +1,180 @@
+"""GPU: the entry-granular dynamic update of C = A*A ((min,+) fp32 and int64
+(+,x)) gives the oracle's C bit for bit and reports exactly the rows whose
+content changed, like the row path; it takes over only when C reflects
+every apply but the last one."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import THREADS, assert_same_csr, changed_rows
+from paper_2202_08808_amd import dsg
+from paper_2202_08808_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SRS = [I.PLUS_TIMES_I64, I.MIN_PLUS_F32]
+SR_ID = {I.PLUS_TIMES_I64: "i64", I.MIN_PLUS_F32: "minplus"}
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dsg.Context(0)
+    yield c
+    c.set_tuning(None)
+
+
+def row_path(ctx, on):
+    """on: whole affected rows only; off: entry-granular whenever it applies."""
+    t = ctx.get_tuning()
+    t.update_path = 1 if on else 2
+    ctx.set_tuning(t)
+
+
+def run(ctx, sr, A, batches, use_row_path=False, expect_entry=True, auto=False):
+    """Apply each batch then update; check C and the reported rows against
+    the oracle after every step (auto: the library chooses the path)."""
+    if auto:
+        ctx.set_tuning(None)
+    else:
+        row_path(ctx, use_row_path)
+    m = dsg.Matrix.from_csr(ctx, A, sr)
+    P = dsg.Product(ctx, m, m)
+    a = oracle.Csr.of(A)
+    C = oracle.spgemm(sr, a, a, nthreads=THREADS)
+    stats = []
+    for t, b in enumerate(batches):
+        m.apply_batch(b)
+        rs = P.update()
+        a, _ = oracle.apply(sr, a, b.rows, b.cols, b.vals, b.ops)
+        want = oracle.spgemm(sr, a, a, nthreads=THREADS)
+        assert_same_csr(sr, P.export(), want, f"step {t}")
+        assert np.array_equal(rs.row_ids(), changed_rows(C, want)), f"step {t}: reported rows"
+        st = P.stats()
+        stats.append(st)
+        if expect_entry and not use_row_path:
+            assert st["path"] == 1, f"step {t}: row path taken"
+        C = want
+    P.destroy()
+    m.destroy()
+    ctx.set_tuning(None)
+    return stats
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_entry_matches_oracle(ctx, sr):
+    say(f"entry path R-MAT {SR_ID[sr]}")
+    hi = 9 if sr == I.PLUS_TIMES_I64 else 100
+    A = I.rmat_csr(10, 8, sr, stream=801, lo=1, hi=hi)
+    bs = I.disjoint_batches(A, sr, [1, 10, 100, 1000, 3000], stream=802, value_lo=1, value_hi=hi)
+    st = run(ctx, sr, A, bs)
+    assert sum(s["lost"] for s in st) > 0  # deletions hit stored minima / contributors
+    run(ctx, sr, A, bs, use_row_path=True)
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_entry_unconstrained_batches(ctx, sr):
+    """Repeated keys, deletes of absent entries, SET over present entries and
+    ADD chains in one batch."""
+    say(f"entry path unconstrained {SR_ID[sr]}")
+    rng = np.random.default_rng(31 + sr)
+    keys = I.er_keys(300, 1500, rng)
+    A = I.csr_from_keys(300, 300, keys, I.draw_values(sr, keys.size, rng, 1, 9))
+    bs = [I.random_batch(300, 300, sr, sz, rng, op_probs=(0.4, 0.3, 0.3), hot_rows=40, hot_cols=60)
+          for sz in (5, 50, 400, 2000)]
+    run(ctx, sr, A, bs)
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_entry_vanishing_entries(ctx, sr):
+    """Deleting the only product of an entry removes the entry; deleting one
+    of two keeps it with the other's value."""
+    say(f"entry path vanishing {SR_ID[sr]}")
+    n = 8
+    # 0->1->2 (one path), 3->4->5 and 3->6->5 (two paths)
+    edges = {(0, 1): 2, (1, 2): 3, (3, 4): 1, (4, 5): 1, (3, 6): 5, (6, 5): 5}
+    keys = np.array(sorted(i * n + j for i, j in edges), np.int64)
+    vdt = np.int64 if sr == I.PLUS_TIMES_I64 else np.float32
+    vals = np.array([edges[(int(k) // n, int(k) % n)] for k in keys]).astype(vdt)
+    A = I.csr_from_keys(n, n, keys, vals)
+    dels = I.Batch(np.array([0, 4], np.int32), np.array([1, 5], np.int32),
+                   np.zeros(2, vdt), np.full(2, I.OP_DELETE, np.uint8))
+    st = run(ctx, sr, A, [dels])
+    assert st[0]["lost"] >= 1
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+@pytest.mark.parametrize("long_row", [3000, 9500])
+def test_entry_long_rows(ctx, sr, long_row):
+    """Lost entries in a row of A longer than the small LDS hash (and, at
+    9500, longer than one chunk of the large one)."""
+    say(f"entry path long rows {SR_ID[sr]} {long_row}")
+    rng = np.random.default_rng(41 + long_row + sr)
+    n = 12000
+    hi = 9 if sr == I.PLUS_TIMES_I64 else 100
+    row0 = np.sort(rng.choice(n, long_row, replace=False)).astype(np.int64)
+    rest = I.er_keys(n, 3 * n, rng)
+    keys = np.unique(np.concatenate([row0, rest]))
+    A = I.csr_from_keys(n, n, keys, I.draw_values(sr, keys.size, rng, 1, hi))
+    # delete / change entries of the long row, insert elsewhere
+    k0 = keys[keys < n]
+    pick = rng.choice(k0.size, 400, replace=False)
+    rows = np.zeros(400, np.int32)
+    cols = (k0[pick] % n).astype(np.int32)
+    ops = np.where(np.arange(400) < 250, I.OP_DELETE, I.OP_SET).astype(np.uint8)
+    vals = I.draw_values(sr, 400, rng, 1, hi)
+    b1 = I.Batch(rows, cols, vals, ops)
+    b2 = I.random_batch(n, n, sr, 2000, rng, op_probs=(0.5, 0.5, 0.0), value_lo=1, value_hi=hi)
+    st = run(ctx, sr, A, [b1, b2])
+    assert st[0]["lost"] > 0
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_entry_needs_every_apply_logged(ctx, sr):
+    """Two applies before an update: only the last one is logged, so the row
+    path runs; the next single apply goes entry-granular again."""
+    say(f"entry path fallback {SR_ID[sr]}")
+    row_path(ctx, False)
+    hi = 9 if sr == I.PLUS_TIMES_I64 else 100
+    A = I.rmat_csr(9, 8, sr, stream=811, lo=1, hi=hi)
+    bs = I.disjoint_batches(A, sr, [50, 50, 50], stream=812, value_lo=1, value_hi=hi)
+    m = dsg.Matrix.from_csr(ctx, A, sr)
+    P = dsg.Product(ctx, m, m)
+    a = oracle.Csr.of(A)
+    m.apply_batch(bs[0])
+    m.apply_batch(bs[1])
+    P.update()
+    for b in bs[:2]:
+        a, _ = oracle.apply(sr, a, b.rows, b.cols, b.vals, b.ops)
+    assert P.stats()["path"] == 0
+    assert_same_csr(sr, P.export(), oracle.spgemm(sr, a, a, nthreads=THREADS), "after two applies")
+    m.apply_batch(bs[2])
+    P.update()
+    a, _ = oracle.apply(sr, a, bs[2].rows, bs[2].cols, bs[2].vals, bs[2].ops)
+    assert P.stats()["path"] == 1
+    assert_same_csr(sr, P.export(), oracle.spgemm(sr, a, a, nthreads=THREADS), "after one apply")
+    # an update with nothing applied since reports no rows
+    assert P.update().n == 0
+    P.destroy()
+    m.destroy()
+    ctx.set_tuning(None)
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_automatic_path_choice(ctx, sr):
+    """Automatic choice: a small batch goes entry-granular, a batch whose
+    changed products are many next to nnz(C) goes to the row path; both
+    exact."""
+    say(f"automatic path {SR_ID[sr]}")
+    ctx.set_tuning(None)
+    hi = 9 if sr == I.PLUS_TIMES_I64 else 100
+    A = I.rmat_csr(11, 16, sr, stream=821, lo=1, hi=hi)
+    bs = I.disjoint_batches(A, sr, [20, 8000], stream=822, value_lo=1, value_hi=hi)
+    st = run(ctx, sr, A, bs, expect_entry=False, auto=True)
+    assert st[0]["path"] == 1 and st[1]["path"] == 0

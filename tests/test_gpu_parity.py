@@ -168,6 +168,52 @@ def test_apply_growth_across_compaction(ctx, sr, with_product):
 
 
 @pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+@pytest.mark.parametrize("with_product", [False, True], ids=["matrix", "product"])
+def test_apply_heavy_rows(ctx, sr, with_product):
+    """Rows that receive thousands of updates in one batch (the workgroup
+    paths of the apply): inserts only (moved rows), overwrites only (in
+    place), a mix with deletions, and more updates than one LDS hash holds."""
+    say(f"apply heavy rows {SR_ID[sr]} {with_product}")
+    rng = np.random.default_rng(51 + sr)
+    n = 25000
+    keys = I.er_keys(n, 3 * n, rng)
+    keys = np.unique(np.concatenate([keys, np.arange(3000, dtype=np.int64) + n]))  # row 1: 3000 entries
+    A = I.csr_from_keys(n, n, keys, I.draw_values(sr, keys.size, rng, 1, 9))
+    Am = dsg.Matrix.from_csr(ctx, A, sr)
+    P = dsg.Product(ctx, Am, Am) if with_product else None
+    cur = oracle.Csr.of(A)
+
+    def batch(rows, cols, ops):
+        return I.Batch(np.asarray(rows, np.int32), np.asarray(cols, np.int32),
+                       I.draw_values(sr, len(rows), rng, 1, 9), np.asarray(ops, np.uint8))
+
+    r0 = np.zeros(5000, np.int32)
+    c0 = rng.choice(n, 5000, replace=False)
+    r1 = np.ones(3000, np.int32)
+    c1 = np.arange(3000)
+    r2 = np.full(4000, 2, np.int32)
+    c2 = rng.integers(0, n, 4000)
+    o2 = rng.choice(3, 4000, p=[0.5, 0.3, 0.2])
+    r3 = np.full(20000, 3, np.int32)
+    c3 = rng.choice(n, 20000, replace=False)
+    b = batch(np.concatenate([r0, r1, r2, r3]), np.concatenate([c0, c1, c2, c3]),
+              np.concatenate([np.zeros(5000), np.zeros(3000), o2, np.zeros(20000)]))
+    b2 = batch(np.concatenate([r3[:9000], r0[:100]]), np.concatenate([c3[:9000], c0[:100]]),
+               np.concatenate([np.full(9000, I.OP_DELETE), np.full(100, I.OP_ADD)]))
+    for t, bb in enumerate((b, b2)):
+        Am.apply_batch(bb)
+        cur, _ = oracle.apply(sr, cur, bb.rows, bb.cols, bb.vals, bb.ops)
+        assert_same_csr(sr, Am.export(), cur, f"after batch {t}")
+        if P is not None:
+            P.update()
+            want = oracle.spgemm(sr, cur, cur, nthreads=THREADS)
+            assert_same_csr(sr, P.export(), want, f"product after batch {t}", A=cur, B=cur)
+    if P is not None:
+        P.destroy()
+    destroy(Am)
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
 @pytest.mark.parametrize("square", [True, False], ids=["AxA", "AxB"])
 def test_dynamic_sequence(ctx, sr, square):
     """D1 (dynamic result = static recompute of the updated operands) and D5
