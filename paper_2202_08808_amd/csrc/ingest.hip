@@ -32,6 +32,7 @@ namespace {
 constexpr uint8_t K_KEEP = 0, K_SET = 1, K_DEL = 2;
 constexpr uint8_t OP_GUARD_ONLY = 3;  // internal op of mat_apply_sorted_add: no value
 constexpr int PLAN_LDS = 1024;        // update columns of a row held in LDS by the plan
+constexpr int HEAVY_LEN = 2048;       // rows longer than this are planned by a whole workgroup
 constexpr uint8_t C_NOP = UPD_NOP, C_INS = UPD_INS, C_DEL = UPD_DEL, C_OVR = UPD_OVR, C_LOST = UPD_LOST;
 
 int bits_for(int64_t n) {
@@ -271,10 +272,10 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
   const int32_t i = U.urow[r];
   const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
   const int32_t nu = u1 - u0;
-  if (nu > PLAN_LDS) return;  // a heavy row: k_plan_heavy
-  const bool in_lds = true;
   const int64_t off = m.row_off[i];
   const int32_t len = m.row_len[i], cap = m.row_cap[i];
+  if (nu > PLAN_LDS || len > HEAVY_LEN) return;  // k_plan_heavy takes this row
+  const bool in_lds = true;
   for (int32_t u = u0 + lane; u < u1; u += 64) {
     U.slot[u] = -1;
     if (in_lds) lk[u - u0] = (int32_t)(U.key[u] & cmask);
@@ -400,99 +401,96 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
       m.row_off[i] = dest;
       m.row_cap[i] = ncap;
     }
-  } else if (ncap == 0) {
-    // ---- in place ----
-    int32_t H = 0, Mc = 0;
-    for (int32_t base = 0; base < len; base += 64) {
-      int32_t s = base + lane;
-      bool act = s < len;
-      bool deleted = false;
-      int32_t u = -1;
-      if (act) {
-        u = find_update(U.key, u0, u1, cmask, m.col[off + s]);
-        if (u >= 0) {
-          uint8_t code = U.code[u];
-          deleted = code == C_DEL;
-          if (code == C_OVR && s < nl) store_raw<VSZ>(m.val, off + s, U.fin[u]);
-        }
+  } else {
+    // ---- the row loses entries: mark the deleted slots (column -1) and
+    // apply the overwrites where they stand ----
+    for (int32_t base = u0; base < u1; base += 64) {
+      const int32_t u = base + lane;
+      if (u < u1) {
+        const uint8_t code = U.code[u];
+        if (code == C_DEL) m.col[off + U.slot[u]] = -1;
+        else if (code == C_OVR) store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
       }
-      bool hole = act && deleted && s < nl;
-      bool mover = act && !deleted && s >= nl;
-      uint64_t hb = __ballot(hole), mb = __ballot(mover);
-      if (hole) U.holes[u0 + H + __popcll(hb & lt)] = s;
-      if (mover) {
-        int32_t k = u0 + Mc + __popcll(mb & lt);
-        U.mv_src[k] = s;
-        U.mv_u[k] = u;
-      }
-      H += __popcll(hb);
-      Mc += __popcll(mb);
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
-    for (int32_t q = lane; q < Mc; q += 64) {
-      int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q], mu = U.mv_u[u0 + q];
-      m.col[off + dst] = m.col[off + src];
-      uint64_t v = (mu >= 0 && U.code[mu] == C_OVR) ? U.fin[mu] : load_raw<VSZ>(m.val, off + src);
-      store_raw<VSZ>(m.val, off + dst, v);
-    }
-    int32_t k = 0;
-    for (int32_t base = u0; base < u1; base += 64) {
-      int32_t u = base + lane;
-      bool ins = u < u1 && U.code[u] == C_INS;
-      uint64_t ib = __ballot(ins);
-      if (ins) {
-        int32_t mm = Mc + k + __popcll(ib & lt);
-        int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
-        m.col[off + dst] = (int32_t)(U.key[u] & cmask);
-        store_raw<VSZ>(m.val, off + dst, U.fin[u]);
+    if (ncap == 0) {
+      // in place: holes are the deleted slots below the new length, movers
+      // the entries left at or above it; inserts fill the remaining holes,
+      // then the space after the old length
+      int32_t H = 0;
+      for (int32_t base = u0; base < u1; base += 64) {
+        const int32_t u = base + lane;
+        const bool hole = u < u1 && U.code[u] == C_DEL && U.slot[u] < nl;
+        const uint64_t hb = __ballot(hole);
+        if (hole) U.holes[u0 + H + __popcll(hb & lt)] = U.slot[u];
+        H += __popcll(hb);
       }
-      k += __popcll(ib);
-    }
-  } else {
-    // ---- move the row to fresh space ----
-    unsigned long long no = 0;
-    if (lane == 0) no = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
-    no = __shfl(no, 0, 64);
-    if ((int64_t)no + ncap > m.pool_cap) {
-      if (lane == 0) atomicOr(err, 1);
-      return;
-    }
-    int32_t kept = 0;
-    for (int32_t base = 0; base < len; base += 64) {
-      int32_t s = base + lane;
-      bool act = s < len;
-      bool keep = false;
-      int32_t u = -1;
-      int32_t c = 0;
-      if (act) {
-        c = m.col[off + s];
-        u = find_update(U.key, u0, u1, cmask, c);
-        keep = !(u >= 0 && U.code[u] == C_DEL);
+      int32_t Mc = 0;
+      for (int32_t s0 = nl; s0 < len; s0 += 64) {
+        const int32_t sl = s0 + lane;
+        const bool mover = sl < len && m.col[off + sl] != -1;
+        const uint64_t mb = __ballot(mover);
+        if (mover) U.mv_src[u0 + Mc + __popcll(mb & lt)] = sl;
+        Mc += __popcll(mb);
       }
-      uint64_t kb = __ballot(keep);
-      if (keep) {
-        int64_t dst = (int64_t)no + kept + __popcll(kb & lt);
-        m.col[dst] = c;
-        uint64_t v = (u >= 0 && U.code[u] == C_OVR) ? U.fin[u] : load_raw<VSZ>(m.val, off + s);
-        store_raw<VSZ>(m.val, dst, v);
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      for (int32_t q = lane; q < Mc; q += 64) {
+        const int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q];
+        m.col[off + dst] = m.col[off + src];
+        store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
       }
-      kept += __popcll(kb);
-    }
-    for (int32_t base = u0; base < u1; base += 64) {
-      int32_t u = base + lane;
-      bool ins = u < u1 && U.code[u] == C_INS;
-      uint64_t ib = __ballot(ins);
-      if (ins) {
-        int64_t dst = (int64_t)no + kept + __popcll(ib & lt);
-        m.col[dst] = (int32_t)(U.key[u] & cmask);
-        store_raw<VSZ>(m.val, dst, U.fin[u]);
+      int32_t k = 0;
+      for (int32_t base = u0; base < u1; base += 64) {
+        const int32_t u = base + lane;
+        const bool ins = u < u1 && U.code[u] == C_INS;
+        const uint64_t ib = __ballot(ins);
+        if (ins) {
+          const int32_t mm = Mc + k + __popcll(ib & lt);
+          const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
+          m.col[off + dst] = (int32_t)(U.key[u] & cmask);
+          store_raw<VSZ>(m.val, off + dst, U.fin[u]);
+        }
+        k += __popcll(ib);
       }
-      kept += __popcll(ib);
-    }
-    if (lane == 0) {
-      m.row_off[i] = (int64_t)no;
-      m.row_cap[i] = ncap;
+    } else {
+      // move the row to fresh space, dropping the marked slots
+      unsigned long long no = 0;
+      if (lane == 0) no = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
+      no = __shfl(no, 0, 64);
+      if ((int64_t)no + ncap > m.pool_cap) {
+        if (lane == 0) atomicOr(err, 1);
+        return;
+      }
+      int32_t kept = 0;
+      for (int32_t base = 0; base < len; base += 64) {
+        const int32_t sl = base + lane;
+        const int32_t c = sl < len ? m.col[off + sl] : -1;
+        const bool keep = c != -1;
+        const uint64_t kb = __ballot(keep);
+        if (keep) {
+          const int64_t dst = (int64_t)no + kept + __popcll(kb & lt);
+          m.col[dst] = c;
+          store_raw<VSZ>(m.val, dst, load_raw<VSZ>(m.val, off + sl));
+        }
+        kept += __popcll(kb);
+      }
+      for (int32_t base = u0; base < u1; base += 64) {
+        const int32_t u = base + lane;
+        const bool ins = u < u1 && U.code[u] == C_INS;
+        const uint64_t ib = __ballot(ins);
+        if (ins) {
+          const int64_t dst = (int64_t)no + kept + __popcll(ib & lt);
+          m.col[dst] = (int32_t)(U.key[u] & cmask);
+          store_raw<VSZ>(m.val, dst, U.fin[u]);
+        }
+        kept += __popcll(ib);
+      }
+      if (lane == 0) {
+        m.row_off[i] = (int64_t)no;
+        m.row_cap[i] = ncap;
+      }
     }
   }
   if (lane == 0) {
@@ -542,10 +540,10 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
   const int64_t nR = *d_nR;
   for (int64_t r = blockIdx.x; r < nR; r += gridDim.x) {
     const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
-    if (u1 - u0 <= PLAN_LDS) continue;
     const int32_t i = U.urow[r];
     const int64_t off = m.row_off[i];
     const int32_t len = m.row_len[i], cap = m.row_cap[i];
+    if (u1 - u0 <= PLAN_LDS && len <= HEAVY_LEN) continue;
     for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) U.slot[u] = -1;
     if (tid < 3) cnt[tid] = 0;
     for (int32_t c0 = u0; c0 < u1; c0 += HEAVY_SLOTS / 2) {
@@ -1016,8 +1014,11 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   Work w = carve_work(ctx_scratch(c, work_bytes(n, deltas)), n, deltas);
   Work wt;
   if (deltas) wt = carve_work(ctx_scratch2(c, work_bytes(n, false)), n, false);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) ctx_timing_begin(c, "apply", 0.0, &e0, &e1);
   apply_pipeline(m, d_rows, d_cols, d_vals, d_ops, n, w, deltas ? &wt : nullptr, false);
   keep_log(m, w, n);
+  if (c->timing) ctx_timing_end(c, e1);
   int* h = (int*)c->pinned;
   h[1] = 0;
   if (deltas) DSG_HIP(hipMemcpyAsync(h + 1, wt.err, 4, hipMemcpyDeviceToHost, s));

@@ -81,8 +81,33 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_apply(const In* in, int64_t* o
   }
 }
 
+// one tile: the whole exclusive scan (and its total) in a single launch
+template <class In>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_single(const In* in, int64_t* out, int64_t n, int64_t* total) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  int64_t v[SCAN_ITEMS];
+  int64_t s = 0;
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    const int64_t i = (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    v[t] = i < n ? (int64_t)in[i] : 0;
+    s += v[t];
+  }
+  int64_t tot;
+  int64_t run = block_exclusive_scan<int64_t>(s, lds, tot);
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    const int64_t i = (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    if (i < n) out[i] = run;
+    run += v[t];
+  }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
 template <class In>
 void scan_impl(const In* in, int64_t* out, int64_t n, int64_t* d_total, void* scratch, hipStream_t s) {
+  if (n <= SCAN_TILE) {
+    hipLaunchKernelGGL(k_scan_single<In>, dim3(1), dim3(SCAN_NT), 0, s, in, out, n, d_total);
+    return;
+  }
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (tiles == 0) tiles = 1;
   int64_t* sums = (int64_t*)scratch;
@@ -269,6 +294,50 @@ void compact_list_by_flags(const int32_t* list, const uint8_t* flags, const int3
   hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, total, d_count);
 }
 
+namespace {
+
+// Bitonic sort of up to SMALL_SORT (key, value) pairs in LDS by (key, value),
+// padded with (max, max).
+constexpr int SMALL_SORT = 4096;
+
+__global__ __launch_bounds__(1024) void k_small_sort(uint64_t* keys, uint32_t* vals, int n) {
+  __shared__ uint64_t sk[SMALL_SORT];
+  __shared__ uint32_t sv[SMALL_SORT];
+  int m = 1;
+  while (m < n) m <<= 1;
+  for (int i = threadIdx.x; i < m; i += 1024) {
+    sk[i] = i < n ? keys[i] : ~0ull;
+    sv[i] = i < n ? vals[i] : ~0u;
+  }
+  __syncthreads();
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < m; i += 1024) {
+        const int p = i ^ j;
+        if (p > i) {
+          const bool up = (i & k) == 0;
+          const uint64_t a = sk[i], b = sk[p];
+          const uint32_t va = sv[i], vb = sv[p];
+          const bool gt = a > b || (a == b && va > vb);
+          if (gt == up) {
+            sk[i] = b;
+            sk[p] = a;
+            sv[i] = vb;
+            sv[p] = va;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < n; i += 1024) {
+    keys[i] = sk[i];
+    vals[i] = sv[i];
+  }
+}
+
+}  // namespace
+
 size_t radix_scratch_bytes(int64_t n) {
   int64_t ntiles = (n + RS_TILE - 1) / RS_TILE + 1;
   return Carve::need({(size_t)n * 8, (size_t)n * 4, (size_t)(256 * ntiles) * 8,
@@ -278,6 +347,12 @@ size_t radix_scratch_bytes(int64_t n) {
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, void* scratch,
                       hipStream_t s) {
   if (n <= 1 || key_bits <= 0) return;
+  if (n <= SMALL_SORT) {
+    // one workgroup: the same order as the stable radix sort when equal keys
+    // carry ascending values (their original positions)
+    hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(1024), 0, s, keys, vals, (int)n);
+    return;
+  }
   int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
   Carve cv(scratch, radix_scratch_bytes(n));
   uint64_t* k2 = cv.take<uint64_t>(n);
