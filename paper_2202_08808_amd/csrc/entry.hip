@@ -351,6 +351,7 @@ struct LostArgs {
   uint32_t* part_hits;
   uint64_t* del_key;
   unsigned long long* ndel;
+  int use_rowside;      // 0: every lost entry from the column side
   const int64_t* s_rp;  // column-sorted copy of A' (row side only)
   const int32_t* s_col;
   const void* s_val;
@@ -481,7 +482,7 @@ __global__ __launch_bounds__(WG) void k_lost_small(LostArgs L) {
       j = (int32_t)(L.key[e] & cmask);
       lj = L.T.len[j];
       toff = L.T.off[j];
-      act = !row_side(d, lj);
+      act = !(L.use_rowside && row_side(d, lj));
     }
     unsigned long long acc = acc_id<SR>();
     uint32_t hits = 0;
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(WG) void k_lost_big(LostArgs L) {
     build_hash<SLOTS>(hk, hp, L.A, aoff, k0, min(d, k0 + CHUNK), tid, WG);
     for (int64_t e = e0 + wv; e < e1; e += WG / 64) {
       const int32_t j = (int32_t)(L.key[e] & cmask);
-      if (row_side(d, L.T.len[j])) continue;
+      if (L.use_rowside && row_side(d, L.T.len[j])) continue;
       unsigned long long acc = acc_id<SR>();
       uint32_t hits = 0;
       column_pass<SR, SLOTS>(L, hk, hp, aoff, j, acc, hits, lane);
@@ -537,7 +538,8 @@ __global__ __launch_bounds__(WG) void k_lost_big(LostArgs L) {
     __syncthreads();
   }
   for (int64_t e = e0 + tid; e < e1; e += WG)
-    if (!row_side(d, L.T.len[(int32_t)(L.key[e] & cmask)])) finish_entry<SR>(L, e, L.part_acc[e], L.part_hits[e]);
+    if (!(L.use_rowside && row_side(d, L.T.len[(int32_t)(L.key[e] & cmask)])))
+      finish_entry<SR>(L, e, L.part_acc[e], L.part_hits[e]);
 }
 
 // lost entries recomputed from the row side: 8 lanes per entry
@@ -553,7 +555,7 @@ __global__ __launch_bounds__(256) void k_lost_rowside(LostArgs L, int64_t nlost)
     i = (int32_t)(L.key[e] >> L.cbits);
     j = (int32_t)(L.key[e] & cmask);
     d = L.A.len[i];
-    act = row_side(d, L.T.len[j]);
+    act = L.use_rowside && row_side(d, L.T.len[j]);
   }
   unsigned long long acc = acc_id<SR>();
   uint32_t hits = 0;
@@ -580,13 +582,26 @@ __global__ __launch_bounds__(256) void k_lost_rowside(LostArgs L, int64_t nlost)
   if (act && l8 == 0) finish_entry<SR>(L, e, acc, hits);
 }
 
+// row-side entries: their count and the column lengths they would stream
 __global__ void k_count_rowside(const uint64_t* key, int64_t n, int cbits, const int32_t* a_len,
                                 const int32_t* t_len, unsigned long long* cnt) {
+  __shared__ unsigned long long sum;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t cmask = (1ull << cbits) - 1;
-  const bool rs = e < n && row_side(a_len[(int32_t)(key[e] >> cbits)], t_len[(int32_t)(key[e] & cmask)]);
-  const int c = __syncthreads_count(rs);  // one atomic per workgroup
-  if (threadIdx.x == 0 && c) atomicAdd(cnt, (unsigned long long)c);
+  if (threadIdx.x == 0) sum = 0;
+  __syncthreads();
+  int32_t lj = 0;
+  bool rs = false;
+  if (e < n) {
+    lj = t_len[(int32_t)(key[e] & cmask)];
+    rs = row_side(a_len[(int32_t)(key[e] >> cbits)], lj);
+  }
+  if (rs) atomicAdd(&sum, (unsigned long long)lj);
+  const int c = __syncthreads_count(rs);  // one atomic per counter and workgroup
+  if (threadIdx.x == 0 && c) {
+    atomicAdd(cnt, (unsigned long long)c);
+    atomicAdd(cnt + 1, sum);
+  }
 }
 
 __global__ void k_del_batch(const uint64_t* key, int64_t n, int cbits, int32_t* rows, int32_t* cols, uint8_t* ops) {
@@ -654,6 +669,35 @@ bool eligible(const DProd* p) {
   return A->log_seq != 0 && A->log_seq == A->apply_seq && A->apply_seq == p->a_seq + 1;
 }
 
+// Step 1, on its own: count the products the last apply changed (the
+// offsets stay in the context's second scratch for entry_finish).
+int64_t count_terms(DProd* p) {
+  Ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  DMat* A = p->A;
+  DMat* T = A->tidx;
+  const int cbits = bits_for(A->ncols);
+  Log L{A->log_key, A->log_old, A->log_new, A->log_code, read_count(c, A->d_log_n)};
+  const int64_t nU = L.n;
+  const size_t b1 = Carve::need({(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64});
+  Carve cv1(ctx_scratch2(c, b1), b1);
+  int64_t* cnt = cv1.take<int64_t>(nU + 1);
+  int64_t* off = cv1.take<int64_t>(nU + 1);
+  void* scan1 = cv1.take<char>(scan_scratch_bytes(nU + 1) + 64);
+  int64_t* d_total = cv1.take<int64_t>(8);
+  int64_t nterm = 0;
+  if (nU > 0) {
+    Phase ph(c, "entry_count");
+    hipLaunchKernelGGL(k_term_counts, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, cbits, (const int32_t*)A->row_len,
+                       (const int32_t*)T->row_len, cnt);
+    exclusive_scan_i64(cnt, off, nU, d_total, scan1, s);
+    nterm = read_count(c, d_total);
+  }
+  p->entry_nU = nU;
+  p->entry_nterm = nterm;
+  return nterm;
+}
+
 template <int SR>
 int32_t entry_update(DProd* p) {
   using V = typename Sem<SR>::V;
@@ -670,28 +714,19 @@ int32_t entry_update(DProd* p) {
   st = dsg_update_stats{};
   st.path = 1;
 
-  // counters: [0] rows of C with changes, [1] lost deletions, [2] probes, [3] lost count
-  Log L{A->log_key, A->log_old, A->log_new, A->log_code, read_count(c, A->d_log_n)};
+  // the counts of step 1 (count_terms), still in the second scratch
+  Log L{A->log_key, A->log_old, A->log_new, A->log_code, p->entry_nU};
   const int64_t nU = L.n;
-  // ---- 1. counts (in the context's second scratch: nothing else uses it
-  // before the products are written) ----
   const size_t b1 = Carve::need({(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64});
   Carve cv1(ctx_scratch2(c, b1), b1);
-  int64_t* cnt = cv1.take<int64_t>(nU + 1);
+  (void)cv1.take<int64_t>(nU + 1);
   int64_t* off = cv1.take<int64_t>(nU + 1);
-  void* scan1 = cv1.take<char>(scan_scratch_bytes(nU + 1) + 64);
+  (void)cv1.take<char>(scan_scratch_bytes(nU + 1) + 64);
   int64_t* d_total = cv1.take<int64_t>(8);
-  int64_t nterm = 0;
-  if (nU > 0) {
-    Phase ph(c, "entry_count");
-    hipLaunchKernelGGL(k_term_counts, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, cbits, (const int32_t*)A->row_len,
-                       (const int32_t*)T->row_len, cnt);
-    exclusive_scan_i64(cnt, off, nU, d_total, scan1, s);
-    nterm = read_count(c, d_total);
-  }
-  // past about one changed product per 64 stored entries of C the row path
-  // is faster (measured crossover on R-MAT, a few million products): hand over
-  if (c->tuning.update_path == 0 && nterm > std::max<int64_t>(C->h_top_ub / 64, 4096)) return -1;
+  const int64_t nterm = p->entry_nterm;
+  // counters: [0] rows of C with changes, [1] lost deletions, [3] lost count,
+  // [5..6] work items, [12] reported rows, [14..15] row-side entries and the
+  // column lengths they would stream
   st.terms = nterm;
 
   // ---- workspace for the products, the entry updates and the lost entries ----
@@ -831,9 +866,14 @@ int32_t entry_update(DProd* p) {
     la.s_col = nullptr;
     la.s_val = nullptr;
     hipLaunchKernelGGL(k_count_rowside, dim3(blocks_for(nlost, 256)), dim3(256), 0, s, lkey, nlost, cbits,
-                       (const int32_t*)A->row_len, (const int32_t*)T->row_len, ctr + 4);
-    const int64_t nrowside = read_count(c, (const int64_t*)(ctr + 4));
-    if (nrowside > 0) {
+                       (const int32_t*)A->row_len, (const int32_t*)T->row_len, ctr + 14);
+    unsigned long long* hrs = (unsigned long long*)((char*)c->pinned + 3072);
+    DSG_HIP(hipMemcpyAsync(hrs, ctr + 14, 16, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipStreamSynchronize(s));
+    // the sorted copy costs a sort of all of A': only worth it when the
+    // row-side entries would otherwise stream a good part of that
+    la.use_rowside = hrs[0] > 0 && hrs[1] > (unsigned long long)(A->h_top_ub / 4);
+    if (la.use_rowside) {
       // column-sorted copy of A' for the row-side searches
       const int64_t annz = A->h_top_ub;  // bound on nnz(A')
       const size_t sb = Carve::need({(size_t)(n + 1) * 8, (size_t)std::max<int64_t>(annz, 1) * 4,
@@ -914,10 +954,8 @@ int32_t entry_update(DProd* p) {
 
 }  // namespace
 
-bool prod_entry_update(DProd* p, int32_t* nchg) {
-  if (!eligible(p)) return false;
-  const int32_t r = p->A->sr == 1 ? entry_update<1>(p) : entry_update<0>(p);
-  if (r < 0) return false;  // too many changed products: the row path takes it
-  *nchg = r;
-  return true;
-}
+bool entry_eligible(const DProd* p) { return eligible(p); }
+
+int64_t entry_count(DProd* p) { return count_terms(p); }
+
+int32_t entry_finish(DProd* p) { return p->A->sr == 1 ? entry_update<1>(p) : entry_update<0>(p); }

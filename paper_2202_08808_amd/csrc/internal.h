@@ -265,6 +265,8 @@ struct DProd {
   size_t ews_bytes = 0;
   void* srt = nullptr;            // column-sorted copy of A (entry-granular path)
   size_t srt_bytes = 0;
+  int64_t entry_nU = 0;           // entry-granular path: log entries and changed
+  int64_t entry_nterm = 0;        // products counted for the pending update
   int refs = 0;                   // batched executors and servers using this product
 };
 
@@ -275,8 +277,13 @@ int32_t prod_run(DProd* p, int mode, bool report_affected);
 
 // Entry-granular dynamic update (entry.hip): for C = A*A over (min,+) or
 // int64 (+,x) when C reflects every apply but the last and A holds that
-// apply's log.  Returns false (nothing done) when it does not apply.
-bool prod_entry_update(DProd* p, int32_t* nchg);
+// apply's log (entry_eligible).  entry_count lists how many products the
+// last apply changed (kept in the context's second scratch); entry_finish,
+// called next with nothing else on that scratch in between, updates C and
+// returns the reported-row count.
+bool entry_eligible(const DProd* p);
+int64_t entry_count(DProd* p);
+int32_t entry_finish(DProd* p);
 
 // Graph-capturable dynamic update (no host round trips) on a caller-owned
 // workspace of prod_graph_work_bytes(p) bytes, after prod_prepare_graph set

@@ -326,8 +326,13 @@ void executor_main(DServer* s) {
           if (g->n > 0) mat_apply_device(g->target, g->d_rows, g->d_cols, g->d_vals, g->d_ops, g->n);
           changed = prod_run(s->p, 0, false);
           if (g->n > 0) {
+            // workspace the update took: products and entry updates on the
+            // entry-granular path, staging and new C space on the row path
+            const dsg_update_stats& st = s->p->stats;
             const double sz = 4.0 + (double)s->p->C->vsz;
-            ws = ((double)s->p->last_arena_demand + sz * (double)s->p->last_c_demand) / (double)g->n;
+            const double bytes = st.path == 1 ? 32.0 * (double)st.terms + 64.0 * (double)st.entries
+                                              : (double)s->p->last_arena_demand + sz * (double)s->p->last_c_demand;
+            ws = std::min(std::max(bytes / (double)g->n, 16.0), 65536.0);
           }
           rb = (4.0 + (double)s->p->C->vsz) * (double)s->p->C->h_top_ub / (double)std::max<int32_t>(s->p->C->nrows, 1);
         } else {

@@ -168,13 +168,38 @@ def test_entry_needs_every_apply_logged(ctx, sr):
 
 @pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
 def test_automatic_path_choice(ctx, sr):
-    """Automatic choice: a small batch goes entry-granular, a batch whose
-    changed products are many next to nnz(C) goes to the row path; both
-    exact."""
+    """The automatic choice follows the cost rule (entry-granular while the
+    affected rows' products exceed 55e6 + 200 per changed product) and gives
+    the row path's C bit for bit.  R-MAT s15: a 200-update batch goes
+    entry-granular, a 30000-update batch to the row path."""
     say(f"automatic path {SR_ID[sr]}")
-    ctx.set_tuning(None)
     hi = 9 if sr == I.PLUS_TIMES_I64 else 100
-    A = I.rmat_csr(11, 16, sr, stream=821, lo=1, hi=hi)
-    bs = I.disjoint_batches(A, sr, [20, 8000], stream=822, value_lo=1, value_hi=hi)
-    st = run(ctx, sr, A, bs, expect_entry=False, auto=True)
-    assert st[0]["path"] == 1 and st[1]["path"] == 0
+    A = I.rmat_csr(15, 16, sr, stream=821, lo=1, hi=hi)
+    bs = I.disjoint_batches(A, sr, [200, 30000], stream=822, value_lo=1, value_hi=hi)
+    prods = {}
+    for mode in (1, 2, 0):  # rows, entries, automatic
+        t = ctx.get_tuning()
+        t.update_path = mode
+        ctx.set_tuning(t)
+        m = dsg.Matrix.from_csr(ctx, A, sr)
+        P = dsg.Product(ctx, m, m)
+        st, Cs = [], []
+        for b in bs:
+            m.apply_batch(b)
+            P.update()
+            st.append(P.stats())
+            Cs.append(P.export())
+        prods[mode] = (st, Cs)
+        P.destroy()
+        m.destroy()
+    ctx.set_tuning(None)
+    chosen = []
+    for k in range(len(bs)):
+        rule = prods[1][0][k]["flops"] > 55e6 + 200 * prods[2][0][k]["terms"]
+        assert prods[0][0][k]["path"] == (1 if rule else 0), f"batch {k}"
+        chosen.append(prods[0][0][k]["path"])
+        for mode in (0, 2):
+            x, y = prods[mode][1][k], prods[1][1][k]
+            assert np.array_equal(x.row_ptr, y.row_ptr) and np.array_equal(x.col, y.col)
+            assert np.asarray(x.val).tobytes() == np.asarray(y.val).tobytes(), f"batch {k} mode {mode}"
+    assert chosen == [1, 0]
