@@ -33,9 +33,12 @@ constexpr int NBINS = 10;
 constexpr int BIN_DENSE = 8;
 constexpr int BIN_GLOBAL = 9;
 constexpr int NSTAT = 7;  // rows, a_entries, flops, nnz_new, nnz_old, old_read, written
-// Workgroup of the one-row-per-workgroup bins: 8 wavefronts, so each lane
-// may hold 256 VGPRs and keep several gathers in flight.
+// Workgroups of the one-row-per-workgroup bins.  The dense bin holds one
+// workgroup per CU (its accumulator fills the LDS), so its size sets how many
+// wavefronts hide the latency of each row's gathers.
+// (512: at 1024 lanes the kernel spills registers and runs slower.)
 constexpr int DENSE_WG = 512;
+constexpr int GLOBAL_WG = 512;
 constexpr int DENSE_ACHUNK = 512;
 
 template <int VSZ>
@@ -470,8 +473,8 @@ struct ChunkSplit {
   int32_t nlong, nshort;
 };
 
-template <class V>
-__device__ inline void split_chunk(const AChunk<V>& ch, int cnt, ChunkSplit& sp, const Grp<DENSE_WG>& grp,
+template <class V, int WG>
+__device__ inline void split_chunk(const AChunk<V>& ch, int cnt, ChunkSplit& sp, const Grp<WG>& grp,
                                    int* wscr) {
   const int lane = grp.lane;
   const bool act = lane < cnt;
@@ -503,9 +506,9 @@ __device__ inline void split_chunk(const AChunk<V>& ch, int cnt, ChunkSplit& sp,
 
 // Stage A entries [cbase, cbase+cnt) and prefix sums of their B-row lengths.
 // Returns the chunk's flop count.  Whole-workgroup call.
-template <class V>
+template <class V, int WG>
 __device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d, int32_t cbase, AChunk<V>& ch,
-                                      const Grp<DENSE_WG>& grp, int* wscr, bool sort_k) {
+                                      const Grp<WG>& grp, int* wscr, bool sort_k) {
   const int lane = grp.lane;
   const int32_t t = cbase + lane;
   const bool act = lane < DENSE_ACHUNK && t < d;
@@ -544,6 +547,21 @@ __device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d,
 // bin 8: dense LDS accumulator over column chunks, one workgroup per row
 // ---------------------------------------------------------------------------
 
+// Value of lane src of a VGPR (src uniform), 64-bit and value-typed forms.
+__device__ inline int64_t lane64(int64_t v, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), src);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class V>
+__device__ inline V lanev(V v, int src) {
+  if constexpr (sizeof(V) == 4) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+  } else {
+    return __builtin_bit_cast(V, lane64(__builtin_bit_cast(int64_t, v), src));
+  }
+}
+
 template <int SR>
 __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_t* list,
                                                          const unsigned long long* d_cnt) {
@@ -551,11 +569,15 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   using V = typename S::V;
   using Acc = typename S::Acc;
   constexpr int CH = dense_cols<sizeof(V)>();
-  // (min,+): an untouched slot still holds the identity key, so no bitmap is
-  // needed; (+,x) needs one because 0 is a legitimate sum.
-  constexpr bool kBits = SR != 1;
+  constexpr int NWV = DENSE_WG / 64;
+  constexpr int NW32 = CH / 32;       // bitmap words per column chunk
+  constexpr int SEGW = NW32 / NWV;    // words of the segment each wavefront drains
+  constexpr int SEG = SEGW * 32;      // columns of that segment
+  static_assert(SEGW >= 2 && SEGW % 2 == 0, "segments are walked 64 columns at a time");
+  // The accumulator and its touched-column bitmap are all identity / zero
+  // between chunks and rows: the drain that reads a chunk out clears it.
   __shared__ Acc acc[CH];
-  __shared__ uint32_t bits[kBits ? CH / 32 : 1];
+  __shared__ uint32_t bits[NW32];
   __shared__ AChunk<V> ch;
   __shared__ ChunkSplit sp;
   __shared__ int wscr[16];
@@ -563,8 +585,12 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   __shared__ int32_t next_row;
   const Grp<DENSE_WG> grp;
   const int tid = threadIdx.x;
+  const int wv = tid >> 6, ln = tid & 63;
+  const uint64_t lt = ln ? (~0ull >> (64 - ln)) : 0ull;
   if (R.defer && *R.defer) return;
   const int64_t count = (int64_t)*d_cnt;
+  for (int x = tid; x < CH; x += DENSE_WG) acc[x] = S::identity();
+  for (int x = tid; x < NW32; x += DENSE_WG) bits[x] = 0u;
   // persistent: rows are taken in list order (longest first) from a counter
   for (;;) {
   if (tid == 0) next_row = (int32_t)atomicAdd(R.dense_next, 1u);
@@ -605,10 +631,6 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   for (int pc = 0; pc < passes; ++pc) {
     const int32_t c0 = pc * CH;
     const int32_t c1 = min(c0 + CH, R.ncols);
-    for (int x = tid; x < CH; x += DENSE_WG) acc[x] = S::identity();
-    if constexpr (kBits)
-      for (int x = tid; x < CH / 32; x += DENSE_WG) bits[x] = 0u;
-    grp.sync();
     // MLP rounds of UNR independent flops per lane: all loads first, then the
     // LDS updates, so each lane keeps UNR gathers in flight
     constexpr int UNR = 8;
@@ -626,7 +648,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
           if (j[u] >= c0 && j[u] < c1) {
             const int x = j[u] - c0;
             S::atomic_combine(&acc[x], S::mul(av[u], bv[u]));
-            if constexpr (kBits) atomicOr(&bits[x >> 5], 1u << (x & 31));
+            atomicOr(&bits[x >> 5], 1u << (x & 31));
           }
         }
       }
@@ -637,32 +659,41 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       if (pc == 0) flops += tot;
       if constexpr (S::order_free) {
         split_chunk<V>(ch, cnt, sp, grp, wscr);
-        // long B rows as 64-entry tiles, UNR tiles per wavefront per round
-        const int wv = tid >> 6, ln = tid & 63;
+        // Long B rows as 64-entry tiles; wavefront w takes UNR consecutive
+        // tiles per round, rounds TSTRIDE tiles apart.  Lane l describes the
+        // (l % UNR)-th tile of the (l / UNR)-th of the next eight rounds (one
+        // segment search per lane), and each round reads its tiles' base,
+        // length and A value from those lanes.
+        static_assert(UNR == 8, "eight rounds of eight tiles per description");
+        constexpr int TSTRIDE = NWV * UNR;
         const int nl = sp.nlong;
         const int ntiles = sp.tpre[nl];
-        for (int tb = wv * UNR; tb < ntiles; tb += (DENSE_WG / 64) * UNR) {
-          int64_t pos[UNR];
-          V av[UNR];
-          bool ok[UNR];
-#pragma unroll
-          for (int u = 0; u < UNR; ++u) {
-            const int tile = tb + u;
-            ok[u] = false;
-            pos[u] = 0;
-            av[u] = V(0);
-            if (tile < ntiles) {
-              const int e = find_seg(sp.tpre, nl, tile);
-              const int t = sp.lidx[e];
-              const int32_t x = ((tile - sp.tpre[e]) << 6) + ln;
-              if (x < ch.pre[t + 1] - ch.pre[t]) {
-                ok[u] = true;
-                pos[u] = ch.b[t] + x;
-                av[u] = ch.a[t];
-              }
-            }
+        for (int tb0 = wv * UNR; tb0 < ntiles; tb0 += TSTRIDE * 8) {
+          const int my = tb0 + (ln >> 3) * TSTRIDE + (ln & 7);
+          int64_t mpos = 0;
+          V ma = V(0);
+          int32_t mrem = 0;
+          if (my < ntiles) {
+            const int e = find_seg(sp.tpre, nl, my);
+            const int t = sp.lidx[e];
+            const int32_t x0 = (my - sp.tpre[e]) << 6;
+            mrem = min(64, ch.pre[t + 1] - ch.pre[t] - x0);
+            mpos = ch.b[t] + x0;
+            ma = ch.a[t];
           }
-          accumulate_round(pos, av, ok);
+          for (int r = 0; r < 8 && tb0 + r * TSTRIDE < ntiles; ++r) {
+            int64_t pos[UNR];
+            V av[UNR];
+            bool ok[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+              const int src = r * UNR + u;
+              ok[u] = ln < __builtin_amdgcn_readlane(mrem, src);
+              pos[u] = lane64(mpos, src) + ln;
+              av[u] = lanev<V>(ma, src);
+            }
+            accumulate_round(pos, av, ok);
+          }
         }
         // short B rows: 8-lane sub-groups, each streaming 4 rows at once (no
         // search; 4 gathers in flight per lane)
@@ -724,28 +755,24 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       }
       grp.sync();
     }
-    // counts of this column chunk: wavefront w owns columns [w*SEG, (w+1)*SEG)
-    // and walks them 64 at a time (bank-conflict-free LDS reads)
-    auto touched = [&](int x) -> bool {
-      if constexpr (kBits) return (bits[x >> 5] >> (x & 31)) & 1u;
-      else return acc[x] != S::identity();
-    };
-    constexpr int NWV = DENSE_WG / 64;
-    constexpr int SEG = CH / NWV;
-    const int cwv = tid >> 6, cln = tid & 63;
-    const uint64_t clt = cln ? (~0ull >> (64 - cln)) : 0ull;
+    // entries of this chunk from the bitmap: wavefront w owns columns
+    // [w*SEG, (w+1)*SEG)
     int32_t mine = 0;
-    for (int r = 0; r < SEG; r += 64) mine += __popcll(__ballot(touched(cwv * SEG + r + cln)));
-    if (cln == 0) wscr[cwv] = mine;
+    for (int w = ln; w < SEGW; w += 64) mine += __popc(bits[wv * SEGW + w]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+    if (ln == 0) wscr[wv] = mine;
     grp.sync();
     int32_t before = 0, ctot = 0;
     for (int x = 0; x < NWV; ++x) {
       const int32_t c = wscr[x];
-      if (x < cwv) before += c;
+      if (x < wv) before += c;
       ctot += c;
     }
     grp.sync();
-    // compare the old entries that fall into this chunk (4 loads in flight per lane)
+    // compare the old entries that fall into this chunk (4 loads in flight per
+    // lane).  (min,+): an untouched slot holds the identity key, which no
+    // stored value maps to, so the key comparison alone decides.
     if (!changed) {
       int32_t in_chunk = 0;
       bool bad = false;
@@ -763,7 +790,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
           if (oc[u] >= c0 && oc[u] < c1) {
             ++in_chunk;
             const int x = oc[u] - c0;
-            bad |= !touched(x) || !same_bits(acc[x], S::to_acc(ov[u]));
+            const bool hit = SR == 1 || ((bits[x >> 5] >> (x & 31)) & 1u);
+            bad |= !hit || !same_bits(acc[x], S::to_acc(ov[u]));
           }
         }
       }
@@ -772,26 +800,31 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       if (grp.any(bad, wscr) || itot != ctot) changed = true;
       old_read = olen;
     }
-    // the chunk's entries in ascending column order, to out[base + ...]
-    auto emit = [&](int32_t* ocol, V* oval, int64_t base, int32_t limit) {
+    // Read the chunk out 64 columns at a time in ascending column order (to
+    // out[base + ...] when writing) and clear what was read.
+    auto drain = [&](int32_t* ocol, V* oval, int64_t base, int32_t limit, bool write) {
       int32_t o = before;
       for (int r = 0; r < SEG; r += 64) {
-        const int x = cwv * SEG + r + cln;
-        const bool tch = touched(x);
-        const uint64_t b = __ballot(tch);
-        if (tch) {
-          const int32_t pos = o + __popcll(b & clt);
-          if (base + pos < limit) {
-            ocol[base + pos] = c0 + x;
-            oval[base + pos] = S::from_acc(acc[x]);
+        const int w0 = (wv * SEG + r) >> 5;
+        const uint64_t b = (uint64_t)bits[w0] | ((uint64_t)bits[w0 + 1] << 32);
+        if ((b >> ln) & 1ull) {
+          const int x = wv * SEG + r + ln;
+          if (write) {
+            const int32_t pos = o + __popcll(b & lt);
+            if (base + pos < limit) {
+              ocol[base + pos] = c0 + x;
+              oval[base + pos] = S::from_acc(acc[x]);
+            }
           }
+          acc[x] = S::identity();
         }
         o += __popcll(b);
       }
+      for (int w = ln; w < SEGW; w += 64) bits[wv * SEGW + w] = 0u;
     };
     if (pc + 1 < passes) {
       // not the last chunk: park its entries in the staging space
-      emit(scol, sval, nnew, stage_n);
+      drain(scol, sval, nnew, stage_n, true);
       nnew += ctot;
       grp.sync();
       continue;
@@ -811,6 +844,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
         dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
         if (dest < 0) {
           if (tid == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
+          drain(nullptr, nullptr, 0, 0, false);
           parked = true;
           break;
         }
@@ -835,7 +869,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
           }
         }
       }
-      emit(R.c_col + dest, (V*)R.c_val + dest, staged, nnew);
+      drain(R.c_col + dest, (V*)R.c_val + dest, staged, nnew, true);
       if (tid == 0) {
         R.c_len[i] = nnew;
         if (ncap) {
@@ -843,6 +877,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
           R.c_cap[i] = ncap;
         }
       }
+    } else {
+      drain(nullptr, nullptr, 0, 0, false);
     }
     grp.sync();
   }
@@ -907,7 +943,7 @@ __device__ inline int64_t ghash_find(const int32_t* keys, int64_t slots, int32_t
 }
 
 template <int SR>
-__global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32_t* list,
+__global__ __launch_bounds__(GLOBAL_WG) void k_rows_global(RowArgs R, const int32_t* list,
                                                           const unsigned long long* d_cnt) {
   using S = Sem<SR>;
   using V = typename S::V;
@@ -915,7 +951,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
   __shared__ AChunk<V> ch;
   __shared__ int wscr[16];
   __shared__ int64_t bslot;
-  const Grp<DENSE_WG> grp;
+  const Grp<GLOBAL_WG> grp;
   const int tid = threadIdx.x;
   if (R.defer && *R.defer) return;
   const int64_t count = (int64_t)*d_cnt;
@@ -936,7 +972,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
   }
   int32_t* keys = (int32_t*)(R.arena + tb);
   Acc* vals = (Acc*)(R.arena + tb + (size_t)slots * 4);
-  for (int64_t s = tid; s < slots; s += DENSE_WG) {
+  for (int64_t s = tid; s < slots; s += GLOBAL_WG) {
     __hip_atomic_store(&keys[s], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&vals[s], S::identity(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
@@ -949,7 +985,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
     int32_t tot = stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, !S::order_free);
     flops += tot;
     if constexpr (S::order_free) {
-      for (int32_t fb = 0; fb < tot; fb += DENSE_WG) {
+      for (int32_t fb = 0; fb < tot; fb += GLOBAL_WG) {
         int32_t f = fb + tid;
         if (f < tot) {
           int ts = find_seg(ch.pre, cnt, f);
@@ -966,7 +1002,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
         const int32_t blen = ch.pre[ts + 1] - ch.pre[ts];
         const int64_t bo = ch.b[ts];
         const V av = ch.a[ts];
-        for (int32_t e = tid; e < blen; e += DENSE_WG) {
+        for (int32_t e = tid; e < blen; e += GLOBAL_WG) {
           Acc p = S::mul(av, ldv<V>(R.b_val, bo + e));
           bool fresh;
           int64_t h = ghash_insert(keys, slots, R.b_col[bo + e], fresh);
@@ -991,7 +1027,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
     continue;
   }
   int32_t nnew = 0;
-  for (int64_t sb = 0; sb < slots; sb += DENSE_WG) {
+  for (int64_t sb = 0; sb < slots; sb += GLOBAL_WG) {
     int tot;
     grp.rank(aload(&keys[sb + tid]) != -1, tot, wscr);
     nnew += tot;
@@ -1002,7 +1038,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
   int64_t old_read = 0;
   if (!changed) {
     old_read = olen;
-    for (int32_t ob = 0; ob < olen; ob += DENSE_WG) {
+    for (int32_t ob = 0; ob < olen; ob += GLOBAL_WG) {
       int32_t e = ob + tid;
       bool bad = false;
       if (e < olen) {
@@ -1020,14 +1056,14 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_global(RowArgs R, const int32
     int32_t ncap = 0;
     if (nnew > R.c_cap[i]) {
       ncap = slack_cap(nnew);
-      dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
+      dest = take_pool<GLOBAL_WG>(R, ncap, grp, &bslot);
       if (dest < 0) {
         if (tid == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
         continue;
       }
     }
     int32_t w = 0;
-    for (int64_t sb = 0; sb < slots; sb += DENSE_WG) {
+    for (int64_t sb = 0; sb < slots; sb += GLOBAL_WG) {
       const int64_t s = sb + tid;
       const int32_t key = aload(&keys[s]);
       int tot;
@@ -1311,7 +1347,7 @@ void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, 
       }
       case BIN_GLOBAL: {
         const unsigned grid = (unsigned)(plan ? cnt : std::min<int64_t>(cnt, cus * 2));
-        hipLaunchKernelGGL((k_rows_global<SR>), dim3(grid), dim3(DENSE_WG), 0, s, R, list, dc);
+        hipLaunchKernelGGL((k_rows_global<SR>), dim3(grid), dim3(GLOBAL_WG), 0, s, R, list, dc);
         break;
       }
     }
