@@ -265,6 +265,11 @@ struct DProd {
   size_t ews_bytes = 0;
   void* srt = nullptr;            // column-sorted copy of A (entry-granular path)
   size_t srt_bytes = 0;
+  void* bsp = nullptr;            // B with each row's entries grouped by dense column chunk
+  size_t bsp_bytes = 0;
+  size_t bsp_col_off = 0, bsp_val_off = 0;
+  int bsp_parts = 0;
+  bool bsp_live = false;          // bsp holds the current B for the running update
   int64_t entry_nU = 0;           // entry-granular path: log entries and changed
   int64_t entry_nterm = 0;        // products counted for the pending update
   int refs = 0;                   // batched executors and servers using this product

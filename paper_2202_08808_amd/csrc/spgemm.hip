@@ -81,6 +81,12 @@ struct RowArgs {
   uint8_t* retry;            // per q: row could not be placed, recompute it
   unsigned long long* c_short;      // C slots the flagged rows need
   unsigned long long* arena_short;  // arena bytes the flagged rows need
+  // B split by dense column chunk (bs_parts > 0): part p of row k spans
+  // [bs_ps[k*bs_parts + p], bs_ps[k*bs_parts + p + 1]) of bs_col / bs_val
+  int32_t bs_parts;
+  const int64_t* bs_ps;
+  const int32_t* bs_col;
+  const void* bs_val;
 };
 
 // Per-row work record, summed per bin by k_reduce_stats.
@@ -506,9 +512,10 @@ __device__ inline void split_chunk(const AChunk<V>& ch, int cnt, ChunkSplit& sp,
 
 // Stage A entries [cbase, cbase+cnt) and prefix sums of their B-row lengths.
 // Returns the chunk's flop count.  Whole-workgroup call.
+// part >= 0: B rows are the entries of column chunk `part` in the split copy.
 template <class V, int WG>
 __device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d, int32_t cbase, AChunk<V>& ch,
-                                      const Grp<WG>& grp, int* wscr, bool sort_k) {
+                                      const Grp<WG>& grp, int* wscr, bool sort_k, int part = -1) {
   const int lane = grp.lane;
   const int32_t t = cbase + lane;
   const bool act = lane < DENSE_ACHUNK && t < d;
@@ -518,8 +525,14 @@ __device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d,
   if (act) {
     k = R.a_col[aoff + t];
     a = ldv<V>(R.a_val, aoff + t);
-    len = R.b_len[k];
-    boff = R.b_off[k];
+    if (part >= 0) {
+      const int64_t* ps = R.bs_ps + (int64_t)k * R.bs_parts + part;
+      boff = ps[0];
+      len = (int32_t)(ps[1] - boff);
+    } else {
+      len = R.b_len[k];
+      boff = R.b_off[k];
+    }
   }
   int32_t tot;
   int32_t incl = grp.scan(len, tot, wscr);
@@ -628,6 +641,10 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   int32_t nnew = 0;
   int64_t flops = 0;
   int64_t old_read = 0;
+  // with the split copy of B each pass streams only its own column chunk
+  const bool split = R.bs_parts == passes && passes > 1;
+  const int32_t* bcol = split ? R.bs_col : R.b_col;
+  const void* bval = split ? R.bs_val : R.b_val;
   for (int pc = 0; pc < passes; ++pc) {
     const int32_t c0 = pc * CH;
     const int32_t c1 = min(c0 + CH, R.ncols);
@@ -639,8 +656,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       V bv[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        j[u] = ok[u] ? R.b_col[pos[u]] : -1;
-        bv[u] = ok[u] ? ldv<V>(R.b_val, pos[u]) : V(0);
+        j[u] = ok[u] ? bcol[pos[u]] : -1;
+        bv[u] = ok[u] ? ldv<V>(bval, pos[u]) : V(0);
       }
       if constexpr (S::order_free) {
 #pragma unroll
@@ -655,8 +672,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     };
     for (int32_t cbase = 0; cbase < d; cbase += DENSE_ACHUNK) {
       const int cnt = min(DENSE_ACHUNK, d - cbase);
-      int32_t tot = stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, !S::order_free);
-      if (pc == 0) flops += tot;
+      int32_t tot = stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, !S::order_free, split ? pc : -1);
+      if (split || pc == 0) flops += tot;
       if constexpr (S::order_free) {
         split_chunk<V>(ch, cnt, sp, grp, wscr);
         // Long B rows as 64-entry tiles; wavefront w takes UNR consecutive
@@ -741,10 +758,10 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
           const int64_t bo = ch.b[ts];
           const V av = ch.a[ts];
           for (int32_t e = tid; e < blen; e += DENSE_WG) {
-            int32_t j = R.b_col[bo + e];
+            int32_t j = bcol[bo + e];
             if (j >= c0 && j < c1) {
               int x = j - c0;
-              Acc p = S::mul(av, ldv<V>(R.b_val, bo + e));
+              Acc p = S::mul(av, ldv<V>(bval, bo + e));
               uint32_t m = 1u << (x & 31);
               uint32_t was = atomicOr(&bits[x >> 5], m);
               acc[x] = (was & m) ? __dadd_rn(acc[x], p) : p;
@@ -1435,6 +1452,126 @@ void ensure_arena(DProd* p, size_t bytes) {
   p->arena_bytes = nb;
 }
 
+// ---------------------------------------------------------------------------
+// B split by dense column chunk: the dense bin's passes each stream only the
+// entries of their own chunk instead of every entry of every B row
+// ---------------------------------------------------------------------------
+
+constexpr int BSPLIT_MAXP = 8;
+
+// one wavefront per row of B: entries per column chunk into ps[k*P + q]
+__global__ __launch_bounds__(256) void k_bsplit_count(const int64_t* b_off, const int32_t* b_len,
+                                                      const int32_t* b_col, int32_t n, int P, int chbits,
+                                                      int64_t* ps) {
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int ln = threadIdx.x & 63;
+  if (k == 0 && ln == 0) ps[(int64_t)n * P] = 0;
+  if (k >= n) return;
+  const int64_t off = b_off[k];
+  const int32_t len = b_len[k];
+  int64_t cnt[BSPLIT_MAXP];
+#pragma unroll
+  for (int q = 0; q < BSPLIT_MAXP; ++q) cnt[q] = 0;
+  for (int32_t e0 = 0; e0 < len; e0 += 64) {
+    const int32_t e = e0 + ln;
+    const int part = e < len ? (b_col[off + e] >> chbits) : -1;
+#pragma unroll
+    for (int q = 0; q < BSPLIT_MAXP; ++q)
+      if (q < P) cnt[q] += __popcll(__ballot(part == q));
+  }
+  if (ln == 0) {
+#pragma unroll
+    for (int q = 0; q < BSPLIT_MAXP; ++q)
+      if (q < P) ps[k * P + q] = cnt[q];
+  }
+}
+
+// one wavefront per row of B: entries to their chunk's segment, in row order
+template <int VSZ>
+__global__ __launch_bounds__(256) void k_bsplit_scatter(const int64_t* b_off, const int32_t* b_len,
+                                                        const int32_t* b_col, const void* b_val, int32_t n, int P,
+                                                        int chbits, const int64_t* ps, int32_t* out_col,
+                                                        void* out_val) {
+  using W = typename std::conditional<VSZ == 8, uint64_t, uint32_t>::type;
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int ln = threadIdx.x & 63;
+  if (k >= n) return;
+  const int64_t off = b_off[k];
+  const int32_t len = b_len[k];
+  const uint64_t lt = ln ? (~0ull >> (64 - ln)) : 0ull;
+  int64_t o[BSPLIT_MAXP];
+#pragma unroll
+  for (int q = 0; q < BSPLIT_MAXP; ++q) o[q] = q < P ? ps[k * P + q] : 0;
+  for (int32_t e0 = 0; e0 < len; e0 += 64) {
+    const int32_t e = e0 + ln;
+    const int32_t col = e < len ? b_col[off + e] : 0;
+    const int part = e < len ? (col >> chbits) : -1;
+    int64_t dst = -1;
+#pragma unroll
+    for (int q = 0; q < BSPLIT_MAXP; ++q) {
+      if (q < P) {
+        const uint64_t m = __ballot(part == q);
+        if (part == q) dst = o[q] + __popcll(m & lt);
+        o[q] += __popcll(m);
+      }
+    }
+    if (dst >= 0) {
+      out_col[dst] = col;
+      ((W*)out_val)[dst] = ((const W*)b_val)[off + e];
+    }
+  }
+}
+
+size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Build the split copy of B for this update (when the dense bin needs more
+// than one pass); leaves p->bsp_live set.
+void build_bsplit(DProd* p) {
+  Ctx* c = p->ctx;
+  hipStream_t s = c->stream;
+  DMat* B = p->B;
+  const int vsz = p->C->vsz;
+  const int P = dense_passes_for(vsz, B->ncols);
+  p->bsp_live = false;
+  if (P < 2 || P > BSPLIT_MAXP || B->nrows == 0) return;
+  const int chbits = vsz == 8 ? 14 : 15;
+  static_assert(dense_cols<8>() == (1 << 14) && dense_cols<4>() == (1 << 15), "chunk widths");
+  const int64_t nps = (int64_t)B->nrows * P + 1;
+  const int64_t cap = std::max<int64_t>(B->h_top_ub, 1);
+  const size_t col_off = round256((size_t)nps * 8);
+  const size_t val_off = col_off + round256((size_t)cap * 4);
+  const size_t bytes = val_off + round256((size_t)cap * vsz);
+  if (bytes > p->bsp_bytes) {
+    if (p->bsp) ctx_free(c, p->bsp, p->bsp_bytes);
+    p->bsp = nullptr;
+    p->bsp_bytes = 0;
+    const size_t nb = bytes + bytes / 4;
+    p->bsp = ctx_alloc(c, nb);
+    p->bsp_bytes = nb;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) ctx_timing_begin(c, "b_split", (double)cap * (4 + vsz) * 2, &e0, &e1);
+  int64_t* ps = (int64_t*)p->bsp;
+  int32_t* ocol = (int32_t*)((char*)p->bsp + col_off);
+  void* oval = (char*)p->bsp + val_off;
+  const unsigned nb = (unsigned)blocks_for((int64_t)B->nrows * 64, 256);
+  hipLaunchKernelGGL(k_bsplit_count, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->nrows, P,
+                     chbits, ps);
+  exclusive_scan_i64(ps, ps, nps, nullptr, ctx_scratch2(c, scan_scratch_bytes(nps)), s);
+  if (vsz == 8)
+    hipLaunchKernelGGL(k_bsplit_scatter<8>, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->val,
+                       B->nrows, P, chbits, (const int64_t*)ps, ocol, oval);
+  else
+    hipLaunchKernelGGL(k_bsplit_scatter<4>, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->val,
+                       B->nrows, P, chbits, (const int64_t*)ps, ocol, oval);
+  DSG_HIP(hipGetLastError());
+  if (c->timing) ctx_timing_end(c, e1);
+  p->bsp_col_off = col_off;
+  p->bsp_val_off = val_off;
+  p->bsp_parts = P;
+  p->bsp_live = true;
+}
+
 RowArgs row_args(DProd* p, ProdWork& w, int mode, bool report_affected) {
   DMat* A = p->A;
   DMat* B = p->B;
@@ -1457,6 +1594,16 @@ RowArgs row_args(DProd* p, ProdWork& w, int mode, bool report_affected) {
   R.retry = w.retry;
   R.c_short = &w.plan->c_short;
   R.arena_short = &w.plan->arena_short;
+  R.bs_parts = 0;
+  R.bs_ps = nullptr;
+  R.bs_col = nullptr;
+  R.bs_val = nullptr;
+  if (p->bsp_live) {
+    R.bs_parts = p->bsp_parts;
+    R.bs_ps = (const int64_t*)p->bsp;
+    R.bs_col = (const int32_t*)((char*)p->bsp + p->bsp_col_off);
+    R.bs_val = (const char*)p->bsp + p->bsp_val_off;
+  }
   return R;
 }
 
@@ -1590,9 +1737,14 @@ int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, int
   // the arena keeps the largest size used so far, up to the analysis bound
   if (plan.arena_demand > p->arena_bytes) ensure_arena(p, std::min<size_t>(plan.arena_demand, std::max<size_t>(p->arena_bytes * 2, (size_t)64 << 20)));
   ensure_changed_cap(p, plan.count);
-  R = row_args(p, w, mode, report_affected);
   // the dense bin runs persistent workgroups: hand them the longest rows first
   const int64_t ndense = (int64_t)plan.bin_count[BIN_DENSE];
+  struct SplitLive {  // the split copy of B serves this update only
+    DProd* p;
+    ~SplitLive() { p->bsp_live = false; }
+  } split_live{p};
+  if (ndense > 0) build_bsplit(p);
+  R = row_args(p, w, mode, report_affected);
   if (ndense > 1) {
     int32_t* dl = w.bins + (int64_t)BIN_DENSE * n;
     const size_t nb = Carve::need({(size_t)ndense * 8, (size_t)ndense * 4, radix_scratch_bytes(ndense)});
@@ -1687,6 +1839,7 @@ void prod_destroy(DProd* p) {
   if (p->d_sync) ctx_free(c, p->d_sync, 16);
   if (p->ews) ctx_free(c, p->ews, p->ews_bytes);
   if (p->srt) ctx_free(c, p->srt, p->srt_bytes);
+  if (p->bsp) ctx_free(c, p->bsp, p->bsp_bytes);
   if (p->C) mat_destroy(p->C);
   if (p->A) p->A->refs--;
   if (p->B) p->B->refs--;
