@@ -560,6 +560,13 @@ __device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d,
 // bin 8: dense LDS accumulator over column chunks, one workgroup per row
 // ---------------------------------------------------------------------------
 
+// Orders the LDS accesses of the lanes of one wavefront.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Value of lane src of a VGPR (src uniform), 64-bit and value-typed forms.
 __device__ inline int64_t lane64(int64_t v, int src) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
@@ -591,8 +598,24 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   // between chunks and rows: the drain that reads a chunk out clears it.
   __shared__ Acc acc[CH];
   __shared__ uint32_t bits[NW32];
-  __shared__ AChunk<V> ch;
-  __shared__ ChunkSplit sp;
+  // The A chunk and its split are dead while a chunk is drained, so their
+  // space doubles as the wavefronts' output buffers.
+  constexpr int OBN = sizeof(V) == 4 ? 256 : 192;  // buffered entries per wavefront
+  struct OutBuf {
+    int32_t col[NWV][OBN];
+    V val[NWV][OBN];
+  };
+  struct InBuf {
+    AChunk<V> ch;
+    ChunkSplit sp;
+  };
+  union Stage {
+    InBuf in;
+    OutBuf out;
+  };
+  __shared__ Stage st;
+  AChunk<V>& ch = st.in.ch;
+  ChunkSplit& sp = st.in.sp;
   __shared__ int wscr[16];
   __shared__ int64_t bslot;
   __shared__ int32_t next_row;
@@ -637,6 +660,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   }
 
   bool changed = R.force_write;
+  bool direct = false;  // the chunks drained so far sit in the row's own place in C
   bool fault = false, parked = false;
   int32_t nnew = 0;
   int64_t flops = 0;
@@ -817,31 +841,83 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       if (grp.any(bad, wscr) || itot != ctot) changed = true;
       old_read = olen;
     }
-    // Read the chunk out 64 columns at a time in ascending column order (to
-    // out[base + ...] when writing) and clear what was read.
+    // Read the chunk out 64 columns at a time in ascending column order and
+    // clear what was read.  When writing, each wavefront packs its entries
+    // into its LDS buffer and stores them to out[base + ...] in full runs.
     auto drain = [&](int32_t* ocol, V* oval, int64_t base, int32_t limit, bool write) {
-      int32_t o = before;
+      int32_t* bc = st.out.col[wv];
+      V* bv = st.out.val[wv];
+      int32_t o = before;  // row position of the first buffered entry
+      int32_t nb = 0;
+      auto flush = [&]() {
+        wave_sync();
+        for (int e = ln; e < nb; e += 64) {
+          const int64_t pos = base + o + e;
+          if (pos < limit) {
+            ocol[pos] = bc[e];
+            oval[pos] = bv[e];
+          }
+        }
+        wave_sync();
+        o += nb;
+        nb = 0;
+      };
       for (int r = 0; r < SEG; r += 64) {
         const int w0 = (wv * SEG + r) >> 5;
         const uint64_t b = (uint64_t)bits[w0] | ((uint64_t)bits[w0 + 1] << 32);
+        if (write && nb + 64 > OBN) flush();
         if ((b >> ln) & 1ull) {
           const int x = wv * SEG + r + ln;
           if (write) {
-            const int32_t pos = o + __popcll(b & lt);
-            if (base + pos < limit) {
-              ocol[base + pos] = c0 + x;
-              oval[base + pos] = S::from_acc(acc[x]);
-            }
+            const int k = nb + __popcll(b & lt);
+            bc[k] = c0 + x;
+            bv[k] = S::from_acc(acc[x]);
           }
           acc[x] = S::identity();
         }
-        o += __popcll(b);
+        nb += __popcll(b);
       }
+      if (write) flush();
       for (int w = ln; w < SEGW; w += 64) bits[wv * SEGW + w] = 0u;
     };
+    // cnt entries from (sc, sv) to (dc, dv), 4 loads in flight per lane
+    auto copy_entries = [&](const int32_t* sc, const V* sv, int32_t* dc, V* dv, int32_t cnt) {
+      for (int32_t e0 = tid; e0 < cnt; e0 += 4 * DENSE_WG) {
+        int32_t cc[4];
+        V vv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t e = e0 + u * DENSE_WG;
+          cc[u] = e < cnt ? sc[e] : 0;
+          vv[u] = e < cnt ? sv[e] : V(0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int32_t e = e0 + u * DENSE_WG;
+          if (e < cnt) {
+            dc[e] = cc[u];
+            dv[e] = vv[u];
+          }
+        }
+      }
+    };
+    int32_t* const ccol = R.c_col + ooff;
+    V* const cval = (V*)R.c_val + ooff;
+    const int32_t ccap = R.c_cap[i];
     if (pc + 1 < passes) {
-      // not the last chunk: park its entries in the staging space
-      drain(scol, sval, nnew, stage_n, true);
+      // Not the last chunk.  A row already known to change whose chunks so
+      // far fit its place in C goes straight there; otherwise the chunk is
+      // parked in the staging space.
+      if (direct && nnew + ctot > ccap) {
+        // (rows of three chunks or more) it outgrew its place: what is in C
+        // moves to the staging space, and staging goes on from there
+        copy_entries(ccol, cval, scol, sval, min(nnew, stage_n));
+        direct = false;
+      } else if (pc == 0 && changed && ctot <= ccap) {
+        direct = true;
+      }
+      if (direct) drain(ccol, cval, nnew, ccap, true);
+      else drain(scol, sval, nnew, stage_n, true);
       nnew += ctot;
       grp.sync();
       continue;
@@ -854,39 +930,29 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       break;
     }
     if (changed) {
+      const int32_t prev = nnew - ctot;  // entries of the earlier chunks
       int64_t dest = ooff;
       int32_t ncap = 0;
-      if (nnew > R.c_cap[i]) {
+      if (nnew > ccap) {
         ncap = slack_cap(nnew);
         dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
         if (dest < 0) {
-          if (tid == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
+          if (tid == 0) {
+            // its place may already hold new entries: as an empty row it is
+            // seen (and reported) as changed when it is recomputed
+            if (direct) R.c_len[i] = 0;
+            mark_retry(R, q, R.c_short, (unsigned long long)ncap);
+          }
           drain(nullptr, nullptr, 0, 0, false);
           parked = true;
           break;
         }
       }
-      // earlier chunks from the staging space (4 loads in flight per lane)
-      const int32_t staged = nnew - ctot;
-      for (int32_t e0 = tid; e0 < staged; e0 += 4 * DENSE_WG) {
-        int32_t sc[4];
-        V sv[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int32_t e = e0 + u * DENSE_WG;
-          sc[u] = e < staged ? scol[e] : 0;
-          sv[u] = e < staged ? sval[e] : V(0);
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int32_t e = e0 + u * DENSE_WG;
-          if (e < staged) {
-            R.c_col[dest + e] = sc[u];
-            ((V*)R.c_val)[dest + e] = sv[u];
-          }
-        }
-      }
-      drain(R.c_col + dest, (V*)R.c_val + dest, staged, nnew, true);
+      // earlier chunks: from the staging space, or from the row's old place
+      // when it moves
+      if (!direct) copy_entries(scol, sval, R.c_col + dest, (V*)R.c_val + dest, prev);
+      else if (dest != ooff) copy_entries(ccol, cval, R.c_col + dest, (V*)R.c_val + dest, prev);
+      drain(R.c_col + dest, (V*)R.c_val + dest, prev, nnew, true);
       if (tid == 0) {
         R.c_len[i] = nnew;
         if (ncap) {
