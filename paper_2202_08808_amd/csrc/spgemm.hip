@@ -674,7 +674,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     const int32_t c1 = min(c0 + CH, R.ncols);
     // MLP rounds of UNR independent flops per lane: all loads first, then the
     // LDS updates, so each lane keeps UNR gathers in flight
-    constexpr int UNR = 8;
+    constexpr int UNR = DENSE_WG >= 1024 ? 4 : 8;
     auto accumulate_round = [&](const int64_t* pos, const V* av, const bool* ok) {
       int32_t j[UNR];
       V bv[UNR];
@@ -702,15 +702,15 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
         split_chunk<V>(ch, cnt, sp, grp, wscr);
         // Long B rows as 64-entry tiles; wavefront w takes UNR consecutive
         // tiles per round, rounds TSTRIDE tiles apart.  Lane l describes the
-        // (l % UNR)-th tile of the (l / UNR)-th of the next eight rounds (one
+        // (l % UNR)-th tile of the (l / UNR)-th of the next RPD rounds (one
         // segment search per lane), and each round reads its tiles' base,
         // length and A value from those lanes.
-        static_assert(UNR == 8, "eight rounds of eight tiles per description");
+        constexpr int RPD = 64 / UNR;  // rounds per description
         constexpr int TSTRIDE = NWV * UNR;
         const int nl = sp.nlong;
         const int ntiles = sp.tpre[nl];
-        for (int tb0 = wv * UNR; tb0 < ntiles; tb0 += TSTRIDE * 8) {
-          const int my = tb0 + (ln >> 3) * TSTRIDE + (ln & 7);
+        for (int tb0 = wv * UNR; tb0 < ntiles; tb0 += TSTRIDE * RPD) {
+          const int my = tb0 + (ln / UNR) * TSTRIDE + (ln % UNR);
           int64_t mpos = 0;
           V ma = V(0);
           int32_t mrem = 0;
@@ -722,7 +722,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
             mpos = ch.b[t] + x0;
             ma = ch.a[t];
           }
-          for (int r = 0; r < 8 && tb0 + r * TSTRIDE < ntiles; ++r) {
+          for (int r = 0; r < RPD && tb0 + r * TSTRIDE < ntiles; ++r) {
             int64_t pos[UNR];
             V av[UNR];
             bool ok[UNR];
@@ -760,7 +760,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
               mx = max(mx, bl[u]);
             }
           }
-          for (int32_t x = l8; x < mx; x += 16) {
+          for (int32_t x = l8; x < mx; x += 2 * UNR) {
             int64_t pos[UNR];
             V av[UNR];
             bool ok[UNR];
