@@ -427,12 +427,20 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
         H += __popcll(hb);
       }
       int32_t Mc = 0;
-      for (int32_t s0 = nl; s0 < len; s0 += 64) {
-        const int32_t sl = s0 + lane;
-        const bool mover = sl < len && m.col[off + sl] != -1;
-        const uint64_t mb = __ballot(mover);
-        if (mover) U.mv_src[u0 + Mc + __popcll(mb & lt)] = sl;
-        Mc += __popcll(mb);
+      for (int32_t s0 = nl; s0 < len; s0 += 256) {  // 4 loads in flight per lane
+        int32_t cc[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int32_t sl = s0 + v * 64 + lane;
+          cc[v] = sl < len ? m.col[off + sl] : -1;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool mover = cc[v] != -1;
+          const uint64_t mb = __ballot(mover);
+          if (mover) U.mv_src[u0 + Mc + __popcll(mb & lt)] = s0 + v * 64 + lane;
+          Mc += __popcll(mb);
+        }
       }
       __threadfence_block();
       __builtin_amdgcn_wave_barrier();
@@ -464,17 +472,26 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
         return;
       }
       int32_t kept = 0;
-      for (int32_t base = 0; base < len; base += 64) {
-        const int32_t sl = base + lane;
-        const int32_t c = sl < len ? m.col[off + sl] : -1;
-        const bool keep = c != -1;
-        const uint64_t kb = __ballot(keep);
-        if (keep) {
-          const int64_t dst = (int64_t)no + kept + __popcll(kb & lt);
-          m.col[dst] = c;
-          store_raw<VSZ>(m.val, dst, load_raw<VSZ>(m.val, off + sl));
+      for (int32_t base = 0; base < len; base += 256) {  // 4 loads in flight per lane
+        int32_t cc[4];
+        uint64_t vv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int32_t sl = base + v * 64 + lane;
+          cc[v] = sl < len ? m.col[off + sl] : -1;
+          vv[v] = sl < len ? load_raw<VSZ>(m.val, off + sl) : 0;
         }
-        kept += __popcll(kb);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const bool keep = cc[v] != -1;
+          const uint64_t kb = __ballot(keep);
+          if (keep) {
+            const int64_t dst = (int64_t)no + kept + __popcll(kb & lt);
+            m.col[dst] = cc[v];
+            store_raw<VSZ>(m.val, dst, vv[v]);
+          }
+          kept += __popcll(kb);
+        }
       }
       for (int32_t base = u0; base < u1; base += 64) {
         const int32_t u = base + lane;

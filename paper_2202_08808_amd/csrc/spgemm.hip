@@ -617,6 +617,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   AChunk<V>& ch = st.in.ch;
   ChunkSplit& sp = st.in.sp;
   __shared__ int wscr[16];
+  __shared__ uint64_t wscr64[NWV];
   __shared__ int64_t bslot;
   __shared__ int32_t next_row;
   const Grp<DENSE_WG> grp;
@@ -627,9 +628,15 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   const int64_t count = (int64_t)*d_cnt;
   for (int x = tid; x < CH; x += DENSE_WG) acc[x] = S::identity();
   for (int x = tid; x < NW32; x += DENSE_WG) bits[x] = 0u;
-  // persistent: rows are taken in list order (longest first) from a counter
+  // persistent: rows are taken in list order (longest first) from a counter;
+  // each workgroup claims its next row while it works on the current one
+  unsigned int pending = 0;
+  if (tid == 0) pending = atomicAdd(R.dense_next, 1u);
   for (;;) {
-  if (tid == 0) next_row = (int32_t)atomicAdd(R.dense_next, 1u);
+  if (tid == 0) {
+    next_row = (int32_t)pending;
+    pending = atomicAdd(R.dense_next, 1u);
+  }
   grp.sync();
   const int32_t qi = next_row;
   grp.sync();
@@ -663,7 +670,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   bool direct = false;  // the chunks drained so far sit in the row's own place in C
   bool fault = false, parked = false;
   int32_t nnew = 0;
-  int64_t flops = 0;
+  const int64_t flops = R.flq[q];  // the row's products, from the analysis
   int64_t old_read = 0;
   // with the split copy of B each pass streams only its own column chunk
   const bool split = R.bs_parts == passes && passes > 1;
@@ -696,10 +703,69 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     };
     for (int32_t cbase = 0; cbase < d; cbase += DENSE_ACHUNK) {
       const int cnt = min(DENSE_ACHUNK, d - cbase);
-      int32_t tot = stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, !S::order_free, split ? pc : -1);
-      if (split || pc == 0) flops += tot;
       if constexpr (S::order_free) {
-        split_chunk<V>(ch, cnt, sp, grp, wscr);
+        // Stage the chunk (A column k, value, this pass's B row offset and
+        // length) and split it by B-row length with one 64-bit workgroup
+        // scan.  Packed fields: bits 0-23 tiles of long rows, 24-39 entries
+        // of short rows, 40-49 short rows, 50-59 long rows (none overflows:
+        // at most 512 rows of at most 2^11 tiles, or of fewer than 64 entries).
+        {
+          const int32_t t = cbase + tid;
+          const bool act = tid < DENSE_ACHUNK && t < d;
+          int32_t k = 0, len = 0;
+          V a = V(0);
+          int64_t boff = 0;
+          if (act) {
+            k = R.a_col[aoff + t];
+            a = ldv<V>(R.a_val, aoff + t);
+            if (split) {
+              const int64_t* ps = R.bs_ps + (int64_t)k * R.bs_parts + pc;
+              boff = ps[0];
+              len = (int32_t)(ps[1] - boff);
+            } else {
+              len = R.b_len[k];
+              boff = R.b_off[k];
+            }
+          }
+          const bool lng = act && len >= LONG_ROW;
+          const bool sht = act && len > 0 && len < LONG_ROW;
+          const uint64_t v = (lng ? (uint64_t)((len + 63) >> 6) : 0ull) | (sht ? (uint64_t)len << 24 : 0ull) |
+                             ((uint64_t)sht << 40) | ((uint64_t)lng << 50);
+          uint64_t inc = wave_inclusive_scan(v);
+          if (ln == 63) wscr64[wv] = inc;
+          grp.sync();
+          uint64_t before = 0, tot = 0;
+          for (int x = 0; x < NWV; ++x) {
+            const uint64_t c = wscr64[x];
+            if (x < wv) before += c;
+            tot += c;
+          }
+          inc += before;
+          const uint64_t exc = inc - v;
+          if (tid < DENSE_ACHUNK) {
+            ch.k[tid] = k;
+            ch.a[tid] = a;
+            ch.b[tid] = boff;
+            ch.so[tid] = len;  // (lengths: the order-free path sorts nothing)
+          }
+          if (lng) {
+            const int rl = (int)((exc >> 50) & 0x3ff);
+            sp.lidx[rl] = tid;
+            sp.tpre[rl + 1] = (int32_t)(inc & 0xffffff);
+          }
+          if (sht) {
+            const int rs = (int)((exc >> 40) & 0x3ff);
+            sp.sidx[rs] = tid;
+            sp.spre[rs + 1] = (int32_t)((inc >> 24) & 0xffff);
+          }
+          if (tid == 0) {
+            sp.spre[0] = 0;
+            sp.tpre[0] = 0;
+            sp.nlong = (int32_t)((tot >> 50) & 0x3ff);
+            sp.nshort = (int32_t)((tot >> 40) & 0x3ff);
+          }
+          grp.sync();
+        }
         // Long B rows as 64-entry tiles; wavefront w takes UNR consecutive
         // tiles per round, rounds TSTRIDE tiles apart.  Lane l describes the
         // (l % UNR)-th tile of the (l / UNR)-th of the next RPD rounds (one
@@ -718,7 +784,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
             const int e = find_seg(sp.tpre, nl, my);
             const int t = sp.lidx[e];
             const int32_t x0 = (my - sp.tpre[e]) << 6;
-            mrem = min(64, ch.pre[t + 1] - ch.pre[t] - x0);
+            mrem = min(64, ch.so[t] - x0);
             mpos = ch.b[t] + x0;
             ma = ch.a[t];
           }
@@ -755,7 +821,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
             if (e < ns) {
               const int t = sp.sidx[e];
               bo[u] = ch.b[t];
-              bl[u] = ch.pre[t + 1] - ch.pre[t];
+              bl[u] = ch.so[t];
               ba[u] = ch.a[t];
               mx = max(mx, bl[u]);
             }
@@ -776,6 +842,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
           }
         }
       } else {
+        stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, true, split ? pc : -1);
         for (int y = 0; y < cnt; ++y) {
           const int ts = ch.so[y];
           const int32_t blen = ch.pre[ts + 1] - ch.pre[ts];
@@ -862,20 +929,39 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
         o += nb;
         nb = 0;
       };
-      for (int r = 0; r < SEG; r += 64) {
-        const int w0 = (wv * SEG + r) >> 5;
-        const uint64_t b = (uint64_t)bits[w0] | ((uint64_t)bits[w0 + 1] << 32);
-        if (write && nb + 64 > OBN) flush();
-        if ((b >> ln) & 1ull) {
-          const int x = wv * SEG + r + ln;
-          if (write) {
-            const int k = nb + __popcll(b & lt);
-            bc[k] = c0 + x;
-            bv[k] = S::from_acc(acc[x]);
-          }
-          acc[x] = S::identity();
+      // DU blocks of 64 columns per step: their bitmap words and touched
+      // accumulator slots are read together
+      constexpr int DU = OBN >= 256 ? 4 : 2;
+      static_assert(SEG % (64 * DU) == 0 && 64 * DU <= OBN, "drain steps");
+      for (int r = 0; r < SEG; r += 64 * DU) {
+        uint64_t b[DU];
+        Acc a[DU];
+        int cnt = 0;
+#pragma unroll
+        for (int u = 0; u < DU; ++u) {
+          const int w0 = (wv * SEG + r + u * 64) >> 5;
+          b[u] = (uint64_t)bits[w0] | ((uint64_t)bits[w0 + 1] << 32);
+          cnt += __popcll(b[u]);
         }
-        nb += __popcll(b);
+#pragma unroll
+        for (int u = 0; u < DU; ++u) {
+          const int x = wv * SEG + r + u * 64 + ln;
+          a[u] = ((b[u] >> ln) & 1ull) ? acc[x] : S::identity();
+        }
+        if (write && nb + cnt > OBN) flush();
+#pragma unroll
+        for (int u = 0; u < DU; ++u) {
+          if ((b[u] >> ln) & 1ull) {
+            const int x = wv * SEG + r + u * 64 + ln;
+            if (write) {
+              const int k = nb + __popcll(b[u] & lt);
+              bc[k] = c0 + x;
+              bv[k] = S::from_acc(a[u]);
+            }
+            acc[x] = S::identity();
+          }
+          nb += __popcll(b[u]);
+        }
       }
       if (write) flush();
       for (int w = ln; w < SEGW; w += 64) bits[wv * SEGW + w] = 0u;
@@ -1242,17 +1328,25 @@ __device__ inline int pick_bin(int32_t ub, int32_t d, const Tun& T) {
   return T.dense_passes <= T.dense_max_passes ? BIN_DENSE : BIN_GLOBAL;
 }
 
-// 16 lanes per affected row: flops, ub, bin; empty output rows are finished here
+// One wavefront per affected row (8 column loads in flight per lane, so a hub
+// row is no long chain of dependent loads): flops, ub, bin
+constexpr int ANALYZE_UNR = 8;
 __global__ __launch_bounds__(256) void k_analyze(RowArgs R, const int32_t* d_count, Tun T) {
-  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-  const int l = threadIdx.x & 15;
+  const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int l = threadIdx.x & 63;
   if (q >= *d_count) return;
   const int32_t i = R.aff[q];
   const int64_t aoff = R.a_off[i];
   const int32_t d = R.a_len[i];
   int64_t f = 0;
-  for (int32_t t = l; t < d; t += 16) f += R.b_len[R.a_col[aoff + t]];
-  for (int s = 8; s > 0; s >>= 1) f += __shfl_xor(f, s, 16);
+  for (int32_t t0 = l; t0 < d; t0 += 64 * ANALYZE_UNR) {
+    int32_t k[ANALYZE_UNR];
+#pragma unroll
+    for (int u = 0; u < ANALYZE_UNR; ++u) k[u] = t0 + u * 64 < d ? R.a_col[aoff + t0 + u * 64] : -1;
+#pragma unroll
+    for (int u = 0; u < ANALYZE_UNR; ++u) f += k[u] >= 0 ? R.b_len[k[u]] : 0;
+  }
+  for (int s = 32; s > 0; s >>= 1) f += __shfl_xor(f, s, 64);
   if (l != 0) return;
   const int32_t ub = (int32_t)min(f, (int64_t)R.ncols);
   R.ub[q] = ub;
@@ -1538,12 +1632,18 @@ __global__ __launch_bounds__(256) void k_bsplit_count(const int64_t* b_off, cons
   int64_t cnt[BSPLIT_MAXP];
 #pragma unroll
   for (int q = 0; q < BSPLIT_MAXP; ++q) cnt[q] = 0;
-  for (int32_t e0 = 0; e0 < len; e0 += 64) {
-    const int32_t e = e0 + ln;
-    const int part = e < len ? (b_col[off + e] >> chbits) : -1;
+  for (int32_t e0 = 0; e0 < len; e0 += 256) {  // 4 loads in flight per lane
+    int part[4];
 #pragma unroll
-    for (int q = 0; q < BSPLIT_MAXP; ++q)
-      if (q < P) cnt[q] += __popcll(__ballot(part == q));
+    for (int v = 0; v < 4; ++v) {
+      const int32_t e = e0 + v * 64 + ln;
+      part[v] = e < len ? (b_col[off + e] >> chbits) : -1;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < BSPLIT_MAXP; ++q)
+        if (q < P) cnt[q] += __popcll(__ballot(part[v] == q));
   }
   if (ln == 0) {
 #pragma unroll
@@ -1568,22 +1668,31 @@ __global__ __launch_bounds__(256) void k_bsplit_scatter(const int64_t* b_off, co
   int64_t o[BSPLIT_MAXP];
 #pragma unroll
   for (int q = 0; q < BSPLIT_MAXP; ++q) o[q] = q < P ? ps[k * P + q] : 0;
-  for (int32_t e0 = 0; e0 < len; e0 += 64) {
-    const int32_t e = e0 + ln;
-    const int32_t col = e < len ? b_col[off + e] : 0;
-    const int part = e < len ? (col >> chbits) : -1;
-    int64_t dst = -1;
+  for (int32_t e0 = 0; e0 < len; e0 += 256) {  // 4 loads in flight per lane
+    int32_t col[4];
+    W val[4];
 #pragma unroll
-    for (int q = 0; q < BSPLIT_MAXP; ++q) {
-      if (q < P) {
-        const uint64_t m = __ballot(part == q);
-        if (part == q) dst = o[q] + __popcll(m & lt);
-        o[q] += __popcll(m);
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int32_t e = e0 + v * 64 + ln;
+      col[v] = e < len ? b_col[off + e] : -1;
+      val[v] = e < len ? ((const W*)b_val)[off + e] : W(0);
     }
-    if (dst >= 0) {
-      out_col[dst] = col;
-      ((W*)out_val)[dst] = ((const W*)b_val)[off + e];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int part = col[v] >= 0 ? (col[v] >> chbits) : -1;
+      int64_t dst = -1;
+#pragma unroll
+      for (int q = 0; q < BSPLIT_MAXP; ++q) {
+        if (q < P) {
+          const uint64_t m = __ballot(part == q);
+          if (part == q) dst = o[q] + __popcll(m & lt);
+          o[q] += __popcll(m);
+        }
+      }
+      if (dst >= 0) {
+        out_col[dst] = col[v];
+        ((W*)out_val)[dst] = val[v];
+      }
     }
   }
 }
@@ -1711,7 +1820,7 @@ void launch_front(DProd* p, int mode, ProdWork& w, const RowArgs& R) {
   T.force_bin = tu.force_bin;
   T.fp64 = A->sr == 2 ? 1 : 0;
   if (n > 0) {
-    hipLaunchKernelGGL(k_analyze, dim3(blocks_for((int64_t)n * 16, 256)), dim3(256), 0, s, R, w.d_count, T);
+    hipLaunchKernelGGL(k_analyze, dim3(blocks_for((int64_t)n * 64, 256)), dim3(256), 0, s, R, w.d_count, T);
     hipLaunchKernelGGL(k_bin_scatter, dim3(blocks_for(n, SCATTER_NT)), dim3(SCATTER_NT), 0, s, R, w.d_count, w.plan,
                        w.bins, n, (const uint8_t*)nullptr);
   }
