@@ -322,6 +322,7 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
   const int32_t d = R.a_len[i];
   int64_t flops = 0;
   bool overflow = false;
+  int32_t fresh_n = 0;  // keys this lane inserted first: the new row length sums them
   for (int32_t cbase = 0; cbase < d; cbase += G) {
     const int32_t t = cbase + lane;
     const int cnt = min(G, d - cbase);
@@ -355,6 +356,7 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
           int h = hash_insert<SLOTS>(keys, j, fresh);
           if (h >= 0) S::atomic_combine(&vals[h], p);
           else overflow = true;
+          fresh_n += fresh;
         }
       }
     } else {
@@ -377,6 +379,7 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
           int h = hash_insert<SLOTS>(keys, j, fresh);
           if (h >= 0) vals[h] = fresh ? p : __dadd_rn(vals[h], p);
           else overflow = true;
+          fresh_n += fresh;
         }
         grp.sync();
       }
@@ -390,11 +393,7 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
 
   // new row length
   int32_t nnew = 0;
-  for (int sb = 0; sb < SLOTS; sb += G) {
-    int tot;
-    grp.rank(keys[sb + lane] != -1, tot, wscr);
-    nnew += tot;
-  }
+  grp.scan(fresh_n, nnew, wscr);
   const int64_t ooff = R.c_off[i];
   const int32_t olen = R.c_len[i];
   bool changed = R.force_write || nnew != olen;
@@ -425,17 +424,22 @@ __global__ __launch_bounds__(WG) void k_rows_group(RowArgs R, const int32_t* lis
         continue;
       }
     }
-    int32_t w = 0;
-    for (int sb = 0; sb < SLOTS; sb += G) {
-      const int s = sb + lane;
+    // lane l writes its slots l, l + G, ... in a run of its own (one scan)
+    constexpr int SPL = SLOTS / G;
+    int32_t mine = 0;
+#pragma unroll
+    for (int u = 0; u < SPL; ++u) mine += keys[u * G + lane] != -1;
+    int32_t ntot;
+    int32_t w = grp.scan(mine, ntot, wscr) - mine;
+#pragma unroll
+    for (int u = 0; u < SPL; ++u) {
+      const int s = u * G + lane;
       const int32_t key = keys[s];
-      int tot;
-      int r = grp.rank(key != -1, tot, wscr);
       if (key != -1) {
-        R.c_col[dest + w + r] = key;
-        ((V*)R.c_val)[dest + w + r] = S::from_acc(vals[s]);
+        R.c_col[dest + w] = key;
+        ((V*)R.c_val)[dest + w] = S::from_acc(vals[s]);
+        ++w;
       }
-      w += tot;
     }
     if (lane == 0) {
       R.c_len[i] = nnew;
