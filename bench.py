@@ -341,10 +341,10 @@ def bench_sweep(args):
         batches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (q.rows, q.cols, q.vals, q.ops))
                    for q in w.batches_A]
         rec = {"batch": b}
-        for path in ("row", "entry"):
+        for path in ("row", "entry", "auto"):
             ctx = dsg.Context(0, stream=torch.cuda.current_stream(dev))
             t = ctx.get_tuning()
-            t.update_path = 1 if path == "row" else 2
+            t.update_path = {"row": 1, "entry": 2, "auto": 0}[path]
             ctx.set_tuning(t)
             A = dsg.Matrix.from_csr(ctx, w.A, w.semiring)
             P = dsg.Product(ctx, A, A)
@@ -359,6 +359,10 @@ def bench_sweep(args):
                     ts.append(time.perf_counter() - t0)
             st = P.stats()
             rec[path + "_ms"] = round(float(np.median(ts)) * 1e3, 4)
+            if path == "row":
+                rec["row_flops"] = st["flops"]
+            if path == "auto":
+                rec["auto_took_entry"] = bool(st["path"] == 1)
             if path == "entry":
                 rec["entry_taken"] = bool(st["path"] == 1)
                 rec["lost_per_batch"] = st["lost"]

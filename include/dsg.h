@@ -127,9 +127,14 @@ typedef struct {
   int32_t force_bin;       /* -1: automatic; 0..7 group bin; 8 dense; 9 global hash (for tests;
                               a group bin is only used for rows that fit it) */
   int32_t update_path;     /* dynamic updates of C = A*A over (min,+) or int64 (+,x):
-                              0 automatic (entry-granular while the changed products are few
-                              next to nnz(C), else whole affected rows); 1 always whole rows;
-                              2 entry-granular whenever it applies.  Same results every way. */
+                              0 automatic (see below); 1 always whole rows; 2 entry-granular
+                              whenever it applies.  Same results every way. */
+  int32_t reserved;        /* 0 */
+  /* Automatic choice: the entry-granular path runs when the products of the
+   * affected rows exceed entry_fixed + entry_per_term * (the changed
+   * products).  Defaults 2e8 and 500 (fitted on MI355X); both finite, >= 0. */
+  double entry_fixed;
+  double entry_per_term;
 } dsg_tuning;
 dsg_status dsg_ctx_get_tuning(const dsg_ctx* ctx, dsg_tuning* t);
 /* t == NULL restores the defaults.  DSG_E_ARG for thresholds outside the

@@ -149,6 +149,9 @@ static void default_tuning(dsg_tuning* t) {
   t->dense_max_passes = 4;
   t->force_bin = -1;
   t->update_path = 0;
+  t->reserved = 0;
+  t->entry_fixed = 2e8;
+  t->entry_per_term = 500.0;
 }
 
 // host-side check of a CSR: row_ptr monotone from 0, columns in range, no
@@ -325,6 +328,8 @@ extern "C" dsg_status dsg_ctx_set_tuning(dsg_ctx* ctx, const dsg_tuning* t) {
   if (t->dense_max_passes < 0) return fail(ctx, DSG_E_ARG, "dense_max_passes < 0");
   if (t->force_bin < -1 || t->force_bin > 9) return fail(ctx, DSG_E_ARG, "force_bin outside [-1, 9]");
   if (t->update_path < 0 || t->update_path > 2) return fail(ctx, DSG_E_ARG, "update_path outside [0, 2]");
+  if (!(t->entry_fixed >= 0.0 && t->entry_fixed < 1e300) || !(t->entry_per_term >= 0.0 && t->entry_per_term < 1e300))
+    return fail(ctx, DSG_E_ARG, "entry_fixed and entry_per_term must be finite and >= 0");
   ctx->c.tuning = *t;
   return DSG_OK;
 }
@@ -646,6 +651,7 @@ static std::vector<dsg_tuning> tuning_candidates() {
     for (int skip_small = 0; skip_small < 2; ++skip_small)
       for (int passes : {1, 2, 4, 8}) {
         dsg_tuning t;
+        default_tuning(&t);
         for (int b = 0; b < 8; ++b) t.group_ub[b] = half ? (16 << b) : (32 << b);
         if (skip_small) t.group_ub[0] = t.group_ub[1] = 0;
         t.dense_max_passes = passes;
@@ -673,7 +679,11 @@ extern "C" dsg_status dsg_prod_autotune(dsg_prod* ph, int32_t reps, dsg_tuning* 
   const bool timing = c->timing;
   c->timing = false;
   try {
-    for (const dsg_tuning& t : tuning_candidates()) {
+    for (dsg_tuning t : tuning_candidates()) {
+      // the trials vary the row kernels only; the path choice stays as set
+      t.update_path = saved.update_path;
+      t.entry_fixed = saved.entry_fixed;
+      t.entry_per_term = saved.entry_per_term;
       c->tuning = t;
       prod_run(ph->p, 1, true);  // warm: sizes the pools and the arena for this setting
       std::vector<float> ms;

@@ -1895,11 +1895,11 @@ Plan retry_rows(DProd* p, ProdWork& w, int mode, bool report_affected, Plan plan
 // Plain mode: one product update (mode 0) or full recompute (mode 1), with
 // host round trips after the analysis (bin sizes) and at the end (results).
 // The entry-granular path wins while its changed products stay few next to
-// the products the affected rows would take (costs measured on MI355X:
-// about 1.5 ms + 4 ns per changed product against 0.4 ms + 0.02 ns per
-// product of an affected row, R-MAT and Erdos-Renyi, 1e2..1e5 updates).
-bool entry_cheaper(int64_t nterm, unsigned long long row_flops) {
-  return (double)row_flops > 55e6 + 200.0 * (double)nterm;
+// the products the affected rows would take: the rule's two constants come
+// from the tuning (their defaults separate every measured R-MAT and
+// Erdos-Renyi case of 1e2..3e4 updates on MI355X).
+bool entry_cheaper(const dsg_tuning& t, int64_t nterm, unsigned long long row_flops) {
+  return (double)row_flops > t.entry_fixed + t.entry_per_term * (double)nterm;
 }
 
 int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, int64_t entry_terms) {
@@ -1911,7 +1911,7 @@ int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, int
   launch_front(p, mode, w, R);
   Plan plan = read_plan(c, w, p->C);
   // nothing of C was touched so far: hand over to the entry-granular path
-  if (entry_terms >= 0 && entry_cheaper(entry_terms, plan.flops)) return ENTRY_INSTEAD;
+  if (entry_terms >= 0 && entry_cheaper(c->tuning, entry_terms, plan.flops)) return ENTRY_INSTEAD;
   // room: C grows only by what rows that do not fit ask for (retry below);
   // the arena keeps the largest size used so far, up to the analysis bound
   if (plan.arena_demand > p->arena_bytes) ensure_arena(p, std::min<size_t>(plan.arena_demand, std::max<size_t>(p->arena_bytes * 2, (size_t)64 << 20)));

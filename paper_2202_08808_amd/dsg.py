@@ -41,7 +41,8 @@ class Rows(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("group_ub", ctypes.c_int32 * 8), ("dense_max_passes", ctypes.c_int32),
-                ("force_bin", ctypes.c_int32), ("update_path", ctypes.c_int32)]
+                ("force_bin", ctypes.c_int32), ("update_path", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("entry_fixed", ctypes.c_double), ("entry_per_term", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -400,7 +401,7 @@ class Product:
             with open(cache_path) as f:
                 cache = json.load(f)
         if key in cache:
-            t = Tuning()
+            t = self.ctx.get_tuning()
             ent = cache[key]
             for b in range(8):
                 t.group_ub[b] = ent["group_ub"][b]

@@ -50,3 +50,39 @@ def test_no_device_reports_device_error():
     h = ctypes.c_void_p()
     assert L.dsg_ctx_create(0, None, 0, ctypes.byref(h)) == dsg.E_DEVICE
     assert b"device" in L.dsg_last_error(None)
+
+
+# ctypes mirror of each struct the header declares
+MIRRORS = {"dsg_rows": "Rows", "dsg_tuning": "Tuning", "dsg_update_stats": "Stats",
+           "dsg_update_set": "UpdateSet", "dsg_batch_stats": "BatchStats", "dsg_server_cfg": "ServerCfg",
+           "dsg_server_result": "ServerResult", "dsg_server_stats": "ServerStats"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Size and field offsets of every struct, as a C compiler lays them out
+    from include/dsg.h, equal those of the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dsg.h"', "int main(void) {"]
+    for cname, pname in MIRRORS.items():
+        cls = getattr(dsg, pname)
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, pname in MIRRORS.items():
+        cls = getattr(dsg, pname)
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, f"{cname}.{f}"

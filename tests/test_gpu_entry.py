@@ -169,17 +169,23 @@ def test_entry_needs_every_apply_logged(ctx, sr):
 @pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
 def test_automatic_path_choice(ctx, sr):
     """The automatic choice follows the cost rule (entry-granular while the
-    affected rows' products exceed 55e6 + 200 per changed product) and gives
-    the row path's C bit for bit.  R-MAT s15: a 200-update batch goes
-    entry-granular, a 30000-update batch to the row path."""
+    affected rows' products exceed entry_fixed + entry_per_term per changed
+    product) and gives the row path's C bit for bit.  R-MAT s15, batches of
+    200 and 30000 updates: with entry_per_term between the two batches'
+    products-per-term ratios, the first goes entry-granular and the second
+    to the row path."""
     say(f"automatic path {SR_ID[sr]}")
+    d = ctx.get_tuning()
+    assert (d.entry_fixed, d.entry_per_term) == (2e8, 500.0)
     hi = 9 if sr == I.PLUS_TIMES_I64 else 100
     A = I.rmat_csr(15, 16, sr, stream=821, lo=1, hi=hi)
     bs = I.disjoint_batches(A, sr, [200, 30000], stream=822, value_lo=1, value_hi=hi)
-    prods = {}
-    for mode in (1, 2, 0):  # rows, entries, automatic
+
+    def run_mode(mode, fixed=None, per_term=None):
         t = ctx.get_tuning()
         t.update_path = mode
+        if fixed is not None:
+            t.entry_fixed, t.entry_per_term = fixed, per_term
         ctx.set_tuning(t)
         m = dsg.Matrix.from_csr(ctx, A, sr)
         P = dsg.Product(ctx, m, m)
@@ -189,17 +195,24 @@ def test_automatic_path_choice(ctx, sr):
             P.update()
             st.append(P.stats())
             Cs.append(P.export())
-        prods[mode] = (st, Cs)
         P.destroy()
         m.destroy()
-    ctx.set_tuning(None)
-    chosen = []
+        ctx.set_tuning(None)
+        return st, Cs
+
+    rows = run_mode(1)
+    entries = run_mode(2)
+    ratio = [rows[0][k]["flops"] / entries[0][k]["terms"] for k in range(len(bs))]
+    assert ratio[0] > ratio[1]
+    per_term = (ratio[0] * ratio[1]) ** 0.5
+    auto = run_mode(0, 0.0, per_term)
+    chosen = [s["path"] for s in auto[0]]
     for k in range(len(bs)):
-        rule = prods[1][0][k]["flops"] > 55e6 + 200 * prods[2][0][k]["terms"]
-        assert prods[0][0][k]["path"] == (1 if rule else 0), f"batch {k}"
-        chosen.append(prods[0][0][k]["path"])
-        for mode in (0, 2):
-            x, y = prods[mode][1][k], prods[1][1][k]
+        # same inputs, so the forced runs' products and terms are the automatic run's
+        want_entry = rows[0][k]["flops"] > per_term * entries[0][k]["terms"]
+        assert chosen[k] == (1 if want_entry else 0), f"batch {k}"
+        for other in (entries, auto):
+            x, y = other[1][k], rows[1][k]
             assert np.array_equal(x.row_ptr, y.row_ptr) and np.array_equal(x.col, y.col)
-            assert np.asarray(x.val).tobytes() == np.asarray(y.val).tobytes(), f"batch {k} mode {mode}"
+            assert np.asarray(x.val).tobytes() == np.asarray(y.val).tobytes(), f"batch {k}"
     assert chosen == [1, 0]
