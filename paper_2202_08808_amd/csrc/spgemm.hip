@@ -564,6 +564,23 @@ __device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d,
 // bin 8: dense LDS accumulator over column chunks, one workgroup per row
 // ---------------------------------------------------------------------------
 
+// Slot of key c in an LDS open-addressing table (linear probing from slot h,
+// whose key k was already read), inserting c where it was absent; -1 when
+// `probes` slots are taken by other keys.
+template <int SLOTS, int PROBES>
+__device__ inline int hash_place(int32_t* keys, int32_t c, uint32_t h, int32_t k) {
+  for (int p = 0; p < PROBES; ++p) {
+    if (k == c) return (int)h;
+    if (k == -1) {
+      const int32_t old = atomicCAS(&keys[h], -1, c);
+      if (old == -1 || old == c) return (int)h;
+    }
+    h = (h + 1) & (SLOTS - 1);
+    k = keys[h];
+  }
+  return -1;
+}
+
 // Orders the LDS accesses of the lanes of one wavefront.
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -654,6 +671,292 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   const int32_t olen = R.c_len[i];
   const int32_t stage_n = min(ub, R.ncols);
   const int passes = (R.ncols + CH - 1) / CH;
+  // MLP rounds of UNR independent flops per lane: all loads first, then the
+  // LDS updates, so each lane keeps UNR gathers in flight
+  constexpr int UNR = DENSE_WG >= 1024 ? 4 : 8;
+  // Stage A entries [cbase, cbase + 512) (column k, value, B row offset and
+  // length: the whole B row, or its column chunk `part` of the split copy)
+  // and split them by B-row length with one 64-bit workgroup scan.  Packed
+  // fields: bits 0-23 tiles of long rows, 24-39 entries of short rows, 40-49
+  // short rows, 50-59 long rows (none overflows: at most 512 rows of at most
+  // 2^11 tiles, or of fewer than 64 entries).
+  auto stage_split = [&](int32_t cbase, bool use_split, int part) {
+    const int32_t t = cbase + tid;
+    const bool act = tid < DENSE_ACHUNK && t < d;
+    int32_t k = 0, len = 0;
+    V a = V(0);
+    int64_t boff = 0;
+    if (act) {
+      k = R.a_col[aoff + t];
+      a = ldv<V>(R.a_val, aoff + t);
+      if (use_split) {
+        const int64_t* ps = R.bs_ps + (int64_t)k * R.bs_parts + part;
+        boff = ps[0];
+        len = (int32_t)(ps[1] - boff);
+      } else {
+        len = R.b_len[k];
+        boff = R.b_off[k];
+      }
+    }
+    const bool lng = act && len >= LONG_ROW;
+    const bool sht = act && len > 0 && len < LONG_ROW;
+    const uint64_t v = (lng ? (uint64_t)((len + 63) >> 6) : 0ull) | (sht ? (uint64_t)len << 24 : 0ull) |
+                       ((uint64_t)sht << 40) | ((uint64_t)lng << 50);
+    uint64_t inc = wave_inclusive_scan(v);
+    if (ln == 63) wscr64[wv] = inc;
+    grp.sync();
+    uint64_t before = 0, tot = 0;
+    for (int x = 0; x < NWV; ++x) {
+      const uint64_t c = wscr64[x];
+      if (x < wv) before += c;
+      tot += c;
+    }
+    inc += before;
+    const uint64_t exc = inc - v;
+    if (tid < DENSE_ACHUNK) {
+      ch.k[tid] = k;
+      ch.a[tid] = a;
+      ch.b[tid] = boff;
+      ch.so[tid] = len;  // (lengths: the order-free path sorts nothing)
+    }
+    if (lng) {
+      const int rl = (int)((exc >> 50) & 0x3ff);
+      sp.lidx[rl] = tid;
+      sp.tpre[rl + 1] = (int32_t)(inc & 0xffffff);
+    }
+    if (sht) {
+      const int rs = (int)((exc >> 40) & 0x3ff);
+      sp.sidx[rs] = tid;
+      sp.spre[rs + 1] = (int32_t)((inc >> 24) & 0xffff);
+    }
+    if (tid == 0) {
+      sp.spre[0] = 0;
+      sp.tpre[0] = 0;
+      sp.nlong = (int32_t)((tot >> 50) & 0x3ff);
+      sp.nshort = (int32_t)((tot >> 40) & 0x3ff);
+    }
+    grp.sync();
+  };
+  // Every product of the staged chunk through round(pos, av, ok), UNR per lane at a time.
+  auto for_rounds = [&](auto&& round) {
+    // Long B rows as 64-entry tiles; wavefront w takes UNR consecutive
+    // tiles per round, rounds TSTRIDE tiles apart.  Lane l describes the
+    // (l % UNR)-th tile of the (l / UNR)-th of the next RPD rounds (one
+    // segment search per lane), and each round reads its tiles' base,
+    // length and A value from those lanes.
+    constexpr int RPD = 64 / UNR;  // rounds per description
+    constexpr int TSTRIDE = NWV * UNR;
+    const int nl = sp.nlong;
+    const int ntiles = sp.tpre[nl];
+    for (int tb0 = wv * UNR; tb0 < ntiles; tb0 += TSTRIDE * RPD) {
+      const int my = tb0 + (ln / UNR) * TSTRIDE + (ln % UNR);
+      int64_t mpos = 0;
+      V ma = V(0);
+      int32_t mrem = 0;
+      if (my < ntiles) {
+        const int e = find_seg(sp.tpre, nl, my);
+        const int t = sp.lidx[e];
+        const int32_t x0 = (my - sp.tpre[e]) << 6;
+        mrem = min(64, ch.so[t] - x0);
+        mpos = ch.b[t] + x0;
+        ma = ch.a[t];
+      }
+      for (int r = 0; r < RPD && tb0 + r * TSTRIDE < ntiles; ++r) {
+        int64_t pos[UNR];
+        V av[UNR];
+        bool ok[UNR];
+  #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int src = r * UNR + u;
+          ok[u] = ln < __builtin_amdgcn_readlane(mrem, src);
+          pos[u] = lane64(mpos, src) + ln;
+          av[u] = lanev<V>(ma, src);
+        }
+        round(pos, av, ok);
+      }
+    }
+    // short B rows: 8-lane sub-groups, each streaming 4 rows at once (no
+    // search; 4 gathers in flight per lane)
+    const int ns = sp.nshort;
+    constexpr int NSG = DENSE_WG / 8;
+    const int sg = tid >> 3, l8 = tid & 7;
+    for (int eb = sg; eb < ns; eb += 4 * NSG) {
+      int64_t bo[4];
+      int32_t bl[4];
+      V ba[4];
+      int32_t mx = 0;
+  #pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = eb + u * NSG;
+        bl[u] = 0;
+        bo[u] = 0;
+        ba[u] = V(0);
+        if (e < ns) {
+          const int t = sp.sidx[e];
+          bo[u] = ch.b[t];
+          bl[u] = ch.so[t];
+          ba[u] = ch.a[t];
+          mx = max(mx, bl[u]);
+        }
+      }
+      for (int32_t x = l8; x < mx; x += 2 * UNR) {
+        int64_t pos[UNR];
+        V av[UNR];
+        bool ok[UNR];
+  #pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int r = u & 3;
+          const int32_t xx = x + (u >> 2) * 8;
+          ok[u] = xx < bl[r];
+          pos[u] = bo[r] + xx;
+          av[u] = ba[r];
+        }
+        round(pos, av, ok);
+      }
+    }
+  };
+  // (min,+) rows expected to hold at most HFILL entries take one pass over
+  // all columns with an open-addressing hash in the accumulator's space
+  // (HSLOTS keys, then HSLOTS values; empty keys and values are both all
+  // ones, the accumulator's identity, so the cleared table is the cleared
+  // accumulator).  The expectation is the old row's length plus slack (the
+  // flop bound when the row is new); a row that outgrows it overflows a probe
+  // chain and is redone with the column passes below.
+  if constexpr (SR == 1) {
+    constexpr int HSLOTS = CH / 2;
+    constexpr int HBITS = __builtin_ctz(HSLOTS);
+    constexpr int HFILL = HSLOTS * 2 / 3;
+    constexpr int HPROBES = 128;
+    static_assert(sizeof(Acc) == 4, "(min,+) keys: the identity 0xffffffff doubles as the empty key -1");
+    int32_t* hk = (int32_t*)acc;
+    Acc* hv = acc + HSLOTS;
+    const int32_t expect = olen > 0 ? olen + (olen >> 3) + 64 : stage_n;
+    if (expect <= HFILL) {
+      bool over = false;
+      auto hash_round = [&](const int64_t* pos, const V* av, const bool* ok) {
+        int32_t j[UNR];
+        V bv[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          j[u] = ok[u] ? R.b_col[pos[u]] : -1;
+          bv[u] = ok[u] ? ldv<V>(R.b_val, pos[u]) : V(0);
+        }
+        uint32_t h[UNR];
+        int32_t k[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {  // first probes read together
+          h[u] = hash_col(j[u]) >> (32 - HBITS);
+          k[u] = ok[u] ? hk[h[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          if (ok[u]) {
+            const int hh = hash_place<HSLOTS, HPROBES>(hk, j[u], h[u], k[u]);
+            if (hh >= 0) atomicMin(&hv[hh], S::mul(av[u], bv[u]));
+            else over = true;
+          }
+        }
+      };
+      for (int32_t cbase = 0; cbase < d; cbase += DENSE_ACHUNK) {
+        stage_split(cbase, false, 0);
+        for_rounds(hash_round);
+        grp.sync();
+      }
+      if (grp.any(over, wscr)) {
+        for (int x = tid; x < CH; x += DENSE_WG) acc[x] = S::identity();
+        grp.sync();
+      } else {
+        // entries per wavefront segment of HSLOTS / NWV slots
+        constexpr int HSEG = HSLOTS / NWV;
+        int32_t mine = 0;
+        for (int r = 0; r < HSEG; r += 64) mine += __popcll(__ballot(hk[wv * HSEG + r + ln] != -1));
+        if (ln == 0) wscr[wv] = mine;
+        grp.sync();
+        int32_t before = 0, nnew = 0;
+        for (int x = 0; x < NWV; ++x) {
+          const int32_t c = wscr[x];
+          if (x < wv) before += c;
+          nnew += c;
+        }
+        grp.sync();
+        bool changed = R.force_write || nnew != olen;
+        int64_t old_read = 0;
+        if (!changed) {  // every old entry present with the same value
+          bool bad = false;
+          for (int32_t e0 = tid; e0 < olen; e0 += 4 * DENSE_WG) {
+            int32_t oc[4];
+            V ov[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int32_t e = e0 + u * DENSE_WG;
+              oc[u] = e < olen ? R.c_col[ooff + e] : -1;
+              ov[u] = e < olen ? ldv<V>(R.c_val, ooff + e) : V(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              if (oc[u] < 0) continue;
+              uint32_t hh = hash_col(oc[u]) >> (32 - HBITS);
+              bool found = false;
+              for (int p = 0; p < HSLOTS; ++p) {
+                const int32_t kk = hk[hh];
+                if (kk == oc[u]) {
+                  found = true;
+                  break;
+                }
+                if (kk == -1) break;
+                hh = (hh + 1) & (HSLOTS - 1);
+              }
+              bad |= !found || !same_bits(hv[hh], S::to_acc(ov[u]));
+            }
+          }
+          if (grp.any(bad, wscr)) changed = true;
+          old_read = olen;
+        }
+        int64_t dest = ooff;
+        int32_t ncap = 0;
+        bool parked = false;
+        if (changed && nnew > R.c_cap[i]) {
+          ncap = slack_cap(nnew);
+          dest = take_pool<DENSE_WG>(R, ncap, grp, &bslot);
+          if (dest < 0) {
+            if (tid == 0) mark_retry(R, q, R.c_short, (unsigned long long)ncap);
+            parked = true;
+          }
+        }
+        // read the table out (slot order) and clear it
+        const bool write = changed && !parked;
+        int32_t o = before;
+        for (int r = 0; r < HSEG; r += 64) {
+          const int sl = wv * HSEG + r + ln;
+          const int32_t kk = hk[sl];
+          const uint64_t b = __ballot(kk != -1);
+          if (kk != -1) {
+            if (write) {
+              const int64_t pos = dest + o + __popcll(b & lt);
+              R.c_col[pos] = kk;
+              ((V*)R.c_val)[pos] = S::from_acc(hv[sl]);
+            }
+            hk[sl] = -1;
+            hv[sl] = S::identity();
+          }
+          o += __popcll(b);
+        }
+        if (write && tid == 0) {
+          R.c_len[i] = nnew;
+          if (ncap) {
+            R.c_off[i] = dest;
+            R.c_cap[i] = ncap;
+          }
+        }
+        grp.sync();
+        if (!parked && tid == 0) {
+          R.chg[q] = changed ? 1 : 0;
+          row_stat(R, q, d, R.flq[q], nnew, olen, old_read, changed ? nnew : 0);
+        }
+        continue;
+      }
+    }
+  }
   // staging space holds the chunks before the last one (none for a one-pass row)
   int32_t* scol = nullptr;
   V* sval = nullptr;
@@ -683,9 +986,6 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   for (int pc = 0; pc < passes; ++pc) {
     const int32_t c0 = pc * CH;
     const int32_t c1 = min(c0 + CH, R.ncols);
-    // MLP rounds of UNR independent flops per lane: all loads first, then the
-    // LDS updates, so each lane keeps UNR gathers in flight
-    constexpr int UNR = DENSE_WG >= 1024 ? 4 : 8;
     auto accumulate_round = [&](const int64_t* pos, const V* av, const bool* ok) {
       int32_t j[UNR];
       V bv[UNR];
@@ -708,143 +1008,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     for (int32_t cbase = 0; cbase < d; cbase += DENSE_ACHUNK) {
       const int cnt = min(DENSE_ACHUNK, d - cbase);
       if constexpr (S::order_free) {
-        // Stage the chunk (A column k, value, this pass's B row offset and
-        // length) and split it by B-row length with one 64-bit workgroup
-        // scan.  Packed fields: bits 0-23 tiles of long rows, 24-39 entries
-        // of short rows, 40-49 short rows, 50-59 long rows (none overflows:
-        // at most 512 rows of at most 2^11 tiles, or of fewer than 64 entries).
-        {
-          const int32_t t = cbase + tid;
-          const bool act = tid < DENSE_ACHUNK && t < d;
-          int32_t k = 0, len = 0;
-          V a = V(0);
-          int64_t boff = 0;
-          if (act) {
-            k = R.a_col[aoff + t];
-            a = ldv<V>(R.a_val, aoff + t);
-            if (split) {
-              const int64_t* ps = R.bs_ps + (int64_t)k * R.bs_parts + pc;
-              boff = ps[0];
-              len = (int32_t)(ps[1] - boff);
-            } else {
-              len = R.b_len[k];
-              boff = R.b_off[k];
-            }
-          }
-          const bool lng = act && len >= LONG_ROW;
-          const bool sht = act && len > 0 && len < LONG_ROW;
-          const uint64_t v = (lng ? (uint64_t)((len + 63) >> 6) : 0ull) | (sht ? (uint64_t)len << 24 : 0ull) |
-                             ((uint64_t)sht << 40) | ((uint64_t)lng << 50);
-          uint64_t inc = wave_inclusive_scan(v);
-          if (ln == 63) wscr64[wv] = inc;
-          grp.sync();
-          uint64_t before = 0, tot = 0;
-          for (int x = 0; x < NWV; ++x) {
-            const uint64_t c = wscr64[x];
-            if (x < wv) before += c;
-            tot += c;
-          }
-          inc += before;
-          const uint64_t exc = inc - v;
-          if (tid < DENSE_ACHUNK) {
-            ch.k[tid] = k;
-            ch.a[tid] = a;
-            ch.b[tid] = boff;
-            ch.so[tid] = len;  // (lengths: the order-free path sorts nothing)
-          }
-          if (lng) {
-            const int rl = (int)((exc >> 50) & 0x3ff);
-            sp.lidx[rl] = tid;
-            sp.tpre[rl + 1] = (int32_t)(inc & 0xffffff);
-          }
-          if (sht) {
-            const int rs = (int)((exc >> 40) & 0x3ff);
-            sp.sidx[rs] = tid;
-            sp.spre[rs + 1] = (int32_t)((inc >> 24) & 0xffff);
-          }
-          if (tid == 0) {
-            sp.spre[0] = 0;
-            sp.tpre[0] = 0;
-            sp.nlong = (int32_t)((tot >> 50) & 0x3ff);
-            sp.nshort = (int32_t)((tot >> 40) & 0x3ff);
-          }
-          grp.sync();
-        }
-        // Long B rows as 64-entry tiles; wavefront w takes UNR consecutive
-        // tiles per round, rounds TSTRIDE tiles apart.  Lane l describes the
-        // (l % UNR)-th tile of the (l / UNR)-th of the next RPD rounds (one
-        // segment search per lane), and each round reads its tiles' base,
-        // length and A value from those lanes.
-        constexpr int RPD = 64 / UNR;  // rounds per description
-        constexpr int TSTRIDE = NWV * UNR;
-        const int nl = sp.nlong;
-        const int ntiles = sp.tpre[nl];
-        for (int tb0 = wv * UNR; tb0 < ntiles; tb0 += TSTRIDE * RPD) {
-          const int my = tb0 + (ln / UNR) * TSTRIDE + (ln % UNR);
-          int64_t mpos = 0;
-          V ma = V(0);
-          int32_t mrem = 0;
-          if (my < ntiles) {
-            const int e = find_seg(sp.tpre, nl, my);
-            const int t = sp.lidx[e];
-            const int32_t x0 = (my - sp.tpre[e]) << 6;
-            mrem = min(64, ch.so[t] - x0);
-            mpos = ch.b[t] + x0;
-            ma = ch.a[t];
-          }
-          for (int r = 0; r < RPD && tb0 + r * TSTRIDE < ntiles; ++r) {
-            int64_t pos[UNR];
-            V av[UNR];
-            bool ok[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-              const int src = r * UNR + u;
-              ok[u] = ln < __builtin_amdgcn_readlane(mrem, src);
-              pos[u] = lane64(mpos, src) + ln;
-              av[u] = lanev<V>(ma, src);
-            }
-            accumulate_round(pos, av, ok);
-          }
-        }
-        // short B rows: 8-lane sub-groups, each streaming 4 rows at once (no
-        // search; 4 gathers in flight per lane)
-        const int ns = sp.nshort;
-        constexpr int NSG = DENSE_WG / 8;
-        const int sg = tid >> 3, l8 = tid & 7;
-        for (int eb = sg; eb < ns; eb += 4 * NSG) {
-          int64_t bo[4];
-          int32_t bl[4];
-          V ba[4];
-          int32_t mx = 0;
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int e = eb + u * NSG;
-            bl[u] = 0;
-            bo[u] = 0;
-            ba[u] = V(0);
-            if (e < ns) {
-              const int t = sp.sidx[e];
-              bo[u] = ch.b[t];
-              bl[u] = ch.so[t];
-              ba[u] = ch.a[t];
-              mx = max(mx, bl[u]);
-            }
-          }
-          for (int32_t x = l8; x < mx; x += 2 * UNR) {
-            int64_t pos[UNR];
-            V av[UNR];
-            bool ok[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) {
-              const int r = u & 3;
-              const int32_t xx = x + (u >> 2) * 8;
-              ok[u] = xx < bl[r];
-              pos[u] = bo[r] + xx;
-              av[u] = ba[r];
-            }
-            accumulate_round(pos, av, ok);
-          }
-        }
+        stage_split(cbase, split, pc);
+        for_rounds(accumulate_round);
       } else {
         stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, true, split ? pc : -1);
         for (int y = 0; y < cnt; ++y) {

@@ -213,6 +213,44 @@ def test_apply_heavy_rows(ctx, sr, with_product):
     destroy(Am)
 
 
+def test_dense_row_outgrows_its_hash(ctx):
+    """(min,+) rows of the dense bin are first tried in a single pass with an
+    LDS hash sized from the old row; a row that grows past it is redone with
+    the column passes.  Row 0 grows from ~20 entries to more than the table
+    holds, shrinks back, then changes a little (the hash path again); C and
+    the reported rows match the oracle at every step."""
+    sr = I.MIN_PLUS_F32
+    say("dense row outgrows its hash")
+    rng = np.random.default_rng(71)
+    n = 30000
+    keys = I.er_keys(n, 10 * n, rng)
+    keys = keys[(keys // n != 0) | (np.arange(keys.size) < 2)]  # row 0 starts with two entries
+    A = I.csr_from_keys(n, n, keys, I.draw_values(sr, keys.size, rng, 1, 100))
+    Am, _, P = gpu_product(ctx, sr, A)
+    cur = oracle.Csr.of(A)
+    C = oracle.spgemm(sr, cur, cur, nthreads=THREADS)
+    grow = rng.choice(np.arange(1, n), 2600, replace=False).astype(np.int32)
+    batches = [
+        I.Batch(np.zeros(2600, np.int32), grow, I.draw_values(sr, 2600, rng, 1, 100),
+                np.full(2600, I.OP_SET, np.uint8)),
+        I.Batch(np.zeros(2500, np.int32), grow[:2500], np.zeros(2500, np.float32),
+                np.full(2500, I.OP_DELETE, np.uint8)),
+        I.Batch(np.zeros(20, np.int32), grow[2500:2520], I.draw_values(sr, 20, rng, 1, 100),
+                np.full(20, I.OP_SET, np.uint8)),
+    ]
+    for t, b in enumerate(batches):
+        Am.apply_batch(b)
+        rs = P.update()
+        cur, _ = oracle.apply(sr, cur, b.rows, b.cols, b.vals, b.ops)
+        want = oracle.spgemm(sr, cur, cur, nthreads=THREADS)
+        assert_same_csr(sr, P.export(), want, f"step {t}", A=cur, B=cur)
+        assert np.array_equal(rs.row_ids(), changed_rows(C, want)), f"step {t}: reported rows"
+        if t == 0:
+            assert want.row_ptr[1] - want.row_ptr[0] > 16384  # more than the table's slots
+        C = want
+    destroy(P, Am)
+
+
 @pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
 @pytest.mark.parametrize("square", [True, False], ids=["AxA", "AxB"])
 def test_dynamic_sequence(ctx, sr, square):
