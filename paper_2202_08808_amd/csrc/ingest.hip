@@ -32,6 +32,8 @@ namespace {
 constexpr uint8_t K_KEEP = 0, K_SET = 1, K_DEL = 2;
 constexpr uint8_t OP_GUARD_ONLY = 3;  // internal op of mat_apply_sorted_add: no value
 constexpr int PLAN_LDS = 1024;        // update columns of a row held in LDS by the plan
+constexpr uint8_t PL_DEL = 1;         // plan flags of a touched row
+constexpr uint8_t PL_HEAVY = 2;
 constexpr int HEAVY_LEN = 2048;       // rows longer than this are planned by a whole workgroup
 constexpr uint8_t C_NOP = UPD_NOP, C_INS = UPD_INS, C_DEL = UPD_DEL, C_OVR = UPD_OVR, C_LOST = UPD_LOST;
 
@@ -93,7 +95,7 @@ struct Uniq {
   int32_t* plen;
   int32_t* pcap;
   uint8_t* pchg;
-  uint8_t* pdel;  // the row loses entries (decided by the plan)
+  uint8_t* pdel;  // plan flags: PL_DEL the row loses entries, PL_HEAVY planned by the workgroup kernel
   int32_t* holes;
   int32_t* mv_src;
   int32_t* mv_u;
@@ -323,7 +325,7 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
     bool reloc = nl > cap;
     U.plen[r] = nl;
     U.pchg[r] = chg ? 1 : 0;
-    U.pdel[r] = n_del > 0 ? 1 : 0;
+    U.pdel[r] = n_del > 0 ? PL_DEL : 0;
     U.pcap[r] = reloc ? slack_cap(nl) : 0;
     if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
   }
@@ -346,10 +348,11 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
   const int32_t ncap = U.pcap[r];
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   // rows that lose no entry take the ordered paths; the heavy ones of those
-  // belong to k_commit_heavy (which runs after this kernel and must not see
-  // the rows handled here: it goes by the plan, not by the row's length)
-  const bool nodel = !U.pdel[r];
-  if (nodel && u1 - u0 > PLAN_LDS) return;
+  // (as the plan recorded them: many updates or a long row) belong to
+  // k_commit_heavy, which runs after this kernel.  (The split goes by the
+  // plan's flags: a row's length changes here.)
+  const bool nodel = !(U.pdel[r] & PL_DEL);
+  if (nodel && (U.pdel[r] & PL_HEAVY)) return;
   if (nodel) {
     // ---- nothing deleted: the entries keep their order (moved as a block
     // when the row outgrows its space), overwrites go to the planned slots,
@@ -617,7 +620,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
       const bool reloc = nl > cap;
       U.plen[r] = nl;
       U.pchg[r] = chg ? 1 : 0;
-      U.pdel[r] = cnt[0] > 0 ? 1 : 0;
+      U.pdel[r] = (cnt[0] > 0 ? PL_DEL : 0) | PL_HEAVY;
       U.pcap[r] = reloc ? slack_cap(nl) : 0;
       if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
     }
@@ -625,9 +628,10 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
   }
 }
 
-// Commit of heavy rows without deletions (k_commit takes heavy rows with
-// deletions): move as a block if needed, overwrite at the planned slots,
-// append the inserts, emit the transpose changes.
+// Commit of heavy rows (more than PLAN_LDS updates or longer than HEAVY_LEN)
+// without deletions (k_commit takes the rows with deletions): move as a
+// block if needed (4 loads in flight per lane), overwrite at the planned
+// slots, append the inserts, emit the transpose changes.
 template <int SR, int VSZ>
 __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t* d_nR, uint64_t cmask, Uniq U,
                                                            const uint32_t* d_epoch, int tbits, uint64_t* dkey,
@@ -640,13 +644,13 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
   const int64_t nR = *d_nR;
   for (int64_t r = blockIdx.x; r < nR; r += gridDim.x) {
     const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
-    if (u1 - u0 <= PLAN_LDS || !U.pchg[r]) continue;
+    // unchanged, losing entries or light: k_commit did it
+    if (!U.pchg[r] || U.pdel[r] != PL_HEAVY) continue;
     const int32_t i = U.urow[r];
     const int64_t off = m.row_off[i];
     const int32_t len = m.row_len[i];
     const int32_t nl = U.plen[r];
     const int32_t ncap = U.pcap[r];
-    if (U.pdel[r]) continue;  // the row loses entries: k_commit did it
     int64_t dest = off;
     if (ncap) {
       if (tid == 0) dest_s = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
@@ -657,9 +661,23 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
         continue;
       }
       dest = (int64_t)dest_s;
-      for (int32_t t = tid; t < len; t += HEAVY_WG) {
-        m.col[dest + t] = m.col[off + t];
-        store_raw<VSZ>(m.val, dest + t, load_raw<VSZ>(m.val, off + t));
+      for (int32_t t0 = tid; t0 < len; t0 += 4 * HEAVY_WG) {
+        int32_t cc[4];
+        uint64_t vv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int32_t t = t0 + v * HEAVY_WG;
+          cc[v] = t < len ? m.col[off + t] : 0;
+          vv[v] = t < len ? load_raw<VSZ>(m.val, off + t) : 0;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int32_t t = t0 + v * HEAVY_WG;
+          if (t < len) {
+            m.col[dest + t] = cc[v];
+            store_raw<VSZ>(m.val, dest + t, vv[v]);
+          }
+        }
       }
       __syncthreads();
     }

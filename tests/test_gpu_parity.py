@@ -213,6 +213,44 @@ def test_apply_heavy_rows(ctx, sr, with_product):
     destroy(Am)
 
 
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+@pytest.mark.parametrize("with_product", [False, True], ids=["matrix", "product"])
+def test_apply_row_crosses_heavy_length(ctx, sr, with_product):
+    """A row planned as light (2040 entries, few updates) that grows past the
+    heavy-row length in the same batch is committed exactly once (the light
+    and workgroup commits split rows by the plan, not by the changed length)."""
+    say(f"apply row crosses heavy length {SR_ID[sr]} {with_product}")
+    rng = np.random.default_rng(91 + sr)
+    n = 6000
+    row0 = np.sort(rng.choice(n, 2040, replace=False)).astype(np.int64)
+    rest = I.er_keys(n, 4 * n, rng)
+    keys = np.unique(np.concatenate([row0, rest[rest >= n]]))
+    A = I.csr_from_keys(n, n, keys, I.draw_values(sr, keys.size, rng, 1, 9))
+    Am = dsg.Matrix.from_csr(ctx, A, sr)
+    P = dsg.Product(ctx, Am, Am) if with_product else None
+    cur = oracle.Csr.of(A)
+    absent = np.setdiff1d(np.arange(n), row0)
+    ins = rng.choice(absent, 30, replace=False).astype(np.int32)
+    other = I.random_batch(n, n, sr, 500, rng, op_probs=(0.5, 0.3, 0.2), value_lo=1, value_hi=9)
+    keep = other.rows != 0  # row 0 gets inserts only (the no-delete commit)
+    other = I.Batch(other.rows[keep], other.cols[keep], other.vals[keep], other.ops[keep])
+    b = I.Batch(np.concatenate([np.zeros(30, np.int32), other.rows]), np.concatenate([ins, other.cols]),
+                np.concatenate([I.draw_values(sr, 30, rng, 1, 9), other.vals]),
+                np.concatenate([np.full(30, I.OP_SET, np.uint8), other.ops]))
+    for t in range(2):
+        Am.apply_batch(b)
+        cur, _ = oracle.apply(sr, cur, b.rows, b.cols, b.vals, b.ops)
+        assert_same_csr(sr, Am.export(), cur, f"after batch {t}")
+        if P is not None:
+            P.update()
+            assert_same_csr(sr, P.export(), oracle.spgemm(sr, cur, cur, nthreads=THREADS), f"product {t}",
+                            A=cur, B=cur)
+        b = I.random_batch(n, n, sr, 300, rng, op_probs=(0.6, 0.2, 0.2), value_lo=1, value_hi=9)
+    if P is not None:
+        P.destroy()
+    destroy(Am)
+
+
 def test_dense_row_outgrows_its_hash(ctx):
     """(min,+) rows of the dense bin are first tried in a single pass with an
     LDS hash sized from the old row; a row that grows past it is redone with
