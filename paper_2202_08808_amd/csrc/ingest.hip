@@ -36,6 +36,8 @@ constexpr uint8_t PL_DEL = 1;         // plan flags of a touched row
 constexpr uint8_t PL_HEAVY = 2;
 constexpr int HEAVY_LEN = 2048;       // rows longer than this are planned by a whole workgroup
 constexpr uint8_t C_NOP = UPD_NOP, C_INS = UPD_INS, C_DEL = UPD_DEL, C_OVR = UPD_OVR, C_LOST = UPD_LOST;
+// the outcomes that change the operand, so the transpose index too
+__device__ inline bool emits_delta(uint8_t code) { return code == C_INS || code == C_DEL || code == C_OVR; }
 
 int bits_for(int64_t n) {
   int b = 0;
@@ -334,7 +336,7 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
 template <int SR, int VSZ>
 __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uint64_t cmask, int cbits,
                                                 Uniq U, const uint32_t* d_epoch, int tbits, uint64_t* dkey,
-                                                uint8_t* dop, void* dval, unsigned long long* d_ndelta,
+                                                uint8_t* dop, void* dval,
                                                 int64_t dcap, int* err) {
   const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
@@ -517,27 +519,20 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
     m.row_len[i] = nl;
     m.row_epoch[i] = *d_epoch;
   }
-  // changes for the transpose index: key (col << tbits) | row, with the value
+  // changes for the transpose index at the update's own index: key
+  // (col << tbits) | row, with the value (k_delta_keys reads the codes)
   if (dkey) {
-    for (int32_t base = u0; base < u1; base += 64) {
-      int32_t u = base + lane;
-      uint8_t code = u < u1 ? U.code[u] : C_NOP;
-      bool emit = code == C_INS || code == C_DEL || code == C_OVR;
-      uint64_t eb = __ballot(emit);
-      unsigned long long pos = 0;
-      if (lane == 0 && eb) pos = atomicAdd(d_ndelta, (unsigned long long)__popcll(eb));
-      pos = __shfl(pos, 0, 64);
-      if (emit) {
-        int64_t q = (int64_t)pos + __popcll(eb & lt);
-        if (q >= dcap) {  // more changes than updates: an internal error, never written past the list
-          atomicOr(err, 4);
-          continue;
-        }
-        uint64_t j = U.key[u] & cmask;
-        dkey[q] = (j << tbits) | (uint64_t)(uint32_t)i;
-        dop[q] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
-        store_raw<VSZ>(dval, q, U.fin[u]);
+    for (int32_t u = u0 + lane; u < u1; u += 64) {
+      const uint8_t code = U.code[u];
+      if (!emits_delta(code)) continue;
+      if (u >= dcap) {  // an internal error, never written past the list
+        atomicOr(err, 4);
+        continue;
       }
+      const uint64_t j = U.key[u] & cmask;
+      dkey[u] = (j << tbits) | (uint64_t)(uint32_t)i;
+      dop[u] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
+      store_raw<VSZ>(dval, u, U.fin[u]);
     }
   }
 }
@@ -635,7 +630,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
 template <int SR, int VSZ>
 __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t* d_nR, uint64_t cmask, Uniq U,
                                                            const uint32_t* d_epoch, int tbits, uint64_t* dkey,
-                                                           uint8_t* dop, void* dval, unsigned long long* d_ndelta,
+                                                           uint8_t* dop, void* dval,
                                                            int64_t dcap, int* err) {
   __shared__ int32_t wc[HEAVY_WG / 64];
   __shared__ unsigned long long dest_s;
@@ -712,34 +707,31 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
         m.row_cap[i] = ncap;
       }
     }
-    if (dkey) {
-      for (int32_t base = u0 + wv * 64; base < u1; base += HEAVY_WG) {
-        const int32_t u = base + lane;
-        const uint8_t code = u < u1 ? U.code[u] : C_NOP;
-        const bool emit = code == C_INS || code == C_DEL || code == C_OVR;
-        const uint64_t eb = __ballot(emit);
-        unsigned long long pos = 0;
-        if (lane == 0 && eb) pos = atomicAdd(d_ndelta, (unsigned long long)__popcll(eb));
-        pos = __shfl(pos, 0, 64);
-        if (emit && (int64_t)pos + __popcll(eb & lt) >= dcap) atomicOr(err, 4);
-        if (emit && (int64_t)pos + __popcll(eb & lt) < dcap) {
-          const int64_t q = (int64_t)pos + __popcll(eb & lt);
-          const uint64_t j = U.key[u] & cmask;
-          dkey[q] = (j << tbits) | (uint64_t)(uint32_t)i;
-          dop[q] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
-          store_raw<VSZ>(dval, q, U.fin[u]);
+    if (dkey) {  // at the update's own index, as in k_commit
+      for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) {
+        const uint8_t code = U.code[u];
+        if (!emits_delta(code)) continue;
+        if (u >= dcap) {
+          atomicOr(err, 4);
+          continue;
         }
+        const uint64_t j = U.key[u] & cmask;
+        dkey[u] = (j << tbits) | (uint64_t)(uint32_t)i;
+        dop[u] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
+        store_raw<VSZ>(dval, u, U.fin[u]);
       }
     }
     __syncthreads();
   }
 }
 
-__global__ void k_delta_keys(const uint64_t* dkey, const unsigned long long* d_nd, uint64_t sentinel,
+// Sort input of the transpose's apply: the delta of unique update t where it
+// changed the operand, the sentinel elsewhere (and past the unique updates).
+__global__ void k_delta_keys(const uint64_t* dkey, const uint8_t* code, const int64_t* d_nU, uint64_t sentinel,
                              uint64_t* keys, uint32_t* idx, int64_t n) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) {
-    keys[t] = t < (int64_t)*d_nd ? dkey[t] : sentinel;
+    keys[t] = t < *d_nU && emits_delta(code[t]) ? dkey[t] : sentinel;
     idx[t] = (uint32_t)t;
   }
 }
@@ -869,9 +861,9 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
   }
   // (graph mode: the caller reserved the worst case, see apply_headroom)
   hipLaunchKernelGGL((k_commit<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, cbits, w.U,
-                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, w.ndelta, n, w.err);
+                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, n, w.err);
   hipLaunchKernelGGL((k_commit_heavy<SR, VSZ>), dim3(nh), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.U,
-                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, w.ndelta, n, w.err);
+                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, n, w.err);
 }
 
 // Steps 2-6 on keys/idx already filled (n entries, sentinel-padded allowed).
@@ -922,9 +914,8 @@ void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const
   if (m->tidx) {
     DMat* t = m->tidx;
     int tk = bits_for(t->ncols) + bits_for(t->nrows);
-    // the emitted deltas occupy [0, ndelta); the rest of the n slots hold the sentinel
-    hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, w.ndelta, 1ull << tk, wt->keys,
-                       wt->idx, n);
+    hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, (const uint8_t*)w.U.code,
+                       (const int64_t*)w.nU, 1ull << tk, wt->keys, wt->idx, n);
     run_core(t, *wt, n, tk, true, w.dop, t->vsz ? w.dval : nullptr, graph);
   }
 }
