@@ -625,6 +625,8 @@ __global__ void k_sync_both(uint32_t* sync, const uint32_t* e) {
   sync[1] = *e;
 }
 
+__global__ void k_zero_i64(int64_t* p) { *p = 0; }
+
 __global__ void k_zero_n(unsigned long long* p, int n) {
   for (int x = threadIdx.x; x < n; x += blockDim.x) p[x] = 0ull;
 }
@@ -671,13 +673,13 @@ bool eligible(const DProd* p) {
 
 // Step 1, on its own: count the products the last apply changed (the
 // offsets stay in the context's second scratch for entry_finish).
-int64_t count_terms(DProd* p) {
+const int64_t* count_terms(DProd* p) {
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
   DMat* A = p->A;
   DMat* T = A->tidx;
   const int cbits = bits_for(A->ncols);
-  Log L{A->log_key, A->log_old, A->log_new, A->log_code, read_count(c, A->d_log_n)};
+  Log L{A->log_key, A->log_old, A->log_new, A->log_code, A->h_log_n};
   const int64_t nU = L.n;
   const size_t b1 = Carve::need({(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64});
   Carve cv1(ctx_scratch2(c, b1), b1);
@@ -685,17 +687,17 @@ int64_t count_terms(DProd* p) {
   int64_t* off = cv1.take<int64_t>(nU + 1);
   void* scan1 = cv1.take<char>(scan_scratch_bytes(nU + 1) + 64);
   int64_t* d_total = cv1.take<int64_t>(8);
-  int64_t nterm = 0;
   if (nU > 0) {
     Phase ph(c, "entry_count");
     hipLaunchKernelGGL(k_term_counts, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, cbits, (const int32_t*)A->row_len,
                        (const int32_t*)T->row_len, cnt);
     exclusive_scan_i64(cnt, off, nU, d_total, scan1, s);
-    nterm = read_count(c, d_total);
+  } else {
+    hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, d_total);
   }
   p->entry_nU = nU;
-  p->entry_nterm = nterm;
-  return nterm;
+  p->entry_nterm = -1;  // until the caller reads *d_total back
+  return d_total;
 }
 
 template <int SR>
@@ -956,6 +958,6 @@ int32_t entry_update(DProd* p) {
 
 bool entry_eligible(const DProd* p) { return eligible(p); }
 
-int64_t entry_count(DProd* p) { return count_terms(p); }
+const int64_t* entry_count(DProd* p) { return count_terms(p); }
 
 int32_t entry_finish(DProd* p) { return p->A->sr == 1 ? entry_update<1>(p) : entry_update<0>(p); }

@@ -1046,12 +1046,15 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   keep_log(m, w, n);
   if (c->timing) ctx_timing_end(c, e1);
   int* h = (int*)c->pinned;
+  int64_t* hn = (int64_t*)((char*)c->pinned + 64);
   h[1] = 0;
   if (deltas) DSG_HIP(hipMemcpyAsync(h + 1, wt.err, 4, hipMemcpyDeviceToHost, s));
   // a failed move (pool exhausted) would leave the batch half applied: report it loudly
   DSG_HIP(hipMemcpyAsync(h, w.err, 4, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipMemcpyAsync(hn, w.nU, 8, hipMemcpyDeviceToHost, s));  // the log's length, in the same wait
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(h[0] == 0 && h[1] == 0, DSG_E_DEVICE, "internal: pool overflow while applying a batch");
+  m->h_log_n = *hn;
   m->apply_seq++;
   m->log_seq = m->apply_seq;
 }

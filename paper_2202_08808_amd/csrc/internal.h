@@ -77,6 +77,7 @@ struct DMat {
   uint64_t* log_new = nullptr;
   uint8_t* log_code = nullptr;
   int64_t* d_log_n = nullptr;     // device: entries in the log
+  int64_t h_log_n = 0;            // host copy of *d_log_n
   int64_t log_cap = 0;
   uint64_t apply_seq = 0;         // applies so far
   uint64_t log_seq = 0;           // the apply whose log is held (0: none)
@@ -287,7 +288,9 @@ int32_t prod_run(DProd* p, int mode, bool report_affected);
 // called next with nothing else on that scratch in between, updates C and
 // returns the reported-row count.
 bool entry_eligible(const DProd* p);
-int64_t entry_count(DProd* p);
+// Queues the count; its total lands in *entry_count's result (device) and is
+// read back by the caller's next synchronisation into p->entry_nterm.
+const int64_t* entry_count(DProd* p);
 int32_t entry_finish(DProd* p);
 
 // Graph-capturable dynamic update (no host round trips) on a caller-owned

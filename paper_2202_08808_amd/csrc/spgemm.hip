@@ -1445,10 +1445,17 @@ __global__ __launch_bounds__(256) void k_scatter_dB(const int32_t* dB, const int
   const int lane = threadIdx.x & 63;
   const int32_t nB = *d_nB;
   for (int64_t x = wv; x < nB; x += nw) {
-    int32_t k = dB[x];
-    int64_t o = t_off[k];
-    int32_t l = t_len[k];
-    for (int32_t e = lane; e < l; e += 64) aff[t_col[o + e]] = 1;
+    const int32_t k = dB[x];
+    const int64_t o = t_off[k];
+    const int32_t l = t_len[k];
+    for (int32_t e0 = lane; e0 < l; e0 += 64 * 8) {  // 8 loads in flight per lane (hub columns)
+      int32_t c[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) c[u] = e0 + u * 64 < l ? t_col[o + e0 + u * 64] : -1;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c[u] >= 0) aff[c[u]] = 1;
+    }
   }
 }
 
@@ -1499,7 +1506,7 @@ __device__ inline int pick_bin(int32_t ub, int32_t d, const Tun& T) {
 
 // One wavefront per affected row (8 column loads in flight per lane, so a hub
 // row is no long chain of dependent loads): flops, ub, bin
-constexpr int ANALYZE_UNR = 8;
+constexpr int ANALYZE_UNR = 16;
 __global__ __launch_bounds__(256) void k_analyze(RowArgs R, const int32_t* d_count, Tun T) {
   const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int l = threadIdx.x & 63;
@@ -1787,6 +1794,7 @@ void ensure_arena(DProd* p, size_t bytes) {
 // ---------------------------------------------------------------------------
 
 constexpr int BSPLIT_MAXP = 8;
+constexpr int BSPLIT_UNR = 8;  // loads in flight per lane (hub rows)
 
 // one wavefront per row of B: entries per column chunk into ps[k*P + q]
 __global__ __launch_bounds__(256) void k_bsplit_count(const int64_t* b_off, const int32_t* b_len,
@@ -1801,15 +1809,15 @@ __global__ __launch_bounds__(256) void k_bsplit_count(const int64_t* b_off, cons
   int64_t cnt[BSPLIT_MAXP];
 #pragma unroll
   for (int q = 0; q < BSPLIT_MAXP; ++q) cnt[q] = 0;
-  for (int32_t e0 = 0; e0 < len; e0 += 256) {  // 4 loads in flight per lane
-    int part[4];
+  for (int32_t e0 = 0; e0 < len; e0 += 64 * BSPLIT_UNR) {  // BSPLIT_UNR loads in flight per lane
+    int part[BSPLIT_UNR];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < BSPLIT_UNR; ++v) {
       const int32_t e = e0 + v * 64 + ln;
       part[v] = e < len ? (b_col[off + e] >> chbits) : -1;
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+    for (int v = 0; v < BSPLIT_UNR; ++v)
 #pragma unroll
       for (int q = 0; q < BSPLIT_MAXP; ++q)
         if (q < P) cnt[q] += __popcll(__ballot(part[v] == q));
@@ -1837,17 +1845,17 @@ __global__ __launch_bounds__(256) void k_bsplit_scatter(const int64_t* b_off, co
   int64_t o[BSPLIT_MAXP];
 #pragma unroll
   for (int q = 0; q < BSPLIT_MAXP; ++q) o[q] = q < P ? ps[k * P + q] : 0;
-  for (int32_t e0 = 0; e0 < len; e0 += 256) {  // 4 loads in flight per lane
-    int32_t col[4];
-    W val[4];
+  for (int32_t e0 = 0; e0 < len; e0 += 64 * BSPLIT_UNR) {  // BSPLIT_UNR loads in flight per lane
+    int32_t col[BSPLIT_UNR];
+    W val[BSPLIT_UNR];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < BSPLIT_UNR; ++v) {
       const int32_t e = e0 + v * 64 + ln;
       col[v] = e < len ? b_col[off + e] : -1;
       val[v] = e < len ? ((const W*)b_val)[off + e] : W(0);
     }
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < BSPLIT_UNR; ++v) {
       const int part = col[v] >= 0 ? (col[v] >> chbits) : -1;
       int64_t dst = -1;
 #pragma unroll
@@ -2007,26 +2015,34 @@ void launch_rows(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
   }
 }
 
-// reported rows, statistics, sync epochs (no host round trip)
-void launch_tail(DProd* p, ProdWork& w, int64_t nmax) {
+void launch_set_sync(DProd* p, ProdWork& w) {
+  hipLaunchKernelGGL(k_set_sync, dim3(1), dim3(1), 0, p->ctx->stream, p->d_sync, (const uint32_t*)p->A->d_epoch,
+                     (const uint32_t*)p->B->d_epoch, (const Plan*)w.plan);
+}
+
+// reported rows, statistics and (when the rows are complete) the epochs C
+// now reflects (no host round trip)
+void launch_tail(DProd* p, ProdWork& w, int64_t nmax, bool set_sync = true) {
   hipStream_t s = p->ctx->stream;
   compact_list_by_flags(w.aff, w.chg, w.d_count, nmax, p->changed_rows, w.d_nchg, w.cscr, s);
   hipLaunchKernelGGL(k_reduce_stats, dim3(blocks_for(nmax, 256)), dim3(256), 0, s, w.rstat, w.binof, w.d_count,
                      w.stats);
-  hipLaunchKernelGGL(k_set_sync, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)p->A->d_epoch,
-                     (const uint32_t*)p->B->d_epoch, (const Plan*)w.plan);
+  if (set_sync) launch_set_sync(p, w);
 }
 
 // Read the plan back; also refresh the host's view of C's pool top, which the
-// row kernels advance on the device.
-Plan read_plan(Ctx* c, ProdWork& w, DMat* C) {
+// row kernels advance on the device (and, when given, one more device count
+// in the same wait).
+Plan read_plan(Ctx* c, ProdWork& w, DMat* C, const int64_t* d_extra = nullptr, int64_t* h_extra = nullptr) {
   Plan* hp = (Plan*)c->pinned;
   int64_t* htop = (int64_t*)((char*)c->pinned + 2048);
   DSG_HIP(hipMemcpyAsync(hp, w.plan, sizeof(Plan), hipMemcpyDeviceToHost, c->stream));
   DSG_HIP(hipMemcpyAsync(&hp->count, w.d_count, 4, hipMemcpyDeviceToHost, c->stream));
   DSG_HIP(hipMemcpyAsync(htop, C->d_top, 8, hipMemcpyDeviceToHost, c->stream));
+  if (d_extra) DSG_HIP(hipMemcpyAsync(htop + 1, d_extra, 8, hipMemcpyDeviceToHost, c->stream));
   DSG_HIP(hipStreamSynchronize(c->stream));
   C->h_top_ub = *htop;
+  if (h_extra) *h_extra = htop[1];
   return *hp;
 }
 
@@ -2067,16 +2083,20 @@ bool entry_cheaper(const dsg_tuning& t, int64_t nterm, unsigned long long row_fl
   return (double)row_flops > t.entry_fixed + t.entry_per_term * (double)nterm;
 }
 
-int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, int64_t entry_terms) {
+int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, const int64_t* d_entry_terms) {
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
   DMat* C = p->C;
   const int32_t n = p->A->nrows;
   RowArgs R = row_args(p, w, mode, report_affected);
   launch_front(p, mode, w, R);
-  Plan plan = read_plan(c, w, p->C);
+  int64_t entry_terms = -1;
+  Plan plan = read_plan(c, w, p->C, d_entry_terms, &entry_terms);
   // nothing of C was touched so far: hand over to the entry-granular path
-  if (entry_terms >= 0 && entry_cheaper(c->tuning, entry_terms, plan.flops)) return ENTRY_INSTEAD;
+  if (d_entry_terms) {
+    p->entry_nterm = entry_terms;
+    if (entry_cheaper(c->tuning, entry_terms, plan.flops)) return ENTRY_INSTEAD;
+  }
   // room: C grows only by what rows that do not fit ask for (retry below);
   // the arena keeps the largest size used so far, up to the analysis bound
   if (plan.arena_demand > p->arena_bytes) ensure_arena(p, std::min<size_t>(plan.arena_demand, std::max<size_t>(p->arena_bytes * 2, (size_t)64 << 20)));
@@ -2103,21 +2123,38 @@ int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, int
   }
   std::vector<std::pair<int, size_t>> timed;
   launch_rows(p, R, w, &plan, timed);
-  Plan after = read_plan(c, w, p->C);
-  if (after.c_short || after.arena_short) after = retry_rows(p, w, mode, report_affected, after, timed);
-  launch_tail(p, w, std::max<int32_t>(plan.count, 1));
-  // ---- results, statistics, errors ----
+  // ---- results, statistics, errors; with them, whether rows wait for room ----
   struct Tail {
     int32_t nchg;
     int32_t err;
+    unsigned long long c_short, arena_short;
+    int64_t c_top;
     unsigned long long stats[NBINS * NSTAT];
   };
-  Tail* ht = (Tail*)c->pinned;
-  DSG_HIP(hipMemcpyAsync(&ht->nchg, w.d_nchg, 4, hipMemcpyDeviceToHost, s));
-  DSG_HIP(hipMemcpyAsync(&ht->err, w.err, 4, hipMemcpyDeviceToHost, s));
-  DSG_HIP(hipMemcpyAsync(ht->stats, w.stats, sizeof(ht->stats), hipMemcpyDeviceToHost, s));
-  DSG_HIP(hipStreamSynchronize(s));
-  Tail tail = *ht;
+  Tail* ht = (Tail*)((char*)c->pinned + 1024);
+  static_assert(1024 + sizeof(Tail) <= 4096, "pinned staging");
+  auto read_tail = [&]() {
+    launch_tail(p, w, std::max<int32_t>(plan.count, 1), false);
+    DSG_HIP(hipMemcpyAsync(&ht->nchg, w.d_nchg, 4, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipMemcpyAsync(&ht->err, w.err, 4, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipMemcpyAsync(&ht->c_short, &w.plan->c_short, 16, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipMemcpyAsync(&ht->c_top, C->d_top, 8, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipMemcpyAsync(ht->stats, w.stats, sizeof(ht->stats), hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipStreamSynchronize(s));
+    C->h_top_ub = ht->c_top;
+    return *ht;
+  };
+  Tail tail = read_tail();
+  if (tail.c_short || tail.arena_short) {
+    // some rows found no room: grow it, recompute them, and take the tail again
+    Plan after = plan;
+    after.c_short = tail.c_short;
+    after.arena_short = tail.arena_short;
+    retry_rows(p, w, mode, report_affected, after, timed);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(256), 0, s, w.stats, NBINS * NSTAT);
+    tail = read_tail();
+  }
+  launch_set_sync(p, w);
   DSG_REQUIRE(tail.err == 0, DSG_E_DEVICE, "internal: row kernel reported error code " + std::to_string(tail.err));
   dsg_update_stats& st = p->stats;
   st = dsg_update_stats{};
@@ -2193,10 +2230,14 @@ void prod_destroy(DProd* p) {
 int32_t prod_run(DProd* p, int mode, bool report_affected) {
   int32_t nchg = 0;
   // entry-granular candidate: count its changed products first (cheap)
-  int64_t nterm = -1;
+  const int64_t* d_nterm = nullptr;
   if (mode == 0 && !report_affected && entry_eligible(p)) {
-    nterm = entry_count(p);
+    d_nterm = entry_count(p);
     if (p->ctx->tuning.update_path == 2) {
+      int64_t* h = (int64_t*)((char*)p->ctx->pinned + 3072);
+      DSG_HIP(hipMemcpyAsync(h, d_nterm, 8, hipMemcpyDeviceToHost, p->ctx->stream));
+      DSG_HIP(hipStreamSynchronize(p->ctx->stream));
+      p->entry_nterm = *h;
       nchg = entry_finish(p);
       p->a_seq = p->A->apply_seq;
       p->b_seq = p->B->apply_seq;
@@ -2208,7 +2249,7 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   ensure_changed_cap(p, 0);
   const size_t need = work_bytes_for(N, nB);
   ProdWork w = carve_prod(ctx_scratch(p->ctx, need), N, nB);
-  nchg = prod_sequence(p, mode, report_affected, w, nterm);
+  nchg = prod_sequence(p, mode, report_affected, w, d_nterm);
   if (nchg == ENTRY_INSTEAD) nchg = entry_finish(p);
   p->a_seq = p->A->apply_seq;
   p->b_seq = p->B->apply_seq;
