@@ -187,20 +187,28 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   bool ws_changed = false;
   for (size_t k = 0; k < sets.size(); ++k) {
     DMat* m = sets[k].m;
-    mat_reserve(m, apply_headroom(m, sets[k].n));
-    if (m->tidx) mat_reserve(m->tidx, apply_headroom(m->tidx, sets[k].n));
+    // (a compaction makes room for about four rounds: each one changes the
+    // pools the graph bakes in)
+    const int64_t hm = apply_headroom(m, sets[k].n);
+    mat_reserve(m, hm, 4 * hm);
+    if (m->tidx) {
+      const int64_t ht = apply_headroom(m->tidx, sets[k].n);
+      mat_reserve(m->tidx, ht, 4 * ht);
+    }
     ensure_ws(c, b->aw, b->aw_bytes, k, apply_work_bytes(sets[k].n, m->tidx != nullptr), ws_changed);
     ensure_ws(c, b->awt, b->awt_bytes, k, apply_work_bytes(sets[k].n, false), ws_changed);
   }
   std::vector<int64_t> c_top_before(np);
   for (size_t j = 0; j < np; ++j) {
     DProd* p = b->prods[j];
-    // room for C: an eighth of its pool or twice what the last run took,
-    // whichever is more; rows that need still more are completed after the
-    // replay
-    const int64_t c_room = std::max<int64_t>(p->C->h_top_ub / 8, 2 * p->last_c_growth) + 4096;
+    // room for C: twice what the last run took, at least 1/64 of its pool;
+    // rows that need still more are completed after the replay.  (A
+    // compaction leaves a third of the new pool free, so a floor this low
+    // makes C's pool, and the graph that bakes it in, change only every few
+    // dozen rounds.)
+    const int64_t c_room = std::max<int64_t>(p->C->h_top_ub / 64, 2 * p->last_c_growth) + 4096;
     const size_t arena = std::max<size_t>(p->arena_bytes, (size_t)1 << 20);
-    prod_prepare_graph(p, c_room, arena);
+    prod_prepare_graph(p, c_room, arena, 4 * c_room);
     ensure_ws(c, b->pw, b->pw_bytes, j, prod_graph_work_bytes(p), ws_changed);
     c_top_before[j] = p->C->h_top_ub;
   }

@@ -181,6 +181,9 @@ DMat* mat_create(Ctx* c, int32_t nrows, int32_t ncols, int sr, const int64_t* d_
 void mat_destroy(DMat* m);
 // Make sure `extra` more slots can be taken from the pool top; may compact.
 void mat_reserve(DMat* m, int64_t extra);
+// Same, but a compaction (only when fewer than `extra` slots are free) makes
+// room for `want` >= extra: fewer compactions for pools that grow fast.
+void mat_reserve(DMat* m, int64_t extra, int64_t want);
 void mat_compact(DMat* m, int64_t extra);
 int64_t mat_nnz(DMat* m);
 // Canonical (column-sorted) CSR copy on the device: row_ptr[nrows+1], col, val.
@@ -302,7 +305,7 @@ int32_t entry_finish(DProd* p);
 // round trips) grows the room, recomputes those rows and returns the final
 // reported-row count.
 size_t prod_graph_work_bytes(const DProd* p);
-void prod_prepare_graph(DProd* p, int64_t c_headroom, size_t arena_bytes);
+void prod_prepare_graph(DProd* p, int64_t c_headroom, size_t arena_bytes, int64_t c_want = 0);
 void prod_update_graph(DProd* p, void* work, int64_t* d_out);
 int32_t prod_finish_graph(DProd* p, void* work);
 

@@ -294,11 +294,13 @@ void mat_compact(DMat* m, int64_t extra) {
   ctx_free(c, new_off, nn * 8);
 }
 
-void mat_reserve(DMat* m, int64_t extra) {
+void mat_reserve(DMat* m, int64_t extra) { mat_reserve(m, extra, extra); }
+
+void mat_reserve(DMat* m, int64_t extra, int64_t want) {
   if (m->pool_cap - m->h_top_ub >= extra) return;
   m->h_top_ub = read_i64(m->ctx, m->d_top);
   if (m->pool_cap - m->h_top_ub >= extra) return;
-  mat_compact(m, extra);
+  mat_compact(m, std::max(extra, want));
 }
 
 int64_t mat_nnz(DMat* m) {

@@ -2260,10 +2260,10 @@ size_t prod_graph_work_bytes(const DProd* p) {
   return work_bytes_for(std::max<int32_t>(p->A->nrows, 1), std::max<int32_t>(p->B->nrows, 1));
 }
 
-void prod_prepare_graph(DProd* p, int64_t c_headroom, size_t arena_bytes) {
+void prod_prepare_graph(DProd* p, int64_t c_headroom, size_t arena_bytes, int64_t c_want) {
   ensure_changed_cap(p, std::max<int32_t>(p->A->nrows, 1));
   ensure_arena(p, arena_bytes);
-  mat_reserve(p->C, c_headroom);
+  mat_reserve(p->C, c_headroom, std::max(c_headroom, c_want));
 }
 
 void prod_update_graph(DProd* p, void* work, int64_t* d_out) {
@@ -2286,6 +2286,9 @@ int32_t prod_finish_graph(DProd* p, void* work) {
   const int64_t nB = std::max<int32_t>(p->B->nrows, 1);
   ProdWork w = carve_prod(work, N, nB);
   Plan plan = read_plan(c, w, p->C);
+  // the next replay should find room for every row: grow the arena by what
+  // this one lacked (C's room follows its measured growth)
+  if (plan.arena_short) ensure_arena(p, p->arena_bytes + plan.arena_short);
   std::vector<std::pair<int, size_t>> none;
   retry_rows(p, w, 0, false, plan, none);
   launch_tail(p, w, N);
