@@ -129,7 +129,8 @@ typedef struct {
   int32_t update_path;     /* dynamic updates of C = A*A over (min,+) or int64 (+,x):
                               0 automatic (see below); 1 always whole rows; 2 entry-granular
                               whenever it applies.  Same results every way. */
-  int32_t reserved;        /* 0 */
+  int32_t batch_direct_log2; /* batched form: products whose C holds at least 2^this slots take the
+                              plain path beside the graph replay (default 24; 0..62) */
   /* Automatic choice: the entry-granular path runs when the products of the
    * affected rows exceed entry_fixed + entry_per_term * (the changed
    * products).  Defaults 2e8 and 500 (fitted on MI355X); both finite, >= 0. */
@@ -268,15 +269,18 @@ dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int32_t nprod,
 /* Apply nsets update sets (each to a distinct operand of one of the batch's
  * products) and bring every product up to date: the same C, row contents and
  * reported rows as dsg_mat_apply on each set followed by dsg_prod_update on
- * each product.  All products' chains (ingest, discovery, row recompute,
- * merge) are one hipGraph replay, with one host round trip before it
- * (validation of every set) and one after it (results).  The graph is
- * captured on the first run and replayed while the set arrays, their sizes
- * and the storage of every object stay the same (a run with other arrays or
- * after storage grew captures again).  Rows of C that find no room in C's
- * pool or in the staging space set aside write nothing during the replay;
- * after it, the room grows by exactly what they asked for and only those rows
- * are recomputed, with the same result.  changed_counts (host, nprod entries)
+ * each product.  The chains (ingest, discovery, row recompute, merge) of
+ * products whose C holds fewer than 2^batch_direct_log2 slots (tuning) are one hipGraph replay, with
+ * one host round trip before it (validation of every set) and one after it
+ * (results); the replay runs on a stream of its own while the products with a
+ * larger C take the plain path (apply and update, with their round trips) on
+ * the context's stream.  The graph is captured on the first run and replayed
+ * while the set arrays, their sizes and the storage of every object it
+ * touches stay the same (a run with other arrays or after storage grew
+ * captures again).  Rows of C that find no room in C's pool or in the staging
+ * space set aside write nothing during the replay; after it, the room grows
+ * by exactly what they asked for and only those rows are recomputed, with the
+ * same result.  changed_counts (host, nprod entries)
  * receives each product's reported row count; dsg_batch_rows gives the rows.
  * Errors: DSG_E_RANGE / DSG_E_ARG for a bad set (nothing is applied). */
 dsg_status dsg_batch_run(dsg_batch* b, const dsg_update_set* sets, int32_t nsets, uint32_t flags,
@@ -291,8 +295,10 @@ typedef struct {
   int64_t deferred;   /* products with rows completed after the replay */
   double prepare_ms;  /* validation round trip and room reservation */
   double capture_ms;  /* capture and instantiation */
-  double replay_ms;   /* launch until the results were read back */
+  double replay_ms;   /* launch until the results were read back (the direct products run meanwhile) */
   double finish_ms;   /* completion of rows that waited for room */
+  int64_t direct;     /* product updates that took the plain path (C of at least 2^24 slots) */
+  double direct_ms;   /* their time (apply and update), beside the replay */
 } dsg_batch_stats;
 dsg_status dsg_batch_info(const dsg_batch* b, dsg_batch_stats* out);
 dsg_status dsg_batch_destroy(dsg_batch* b);

@@ -149,7 +149,7 @@ static void default_tuning(dsg_tuning* t) {
   t->dense_max_passes = 4;
   t->force_bin = -1;
   t->update_path = 0;
-  t->reserved = 0;
+  t->batch_direct_log2 = 24;
   t->entry_fixed = 2e8;
   t->entry_per_term = 500.0;
 }
@@ -328,6 +328,8 @@ extern "C" dsg_status dsg_ctx_set_tuning(dsg_ctx* ctx, const dsg_tuning* t) {
   if (t->dense_max_passes < 0) return fail(ctx, DSG_E_ARG, "dense_max_passes < 0");
   if (t->force_bin < -1 || t->force_bin > 9) return fail(ctx, DSG_E_ARG, "force_bin outside [-1, 9]");
   if (t->update_path < 0 || t->update_path > 2) return fail(ctx, DSG_E_ARG, "update_path outside [0, 2]");
+  if (t->batch_direct_log2 < 0 || t->batch_direct_log2 > 62)
+    return fail(ctx, DSG_E_ARG, "batch_direct_log2 outside [0, 62]");
   if (!(t->entry_fixed >= 0.0 && t->entry_fixed < 1e300) || !(t->entry_per_term >= 0.0 && t->entry_per_term < 1e300))
     return fail(ctx, DSG_E_ARG, "entry_fixed and entry_per_term must be finite and >= 0");
   ctx->c.tuning = *t;

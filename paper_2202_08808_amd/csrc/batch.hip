@@ -1,5 +1,10 @@
 // Batched form: many independent products, each with its own update sets,
-// brought up to date by one hipGraph replay.
+// brought up to date together.  Products whose C is large (at least
+// 2^batch_direct_log2 slots, a tuning field) take the plain path on the context's stream, with its host
+// round trips, which their kernel time hides, and with everything it offers
+// (the split copy of B, the entry-granular choice, room sized from the
+// plan); the others are brought up to date by one hipGraph replay on a
+// stream of its own, which runs meanwhile.
 //
 // Each product's chain (apply its operands' sets, then the dynamic update)
 // is captured on a stream of its own, forked from and joined to the
@@ -54,10 +59,13 @@ struct DBatch {
   int64_t** d_top_ptrs = nullptr;
   int* d_valid = nullptr;
   std::vector<hipStream_t> streams;
+  hipStream_t replay_stream = nullptr;  // the graph's replay runs here, beside the direct products
+  hipEvent_t ev_ready = nullptr;        // preparation on the context's stream done
+  std::vector<uint8_t> graphed;         // per product: in the graph (else the plain path)
   hipEvent_t ev_fork = nullptr;
   std::vector<hipEvent_t> ev_join;
-  int64_t captures = 0, replays = 0, deferred = 0;
-  double prepare_ms = 0, capture_ms = 0, replay_ms = 0, finish_ms = 0;
+  int64_t captures = 0, replays = 0, deferred = 0, direct = 0;
+  double prepare_ms = 0, capture_ms = 0, replay_ms = 0, finish_ms = 0, direct_ms = 0;
 };
 
 static double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -97,6 +105,8 @@ DBatch* batch_create(Ctx* c, const std::vector<DProd*>& prods) {
       DSG_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
       b->streams.push_back(s);
     }
+    DSG_HIP(hipStreamCreateWithFlags(&b->replay_stream, hipStreamNonBlocking));
+    DSG_HIP(hipEventCreateWithFlags(&b->ev_ready, hipEventDisableTiming));
     DSG_HIP(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
     b->ev_join.resize(prods.size());
     for (auto& e : b->ev_join) DSG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -121,6 +131,11 @@ void batch_destroy(DBatch* b) {
   ctx_free(c, b->d_top_ptrs, b->mats.size() * 8 + 8);
   ctx_free(c, b->d_valid, 4 * (np * 2 + 1));
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  if (b->replay_stream) {
+    (void)hipStreamSynchronize(b->replay_stream);
+    (void)hipStreamDestroy(b->replay_stream);
+  }
+  if (b->ev_ready) (void)hipEventDestroy(b->ev_ready);
   if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
   for (auto& e : b->ev_join)
     if (e) (void)hipEventDestroy(e);
@@ -138,6 +153,8 @@ void batch_info(const DBatch* b, dsg_batch_stats* out) {
   out->capture_ms = b->capture_ms;
   out->replay_ms = b->replay_ms;
   out->finish_ms = b->finish_ms;
+  out->direct = b->direct;
+  out->direct_ms = b->direct_ms;
 }
 
 static void ensure_ws(Ctx* c, std::vector<void*>& v, std::vector<size_t>& have, size_t i, size_t bytes,
@@ -183,9 +200,22 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
       if (h[k] & 2) return DSG_E_ARG;
     }
   }
-  // ---- room: worst case for operands, last need plus margin for C ----
+  // ---- which products the graph takes: the ones whose C is small ----
+  std::vector<uint8_t> graphed(np, 0);
+  std::vector<DMat*> gmats;  // the matrices the graph touches
+  size_t ng = 0;
+  for (size_t j = 0; j < np; ++j) {
+    DProd* p = b->prods[j];
+    graphed[j] = p->C->h_top_ub < (int64_t(1) << c->tuning.batch_direct_log2) ? 1 : 0;
+    if (!graphed[j]) continue;
+    ++ng;
+    for (DMat* m : {p->A, p->B, p->A->tidx, p->C})
+      if (m && std::find(gmats.begin(), gmats.end(), m) == gmats.end()) gmats.push_back(m);
+  }
+  // ---- room for the graph: worst case for operands, last need plus margin for C ----
   bool ws_changed = false;
   for (size_t k = 0; k < sets.size(); ++k) {
+    if (!graphed[(size_t)owner[k]]) continue;
     DMat* m = sets[k].m;
     // (a compaction makes room for about four rounds: each one changes the
     // pools the graph bakes in)
@@ -200,6 +230,7 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   }
   std::vector<int64_t> c_top_before(np);
   for (size_t j = 0; j < np; ++j) {
+    if (!graphed[j]) continue;
     DProd* p = b->prods[j];
     // room for C: twice what the last run took, at least 1/64 of its pool;
     // rows that need still more are completed after the replay.  (A
@@ -213,17 +244,19 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     c_top_before[j] = p->C->h_top_ub;
   }
   // ---- the signature of what a graph bakes in ----
-  std::vector<uintptr_t> sig;
+  std::vector<uintptr_t> sig(graphed.begin(), graphed.end());
   for (size_t k = 0; k < sets.size(); ++k) {
-    const DBatchSet& s = sets[k];
-    for (uintptr_t x : {(uintptr_t)s.m, (uintptr_t)s.rows, (uintptr_t)s.cols, (uintptr_t)s.vals, (uintptr_t)s.ops,
-                        (uintptr_t)s.n, (uintptr_t)b->aw[k], (uintptr_t)b->awt[k]})
+    if (!graphed[(size_t)owner[k]]) continue;
+    const DBatchSet& st = sets[k];
+    for (uintptr_t x : {(uintptr_t)st.m, (uintptr_t)st.rows, (uintptr_t)st.cols, (uintptr_t)st.vals,
+                        (uintptr_t)st.ops, (uintptr_t)st.n, (uintptr_t)b->aw[k], (uintptr_t)b->awt[k]})
       sig.push_back(x);
   }
-  for (DMat* m : b->mats)
+  for (DMat* m : gmats)
     for (uintptr_t x : {(uintptr_t)m->col, (uintptr_t)m->val, (uintptr_t)m->pool_cap, (uintptr_t)m->version})
       sig.push_back(x);
   for (size_t j = 0; j < np; ++j) {
+    if (!graphed[j]) continue;
     DProd* p = b->prods[j];
     for (uintptr_t x : {(uintptr_t)p->changed_rows, (uintptr_t)p->arena, (uintptr_t)p->arena_bytes,
                         (uintptr_t)p->arena_top, (uintptr_t)b->pw[j]})
@@ -234,31 +267,34 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   sig.push_back((uintptr_t)t.dense_max_passes);
   sig.push_back((uintptr_t)(t.force_bin + 1));
   b->prepare_ms += ms_since(t0);
-  if (!b->exec || sig != b->signature) {
+  if (ng > 0 && (!b->exec || sig != b->signature)) {
     t0 = std::chrono::steady_clock::now();
     drop_graph(b);
-    // device table of the pool tops the graph reports back
-    std::vector<int64_t*> tops;
-    for (DMat* m : b->mats) tops.push_back(m->d_top);
-    DSG_HIP(hipMemcpyAsync(b->d_top_ptrs, tops.data(), tops.size() * 8, hipMemcpyHostToDevice, main));
+    // device table of the pool tops the graph reports back (device addresses
+    // of each touched matrix's top)
+    std::vector<int64_t*> top_ptrs;
+    for (DMat* m : gmats) top_ptrs.push_back(m->d_top);
+    DSG_HIP(hipMemcpyAsync(b->d_top_ptrs, top_ptrs.data(), top_ptrs.size() * 8, hipMemcpyHostToDevice, main));
     DSG_HIP(hipStreamSynchronize(main));
     hipGraph_t graph = nullptr;
     DSG_HIP(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
     try {
       hipLaunchKernelGGL(k_clear_out, dim3(1), dim3(256), 0, main, b->d_out, (int)(np * OUT_WORDS));
       DSG_HIP(hipEventRecord(b->ev_fork, main));
+      size_t lane = 0;
       for (size_t j = 0; j < np; ++j) {
-        hipStream_t sj = b->streams[j % b->streams.size()];
+        if (!graphed[j]) continue;
+        hipStream_t sj = b->streams[lane++ % b->streams.size()];
         DSG_HIP(hipStreamWaitEvent(sj, b->ev_fork, 0));
         c->stream = sj;
         int slot = 6;
         for (size_t k = 0; k < sets.size(); ++k) {
           if (owner[k] != (int)j) continue;
-          const DBatchSet& s = sets[k];
-          mat_apply_graph(s.m, s.rows, s.cols, s.vals, s.ops, s.n, b->aw[k], b->awt[k]);
-          if (s.n > 0) {
-            const int* e1 = apply_err_ptr(b->aw[k], s.n, s.m->tidx != nullptr);
-            const int* e2 = s.m->tidx ? apply_err_ptr(b->awt[k], s.n, false) : nullptr;
+          const DBatchSet& st = sets[k];
+          mat_apply_graph(st.m, st.rows, st.cols, st.vals, st.ops, st.n, b->aw[k], b->awt[k]);
+          if (st.n > 0) {
+            const int* e1 = apply_err_ptr(b->aw[k], st.n, st.m->tidx != nullptr);
+            const int* e2 = st.m->tidx ? apply_err_ptr(b->awt[k], st.n, false) : nullptr;
             hipLaunchKernelGGL(k_or_flags, dim3(1), dim3(1), 0, sj, e1, e2, b->d_out + j * OUT_WORDS + slot);
           }
           slot = 7;
@@ -267,9 +303,10 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
         DSG_HIP(hipEventRecord(b->ev_join[j], sj));
       }
       c->stream = main;
-      for (size_t j = 0; j < np; ++j) DSG_HIP(hipStreamWaitEvent(main, b->ev_join[j], 0));
+      for (size_t j = 0; j < np; ++j)
+        if (graphed[j]) DSG_HIP(hipStreamWaitEvent(main, b->ev_join[j], 0));
       hipLaunchKernelGGL(k_gather_tops, dim3(1), dim3(256), 0, main, (int64_t* const*)b->d_top_ptrs,
-                         (int)b->mats.size(), b->d_tops);
+                         (int)gmats.size(), b->d_tops);
       DSG_HIP(hipGetLastError());
     } catch (...) {
       c->stream = main;
@@ -285,21 +322,39 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     b->captures++;
     b->capture_ms += ms_since(t0);
   }
-  // ---- one replay for every product ----
+  // ---- the replay, on its own stream once the preparation is done ----
   t0 = std::chrono::steady_clock::now();
-  DSG_HIP(hipGraphLaunch(b->exec, main));
-  b->replays++;
-  std::vector<int64_t> out(np * OUT_WORDS), tops(b->mats.size());
-  DSG_HIP(hipMemcpyAsync(out.data(), b->d_out, out.size() * 8, hipMemcpyDeviceToHost, main));
-  DSG_HIP(hipMemcpyAsync(tops.data(), b->d_tops, tops.size() * 8, hipMemcpyDeviceToHost, main));
-  DSG_HIP(hipStreamSynchronize(main));
-  for (size_t i = 0; i < b->mats.size(); ++i) b->mats[i]->h_top_ub = tops[i];
+  if (ng > 0) {
+    DSG_HIP(hipEventRecord(b->ev_ready, main));
+    DSG_HIP(hipStreamWaitEvent(b->replay_stream, b->ev_ready, 0));
+    DSG_HIP(hipGraphLaunch(b->exec, b->replay_stream));
+    b->replays++;
+  }
+  // ---- meanwhile the large products, plain path, on the context's stream ----
+  const auto td = std::chrono::steady_clock::now();
+  for (size_t j = 0; j < np; ++j) {
+    if (graphed[j]) continue;
+    for (size_t k = 0; k < sets.size(); ++k)
+      if (owner[k] == (int)j) mat_apply_device(sets[k].m, sets[k].rows, sets[k].cols, sets[k].vals, sets[k].ops,
+                                               sets[k].n);
+    counts[j] = prod_run(b->prods[j], 0, false);
+    b->direct++;
+  }
+  b->direct_ms += ms_since(td);
+  if (ng == 0) return DSG_OK;
+  // ---- the graph's results ----
+  std::vector<int64_t> out(np * OUT_WORDS), tops(gmats.size());
+  DSG_HIP(hipMemcpyAsync(out.data(), b->d_out, out.size() * 8, hipMemcpyDeviceToHost, b->replay_stream));
+  DSG_HIP(hipMemcpyAsync(tops.data(), b->d_tops, tops.size() * 8, hipMemcpyDeviceToHost, b->replay_stream));
+  DSG_HIP(hipStreamSynchronize(b->replay_stream));
+  for (size_t i = 0; i < gmats.size(); ++i) gmats[i]->h_top_ub = tops[i];
   // these applies keep no log: the entry-granular update does not follow them
-  for (const DBatchSet& st : sets)
-    if (st.n > 0) st.m->apply_seq++;
+  for (size_t k = 0; k < sets.size(); ++k)
+    if (graphed[(size_t)owner[k]] && sets[k].n > 0) sets[k].m->apply_seq++;
   b->replay_ms += ms_since(t0);
   t0 = std::chrono::steady_clock::now();
   for (size_t j = 0; j < np; ++j) {
+    if (!graphed[j]) continue;
     const int64_t* o = &out[j * OUT_WORDS];
     DSG_REQUIRE(o[2] == 0 && o[6] == 0 && o[7] == 0, DSG_E_DEVICE,
                 "internal: device error flags " + std::to_string(o[2]) + "/" + std::to_string(o[6]) + "/" +

@@ -41,7 +41,7 @@ class Rows(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("group_ub", ctypes.c_int32 * 8), ("dense_max_passes", ctypes.c_int32),
-                ("force_bin", ctypes.c_int32), ("update_path", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("force_bin", ctypes.c_int32), ("update_path", ctypes.c_int32), ("batch_direct_log2", ctypes.c_int32),
                 ("entry_fixed", ctypes.c_double), ("entry_per_term", ctypes.c_double)]
 
 
@@ -63,7 +63,8 @@ class Stats(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("captures", ctypes.c_int64), ("replays", ctypes.c_int64), ("deferred", ctypes.c_int64),
                 ("prepare_ms", ctypes.c_double), ("capture_ms", ctypes.c_double),
-                ("replay_ms", ctypes.c_double), ("finish_ms", ctypes.c_double)]
+                ("replay_ms", ctypes.c_double), ("finish_ms", ctypes.c_double), ("direct", ctypes.c_int64),
+                ("direct_ms", ctypes.c_double)]
 
 
 class ServerCfg(ctypes.Structure):

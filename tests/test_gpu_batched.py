@@ -41,9 +41,15 @@ def to_dev(b):
     return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (b.rows, b.cols, b.vals, b.ops)]
 
 
-def test_batched_equals_plain_loop(ctx):
+@pytest.mark.parametrize("direct_log2", [24, 16, 0], ids=["graph", "mixed", "direct"])
+def test_batched_equals_plain_loop(ctx, direct_log2):
+    """All instances in the graph (C under 2^24 slots), a mix (the three with
+    C over 2^16 slots take the plain path beside the replay), and none."""
     import torch
-    say("batched vs plain loop")
+    say(f"batched vs plain loop, direct from 2^{direct_log2}")
+    tu = ctx.get_tuning()
+    tu.batch_direct_log2 = direct_log2
+    ctx.set_tuning(tu)
     inst = instances(6, 3)
     plain, batched, oracles = [], [], []
     for sr, A, _ in inst:
@@ -82,7 +88,13 @@ def test_batched_equals_plain_loop(ctx):
             assert_same_csr(sr, got_batch, want, f"oracle round {rnd} instance {t}")
             assert np.array_equal(rs.row_ids(), changed_rows(C_before, want))
     info = B.info()
-    assert info["replays"] == 3 and info["captures"] >= 1
+    if direct_log2 == 24:
+        assert info["replays"] == 3 and info["captures"] >= 1 and info["direct"] == 0
+    elif direct_log2 == 0:
+        assert info["replays"] == 0 and info["direct"] == 3 * len(inst)
+    else:
+        assert info["replays"] == 3 and 0 < info["direct"] < 3 * len(inst)
+    ctx.set_tuning(None)
     B.destroy()
     for a, p in plain + batched:
         p.destroy()
