@@ -16,8 +16,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-PLUS_TIMES_I64, MIN_PLUS_F32, PLUS_TIMES_F64 = 0, 1, 2
-DTYPE = {PLUS_TIMES_I64: np.int64, MIN_PLUS_F32: np.float32, PLUS_TIMES_F64: np.float64}
+PLUS_TIMES_I64, MIN_PLUS_F32, PLUS_TIMES_F64, OR_AND_U32 = 0, 1, 2, 3
+DTYPE = {PLUS_TIMES_I64: np.int64, MIN_PLUS_F32: np.float32, PLUS_TIMES_F64: np.float64,
+         OR_AND_U32: np.uint32}
 
 
 def build(out_path: str = LIB_PATH, src_dir: str = HERE) -> str:
@@ -45,6 +46,10 @@ def lib(path: str = LIB_PATH):
     L.orc_spgemm.restype = ctypes.c_int
     L.orc_spgemm.argtypes = [ctypes.c_int, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                              P, P, P, P, P, P, P, ctypes.c_int32, P, P, P, ctypes.c_int]
+    L.orc_transpose.restype = ctypes.c_int64
+    L.orc_transpose.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P]
+    L.orc_axpby.restype = ctypes.c_int64
+    L.orc_axpby.argtypes = [ctypes.c_int, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P]
     if path == LIB_PATH:
         _lib = L
     return L
@@ -115,3 +120,40 @@ def spgemm(semiring: int, A, B, rows=None, nthreads: int = 1, L=None):
     if L.orc_spgemm(*args, _p(crp), _p(cci), _p(cv), nthreads) != 0:
         raise ValueError("oracle spgemm: bad arguments")
     return Csr(nq, B.ncols, crp, cci[:nnz], cv[:nnz])
+
+
+def transpose(A, L=None):
+    """A^T (t_ji = a_ij), sorted CSR; values keep their dtype."""
+    L = L or lib()
+    val = np.ascontiguousarray(A.val)
+    vs = val.dtype.itemsize
+    trp = np.zeros(A.ncols + 1, np.int64)
+    tci = np.zeros(max(A.nnz, 1), np.int32)
+    tv = np.zeros(max(A.nnz, 1), val.dtype)
+    nnz = L.orc_transpose(A.nrows, A.ncols, vs, _p(A.row_ptr), _p(A.col), _p(val), _p(trp), _p(tci), _p(tv))
+    if nnz < 0:
+        raise ValueError("oracle transpose: bad arguments")
+    return Csr(A.ncols, A.nrows, trp, tci[:nnz].copy(), tv[:nnz].copy())
+
+
+def axpby(semiring: int, alpha, C, beta, X, L=None):
+    """(alpha (x) C) (+) (beta (x) X) entry by entry; X None means empty."""
+    L = L or lib()
+    dt = DTYPE[semiring]
+    if X is None:
+        X = Csr(C.nrows, C.ncols, np.zeros(C.nrows + 1, np.int64), np.zeros(0, np.int32), np.zeros(0, dt))
+    if (C.nrows, C.ncols) != (X.nrows, X.ncols):
+        raise ValueError("shape mismatch")
+    a = np.array([alpha], dt)
+    b = np.array([beta], dt)
+    Cv = np.ascontiguousarray(C.val, dt)
+    Xv = np.ascontiguousarray(X.val, dt)
+    cap = max(C.nnz + X.nnz, 1)
+    drp = np.zeros(C.nrows + 1, np.int64)
+    dci = np.zeros(cap, np.int32)
+    dv = np.zeros(cap, dt)
+    nnz = L.orc_axpby(semiring, C.nrows, _p(a), _p(C.row_ptr), _p(C.col), _p(Cv), _p(b), _p(X.row_ptr),
+                      _p(X.col), _p(Xv), _p(drp), _p(dci), _p(dv))
+    if nnz < 0:
+        raise ValueError("oracle axpby: bad arguments")
+    return Csr(C.nrows, C.ncols, drp, dci[:nnz].copy(), dv[:nnz].copy())

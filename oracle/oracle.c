@@ -21,7 +21,14 @@
  *    present iff some k has both a_ik and b_kj present, and its value is the
  *    semiring sum over those k, taken in ascending k, of a_ik (x) b_kj;
  *  - (min,+) on fp32: (x) is the rounded fp32 sum; (+) is the minimum with
- *    -0 ordered below +0; (+,x) on int64 wraps around (two's complement).
+ *    -0 ordered below +0; (+,x) on int64 wraps around (two's complement);
+ *  - the Boolean semiring (Section 3 lists (or, and)) on 32-bit words: (+)
+ *    is bitwise or, (x) bitwise and, 0 the neutral element, so each bit is
+ *    one Boolean semiring;
+ *  - a transposed operand is the matrix with t_ji = a_ij (Section 3 allows
+ *    either operand transposed; Section 5, "Handling Transposition");
+ *  - C = alpha A B + beta X (Section 3) scales with the semiring's (x) and
+ *    adds with its (+); an entry present in either term is present.
  */
 #include "oracle.h"
 
@@ -37,6 +44,7 @@ int orc_value_size(int semiring) {
     case ORC_PLUS_TIMES_I64: return 8;
     case ORC_MIN_PLUS_F32: return 4;
     case ORC_PLUS_TIMES_F64: return 8;
+    case ORC_OR_AND_U32: return 4;
     default: return 0;
   }
 }
@@ -61,6 +69,11 @@ static void sr_add(int sr, void* dst, const void* x, const void* y) {
     memcpy(&a, x, 4); memcpy(&b, y, 4);
     r = mp_add(a, b);
     memcpy(dst, &r, 4);
+  } else if (sr == ORC_OR_AND_U32) {
+    uint32_t a, b, r;
+    memcpy(&a, x, 4); memcpy(&b, y, 4);
+    r = a | b;
+    memcpy(dst, &r, 4);
   } else {
     double a, b, r;
     memcpy(&a, x, 8); memcpy(&b, y, 8);
@@ -80,6 +93,11 @@ static void sr_mul(int sr, void* dst, const void* x, const void* y) {
     float a, b, r;
     memcpy(&a, x, 4); memcpy(&b, y, 4);
     r = a + b;
+    memcpy(dst, &r, 4);
+  } else if (sr == ORC_OR_AND_U32) {
+    uint32_t a, b, r;
+    memcpy(&a, x, 4); memcpy(&b, y, 4);
+    r = a & b;
     memcpy(dst, &r, 4);
   } else {
     double a, b, r;
@@ -286,4 +304,72 @@ int orc_spgemm(int sr, int32_t nrows, int32_t ninner, int32_t ncols,
     for (int64_t q = 0; q < nout; ++q) crp[q + 1] += crp[q];
   }
   return 0;
+}
+
+/* ---- transposition (Section 3; Section 5, "Handling Transposition") ---- */
+
+int64_t orc_transpose(int32_t nrows, int32_t ncols, int vs,
+                      const int64_t* rp, const int32_t* ci, const void* v,
+                      int64_t* trp, int32_t* tci, void* tv) {
+  if (nrows < 0 || ncols < 0 || vs <= 0) return -1;
+  const int64_t nnz = rp[nrows];
+  for (int64_t e = 0; e < nnz; ++e)
+    if (ci[e] < 0 || ci[e] >= ncols) return -1;
+  /* row j of T holds the entries of column j of A: count them ... */
+  for (int32_t j = 0; j <= ncols; ++j) trp[j] = 0;
+  for (int64_t e = 0; e < nnz; ++e) trp[ci[e] + 1]++;
+  for (int32_t j = 0; j < ncols; ++j) trp[j + 1] += trp[j];
+  /* ... then place a_ij at t_ji, visiting i in ascending order so that each
+   * row of T comes out sorted by its column i */
+  int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * ((size_t)ncols + 1));
+  memcpy(fill, trp, sizeof(int64_t) * ((size_t)ncols + 1));
+  for (int32_t i = 0; i < nrows; ++i) {
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+      int64_t o = fill[ci[e]]++;
+      tci[o] = i;
+      memcpy((char*)tv + (size_t)vs * (size_t)o, (const char*)v + (size_t)vs * (size_t)e, (size_t)vs);
+    }
+  }
+  free(fill);
+  return nnz;
+}
+
+/* ---- C = alpha A B + beta X (Section 3) ---- */
+
+int64_t orc_axpby(int sr, int32_t nrows, const void* alpha,
+                  const int64_t* crp, const int32_t* cci, const void* cv,
+                  const void* beta, const int64_t* xrp, const int32_t* xci, const void* xv,
+                  int64_t* drp, int32_t* dci, void* dv) {
+  const int vs = orc_value_size(sr);
+  if (vs == 0 || nrows < 0) return -1;
+  char t1[8], t2[8];
+  int64_t out = 0;
+  drp[0] = 0;
+  for (int32_t i = 0; i < nrows; ++i) {
+    /* walk the two sorted rows together */
+    int64_t a = crp[i], b = xrp[i];
+    while (a < crp[i + 1] || b < xrp[i + 1]) {
+      const int take_c = a < crp[i + 1] && (b >= xrp[i + 1] || cci[a] <= xci[b]);
+      const int take_x = b < xrp[i + 1] && (a >= crp[i + 1] || xci[b] <= cci[a]);
+      char* d = (char*)dv + (size_t)vs * (size_t)out;
+      if (take_c && take_x) {
+        sr_mul(sr, t1, alpha, (const char*)cv + (size_t)vs * (size_t)a);
+        sr_mul(sr, t2, beta, (const char*)xv + (size_t)vs * (size_t)b);
+        sr_add(sr, d, t1, t2);
+        dci[out] = cci[a];
+        ++a; ++b;
+      } else if (take_c) {
+        sr_mul(sr, d, alpha, (const char*)cv + (size_t)vs * (size_t)a);
+        dci[out] = cci[a];
+        ++a;
+      } else {
+        sr_mul(sr, d, beta, (const char*)xv + (size_t)vs * (size_t)b);
+        dci[out] = xci[b];
+        ++b;
+      }
+      ++out;
+    }
+    drp[i + 1] = out;
+  }
+  return out;
 }

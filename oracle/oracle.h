@@ -13,7 +13,13 @@
  *     add, applied one by one in batch order (Section 4.1);
  *   - the dynamic product's defining result C' = A' B' (Section 5, problem
  *     statement), computed from scratch with row-wise Gustavson and a dense
- *     accumulator (Section 6.1 names Gustavson's algorithm).
+ *     accumulator (Section 6.1 names Gustavson's algorithm);
+ *   - the Boolean (or, and) semiring that Section 3 lists, applied bitwise to
+ *     32-bit words (32 Boolean semirings side by side; values 0/1 give the
+ *     plain Boolean product);
+ *   - transposed operands and C = alpha A B + beta X, the general form of the
+ *     problem in Section 3 (transposition: Section 5, "Handling
+ *     Transposition").
  *
  * Matrices are CSR with each row sorted by column and no duplicate keys.
  * Pins: dense brute force, 2-walk enumeration, scipy, closed forms and
@@ -27,7 +33,7 @@
 extern "C" {
 #endif
 
-enum { ORC_PLUS_TIMES_I64 = 0, ORC_MIN_PLUS_F32 = 1, ORC_PLUS_TIMES_F64 = 2 };
+enum { ORC_PLUS_TIMES_I64 = 0, ORC_MIN_PLUS_F32 = 1, ORC_PLUS_TIMES_F64 = 2, ORC_OR_AND_U32 = 3 };
 enum { ORC_OP_SET = 0, ORC_OP_DELETE = 1, ORC_OP_ADD = 2 };
 
 /* Value size in bytes of a semiring, or 0 for an unknown id. */
@@ -61,6 +67,27 @@ int orc_spgemm(int semiring, int32_t nrows, int32_t ninner, int32_t ncols,
                const int64_t* brp, const int32_t* bci, const void* bv,
                const int32_t* rows, int32_t nq,
                int64_t* crp, int32_t* cci, void* cv, int nthreads);
+
+/* Transpose: T = A^T, t_ji = a_ij, for the sorted CSR A (nrows x ncols) with
+ * values of vs bytes.  T is ncols x nrows: trp[ncols+1], tci / tv with room
+ * for nnz(A) entries, each row sorted by column.  Returns nnz, or -1 on bad
+ * arguments. */
+int64_t orc_transpose(int32_t nrows, int32_t ncols, int vs,
+                      const int64_t* rp, const int32_t* ci, const void* v,
+                      int64_t* trp, int32_t* tci, void* tv);
+
+/* D = (alpha (x) C) (+) (beta (x) X), entry by entry, for C and X of the same
+ * shape (Section 3: C = alpha A B + beta X with the product in place of A B).
+ * D holds an entry wherever C or X does: alpha (x) c where only C has one,
+ * beta (x) x where only X has one, (alpha (x) c) (+) (beta (x) x) where
+ * both do (an absent entry is the neutral element, which (x) maps to itself
+ * and (+) ignores).  alpha and beta point to one value each.  Output:
+ * drp[nrows+1], dci / dv with room for nnz(C) + nnz(X).  Returns nnz(D), or
+ * -1 on bad arguments. */
+int64_t orc_axpby(int semiring, int32_t nrows, const void* alpha,
+                  const int64_t* crp, const int32_t* cci, const void* cv,
+                  const void* beta, const int64_t* xrp, const int32_t* xci, const void* xv,
+                  int64_t* drp, int32_t* dci, void* dv);
 
 #ifdef __cplusplus
 }

@@ -30,9 +30,10 @@ OP_ADD = 2      # a <- a (+) x, insert x if absent (algebraic update, Section 4.
 PLUS_TIMES_I64 = 0
 MIN_PLUS_F32 = 1
 PLUS_TIMES_F64 = 2
+OR_AND_U32 = 3
 
 VALUE_DTYPE = {PLUS_TIMES_I64: np.int64, MIN_PLUS_F32: np.float32,
-               PLUS_TIMES_F64: np.float64}
+               PLUS_TIMES_F64: np.float64, OR_AND_U32: np.uint32}
 
 
 def rng_for(stream: int, index: int = 0) -> np.random.Generator:
@@ -154,14 +155,17 @@ def k_per_row_keys(nrows: int, ncols: int, k: int, rng: np.random.Generator) -> 
 
 def draw_values(semiring: int, count: int, rng: np.random.Generator,
                 lo: int = 1, hi: int = 9) -> np.ndarray:
-    """Values by workload family: uniform integers in [lo, hi] for int64 and
-    min-plus fp32 (stored as float32), N(0, 1) for fp64."""
+    """Values by workload family: uniform integers in [lo, hi] for int64,
+    min-plus fp32 (stored as float32) and 32-bit words (uint32), N(0, 1) for
+    fp64."""
     if semiring == PLUS_TIMES_I64:
         return rng.integers(lo, hi + 1, count, dtype=np.int64)
     if semiring == MIN_PLUS_F32:
         return rng.integers(lo, hi + 1, count, dtype=np.int64).astype(np.float32)
     if semiring == PLUS_TIMES_F64:
         return rng.standard_normal(count)
+    if semiring == OR_AND_U32:
+        return rng.integers(lo, hi + 1, count, dtype=np.uint64).astype(np.uint32)
     raise ValueError(semiring)
 
 

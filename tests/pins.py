@@ -56,6 +56,13 @@ def random_csr(rng, nr, nc, density, sr, lo=1, hi=9, zeros=False):
         vals = rng.standard_normal(ii.size)
     elif sr == I.MIN_PLUS_F32:
         vals = rng.integers(-20, 100, ii.size).astype(np.float32)
+    elif sr == I.OR_AND_U32:
+        # a few low bits plus, now and then, the top bit: zeros, partial
+        # overlaps and full words all occur
+        vals = rng.integers(0, 16, ii.size).astype(np.uint32)
+        vals[rng.random(ii.size) < 0.2] |= np.uint32(1 << 31)
+        if not zeros:
+            vals[vals == 0] = 1
     else:
         vals = rng.integers(-9, 10, ii.size).astype(np.int64)
         if not zeros:
@@ -70,6 +77,8 @@ def random_csr(rng, nr, nc, density, sr, lo=1, hi=9, zeros=False):
 def py_mul(sr, a, b):
     if sr == I.PLUS_TIMES_I64:
         return ((int(a) * int(b)) % U64)
+    if sr == I.OR_AND_U32:
+        return int(a) & int(b)
     if sr == I.MIN_PLUS_F32:
         return np.float32(np.float32(a) + np.float32(b))
     return float(a) * float(b)
@@ -78,6 +87,8 @@ def py_mul(sr, a, b):
 def py_add(sr, a, b):
     if sr == I.PLUS_TIMES_I64:
         return (int(a) + int(b)) % U64
+    if sr == I.OR_AND_U32:
+        return int(a) | int(b)
     if sr == I.MIN_PLUS_F32:
         a, b = np.float32(a), np.float32(b)
         if a != b:
@@ -149,9 +160,12 @@ def dense_bruteforce(sr, A, B):
     return out
 
 
+SEMIRINGS = (I.PLUS_TIMES_I64, I.MIN_PLUS_F32, I.PLUS_TIMES_F64, I.OR_AND_U32)
+
+
 def pin_dense_bruteforce(L, trials=6, seed=7):
     rng = np.random.default_rng(seed)
-    for sr in (I.PLUS_TIMES_I64, I.MIN_PLUS_F32, I.PLUS_TIMES_F64):
+    for sr in SEMIRINGS:
         for t in range(trials):
             nr, nk, nc = rng.integers(1, 14, 3)
             dens = [0.0, 0.15, 0.4, 1.0][t % 4]
@@ -346,10 +360,10 @@ def dict_apply(sr, A, rows, cols, vals, ops):
     return d
 
 
-def pin_apply_vs_dict(L, seed=4, trials=20):
+def pin_apply_vs_dict(L, seed=4, trials=24):
     rng = np.random.default_rng(seed)
     for t in range(trials):
-        sr = [I.PLUS_TIMES_I64, I.MIN_PLUS_F32, I.PLUS_TIMES_F64][t % 3]
+        sr = SEMIRINGS[t % 4]
         nr, nc = int(rng.integers(1, 12)), int(rng.integers(1, 12))
         A = random_csr(rng, nr, nc, 0.3, sr)
         b = int(rng.integers(0, 60))
@@ -367,6 +381,126 @@ def pin_apply_vs_dict(L, seed=4, trials=20):
             assert bool(changed[i]) == (rb != ra), (t, i)
 
 
+def pin_boolean_bit_slices(L, seed=12):
+    """Bitwise (or, and) is 32 Boolean semirings side by side: bit b of c_ij
+    is set iff some k has bit b set in both a_ik and b_kj, and c_ij is present
+    iff some k has both entries present (scipy's integer product of 0/1
+    matrices counts those k)."""
+    rng = np.random.default_rng(seed)
+    sr = I.OR_AND_U32
+    for nr, nk, nc, da, db in ((40, 60, 50, 0.1, 0.1), (30, 20, 45, 0.4, 0.25), (1, 70, 9, 0.5, 0.5)):
+        ka = np.flatnonzero(rng.random(nr * nk) < da).astype(np.int64)
+        kb = np.flatnonzero(rng.random(nk * nc) < db).astype(np.int64)
+        wa = rng.integers(0, 1 << 32, ka.size, dtype=np.uint64).astype(np.uint32)
+        wb = rng.integers(0, 1 << 32, kb.size, dtype=np.uint64).astype(np.uint32)
+        wa[::7] = 0   # present entries whose every bit is clear
+        A = oracle.Csr.of(I.csr_from_keys(nr, nk, ka, wa))
+        B = oracle.Csr.of(I.csr_from_keys(nk, nc, kb, wb))
+        C = oracle.spgemm(sr, A, B, L=L)
+
+        def mat(M, data):
+            return sp.csr_matrix((data, M.col, M.row_ptr), shape=(M.nrows, M.ncols)).toarray()
+        present = (mat(A, np.ones(A.nnz, np.int64)) @ mat(B, np.ones(B.nnz, np.int64))) > 0
+        got = np.zeros((nr, nc), np.uint64)
+        gmask = np.zeros((nr, nc), bool)
+        for i in range(nr):
+            for e in range(C.row_ptr[i], C.row_ptr[i + 1]):
+                got[i, C.col[e]] = C.val[e]
+                gmask[i, C.col[e]] = True
+        assert np.array_equal(gmask, present)
+        for b in range(32):
+            ab = mat(A, ((A.val.astype(np.int64) >> b) & 1))
+            bb = mat(B, ((B.val.astype(np.int64) >> b) & 1))
+            want = (ab @ bb) > 0
+            assert np.array_equal(((got >> np.uint64(b)) & np.uint64(1)).astype(bool), want), b
+
+
+def dense_of(M):
+    """(presence, values) as dense arrays, from the CSR arrays directly."""
+    pres = np.zeros((M.nrows, M.ncols), bool)
+    vals = np.zeros((M.nrows, M.ncols), np.asarray(M.val).dtype)
+    for i in range(M.nrows):
+        for e in range(M.row_ptr[i], M.row_ptr[i + 1]):
+            pres[i, M.col[e]] = True
+            vals[i, M.col[e]] = M.val[e]
+    return pres, vals
+
+
+def pin_transpose(L, seed=13):
+    """t_ji = a_ij (numpy's transpose of the dense form), rows sorted, the
+    transpose of the transpose is the matrix itself, and products with a
+    transposed operand follow the brute-force definition on the swapped keys."""
+    rng = np.random.default_rng(seed)
+    for t in range(8):
+        sr = SEMIRINGS[t % 4]
+        nr, nc = int(rng.integers(1, 30)), int(rng.integers(1, 30))
+        A = random_csr(rng, nr, nc, [0.0, 0.1, 0.5, 1.0][t % 4], sr, zeros=True)
+        T = oracle.transpose(A, L=L)
+        assert (T.nrows, T.ncols, T.nnz) == (nc, nr, A.nnz)
+        pa, va = dense_of(A)
+        pt, vt = dense_of(T)
+        assert np.array_equal(pt, pa.T)
+        assert same_bits(vt[pt], va.T[pa.T])
+        for i in range(T.nrows):
+            r = T.col[T.row_ptr[i]:T.row_ptr[i + 1]]
+            assert np.all(np.diff(r) > 0), (t, i)
+        TT = oracle.transpose(T, L=L)
+        assert np.array_equal(TT.row_ptr, A.row_ptr) and np.array_equal(TT.col, A.col)
+        assert same_bits(TT.val, A.val)
+        # A^T B and A B^T against the definition
+        nk = int(rng.integers(1, 12))
+        B = random_csr(rng, nr, nk, 0.3, sr, zeros=True)    # A^T B: (nc x nr)(nr x nk)
+        B2 = random_csr(rng, nk, nc, 0.3, sr, zeros=True)   # A B2^T: (nr x nc)(nc x nk)
+
+        def swapped(M):
+            return csr_from_entries((M.ncols, M.nrows), [(j, i, v) for (i, j), v in entries_of(M).items()],
+                                    oracle.DTYPE[sr])
+        for X, Y, XY in ((oracle.transpose(A, L=L), B, (swapped(A), B)),
+                         (A, oracle.transpose(B2, L=L), (A, swapped(B2)))):
+            got = entries_of(oracle.spgemm(sr, X, Y, L=L))
+            want = dense_bruteforce(sr, *XY)
+            assert set(got) == set(want), t
+            for k in want:
+                assert same_bits(got[k], want[k]), (t, k)
+
+
+def pin_axpby(L, seed=14):
+    """Entry by entry against plain Python semiring arithmetic, on the union of
+    the two structures; special cases: beta applied to an empty X leaves
+    alpha (x) C, and with the (x)-identity for alpha and beta the result is
+    C (+) X."""
+    rng = np.random.default_rng(seed)
+    one = {I.PLUS_TIMES_I64: 1, I.MIN_PLUS_F32: 0.0, I.PLUS_TIMES_F64: 1.0, I.OR_AND_U32: 0xffffffff}
+    for t in range(12):
+        sr = SEMIRINGS[t % 4]
+        dt = oracle.DTYPE[sr]
+        nr, nc = int(rng.integers(1, 20)), int(rng.integers(1, 20))
+        C = random_csr(rng, nr, nc, [0.0, 0.2, 0.6][t % 3], sr, zeros=True)
+        X = random_csr(rng, nr, nc, [0.3, 0.0, 0.6][t % 3], sr, zeros=True)
+        a = random_csr(rng, 1, 1, 1.0, sr).val[0]
+        b = random_csr(rng, 1, 1, 1.0, sr).val[0]
+        ec, ex = entries_of(C), entries_of(X)
+        got = entries_of(oracle.axpby(sr, a, C, b, X, L=L))
+        assert set(got) == set(ec) | set(ex), t
+        for k in got:
+            if k in ec and k in ex:
+                w = py_add(sr, py_mul(sr, a, ec[k]), py_mul(sr, b, ex[k]))
+            elif k in ec:
+                w = py_mul(sr, a, ec[k])
+            else:
+                w = py_mul(sr, b, ex[k])
+            assert same_bits(got[k], as_stored(sr, w)), (t, k)
+        alone = entries_of(oracle.axpby(sr, a, C, b, None, L=L))
+        assert set(alone) == set(ec)
+        for k in ec:
+            assert same_bits(alone[k], as_stored(sr, py_mul(sr, a, ec[k]))), (t, k)
+        plain = entries_of(oracle.axpby(sr, dt(one[sr]), C, dt(one[sr]), X, L=L))
+        for k in plain:
+            w = py_add(sr, ec[k], ex[k]) if (k in ec and k in ex) else (ec[k] if k in ec else ex[k])
+            assert same_bits(plain[k], as_stored(sr, w)), (t, k)
+
+
 ALL_PINS = [pin_golden_products, pin_golden_apply, pin_dense_bruteforce, pin_minplus_two_walks,
             pin_scipy_int64, pin_numpy_fp64, pin_stencil_small_boundary, pin_identity_and_relabel,
-            pin_apply_vs_dict, pin_int64_invariants, pin_minplus_invariants]
+            pin_apply_vs_dict, pin_int64_invariants, pin_minplus_invariants, pin_boolean_bit_slices,
+            pin_transpose, pin_axpby]

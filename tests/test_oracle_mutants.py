@@ -33,6 +33,20 @@ MUTANTS = [
     ("add_overwrites", "if (bop[t] == ORC_OP_SET) memcpy(", "if (1) memcpy(", 0),
     ("batch_order_reversed", "int64_t t = order[u];", "int64_t t = order[first[i] + first[i + 1] - 1 - u];", 0),
     ("changed_means_length_change", "changed[i] = (uint8_t)diff;", "changed[i] = (uint8_t)(len != len0);", 0),
+    ("bool_or_becomes_xor", "r = a | b;", "r = a ^ b;", 0),
+    ("bool_and_becomes_or", "r = a & b;", "r = a | b;", 0),
+    ("bool_words_truncated", "case ORC_OR_AND_U32: return 4;", "case ORC_OR_AND_U32: return 2;", 0),
+    ("transpose_keeps_column", "tci[o] = i;", "tci[o] = ci[e];", 0),
+    ("transpose_rows_reversed", "for (int32_t i = 0; i < nrows; ++i) {\n    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {\n      int64_t o",
+     "for (int32_t i = nrows - 1; i >= 0; --i) {\n    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {\n      int64_t o", 0),
+    ("transpose_value_shifted", "(const char*)v + (size_t)vs * (size_t)e, (size_t)vs);",
+     "(const char*)v + (size_t)vs * (size_t)(e > 0 ? e - 1 : 0), (size_t)vs);", 0),
+    ("axpby_beta_ignored", "sr_mul(sr, t2, beta, (const char*)xv + (size_t)vs * (size_t)b);",
+     "memcpy(t2, (const char*)xv + (size_t)vs * (size_t)b, (size_t)vs);", 0),
+    ("axpby_overlap_keeps_c", "sr_add(sr, d, t1, t2);", "memcpy(d, t1, (size_t)vs);", 0),
+    ("axpby_x_only_scaled_by_alpha", "sr_mul(sr, d, beta,", "sr_mul(sr, d, alpha,", 0),
+    ("axpby_x_only_dropped", "        dci[out] = xci[b];\n        ++b;\n      }\n      ++out;",
+     "        dci[out] = xci[b];\n        ++b;\n        continue;\n      }\n      ++out;", 0),
 ]
 
 
