@@ -58,11 +58,16 @@ typedef enum {
  *   DSG_PLUS_TIMES_I64: (+, x) over int64, two's-complement wrap-around;
  *   DSG_MIN_PLUS_F32:   (min, +) over fp32, +inf neutral, -0 ordered below +0;
  *   DSG_PLUS_TIMES_F64: (+, x) over fp64, each product and sum rounded once
- *                       (no fused multiply-add). */
+ *                       (no fused multiply-add);
+ *   DSG_OR_AND_U32:     the Boolean (or, and) semiring applied bitwise to
+ *                       uint32 words: 32 Boolean semirings side by side, 0
+ *                       neutral; values 0 and 1 give the plain Boolean
+ *                       product. */
 typedef enum {
   DSG_PLUS_TIMES_I64 = 0,
   DSG_MIN_PLUS_F32 = 1,
-  DSG_PLUS_TIMES_F64 = 2
+  DSG_PLUS_TIMES_F64 = 2,
+  DSG_OR_AND_U32 = 3
 } dsg_semiring;
 
 /* Update operations (Section 4.1). */
@@ -181,8 +186,26 @@ dsg_status dsg_mat_destroy(dsg_mat* m);
 
 /* Create the product C = A B (B may be A) and compute it from scratch with
  * the row kernels.  DSG_E_STATE on semiring mismatch or ncols(A) != nrows(B).
- * The product keeps a structure-only transpose index of A current. */
+ * The matrix keeps a transpose index (valued) of A current: every apply of A
+ * updates it, and updates use it to find the rows of A that reach a changed
+ * row of B.  Same as dsg_prod_create with ops = 0. */
 dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod** out);
+
+/* Operand forms (Section 3: either operand of SpGEMM may be transposed;
+ * Section 5, "Handling Transposition"). */
+#define DSG_TRANS_A 0x1u  /* the product reads A^T in place of A */
+#define DSG_TRANS_B 0x2u  /* the product reads B^T in place of B */
+
+/* Create C = op(A) op(B), op(X) = X^T when ops holds X's flag, and compute
+ * it from scratch.  A transposed operand is read from its transpose index,
+ * which every apply of the matrix keeps current (the index is built here if
+ * the matrix has none), so updates are applied to A and B as usual and
+ * dsg_prod_update recomputes the rows that op(A)'s changed rows and op(B)'s
+ * changed rows reach.  Products with a transposed operand always take the
+ * row path (never the entry-granular one).  Errors: DSG_E_ARG (unknown flag),
+ * DSG_E_STATE (semiring mismatch, inner dimensions of op(A) and op(B)
+ * differ). */
+dsg_status dsg_prod_create(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, uint32_t ops, dsg_prod** out);
 
 /* Recompute every row of C from the current A and B (the static baseline),
  * consuming the pending changes.  flags: DSG_SYNC. */

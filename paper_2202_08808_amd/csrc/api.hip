@@ -119,7 +119,7 @@ static dsg_status fail(dsg_ctx* ctx, dsg_status code, const std::string& msg) {
   }                                                               \
   return DSG_OK;
 
-static int value_size(int sr) { return sr == DSG_MIN_PLUS_F32 ? 4 : 8; }
+static int value_size(int sr) { return sr == DSG_MIN_PLUS_F32 || sr == DSG_OR_AND_U32 ? 4 : 8; }
 
 static void set_device(dsg_ctx* ctx) { DSG_HIP(hipSetDevice(ctx->c.device)); }
 
@@ -347,7 +347,7 @@ extern "C" dsg_status dsg_mat_create(dsg_ctx* ctx, int32_t nrows, int32_t ncols,
   if (!out) return fail(ctx, DSG_E_ARG, "out is NULL");
   *out = nullptr;
   if (nrows < 0 || ncols < 0) return fail(ctx, DSG_E_ARG, "negative shape");
-  if (sr < DSG_PLUS_TIMES_I64 || sr > DSG_PLUS_TIMES_F64) return fail(ctx, DSG_E_ARG, "unknown semiring");
+  if (sr < DSG_PLUS_TIMES_I64 || sr > DSG_OR_AND_U32) return fail(ctx, DSG_E_ARG, "unknown semiring");
   if (flags & ~(uint32_t)(DSG_INPUT_DEVICE | DSG_SYNC)) return fail(ctx, DSG_E_ARG, "unknown flag");
   API_BEGIN(ctx)
   set_device(ctx);
@@ -515,18 +515,25 @@ static void fill_rows(DProd* p, const int32_t* rows, int32_t n, dsg_rows* out) {
   out->val = p->C->val;
 }
 
-extern "C" dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod** out) {
+extern "C" dsg_status dsg_prod_create(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, uint32_t ops, dsg_prod** out) {
   if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
   if (!out || !A || !B || !A->alive || !B->alive) return fail(ctx, DSG_E_ARG, "NULL or destroyed argument");
   *out = nullptr;
+  if (ops & ~(uint32_t)(DSG_TRANS_A | DSG_TRANS_B)) return fail(ctx, DSG_E_ARG, "unknown operand flag");
   if (A->owner != ctx || B->owner != ctx) return fail(ctx, DSG_E_STATE, "operands belong to another context");
   if (A->m->sr != B->m->sr) return fail(ctx, DSG_E_STATE, "semiring mismatch");
-  if (A->m->ncols != B->m->nrows) return fail(ctx, DSG_E_STATE, "shape mismatch: ncols(A) != nrows(B)");
+  const int32_t inner_a = (ops & DSG_TRANS_A) ? A->m->nrows : A->m->ncols;
+  const int32_t inner_b = (ops & DSG_TRANS_B) ? B->m->ncols : B->m->nrows;
+  if (inner_a != inner_b) return fail(ctx, DSG_E_STATE, "shape mismatch: inner dimensions of op(A) and op(B) differ");
   API_BEGIN(ctx)
   set_device(ctx);
-  DProd* p = prod_create(&ctx->c, A->m, B->m);
+  DProd* p = prod_create(&ctx->c, A->m, B->m, ops);
   *out = new dsg_prod{p, ctx, A, B};
   API_END
+}
+
+extern "C" dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod** out) {
+  return dsg_prod_create(ctx, A, B, 0, out);
 }
 
 extern "C" dsg_status dsg_prod_recompute_static(dsg_prod* ph, uint32_t flags) {
@@ -746,8 +753,8 @@ extern "C" dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int
   std::vector<DMat*> seen;
   for (int32_t i = 0; i < nprod; ++i) {
     if (!prods[i] || prods[i]->owner != ctx) return fail(ctx, DSG_E_STATE, "product of another context");
-    for (DMat* m : {prods[i]->p->A, prods[i]->p->B}) {
-      if (std::find(seen.begin(), seen.end(), m) != seen.end() && !(m == prods[i]->p->B && m == prods[i]->p->A))
+    for (DMat* m : {prods[i]->p->src_a, prods[i]->p->src_b}) {
+      if (std::find(seen.begin(), seen.end(), m) != seen.end() && !(m == prods[i]->p->src_b && m == prods[i]->p->src_a))
         return fail(ctx, DSG_E_STATE, "products of a batch must not share operands");
       seen.push_back(m);
     }

@@ -15,6 +15,7 @@
 // room has grown by exactly what they asked for.  The graph is captured on the first run and
 // replayed while every pointer and size it baked in is unchanged.
 #include <algorithm>
+#include <array>
 #include <chrono>
 
 #include "internal.h"
@@ -46,7 +47,6 @@ __global__ void k_zero_ints(int* p, int n) {
 struct DBatch {
   Ctx* c = nullptr;
   std::vector<DProd*> prods;
-  std::vector<DMat*> mats;          // every matrix the graph may touch (operands, indexes, products)
   hipGraphExec_t exec = nullptr;
   std::vector<uintptr_t> signature; // what the captured graph baked in
   // workspaces: per set (apply, transpose index) and per product
@@ -55,6 +55,7 @@ struct DBatch {
   std::vector<void*> pw;
   std::vector<size_t> pw_bytes;
   int64_t* d_out = nullptr;
+  size_t ntop = 0;                  // room of the two tables below: 5 matrices per product (prod_matrices)
   int64_t* d_tops = nullptr;
   int64_t** d_top_ptrs = nullptr;
   int* d_valid = nullptr;
@@ -67,6 +68,12 @@ struct DBatch {
   int64_t captures = 0, replays = 0, deferred = 0, direct = 0;
   double prepare_ms = 0, capture_ms = 0, replay_ms = 0, finish_ms = 0, direct_ms = 0;
 };
+
+// Every matrix a product's update chain may touch: the caller's operands
+// and their transposes (an apply writes both), and C.
+static std::array<DMat*, 5> prod_matrices(const DProd* p) {
+  return {p->src_a, p->src_a->tidx, p->src_b, p->src_b->tidx, p->C};
+}
 
 static double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -90,14 +97,11 @@ DBatch* batch_create(Ctx* c, const std::vector<DProd*>& prods) {
   b->prods = prods;
   for (DProd* p : prods) p->refs++;  // released by batch_destroy
   try {
-    for (DProd* p : prods) {
-      for (DMat* m : {p->A, p->B, p->A->tidx, p->C})
-        if (m && std::find(b->mats.begin(), b->mats.end(), m) == b->mats.end()) b->mats.push_back(m);
-    }
     const size_t np = prods.size() ? prods.size() : 1;
     b->d_out = (int64_t*)ctx_alloc(c, np * OUT_WORDS * 8);
-    b->d_tops = (int64_t*)ctx_alloc(c, b->mats.size() * 8 + 8);
-    b->d_top_ptrs = (int64_t**)ctx_alloc(c, b->mats.size() * 8 + 8);
+    b->ntop = 5 * np + 1;
+    b->d_tops = (int64_t*)ctx_alloc(c, b->ntop * 8);
+    b->d_top_ptrs = (int64_t**)ctx_alloc(c, b->ntop * 8);
     b->d_valid = (int*)ctx_alloc(c, 4 * (np * 2 + 1));
     const int nstreams = (int)std::min<size_t>(prods.size(), 8);
     for (int i = 0; i < nstreams; ++i) {
@@ -127,8 +131,8 @@ void batch_destroy(DBatch* b) {
   free_ws(c, b->pw, b->pw_bytes);
   const size_t np = b->prods.size() ? b->prods.size() : 1;
   ctx_free(c, b->d_out, np * OUT_WORDS * 8);
-  ctx_free(c, b->d_tops, b->mats.size() * 8 + 8);
-  ctx_free(c, b->d_top_ptrs, b->mats.size() * 8 + 8);
+  ctx_free(c, b->d_tops, b->ntop * 8);
+  ctx_free(c, b->d_top_ptrs, b->ntop * 8);
   ctx_free(c, b->d_valid, 4 * (np * 2 + 1));
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   if (b->replay_stream) {
@@ -182,7 +186,7 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   std::vector<int> owner(sets.size(), -1);
   for (size_t k = 0; k < sets.size(); ++k) {
     for (size_t j = 0; j < np; ++j)
-      if (sets[k].m == b->prods[j]->A || sets[k].m == b->prods[j]->B) owner[k] = (int)j;
+      if (sets[k].m == b->prods[j]->src_a || sets[k].m == b->prods[j]->src_b) owner[k] = (int)j;
     if (owner[k] < 0) throw DsgError{DSG_E_ARG, "update set names a matrix outside the batch"};
     for (size_t k2 = 0; k2 < k; ++k2)
       if (sets[k2].m == sets[k].m) throw DsgError{DSG_E_ARG, "two update sets name the same matrix"};
@@ -209,7 +213,7 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     graphed[j] = p->C->h_top_ub < (int64_t(1) << c->tuning.batch_direct_log2) ? 1 : 0;
     if (!graphed[j]) continue;
     ++ng;
-    for (DMat* m : {p->A, p->B, p->A->tidx, p->C})
+    for (DMat* m : prod_matrices(p))
       if (m && std::find(gmats.begin(), gmats.end(), m) == gmats.end()) gmats.push_back(m);
   }
   // ---- room for the graph: worst case for operands, last need plus margin for C ----
@@ -248,8 +252,11 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   for (size_t k = 0; k < sets.size(); ++k) {
     if (!graphed[(size_t)owner[k]]) continue;
     const DBatchSet& st = sets[k];
-    for (uintptr_t x : {(uintptr_t)st.m, (uintptr_t)st.rows, (uintptr_t)st.cols, (uintptr_t)st.vals,
-                        (uintptr_t)st.ops, (uintptr_t)st.n, (uintptr_t)b->aw[k], (uintptr_t)b->awt[k]})
+    // (the transpose too: one built later, for another product, must be
+    // updated by this set's apply as well)
+    for (uintptr_t x : {(uintptr_t)st.m, (uintptr_t)st.m->tidx, (uintptr_t)st.rows, (uintptr_t)st.cols,
+                        (uintptr_t)st.vals, (uintptr_t)st.ops, (uintptr_t)st.n, (uintptr_t)b->aw[k],
+                        (uintptr_t)b->awt[k]})
       sig.push_back(x);
   }
   for (DMat* m : gmats)
@@ -274,6 +281,7 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     // of each touched matrix's top)
     std::vector<int64_t*> top_ptrs;
     for (DMat* m : gmats) top_ptrs.push_back(m->d_top);
+    DSG_REQUIRE(top_ptrs.size() <= b->ntop, DSG_E_DEVICE, "internal: pool-top table too small");
     DSG_HIP(hipMemcpyAsync(b->d_top_ptrs, top_ptrs.data(), top_ptrs.size() * 8, hipMemcpyHostToDevice, main));
     DSG_HIP(hipStreamSynchronize(main));
     hipGraph_t graph = nullptr;
@@ -371,8 +379,8 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     } else {
       counts[j] = (int32_t)o[0];
     }
-    p->a_seq = p->A->apply_seq;
-    p->b_seq = p->B->apply_seq;
+    p->a_seq = p->src_a->apply_seq;
+    p->b_seq = p->src_b->apply_seq;
   }
   b->finish_ms += ms_since(t0);
   return DSG_OK;

@@ -665,7 +665,7 @@ int64_t read_count(Ctx* c, const int64_t* d) {
 
 bool eligible(const DProd* p) {
   const DMat* A = p->A;
-  if (p->B != A || (A->sr != 0 && A->sr != 1)) return false;
+  if (p->ops || p->B != A || (A->sr != 0 && A->sr != 1)) return false;
   if (p->ctx->tuning.update_path == 1) return false;
   if (!A->tidx || A->tidx->vsz != A->vsz) return false;
   return A->log_seq != 0 && A->log_seq == A->apply_seq && A->apply_seq == p->a_seq + 1;

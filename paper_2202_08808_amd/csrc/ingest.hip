@@ -896,6 +896,7 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
     case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
     case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
     case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
+    case 3: launch_plan_commit<3, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
     default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
   }
   DSG_HIP(hipGetLastError());

@@ -249,9 +249,15 @@ dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* 
 
 struct DProd {
   Ctx* ctx = nullptr;
+  // The operands as the kernels read them: the caller's matrices, or their
+  // valued transposes when the product takes an operand transposed.
   DMat* A = nullptr;
   DMat* B = nullptr;
   DMat* C = nullptr;
+  DMat* src_a = nullptr;  // the caller's matrices: referenced, and the ones updates are applied to
+  DMat* src_b = nullptr;
+  DMat* lt = nullptr;     // transpose of the left operand (rows of A per column), for discovery
+  uint32_t ops = 0;       // DSG_TRANS_A / DSG_TRANS_B
   uint32_t* d_sync = nullptr;      // device [2]: epochs of A and B that C reflects
   int32_t* changed_rows = nullptr;  // device list of the last update's reported rows
   int64_t changed_cap = 0;
@@ -279,7 +285,8 @@ struct DProd {
   int refs = 0;                   // batched executors and servers using this product
 };
 
-DProd* prod_create(Ctx* c, DMat* A, DMat* B);
+// C = op(A) op(B), op(X) = X^T under DSG_TRANS_A / DSG_TRANS_B in ops.
+DProd* prod_create(Ctx* c, DMat* A, DMat* B, uint32_t ops = 0);
 void prod_destroy(DProd* p);
 // mode 0: dynamic update; 1: recompute every row (static); with report_affected.
 int32_t prod_run(DProd* p, int mode, bool report_affected);

@@ -72,6 +72,19 @@ struct Sem<2> {  // (+, x) over fp64, one rounding per operation
   __device__ static V add(V a, V b) { return __dadd_rn(a, b); }
 };
 
+template <>
+struct Sem<3> {  // (or, and) on 32-bit words: each bit is one Boolean semiring
+  using V = uint32_t;
+  using Acc = uint32_t;
+  static constexpr bool order_free = true;
+  __device__ static Acc identity() { return 0u; }
+  __device__ static Acc mul(V a, V b) { return a & b; }
+  __device__ static Acc to_acc(V v) { return v; }
+  __device__ static V from_acc(Acc a) { return a; }
+  __device__ static void atomic_combine(Acc* p, Acc x) { atomicOr(p, x); }
+  __device__ static V add(V a, V b) { return a | b; }
+};
+
 template <class T>
 __device__ inline bool same_bits(T a, T b) {
   static_assert(sizeof(T) == 4 || sizeof(T) == 8, "value size");

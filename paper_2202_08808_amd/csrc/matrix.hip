@@ -164,7 +164,7 @@ DMat* mat_create(Ctx* c, int32_t nrows, int32_t ncols, int sr, const int64_t* d_
   m->nrows = nrows;
   m->ncols = ncols;
   m->sr = sr;
-  m->vsz = sr < 0 ? 0 : (sr == 1 ? 4 : 8);
+  m->vsz = sr < 0 ? 0 : (sr == 1 || sr == 3 ? 4 : 8);
   hipStream_t s = c->stream;
   try {
     size_t n = (size_t)(nrows > 0 ? nrows : 1);

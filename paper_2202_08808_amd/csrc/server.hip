@@ -475,7 +475,7 @@ void server_destroy(DServer* s) {
 
 uint64_t server_submit_update(DServer* s, DMat* m, const int32_t* rows, const int32_t* cols, const void* vals,
                               const uint8_t* ops, int64_t n) {
-  DSG_REQUIRE(m == s->p->A || m == s->p->B, DSG_E_ARG, "matrix is not an operand of the served product");
+  DSG_REQUIRE(m == s->p->src_a || m == s->p->src_b, DSG_E_ARG, "matrix is not an operand of the served product");
   check_entries(m, rows, cols, ops, n);
   SReq* r = new SReq();
   r->kind = 0;

@@ -1980,7 +1980,7 @@ void launch_front(DProd* p, int mode, ProdWork& w, const RowArgs& R) {
       hipLaunchKernelGGL(k_mark_changed, dim3(blocks_for(B->nrows, 256)), dim3(256), 0, s, B->nrows, B->row_epoch,
                          (const uint32_t*)p->d_sync + 1, w.b_flags);
       compact_flags(w.b_flags, B->nrows, w.dB, w.d_nB, w.cscr, s);
-      DMat* T = A->tidx;
+      DMat* T = p->lt;
       unsigned nbk = (unsigned)std::min<int64_t>(blocks_for((int64_t)B->nrows * 64, 256), 8192);
       hipLaunchKernelGGL(k_scatter_dB, dim3(nbk), dim3(256), 0, s, w.dB, w.d_nB, T->row_off, T->row_len, T->col,
                          w.aff_flags);
@@ -2011,7 +2011,8 @@ void launch_rows(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
   switch (p->A->sr) {
     case 0: launch_bins<0>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
     case 1: launch_bins<1>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
-    default: launch_bins<2>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
+    case 2: launch_bins<2>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
+    default: launch_bins<3>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
   }
 }
 
@@ -2183,14 +2184,21 @@ int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, con
 
 }  // namespace
 
-DProd* prod_create(Ctx* c, DMat* A, DMat* B) {
+DProd* prod_create(Ctx* c, DMat* A, DMat* B, uint32_t ops) {
   DProd* p = new DProd();
   p->ctx = c;
-  p->A = A;
-  p->B = B;
+  p->src_a = A;
+  p->src_b = B;
+  p->ops = ops;
   try {
+    // A's transpose serves either as the left operand (A^T) or as the
+    // column index of the left operand (A); every apply of A keeps it current
     mat_build_transpose(A);
-    p->C = mat_create(c, A->nrows, B->ncols, A->sr, nullptr, nullptr, nullptr);
+    if (ops & DSG_TRANS_B) mat_build_transpose(B);
+    p->A = (ops & DSG_TRANS_A) ? A->tidx : A;
+    p->lt = (ops & DSG_TRANS_A) ? A : A->tidx;
+    p->B = (ops & DSG_TRANS_B) ? B->tidx : B;
+    p->C = mat_create(c, p->A->nrows, p->B->ncols, A->sr, nullptr, nullptr, nullptr);
     p->d_sync = (uint32_t*)ctx_alloc(c, 16);
   } catch (...) {
     if (p->C) mat_destroy(p->C);
@@ -2222,8 +2230,8 @@ void prod_destroy(DProd* p) {
   if (p->srt) ctx_free(c, p->srt, p->srt_bytes);
   if (p->bsp) ctx_free(c, p->bsp, p->bsp_bytes);
   if (p->C) mat_destroy(p->C);
-  if (p->A) p->A->refs--;
-  if (p->B) p->B->refs--;
+  if (p->src_a) p->src_a->refs--;
+  if (p->src_b) p->src_b->refs--;
   delete p;
 }
 
@@ -2239,8 +2247,8 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
       DSG_HIP(hipStreamSynchronize(p->ctx->stream));
       p->entry_nterm = *h;
       nchg = entry_finish(p);
-      p->a_seq = p->A->apply_seq;
-      p->b_seq = p->B->apply_seq;
+      p->a_seq = p->src_a->apply_seq;
+      p->b_seq = p->src_b->apply_seq;
       return nchg;
     }
   }
@@ -2251,8 +2259,8 @@ int32_t prod_run(DProd* p, int mode, bool report_affected) {
   ProdWork w = carve_prod(ctx_scratch(p->ctx, need), N, nB);
   nchg = prod_sequence(p, mode, report_affected, w, d_nterm);
   if (nchg == ENTRY_INSTEAD) nchg = entry_finish(p);
-  p->a_seq = p->A->apply_seq;
-  p->b_seq = p->B->apply_seq;
+  p->a_seq = p->src_a->apply_seq;
+  p->b_seq = p->src_b->apply_seq;
   return nchg;
 }
 

@@ -18,10 +18,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdsg.so")
 
 OK, E_ARG, E_RANGE, E_OOM, E_DEVICE, E_STATE, E_UNSUPPORTED = range(7)
-PLUS_TIMES_I64, MIN_PLUS_F32, PLUS_TIMES_F64 = 0, 1, 2
+PLUS_TIMES_I64, MIN_PLUS_F32, PLUS_TIMES_F64, OR_AND_U32 = 0, 1, 2, 3
 OP_SET, OP_DELETE, OP_ADD = 0, 1, 2
 INPUT_DEVICE, SYNC, REPORT_AFFECTED = 0x1, 0x2, 0x4
-DTYPE = {PLUS_TIMES_I64: np.int64, MIN_PLUS_F32: np.float32, PLUS_TIMES_F64: np.float64}
+TRANS_A, TRANS_B = 0x1, 0x2
+DTYPE = {PLUS_TIMES_I64: np.int64, MIN_PLUS_F32: np.float32, PLUS_TIMES_F64: np.float64,
+         OR_AND_U32: np.uint32}
 NAMES = {OK: "DSG_OK", E_ARG: "DSG_E_ARG", E_RANGE: "DSG_E_RANGE", E_OOM: "DSG_E_OOM",
          E_DEVICE: "DSG_E_DEVICE", E_STATE: "DSG_E_STATE", E_UNSUPPORTED: "DSG_E_UNSUPPORTED"}
 
@@ -106,6 +108,7 @@ SIGNATURES = {
     "dsg_mat_export": [P, P, P, P, ctypes.c_int64, P],
     "dsg_mat_destroy": [P],
     "dsg_prod_create_static": [P, P, P, P],
+    "dsg_prod_create": [P, P, P, ctypes.c_uint32, P],
     "dsg_prod_recompute_static": [P, ctypes.c_uint32],
     "dsg_prod_update": [P, ctypes.c_uint32, P],
     "dsg_prod_rows": [P, P, ctypes.c_int32, ctypes.c_uint32, P],
@@ -352,13 +355,18 @@ def _hip():
 
 
 class Product:
-    def __init__(self, ctx: Context, A: Matrix, B: Matrix):
+    """C = op(A) op(B), op(X) = X^T when trans_a / trans_b is set."""
+
+    def __init__(self, ctx: Context, A: Matrix, B: Matrix, trans_a: bool = False, trans_b: bool = False):
         self.ctx, self.L = ctx, ctx.L
         self.A, self.B = A, B
+        self.trans_a, self.trans_b = bool(trans_a), bool(trans_b)
         self.semiring = A.semiring
-        self.nrows, self.ncols = A.nrows, B.ncols
+        self.nrows = A.ncols if trans_a else A.nrows
+        self.ncols = B.nrows if trans_b else B.ncols
         h = P()
-        ctx._check(self.L.dsg_prod_create_static(ctx.h, A.h, B.h, ctypes.byref(h)))
+        ops = (TRANS_A if trans_a else 0) | (TRANS_B if trans_b else 0)
+        ctx._check(self.L.dsg_prod_create(ctx.h, A.h, B.h, ops, ctypes.byref(h)))
         self.h = h
 
     def update(self, report_affected: bool = False) -> RowSet:
@@ -395,7 +403,7 @@ class Product:
         library).  With cache_path, results are stored in a JSON file keyed by
         (device arch, semiring, shape, nnz(A) and nnz(C) to two significant
         digits) and reused without trials."""
-        key = json.dumps([_arch(), self.semiring, self.nrows, self.ncols,
+        key = json.dumps([_arch(), self.semiring, self.trans_a, self.trans_b, self.nrows, self.ncols,
                           float(f"{self.A.nnz():.2g}"), float(f"{self.nnz():.2g}")])
         cache = {}
         if cache_path and os.path.exists(cache_path):

@@ -16,8 +16,8 @@ from paper_2202_08808_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-SRS = [I.PLUS_TIMES_I64, I.MIN_PLUS_F32, I.PLUS_TIMES_F64]
-SR_ID = {I.PLUS_TIMES_I64: "i64", I.MIN_PLUS_F32: "minplus", I.PLUS_TIMES_F64: "f64"}
+SRS = [I.PLUS_TIMES_I64, I.MIN_PLUS_F32, I.PLUS_TIMES_F64, I.OR_AND_U32]
+SR_ID = {I.PLUS_TIMES_I64: "i64", I.MIN_PLUS_F32: "minplus", I.PLUS_TIMES_F64: "f64", I.OR_AND_U32: "orand"}
 
 
 def say(msg):
@@ -51,8 +51,12 @@ def rand_csr(rng, nr, nc, density, sr, row_skew=False):
         cols.append(c)
     r = np.concatenate(rows) if rows else np.zeros(0, np.int64)
     c = np.concatenate(cols) if cols else np.zeros(0, np.int64)
-    vals = I.draw_values(sr, r.size, rng, 1, 9) if sr != I.MIN_PLUS_F32 else \
-        rng.integers(-5, 100, r.size).astype(np.float32)
+    if sr == I.MIN_PLUS_F32:
+        vals = rng.integers(-5, 100, r.size).astype(np.float32)
+    elif sr == I.OR_AND_U32:
+        vals = I.draw_values(sr, r.size, rng, 0, (1 << 32) - 1)   # full 32-bit words
+    else:
+        vals = I.draw_values(sr, r.size, rng, 1, 9)
     return I.csr_from_keys(nr, nc, r * nc + c, vals)
 
 
