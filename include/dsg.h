@@ -207,6 +207,19 @@ dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod
  * differ). */
 dsg_status dsg_prod_create(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, uint32_t ops, dsg_prod** out);
 
+/* A new matrix D = (alpha (x) C) (+) (beta (x) X), the general SpGEMM result
+ * alpha op(A) op(B) + beta X of Section 3, from the product's C as of its
+ * last update or recompute.  D holds an entry wherever C or X holds one:
+ * alpha (x) c where only C has it, beta (x) x where only X has it, and
+ * (alpha (x) c) (+) (beta (x) x) where both do (each operation rounded
+ * once).  alpha and beta are host pointers to one value of the semiring's
+ * type; X is a matrix of C's shape and semiring, or NULL (then D =
+ * alpha (x) C and beta may be NULL).  D is a plain matrix owned by the caller
+ * (dsg_mat_destroy): later updates of the product do not change it.  Errors:
+ * DSG_E_ARG (NULL product, alpha or out; destroyed X), DSG_E_STATE (X of
+ * another context, semiring or shape). */
+dsg_status dsg_prod_scale_add(dsg_prod* p, const void* alpha, dsg_mat* X, const void* beta, dsg_mat** out);
+
 /* Recompute every row of C from the current A and B (the static baseline),
  * consuming the pending changes.  flags: DSG_SYNC. */
 dsg_status dsg_prod_recompute_static(dsg_prod* p, uint32_t flags);

@@ -536,6 +536,26 @@ extern "C" dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* 
   return dsg_prod_create(ctx, A, B, 0, out);
 }
 
+extern "C" dsg_status dsg_prod_scale_add(dsg_prod* ph, const void* alpha, dsg_mat* X, const void* beta,
+                                         dsg_mat** out) {
+  if (!ph) return fail(nullptr, DSG_E_ARG, "product is NULL");
+  dsg_ctx* ctx = ph->owner;
+  if (!out || !alpha || (X && !beta)) return fail(ctx, DSG_E_ARG, "NULL argument");
+  *out = nullptr;
+  const DMat* C = ph->p->C;
+  if (X) {
+    if (!X->alive) return fail(ctx, DSG_E_ARG, "X is destroyed");
+    if (X->owner != ctx) return fail(ctx, DSG_E_STATE, "X belongs to another context");
+    if (X->m->sr != C->sr) return fail(ctx, DSG_E_STATE, "semiring mismatch");
+    if (X->m->nrows != C->nrows || X->m->ncols != C->ncols) return fail(ctx, DSG_E_STATE, "shape of X differs from C");
+  }
+  API_BEGIN(ctx)
+  set_device(ctx);
+  DMat* d = prod_scale_add(ph->p, alpha, X ? X->m : nullptr, beta);
+  *out = new dsg_mat{d, ctx, true};
+  API_END
+}
+
 extern "C" dsg_status dsg_prod_recompute_static(dsg_prod* ph, uint32_t flags) {
   if (!ph) return fail(nullptr, DSG_E_ARG, "product is NULL");
   if (flags & ~(uint32_t)DSG_SYNC) return fail(ph->owner, DSG_E_ARG, "unknown flag");

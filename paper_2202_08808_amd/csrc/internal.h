@@ -287,6 +287,9 @@ struct DProd {
 
 // C = op(A) op(B), op(X) = X^T under DSG_TRANS_A / DSG_TRANS_B in ops.
 DProd* prod_create(Ctx* c, DMat* A, DMat* B, uint32_t ops = 0);
+// A new matrix (alpha (x) C) (+) (beta (x) X) from the product's current C;
+// X may be null (then beta is not read).  alpha, beta: host values.
+DMat* prod_scale_add(DProd* p, const void* alpha, DMat* X, const void* beta);
 void prod_destroy(DProd* p);
 // mode 0: dynamic update; 1: recompute every row (static); with report_affected.
 int32_t prod_run(DProd* p, int mode, bool report_affected);

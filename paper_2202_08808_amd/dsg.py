@@ -109,6 +109,7 @@ SIGNATURES = {
     "dsg_mat_destroy": [P],
     "dsg_prod_create_static": [P, P, P, P],
     "dsg_prod_create": [P, P, P, ctypes.c_uint32, P],
+    "dsg_prod_scale_add": [P, P, P, P, P],
     "dsg_prod_recompute_static": [P, ctypes.c_uint32],
     "dsg_prod_update": [P, ctypes.c_uint32, P],
     "dsg_prod_rows": [P, P, ctypes.c_int32, ctypes.c_uint32, P],
@@ -247,6 +248,15 @@ class Matrix:
         self.h = h
 
     @classmethod
+    def _wrap(cls, ctx: Context, h, nrows: int, ncols: int, semiring: int):
+        """A Matrix around a handle the library created."""
+        m = cls.__new__(cls)
+        m.ctx, m.L = ctx, ctx.L
+        m.nrows, m.ncols, m.semiring = int(nrows), int(ncols), int(semiring)
+        m.h = h
+        return m
+
+    @classmethod
     def from_csr(cls, ctx: Context, csr, semiring: int):
         return cls(ctx, csr.nrows, csr.ncols, semiring, np.ascontiguousarray(csr.row_ptr, np.int64),
                    np.ascontiguousarray(csr.col, np.int32),
@@ -377,6 +387,17 @@ class Product:
 
     def recompute_static(self):
         self.ctx._check(self.L.dsg_prod_recompute_static(self.h, 0))
+
+    def scale_add(self, alpha, X: Optional["Matrix"] = None, beta=None) -> "Matrix":
+        """A new Matrix (alpha (x) C) (+) (beta (x) X) from the current C."""
+        dt = DTYPE[self.semiring]
+        a = np.array([alpha], dt)
+        b = np.array([0 if beta is None else beta], dt)
+        h = P()
+        self.ctx._check(self.L.dsg_prod_scale_add(self.h, a.ctypes.data_as(P), X.h if X is not None else None,
+                                                  b.ctypes.data_as(P) if X is not None else None,
+                                                  ctypes.byref(h)))
+        return Matrix._wrap(self.ctx, h, self.nrows, self.ncols, self.semiring)
 
     def rows(self, rows) -> RowSet:
         v = Rows()
