@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+EXTRA = 3  # steps after the timed ones, every phase timed, for the per-phase breakdown
 
 
 def log(*a):
@@ -385,12 +386,72 @@ def bench_sweep(args):
     print(json.dumps({"workload": args.workload, "sweep": out}), flush=True)
 
 
+FORMS = [("minplus", False, False), ("minplus", True, False), ("minplus", False, True),
+         ("orand", False, False), ("orand", True, False)]
+
+
+def bench_forms(args):
+    """Operand forms and semirings on one R-MAT graph (scale 16, edge factor
+    16, the default workload's structure and batch recipe): per batch size,
+    ms per step of the dynamic update (apply + update, row path) and of a
+    static recompute, for C = A A, A^T A and A A^T over (min,+) and the
+    bitwise (or, and) semiring on 32-bit words."""
+    import torch
+    from paper_2202_08808_amd import dsg
+    from paper_2202_08808_amd import inputs as I
+    sr_of = {"minplus": (I.MIN_PLUS_F32, 1, 100), "orand": (I.OR_AND_U32, 0, (1 << 32) - 1)}
+    dev = torch.device("cuda:0")
+    out = []
+    for b in args.sweep or [args.batch]:
+        for name, ta, tb in FORMS:
+            sr, lo, hi = sr_of[name]
+            A0 = I.rmat_csr(16, 16, sr, stream=201, lo=lo, hi=hi)
+            bs = I.disjoint_batches(A0, sr, [b] * (args.steps + args.warmup), stream=202 + b % 997,
+                                    value_lo=lo, value_hi=hi)
+            batches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (q.rows, q.cols, q.vals, q.ops))
+                       for q in bs]
+            ctx = dsg.Context(0, stream=torch.cuda.current_stream(dev))
+            t = ctx.get_tuning()
+            t.update_path = 1
+            ctx.set_tuning(t)
+            A = dsg.Matrix.from_csr(ctx, A0, sr)
+            P = dsg.Product(ctx, A, A, trans_a=ta, trans_b=tb)
+            ts = []
+            for k in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                A.apply(*batches[k])
+                P.update()
+                torch.cuda.synchronize()
+                if k >= args.warmup:
+                    ts.append(time.perf_counter() - t0)
+            st = P.stats()
+            rec = {"batch": b, "semiring": name, "form": ("At" if ta else "A") + ("At" if tb else "A"),
+                   "ms": round(float(np.median(ts)) * 1e3, 4), "updates_per_s": round(b / float(np.median(ts)), 1),
+                   "affected_rows": st["affected_rows"], "flops": st["flops"], "nnz_c": P.nnz()}
+            ts = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                P.recompute_static()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            rec["static_ms"] = round(float(np.median(ts)) * 1e3, 4)
+            rec["speedup"] = round(rec["static_ms"] / rec["ms"], 3)
+            log(f"[forms] {json.dumps(rec)}")
+            out.append(rec)
+            P.destroy()
+            A.destroy()
+            ctx.close()
+    print(json.dumps({"workload": "forms", "sweep": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat12", "stencil", "er", "batched", "serve"])
+    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "rmat12", "stencil", "er", "batched", "serve", "forms"])
     ap.add_argument("--instances", type=int, default=64, help="batched workload: number of instances")
     ap.add_argument("--max-scale", type=int, default=16, help="batched workload: largest R-MAT scale")
     ap.add_argument("--batch", type=int, default=10000)
@@ -414,6 +475,8 @@ def main():
         raise SystemExit(2)
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "forms":
+        return bench_forms(args)
     if args.workload == "serve":
         return bench_serve(args)
     if args.sweep:
@@ -433,8 +496,8 @@ def main():
         log(f"[bench] calibration copy: 3 x {args.calibrate_copy} MiB device to device")
         del x, y
     t0 = time.perf_counter()
-    w = make_workload(args.workload, args.batch, K + W)
-    log(f"[bench] workload {w.name}: n={w.A.nrows} nnz(A)={w.A.nnz} batches={K + W} "
+    w = make_workload(args.workload, args.batch, K + W + EXTRA)
+    log(f"[bench] workload {w.name}: n={w.A.nrows} nnz(A)={w.A.nnz} batches={K + W + EXTRA} "
         f"({time.perf_counter() - t0:.1f}s to generate)")
     sr = w.semiring
     dev = torch.device("cuda:0")
@@ -451,7 +514,7 @@ def main():
         return (torch.from_numpy(b.rows).to(dev), torch.from_numpy(b.cols).to(dev),
                 torch.from_numpy(np.ascontiguousarray(b.vals)).to(dev), torch.from_numpy(b.ops).to(dev))
     batches = [(dev_batch(w.batches_A[t]), dev_batch(w.batches_B[t]) if w.B is not None else None)
-               for t in range(K + W)]
+               for t in range(K + W + EXTRA)]
     per_step_updates = len(w.batches_A[0]) + (len(w.batches_B[0]) if w.B is not None else 0)
     torch.cuda.synchronize()
 
@@ -462,12 +525,17 @@ def main():
             B.apply(*bb)
         return P.update()
 
+    # warmup, every phase timed: names the dominant kernel
+    ctx.set_timing(True)
     for t in range(W):
         step(t)
     torch.cuda.synchronize()
-    log("[bench] warmup done")
+    warm = ctx.timing_report()["kernels"]
+    dom_name = max(warm, key=lambda k: warm[k]["ms"]) if warm else None
+    log(f"[bench] warmup done; dominant kernel {dom_name}")
 
-    ctx.set_timing(True)
+    # timed steps: HIP events around the dominant kernel's launches only
+    ctx.set_timing(True, phase=dom_name)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     stops = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     affected = changed = 0
@@ -483,9 +551,16 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     report = ctx.timing_report()
-    ctx.set_timing(False)
+    if dom_name is None and report["kernels"]:   # no warmup: every phase was timed
+        dom_name = max(report["kernels"], key=lambda k: report["kernels"][k]["ms"])
     lat = np.array([starts[k].elapsed_time(stops[k]) for k in range(K)])
     log(f"[bench] timed {K} steps in {wall:.3f}s; per-step ms: {np.round(lat, 3).tolist()}")
+    # untimed extra steps with every phase timed: the per-phase breakdown
+    ctx.set_timing(True)
+    for t in range(W + K, W + K + EXTRA):
+        step(t)
+    breakdown = ctx.timing_report()["kernels"]
+    ctx.set_timing(False)
 
     # static recompute on the same GPU, same kernels, full C written
     torch.cuda.synchronize()
@@ -500,9 +575,8 @@ def main():
 
     ms_per_step = wall / K * 1e3
     kern = report["kernels"]
-    dom_name = max(kern, key=lambda k: kern[k]["ms"]) if kern else None
     roof = None
-    if dom_name:
+    if dom_name and dom_name in kern:
         d = kern[dom_name]
         gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
         traffic = measured_traffic(dom_name, w.name, per_step_updates)
@@ -540,9 +614,11 @@ def main():
         "affected_rows_per_batch": affected / K,
         "changed_rows_per_batch": changed / K,
         "recomputed_rows_per_s": round(affected / wall, 1),
+        # per-phase HIP-event times of EXTRA steps after the timed ones
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 4),
                         "GB/s": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1) if v["ms"] else None}
-                    for k, v in kern.items()},
+                    for k, v in breakdown.items()},
+        "kernels_steps": EXTRA,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

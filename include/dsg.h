@@ -120,6 +120,10 @@ dsg_status dsg_ctx_memory(const dsg_ctx* ctx, size_t* bytes);
  * {"kernels": {name: {"launches": n, "ms": total, "bytes": algorithmic
  * bytes}}} into buf (NUL-terminated, truncated to cap) after synchronising. */
 dsg_status dsg_ctx_set_timing(dsg_ctx* ctx, int on);
+/* Time only the phases named `phase` (as in the report; NULL or "": every
+ * phase), so that a timed run pays two event records per launch of the one
+ * kernel of interest and none elsewhere. */
+dsg_status dsg_ctx_set_timing_phase(dsg_ctx* ctx, const char* phase);
 dsg_status dsg_ctx_timing_report(dsg_ctx* ctx, char* buf, size_t cap);
 
 /* Row-kernel tuning: output-row-size thresholds of the accumulator bins.

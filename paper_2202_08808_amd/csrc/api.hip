@@ -68,24 +68,44 @@ void* ctx_scratch2(Ctx* c, size_t bytes) { return grow_scratch(c, c->scratch2, c
 
 void ctx_sync(Ctx* c) { DSG_HIP(hipStreamSynchronize(c->stream)); }
 
-void ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop) {
+// Timing events come from a pool filled when timing is switched on, so that
+// a timed phase costs two event records and no event creation.
+static hipEvent_t take_event(Ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  DSG_HIP(hipEventCreate(&e));
+  return e;
+}
+
+bool ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop) {
+  if (!c->timing_phase.empty() && c->timing_phase != name) {
+    *start = *stop = nullptr;
+    return false;
+  }
   KernelTiming t;
   t.name = name;
   t.bytes = bytes;
-  DSG_HIP(hipEventCreate(&t.start));
-  DSG_HIP(hipEventCreate(&t.stop));
+  t.start = take_event(c);
+  t.stop = take_event(c);
   DSG_HIP(hipEventRecord(t.start, c->stream));
   *start = t.start;
   *stop = t.stop;
   c->timings.push_back(t);
+  return true;
 }
 
-void ctx_timing_end(Ctx* c, hipEvent_t stop) { DSG_HIP(hipEventRecord(stop, c->stream)); }
+void ctx_timing_end(Ctx* c, hipEvent_t stop) {
+  if (stop) DSG_HIP(hipEventRecord(stop, c->stream));
+}
 
 static void clear_timings(Ctx* c) {
   for (auto& t : c->timings) {
-    (void)hipEventDestroy(t.start);
-    (void)hipEventDestroy(t.stop);
+    c->event_pool.push_back(t.start);
+    c->event_pool.push_back(t.stop);
   }
   c->timings.clear();
 }
@@ -236,6 +256,8 @@ extern "C" dsg_status dsg_ctx_destroy(dsg_ctx* ctx) {
   (void)hipSetDevice(c.device);
   (void)hipStreamSynchronize(c.stream);
   clear_timings(&c);
+  for (hipEvent_t e : c.event_pool) (void)hipEventDestroy(e);
+  c.event_pool.clear();
   ctx_free(&c, c.scratch, c.scratch_bytes);
   ctx_free(&c, c.scratch2, c.scratch2_bytes);
   if (c.pinned) (void)hipHostFree(c.pinned);
@@ -269,6 +291,19 @@ extern "C" dsg_status dsg_ctx_set_timing(dsg_ctx* ctx, int on) {
   ctx_sync(&ctx->c);
   clear_timings(&ctx->c);
   ctx->c.timing = on != 0;
+  // enough events for many timed calls (more are created when these run out)
+  while (ctx->c.timing && ctx->c.event_pool.size() < 1024) {
+    hipEvent_t e;
+    DSG_HIP(hipEventCreate(&e));
+    ctx->c.event_pool.push_back(e);
+  }
+  API_END
+}
+
+extern "C" dsg_status dsg_ctx_set_timing_phase(dsg_ctx* ctx, const char* phase) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  API_BEGIN(ctx)
+  ctx->c.timing_phase = phase ? phase : "";
   API_END
 }
 

@@ -103,6 +103,7 @@ struct Ctx {
   int num_cus = 256;  // compute units of the device
   dsg_tuning tuning;
   bool timing = false;
+  std::string timing_phase;  // when not empty, only phases of this name are timed
   std::vector<KernelTiming> timings;
   std::vector<hipEvent_t> event_pool;
   // pinned host staging block for small device->host reads
@@ -119,7 +120,9 @@ void ctx_free(Ctx* c, void* p, size_t bytes);
 void* ctx_scratch(Ctx* c, size_t bytes);   // contents undefined; valid until the next call
 void* ctx_scratch2(Ctx* c, size_t bytes);
 void ctx_sync(Ctx* c);
-void ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop);
+// Records a phase's start unless a phase filter excludes it (then both
+// events are null and false is returned); ctx_timing_end ignores a null event.
+bool ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop);
 void ctx_timing_end(Ctx* c, hipEvent_t stop);
 
 // Bump allocator for device scratch carved out of one allocation.

@@ -336,6 +336,65 @@ __global__ __launch_bounds__(1024) void k_small_sort(uint64_t* keys, uint32_t* v
   }
 }
 
+// Bitonic sort of up to MID_SORT keys of at most MID_KEY_BITS bits in one
+// workgroup: each key is packed with its input position into one 64-bit word,
+// so the words sort by (key, position), which is exactly the stable order,
+// and the values follow through their positions.  64 KB of LDS holds the
+// words and then the values.  Each of the log2(m)(log2(m)+1)/2 stages moves
+// 32 bytes of LDS per pair, so beyond 8192 keys the multi-pass radix sort is
+// faster (16384 keys: ~90 us here against ~65 us).
+constexpr int MID_SORT = 8192;
+constexpr int MID_POS_BITS = 13;
+constexpr int MID_KEY_BITS = 64 - MID_POS_BITS;
+constexpr int MID_NT = 1024;
+constexpr int MID_PER = MID_SORT / MID_NT;
+static_assert((1 << MID_POS_BITS) == MID_SORT, "positions fill the low bits");
+
+__global__ __launch_bounds__(MID_NT) void k_mid_sort(uint64_t* keys, uint32_t* vals, int n) {
+  __shared__ uint64_t sw[MID_SORT];
+  int m = 1;
+  while (m < n) m <<= 1;
+  for (int i = threadIdx.x; i < m; i += MID_NT)
+    sw[i] = i < n ? ((keys[i] << MID_POS_BITS) | (uint64_t)i) : ~0ull;  // padding sorts last
+  __syncthreads();
+  const int half = m >> 1;
+  for (int k = 2; k <= m; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      // pair q: i has a 0 at bit log2(j), its partner i + j a 1
+      for (int q = threadIdx.x; q < half; q += MID_NT) {
+        const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));
+        const int p = i | j;
+        const uint64_t a = sw[i], b = sw[p];
+        if ((a > b) == ((i & k) == 0)) {
+          sw[i] = b;
+          sw[p] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  uint32_t pos[MID_PER];
+#pragma unroll
+  for (int r = 0; r < MID_PER; ++r) {
+    const int j = threadIdx.x + r * MID_NT;
+    pos[r] = 0;
+    if (j < n) {
+      const uint64_t w = sw[j];
+      pos[r] = (uint32_t)(w & (MID_SORT - 1));
+      keys[j] = w >> MID_POS_BITS;
+    }
+  }
+  __syncthreads();
+  uint32_t* sv = (uint32_t*)sw;
+  for (int i = threadIdx.x; i < n; i += MID_NT) sv[i] = vals[i];
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < MID_PER; ++r) {
+    const int j = threadIdx.x + r * MID_NT;
+    if (j < n) vals[j] = sv[pos[r]];
+  }
+}
+
 }  // namespace
 
 size_t radix_scratch_bytes(int64_t n) {
@@ -347,6 +406,10 @@ size_t radix_scratch_bytes(int64_t n) {
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, void* scratch,
                       hipStream_t s) {
   if (n <= 1 || key_bits <= 0) return;
+  if (n <= MID_SORT && key_bits <= MID_KEY_BITS) {
+    hipLaunchKernelGGL(k_mid_sort, dim3(1), dim3(MID_NT), 0, s, keys, vals, (int)n);
+    return;
+  }
   if (n <= SMALL_SORT) {
     // one workgroup: the same order as the stable radix sort when equal keys
     // carry ascending values (their original positions)

@@ -1671,10 +1671,8 @@ void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, 
     const int32_t* list = bins + (int64_t)b * stride;
     const unsigned long long* dc = d_counts + b;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing && plan) {
-      ctx_timing_begin(c, kBinNames[b], 0.0, &e0, &e1);
+    if (c->timing && plan && ctx_timing_begin(c, kBinNames[b], 0.0, &e0, &e1))
       timed.push_back({b, c->timings.size() - 1});
-    }
     switch (b) {
 #define GROUP_CASE(B, G, WG)                                                                              \
   case B: {                                                                                               \

@@ -98,6 +98,7 @@ SIGNATURES = {
     "dsg_ctx_synchronize": [P],
     "dsg_ctx_memory": [P, P],
     "dsg_ctx_set_timing": [P, ctypes.c_int],
+    "dsg_ctx_set_timing_phase": [P, ctypes.c_char_p],
     "dsg_ctx_timing_report": [P, ctypes.c_char_p, ctypes.c_size_t],
     "dsg_ctx_get_tuning": [P, P],
     "dsg_ctx_set_tuning": [P, P],
@@ -215,7 +216,9 @@ class Context:
         self._check(self.L.dsg_ctx_memory(self.h, ctypes.byref(v)))
         return v.value
 
-    def set_timing(self, on: bool):
+    def set_timing(self, on: bool, phase: Optional[str] = None):
+        """Per-phase HIP-event timing; with phase, only phases of that name."""
+        self._check(self.L.dsg_ctx_set_timing_phase(self.h, phase.encode() if phase else None))
         self._check(self.L.dsg_ctx_set_timing(self.h, 1 if on else 0))
 
     def timing_report(self) -> dict:

@@ -123,8 +123,9 @@ def test_apply_matches_oracle(ctx, sr):
     A = rand_csr(rng, 90, 70, 0.1, sr)
     Am = dsg.Matrix.from_csr(ctx, A, sr)
     cur = oracle.Csr.of(A)
-    for t in range(6):
-        b = I.random_batch(90, 70, sr, [0, 1, 17, 300, 2000, 5000][t], rng, hot_rows=40 if t % 2 else None)
+    # sizes on both sides of the one-workgroup sorts' limits (4096, 8192)
+    for t, size in enumerate([0, 1, 17, 300, 2000, 4097, 5000, 8192, 8193, 12000]):
+        b = I.random_batch(90, 70, sr, size, rng, hot_rows=40 if t % 2 else None)
         Am.apply_batch(b)
         cur, _ = oracle.apply(sr, cur, b.rows, b.cols, b.vals, b.ops)
         got = Am.export()
