@@ -82,7 +82,8 @@ struct RowArgs {
   unsigned long long* c_short;      // C slots the flagged rows need
   unsigned long long* arena_short;  // arena bytes the flagged rows need
   // B split by dense column chunk (bs_parts > 0): part p of row k spans
-  // [bs_ps[k*bs_parts + p], bs_ps[k*bs_parts + p + 1]) of bs_col / bs_val
+  // [bs_ps[k*(bs_parts+1) + p], bs_ps[k*(bs_parts+1) + p + 1]) of bs_col /
+  // bs_val (positions inside the row's slots of B's pool)
   int32_t bs_parts;
   const int64_t* bs_ps;
   const int32_t* bs_col;
@@ -530,7 +531,7 @@ __device__ inline int32_t stage_chunk(const RowArgs& R, int64_t aoff, int32_t d,
     k = R.a_col[aoff + t];
     a = ldv<V>(R.a_val, aoff + t);
     if (part >= 0) {
-      const int64_t* ps = R.bs_ps + (int64_t)k * R.bs_parts + part;
+      const int64_t* ps = R.bs_ps + (int64_t)k * (R.bs_parts + 1) + part;
       boff = ps[0];
       len = (int32_t)(ps[1] - boff);
     } else {
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       k = R.a_col[aoff + t];
       a = ldv<V>(R.a_val, aoff + t);
       if (use_split) {
-        const int64_t* ps = R.bs_ps + (int64_t)k * R.bs_parts + part;
+        const int64_t* ps = R.bs_ps + (int64_t)k * (R.bs_parts + 1) + part;
         boff = ps[0];
         len = (int32_t)(ps[1] - boff);
       } else {
@@ -825,7 +826,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   if constexpr (SR == 1) {
     constexpr int HSLOTS = CH / 2;
     constexpr int HBITS = __builtin_ctz(HSLOTS);
-    constexpr int HFILL = HSLOTS * 2 / 3;
+    constexpr int HFILL = HSLOTS * 3 / 5;  // measured: 1/3 2/5 1/2 3/5 2/3 3/4 4/5, 3/5 fastest
     constexpr int HPROBES = 128;
     static_assert(sizeof(Acc) == 4, "(min,+) keys: the identity 0xffffffff doubles as the empty key -1");
     int32_t* hk = (int32_t*)acc;
@@ -1794,20 +1795,26 @@ void ensure_arena(DProd* p, size_t bytes) {
 constexpr int BSPLIT_MAXP = 8;
 constexpr int BSPLIT_UNR = 8;  // loads in flight per lane (hub rows)
 
-// one wavefront per row of B: entries per column chunk into ps[k*P + q]
-__global__ __launch_bounds__(256) void k_bsplit_count(const int64_t* b_off, const int32_t* b_len,
-                                                      const int32_t* b_col, int32_t n, int P, int chbits,
-                                                      int64_t* ps) {
+// One wavefront per row of B: the row's entries, grouped by column chunk,
+// into the copy at the row's own pool offset (tombstones left out), and the
+// P + 1 chunk boundaries of the row into bs[k*(P+1) ...].  The row is read
+// twice, to count and to place, and no scan over rows is needed.  Entries
+// keep their order inside a chunk.
+template <int VSZ>
+__global__ __launch_bounds__(256) void k_bsplit(const int64_t* b_off, const int32_t* b_len, const int32_t* b_col,
+                                                const void* b_val, int32_t n, int P, int chbits, int64_t* bs,
+                                                int32_t* out_col, void* out_val) {
+  using W = typename std::conditional<VSZ == 8, uint64_t, uint32_t>::type;
   const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int ln = threadIdx.x & 63;
-  if (k == 0 && ln == 0) ps[(int64_t)n * P] = 0;
   if (k >= n) return;
   const int64_t off = b_off[k];
   const int32_t len = b_len[k];
-  int64_t cnt[BSPLIT_MAXP];
+  const uint64_t lt = ln ? (~0ull >> (64 - ln)) : 0ull;
+  int64_t o[BSPLIT_MAXP];
 #pragma unroll
-  for (int q = 0; q < BSPLIT_MAXP; ++q) cnt[q] = 0;
-  for (int32_t e0 = 0; e0 < len; e0 += 64 * BSPLIT_UNR) {  // BSPLIT_UNR loads in flight per lane
+  for (int q = 0; q < BSPLIT_MAXP; ++q) o[q] = 0;
+  for (int32_t e0 = 0; e0 < len; e0 += 64 * BSPLIT_UNR) {  // count; BSPLIT_UNR loads in flight per lane
     int part[BSPLIT_UNR];
 #pragma unroll
     for (int v = 0; v < BSPLIT_UNR; ++v) {
@@ -1818,32 +1825,25 @@ __global__ __launch_bounds__(256) void k_bsplit_count(const int64_t* b_off, cons
     for (int v = 0; v < BSPLIT_UNR; ++v)
 #pragma unroll
       for (int q = 0; q < BSPLIT_MAXP; ++q)
-        if (q < P) cnt[q] += __popcll(__ballot(part[v] == q));
+        if (q < P) o[q] += __popcll(__ballot(part[v] == q));
+  }
+  // chunk starts inside the row's slots
+  int64_t run = off;
+#pragma unroll
+  for (int q = 0; q < BSPLIT_MAXP; ++q) {
+    if (q < P) {
+      const int64_t c = o[q];
+      o[q] = run;
+      run += c;
+    }
   }
   if (ln == 0) {
 #pragma unroll
     for (int q = 0; q < BSPLIT_MAXP; ++q)
-      if (q < P) ps[k * P + q] = cnt[q];
+      if (q < P) bs[k * (P + 1) + q] = o[q];
+    bs[k * (P + 1) + P] = run;
   }
-}
-
-// one wavefront per row of B: entries to their chunk's segment, in row order
-template <int VSZ>
-__global__ __launch_bounds__(256) void k_bsplit_scatter(const int64_t* b_off, const int32_t* b_len,
-                                                        const int32_t* b_col, const void* b_val, int32_t n, int P,
-                                                        int chbits, const int64_t* ps, int32_t* out_col,
-                                                        void* out_val) {
-  using W = typename std::conditional<VSZ == 8, uint64_t, uint32_t>::type;
-  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const int ln = threadIdx.x & 63;
-  if (k >= n) return;
-  const int64_t off = b_off[k];
-  const int32_t len = b_len[k];
-  const uint64_t lt = ln ? (~0ull >> (64 - ln)) : 0ull;
-  int64_t o[BSPLIT_MAXP];
-#pragma unroll
-  for (int q = 0; q < BSPLIT_MAXP; ++q) o[q] = q < P ? ps[k * P + q] : 0;
-  for (int32_t e0 = 0; e0 < len; e0 += 64 * BSPLIT_UNR) {  // BSPLIT_UNR loads in flight per lane
+  for (int32_t e0 = 0; e0 < len; e0 += 64 * BSPLIT_UNR) {  // place
     int32_t col[BSPLIT_UNR];
     W val[BSPLIT_UNR];
 #pragma unroll
@@ -1886,8 +1886,8 @@ void build_bsplit(DProd* p) {
   if (P < 2 || P > BSPLIT_MAXP || B->nrows == 0) return;
   const int chbits = vsz == 8 ? 14 : 15;
   static_assert(dense_cols<8>() == (1 << 14) && dense_cols<4>() == (1 << 15), "chunk widths");
-  const int64_t nps = (int64_t)B->nrows * P + 1;
-  const int64_t cap = std::max<int64_t>(B->h_top_ub, 1);
+  const int64_t nps = (int64_t)B->nrows * (P + 1);
+  const int64_t cap = std::max<int64_t>(B->h_top_ub, 1);  // every row's slots lie below the pool top
   const size_t col_off = round256((size_t)nps * 8);
   const size_t val_off = col_off + round256((size_t)cap * 4);
   const size_t bytes = val_off + round256((size_t)cap * vsz);
@@ -1901,19 +1901,16 @@ void build_bsplit(DProd* p) {
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) ctx_timing_begin(c, "b_split", (double)cap * (4 + vsz) * 2, &e0, &e1);
-  int64_t* ps = (int64_t*)p->bsp;
+  int64_t* bs = (int64_t*)p->bsp;
   int32_t* ocol = (int32_t*)((char*)p->bsp + col_off);
   void* oval = (char*)p->bsp + val_off;
   const unsigned nb = (unsigned)blocks_for((int64_t)B->nrows * 64, 256);
-  hipLaunchKernelGGL(k_bsplit_count, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->nrows, P,
-                     chbits, ps);
-  exclusive_scan_i64(ps, ps, nps, nullptr, ctx_scratch2(c, scan_scratch_bytes(nps)), s);
   if (vsz == 8)
-    hipLaunchKernelGGL(k_bsplit_scatter<8>, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->val,
-                       B->nrows, P, chbits, (const int64_t*)ps, ocol, oval);
+    hipLaunchKernelGGL(k_bsplit<8>, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->val, B->nrows,
+                       P, chbits, bs, ocol, oval);
   else
-    hipLaunchKernelGGL(k_bsplit_scatter<4>, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->val,
-                       B->nrows, P, chbits, (const int64_t*)ps, ocol, oval);
+    hipLaunchKernelGGL(k_bsplit<4>, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->val, B->nrows,
+                       P, chbits, bs, ocol, oval);
   DSG_HIP(hipGetLastError());
   if (c->timing) ctx_timing_end(c, e1);
   p->bsp_col_off = col_off;

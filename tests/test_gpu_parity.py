@@ -295,6 +295,41 @@ def test_dense_row_outgrows_its_hash(ctx):
 
 
 @pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_dense_passes_split_b(tuned, sr):
+    """Every row in the dense bin with C 70,000 columns wide: 3 column passes
+    for 4-byte values, 5 for 8-byte ones, each streaming its own part of the
+    split copy of B, which is rebuilt for every update of A and B."""
+    ctx = tuned
+    say(f"dense passes over split B {SR_ID[sr]}")
+    t = ctx.get_tuning()
+    t.force_bin = 8
+    t.dense_max_passes = 8
+    ctx.set_tuning(t)
+    rng = np.random.default_rng(90 + sr)
+    A = rand_csr(rng, 120, 2500, 0.012, sr, row_skew=True)
+    B = rand_csr(rng, 2500, 70000, 0.0003, sr, row_skew=True)
+    Am, Bm, P = gpu_product(ctx, sr, A, B)
+    a, b = oracle.Csr.of(A), oracle.Csr.of(B)
+    C = check_product(sr, P, A, B, "initial")
+    for k, size in enumerate([30, 600]):
+        ba = I.random_batch(120, 2500, sr, size, rng)
+        bb = I.random_batch(2500, 70000, sr, 4 * size, rng)
+        Am.apply_batch(ba)
+        Bm.apply_batch(bb)
+        a, _ = oracle.apply(sr, a, ba.rows, ba.cols, ba.vals, ba.ops)
+        b, _ = oracle.apply(sr, b, bb.rows, bb.cols, bb.vals, bb.ops)
+        rs = P.update()
+        want = oracle.spgemm(sr, a, b, nthreads=THREADS)
+        assert_same_csr(sr, P.export(), want, f"batch {k}", A=a, B=b)
+        truth = changed_rows(C, want)
+        if sr != I.PLUS_TIMES_F64:
+            assert np.array_equal(rs.row_ids(), truth), f"batch {k}: reported rows"
+        C = want
+    assert P.stats()["bin_rows"][8] > 0
+    destroy(P, Am, Bm)
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
 @pytest.mark.parametrize("square", [True, False], ids=["AxA", "AxB"])
 def test_dynamic_sequence(ctx, sr, square):
     """D1 (dynamic result = static recompute of the updated operands) and D5
