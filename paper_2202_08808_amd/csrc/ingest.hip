@@ -563,23 +563,29 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
     if (tid < 3) cnt[tid] = 0;
     for (int32_t c0 = u0; c0 < u1; c0 += HEAVY_SLOTS / 2) {
       const int32_t c1 = min(u1, c0 + HEAVY_SLOTS / 2);
-      for (int x = tid; x < HEAVY_SLOTS; x += HEAVY_WG) hk[x] = -1;
+      // a table of twice this pass's updates (load <= 1/2): a long row with
+      // few updates clears a few hundred slots, not all of them
+      int32_t S = 256;
+      while (S < 2 * (c1 - c0)) S <<= 1;
+      const uint32_t hm = (uint32_t)S - 1;
+      for (int x = tid; x < S; x += HEAVY_WG) hk[x] = -1;
       __syncthreads();
       for (int32_t u = c0 + tid; u < c1; u += HEAVY_WG) {
         const int32_t col = (int32_t)(U.key[u] & cmask);
-        uint32_t h = hash_col(col) & (HEAVY_SLOTS - 1);
-        while (atomicCAS(&hk[h], -1, col) != -1) h = (h + 1) & (HEAVY_SLOTS - 1);
+        uint32_t h = hash_col(col) & hm;
+        while (atomicCAS(&hk[h], -1, col) != -1) h = (h + 1) & hm;
         hu[h] = u;
       }
       __syncthreads();
-      for (int32_t s0 = tid; s0 < len; s0 += 4 * HEAVY_WG) {
-        int32_t cc[4];
+      constexpr int SU = 8;  // row loads in flight per lane
+      for (int32_t s0 = tid; s0 < len; s0 += SU * HEAVY_WG) {
+        int32_t cc[SU];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) cc[v] = s0 + v * HEAVY_WG < len ? m.col[off + s0 + v * HEAVY_WG] : -1;
+        for (int v = 0; v < SU; ++v) cc[v] = s0 + v * HEAVY_WG < len ? m.col[off + s0 + v * HEAVY_WG] : -1;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
+        for (int v = 0; v < SU; ++v) {
           if (cc[v] < 0) continue;
-          uint32_t h = hash_col(cc[v]) & (HEAVY_SLOTS - 1);
+          uint32_t h = hash_col(cc[v]) & hm;
           for (;;) {
             const int32_t x = hk[h];
             if (x == cc[v]) {
@@ -587,7 +593,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
               break;
             }
             if (x == -1) break;
-            h = (h + 1) & (HEAVY_SLOTS - 1);
+            h = (h + 1) & hm;
           }
         }
       }
