@@ -123,3 +123,79 @@ def test_batched_defers_when_room_is_short(ctx):
     p.destroy()
     a.destroy()
     torch.cuda.synchronize()
+
+
+def to_dev_bits(b):
+    """Device copies of a batch; 32-bit words travel as int32 (same bits)."""
+    import torch
+    vals = np.ascontiguousarray(b.vals)
+    if vals.dtype == np.uint32:
+        vals = vals.view(np.int32)
+    return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (b.rows, b.cols, vals, b.ops)]
+
+
+@pytest.mark.parametrize("direct_log2", [24, 0], ids=["graph", "direct"])
+def test_batched_boolean_and_fp64(ctx, direct_log2):
+    """Bitwise (or, and) products (A A and A^T A) and an fp64 A B in one batch,
+    in the graph and on the plain path, against the oracle and the reported
+    rows against the changed rows."""
+    import torch
+    say(f"batched boolean and fp64, direct from 2^{direct_log2}")
+    tu = ctx.get_tuning()
+    tu.batch_direct_log2 = direct_log2
+    ctx.set_tuning(tu)
+    try:
+        rng = np.random.default_rng(77)
+        specs = [(I.OR_AND_U32, False, True), (I.OR_AND_U32, True, True), (I.PLUS_TIMES_F64, False, False)]
+        objs, host = [], []
+        for t, (sr, ta, square) in enumerate(specs):
+            lo, hi = (0, (1 << 32) - 1) if sr == I.OR_AND_U32 else (1, 9)
+            A = I.rmat_csr(10, 8, sr, stream=760 + t, lo=lo, hi=hi)
+            a = dsg.Matrix.from_csr(ctx, A, sr)
+            if square:
+                b, B = a, A
+            else:
+                B = I.rmat_csr(10, 8, sr, stream=770 + t, lo=lo, hi=hi)
+                b = dsg.Matrix.from_csr(ctx, B, sr)
+            p = dsg.Product(ctx, a, b, trans_a=ta)
+            objs.append((a, b, p))
+            host.append([oracle.Csr.of(A), oracle.Csr.of(B), None])
+        for j, (sr, ta, square) in enumerate(specs):
+            ha = host[j]
+            ha[2] = oracle.spgemm(sr, oracle.transpose(ha[0]) if ta else ha[0], ha[0] if square else ha[1])
+        bx = dsg.Batch(ctx, [p for _, _, p in objs])
+        for rnd in range(3):
+            sets, keep = [], []
+            for j, (sr, ta, square) in enumerate(specs):
+                a, b, p = objs[j]
+                ba = I.random_batch(1024, 1024, sr, 60 * (rnd + 1), rng)
+                dev = to_dev_bits(ba)
+                keep.append(dev)
+                sets.append((a, *dev))
+                host[j][0], _ = oracle.apply(sr, host[j][0], ba.rows, ba.cols, ba.vals, ba.ops)
+                if not square:
+                    bb = I.random_batch(1024, 1024, sr, 30 * (rnd + 1), rng)
+                    dev = to_dev_bits(bb)
+                    keep.append(dev)
+                    sets.append((b, *dev))
+                    host[j][1], _ = oracle.apply(sr, host[j][1], bb.rows, bb.cols, bb.vals, bb.ops)
+            counts = bx.run(sets)
+            for j, (sr, ta, square) in enumerate(specs):
+                ha = host[j]
+                lhs = oracle.transpose(ha[0]) if ta else ha[0]
+                rhs = ha[0] if square else ha[1]
+                want = oracle.spgemm(sr, lhs, rhs)
+                assert_same_csr(sr, objs[j][2].export(), want, f"round {rnd} product {j}", A=lhs, B=rhs)
+                if sr != I.PLUS_TIMES_F64:
+                    assert counts[j] == len(changed_rows(ha[2], want)), f"round {rnd} product {j}: row count"
+                ha[2] = want
+        bx.destroy()
+        for a, b, p in objs:
+            p.destroy()
+        for a, b, p in objs:
+            if b is not a:
+                b.destroy()
+            a.destroy()
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_tuning(None)

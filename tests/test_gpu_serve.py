@@ -174,6 +174,49 @@ def test_served_product_of_two_operands(ctx):
     mb.destroy()
 
 
+@pytest.mark.parametrize("sr,ta,tb", [(I.MIN_PLUS_F32, True, False), (I.MIN_PLUS_F32, False, True),
+                                       (I.OR_AND_U32, True, False)], ids=["AtB", "ABt", "orand-AtB"])
+def test_served_transposed_product(ctx, sr, ta, tb):
+    """A served product with a transposed operand (and the bitwise (or, and)
+    semiring): updates go to the caller's matrices, queries read op(A) op(B)."""
+    say(f"served transposed {sr} {ta} {tb}")
+    n = 1500
+    lo, hi = (0, (1 << 32) - 1) if sr == I.OR_AND_U32 else (1, 100)
+
+    def mat(seed):
+        keys = I.er_keys(n, 8 * n, I.rng_for(seed, 0))
+        return I.csr_from_keys(n, n, keys, I.draw_values(sr, keys.size, I.rng_for(seed, 1), lo, hi))
+    A, B = mat(16), mat(17)
+    ba = I.disjoint_batches(A, sr, [40] * 5, stream=651, value_lo=lo, value_hi=hi)
+    bb = I.disjoint_batches(B, sr, [40] * 5, stream=652, value_lo=lo, value_hi=hi)
+    ma, mb = dsg.Matrix.from_csr(ctx, A, sr), dsg.Matrix.from_csr(ctx, B, sr)
+    P = dsg.Product(ctx, ma, mb, trans_a=ta, trans_b=tb)
+    S = dsg.Server(ctx, P)
+    a, b = oracle.Csr.of(A), oracle.Csr.of(B)
+
+    def want_c():
+        return oracle.spgemm(sr, oracle.transpose(a) if ta else a, oracle.transpose(b) if tb else b,
+                             nthreads=THREADS)
+    qt, want = [], []
+    rng = np.random.default_rng(6)
+    for x, y in zip(ba, bb):
+        S.submit_batch(ma, x)
+        S.submit_batch(mb, y)
+        a, _ = oracle.apply(sr, a, x.rows, x.cols, x.vals, x.ops)
+        b, _ = oracle.apply(sr, b, y.rows, y.cols, y.vals, y.ops)
+        rows = np.sort(rng.choice(n, 40, replace=False)).astype(np.int32)
+        qt.append(S.submit_query(rows))
+        want.append(rows_of(want_c(), rows))
+    S.drain()
+    for k, (t, w) in enumerate(zip(qt, want)):
+        assert_same_csr(sr, S.query_result(t), w, f"query {k}")
+    S.destroy()
+    assert_same_csr(sr, P.export(), want_c(), "final C")
+    P.destroy()
+    ma.destroy()
+    mb.destroy()
+
+
 def test_served_errors_and_ownership(ctx):
     say("served errors")
     A = er(1024, 16)
