@@ -471,7 +471,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): the whole problem lives on one "
-              "MI355X and this build has no multi-GPU path", file=sys.stderr)
+              "MI355X and the library has no multi-GPU path", file=sys.stderr)
         raise SystemExit(2)
     if args.workload == "batched":
         return bench_batched(args)
