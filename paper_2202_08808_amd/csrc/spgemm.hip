@@ -884,17 +884,17 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
         int64_t old_read = 0;
         if (!changed) {  // every old entry present with the same value
           bool bad = false;
-          for (int32_t e0 = tid; e0 < olen; e0 += 4 * DENSE_WG) {
-            int32_t oc[4];
-            V ov[4];
+          for (int32_t e0 = tid; e0 < olen; e0 += 8 * DENSE_WG) {
+            int32_t oc[8];
+            V ov[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
               const int32_t e = e0 + u * DENSE_WG;
               oc[u] = e < olen ? R.c_col[ooff + e] : -1;
               ov[u] = e < olen ? ldv<V>(R.c_val, ooff + e) : V(0);
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < 8; ++u) {
               if (oc[u] < 0) continue;
               uint32_t hh = hash_col(oc[u]) >> (32 - HBITS);
               bool found = false;
@@ -1048,23 +1048,23 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       ctot += c;
     }
     grp.sync();
-    // compare the old entries that fall into this chunk (4 loads in flight per
+    // compare the old entries that fall into this chunk (8 loads in flight per
     // lane).  (min,+): an untouched slot holds the identity key, which no
     // stored value maps to, so the key comparison alone decides.
     if (!changed) {
       int32_t in_chunk = 0;
       bool bad = false;
-      for (int32_t e0 = tid; e0 < olen; e0 += 4 * DENSE_WG) {
-        int32_t oc[4];
-        V ov[4];
+      for (int32_t e0 = tid; e0 < olen; e0 += 8 * DENSE_WG) {
+        int32_t oc[8];
+        V ov[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           const int32_t e = e0 + u * DENSE_WG;
           oc[u] = e < olen ? R.c_col[ooff + e] : -1;
           ov[u] = e < olen ? ldv<V>(R.c_val, ooff + e) : V(0);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           if (oc[u] >= c0 && oc[u] < c1) {
             ++in_chunk;
             const int x = oc[u] - c0;
@@ -1136,19 +1136,19 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       if (write) flush();
       for (int w = ln; w < SEGW; w += 64) bits[wv * SEGW + w] = 0u;
     };
-    // cnt entries from (sc, sv) to (dc, dv), 4 loads in flight per lane
+    // cnt entries from (sc, sv) to (dc, dv), 8 loads in flight per lane
     auto copy_entries = [&](const int32_t* sc, const V* sv, int32_t* dc, V* dv, int32_t cnt) {
-      for (int32_t e0 = tid; e0 < cnt; e0 += 4 * DENSE_WG) {
-        int32_t cc[4];
-        V vv[4];
+      for (int32_t e0 = tid; e0 < cnt; e0 += 8 * DENSE_WG) {
+        int32_t cc[8];
+        V vv[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           const int32_t e = e0 + u * DENSE_WG;
           cc[u] = e < cnt ? sc[e] : 0;
           vv[u] = e < cnt ? sv[e] : V(0);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
           const int32_t e = e0 + u * DENSE_WG;
           if (e < cnt) {
             dc[e] = cc[u];
