@@ -81,7 +81,8 @@ static hipEvent_t take_event(Ctx* c) {
   return e;
 }
 
-bool ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop) {
+bool ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop,
+                      hipStream_t on) {
   if (!c->timing_phase.empty() && c->timing_phase != name) {
     *start = *stop = nullptr;
     return false;
@@ -91,15 +92,24 @@ bool ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start,
   t.bytes = bytes;
   t.start = take_event(c);
   t.stop = take_event(c);
-  DSG_HIP(hipEventRecord(t.start, c->stream));
+  DSG_HIP(hipEventRecord(t.start, on ? on : c->stream));
   *start = t.start;
   *stop = t.stop;
   c->timings.push_back(t);
   return true;
 }
 
-void ctx_timing_end(Ctx* c, hipEvent_t stop) {
-  if (stop) DSG_HIP(hipEventRecord(stop, c->stream));
+void ctx_timing_end(Ctx* c, hipEvent_t stop, hipStream_t on) {
+  if (stop) DSG_HIP(hipEventRecord(stop, on ? on : c->stream));
+}
+
+hipStream_t ctx_side_stream(Ctx* c) {
+  if (!c->side) {
+    DSG_HIP(hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming));
+    DSG_HIP(hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming));
+    DSG_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  }
+  return c->side;
 }
 
 static void clear_timings(Ctx* c) {
@@ -261,6 +271,12 @@ extern "C" dsg_status dsg_ctx_destroy(dsg_ctx* ctx) {
   ctx_free(&c, c.scratch, c.scratch_bytes);
   ctx_free(&c, c.scratch2, c.scratch2_bytes);
   if (c.pinned) (void)hipHostFree(c.pinned);
+  if (c.side) {
+    (void)hipStreamSynchronize(c.side);
+    (void)hipStreamDestroy(c.side);
+  }
+  if (c.fork_ev) (void)hipEventDestroy(c.fork_ev);
+  if (c.join_ev) (void)hipEventDestroy(c.join_ev);
   if (c.own_stream) (void)hipStreamDestroy(c.stream);
   delete ctx;
   return DSG_OK;

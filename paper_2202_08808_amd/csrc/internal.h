@@ -113,6 +113,10 @@ struct Ctx {
   size_t scratch_bytes = 0;
   void* scratch2 = nullptr;
   size_t scratch2_bytes = 0;
+  // second stream (default priority) for the short row bins, which run beside
+  // the long ones; created on first use, joined back through the two events
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 };
 
 void* ctx_alloc(Ctx* c, size_t bytes);
@@ -122,8 +126,12 @@ void* ctx_scratch2(Ctx* c, size_t bytes);
 void ctx_sync(Ctx* c);
 // Records a phase's start unless a phase filter excludes it (then both
 // events are null and false is returned); ctx_timing_end ignores a null event.
-bool ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop);
-void ctx_timing_end(Ctx* c, hipEvent_t stop);
+// Both record on stream `on` (nullptr: the context's stream).
+bool ctx_timing_begin(Ctx* c, const char* name, double bytes, hipEvent_t* start, hipEvent_t* stop,
+                      hipStream_t on = nullptr);
+void ctx_timing_end(Ctx* c, hipEvent_t stop, hipStream_t on = nullptr);
+// The side stream and its fork/join events, created on first use.
+hipStream_t ctx_side_stream(Ctx* c);
 
 // Bump allocator for device scratch carved out of one allocation.
 struct Carve {

@@ -1664,15 +1664,34 @@ const char* kBinNames[NBINS] = {"rows_g8",   "rows_g16",  "rows_g32",   "rows_g6
 template <int SR>
 void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, const unsigned long long* d_counts,
                  const Plan* plan, int64_t nrows, std::vector<std::pair<int, size_t>>& timed) {
-  hipStream_t s = c->stream;
   const int64_t cus = c->num_cus;
+  // With the bin sizes known, the bins of lane groups up to 256 lanes, whose
+  // launches are short and mostly latency, run on a second stream beside the
+  // longer bins: they finish while the 512- and 1024-lane groups run, before
+  // the persistent dense workgroups take every CU.  The bins touch disjoint
+  // rows and share only atomically claimed pools and counters.
+  constexpr int SIDE_BINS = 6;
+  bool split = false;
+  if (plan) {
+    int64_t small = 0, large = 0;
+    for (int b = 0; b < NBINS; ++b) (b < SIDE_BINS ? small : large) += (int64_t)plan->bin_count[b];
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    DSG_HIP(hipStreamIsCapturing(c->stream, &cap));
+    split = small > 0 && large > 0 && cap == hipStreamCaptureStatusNone;
+  }
+  if (split) {
+    hipStream_t side = ctx_side_stream(c);
+    DSG_HIP(hipEventRecord(c->fork_ev, c->stream));
+    DSG_HIP(hipStreamWaitEvent(side, c->fork_ev, 0));
+  }
   for (int b = 0; b < NBINS; ++b) {
     const int64_t cnt = plan ? (int64_t)plan->bin_count[b] : nrows;
     if (cnt == 0) continue;
+    const hipStream_t s = split && b < SIDE_BINS ? c->side : c->stream;
     const int32_t* list = bins + (int64_t)b * stride;
     const unsigned long long* dc = d_counts + b;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing && plan && ctx_timing_begin(c, kBinNames[b], 0.0, &e0, &e1))
+    if (c->timing && plan && ctx_timing_begin(c, kBinNames[b], 0.0, &e0, &e1, s))
       timed.push_back({b, c->timings.size() - 1});
     switch (b) {
 #define GROUP_CASE(B, G, WG)                                                                              \
@@ -1703,7 +1722,11 @@ void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, 
         break;
       }
     }
-    if (c->timing && plan) ctx_timing_end(c, e1);
+    if (c->timing && plan) ctx_timing_end(c, e1, s);
+  }
+  if (split) {
+    DSG_HIP(hipEventRecord(c->join_ev, c->side));
+    DSG_HIP(hipStreamWaitEvent(c->stream, c->join_ev, 0));
   }
   DSG_HIP(hipGetLastError());
 }
