@@ -1481,14 +1481,20 @@ struct Plan {
   unsigned long long flops;         // products the affected rows take
 };
 
-// longest rows first: key = (2^20 - 1) - min(flops, 2^20 - 1)
-constexpr int FLOP_KEY_BITS = 20;
+// longest rows first, to within 1/8: the key is 255 minus a log-scale bucket
+// of the row's products (the exponent and the next three bits), so that one
+// 8-bit radix pass orders the dense rows
+constexpr int FLOP_KEY_BITS = 8;
+__device__ inline uint32_t flop_bucket(int32_t f) {
+  if (f < 8) return (uint32_t)max(f, 0);
+  const int e = 31 - __clz(f);  // 3..30
+  return (uint32_t)((e - 2) * 8 + ((f >> (e - 3)) & 7));  // 8..231, monotone in f
+}
 __global__ void k_flop_keys(const int32_t* list, int32_t n, const int32_t* flq, uint64_t* keys, uint32_t* vals) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) {
     const int32_t q = list[t];
-    const int32_t f = min(flq[q], (1 << FLOP_KEY_BITS) - 1);
-    keys[t] = (uint64_t)(((1 << FLOP_KEY_BITS) - 1) - f);
+    keys[t] = (uint64_t)(255u - flop_bucket(flq[q]));
     vals[t] = (uint32_t)q;
   }
 }
@@ -1658,36 +1664,17 @@ int dense_passes_for(int vsz, int32_t ncols) {
 const char* kBinNames[NBINS] = {"rows_g8",   "rows_g16",  "rows_g32",   "rows_g64",   "rows_g128",
                                 "rows_g256", "rows_g512", "rows_g1024", "rows_dense", "rows_global"};
 
-// Launch every non-empty bin.  plan == nullptr (graph mode): bin sizes are
-// only on the device, so every bin is launched with a persistent grid that
-// reads its count from d_counts.
+// Launch the non-empty bins in [lo, hi) on stream s.  plan == nullptr (graph
+// mode): bin sizes are only on the device, so every bin is launched with a
+// persistent grid that reads its count from d_counts.
 template <int SR>
 void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, const unsigned long long* d_counts,
-                 const Plan* plan, int64_t nrows, std::vector<std::pair<int, size_t>>& timed) {
+                 const Plan* plan, int64_t nrows, std::vector<std::pair<int, size_t>>& timed, int lo, int hi,
+                 hipStream_t s) {
   const int64_t cus = c->num_cus;
-  // With the bin sizes known, the bins of lane groups up to 256 lanes, whose
-  // launches are short and mostly latency, run on a second stream beside the
-  // longer bins: they finish while the 512- and 1024-lane groups run, before
-  // the persistent dense workgroups take every CU.  The bins touch disjoint
-  // rows and share only atomically claimed pools and counters.
-  constexpr int SIDE_BINS = 6;
-  bool split = false;
-  if (plan) {
-    int64_t small = 0, large = 0;
-    for (int b = 0; b < NBINS; ++b) (b < SIDE_BINS ? small : large) += (int64_t)plan->bin_count[b];
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    DSG_HIP(hipStreamIsCapturing(c->stream, &cap));
-    split = small > 0 && large > 0 && cap == hipStreamCaptureStatusNone;
-  }
-  if (split) {
-    hipStream_t side = ctx_side_stream(c);
-    DSG_HIP(hipEventRecord(c->fork_ev, c->stream));
-    DSG_HIP(hipStreamWaitEvent(side, c->fork_ev, 0));
-  }
-  for (int b = 0; b < NBINS; ++b) {
+  for (int b = lo; b < hi; ++b) {
     const int64_t cnt = plan ? (int64_t)plan->bin_count[b] : nrows;
     if (cnt == 0) continue;
-    const hipStream_t s = split && b < SIDE_BINS ? c->side : c->stream;
     const int32_t* list = bins + (int64_t)b * stride;
     const unsigned long long* dc = d_counts + b;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1723,10 +1710,6 @@ void launch_bins(Ctx* c, const RowArgs& R, const int32_t* bins, int32_t stride, 
       }
     }
     if (c->timing && plan) ctx_timing_end(c, e1, s);
-  }
-  if (split) {
-    DSG_HIP(hipEventRecord(c->join_ev, c->side));
-    DSG_HIP(hipStreamWaitEvent(c->stream, c->join_ev, 0));
   }
   DSG_HIP(hipGetLastError());
 }
@@ -2021,16 +2004,64 @@ void launch_front(DProd* p, int mode, ProdWork& w, const RowArgs& R) {
   }
 }
 
+void launch_bin_range(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
+                      std::vector<std::pair<int, size_t>>& timed, int lo, int hi, hipStream_t s) {
+  Ctx* c = p->ctx;
+  const int32_t n = p->A->nrows;
+  switch (p->A->sr) {
+    case 0: launch_bins<0>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed, lo, hi, s); break;
+    case 1: launch_bins<1>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed, lo, hi, s); break;
+    case 2: launch_bins<2>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed, lo, hi, s); break;
+    default: launch_bins<3>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed, lo, hi, s); break;
+  }
+}
+
+// With the bin sizes known, bins [0, hi) may run on a second stream beside
+// bins [hi, NBINS): the short lane-group launches are mostly latency.  The
+// bins touch disjoint rows and share only atomically claimed pools and
+// counters.  Not under graph capture.
+bool side_split(Ctx* c, const Plan* plan, int hi) {
+  if (!plan) return false;
+  int64_t lo_rows = 0, hi_rows = 0;
+  for (int b = 0; b < NBINS; ++b) (b < hi ? lo_rows : hi_rows) += (int64_t)plan->bin_count[b];
+  if (lo_rows == 0 || hi_rows == 0) return false;
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  DSG_HIP(hipStreamIsCapturing(c->stream, &cap));
+  return cap == hipStreamCaptureStatusNone;
+}
+
+void zero_arena_top(DProd* p) {
+  if (p->arena_top) hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, p->ctx->stream, p->arena_top, 1);
+}
+
+// bins [0, hi) on the side stream, after everything queued so far on the
+// context's stream; join_side makes the context's stream wait for them
+void fork_side(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
+               std::vector<std::pair<int, size_t>>& timed, int hi) {
+  Ctx* c = p->ctx;
+  hipStream_t side = ctx_side_stream(c);
+  DSG_HIP(hipEventRecord(c->fork_ev, c->stream));
+  DSG_HIP(hipStreamWaitEvent(side, c->fork_ev, 0));
+  launch_bin_range(p, R, w, hplan, timed, 0, hi, side);
+  DSG_HIP(hipEventRecord(c->join_ev, side));
+}
+
+void join_side(Ctx* c) { DSG_HIP(hipStreamWaitEvent(c->stream, c->join_ev, 0)); }
+
+// Bins 0-5 (lane groups of up to 256 lanes) finish beside the 512- and
+// 1024-lane groups, before the persistent dense workgroups take every CU.
+constexpr int SIDE_BINS = 6;
+
 void launch_rows(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
                  std::vector<std::pair<int, size_t>>& timed) {
   Ctx* c = p->ctx;
-  const int32_t n = p->A->nrows;
-  if (p->arena_top) hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, c->stream, p->arena_top, 1);
-  switch (p->A->sr) {
-    case 0: launch_bins<0>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
-    case 1: launch_bins<1>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
-    case 2: launch_bins<2>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
-    default: launch_bins<3>(c, R, w.bins, n, w.plan->bin_count, hplan, n, timed); break;
+  zero_arena_top(p);
+  if (side_split(c, hplan, SIDE_BINS)) {
+    fork_side(p, R, w, hplan, timed, SIDE_BINS);
+    launch_bin_range(p, R, w, hplan, timed, SIDE_BINS, NBINS, c->stream);
+    join_side(c);
+  } else {
+    launch_bin_range(p, R, w, hplan, timed, 0, NBINS, c->stream);
   }
 }
 
