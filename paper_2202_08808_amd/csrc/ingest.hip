@@ -541,8 +541,12 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
 // rows taken in turn by a persistent grid.  The row's update columns go into
 // an LDS hash (in runs of HEAVY_SLOTS/2 updates when there are more), the row
 // is streamed once per run, and the outcomes are decided by all 8 waves.
+// The two 4096-slot tables (32 KB) leave room for HEAVY_PLAN_PER_CU
+// workgroups per CU: streaming a long row is latency-bound, and most heavy
+// rows are long rows with few updates (an apply of sums to a product's rows).
 constexpr int HEAVY_WG = 512;
-constexpr int HEAVY_SLOTS = 16384;
+constexpr int HEAVY_SLOTS = 4096;
+constexpr int HEAVY_PLAN_PER_CU = 4;
 
 template <int SR, int VSZ>
 __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* d_nR, uint64_t cmask,
@@ -836,9 +840,10 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
   hipStream_t s = c->stream;
   unsigned nb = blocks_for(n * 64, 256);
   const unsigned nh = (unsigned)std::max(1, c->num_cus);
+  const unsigned nph = nh * HEAVY_PLAN_PER_CU;
   hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
                      w.demand, G);
-  hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nh), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
+  hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
                      w.demand, G);
   if (!graph) {
     // the one host round trip: how much pool space moved rows need
@@ -861,7 +866,7 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
       if (G.nlost) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, G.nlost);
       hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
                          w.demand, G);
-      hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nh), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals,
+      hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals,
                          w.U, w.demand, G);
     }
   }
