@@ -286,13 +286,14 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
   }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
-  // stream the row once (4 loads in flight per lane) and find each slot's update
-  for (int32_t s0 = lane; s0 < len; s0 += 256) {
-    int32_t cc[4];
+  // stream the row once (PU loads in flight per lane) and find each slot's update
+  constexpr int PU = 8;
+  for (int32_t s0 = lane; s0 < len; s0 += 64 * PU) {
+    int32_t cc[PU];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) cc[v] = s0 + v * 64 < len ? m.col[off + s0 + v * 64] : -1;
+    for (int v = 0; v < PU; ++v) cc[v] = s0 + v * 64 < len ? m.col[off + s0 + v * 64] : -1;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
+    for (int v = 0; v < PU; ++v) {
       if (cc[v] < 0) continue;
       int32_t u;
       if (in_lds) {
@@ -840,7 +841,7 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
   hipStream_t s = c->stream;
   unsigned nb = blocks_for(n * 64, 256);
   const unsigned nh = (unsigned)std::max(1, c->num_cus);
-  const unsigned nph = nh * HEAVY_PLAN_PER_CU;
+  const unsigned nph = nh * HEAVY_PLAN_PER_CU;  // the heavy commit takes the same grid
   hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
                      w.demand, G);
   hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
@@ -873,7 +874,7 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
   // (graph mode: the caller reserved the worst case, see apply_headroom)
   hipLaunchKernelGGL((k_commit<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, cbits, w.U,
                      (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, n, w.err);
-  hipLaunchKernelGGL((k_commit_heavy<SR, VSZ>), dim3(nh), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.U,
+  hipLaunchKernelGGL((k_commit_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.U,
                      (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, n, w.err);
 }
 
