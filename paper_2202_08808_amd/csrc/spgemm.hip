@@ -1799,7 +1799,9 @@ void ensure_arena(DProd* p, size_t bytes) {
 // ---------------------------------------------------------------------------
 
 constexpr int BSPLIT_MAXP = 8;
-constexpr int BSPLIT_UNR = 8;  // loads in flight per lane (hub rows)
+constexpr int BSPLIT_UNR = 8;     // loads in flight per lane (hub rows)
+constexpr int BSPLIT_LONG = 2048; // longer rows are split by a workgroup each (k_bsplit_long)
+constexpr int BSPLIT_WG = 512;
 
 // One wavefront per row of B: the row's entries, grouped by column chunk,
 // into the copy at the row's own pool offset (tombstones left out), and the
@@ -1816,6 +1818,7 @@ __global__ __launch_bounds__(256) void k_bsplit(const int64_t* b_off, const int3
   if (k >= n) return;
   const int64_t off = b_off[k];
   const int32_t len = b_len[k];
+  if (len > BSPLIT_LONG) return;  // k_bsplit_long
   const uint64_t lt = ln ? (~0ull >> (64 - ln)) : 0ull;
   int64_t o[BSPLIT_MAXP];
 #pragma unroll
@@ -1878,6 +1881,97 @@ __global__ __launch_bounds__(256) void k_bsplit(const int64_t* b_off, const int3
   }
 }
 
+// Rows longer than BSPLIT_LONG (hub rows, which one wavefront walks in
+// many dependent rounds): one workgroup per row, taken in turn by a
+// persistent grid.  Each wavefront counts and places one contiguous segment
+// of the row; a chunk holds the segments' entries in segment order, so the
+// order inside a chunk is the row's order, as in k_bsplit.
+template <int VSZ>
+__global__ __launch_bounds__(BSPLIT_WG) void k_bsplit_long(const int64_t* b_off, const int32_t* b_len,
+                                                           const int32_t* b_col, const void* b_val, int32_t n, int P,
+                                                           int chbits, int64_t* bs, int32_t* out_col,
+                                                           void* out_val) {
+  using W = typename std::conditional<VSZ == 8, uint64_t, uint32_t>::type;
+  constexpr int NW = BSPLIT_WG / 64;
+  __shared__ int64_t wcnt[NW][BSPLIT_MAXP];
+  const int tid = threadIdx.x, ln = tid & 63, wv = tid >> 6;
+  const uint64_t lt = ln ? (~0ull >> (64 - ln)) : 0ull;
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const int32_t len = b_len[k];
+    if (len <= BSPLIT_LONG) continue;  // the same for the whole workgroup
+    const int64_t off = b_off[k];
+    const int32_t seg = (len + NW - 1) / NW;
+    const int32_t s0 = min(len, wv * seg), s1 = min(len, s0 + seg);
+    int64_t o[BSPLIT_MAXP];
+#pragma unroll
+    for (int q = 0; q < BSPLIT_MAXP; ++q) o[q] = 0;
+    for (int32_t e0 = s0; e0 < s1; e0 += 64 * BSPLIT_UNR) {  // count this wavefront's segment
+      int part[BSPLIT_UNR];
+#pragma unroll
+      for (int v = 0; v < BSPLIT_UNR; ++v) {
+        const int32_t e = e0 + v * 64 + ln;
+        part[v] = e < s1 ? (b_col[off + e] >> chbits) : -1;
+      }
+#pragma unroll
+      for (int v = 0; v < BSPLIT_UNR; ++v)
+#pragma unroll
+        for (int q = 0; q < BSPLIT_MAXP; ++q)
+          if (q < P) o[q] += __popcll(__ballot(part[v] == q));
+    }
+    if (ln == 0) {
+#pragma unroll
+      for (int q = 0; q < BSPLIT_MAXP; ++q) wcnt[wv][q] = o[q];
+    }
+    __syncthreads();
+    // chunk q starts after chunks 0..q-1; this segment's part of chunk q
+    // after the earlier segments' parts
+    int64_t run = off;
+#pragma unroll
+    for (int q = 0; q < BSPLIT_MAXP; ++q) {
+      if (q < P) {
+        int64_t tot = 0, before = 0;
+        for (int w = 0; w < NW; ++w) {
+          const int64_t c = wcnt[w][q];
+          tot += c;
+          if (w < wv) before += c;
+        }
+        if (tid == 0) bs[k * (P + 1) + q] = run;
+        o[q] = run + before;
+        run += tot;
+      }
+    }
+    if (tid == 0) bs[k * (P + 1) + P] = run;
+    for (int32_t e0 = s0; e0 < s1; e0 += 64 * BSPLIT_UNR) {  // place
+      int32_t col[BSPLIT_UNR];
+      W val[BSPLIT_UNR];
+#pragma unroll
+      for (int v = 0; v < BSPLIT_UNR; ++v) {
+        const int32_t e = e0 + v * 64 + ln;
+        col[v] = e < s1 ? b_col[off + e] : -1;
+        val[v] = e < s1 ? ((const W*)b_val)[off + e] : W(0);
+      }
+#pragma unroll
+      for (int v = 0; v < BSPLIT_UNR; ++v) {
+        const int part = col[v] >= 0 ? (col[v] >> chbits) : -1;
+        int64_t dst = -1;
+#pragma unroll
+        for (int q = 0; q < BSPLIT_MAXP; ++q) {
+          if (q < P) {
+            const uint64_t m = __ballot(part == q);
+            if (part == q) dst = o[q] + __popcll(m & lt);
+            o[q] += __popcll(m);
+          }
+        }
+        if (dst >= 0) {
+          out_col[dst] = col[v];
+          ((W*)out_val)[dst] = val[v];
+        }
+      }
+    }
+    __syncthreads();  // wcnt is reused by the next row
+  }
+}
+
 size_t round256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Build the split copy of B for this update (when the dense bin needs more
@@ -1911,12 +2005,19 @@ void build_bsplit(DProd* p) {
   int32_t* ocol = (int32_t*)((char*)p->bsp + col_off);
   void* oval = (char*)p->bsp + val_off;
   const unsigned nb = (unsigned)blocks_for((int64_t)B->nrows * 64, 256);
-  if (vsz == 8)
+  // long rows first, a workgroup each (four per CU), then the rest
+  const unsigned nl = (unsigned)std::min<int64_t>(B->nrows, (int64_t)c->num_cus * 4);
+  if (vsz == 8) {
+    hipLaunchKernelGGL(k_bsplit_long<8>, dim3(nl), dim3(BSPLIT_WG), 0, s, B->row_off, B->row_len, B->col, B->val,
+                       B->nrows, P, chbits, bs, ocol, oval);
     hipLaunchKernelGGL(k_bsplit<8>, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->val, B->nrows,
                        P, chbits, bs, ocol, oval);
-  else
+  } else {
+    hipLaunchKernelGGL(k_bsplit_long<4>, dim3(nl), dim3(BSPLIT_WG), 0, s, B->row_off, B->row_len, B->col, B->val,
+                       B->nrows, P, chbits, bs, ocol, oval);
     hipLaunchKernelGGL(k_bsplit<4>, dim3(nb), dim3(256), 0, s, B->row_off, B->row_len, B->col, B->val, B->nrows,
                        P, chbits, bs, ocol, oval);
+  }
   DSG_HIP(hipGetLastError());
   if (c->timing) ctx_timing_end(c, e1);
   p->bsp_col_off = col_off;
