@@ -2143,7 +2143,13 @@ void fork_side(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
   hipStream_t side = ctx_side_stream(c);
   DSG_HIP(hipEventRecord(c->fork_ev, c->stream));
   DSG_HIP(hipStreamWaitEvent(side, c->fork_ev, 0));
-  launch_bin_range(p, R, w, hplan, timed, 0, hi, side);
+  try {
+    launch_bin_range(p, R, w, hplan, timed, 0, hi, side);
+  } catch (...) {
+    (void)hipEventRecord(c->join_ev, side);
+    (void)hipStreamWaitEvent(c->stream, c->join_ev, 0);
+    throw;
+  }
   DSG_HIP(hipEventRecord(c->join_ev, side));
 }
 
@@ -2159,7 +2165,12 @@ void launch_rows(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
   zero_arena_top(p);
   if (side_split(c, hplan, SIDE_BINS)) {
     fork_side(p, R, w, hplan, timed, SIDE_BINS);
-    launch_bin_range(p, R, w, hplan, timed, SIDE_BINS, NBINS, c->stream);
+    try {
+      launch_bin_range(p, R, w, hplan, timed, SIDE_BINS, NBINS, c->stream);
+    } catch (...) {
+      join_side(c);  // later work on the context's stream still waits for the side bins
+      throw;
+    }
     join_side(c);
   } else {
     launch_bin_range(p, R, w, hplan, timed, 0, NBINS, c->stream);
