@@ -168,9 +168,15 @@ def bench_batched(args):
             t_batch.append(dt_batch)
         log(f"[bench] round {r}: plain loop {dt_plain * 1e3:.2f} ms, batched {dt_batch * 1e3:.2f} ms, "
             f"{sum(counts)} rows reported")
-    # the two copies must agree (spot check: every instance's row count)
+    # the two copies must agree bit for bit: canonical row pointers, columns
+    # and value bits of every instance's C (one instance at a time on the host)
     for t in range(len(desc)):
-        assert plain[t][1].nnz() == batched[t][1].nnz(), f"instance {t} differs"
+        x, y = plain[t][1].export(), batched[t][1].export()
+        same = (np.array_equal(x.row_ptr, y.row_ptr) and np.array_equal(x.col, y.col)
+                and np.ascontiguousarray(x.val).tobytes() == np.ascontiguousarray(y.val).tobytes())
+        assert same, f"instance {t}: batched C differs from the plain loop's"
+        del x, y
+    log(f"[bench] all {len(desc)} instances: batched C equals the plain loop's bit for bit")
     info = B.info()
     tp, tb = float(np.sum(t_plain)), float(np.sum(t_batch))
     out = {

@@ -302,8 +302,11 @@ typedef struct {
 } dsg_update_set;
 
 /* Create a batched executor over nprod products of ctx.  The products must
- * not share operands (each instance is independent); they and their
- * operands stay alive until dsg_batch_destroy.  DSG_E_STATE otherwise. */
+ * not share operands (each instance is independent): a product may name one
+ * matrix as both operands (C = A A), but no matrix may belong to two entries
+ * of the list, so neither two products over one matrix nor one product
+ * listed twice are accepted (DSG_E_STATE).  The products and their operands
+ * stay alive until dsg_batch_destroy. */
 dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int32_t nprod, dsg_batch** out);
 
 /* Apply nsets update sets (each to a distinct operand of one of the batch's

@@ -821,14 +821,19 @@ extern "C" dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int
   if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
   if (!out || (nprod > 0 && !prods) || nprod < 0) return fail(ctx, DSG_E_ARG, "bad arguments");
   *out = nullptr;
+  // Every matrix belongs to one product only: a product may name one matrix
+  // twice (C = A A), but no matrix -- and so no product -- may appear in two
+  // entries of the list, since each matrix takes its updates inside its own
+  // product's chain.
   std::vector<DMat*> seen;
   for (int32_t i = 0; i < nprod; ++i) {
     if (!prods[i] || prods[i]->owner != ctx) return fail(ctx, DSG_E_STATE, "product of another context");
-    for (DMat* m : {prods[i]->p->src_a, prods[i]->p->src_b}) {
-      if (std::find(seen.begin(), seen.end(), m) != seen.end() && !(m == prods[i]->p->src_b && m == prods[i]->p->src_a))
+    DMat* mine[2] = {prods[i]->p->src_a, prods[i]->p->src_b};
+    for (DMat* m : mine)
+      if (std::find(seen.begin(), seen.end(), m) != seen.end())
         return fail(ctx, DSG_E_STATE, "products of a batch must not share operands");
-      seen.push_back(m);
-    }
+    seen.push_back(mine[0]);
+    if (mine[1] != mine[0]) seen.push_back(mine[1]);
   }
   API_BEGIN(ctx)
   set_device(ctx);

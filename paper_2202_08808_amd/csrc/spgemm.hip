@@ -1631,9 +1631,12 @@ __global__ void k_reset_bins(Plan* plan) {
   }
 }
 
-// C now reflects the operands' current epochs -- unless rows still wait for room
-__global__ void k_set_sync(uint32_t* sync, const uint32_t* ea, const uint32_t* eb, const Plan* plan) {
-  if (plan->c_short || plan->arena_short) return;
+// C now reflects the operands' current epochs -- unless rows still wait for
+// room or a row kernel failed (then the rows it skipped stay affected, and the
+// next update recomputes them)
+__global__ void k_set_sync(uint32_t* sync, const uint32_t* ea, const uint32_t* eb, const Plan* plan,
+                           const int* err) {
+  if (plan->c_short || plan->arena_short || *err != 0) return;
   sync[0] = *ea;
   sync[1] = *eb;
 }
@@ -2179,7 +2182,7 @@ void launch_rows(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
 
 void launch_set_sync(DProd* p, ProdWork& w) {
   hipLaunchKernelGGL(k_set_sync, dim3(1), dim3(1), 0, p->ctx->stream, p->d_sync, (const uint32_t*)p->A->d_epoch,
-                     (const uint32_t*)p->B->d_epoch, (const Plan*)w.plan);
+                     (const uint32_t*)p->B->d_epoch, (const Plan*)w.plan, (const int*)w.err);
 }
 
 // reported rows, statistics and (when the rows are complete) the epochs C

@@ -21,6 +21,18 @@ import scipy.sparse as sp
 import oracle
 from paper_2202_08808_amd import inputs as I
 
+# Threads of the oracle's product in every pin: 1 runs its plain loop over
+# rows, more runs the same loop split over OpenMP threads (the configuration
+# the GPU parity tests and the CPU baseline use), which the pins must hold
+# for as well.
+NTHREADS = 1
+
+
+def spgemm(*args, **kw):
+    kw.setdefault("nthreads", NTHREADS)
+    return oracle.spgemm(*args, **kw)
+
+
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 OPS = {"SET": 0, "DELETE": 1, "ADD": 2}
 U64 = (1 << 64)
@@ -117,7 +129,7 @@ def pin_golden_products(L):
         dt = oracle.DTYPE[sr]
         A = csr_from_entries(g["A"]["shape"], g["A"]["entries"], dt)
         B = A if g["B"] == "A" else csr_from_entries(g["B"]["shape"], g["B"]["entries"], dt)
-        C = oracle.spgemm(sr, A, B, L=L)
+        C = spgemm(sr, A, B, L=L)
         got = entries_of(C)
         want = {(i, j): v for i, j, v in g["C"]["entries"]}
         assert set(got) == set(want), (path, sorted(got), sorted(want))
@@ -171,7 +183,7 @@ def pin_dense_bruteforce(L, trials=6, seed=7):
             dens = [0.0, 0.15, 0.4, 1.0][t % 4]
             A = random_csr(rng, nr, nk, dens, sr, zeros=True)
             B = random_csr(rng, nk, nc, rng.choice([0.1, 0.3, 0.7]), sr, zeros=True)
-            got = entries_of(oracle.spgemm(sr, A, B, L=L))
+            got = entries_of(spgemm(sr, A, B, L=L))
             want = dense_bruteforce(sr, A, B)
             assert set(got) == set(want), (sr, t)
             for k in want:
@@ -192,7 +204,7 @@ def pin_minplus_two_walks(L, n=60, m=400, seed=11):
     for i, k, w1 in edges:
         for j, w2 in out_of.get(k, []):
             best[(i, j)] = min(best.get((i, j), np.inf), w1 + w2)
-    got = entries_of(oracle.spgemm(I.MIN_PLUS_F32, A, A, L=L))
+    got = entries_of(spgemm(I.MIN_PLUS_F32, A, A, L=L))
     assert set(got) == set(best)
     for k, v in best.items():
         assert got[k] == v, (k, got[k], v)
@@ -203,7 +215,7 @@ def pin_scipy_int64(L, seed=5):
     cancellation, so scipy keeps every structural entry)."""
     w = I.workload_rmat12_i64()
     A = oracle.Csr.of(w.A)
-    C = oracle.spgemm(I.PLUS_TIMES_I64, A, A, L=L)
+    C = spgemm(I.PLUS_TIMES_I64, A, A, L=L)
     S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.nrows, A.ncols))
     R = (S @ S).tocsr()
     R.sort_indices()
@@ -214,7 +226,7 @@ def pin_scipy_int64(L, seed=5):
     rng = np.random.default_rng(seed)
     A2 = random_csr(rng, 30, 50, 0.1, I.PLUS_TIMES_I64)
     B2 = random_csr(rng, 50, 20, 0.1, I.PLUS_TIMES_I64)
-    C2 = oracle.spgemm(I.PLUS_TIMES_I64, A2, B2, L=L)
+    C2 = spgemm(I.PLUS_TIMES_I64, A2, B2, L=L)
     D = (sp.csr_matrix((A2.val, A2.col, A2.row_ptr), shape=(30, 50)) @
          sp.csr_matrix((B2.val, B2.col, B2.row_ptr), shape=(50, 20))).toarray()
     Sa = sp.csr_matrix((np.ones(A2.nnz), A2.col, A2.row_ptr), shape=(30, 50))
@@ -241,7 +253,7 @@ def pin_numpy_fp64(L, seed=3):
     struct = ((Ad != 0).astype(int) @ (Bd != 0).astype(int)) > 0
     got = np.zeros_like(ref)
     have = np.zeros(ref.shape, bool)
-    for (i, j), v in entries_of(oracle.spgemm(I.PLUS_TIMES_F64, A, B, L=L)).items():
+    for (i, j), v in entries_of(spgemm(I.PLUS_TIMES_F64, A, B, L=L)).items():
         got[i, j] = v
         have[i, j] = True
     assert np.array_equal(have, struct)
@@ -259,7 +271,7 @@ def pin_stencil_closed_form(L, side=1024, sample=600, seed=2):
     ys = rng.integers(2, side - 2, sample)
     xs = rng.integers(2, side - 2, sample)
     rows = (ys * side + xs).astype(np.int32)
-    C = oracle.spgemm(I.PLUS_TIMES_I64, A, A, rows=rows, L=L)
+    C = spgemm(I.PLUS_TIMES_I64, A, A, rows=rows, L=L)
     for q in range(sample):
         r = int(rows[q])
         ry, rx = divmod(r, side)
@@ -275,7 +287,7 @@ def pin_stencil_small_boundary(L, side=8):
     keys = I.stencil9_keys(side)
     n = side * side
     A = oracle.Csr.of(I.csr_from_keys(n, n, keys, np.ones(keys.size, np.int64)))
-    got = entries_of(oracle.spgemm(I.PLUS_TIMES_I64, A, A, L=L))
+    got = entries_of(spgemm(I.PLUS_TIMES_I64, A, A, L=L))
     Ad = np.zeros((n, n), np.int64)
     for e in keys:
         Ad[e // n, e % n] = 1
@@ -290,7 +302,7 @@ def pin_int64_invariants(L):
     1^T C = (1^T A) A, and the structure of the boolean product."""
     w = I.workload_rmat12_i64()
     A = oracle.Csr.of(w.A)
-    C = oracle.spgemm(I.PLUS_TIMES_I64, A, A, L=L)
+    C = spgemm(I.PLUS_TIMES_I64, A, A, L=L)
     S = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.nrows, A.ncols))
     Cs = sp.csr_matrix((C.val, C.col, C.row_ptr), shape=(C.nrows, C.ncols))
     one = np.ones(A.nrows, np.int64)
@@ -304,7 +316,7 @@ def pin_minplus_invariants(L):
     """R-MAT scale 11 min-plus: row minima min_j c_ij = min_k (a_ik + min_j
     b_kj); values within [2, 200]; structure = boolean product."""
     A = oracle.Csr.of(I.rmat_csr(11, 16, I.MIN_PLUS_F32, stream=901, lo=1, hi=100))
-    C = oracle.spgemm(I.MIN_PLUS_F32, A, A, L=L)
+    C = spgemm(I.MIN_PLUS_F32, A, A, L=L)
     rowmin_B = np.full(A.nrows, np.inf)
     for k in range(A.nrows):
         if A.row_ptr[k + 1] > A.row_ptr[k]:
@@ -329,7 +341,7 @@ def pin_identity_and_relabel(L, seed=9):
         A = random_csr(rng, n, n, 0.2, sr)
         one = dt(0) if sr == I.MIN_PLUS_F32 else dt(1)   # multiplicative identity
         Id = csr_from_entries((n, n), [(i, i, one) for i in range(n)], dt)
-        for X in (oracle.spgemm(sr, A, Id, L=L), oracle.spgemm(sr, Id, A, L=L)):
+        for X in (spgemm(sr, A, Id, L=L), spgemm(sr, Id, A, L=L)):
             assert np.array_equal(X.row_ptr, A.row_ptr) and np.array_equal(X.col, A.col)
             assert same_bits(X.val, A.val)
     # relabelling commutes with the product (int64 exact)
@@ -341,8 +353,8 @@ def pin_identity_and_relabel(L, seed=9):
     def relabel(M):
         return csr_from_entries((n, n), [(perm[i], perm[j], v) for (i, j), v in entries_of(M).items()],
                                 np.int64)
-    C = entries_of(oracle.spgemm(sr, A, B, L=L))
-    Cp = entries_of(oracle.spgemm(sr, relabel(A), relabel(B), L=L))
+    C = entries_of(spgemm(sr, A, B, L=L))
+    Cp = entries_of(spgemm(sr, relabel(A), relabel(B), L=L))
     assert Cp == {(perm[i], perm[j]): v for (i, j), v in C.items()}
 
 
@@ -396,7 +408,7 @@ def pin_boolean_bit_slices(L, seed=12):
         wa[::7] = 0   # present entries whose every bit is clear
         A = oracle.Csr.of(I.csr_from_keys(nr, nk, ka, wa))
         B = oracle.Csr.of(I.csr_from_keys(nk, nc, kb, wb))
-        C = oracle.spgemm(sr, A, B, L=L)
+        C = spgemm(sr, A, B, L=L)
 
         def mat(M, data):
             return sp.csr_matrix((data, M.col, M.row_ptr), shape=(M.nrows, M.ncols)).toarray()
@@ -457,7 +469,7 @@ def pin_transpose(L, seed=13):
                                     oracle.DTYPE[sr])
         for X, Y, XY in ((oracle.transpose(A, L=L), B, (swapped(A), B)),
                          (A, oracle.transpose(B2, L=L), (A, swapped(B2)))):
-            got = entries_of(oracle.spgemm(sr, X, Y, L=L))
+            got = entries_of(spgemm(sr, X, Y, L=L))
             want = dense_bruteforce(sr, *XY)
             assert set(got) == set(want), t
             for k in want:

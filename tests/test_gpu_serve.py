@@ -244,3 +244,42 @@ def test_served_errors_and_ownership(ctx):
     P.update()
     P.destroy()
     m.destroy()
+
+
+@pytest.mark.timeout(600)
+def test_served_config5_scale(ctx):
+    """The serving workload at full size: Erdos-Renyi with 2^21 rows and mean
+    degree 8 (16.8M entries), C = A A over (min,+) resident in HBM, a Poisson
+    trace of update batches of floor(10^X) entries (X ~ N(3, 0.67) on [1, 5],
+    mix 50/25/25) and queries of 1..1024 rows.  Every query answer and the
+    final C equal the oracle's, both when the whole trace is queued at once
+    (continuous batching) and when each request runs alone, and the two runs
+    agree bit for bit."""
+    say("served at full size: ER 2^21")
+    n = 1 << 21
+    A = er(n, 501)
+    trace = I.serve_trace(A, SR, 24, 1e9, stream=681)
+    say(f"trace: {sum(r.kind == 'update' for r in trace)} updates "
+        f"({sum(len(r.batch.ops) for r in trace if r.kind == 'update')} entries), "
+        f"{sum(r.kind == 'query' for r in trace)} queries")
+    a = oracle.Csr.of(A)
+    want_answers = []
+    for r in trace:
+        if r.kind == "update":
+            b = r.batch
+            a, _ = oracle.apply(SR, a, b.rows, b.cols, b.vals, b.ops)
+        else:
+            want_answers.append(oracle.spgemm(SR, a, a, rows=r.rows, nthreads=THREADS))
+    want_C = oracle.spgemm(SR, a, a, nthreads=THREADS)
+    mix = run_served(ctx, A, trace, mem_budget=4 << 30)
+    say(f"mix: {mix[3]['update_groups']} update groups for {mix[3]['update_requests']} updates")
+    alone = run_served(ctx, A, trace, alone=True, mem_budget=4 << 30)
+    for name, (answers, C, results, stats) in (("mix", mix), ("alone", alone)):
+        assert all(r["status"] == dsg.OK for r in results), name
+        assert len(answers) == len(want_answers)
+        for k, (got, want) in enumerate(zip(answers, want_answers)):
+            assert_same_csr(SR, got, want, f"{name} query {k}")
+        assert_same_csr(SR, C, want_C, f"{name} final C")
+    for k, (x, y) in enumerate(zip(mix[0], alone[0])):
+        same_rows(x, y, f"query {k}")
+    same_rows(mix[1], alone[1], "final C")
