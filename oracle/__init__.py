@@ -50,6 +50,19 @@ def lib(path: str = LIB_PATH):
     L.orc_transpose.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int, P, P, P, P, P, P]
     L.orc_axpby.restype = ctypes.c_int64
     L.orc_axpby.argtypes = [ctypes.c_int, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P]
+    I32, I64 = ctypes.c_int32, ctypes.c_int64
+    L.orc_changed_entries.restype = ctypes.c_int
+    L.orc_changed_entries.argtypes = [I32, ctypes.c_int, P, P, P, P, P, P, P, P]
+    L.orc_bloom.restype = ctypes.c_int
+    L.orc_bloom.argtypes = [I32, I32, P, P, P, P, P, P, P]
+    L.orc_pattern.restype = ctypes.c_int
+    L.orc_pattern.argtypes = [I32, I32] + [P] * 13
+    L.orc_row_filter.restype = ctypes.c_int
+    L.orc_row_filter.argtypes = [I32] + [P] * 7
+    L.orc_masked_product.restype = ctypes.c_int
+    L.orc_masked_product.argtypes = [ctypes.c_int, I32, I32] + [P] * 12
+    L.orc_masked_merge.restype = ctypes.c_int
+    L.orc_masked_merge.argtypes = [I32, ctypes.c_int] + [P] * 10
     if path == LIB_PATH:
         _lib = L
     return L
@@ -157,3 +170,85 @@ def axpby(semiring: int, alpha, C, beta, X, L=None):
     if nnz < 0:
         raise ValueError("oracle axpby: bad arguments")
     return Csr(C.nrows, C.ncols, drp, dci[:nnz].copy(), dv[:nnz].copy())
+
+
+# ---- general updates filtered by a Bloom matrix (Section 5.2, Algorithm 2) ----
+
+BLOOM_L = 64
+
+
+def _two_phase(fn, nrows, args_before, dt=None, extra=None):
+    """Run a two-phase oracle function: row pointers, then columns (and values)."""
+    rp = np.zeros(nrows + 1, np.int64)
+    if fn(*args_before, _p(rp), None, *([None] * (extra or 0))) != 0:
+        raise ValueError("oracle: bad arguments")
+    nnz = int(rp[-1])
+    ci = np.zeros(max(nnz, 1), np.int32)
+    outs = [np.zeros(max(nnz, 1), d) for d in (dt or [])]
+    if fn(*args_before, _p(rp), _p(ci), *[_p(o) for o in outs]) != 0:
+        raise ValueError("oracle: bad arguments")
+    return rp, ci[:nnz], [o[:nnz] for o in outs]
+
+
+def changed_entries(A, A2, L=None):
+    """Structure of A*: entries present in exactly one of A, A', or in both with
+    different value bits (Section 5: deletions count as changed entries)."""
+    L = L or lib()
+    v, v2 = np.ascontiguousarray(A.val), np.ascontiguousarray(A2.val)
+    vs = v.dtype.itemsize
+    rp, ci, _ = _two_phase(L.orc_changed_entries, A.nrows,
+                           (A.nrows, vs, _p(A.row_ptr), _p(A.col), _p(v), _p(A2.row_ptr), _p(A2.col), _p(v2)))
+    return Csr(A.nrows, A.ncols, rp, ci, np.zeros(ci.size, np.uint8))
+
+
+def bloom(A, B, L=None):
+    """F for C = A B: C's structure; bit (k mod 64) of f_ij set iff a_ik and b_kj
+    are present (Section 5.2)."""
+    L = L or lib()
+    if A.ncols != B.nrows:
+        raise ValueError("shape mismatch")
+    rp, ci, (fv,) = _two_phase(L.orc_bloom, A.nrows,
+                               (A.nrows, B.ncols, _p(A.row_ptr), _p(A.col), _p(B.row_ptr), _p(B.col)),
+                               dt=[np.uint64], extra=1)
+    return Csr(A.nrows, B.ncols, rp, ci, fv)
+
+
+def general_update(semiring: int, A, A2, B, B2, C, F, L=None):
+    """One dynamic multiply with general updates, Algorithm 2 on one process.
+    A, B: operands before the batch; A2, B2 after; C = A B and F its Bloom
+    matrix.  Returns a dict with C2 (C'), F2 (F'), Cstar (C* with f*_ij as
+    values), R (r_i per row), Astar, Bstar (structures)."""
+    L = L or lib()
+    dt = DTYPE[semiring]
+    n, m = A.nrows, B.ncols
+    As = changed_entries(A, A2, L)
+    Bs = changed_entries(B, B2, L)
+    # computePattern
+    rp, ci, (fs,) = _two_phase(L.orc_pattern, n,
+                               (n, m, _p(A.row_ptr), _p(A.col), _p(As.row_ptr), _p(As.col), _p(A2.row_ptr),
+                                _p(A2.col), _p(Bs.row_ptr), _p(Bs.col), _p(B2.row_ptr), _p(B2.col)),
+                               dt=[np.uint64], extra=1)
+    Cs = Csr(n, m, rp, ci, fs)
+    # E, R
+    r = np.zeros(max(n, 1), np.uint64)
+    fv = np.ascontiguousarray(F.val, np.uint64)
+    if L.orc_row_filter(n, _p(Cs.row_ptr), _p(Cs.col), _p(Cs.val), _p(F.row_ptr), _p(F.col), _p(fv), _p(r)) != 0:
+        raise ValueError("oracle: bad arguments")
+    r = r[:n]
+    # Z, H = A^R B' masked at C*
+    nz = max(Cs.nnz, 1)
+    zv, zp, hv = np.zeros(nz, dt), np.zeros(nz, np.uint8), np.zeros(nz, np.uint64)
+    a2v, b2v = np.ascontiguousarray(A2.val, dt), np.ascontiguousarray(B2.val, dt)
+    if L.orc_masked_product(semiring, n, m, _p(A2.row_ptr), _p(A2.col), _p(a2v), _p(r), _p(B2.row_ptr),
+                            _p(B2.col), _p(b2v), _p(Cs.row_ptr), _p(Cs.col), _p(zv), _p(zp), _p(hv)) != 0:
+        raise ValueError("oracle: bad arguments")
+
+    def merge(X, vals, dtype):
+        xv = np.ascontiguousarray(X.val, dtype)
+        rp2, ci2, (ov,) = _two_phase(L.orc_masked_merge, n,
+                                     (n, np.dtype(dtype).itemsize, _p(X.row_ptr), _p(X.col), _p(xv),
+                                      _p(Cs.row_ptr), _p(Cs.col), _p(vals), _p(zp)),
+                                     dt=[dtype], extra=1)
+        return Csr(n, m, rp2, ci2, ov)
+    return {"C2": merge(C, zv, dt), "F2": merge(F, hv, np.uint64), "Cstar": Cs, "R": r,
+            "Astar": As, "Bstar": Bs, "Z": zv[:Cs.nnz], "Zp": zp[:Cs.nnz], "H": hv[:Cs.nnz]}

@@ -373,3 +373,257 @@ int64_t orc_axpby(int sr, int32_t nrows, const void* alpha,
   }
   return out;
 }
+
+/* ---- general updates filtered by a Bloom matrix (Section 5.2, Algorithm 2)
+ *
+ * One process holds every block, so the algorithm's broadcasts, sends and
+ * aggregations over the process grid are the identity here; what remains is
+ * its local arithmetic, step by step in the algorithm's order:
+ *   computePattern   C* = A* B' + A B* (Eq. 1) as a structure, and F* with
+ *                    bit (k mod l) of f*_ij set when a*_ik b'_kj or
+ *                    a'_ik b*_kj is a term of c*_ij;
+ *   E                F (+) F* (bitwise or), masked at C*;
+ *   R                the bitwise or of E over each row;
+ *   A^R              A' keeping, in row i, the columns k with bit (k mod l)
+ *                    of r_i set;
+ *   Z, H             A^R B' masked at C*: for (i,j) in C*, z_ij is the
+ *                    semiring sum over those k (ascending) with b'_kj present
+ *                    and h_ij the Bloom bits of those k;
+ *   merge            C' = C outside C*, z_ij on C* where some term exists,
+ *                    no entry where none does; F' likewise from F and H.
+ * F is the Bloom matrix of C = A B: on C's structure, bit (k mod l) of f_ij
+ * is set iff a_ik and b_kj are both present.  l = 64, the width the paper
+ * uses.  A* (and B*) mark the changed entries: present in exactly one of A
+ * and A', or in both with different value bits (deletions included). */
+
+#define ORC_BLOOM_L 64
+
+static uint64_t bloom_bit(int32_t k) { return (uint64_t)1 << ((uint32_t)k % ORC_BLOOM_L); }
+
+/* Structure of the changed entries between two sorted CSR matrices of the
+ * same shape (values of vs bytes).  Two phases as orc_spgemm: srp only when
+ * sci == NULL, then sci. */
+int orc_changed_entries(int32_t nrows, int vs,
+                        const int64_t* rp, const int32_t* ci, const void* v,
+                        const int64_t* rp2, const int32_t* ci2, const void* v2,
+                        int64_t* srp, int32_t* sci) {
+  if (nrows < 0 || vs <= 0) return -1;
+  if (sci == NULL) srp[0] = 0;
+  for (int32_t i = 0; i < nrows; ++i) {
+    int64_t a = rp[i], b = rp2[i], n = 0;
+    while (a < rp[i + 1] || b < rp2[i + 1]) {
+      int32_t j;
+      int changed;
+      if (b >= rp2[i + 1] || (a < rp[i + 1] && ci[a] < ci2[b])) {
+        j = ci[a++]; changed = 1;                           /* deleted */
+      } else if (a >= rp[i + 1] || ci2[b] < ci[a]) {
+        j = ci2[b++]; changed = 1;                          /* inserted */
+      } else {
+        j = ci[a];                                          /* in both: compare value bits */
+        changed = memcmp((const char*)v + (size_t)vs * (size_t)a,
+                         (const char*)v2 + (size_t)vs * (size_t)b, (size_t)vs) != 0;
+        ++a; ++b;
+      }
+      if (!changed) continue;
+      if (sci) sci[srp[i] + n] = j;
+      ++n;
+    }
+    if (sci == NULL) srp[i + 1] = srp[i] + n;
+  }
+  return 0;
+}
+
+/* Bloom matrix F of C = A B (structures only): frp / fci are C's structure,
+ * fv[e] the bits of the k's contributing to that entry.  Two phases. */
+int orc_bloom(int32_t nrows, int32_t ncols,
+              const int64_t* arp, const int32_t* aci, const int64_t* brp, const int32_t* bci,
+              int64_t* frp, int32_t* fci, uint64_t* fv) {
+  if (nrows < 0 || ncols < 0) return -1;
+  size_t nc = (size_t)(ncols > 0 ? ncols : 1);
+  int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * nc);
+  uint64_t* bits = (uint64_t*)malloc(sizeof(uint64_t) * nc);
+  int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * nc);
+  if (!mark || !bits || !touched) { free(mark); free(bits); free(touched); return -1; }
+  for (size_t j = 0; j < nc; ++j) mark[j] = -1;
+  if (fci == NULL) frp[0] = 0;
+  for (int32_t i = 0; i < nrows; ++i) {
+    int64_t nt = 0;
+    for (int64_t ea = arp[i]; ea < arp[i + 1]; ++ea) {
+      int32_t k = aci[ea];
+      for (int64_t eb = brp[k]; eb < brp[k + 1]; ++eb) {
+        int32_t j = bci[eb];
+        if (mark[j] != i) { mark[j] = i; bits[j] = 0; touched[nt++] = j; }
+        bits[j] |= bloom_bit(k);
+      }
+    }
+    qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+    if (fci == NULL) {
+      frp[i + 1] = frp[i] + nt;
+    } else {
+      for (int64_t t = 0; t < nt; ++t) {
+        fci[frp[i] + t] = touched[t];
+        fv[frp[i] + t] = bits[touched[t]];
+      }
+    }
+  }
+  free(mark); free(bits); free(touched);
+  return 0;
+}
+
+/* computePattern: C* = A* B' + A B* as a structure, with F* (see above).
+ * A, A*, A' are nrows x ninner, B', B* ninner x ncols, all structures sorted
+ * by column.  Output: C* (csrp, csci) and fs[e] = f*_ij.  Two phases. */
+int orc_pattern(int32_t nrows, int32_t ncols,
+                const int64_t* arp, const int32_t* aci,       /* A  */
+                const int64_t* asrp, const int32_t* asci,     /* A* */
+                const int64_t* a2rp, const int32_t* a2ci,     /* A' */
+                const int64_t* bsrp, const int32_t* bsci,     /* B* */
+                const int64_t* b2rp, const int32_t* b2ci,     /* B' */
+                int64_t* csrp, int32_t* csci, uint64_t* fs) {
+  if (nrows < 0 || ncols < 0) return -1;
+  size_t nc = (size_t)(ncols > 0 ? ncols : 1);
+  int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * nc);   /* j holds an entry of C* in row i */
+  int32_t* seen = (int32_t*)malloc(sizeof(int32_t) * nc);   /* bits[j] belongs to row i */
+  uint64_t* bits = (uint64_t*)malloc(sizeof(uint64_t) * nc);
+  int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * nc);
+  if (!mark || !seen || !bits || !touched) { free(mark); free(seen); free(bits); free(touched); return -1; }
+  for (size_t j = 0; j < nc; ++j) mark[j] = seen[j] = -1;
+  if (csci == NULL) csrp[0] = 0;
+  for (int32_t i = 0; i < nrows; ++i) {
+    int64_t nt = 0;
+#define ORC_BITS(j, k) do { if (seen[j] != i) { seen[j] = i; bits[j] = 0; } bits[j] |= bloom_bit(k); } while (0)
+    /* A* B': pattern and bits */
+    for (int64_t e = asrp[i]; e < asrp[i + 1]; ++e) {
+      int32_t k = asci[e];
+      for (int64_t f = b2rp[k]; f < b2rp[k + 1]; ++f) {
+        int32_t j = b2ci[f];
+        if (mark[j] != i) { mark[j] = i; touched[nt++] = j; }
+        ORC_BITS(j, k);
+      }
+    }
+    /* A B*: pattern */
+    for (int64_t e = arp[i]; e < arp[i + 1]; ++e) {
+      int32_t k = aci[e];
+      for (int64_t f = bsrp[k]; f < bsrp[k + 1]; ++f) {
+        int32_t j = bsci[f];
+        if (mark[j] != i) { mark[j] = i; touched[nt++] = j; }
+      }
+    }
+    /* A' B*: bits */
+    for (int64_t e = a2rp[i]; e < a2rp[i + 1]; ++e) {
+      int32_t k = a2ci[e];
+      for (int64_t f = bsrp[k]; f < bsrp[k + 1]; ++f) ORC_BITS(bsci[f], k);
+    }
+#undef ORC_BITS
+    qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+    if (csci == NULL) {
+      csrp[i + 1] = csrp[i] + nt;
+    } else {
+      for (int64_t t = 0; t < nt; ++t) {
+        int32_t j = touched[t];
+        csci[csrp[i] + t] = j;
+        fs[csrp[i] + t] = seen[j] == i ? bits[j] : 0;
+      }
+    }
+  }
+  free(mark); free(seen); free(bits); free(touched);
+  return 0;
+}
+
+/* E and R: r_i = bitwise or over (i, j) in C* of f_ij | f*_ij, with f_ij = 0
+ * where C (structure frp / fci, bits fv) has no entry (i, j). */
+int orc_row_filter(int32_t nrows,
+                   const int64_t* csrp, const int32_t* csci, const uint64_t* fs,
+                   const int64_t* frp, const int32_t* fci, const uint64_t* fv,
+                   uint64_t* r) {
+  if (nrows < 0) return -1;
+  for (int32_t i = 0; i < nrows; ++i) {
+    uint64_t acc = 0;
+    int64_t f = frp[i];
+    for (int64_t e = csrp[i]; e < csrp[i + 1]; ++e) {
+      const int32_t j = csci[e];
+      uint64_t x = fs[e];                                   /* f*_ij */
+      while (f < frp[i + 1] && fci[f] < j) ++f;
+      if (f < frp[i + 1] && fci[f] == j) x |= fv[f];        /* f_ij */
+      acc |= x;                                             /* e_ij into r_i */
+    }
+    r[i] = acc;
+  }
+  return 0;
+}
+
+/* Z and H: A^R B' masked at C*.  For every entry e = (i, j) of C*: zp[e] = 1
+ * and zv[e] = the semiring sum, over k ascending in A' row i with bit
+ * (k mod l) of r_i set and b'_kj present, of a'_ik (x) b'_kj, and hv[e] the
+ * bits of those k; zp[e] = 0 and hv[e] = 0 where there is no such k. */
+int orc_masked_product(int sr, int32_t nrows, int32_t ncols,
+                       const int64_t* a2rp, const int32_t* a2ci, const void* a2v, const uint64_t* r,
+                       const int64_t* b2rp, const int32_t* b2ci, const void* b2v,
+                       const int64_t* csrp, const int32_t* csci,
+                       void* zv, uint8_t* zp, uint64_t* hv) {
+  const int vs = orc_value_size(sr);
+  if (vs == 0 || nrows < 0 || ncols < 0) return -1;
+  size_t nc = (size_t)(ncols > 0 ? ncols : 1);
+  int64_t* where = (int64_t*)malloc(sizeof(int64_t) * nc);  /* position in C* of (i, j), or -1 */
+  if (!where) return -1;
+  for (size_t j = 0; j < nc; ++j) where[j] = -1;
+  char p[8];
+  for (int32_t i = 0; i < nrows; ++i) {
+    for (int64_t e = csrp[i]; e < csrp[i + 1]; ++e) {
+      where[csci[e]] = e;
+      zp[e] = 0;
+      hv[e] = 0;
+    }
+    for (int64_t ea = a2rp[i]; ea < a2rp[i + 1]; ++ea) {    /* ascending k */
+      const int32_t k = a2ci[ea];
+      if (!(r[i] & bloom_bit(k))) continue;                 /* not in A^R */
+      const char* a = (const char*)a2v + (size_t)vs * (size_t)ea;
+      for (int64_t eb = b2rp[k]; eb < b2rp[k + 1]; ++eb) {
+        const int64_t e = where[b2ci[eb]];
+        if (e < 0) continue;                                /* masked out */
+        char* z = (char*)zv + (size_t)vs * (size_t)e;
+        sr_mul(sr, p, a, (const char*)b2v + (size_t)vs * (size_t)eb);
+        if (!zp[e]) { memcpy(z, p, (size_t)vs); zp[e] = 1; }
+        else sr_add(sr, z, z, p);
+        hv[e] |= bloom_bit(k);
+      }
+    }
+    for (int64_t e = csrp[i]; e < csrp[i + 1]; ++e) where[csci[e]] = -1;
+  }
+  free(where);
+  return 0;
+}
+
+/* Merge masked at C*: out = X outside C*; on C*, the entry z (present where
+ * zp) and no entry where !zp.  X: sorted CSR with values of vs bytes.  Two
+ * phases (orp only when oci == NULL). */
+int orc_masked_merge(int32_t nrows, int vs,
+                     const int64_t* xrp, const int32_t* xci, const void* xv,
+                     const int64_t* csrp, const int32_t* csci, const void* zv, const uint8_t* zp,
+                     int64_t* orp, int32_t* oci, void* ov) {
+  if (nrows < 0 || vs <= 0) return -1;
+  if (oci == NULL) orp[0] = 0;
+  for (int32_t i = 0; i < nrows; ++i) {
+    int64_t a = xrp[i], b = csrp[i], n = 0;
+    while (a < xrp[i + 1] || b < csrp[i + 1]) {
+      const void* src = NULL;
+      int32_t j;
+      if (b >= csrp[i + 1] || (a < xrp[i + 1] && xci[a] < csci[b])) {
+        j = xci[a]; src = (const char*)xv + (size_t)vs * (size_t)a; ++a;     /* outside C*: kept */
+      } else {
+        j = csci[b];
+        if (zp[b]) src = (const char*)zv + (size_t)vs * (size_t)b;         /* on C*: z, or nothing */
+        if (a < xrp[i + 1] && xci[a] == j) ++a;
+        ++b;
+      }
+      if (!src) continue;
+      if (oci) {
+        oci[orp[i] + n] = j;
+        memcpy((char*)ov + (size_t)vs * (size_t)(orp[i] + n), src, (size_t)vs);
+      }
+      ++n;
+    }
+    if (oci == NULL) orp[i + 1] = orp[i] + n;
+  }
+  return 0;
+}

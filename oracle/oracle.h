@@ -89,6 +89,52 @@ int64_t orc_axpby(int semiring, int32_t nrows, const void* alpha,
                   const void* beta, const int64_t* xrp, const int32_t* xci, const void* xv,
                   int64_t* drp, int32_t* dci, void* dv);
 
+/* ---- general updates filtered by a Bloom matrix (Section 5.2, Algorithm 2)
+ * on one process: the steps of the algorithm in its order, each on sorted
+ * CSR structures.  l = 64 (bit k mod 64 stands for column / row k).  Every
+ * two-phase function fills the row pointers when its column output is NULL
+ * and the columns (and values) on a second call. */
+
+/* A*: entries present in exactly one of A and A', or in both with different
+ * value bits (vs bytes per value). */
+int orc_changed_entries(int32_t nrows, int vs,
+                        const int64_t* rp, const int32_t* ci, const void* v,
+                        const int64_t* rp2, const int32_t* ci2, const void* v2,
+                        int64_t* srp, int32_t* sci);
+
+/* F, the Bloom matrix of C = A B: C's structure, and for each entry the bits
+ * (k mod 64) of the k with a_ik and b_kj present. */
+int orc_bloom(int32_t nrows, int32_t ncols,
+              const int64_t* arp, const int32_t* aci, const int64_t* brp, const int32_t* bci,
+              int64_t* frp, int32_t* fci, uint64_t* fv);
+
+/* computePattern: C* = A* B' + A B* (Eq. 1) as a structure; fs[e] = f*_ij,
+ * the bits of the k with a*_ik b'_kj or a'_ik b*_kj present. */
+int orc_pattern(int32_t nrows, int32_t ncols,
+                const int64_t* arp, const int32_t* aci, const int64_t* asrp, const int32_t* asci,
+                const int64_t* a2rp, const int32_t* a2ci, const int64_t* bsrp, const int32_t* bsci,
+                const int64_t* b2rp, const int32_t* b2ci,
+                int64_t* csrp, int32_t* csci, uint64_t* fs);
+
+/* E = (F | F*) masked at C*, and r_i = bitwise or of row i of E. */
+int orc_row_filter(int32_t nrows, const int64_t* csrp, const int32_t* csci, const uint64_t* fs,
+                   const int64_t* frp, const int32_t* fci, const uint64_t* fv, uint64_t* r);
+
+/* Z, H = A^R B' masked at C*: per entry of C*, the semiring sum (ascending k)
+ * over the k of A' row i whose bit is in r_i, with b'_kj present (zv, zp = 1
+ * when there is one) and the bits of those k (hv). */
+int orc_masked_product(int sr, int32_t nrows, int32_t ncols,
+                       const int64_t* a2rp, const int32_t* a2ci, const void* a2v, const uint64_t* r,
+                       const int64_t* b2rp, const int32_t* b2ci, const void* b2v,
+                       const int64_t* csrp, const int32_t* csci,
+                       void* zv, uint8_t* zp, uint64_t* hv);
+
+/* Merge masked at C*: X outside C*; z where zp, nothing where !zp, on C*. */
+int orc_masked_merge(int32_t nrows, int vs,
+                     const int64_t* xrp, const int32_t* xci, const void* xv,
+                     const int64_t* csrp, const int32_t* csci, const void* zv, const uint8_t* zp,
+                     int64_t* orp, int32_t* oci, void* ov);
+
 #ifdef __cplusplus
 }
 #endif

@@ -512,7 +512,135 @@ def pin_axpby(L, seed=14):
             assert same_bits(plain[k], as_stored(sr, w)), (t, k)
 
 
+# ---------------------------------------------------------------------------
+# Section 5.2, Algorithm 2: the Bloom matrix and the general-update steps
+# ---------------------------------------------------------------------------
+
+def bloom_bruteforce(A, B):
+    """{(i, j): bits} over every pair with a common k, by plain loops."""
+    ea, eb = entries_of(A), entries_of(B)
+    rows_b = {}
+    for (k, j) in eb:
+        rows_b.setdefault(k, []).append(j)
+    out = {}
+    for (i, k) in ea:
+        for j in rows_b.get(k, []):
+            out[(i, j)] = out.get((i, j), 0) | (1 << (k % 64))
+    return out
+
+
+def pin_bloom_bruteforce(L, seed=31):
+    """F against plain loops, on shapes whose inner dimension passes 64 and
+    128 (bits wrap around), with empty rows and columns."""
+    rng = np.random.default_rng(seed)
+    for (n, kk, m, d) in [(7, 5, 6, 0.5), (30, 150, 40, 0.08), (50, 200, 20, 0.05), (12, 70, 12, 0.0)]:
+        A = random_csr(rng, n, kk, d, I.PLUS_TIMES_I64)
+        B = random_csr(rng, kk, m, d, I.PLUS_TIMES_I64)
+        F = oracle.bloom(A, B, L=L)
+        want = bloom_bruteforce(A, B)
+        got = {k: int(v) for k, v in entries_of(F).items()}
+        assert got == want, (n, kk, m)
+        C = spgemm(I.PLUS_TIMES_I64, A, B, L=L)
+        assert np.array_equal(C.row_ptr, F.row_ptr) and np.array_equal(C.col, F.col)
+
+
+def batch_of(rng, A, sr, size, lo=1, hi=9):
+    """Random SET / DELETE mix over present and absent positions."""
+    ent = list(entries_of(A))
+    rows, cols, vals, ops = [], [], [], []
+    for _ in range(size):
+        if ent and rng.random() < 0.6:
+            i, j = ent[int(rng.integers(len(ent)))]
+        else:
+            i, j = int(rng.integers(A.nrows)), int(rng.integers(A.ncols))
+        op = 1 if rng.random() < 0.4 else 0
+        rows.append(i)
+        cols.append(j)
+        vals.append(rng.integers(lo, hi + 1))
+        ops.append(op)
+    dt = oracle.DTYPE[sr]
+    if sr == I.PLUS_TIMES_F64:
+        vals = list(rng.standard_normal(size))
+    return (np.array(rows, np.int32), np.array(cols, np.int32), np.array(vals, dt), np.array(ops, np.uint8))
+
+
+def pin_general_update(L, seed=32):
+    """Algorithm 2 on one process, for all four semirings, A B and A A:
+    C' equals the static product of the updated operands bit for bit (the
+    defining result, Section 5), F' equals the Bloom matrix of the updated
+    operands, C* equals the structure of A* B' + A B* enumerated by plain
+    loops from a dictionary diff, every entry that changed lies in C*, and
+    r_i holds the bit of every k that a'_ik b'_kj of an entry of C* needs."""
+    rng = np.random.default_rng(seed)
+    for sr in (I.PLUS_TIMES_I64, I.MIN_PLUS_F32, I.PLUS_TIMES_F64, I.OR_AND_U32):
+        for square in (True, False):
+            for (n, kk, m, d, nb) in [(20, 20, 20, 0.15, 6), (40, 90, 30, 0.06, 25), (60, 150, 60, 0.04, 40)]:
+                if square:
+                    kk = m = n
+                A = random_csr(rng, n, kk, d, sr)
+                B = A if square else random_csr(rng, kk, m, d, sr)
+                A2, _ = oracle.apply(sr, A, *batch_of(rng, A, sr, nb), L=L)
+                B2 = A2 if square else oracle.apply(sr, B, *batch_of(rng, B, sr, nb), L=L)[0]
+                C = spgemm(sr, A, B, L=L)
+                F = oracle.bloom(A, B, L=L)
+                r = oracle.general_update(sr, A, A2, B, B2, C, F, L=L)
+                want = spgemm(sr, A2, B2, L=L)
+                assert np.array_equal(r["C2"].row_ptr, want.row_ptr), (sr, square, n)
+                assert np.array_equal(r["C2"].col, want.col), (sr, square, n)
+                assert same_bits(r["C2"].val, want.val), (sr, square, n)
+                F2 = bloom_bruteforce(A2, B2)
+                assert {k: int(v) for k, v in entries_of(r["F2"]).items()} == F2, (sr, square, n)
+                # C* from a dictionary diff and plain loops
+                def star(X, X2):
+                    x, x2 = entries_of(X), entries_of(X2)
+                    return {k for k in set(x) | set(x2)
+                            if k not in x or k not in x2 or not same_bits(x[k], x2[k])}
+                As, Bs = star(A, A2), star(B, B2)
+                eb2, ea = entries_of(B2), entries_of(A)
+                cs = set()
+                for (i, k) in As:
+                    cs |= {(i, j) for (k2, j) in eb2 if k2 == k}
+                for (i, k) in ea:
+                    cs |= {(i, j) for (k2, j) in Bs if k2 == k}
+                assert set(entries_of(r["Cstar"])) == cs, (sr, square, n)
+                c_old, c_new = entries_of(C), entries_of(want)
+                moved = {k for k in set(c_old) | set(c_new)
+                         if k not in c_old or k not in c_new or not same_bits(c_old[k], c_new[k])}
+                assert moved <= cs, (sr, square, n)
+                a2rows = {}
+                for (i, k) in entries_of(A2):
+                    a2rows.setdefault(i, []).append(k)
+                for (i, j) in cs:
+                    for k in a2rows.get(i, []):
+                        if (k, j) in eb2:
+                            assert int(r["R"][i]) >> (k % 64) & 1, (sr, square, n, i, j, k)
+
+
+def pin_general_update_worked(L):
+    """The hand-derived example (tests/golden/bloom_general_worked.json):
+    every intermediate of Algorithm 2 and the results."""
+    g = json.load(open(os.path.join(GOLDEN, "bloom_general_worked.json")))
+    sr = g["semiring"]
+    dt = oracle.DTYPE[sr]
+    A = csr_from_entries(g["A"]["shape"], g["A"]["entries"], dt)
+    b = g["batch"]
+    A2, _ = oracle.apply(sr, A, np.array([x[0] for x in b], np.int32), np.array([x[1] for x in b], np.int32),
+                         np.array([x[2] for x in b], dt), np.array([OPS[x[3]] for x in b], np.uint8), L=L)
+    C = spgemm(sr, A, A, L=L)
+    F = oracle.bloom(A, A, L=L)
+    assert {k: float(v) for k, v in entries_of(C).items()} == {(i, j): v for i, j, v in g["C"]["entries"]}
+    assert {k: int(v) for k, v in entries_of(F).items()} == {(i, j): v for i, j, v in g["F"]}
+    r = oracle.general_update(sr, A, A2, A, A2, C, F, L=L)
+    assert set(entries_of(r["Astar"])) == {tuple(x) for x in g["Astar"]}
+    assert {k: int(v) for k, v in entries_of(r["Cstar"]).items()} == {(i, j): v for i, j, v in g["Cstar"]}
+    assert [int(x) for x in r["R"]] == g["R"]
+    kept = {(i, k) for (i, k) in entries_of(A2) if int(r["R"][i]) >> (k % 64) & 1}
+    assert kept == {tuple(x) for x in g["AR"]}
+    assert {k: float(v) for k, v in entries_of(r["C2"]).items()} == {(i, j): v for i, j, v in g["C2"]}
+    assert {k: int(v) for k, v in entries_of(r["F2"]).items()} == {(i, j): v for i, j, v in g["F2"]}
+
+
 ALL_PINS = [pin_golden_products, pin_golden_apply, pin_dense_bruteforce, pin_minplus_two_walks,
             pin_scipy_int64, pin_numpy_fp64, pin_stencil_small_boundary, pin_identity_and_relabel,
             pin_apply_vs_dict, pin_int64_invariants, pin_minplus_invariants, pin_boolean_bit_slices,
-            pin_transpose, pin_axpby]
+            pin_transpose, pin_axpby, pin_bloom_bruteforce, pin_general_update, pin_general_update_worked]

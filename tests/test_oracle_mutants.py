@@ -47,6 +47,14 @@ MUTANTS = [
     ("axpby_x_only_scaled_by_alpha", "sr_mul(sr, d, beta,", "sr_mul(sr, d, alpha,", 0),
     ("axpby_x_only_dropped", "        dci[out] = xci[b];\n        ++b;\n      }\n      ++out;",
      "        dci[out] = xci[b];\n        ++b;\n        continue;\n      }\n      ++out;", 0),
+    ("bloom_bits_mod_32", "((uint32_t)k % ORC_BLOOM_L)", "((uint32_t)k % 32)", 0),
+    ("pattern_without_a_bstar", "if (mark[j] != i) { mark[j] = i; touched[nt++] = j; }\n      }\n    }\n    /* A' B*",
+     "(void)j;\n      }\n    }\n    /* A' B*", 0),
+    ("filter_ignores_fstar", "uint64_t x = fs[e];", "uint64_t x = 0; (void)fs;", 0),
+    ("filter_and_instead_of_or", "acc |= x;", "acc &= x;", 0),
+    ("masked_merge_keeps_deleted", "if (zp[b]) src = (const char*)zv + (size_t)vs * (size_t)b;",
+     "src = zp[b] ? (const char*)zv + (size_t)vs * (size_t)b\n                    : (a < xrp[i + 1] && xci[a] == j) ? (const char*)xv + (size_t)vs * (size_t)a : NULL;", 0),
+    ("changed_ignores_values", "(size_t)vs) != 0;\n        ++a; ++b;", "(size_t)vs) != 0 && 0;\n        ++a; ++b;", 0),
 ]
 
 

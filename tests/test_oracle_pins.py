@@ -8,7 +8,8 @@ import pins
 PRODUCT_PINS = [pins.pin_golden_products, pins.pin_dense_bruteforce, pins.pin_minplus_two_walks,
                 pins.pin_scipy_int64, pins.pin_numpy_fp64, pins.pin_stencil_small_boundary,
                 pins.pin_identity_and_relabel, pins.pin_int64_invariants, pins.pin_minplus_invariants,
-                pins.pin_boolean_bit_slices, pins.pin_transpose, pins.pin_stencil_closed_form]
+                pins.pin_boolean_bit_slices, pins.pin_transpose, pins.pin_stencil_closed_form,
+                pins.pin_general_update]
 
 
 @pytest.mark.parametrize("pin", pins.ALL_PINS + [pins.pin_stencil_closed_form],
