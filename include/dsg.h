@@ -249,6 +249,19 @@ dsg_status dsg_prod_rows(dsg_prod* p, const int32_t* rows, int32_t nq, uint32_t 
 dsg_status dsg_rows_export(dsg_prod* p, const dsg_rows* v, int64_t* row_ptr, int32_t* col, void* val,
                            int64_t cap, int64_t* nnz_out);
 
+/* The same export for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid allocation): no hipMalloc, hipFree or
+ * allocating library routine is called.  The device staging (row lengths,
+ * offsets, gathered entries) lives in a fixed array of the library, one per
+ * GPU, held from the first context on that GPU until the process ends.
+ * Limits: at most 262,144 rows and 2,097,152 entries per call (DSG_E_ARG
+ * beyond them; when the entry limit is what fails, *nnz_out and row_ptr are
+ * still written); row_ptr and val are required whenever col is given.  Calls
+ * on one GPU share its array and run one at a time (each returns after its
+ * device work has finished). */
+dsg_status dsg_rows_export_noalloc(dsg_prod* p, const dsg_rows* v, int64_t* row_ptr, int32_t* col, void* val,
+                                   int64_t cap, int64_t* nnz_out);
+
 dsg_status dsg_prod_nnz(dsg_prod* p, int64_t* nnz);
 /* Canonical host CSR of C, as dsg_mat_export. */
 dsg_status dsg_prod_export(dsg_prod* p, int64_t* row_ptr, int32_t* col, void* val, int64_t cap,

@@ -245,6 +245,7 @@ extern "C" dsg_status dsg_ctx_create(int device, void* hip_stream, size_t mem_bu
       c.own_stream = true;
     }
     DSG_HIP(hipHostMalloc(&c.pinned, 4096, hipHostMallocDefault));
+    noalloc_init(device);  // the allocation-free row export's staging array on this device
   } catch (const DsgError& e) {
     if (ctx) {
       if (ctx->c.own_stream) (void)hipStreamDestroy(ctx->c.stream);
@@ -696,6 +697,17 @@ extern "C" dsg_status dsg_rows_export(dsg_prod* ph, const dsg_rows* v, int64_t* 
   if (nnz == 0) return DSG_OK;
   memcpy(col, h.col.data(), (size_t)nnz * 4);
   memcpy(val, h.val.data(), h.val.size());
+  API_END
+}
+
+extern "C" dsg_status dsg_rows_export_noalloc(dsg_prod* ph, const dsg_rows* v, int64_t* row_ptr, int32_t* col,
+                                              void* val, int64_t cap, int64_t* nnz_out) {
+  if (!ph || !v || !nnz_out) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
+  if (col && (!val || !row_ptr)) return fail(ph->owner, DSG_E_ARG, "val or row_ptr is NULL");
+  if (v->n < 0 || (v->n > 0 && !v->rows)) return fail(ph->owner, DSG_E_ARG, "bad view");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  *nnz_out = rows_export_noalloc(ph->p->C, v->rows, v->n, row_ptr, col, val, cap);
   API_END
 }
 

@@ -227,6 +227,23 @@ struct GatherBufs {
 void mat_gather_rows(DMat* m, const int32_t* d_rows, int32_t n, GatherBufs& g, RowsHost& out, hipStream_t s,
                      bool entries = true);
 void gather_bufs_free(Ctx* c, GatherBufs& g);
+// The device steps of mat_gather_rows on caller-owned buffers (nothing
+// allocated): the n listed rows' lengths into d_lens[n] and their offsets
+// into d_rp[n + 1] (total in d_rp[n]; d_scan: scan_scratch_bytes(n) bytes),
+// then their entries, in list order and in each row's stored order, into
+// d_col / d_val at those offsets.  Queued on stream s.
+void gather_row_ptr(DMat* m, const int32_t* d_rows, int32_t n, int64_t* d_lens, int64_t* d_rp, void* d_scan,
+                    hipStream_t s);
+void gather_row_entries(DMat* m, const int32_t* d_rows, int32_t n, const int64_t* d_rp, int32_t* d_col,
+                        void* d_val, hipStream_t s);
+
+// Row export that allocates no device memory (noalloc.hip): the listed rows
+// of m, each sorted by column, into the caller's host arrays, staged through
+// a fixed device array of the library.  noalloc_init looks that array up on
+// the current device (once per device; the context creation calls it).
+void noalloc_init(int device);
+int64_t rows_export_noalloc(DMat* m, const int32_t* d_rows, int32_t n, int64_t* row_ptr, int32_t* col, void* val,
+                            int64_t cap);
 
 // Apply a device-resident batch (validated).  Returns nothing; updates epochs.
 void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,

@@ -458,6 +458,29 @@ void gather_bufs_free(Ctx* c, GatherBufs& g) {
   g = GatherBufs{};
 }
 
+void gather_row_ptr(DMat* m, const int32_t* d_rows, int32_t n, int64_t* d_lens, int64_t* d_rp, void* d_scan,
+                    hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_gather_lens, dim3(blocks_for(n, 256)), dim3(256), 0, s, d_rows, n, m->row_len, d_lens);
+  exclusive_scan_i64(d_lens, d_rp, n, d_rp + n, d_scan, s);
+}
+
+void gather_row_entries(DMat* m, const int32_t* d_rows, int32_t n, const int64_t* d_rp, int32_t* d_col,
+                        void* d_val, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned nb = (unsigned)blocks_for((int64_t)n * 64, 256);
+  if (m->vsz == 8)
+    hipLaunchKernelGGL(k_gather_rows<8>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
+                       (const char*)m->val, d_rp, d_col, (char*)d_val);
+  else if (m->vsz == 4)
+    hipLaunchKernelGGL(k_gather_rows<4>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
+                       (const char*)m->val, d_rp, d_col, (char*)d_val);
+  else
+    hipLaunchKernelGGL(k_gather_rows<0>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
+                       (const char*)m->val, d_rp, d_col, (char*)d_val);
+  DSG_HIP(hipGetLastError());
+}
+
 void mat_gather_rows(DMat* m, const int32_t* d_rows, int32_t n, GatherBufs& g, RowsHost& out, hipStream_t s,
                      bool entries) {
   Ctx* c = m->ctx;
@@ -465,10 +488,7 @@ void mat_gather_rows(DMat* m, const int32_t* d_rows, int32_t n, GatherBufs& g, R
   ensure_buf(c, g.lens, g.lens_bytes, (size_t)(n + 1) * 8);
   ensure_buf(c, g.rp, g.rp_bytes, (size_t)(n + 1) * 8);
   ensure_buf(c, g.scan, g.scan_bytes, scan_scratch_bytes(n) + 64);
-  if (n > 0)
-    hipLaunchKernelGGL(k_gather_lens, dim3(blocks_for(n, 256)), dim3(256), 0, s, d_rows, n, m->row_len,
-                       (int64_t*)g.lens);
-  exclusive_scan_i64((const int64_t*)g.lens, (int64_t*)g.rp, n, (int64_t*)g.rp + n, g.scan, s);
+  gather_row_ptr(m, d_rows, n, (int64_t*)g.lens, (int64_t*)g.rp, g.scan, s);
   out.row_ptr.assign((size_t)n + 1, 0);
   DSG_HIP(hipMemcpyAsync(out.row_ptr.data(), g.rp, out.row_ptr.size() * 8, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));
@@ -479,16 +499,7 @@ void mat_gather_rows(DMat* m, const int32_t* d_rows, int32_t n, GatherBufs& g, R
   if (nnz == 0) return;
   ensure_buf(c, g.col, g.col_bytes, (size_t)nnz * 4);
   ensure_buf(c, g.val, g.val_bytes, (size_t)nnz * (vs ? vs : 1));
-  const unsigned nb = (unsigned)blocks_for((int64_t)n * 64, 256);
-  if (vs == 8)
-    hipLaunchKernelGGL(k_gather_rows<8>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
-                       (const char*)m->val, (const int64_t*)g.rp, (int32_t*)g.col, (char*)g.val);
-  else if (vs == 4)
-    hipLaunchKernelGGL(k_gather_rows<4>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
-                       (const char*)m->val, (const int64_t*)g.rp, (int32_t*)g.col, (char*)g.val);
-  else
-    hipLaunchKernelGGL(k_gather_rows<0>, dim3(nb), dim3(256), 0, s, d_rows, n, m->row_off, m->row_len, m->col,
-                       (const char*)m->val, (const int64_t*)g.rp, (int32_t*)g.col, (char*)g.val);
+  gather_row_entries(m, d_rows, n, (const int64_t*)g.rp, (int32_t*)g.col, g.val, s);
   std::vector<int32_t> hc((size_t)nnz);
   std::vector<char> hv((size_t)nnz * vs);
   DSG_HIP(hipMemcpyAsync(hc.data(), g.col, (size_t)nnz * 4, hipMemcpyDeviceToHost, s));

@@ -115,6 +115,7 @@ SIGNATURES = {
     "dsg_prod_update": [P, ctypes.c_uint32, P],
     "dsg_prod_rows": [P, P, ctypes.c_int32, ctypes.c_uint32, P],
     "dsg_rows_export": [P, P, P, P, P, ctypes.c_int64, P],
+    "dsg_rows_export_noalloc": [P, P, P, P, P, ctypes.c_int64, P],
     "dsg_prod_nnz": [P, P],
     "dsg_prod_export": [P, P, P, P, ctypes.c_int64, P],
     "dsg_prod_stats": [P, P],
@@ -334,6 +335,23 @@ class RowSet:
         val = np.zeros(max(nnz.value, 1), DTYPE[p.semiring])
         p.ctx._check(L.dsg_rows_export(p.h, ctypes.byref(self.v), rp.ctypes.data_as(P), col.ctypes.data_as(P),
                                        val.ctypes.data_as(P), col.size, ctypes.byref(nnz)))
+        return self.row_ids(), rp, col[:nnz.value], val[:nnz.value]
+
+    def to_host_noalloc(self, cap: Optional[int] = None):
+        """As to_host, through dsg_rows_export_noalloc (no device allocation;
+        cap: room of the entry arrays, default the view's entry count)."""
+        p = self.prod
+        L = p.L
+        nnz = ctypes.c_int64()
+        rp = np.zeros(self.n + 1, np.int64)
+        p.ctx._check(L.dsg_rows_export_noalloc(p.h, ctypes.byref(self.v), rp.ctypes.data_as(P), None, None, 0,
+                                               ctypes.byref(nnz)))
+        room = nnz.value if cap is None else cap
+        col = np.zeros(max(room, 1), np.int32)
+        val = np.zeros(max(room, 1), DTYPE[p.semiring])
+        p.ctx._check(L.dsg_rows_export_noalloc(p.h, ctypes.byref(self.v), rp.ctypes.data_as(P),
+                                               col.ctypes.data_as(P), val.ctypes.data_as(P), room,
+                                               ctypes.byref(nnz)))
         return self.row_ids(), rp, col[:nnz.value], val[:nnz.value]
 
     def row_ids(self) -> np.ndarray:
