@@ -337,7 +337,9 @@ def bench_serve(args):
 
 def bench_sweep(args):
     """Per batch size on the default workload: ms per step of the row path,
-    of the entry-granular path, and of a static recompute, same GPU."""
+    of the entry-granular path, of the automatic choice between them, of the
+    general-update algorithm with the Bloom matrix, and of a static
+    recompute, same GPU."""
     import torch
     from paper_2202_08808_amd import dsg
     from paper_2202_08808_amd import inputs as I
@@ -348,13 +350,13 @@ def bench_sweep(args):
         batches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (q.rows, q.cols, q.vals, q.ops))
                    for q in w.batches_A]
         rec = {"batch": b}
-        for path in ("row", "entry", "auto"):
+        for path in ("row", "entry", "auto", "bloom"):
             ctx = dsg.Context(0, stream=torch.cuda.current_stream(dev))
             t = ctx.get_tuning()
-            t.update_path = {"row": 1, "entry": 2, "auto": 0}[path]
+            t.update_path = {"row": 1, "entry": 2, "auto": 0, "bloom": 0}[path]
             ctx.set_tuning(t)
             A = dsg.Matrix.from_csr(ctx, w.A, w.semiring)
-            P = dsg.Product(ctx, A, A)
+            P = dsg.Product(ctx, A, A, bloom=path == "bloom")
             ts = []
             for k in range(args.warmup + args.steps):
                 torch.cuda.synchronize()
@@ -370,6 +372,14 @@ def bench_sweep(args):
                 rec["row_flops"] = st["flops"]
             if path == "auto":
                 rec["auto_took_entry"] = bool(st["path"] == 1)
+            if path == "bloom":
+                # Algorithm 2: entries of C*, and the columns of A' the row
+                # filter kept against those its rows hold
+                rec["bloom_taken"] = bool(st["path"] == 2)
+                rec["bloom_cstar_entries"] = st["entries"]
+                rec["bloom_cstar_rows"] = st["affected_rows"]
+                rec["bloom_kept_a_entries"] = st["a_entries"]
+                rec["bloom_masked_products"] = st["flops"]
             if path == "entry":
                 rec["entry_taken"] = bool(st["path"] == 1)
                 rec["lost_per_batch"] = st["lost"]
@@ -387,6 +397,7 @@ def bench_sweep(args):
             ctx.close()
         rec["speedup_row"] = round(rec["static_ms"] / rec["row_ms"], 3)
         rec["speedup_entry"] = round(rec["static_ms"] / rec["entry_ms"], 3)
+        rec["speedup_bloom"] = round(rec["static_ms"] / rec["bloom_ms"], 3)
         log(f"[sweep] {json.dumps(rec)}")
         out.append(rec)
     print(json.dumps({"workload": args.workload, "sweep": out}), flush=True)

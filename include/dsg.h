@@ -199,6 +199,18 @@ dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod
  * Section 5, "Handling Transposition"). */
 #define DSG_TRANS_A 0x1u  /* the product reads A^T in place of A */
 #define DSG_TRANS_B 0x2u  /* the product reads B^T in place of B */
+/* General updates filtered by a Bloom matrix (Section 5.2, Algorithm 2): the
+ * product keeps, beside C, the matrix F of C's structure whose entry f_ij has
+ * bit (k mod 64) set when a_ik b_kj is a term of c_ij.  Each dynamic multiply
+ * then finds the pattern C* = A* B + A' B* of the changed terms with their
+ * bits F*, ors F and F* over each row of C* into a filter R, recomputes only
+ * the entries of C* from the columns k of A' that R lets through, and merges
+ * the new entries and bits into C and F.  When an operand took more than one
+ * apply since the last update (the change logs hold one apply), the row path
+ * runs and F is rebuilt.  Not with DSG_TRANS_A / DSG_TRANS_B
+ * (DSG_E_UNSUPPORTED), nor in the batched form.  Results equal those of the
+ * other paths. */
+#define DSG_GENERAL_BLOOM 0x4u
 
 /* Create C = op(A) op(B), op(X) = X^T when ops holds X's flag, and compute
  * it from scratch.  A transposed operand is read from its transpose index,
@@ -210,6 +222,12 @@ dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod
  * DSG_E_STATE (semiring mismatch, inner dimensions of op(A) and op(B)
  * differ). */
 dsg_status dsg_prod_create(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, uint32_t ops, dsg_prod** out);
+
+/* Canonical host CSR of a DSG_GENERAL_BLOOM product's Bloom matrix F (same
+ * structure as C; val holds one uint64 bit field per entry), as
+ * dsg_prod_export.  DSG_E_STATE for a product without F. */
+dsg_status dsg_prod_export_bloom(dsg_prod* p, int64_t* row_ptr, int32_t* col, uint64_t* val, int64_t cap,
+                                 int64_t* nnz_out);
 
 /* A new matrix D = (alpha (x) C) (+) (beta (x) X), the general SpGEMM result
  * alpha op(A) op(B) + beta X of Section 3, from the product's C as of its
@@ -277,7 +295,10 @@ typedef struct {
   int64_t nnz_old;      /* entries of those rows before it */
   int64_t bin_rows[10]; /* rows per accumulator bin (8 group bins, dense, global hash) */
   int64_t bin_flops[10];
-  int32_t path;         /* 0: affected rows recomputed; 1: entry-granular */
+  int32_t path;         /* 0: affected rows recomputed; 1: entry-granular; 2: general updates with the
+                           Bloom filter (affected_rows: rows of C*, entries: entries of C*, terms: terms
+                           of the pattern, a_entries: columns of A' kept by the filter, flops: products
+                           of the masked multiply tried) */
   int32_t pad;
   int64_t terms;        /* entry-granular: changed products a_ik * b_kj enumerated */
   int64_t entries;      /* entry-granular: entries of C with changed products */

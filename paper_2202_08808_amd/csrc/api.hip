@@ -571,7 +571,9 @@ extern "C" dsg_status dsg_prod_create(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, uint
   if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
   if (!out || !A || !B || !A->alive || !B->alive) return fail(ctx, DSG_E_ARG, "NULL or destroyed argument");
   *out = nullptr;
-  if (ops & ~(uint32_t)(DSG_TRANS_A | DSG_TRANS_B)) return fail(ctx, DSG_E_ARG, "unknown operand flag");
+  if (ops & ~(uint32_t)(DSG_TRANS_A | DSG_TRANS_B | DSG_GENERAL_BLOOM)) return fail(ctx, DSG_E_ARG, "unknown operand flag");
+  if ((ops & DSG_GENERAL_BLOOM) && (ops & (DSG_TRANS_A | DSG_TRANS_B)))
+    return fail(ctx, DSG_E_UNSUPPORTED, "general updates with the Bloom matrix take untransposed operands");
   if (A->owner != ctx || B->owner != ctx) return fail(ctx, DSG_E_STATE, "operands belong to another context");
   if (A->m->sr != B->m->sr) return fail(ctx, DSG_E_STATE, "semiring mismatch");
   const int32_t inner_a = (ops & DSG_TRANS_A) ? A->m->nrows : A->m->ncols;
@@ -729,6 +731,17 @@ extern "C" dsg_status dsg_prod_export(dsg_prod* ph, int64_t* row_ptr, int32_t* c
   API_END
 }
 
+extern "C" dsg_status dsg_prod_export_bloom(dsg_prod* ph, int64_t* row_ptr, int32_t* col, uint64_t* val, int64_t cap,
+                                            int64_t* nnz_out) {
+  if (!ph || !nnz_out) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
+  if (col && !val) return fail(ph->owner, DSG_E_ARG, "val is NULL");
+  if (!ph->p->F) return fail(ph->owner, DSG_E_STATE, "product keeps no Bloom matrix");
+  API_BEGIN(ph->owner)
+  set_device(ctx__);
+  export_impl(ph->p->F, row_ptr, col, val, cap, nnz_out);
+  API_END
+}
+
 extern "C" dsg_status dsg_prod_stats(const dsg_prod* ph, dsg_update_stats* s) {
   if (!ph || !s) return fail(ph ? ph->owner : nullptr, DSG_E_ARG, "NULL argument");
   *s = ph->p->stats;
@@ -840,6 +853,8 @@ extern "C" dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int
   std::vector<DMat*> seen;
   for (int32_t i = 0; i < nprod; ++i) {
     if (!prods[i] || prods[i]->owner != ctx) return fail(ctx, DSG_E_STATE, "product of another context");
+    if (prods[i]->p->bloom)
+      return fail(ctx, DSG_E_UNSUPPORTED, "products with the Bloom matrix are not taken by the batched form");
     DMat* mine[2] = {prods[i]->p->src_a, prods[i]->p->src_b};
     for (DMat* m : mine)
       if (std::find(seen.begin(), seen.end(), m) != seen.end())

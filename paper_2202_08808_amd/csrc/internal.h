@@ -311,6 +311,12 @@ struct DProd {
   int64_t entry_nU = 0;           // entry-granular path: log entries and changed
   int64_t entry_nterm = 0;        // products counted for the pending update
   int refs = 0;                   // batched executors and servers using this product
+  // general updates filtered by a Bloom matrix (DSG_GENERAL_BLOOM): F has C's
+  // structure, bit (k mod 64) of f_ij set when a_ik b_kj is a term of c_ij
+  bool bloom = false;
+  DMat* F = nullptr;
+  void* gws = nullptr;            // workspace of the general-update path
+  size_t gws_bytes = 0;
 };
 
 // C = op(A) op(B), op(X) = X^T under DSG_TRANS_A / DSG_TRANS_B in ops.
@@ -333,6 +339,15 @@ bool entry_eligible(const DProd* p);
 // read back by the caller's next synchronisation into p->entry_nterm.
 const int64_t* entry_count(DProd* p);
 int32_t entry_finish(DProd* p);
+
+// General updates with the Bloom matrix (general.hip, Section 5.2,
+// Algorithm 2).  bloom_build computes F from the current C, A and B;
+// general_eligible tells whether the logs of the operands cover every apply
+// since the product last saw them (then general_update brings C and F up to
+// date and returns the reported-row count).
+void bloom_build(DProd* p);
+bool general_eligible(const DProd* p);
+int32_t general_update(DProd* p);
 
 // Graph-capturable dynamic update (no host round trips) on a caller-owned
 // workspace of prod_graph_work_bytes(p) bytes, after prod_prepare_graph set

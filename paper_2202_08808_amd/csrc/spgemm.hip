@@ -2353,7 +2353,8 @@ DProd* prod_create(Ctx* c, DMat* A, DMat* B, uint32_t ops) {
   p->ctx = c;
   p->src_a = A;
   p->src_b = B;
-  p->ops = ops;
+  p->ops = ops & (DSG_TRANS_A | DSG_TRANS_B);
+  p->bloom = (ops & DSG_GENERAL_BLOOM) != 0;
   try {
     // A's transpose serves either as the left operand (A^T) or as the
     // column index of the left operand (A); every apply of A keeps it current
@@ -2393,6 +2394,8 @@ void prod_destroy(DProd* p) {
   if (p->ews) ctx_free(c, p->ews, p->ews_bytes);
   if (p->srt) ctx_free(c, p->srt, p->srt_bytes);
   if (p->bsp) ctx_free(c, p->bsp, p->bsp_bytes);
+  if (p->gws) ctx_free(c, p->gws, p->gws_bytes);
+  if (p->F) mat_destroy(p->F);
   if (p->C) mat_destroy(p->C);
   if (p->src_a) p->src_a->refs--;
   if (p->src_b) p->src_b->refs--;
@@ -2401,6 +2404,29 @@ void prod_destroy(DProd* p) {
 
 int32_t prod_run(DProd* p, int mode, bool report_affected) {
   int32_t nchg = 0;
+  if (p->bloom) {
+    // Algorithm 2 keeps C and F current together; where it cannot run (no F
+    // yet, a static recompute, several applies since the last update, every
+    // recomputed row asked for), the row path brings C up to date and F is
+    // built again from it
+    if (mode == 0 && !report_affected && general_eligible(p)) {
+      nchg = general_update(p);
+    } else {
+      const bool b = p->bloom;
+      p->bloom = false;
+      try {
+        nchg = prod_run(p, mode, report_affected);
+      } catch (...) {
+        p->bloom = b;
+        throw;
+      }
+      p->bloom = b;
+      bloom_build(p);
+    }
+    p->a_seq = p->src_a->apply_seq;
+    p->b_seq = p->src_b->apply_seq;
+    return nchg;
+  }
   // entry-granular candidate: count its changed products first (cheap)
   const int64_t* d_nterm = nullptr;
   if (mode == 0 && !report_affected && entry_eligible(p)) {

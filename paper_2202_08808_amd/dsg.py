@@ -21,7 +21,7 @@ OK, E_ARG, E_RANGE, E_OOM, E_DEVICE, E_STATE, E_UNSUPPORTED = range(7)
 PLUS_TIMES_I64, MIN_PLUS_F32, PLUS_TIMES_F64, OR_AND_U32 = 0, 1, 2, 3
 OP_SET, OP_DELETE, OP_ADD = 0, 1, 2
 INPUT_DEVICE, SYNC, REPORT_AFFECTED = 0x1, 0x2, 0x4
-TRANS_A, TRANS_B = 0x1, 0x2
+TRANS_A, TRANS_B, GENERAL_BLOOM = 0x1, 0x2, 0x4
 DTYPE = {PLUS_TIMES_I64: np.int64, MIN_PLUS_F32: np.float32, PLUS_TIMES_F64: np.float64,
          OR_AND_U32: np.uint32}
 NAMES = {OK: "DSG_OK", E_ARG: "DSG_E_ARG", E_RANGE: "DSG_E_RANGE", E_OOM: "DSG_E_OOM",
@@ -118,6 +118,7 @@ SIGNATURES = {
     "dsg_rows_export_noalloc": [P, P, P, P, P, ctypes.c_int64, P],
     "dsg_prod_nnz": [P, P],
     "dsg_prod_export": [P, P, P, P, ctypes.c_int64, P],
+    "dsg_prod_export_bloom": [P, P, P, P, ctypes.c_int64, P],
     "dsg_prod_stats": [P, P],
     "dsg_prod_autotune": [P, ctypes.c_int32, P, P, ctypes.c_char_p, ctypes.c_size_t],
     "dsg_prod_destroy": [P],
@@ -388,7 +389,8 @@ def _hip():
 class Product:
     """C = op(A) op(B), op(X) = X^T when trans_a / trans_b is set."""
 
-    def __init__(self, ctx: Context, A: Matrix, B: Matrix, trans_a: bool = False, trans_b: bool = False):
+    def __init__(self, ctx: Context, A: Matrix, B: Matrix, trans_a: bool = False, trans_b: bool = False,
+                 bloom: bool = False):
         self.ctx, self.L = ctx, ctx.L
         self.A, self.B = A, B
         self.trans_a, self.trans_b = bool(trans_a), bool(trans_b)
@@ -396,7 +398,7 @@ class Product:
         self.nrows = A.ncols if trans_a else A.nrows
         self.ncols = B.nrows if trans_b else B.ncols
         h = P()
-        ops = (TRANS_A if trans_a else 0) | (TRANS_B if trans_b else 0)
+        ops = (TRANS_A if trans_a else 0) | (TRANS_B if trans_b else 0) | (GENERAL_BLOOM if bloom else 0)
         ctx._check(self.L.dsg_prod_create(ctx.h, A.h, B.h, ops, ctypes.byref(h)))
         self.h = h
 
@@ -434,6 +436,19 @@ class Product:
 
     def export(self):
         return _export(self.ctx, self.L.dsg_prod_export, self.h, self.nrows, self.ncols, self.semiring)
+
+    def export_bloom(self):
+        """Canonical CSR of the Bloom matrix F (uint64 bit fields), for a
+        product created with bloom=True."""
+        nnz = ctypes.c_int64()
+        rp = np.zeros(self.nrows + 1, np.int64)
+        fn = self.L.dsg_prod_export_bloom
+        self.ctx._check(fn(self.h, rp.ctypes.data_as(P), None, None, 0, ctypes.byref(nnz)))
+        col = np.zeros(max(nnz.value, 1), np.int32)
+        val = np.zeros(max(nnz.value, 1), np.uint64)
+        self.ctx._check(fn(self.h, rp.ctypes.data_as(P), col.ctypes.data_as(P), val.ctypes.data_as(P), col.size,
+                           ctypes.byref(nnz)))
+        return Csr(self.nrows, self.ncols, rp, col[:nnz.value], val[:nnz.value])
 
     def stats(self) -> dict:
         s = Stats()

@@ -1,0 +1,266 @@
+"""GPU: dynamic multiplies by the general-update algorithm with the Bloom
+matrix (Section 5.2, Algorithm 2) give the oracle's C' bit for bit, keep F
+equal to the Bloom matrix of the updated operands, report exactly the rows
+whose content changed, and agree with the oracle's own run of the
+algorithm."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import THREADS, assert_same_csr, changed_rows
+from paper_2202_08808_amd import dsg
+from paper_2202_08808_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SEMIRINGS = [I.PLUS_TIMES_I64, I.MIN_PLUS_F32, I.PLUS_TIMES_F64, I.OR_AND_U32]
+NAMES = {I.PLUS_TIMES_I64: "i64", I.MIN_PLUS_F32: "minplus", I.PLUS_TIMES_F64: "f64", I.OR_AND_U32: "orand"}
+
+
+def say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return dsg.Context(0)
+
+
+def vrange(sr):
+    return (0, (1 << 32) - 1) if sr == I.OR_AND_U32 else ((1, 100) if sr == I.MIN_PLUS_F32 else (1, 9))
+
+
+def to_dev(b):
+    import torch
+    vals = np.ascontiguousarray(b.vals)
+    if vals.dtype == np.uint32:
+        vals = vals.view(np.int32)
+    return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (b.rows, b.cols, vals, b.ops)]
+
+
+def same_bloom(got, want, what):
+    assert np.array_equal(got.row_ptr, want.row_ptr), f"{what}: F row pointers differ"
+    assert np.array_equal(got.col, want.col), f"{what}: F columns differ"
+    assert np.array_equal(np.asarray(got.val, np.uint64), np.asarray(want.val, np.uint64)), f"{what}: F bits differ"
+
+
+def run_rounds(ctx, sr, A0, B0, sizes, seed, what, rounds_each=1, check_oracle_alg=True):
+    """Product with the Bloom matrix over A0 (and B0, or A0 A0), one apply per
+    operand and round, checked against the oracle after every update."""
+    lo, hi = vrange(sr)
+    square = B0 is None
+    a = dsg.Matrix.from_csr(ctx, A0, sr)
+    b = a if square else dsg.Matrix.from_csr(ctx, B0, sr)
+    P = dsg.Product(ctx, a, b, bloom=True)
+    ha = oracle.Csr.of(A0)
+    hb = ha if square else oracle.Csr.of(B0)
+    C = oracle.spgemm(sr, ha, hb, nthreads=THREADS)
+    F = oracle.bloom(ha, hb)
+    assert_same_csr(sr, P.export(), C, f"{what}: static C")
+    same_bloom(P.export_bloom(), F, f"{what}: static F")
+    bas = I.disjoint_batches(A0, sr, sizes, stream=seed, value_lo=lo, value_hi=hi)
+    bbs = None if square else I.disjoint_batches(B0, sr, sizes, stream=seed + 1, value_lo=lo, value_hi=hi)
+    for t in range(len(sizes)):
+        ba = bas[t]
+        a.apply(*to_dev(ba))
+        ha2, _ = oracle.apply(sr, ha, ba.rows, ba.cols, ba.vals, ba.ops)
+        if square:
+            hb2 = ha2
+        else:
+            bb = bbs[t]
+            b.apply(*to_dev(bb))
+            hb2, _ = oracle.apply(sr, hb, bb.rows, bb.cols, bb.vals, bb.ops)
+        rs = P.update()
+        st = P.stats()
+        assert st["path"] == 2, f"{what} round {t}: the general path did not run"
+        want = oracle.spgemm(sr, ha2, hb2, nthreads=THREADS)
+        got = P.export()
+        assert_same_csr(sr, got, want, f"{what} round {t}: C'")
+        assert got.val.tobytes() == want.val.tobytes(), f"{what} round {t}: C' values not bit for bit"
+        F2 = oracle.bloom(ha2, hb2)
+        same_bloom(P.export_bloom(), F2, f"{what} round {t}")
+        assert np.array_equal(rs.row_ids(), changed_rows(C, want)), f"{what} round {t}: reported rows"
+        if check_oracle_alg:
+            r = oracle.general_update(sr, ha, ha2, hb, hb2, C, F)
+            # the device pattern is a superset of C* (rows of B' with this apply's insertions)
+            assert st["entries"] >= r["Cstar"].nnz
+            assert r["C2"].val.tobytes() == want.val.tobytes()
+        ha, hb, C, F = ha2, hb2, want, F2
+    P.destroy()
+    if not square:
+        b.destroy()
+    a.destroy()
+    return st
+
+
+@pytest.mark.parametrize("sr", SEMIRINGS, ids=[NAMES[s] for s in SEMIRINGS])
+@pytest.mark.parametrize("square", [True, False], ids=["AA", "AB"])
+def test_general_rmat(ctx, sr, square):
+    """R-MAT scale 11, edge factor 8: batches of 30, 300 and 1000 entries
+    (50% insertions, 25% deletions, 25% value changes), C = A A or A B with
+    both operands updated in the same round."""
+    say(f"general update rmat {NAMES[sr]} {'AA' if square else 'AB'}")
+    lo, hi = vrange(sr)
+    A = I.rmat_csr(11, 8, sr, stream=1100 + sr, lo=lo, hi=hi)
+    B = None if square else I.rmat_csr(11, 8, sr, stream=1110 + sr, lo=lo, hi=hi)
+    st = run_rounds(ctx, sr, A, B, [30, 300, 1000], 1120 + sr, f"rmat {NAMES[sr]}")
+    assert st["terms"] > 0 and st["entries"] > 0
+
+
+@pytest.mark.parametrize("sr", SEMIRINGS, ids=[NAMES[s] for s in SEMIRINGS])
+def test_general_filter_drops_columns(ctx, sr):
+    """Erdos-Renyi rows of degree ~8 over 4096 columns: the row filter R keeps
+    only the columns of A' whose bit the masked entries need, fewer than the
+    rows hold, and the result is still exact."""
+    say(f"general update filter {NAMES[sr]}")
+    lo, hi = vrange(sr)
+    n = 4096
+    keys = I.er_keys(n, 8 * n, I.rng_for(1130 + sr, 0))
+    A = I.csr_from_keys(n, n, keys, I.draw_values(sr, keys.size, I.rng_for(1130 + sr, 1), lo, hi))
+    a = dsg.Matrix.from_csr(ctx, A, sr)
+    P = dsg.Product(ctx, a, a, bloom=True)
+    ba = I.disjoint_batches(A, sr, [40], stream=1140 + sr, value_lo=lo, value_hi=hi)[0]
+    a.apply(*to_dev(ba))
+    P.update()
+    st = P.stats()
+    ha2, _ = oracle.apply(sr, oracle.Csr.of(A), ba.rows, ba.cols, ba.vals, ba.ops)
+    assert_same_csr(sr, P.export(), oracle.spgemm(sr, ha2, ha2), "C'")
+    same_bloom(P.export_bloom(), oracle.bloom(ha2, ha2), "F'")
+    # the A' entries of the rows of C*, against the ones the filter kept
+    assert st["path"] == 2 and 0 < st["a_entries"]
+    r = oracle.general_update(sr, oracle.Csr.of(A), ha2, oracle.Csr.of(A), ha2,
+                              oracle.spgemm(sr, oracle.Csr.of(A), oracle.Csr.of(A)),
+                              oracle.bloom(oracle.Csr.of(A), oracle.Csr.of(A)))
+    rows = np.unique(np.repeat(np.arange(n), np.diff(r["Cstar"].row_ptr)))
+    held = int(np.sum(np.diff(ha2.row_ptr)[rows]))
+    kept = 0
+    for i in rows:
+        ri = int(r["R"][i])
+        kept += sum(1 for e in range(ha2.row_ptr[i], ha2.row_ptr[i + 1]) if (ri >> (int(ha2.col[e]) % 64)) & 1)
+    assert st["a_entries"] == kept, (st["a_entries"], kept)
+    assert kept < held, "the filter kept every column"
+    P.destroy()
+    a.destroy()
+
+
+@pytest.mark.parametrize("sr", SEMIRINGS, ids=[NAMES[s] for s in SEMIRINGS])
+def test_general_long_mask_rows(ctx, sr):
+    """A row of C* longer than the LDS tables (its masked columns found by
+    binary search in the sorted pattern): 60 changed entries of one row of A,
+    each reaching a row of B of 100 columns out of 20,000."""
+    say(f"general update long mask rows {NAMES[sr]}")
+    lo, hi = vrange(sr)
+    rng = np.random.default_rng(1150 + sr)
+    n, k, m = 64, 200, 20000
+    ka = np.unique(np.concatenate([np.arange(0, 120, dtype=np.int64),                    # row 0: k = 0..119
+                                   rng.integers(k, n * k, 400)]))
+    A = I.csr_from_keys(n, k, ka, I.draw_values(sr, ka.size, rng, lo, hi))
+    kb = np.unique((np.repeat(np.arange(k, dtype=np.int64), 100) * m + rng.integers(0, m, k * 100)))
+    B = I.csr_from_keys(k, m, kb, I.draw_values(sr, kb.size, rng, lo, hi))
+    a = dsg.Matrix.from_csr(ctx, A, sr)
+    b = dsg.Matrix.from_csr(ctx, B, sr)
+    P = dsg.Product(ctx, a, b, bloom=True)
+    # change 60 entries of row 0 (value changes and deletions), nothing in B
+    rows = np.zeros(60, np.int32)
+    cols = np.arange(60, dtype=np.int32)
+    vals = I.draw_values(sr, 60, rng, lo, hi)
+    ops = np.where(np.arange(60) % 3 == 0, 1, 0).astype(np.uint8)
+    bat = I.Batch(rows, cols, vals, ops)
+    a.apply(*to_dev(bat))
+    rs = P.update()
+    st = P.stats()
+    assert st["path"] == 2 and st["entries"] > 4096
+    ha2, _ = oracle.apply(sr, oracle.Csr.of(A), rows, cols, vals, ops)
+    want = oracle.spgemm(sr, ha2, oracle.Csr.of(B))
+    got = P.export()
+    assert_same_csr(sr, got, want, "C'")
+    assert got.val.tobytes() == want.val.tobytes()
+    same_bloom(P.export_bloom(), oracle.bloom(ha2, oracle.Csr.of(B)), "F'")
+    before = oracle.spgemm(sr, oracle.Csr.of(A), oracle.Csr.of(B))
+    assert np.array_equal(rs.row_ids(), changed_rows(before, want))
+    P.destroy()
+    b.destroy()
+    a.destroy()
+
+
+def test_general_several_applies_fall_back(ctx):
+    """Two applies before one update: the change log holds one apply, so the
+    row path runs and F is built again -- same C and F as the oracle."""
+    say("general update fallback")
+    sr = I.MIN_PLUS_F32
+    A = I.rmat_csr(10, 8, sr, stream=1160, lo=1, hi=100)
+    a = dsg.Matrix.from_csr(ctx, A, sr)
+    P = dsg.Product(ctx, a, a, bloom=True)
+    bs = I.disjoint_batches(A, sr, [50, 50, 50], stream=1161, value_lo=1, value_hi=100)
+    ha = oracle.Csr.of(A)
+    C = oracle.spgemm(sr, ha, ha)
+    for t in range(2):
+        a.apply(*to_dev(bs[t]))
+        ha, _ = oracle.apply(sr, ha, bs[t].rows, bs[t].cols, bs[t].vals, bs[t].ops)
+    rs = P.update()
+    assert P.stats()["path"] == 0
+    want = oracle.spgemm(sr, ha, ha)
+    assert_same_csr(sr, P.export(), want, "C' after two applies")
+    same_bloom(P.export_bloom(), oracle.bloom(ha, ha), "F' after two applies")
+    assert np.array_equal(rs.row_ids(), changed_rows(C, want))
+    # and the next single apply takes the general path again
+    a.apply(*to_dev(bs[2]))
+    ha2, _ = oracle.apply(sr, ha, bs[2].rows, bs[2].cols, bs[2].vals, bs[2].ops)
+    P.update()
+    assert P.stats()["path"] == 2
+    assert_same_csr(sr, P.export(), oracle.spgemm(sr, ha2, ha2), "C' after the next apply")
+    same_bloom(P.export_bloom(), oracle.bloom(ha2, ha2), "F' after the next apply")
+    P.recompute_static()
+    same_bloom(P.export_bloom(), oracle.bloom(ha2, ha2), "F' after a static recompute")
+    P.destroy()
+    a.destroy()
+
+
+def test_general_argument_errors(ctx):
+    say("general update errors")
+    sr = I.MIN_PLUS_F32
+    A = I.rmat_csr(8, 4, sr, stream=1170, lo=1, hi=100)
+    a = dsg.Matrix.from_csr(ctx, A, sr)
+    with pytest.raises(dsg.DsgError) as e:
+        dsg.Product(ctx, a, a, trans_a=True, bloom=True)
+    assert e.value.status == dsg.E_UNSUPPORTED
+    P = dsg.Product(ctx, a, a, bloom=True)
+    with pytest.raises(dsg.DsgError) as e:
+        dsg.Batch(ctx, [P])
+    assert e.value.status == dsg.E_UNSUPPORTED
+    Q = dsg.Product(ctx, a, a)
+    with pytest.raises(dsg.DsgError) as e:
+        Q.export_bloom()
+    assert e.value.status == dsg.E_STATE
+    Q.destroy()
+    P.destroy()
+    a.destroy()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("batch", [100, 1000, 10000])
+def test_general_rmat16_full_size(ctx, batch):
+    """The benchmark's product at full size (R-MAT scale 16, edge factor 16,
+    (min,+) fp32, mix 50/25/25) by the general path: C' against the oracle
+    over all rows, F' against the oracle's Bloom matrix, exact reported rows."""
+    say(f"general update rmat16 full size, batch {batch}")
+    w = I.workload_rmat16_minplus(batch=batch, n_batches=1)
+    sr = w.semiring
+    a = dsg.Matrix.from_csr(ctx, w.A, sr)
+    P = dsg.Product(ctx, a, a, bloom=True)
+    ha = oracle.Csr.of(w.A)
+    C = oracle.spgemm(sr, ha, ha, nthreads=THREADS)
+    ba = w.batches_A[0]
+    a.apply(*to_dev(ba))
+    ha2, _ = oracle.apply(sr, ha, ba.rows, ba.cols, ba.vals, ba.ops)
+    rs = P.update()
+    assert P.stats()["path"] == 2
+    want = oracle.spgemm(sr, ha2, ha2, nthreads=THREADS)
+    assert_same_csr(sr, P.export(), want, "C'")
+    same_bloom(P.export_bloom(), oracle.bloom(ha2, ha2), "F'")
+    assert np.array_equal(rs.row_ids(), changed_rows(C, want))
+    P.destroy()
+    a.destroy()
