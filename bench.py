@@ -72,33 +72,50 @@ def measured_traffic(kernel: str, workload: str, batch: int):
     return rec.get("traffic_bytes_per_launch")
 
 
-def cpu_baseline(w, n_batches: int, budget_s: float = 20.0):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, n_batches: int, budget_s: float = 12.0):
     """The oracle as it stands: apply the batch, recompute C' = A'B' from
-    scratch; timed on this host's cores, on a bounded number of batches."""
+    scratch; timed on this host's cores (OpenMP over rows, every thread the
+    host gives this process) and on one thread, each on a bounded number of
+    batches (the first that end past budget_s seconds)."""
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
-    A = oracle.Csr.of(w.A)
-    B = None if w.B is None else oracle.Csr.of(w.B)
-    done = 0
-    updates = 0
-    t0 = time.perf_counter()
-    for t in range(n_batches):
-        b = w.batches_A[t]
-        A, _ = oracle.apply(w.semiring, A, b.rows, b.cols, b.vals, b.ops)
-        updates += len(b)
-        if B is not None:
-            bb = w.batches_B[t]
-            B, _ = oracle.apply(w.semiring, B, bb.rows, bb.cols, bb.vals, bb.ops)
-            updates += len(bb)
-        oracle.spgemm(w.semiring, A, A if B is None else B, nthreads=threads)
-        done += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": updates / dt, "unit": "updates/s", "cores": threads, "kind": "oracle",
+
+    def leg(nthreads):
+        A = oracle.Csr.of(w.A)
+        B = None if w.B is None else oracle.Csr.of(w.B)
+        done = updates = 0
+        t0 = time.perf_counter()
+        for t in range(n_batches):
+            b = w.batches_A[t]
+            A, _ = oracle.apply(w.semiring, A, b.rows, b.cols, b.vals, b.ops)
+            updates += len(b)
+            if B is not None:
+                bb = w.batches_B[t]
+                B, _ = oracle.apply(w.semiring, B, bb.rows, bb.cols, bb.vals, bb.ops)
+                updates += len(bb)
+            oracle.spgemm(w.semiring, A, A if B is None else B, nthreads=nthreads)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        return updates / (time.perf_counter() - t0), done, time.perf_counter() - t0
+    v, done, dt = leg(threads)
+    v1, done1, dt1 = leg(1)
+    return {"value": v, "unit": "updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} batch(es) of the same workload: sequential apply + full static "
-                      f"recompute of C' ({dt:.1f} s)"}
+                      f"recompute of C' ({dt:.1f} s on {threads} threads); {done1} batch(es) on one "
+                      f"thread ({dt1:.1f} s)",
+            "single_thread_value": v1, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def bench_batched(args):
@@ -350,7 +367,7 @@ def bench_sweep(args):
         batches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (q.rows, q.cols, q.vals, q.ops))
                    for q in w.batches_A]
         rec = {"batch": b}
-        for path in ("row", "entry", "auto", "bloom"):
+        for path in args.sweep_paths:
             ctx = dsg.Context(0, stream=torch.cuda.current_stream(dev))
             t = ctx.get_tuning()
             t.update_path = {"row": 1, "entry": 2, "auto": 0, "bloom": 0}[path]
@@ -384,6 +401,9 @@ def bench_sweep(args):
                 rec["entry_taken"] = bool(st["path"] == 1)
                 rec["lost_per_batch"] = st["lost"]
                 rec["terms_per_batch"] = st["terms"]
+            # the static recompute on a product without the Bloom matrix (which
+            # would also rebuild F)
+            if path == next((x for x in args.sweep_paths if x != "bloom"), None):
                 ts = []
                 for _ in range(3):
                     torch.cuda.synchronize()
@@ -395,9 +415,11 @@ def bench_sweep(args):
             P.destroy()
             A.destroy()
             ctx.close()
-        rec["speedup_row"] = round(rec["static_ms"] / rec["row_ms"], 3)
-        rec["speedup_entry"] = round(rec["static_ms"] / rec["entry_ms"], 3)
-        rec["speedup_bloom"] = round(rec["static_ms"] / rec["bloom_ms"], 3)
+        if "static_ms" not in rec:
+            rec["static_ms"] = None
+        for path in args.sweep_paths:
+            if path != "auto" and rec["static_ms"]:
+                rec[f"speedup_{path}"] = round(rec["static_ms"] / rec[path + "_ms"], 3)
         log(f"[sweep] {json.dumps(rec)}")
         out.append(rec)
     print(json.dumps({"workload": args.workload, "sweep": out}), flush=True)
@@ -474,6 +496,8 @@ def main():
     ap.add_argument("--batch", type=int, default=10000)
     ap.add_argument("--sweep", type=int, nargs="*", default=None,
                     help="time the row and entry-granular paths and a static recompute at these batch sizes")
+    ap.add_argument("--sweep-paths", nargs="+", default=["row", "entry", "auto", "bloom"],
+                    choices=["row", "entry", "auto", "bloom"], help="paths the sweep times")
     ap.add_argument("--serve-scale", type=int, default=21, help="serve workload: log2 of the ER rows")
     ap.add_argument("--serve-requests", type=int, default=10000)
     ap.add_argument("--serve-calib", type=int, default=300)
@@ -607,7 +631,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
         cpu = cpu_baseline(w, K + W)
-        log(f"[bench] CPU oracle: {cpu['value']:.1f} updates/s on {cpu['cores']} threads")
+        log(f"[bench] CPU oracle: {cpu['value']:.1f} updates/s on {cpu['cores']} threads, "
+            f"{cpu['single_thread_value']:.1f} on one ({cpu['cpu_model']})")
     out = {
         "metric": "dynamic SpGEMM updates/s",
         "value": round(per_step_updates * K / wall, 2),

@@ -834,14 +834,38 @@ __global__ void k_zero_counters(unsigned long long* a, unsigned long long* b, in
   *c = 0;
 }
 
+// The transpose deltas of a planned apply (what k_commit / k_commit_heavy
+// write while committing), taken from the plan's outcomes before anything is
+// committed, so that the transpose index can be planned -- and its room
+// reserved -- before either matrix changes.
+template <int VSZ>
+__global__ void k_plan_deltas(Uniq U, const int64_t* d_nU, uint64_t cmask, int cbits, int tbits, uint64_t* dkey,
+                              uint8_t* dop, void* dval) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= *d_nU) return;
+  const uint8_t code = U.code[u];
+  if (!emits_delta(code)) return;
+  const uint64_t i = U.key[u] >> cbits, j = U.key[u] & cmask;
+  dkey[u] = (j << tbits) | i;
+  dop[u] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
+  store_raw<VSZ>(dval, u, U.fin[u]);
+}
+
+// Phases of one matrix's apply: PH_PLAN plans the unique updates (and, outside
+// graphs, reserves the room moved rows need, re-planning after a compaction);
+// PH_COMMIT commits them, writing the transpose deltas too unless they were
+// taken from the plan already (deltas_done).
+constexpr int PH_PLAN = 1, PH_COMMIT = 2;
+
 template <int SR, int VSZ>
 void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, const void* vals, int tbits,
-                        bool graph, const Guard& G) {
+                        bool graph, const Guard& G, int phases = PH_PLAN | PH_COMMIT, bool deltas_done = false) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   unsigned nb = blocks_for(n * 64, 256);
   const unsigned nh = (unsigned)std::max(1, c->num_cus);
   const unsigned nph = nh * HEAVY_PLAN_PER_CU;  // the heavy commit takes the same grid
+  if (phases & PH_PLAN) {
   hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
                      w.demand, G);
   hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
@@ -871,21 +895,39 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
                          w.U, w.demand, G);
     }
   }
+  }
+  if (!(phases & PH_COMMIT)) return;
   // (graph mode: the caller reserved the worst case, see apply_headroom)
+  uint64_t* dk = deltas_done ? nullptr : w.dkey;
   hipLaunchKernelGGL((k_commit<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, cbits, w.U,
-                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, n, w.err);
+                     (const uint32_t*)m->d_epoch, tbits, dk, w.dop, w.dval, n, w.err);
   hipLaunchKernelGGL((k_commit_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.U,
-                     (const uint32_t*)m->d_epoch, tbits, w.dkey, w.dop, w.dval, n, w.err);
+                     (const uint32_t*)m->d_epoch, tbits, dk, w.dop, w.dval, n, w.err);
 }
 
-// Steps 2-6 on keys/idx already filled (n entries, sentinel-padded allowed).
+// Steps 2-6 on keys/idx already filled (n entries, sentinel-padded allowed);
+// phases as launch_plan_commit (sorting, folding and the epoch bump belong to
+// the plan).
 void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint8_t* ops, const void* vals,
-              bool graph, bool presorted = false, const Guard& G = Guard()) {
+              bool graph, bool presorted = false, const Guard& G = Guard(), int phases = PH_PLAN | PH_COMMIT,
+              bool deltas_done = false) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   int cbits = bits_for(m->ncols);
   uint64_t sentinel = 1ull << key_bits;
   uint64_t cmask = (1ull << cbits) - 1;
+  int tbits = bits_for(m->nrows);
+  if (!(phases & PH_PLAN)) {
+    switch (m->sr) {
+      case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
+      case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
+      case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
+      case 3: launch_plan_commit<3, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
+      default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
+    }
+    DSG_HIP(hipGetLastError());
+    return;
+  }
   if (!presorted) radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s);
   unsigned nb = blocks_for(n, 256);
   hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, s, w.keys, n, cbits, sentinel, w.kh, w.rh);
@@ -903,19 +945,22 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
   else
     hipLaunchKernelGGL(k_fold<0>, dim3(nb), dim3(256), 0, s, w.keys, w.idx, n, cbits, ops, vals, w.kh,
                        w.ukpos, w.rh, w.urpos, w.nU, w.nR, w.U);
-  int tbits = bits_for(m->nrows);
   switch (m->sr) {
-    case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
-    case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
-    case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
-    case 3: launch_plan_commit<3, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
-    default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph, G); break;
+    case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G, phases, deltas_done); break;
+    case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G, phases, deltas_done); break;
+    case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G, phases, deltas_done); break;
+    case 3: launch_plan_commit<3, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G, phases, deltas_done); break;
+    default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph, G, phases, deltas_done); break;
   }
   DSG_HIP(hipGetLastError());
 }
 
-// Everything of mat_apply_device without host round trips, on caller-owned
-// workspaces (capturable in a graph).  Error flags stay on the device.
+// Everything of mat_apply_device.  In a graph (no host round trips, on
+// caller-owned workspaces, error flags left on the device) the matrix is
+// planned and committed, then its transpose index.  Outside graphs both are
+// planned first -- the transpose's deltas come from the matrix's plan -- and
+// room is reserved for both before either is committed, so that a failed
+// reservation (DSG_E_OOM) leaves both unchanged.
 void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
                     const uint8_t* d_ops, int64_t n, Work& w, Work* wt, bool graph) {
   hipStream_t s = m->ctx->stream;
@@ -923,22 +968,45 @@ void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const
   int kbits = cbits + bits_for(m->nrows);
   unsigned nb = blocks_for(n, 256);
   hipLaunchKernelGGL(k_batch_keys, dim3(nb), dim3(256), 0, s, d_rows, d_cols, n, cbits, w.keys, w.idx);
-  run_core(m, w, n, kbits, false, d_ops, d_vals, graph);
-  if (m->tidx) {
-    DMat* t = m->tidx;
-    int tk = bits_for(t->ncols) + bits_for(t->nrows);
-    hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, (const uint8_t*)w.U.code,
-                       (const int64_t*)w.nU, 1ull << tk, wt->keys, wt->idx, n);
-    run_core(t, *wt, n, tk, true, w.dop, t->vsz ? w.dval : nullptr, graph);
+  DMat* t = m->tidx;
+  if (graph || !t) {
+    run_core(m, w, n, kbits, false, d_ops, d_vals, graph);
+    if (t) {
+      int tk = bits_for(t->ncols) + bits_for(t->nrows);
+      hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, (const uint8_t*)w.U.code,
+                         (const int64_t*)w.nU, 1ull << tk, wt->keys, wt->idx, n);
+      run_core(t, *wt, n, tk, true, w.dop, t->vsz ? w.dval : nullptr, graph);
+    }
+    return;
   }
+  run_core(m, w, n, kbits, false, d_ops, d_vals, false, false, Guard(), PH_PLAN);
+  const int tbits = bits_for(m->nrows);
+  const uint64_t cmask = (1ull << cbits) - 1;
+  if (m->vsz == 8)
+    hipLaunchKernelGGL(k_plan_deltas<8>, dim3(nb), dim3(256), 0, s, w.U, (const int64_t*)w.nU, cmask, cbits, tbits,
+                       w.dkey, w.dop, w.dval);
+  else if (m->vsz == 4)
+    hipLaunchKernelGGL(k_plan_deltas<4>, dim3(nb), dim3(256), 0, s, w.U, (const int64_t*)w.nU, cmask, cbits, tbits,
+                       w.dkey, w.dop, w.dval);
+  else
+    hipLaunchKernelGGL(k_plan_deltas<0>, dim3(nb), dim3(256), 0, s, w.U, (const int64_t*)w.nU, cmask, cbits, tbits,
+                       w.dkey, w.dop, w.dval);
+  int tk = bits_for(t->ncols) + bits_for(t->nrows);
+  hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, (const uint8_t*)w.U.code,
+                     (const int64_t*)w.nU, 1ull << tk, wt->keys, wt->idx, n);
+  const void* tvals = t->vsz ? (const void*)w.dval : nullptr;
+  run_core(t, *wt, n, tk, true, w.dop, tvals, false, false, Guard(), PH_PLAN);
+  // a compaction of the transpose does not move the matrix: its plan stands
+  run_core(m, w, n, kbits, false, d_ops, d_vals, false, false, Guard(), PH_COMMIT, true);
+  run_core(t, *wt, n, tk, true, w.dop, tvals, false, false, Guard(), PH_COMMIT);
 }
 
-// Keep the unique keys of this apply with their values before and after and
-// their outcomes: the entry-granular product update reads them.
-void keep_log(DMat* m, Work& w, int64_t n) {
+// Room for the log of an apply of n updates (taken before the apply changes
+// anything, so that a failed allocation leaves the matrix as it was).
+void reserve_log(DMat* m, int64_t n) {
   Ctx* c = m->ctx;
-  hipStream_t s = c->stream;
   if (m->log_cap < n) {
+    m->log_seq = 0;  // the held log goes with its buffers
     ctx_free(c, m->log_key, (size_t)m->log_cap * 8);
     ctx_free(c, m->log_old, (size_t)m->log_cap * 8);
     ctx_free(c, m->log_new, (size_t)m->log_cap * 8);
@@ -954,6 +1022,13 @@ void keep_log(DMat* m, Work& w, int64_t n) {
     m->log_cap = cap;
   }
   if (!m->d_log_n) m->d_log_n = (int64_t*)ctx_alloc(c, 64);
+}
+
+// Keep the unique keys of this apply with their values before and after and
+// their outcomes: the entry-granular and general-update product paths read
+// them.  reserve_log(m, n) must have run.
+void keep_log(DMat* m, Work& w, int64_t n) {
+  hipStream_t s = m->ctx->stream;
   DSG_HIP(hipMemcpyAsync(m->log_key, w.U.key, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
   DSG_HIP(hipMemcpyAsync(m->log_old, w.U.old, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
   DSG_HIP(hipMemcpyAsync(m->log_new, w.U.fin, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
@@ -1053,6 +1128,7 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   Work w = carve_work(ctx_scratch(c, work_bytes(n, deltas)), n, deltas);
   Work wt;
   if (deltas) wt = carve_work(ctx_scratch2(c, work_bytes(n, false)), n, false);
+  reserve_log(m, n);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) ctx_timing_begin(c, "apply", 0.0, &e0, &e1);
   apply_pipeline(m, d_rows, d_cols, d_vals, d_ops, n, w, deltas ? &wt : nullptr, false);

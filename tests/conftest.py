@@ -19,3 +19,13 @@ def pytest_configure(config):
 def orc():
     import oracle
     return oracle.lib()
+
+
+def pytest_terminal_summary(terminalreporter, exitstatus, config):
+    """How the fp64 parity comparisons of the session went (bit for bit, or
+    within the tolerance, and how often only the cancellation clause of the
+    tolerance held)."""
+    import sys as _sys
+    gu = _sys.modules.get("gpu_util")
+    if gu is not None and gu.FP64_TALLY["comparisons"]:
+        terminalreporter.write_line(f"fp64 parity: {gu.FP64_TALLY}")

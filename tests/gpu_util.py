@@ -11,6 +11,11 @@ from paper_2202_08808_amd import inputs as I
 U = 2.0 ** -53
 THREADS = max(1, min(16, os.cpu_count() or 1))
 
+# fp64 comparisons of the session: how many were bit for bit, how many needed
+# the tolerance, and how many entries passed only through the cancellation
+# clause (beyond 1e-12 relative, within the recursive-summation bound)
+FP64_TALLY = {"comparisons": 0, "bitwise": 0, "entries": 0, "entries_differing": 0, "cancellation_clause": 0}
+
 
 def assert_same_csr(sr, got, want, what="", A=None, B=None):
     """Structure bit-exact.  Values bit-exact for int64 and min-plus; for fp64
@@ -22,13 +27,18 @@ def assert_same_csr(sr, got, want, what="", A=None, B=None):
     assert np.array_equal(np.asarray(got.col), np.asarray(want.col)), f"{what}: columns differ"
     gv = np.ascontiguousarray(got.val)
     wv = np.ascontiguousarray(want.val)
+    if sr == I.PLUS_TIMES_F64:
+        FP64_TALLY["comparisons"] += 1
+        FP64_TALLY["entries"] += int(wv.size)
     if gv.tobytes() == wv.tobytes():
+        if sr == I.PLUS_TIMES_F64:
+            FP64_TALLY["bitwise"] += 1
         return
     if sr != I.PLUS_TIMES_F64:
         idx = np.nonzero(gv.view(np.int32 if gv.itemsize == 4 else np.int64) !=
                          wv.view(np.int32 if wv.itemsize == 4 else np.int64))[0][:5]
         raise AssertionError(f"{what}: values differ at {idx}: got {gv[idx]} want {wv[idx]}")
-    tol = 1e-12 * np.abs(wv)
+    tol = rel = 1e-12 * np.abs(wv)
     if A is not None and B is not None:
         absA = oracle.Csr(A.nrows, A.ncols, A.row_ptr, A.col, np.abs(A.val))
         absB = oracle.Csr(B.nrows, B.ncols, B.row_ptr, B.col, np.abs(B.val))
@@ -39,6 +49,8 @@ def assert_same_csr(sr, got, want, what="", A=None, B=None):
         cnt = oracle.spgemm(I.PLUS_TIMES_F64, ones(A), ones(B), nthreads=THREADS)
         tol = np.maximum(tol, 2.0 * cnt.val * U * mag.val)
     err = np.abs(gv - wv)
+    FP64_TALLY["entries_differing"] += int(np.count_nonzero(gv.view(np.int64) != wv.view(np.int64)))
+    FP64_TALLY["cancellation_clause"] += int(np.count_nonzero((err > rel) & (err <= tol)))
     bad = np.nonzero(err > tol)[0]
     assert bad.size == 0, f"{what}: {bad.size} fp64 values outside tolerance, e.g. {bad[:5]} {gv[bad[:5]]} {wv[bad[:5]]}"
 

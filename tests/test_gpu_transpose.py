@@ -277,7 +277,7 @@ def test_transposed_argument_errors(ctx):
         dsg.Product(ctx, A, B, trans_b=True)        # (20 x 30)(40 x 20)
     assert e.value.status == dsg.E_STATE
     h = dsg.P()
-    st = ctx.L.dsg_prod_create(ctx.h, A.h, B.h, 0x4, dsg.ctypes.byref(h))
+    st = ctx.L.dsg_prod_create(ctx.h, A.h, B.h, 0x8, dsg.ctypes.byref(h))
     assert st == dsg.E_ARG
     P.destroy()
     A.destroy()
