@@ -107,6 +107,26 @@ typedef struct {
  * device bytes the context may hold (0: no cap); exceeding it gives
  * DSG_E_OOM. */
 dsg_status dsg_ctx_create(int device, void* hip_stream, size_t mem_budget, dsg_ctx** out);
+/* Device memory from the caller's allocator instead of hipMalloc / hipFree
+ * (a framework's caching allocator, a pool): once set, every device
+ * allocation of the context -- matrix pools, products, workspaces, scratch --
+ * is alloc(bytes, stream, user) and is returned through free(ptr, bytes,
+ * stream, user), with the context's HIP stream; the library uses a block
+ * only in that stream's order (other streams it forks join it before the
+ * block is freed).  alloc returns NULL when it cannot allocate (DSG_E_OOM);
+ * both may be called from the served form's threads.  The memory budget
+ * still applies.  Set before the context allocates anything (DSG_E_STATE
+ * afterwards); a = NULL keeps hipMalloc.  This is the allocator callback the
+ * problem's boundary leaves to the caller: the library holds no device
+ * memory of its own beyond what it asks for here (and the fixed staging
+ * array of dsg_rows_export_noalloc). */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* user);
+  void* user;
+} dsg_allocator;
+dsg_status dsg_ctx_set_allocator(dsg_ctx* ctx, const dsg_allocator* a);
+
 /* Destroy a context.  DSG_E_STATE while it still owns matrices or products. */
 dsg_status dsg_ctx_destroy(dsg_ctx* ctx);
 /* Message describing the last failure on this context (never NULL). */

@@ -34,10 +34,15 @@ void* ctx_alloc(Ctx* c, size_t bytes) {
     throw DsgError{DSG_E_OOM, "memory budget exceeded (" + std::to_string(c->held + bytes) + " > " +
                                   std::to_string(c->budget) + " bytes)"};
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess || !p) {
-    (void)hipGetLastError();
-    throw DsgError{DSG_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  if (c->allocator.alloc) {
+    p = c->allocator.alloc(bytes, (void*)c->stream, c->allocator.user);
+    if (!p) throw DsgError{DSG_E_OOM, "the caller's allocator refused " + std::to_string(bytes) + " bytes"};
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw DsgError{DSG_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
   }
   c->held += bytes;
   return p;
@@ -47,7 +52,8 @@ void ctx_free(Ctx* c, void* p, size_t bytes) {
   if (!p) return;
   if (bytes == 0) bytes = 1;
   std::lock_guard<std::mutex> lk(c->alloc_mu);
-  (void)hipFree(p);
+  if (c->allocator.alloc) c->allocator.free(p, bytes, (void*)c->stream, c->allocator.user);
+  else (void)hipFree(p);
   c->held -= std::min(c->held, bytes);
 }
 
@@ -280,6 +286,16 @@ extern "C" dsg_status dsg_ctx_destroy(dsg_ctx* ctx) {
   if (c.join_ev) (void)hipEventDestroy(c.join_ev);
   if (c.own_stream) (void)hipStreamDestroy(c.stream);
   delete ctx;
+  return DSG_OK;
+}
+
+extern "C" dsg_status dsg_ctx_set_allocator(dsg_ctx* ctx, const dsg_allocator* a) {
+  if (!ctx) return fail(nullptr, DSG_E_ARG, "ctx is NULL");
+  if (a && (!a->alloc || !a->free)) return fail(ctx, DSG_E_ARG, "allocator without alloc or free");
+  std::lock_guard<std::mutex> lk(ctx->c.alloc_mu);
+  if (ctx->c.held > 0) return fail(ctx, DSG_E_STATE, "the context already holds device memory");
+  if (a) ctx->c.allocator = *a;
+  else ctx->c.allocator = dsg_allocator{};
   return DSG_OK;
 }
 

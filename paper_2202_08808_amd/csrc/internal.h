@@ -96,6 +96,7 @@ struct Ctx {
   bool own_stream = false;
   size_t budget = 0;
   size_t held = 0;
+  dsg_allocator allocator{};   // the caller's allocator (alloc == nullptr: hipMalloc / hipFree)
   std::mutex alloc_mu;  // ctx_alloc / ctx_free may run on a server's threads
   std::string last_error = "";
   bool served = false;  // owned by a server thread: the ABI refuses other calls

@@ -92,9 +92,33 @@ class ServerStats(ctypes.Structure):
 
 PENDING = -1
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def torch_allocator(device: int = 0) -> Allocator:
+    """dsg_allocator callbacks on PyTorch's caching allocator: blocks come from
+    torch.cuda.caching_allocator_alloc on the context's stream."""
+    import torch
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device, stream=int(stream or 0))
+        except RuntimeError:
+            return None
+
+    def free(ptr, nbytes, stream, user):
+        torch.cuda.caching_allocator_delete(ptr)
+    return Allocator(_ALLOC_FN(alloc), _FREE_FN(free), None)
+
 SIGNATURES = {
     "dsg_ctx_create": [ctypes.c_int, P, ctypes.c_size_t, P],
     "dsg_ctx_destroy": [P],
+    "dsg_ctx_set_allocator": [P, P],
     "dsg_ctx_synchronize": [P],
     "dsg_ctx_memory": [P, P],
     "dsg_ctx_set_timing": [P, ctypes.c_int],
@@ -191,13 +215,20 @@ def _ptr(a):
 
 
 class Context:
-    def __init__(self, device: int = 0, stream=None, budget: int = 0):
-        """stream: a torch.cuda.Stream (or None for the library's own)."""
+    def __init__(self, device: int = 0, stream=None, budget: int = 0, allocator=None):
+        """stream: a torch.cuda.Stream (or None for the library's own).
+        allocator: None (hipMalloc), "torch" (PyTorch's caching allocator)
+        or an Allocator."""
         self.L = lib()
         h = P()
         s = None if stream is None else P(stream.cuda_stream)
         self._check(self.L.dsg_ctx_create(device, s, budget, ctypes.byref(h)), None)
         self.h = h
+        self._allocator = None
+        if allocator is not None:
+            a = torch_allocator(device) if allocator == "torch" else allocator
+            self._check(self.L.dsg_ctx_set_allocator(self.h, ctypes.byref(a)))
+            self._allocator = a  # the callbacks live as long as the context
 
     def _check(self, st, h="self"):
         if st != OK:

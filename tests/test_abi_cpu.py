@@ -55,7 +55,7 @@ def test_no_device_reports_device_error():
 # ctypes mirror of each struct the header declares
 MIRRORS = {"dsg_rows": "Rows", "dsg_tuning": "Tuning", "dsg_update_stats": "Stats",
            "dsg_update_set": "UpdateSet", "dsg_batch_stats": "BatchStats", "dsg_server_cfg": "ServerCfg",
-           "dsg_server_result": "ServerResult", "dsg_server_stats": "ServerStats"}
+           "dsg_server_result": "ServerResult", "dsg_server_stats": "ServerStats", "dsg_allocator": "Allocator"}
 
 
 def test_binding_structs_match_the_header(tmp_path):
