@@ -118,6 +118,70 @@ def cpu_baseline(w, n_batches: int, budget_s: float = 12.0):
             "single_thread_value": v1, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
+OTHER_CONFIGS = [("rmat12", 100), ("stencil", 0), ("er", 1000), ("er", 10000)]
+
+
+def bench_other_configs(steps: int = 5, warmup: int = 1):
+    """The other evaluation workloads, briefly, on the same GPU: median ms of
+    apply + update per batch (every phase on the context's stream, batches
+    resident in HBM), the static recompute of the same product, and the path
+    the update took.  R-MAT scale 12 int64 with 100 insertions, the stencil
+    fp64 A B with 1e4 changes + 1e3 insertions in each operand, the
+    Erdos-Renyi 2^21 min-plus product at 1e3 and 1e4 updates."""
+    import torch
+    from paper_2202_08808_amd import dsg
+    dev = torch.device("cuda:0")
+    out = []
+    for name, b in OTHER_CONFIGS:
+        t0 = time.perf_counter()
+        w = make_workload(name, b, steps + warmup)
+        gen_s = time.perf_counter() - t0
+        ctx = dsg.Context(0, stream=torch.cuda.current_stream(dev))
+        A = dsg.Matrix.from_csr(ctx, w.A, w.semiring)
+        B = A if w.B is None else dsg.Matrix.from_csr(ctx, w.B, w.semiring)
+        P = dsg.Product(ctx, A, B)
+
+        def dev_batch(q):
+            return [torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (q.rows, q.cols, q.vals, q.ops)]
+        ba = [dev_batch(q) for q in w.batches_A]
+        bb = [dev_batch(q) for q in w.batches_B] if w.B is not None else None
+        per = len(w.batches_A[0]) + (len(w.batches_B[0]) if w.B is not None else 0)
+        ts, paths = [], []
+        for k in range(warmup + steps):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            A.apply(*ba[k])
+            if bb is not None:
+                B.apply(*bb[k])
+            P.update()
+            torch.cuda.synchronize()
+            if k >= warmup:
+                ts.append(time.perf_counter() - t1)
+                paths.append(P.stats()["path"])
+        st = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            P.recompute_static()
+            torch.cuda.synchronize()
+            st.append(time.perf_counter() - t1)
+        ms = float(np.median(ts)) * 1e3
+        sms = float(np.median(st)) * 1e3
+        rec = {"workload": w.name, "n": w.A.nrows, "nnz_A": w.A.nnz, "nnz_B": None if w.B is None else w.B.nnz,
+               "nnz_C": P.nnz(), "updates_per_batch": per, "ms_per_step": round(ms, 4),
+               "updates_per_s": round(per / ms * 1e3, 1), "static_recompute_ms": round(sms, 4),
+               "speedup_vs_static_gpu_recompute": round(sms / ms, 3),
+               "paths": sorted(set({0: "rows", 1: "entries", 2: "bloom"}[x] for x in paths)), "steps": steps}
+        log(f"[bench] {json.dumps(rec)} (inputs in {gen_s:.1f}s)")
+        out.append(rec)
+        P.destroy()
+        if B is not A:
+            B.destroy()
+        A.destroy()
+        ctx.close()
+    return out
+
+
 def bench_batched(args):
     """Batched form: independent R-MAT instances (scale ~ U{10..16}, edge
     factor ~ U{4,8,16,32}, int64 plus-times and min-plus alternating, one
@@ -506,6 +570,8 @@ def main():
     ap.add_argument("--serve-budget", type=int, default=4096, help="serve workload: memory budget in MiB")
     ap.add_argument("--static-reps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="skip the short runs of the other evaluation workloads")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy a buffer of this many MiB device to device three times (reference "
                          "dispatches for the HBM byte counters)")
@@ -627,6 +693,10 @@ def main():
                 "kernel": dom_name,
                 "launches": d["launches"], "avg_launch_ms": round(d["ms"] / max(d["launches"], 1), 4),
                 "bytes_per_launch": round(d["bytes"] / max(d["launches"], 1), 1)}
+    others = None
+    if not args.no_other_configs:
+        log("[bench] other evaluation workloads ...")
+        others = bench_other_configs()
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline ...")
@@ -668,6 +738,7 @@ def main():
         "kernels_steps": EXTRA,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_configs": others,
     }
     P.destroy()
     if B is not A:

@@ -827,6 +827,19 @@ Work carve_work(void* base, int64_t n, bool deltas) {
 }
 
 __global__ void k_bump_epoch(uint32_t* e) { *e += 1; }
+
+// Entries of the rows an apply touches, before it changes them (the rows its
+// plan streams): one atomic per workgroup.
+__global__ __launch_bounds__(256) void k_touched_len(const int32_t* urow, const int64_t* d_nR, const int32_t* row_len,
+                                                     unsigned long long* acc) {
+  __shared__ unsigned long long sum;
+  if (threadIdx.x == 0) sum = 0;
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < *d_nR) atomicAdd(&sum, (unsigned long long)row_len[urow[r]]);
+  __syncthreads();
+  if (threadIdx.x == 0 && sum) atomicAdd(acc, sum);
+}
 __global__ void k_zero_u64(unsigned long long* a) { *a = 0; }
 __global__ void k_zero_counters(unsigned long long* a, unsigned long long* b, int* c) {
   *a = 0;
@@ -962,7 +975,7 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
 // room is reserved for both before either is committed, so that a failed
 // reservation (DSG_E_OOM) leaves both unchanged.
 void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const void* d_vals,
-                    const uint8_t* d_ops, int64_t n, Work& w, Work* wt, bool graph) {
+                    const uint8_t* d_ops, int64_t n, Work& w, Work* wt, bool graph, bool count_touched = false) {
   hipStream_t s = m->ctx->stream;
   int cbits = bits_for(m->ncols);
   int kbits = cbits + bits_for(m->nrows);
@@ -980,6 +993,9 @@ void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const
     return;
   }
   run_core(m, w, n, kbits, false, d_ops, d_vals, false, false, Guard(), PH_PLAN);
+  if (count_touched)
+    hipLaunchKernelGGL(k_touched_len, dim3(nb), dim3(256), 0, s, (const int32_t*)w.U.urow, (const int64_t*)w.nR,
+                       (const int32_t*)m->row_len, w.demand + 2);
   const int tbits = bits_for(m->nrows);
   const uint64_t cmask = (1ull << cbits) - 1;
   if (m->vsz == 8)
@@ -996,6 +1012,9 @@ void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const
                      (const int64_t*)w.nU, 1ull << tk, wt->keys, wt->idx, n);
   const void* tvals = t->vsz ? (const void*)w.dval : nullptr;
   run_core(t, *wt, n, tk, true, w.dop, tvals, false, false, Guard(), PH_PLAN);
+  if (count_touched)
+    hipLaunchKernelGGL(k_touched_len, dim3(nb), dim3(256), 0, s, (const int32_t*)wt->U.urow, (const int64_t*)wt->nR,
+                       (const int32_t*)t->row_len, wt->demand + 2);
   // a compaction of the transpose does not move the matrix: its plan stands
   run_core(m, w, n, kbits, false, d_ops, d_vals, false, false, Guard(), PH_COMMIT, true);
   run_core(t, *wt, n, tk, true, w.dop, tvals, false, false, Guard(), PH_COMMIT);
@@ -1130,10 +1149,22 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   if (deltas) wt = carve_work(ctx_scratch2(c, work_bytes(n, false)), n, false);
   reserve_log(m, n);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (c->timing) ctx_timing_begin(c, "apply", 0.0, &e0, &e1);
-  apply_pipeline(m, d_rows, d_cols, d_vals, d_ops, n, w, deltas ? &wt : nullptr, false);
+  const bool timed = c->timing && ctx_timing_begin(c, "apply", 0.0, &e0, &e1);
+  const size_t tslot = c->timings.size() - (timed ? 1 : 0);
+  // (timed: the entries of the touched rows, counted before the commits change them)
+  unsigned long long* touched = (unsigned long long*)((char*)c->pinned + 256);
+  if (timed) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, w.demand + 2);
+    if (deltas) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, wt.demand + 2);
+  }
+  apply_pipeline(m, d_rows, d_cols, d_vals, d_ops, n, w, deltas ? &wt : nullptr, false, timed);
   keep_log(m, w, n);
   if (c->timing) ctx_timing_end(c, e1);
+  if (timed) {
+    DSG_HIP(hipMemcpyAsync(touched, w.demand + 2, 8, hipMemcpyDeviceToHost, s));
+    touched[1] = 0;
+    if (deltas) DSG_HIP(hipMemcpyAsync(touched + 1, wt.demand + 2, 8, hipMemcpyDeviceToHost, s));
+  }
   int* h = (int*)c->pinned;
   int64_t* hn = (int64_t*)((char*)c->pinned + 64);
   h[1] = 0;
@@ -1144,6 +1175,18 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(h[0] == 0 && h[1] == 0, DSG_E_DEVICE, "internal: pool overflow while applying a batch");
   m->h_log_n = *hn;
+  if (timed && tslot < c->timings.size()) {
+    // algorithmic bytes: the batch read (row, column, value, op), the touched
+    // rows streamed by the plan, the unique updates written; for the
+    // transpose index its deltas, its touched rows and its writes
+    const double v = (double)m->vsz, nu = (double)*hn;
+    double bytes = (double)n * (9.0 + v) + (double)touched[0] * (4.0 + v) + nu * (4.0 + v);
+    if (deltas) {
+      const double vt = (double)m->tidx->vsz;
+      bytes += nu * (9.0 + vt) + (double)touched[1] * (4.0 + vt) + nu * (4.0 + vt);
+    }
+    c->timings[tslot].bytes = bytes;
+  }
   m->apply_seq++;
   m->log_seq = m->apply_seq;
 }
