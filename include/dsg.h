@@ -193,7 +193,12 @@ dsg_status dsg_mat_create(dsg_ctx* ctx, int32_t nrows, int32_t ncols, dsg_semiri
 dsg_status dsg_mat_apply(dsg_mat* m, const int32_t* rows, const int32_t* cols, const void* vals,
                          const uint8_t* ops, int64_t n, uint32_t flags);
 
+/* Number of stored entries of the matrix, nnz(A) in the notation of
+ * Section 3 (a dynamic matrix of Section 4: slots that hold a tombstone are
+ * not counted).  Synchronises with the device.  Errors: DSG_E_ARG (null). */
 dsg_status dsg_mat_nnz(dsg_mat* m, int64_t* nnz);
+/* Shape and semiring the matrix was created with (any pointer may be NULL).
+ * DSG_E_ARG for a NULL or destroyed matrix. */
 dsg_status dsg_mat_shape(const dsg_mat* m, int32_t* nrows, int32_t* ncols, dsg_semiring* sr);
 
 /* Copy the matrix to host CSR arrays in canonical form (rows sorted by
@@ -276,14 +281,21 @@ dsg_status dsg_prod_update(dsg_prod* p, uint32_t flags, dsg_rows* changed);
 
 /* Views of nq rows of C (rows: host int32 array, or device with
  * DSG_INPUT_DEVICE; any order, repeats allowed; out->rows lists them as
- * given).  DSG_E_RANGE for a bad row. */
+ * given).  C is kept as a dynamic matrix (Section 4; Section 6.1 keeps C' in
+ * that form), so a row is read in place by its offset and length, without a
+ * search.  The view points into C's storage: it holds until the next call
+ * that changes C (an update, a static recompute) or the next dsg_prod_rows
+ * on this product.  DSG_E_RANGE for a bad row. */
 dsg_status dsg_prod_rows(dsg_prod* p, const int32_t* rows, int32_t nq, uint32_t flags,
                          dsg_rows* out);
 
 /* Copy the rows of a view (from dsg_prod_update or dsg_prod_rows on this
  * product, still valid) to host CSR arrays in view order, each row sorted by
  * column: row_ptr[v->n + 1], col/val with room for cap entries.  With col ==
- * NULL only *nnz_out and row_ptr are written.  DSG_E_ARG if cap < nnz. */
+ * NULL only *nnz_out and row_ptr are written.  The rows are those of the
+ * dynamic matrix C' (Sections 4 and 6.1); the host arrays are the plain CSR
+ * of Section 4's static matrices.  DSG_E_ARG if cap < nnz; a view that no
+ * longer holds is not detected. */
 dsg_status dsg_rows_export(dsg_prod* p, const dsg_rows* v, int64_t* row_ptr, int32_t* col, void* val,
                            int64_t cap, int64_t* nnz_out);
 
@@ -300,8 +312,12 @@ dsg_status dsg_rows_export(dsg_prod* p, const dsg_rows* v, int64_t* row_ptr, int
 dsg_status dsg_rows_export_noalloc(dsg_prod* p, const dsg_rows* v, int64_t* row_ptr, int32_t* col, void* val,
                                    int64_t cap, int64_t* nnz_out);
 
+/* nnz(C) (Section 3), as dsg_mat_nnz.  Synchronises with the device. */
 dsg_status dsg_prod_nnz(dsg_prod* p, int64_t* nnz);
-/* Canonical host CSR of C, as dsg_mat_export. */
+/* Canonical host CSR of C = op(A)·op(B) over the product's semiring
+ * (Section 3), as dsg_mat_export: rows sorted by column, tombstones dropped.
+ * row_ptr[nrows + 1]; col/val with room for cap entries; col == NULL writes
+ * only row_ptr and *nnz_out.  DSG_E_ARG if cap < nnz. */
 dsg_status dsg_prod_export(dsg_prod* p, int64_t* row_ptr, int32_t* col, void* val, int64_t cap,
                            int64_t* nnz_out);
 
@@ -398,6 +414,7 @@ typedef struct {
   double direct_ms;   /* their time (apply and update), beside the replay */
 } dsg_batch_stats;
 dsg_status dsg_batch_info(const dsg_batch* b, dsg_batch_stats* out);
+/* Free the batched form's graph and buffers; its products are untouched. */
 dsg_status dsg_batch_destroy(dsg_batch* b);
 
 /* ---- served form: a request loop over resident A, B and C ----
