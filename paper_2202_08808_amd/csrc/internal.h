@@ -47,6 +47,14 @@ struct Ctx;
 // Outcome of one unique update key when it is applied to a row.
 enum : uint8_t { UPD_NOP = 0, UPD_INS = 1, UPD_DEL = 2, UPD_OVR = 3, UPD_LOST = 4 };
 
+// Entry pools (col and val) are allocated POOL_PAD entries beyond their
+// capacity.  A kernel may then read a window of up to POOL_PAD entries from
+// any position inside a row without a per-lane bounds check: the entries
+// past the row are read and discarded, never used as content.
+constexpr int64_t POOL_PAD = 256;
+inline size_t pool_bytes(int64_t cap, int entry_size) { return (size_t)(cap + POOL_PAD) * (size_t)entry_size; }
+
+
 // Device-resident dynamic matrix: every row owns a slot range
 // [row_off[i], row_off[i] + row_cap[i]) of the column/value pools and uses its
 // first row_len[i] slots, in no particular column order.  Rows that outgrow

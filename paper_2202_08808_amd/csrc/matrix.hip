@@ -191,8 +191,8 @@ DMat* mat_create(Ctx* c, int32_t nrows, int32_t ncols, int sr, const int64_t* d_
       total = read_i64(c, d_total);
     }
     m->pool_cap = total + total / 4 + 1024;
-    m->col = (int32_t*)ctx_alloc(c, (size_t)m->pool_cap * 4);
-    if (m->vsz) m->val = ctx_alloc(c, (size_t)m->pool_cap * m->vsz);
+    m->col = (int32_t*)ctx_alloc(c, pool_bytes(m->pool_cap, 4));
+    if (m->vsz) m->val = ctx_alloc(c, pool_bytes(m->pool_cap, m->vsz));
     if (d_rp && nrows > 0) {
       unsigned nb = blocks_for((int64_t)nrows * 64, 256);
       if (m->vsz == 8)
@@ -226,8 +226,8 @@ void mat_destroy(DMat* m) {
   ctx_free(c, m->row_cap, n * 4);
   ctx_free(c, m->row_epoch, n * 4);
   ctx_free(c, m->d_top, 16);
-  ctx_free(c, m->col, (size_t)m->pool_cap * 4);
-  if (m->val) ctx_free(c, m->val, (size_t)m->pool_cap * m->vsz);
+  ctx_free(c, m->col, pool_bytes(m->pool_cap, 4));
+  if (m->val) ctx_free(c, m->val, pool_bytes(m->pool_cap, m->vsz));
   ctx_free(c, m->log_key, (size_t)m->log_cap * 8);
   ctx_free(c, m->log_old, (size_t)m->log_cap * 8);
   ctx_free(c, m->log_new, (size_t)m->log_cap * 8);
@@ -256,13 +256,13 @@ void mat_compact(DMat* m, int64_t extra) {
       ctx_free(c, scr, sb);
     }
     int64_t cap = total + extra + (total + extra) / 2 + 1024;
-    int32_t* ncol = (int32_t*)ctx_alloc(c, (size_t)cap * 4);
+    int32_t* ncol = (int32_t*)ctx_alloc(c, pool_bytes(cap, 4));
     void* nval = nullptr;
     if (m->vsz) {
       try {
-        nval = ctx_alloc(c, (size_t)cap * m->vsz);
+        nval = ctx_alloc(c, pool_bytes(cap, m->vsz));
       } catch (...) {
-        ctx_free(c, ncol, (size_t)cap * 4);
+        ctx_free(c, ncol, pool_bytes(cap, 4));
         throw;
       }
     }
@@ -280,8 +280,8 @@ void mat_compact(DMat* m, int64_t extra) {
       DSG_HIP(hipMemcpyAsync(m->row_off, new_off, nn * 8, hipMemcpyDeviceToDevice, s));
     }
     DSG_HIP(hipStreamSynchronize(s));
-    ctx_free(c, m->col, (size_t)m->pool_cap * 4);
-    if (m->val) ctx_free(c, m->val, (size_t)m->pool_cap * m->vsz);
+    ctx_free(c, m->col, pool_bytes(m->pool_cap, 4));
+    if (m->val) ctx_free(c, m->val, pool_bytes(m->pool_cap, m->vsz));
     m->col = ncol;
     m->val = nval;
     m->pool_cap = cap;
@@ -381,14 +381,14 @@ void mat_build_transpose(DMat* m) {
       hipLaunchKernelGGL(k_slack_of_len, dim3(blocks_for(nt, 256)), dim3(256), 0, s, nt, cnt, t->row_cap);
       exclusive_scan_i32_to_i64(t->row_cap, t->row_off, nt, d_total, scr, s);
       int64_t total = read_i64(c, d_total);
-      ctx_free(c, t->col, (size_t)t->pool_cap * 4);
-      if (t->val) ctx_free(c, t->val, (size_t)t->pool_cap * t->vsz);
+      ctx_free(c, t->col, pool_bytes(t->pool_cap, 4));
+      if (t->val) ctx_free(c, t->val, pool_bytes(t->pool_cap, t->vsz));
       t->col = nullptr;
       t->val = nullptr;
       t->pool_cap = total + total / 4 + 1024;
       t->version++;
-      t->col = (int32_t*)ctx_alloc(c, (size_t)t->pool_cap * 4);
-      if (t->vsz) t->val = ctx_alloc(c, (size_t)t->pool_cap * t->vsz);
+      t->col = (int32_t*)ctx_alloc(c, pool_bytes(t->pool_cap, 4));
+      if (t->vsz) t->val = ctx_alloc(c, pool_bytes(t->pool_cap, t->vsz));
       DSG_HIP(hipMemsetAsync(t->row_len, 0, (size_t)nt * 4, s));
       if (t->vsz == 8)
         hipLaunchKernelGGL(k_fill_transpose<8>, dim3(nb), dim3(256), 0, s, m->nrows, m->row_off, m->row_len,

@@ -678,9 +678,9 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   // Stage A entries [cbase, cbase + 512) (column k, value, B row offset and
   // length: the whole B row, or its column chunk `part` of the split copy)
   // and split them by B-row length with one 64-bit workgroup scan.  Packed
-  // fields: bits 0-23 tiles of long rows, 24-39 entries of short rows, 40-49
-  // short rows, 50-59 long rows (none overflows: at most 512 rows of at most
-  // 2^11 tiles, or of fewer than 64 entries).
+  // fields: bits 0-23 quads (256 entries) of long rows, 24-39 entries of
+  // short rows, 40-49 short rows, 50-59 long rows (none overflows: at most
+  // 512 rows of at most 2^15 quads, or of fewer than 64 entries).
   auto stage_split = [&](int32_t cbase, bool use_split, int part) {
     const int32_t t = cbase + tid;
     const bool act = tid < DENSE_ACHUNK && t < d;
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     }
     const bool lng = act && len >= LONG_ROW;
     const bool sht = act && len > 0 && len < LONG_ROW;
-    const uint64_t v = (lng ? (uint64_t)((len + 63) >> 6) : 0ull) | (sht ? (uint64_t)len << 24 : 0ull) |
+    const uint64_t v = (lng ? (uint64_t)((len + 255) >> 8) : 0ull) | (sht ? (uint64_t)len << 24 : 0ull) |
                        ((uint64_t)sht << 40) | ((uint64_t)lng << 50);
     uint64_t inc = wave_inclusive_scan(v);
     if (ln == 63) wscr64[wv] = inc;
@@ -738,46 +738,67 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     }
     grp.sync();
   };
-  // Every product of the staged chunk through round(pos, av, ok), UNR per lane at a time.
-  auto for_rounds = [&](auto&& round) {
-    // Long B rows as 64-entry tiles; wavefront w takes UNR consecutive
-    // tiles per round, rounds TSTRIDE tiles apart.  Lane l describes the
-    // (l % UNR)-th tile of the (l / UNR)-th of the next RPD rounds (one
-    // segment search per lane), and each round reads its tiles' base,
-    // length and A value from those lanes.
-    constexpr int RPD = 64 / UNR;  // rounds per description
-    constexpr int TSTRIDE = NWV * UNR;
+  // Every product of the staged chunk through round(jp, vp, av, ok), UNR per
+  // lane at a time: jp/vp point at the lane's B column index and value (in
+  // bcol/bval), av is the A value, ok whether the product exists.  Every
+  // pointer is readable, so the rounds load without branches.
+  auto for_rounds = [&](auto&& round, const int32_t* bcol, const void* bval) {
+    // Long B rows as quads: four 64-entry tiles, 256 entries of one row.
+    // Wavefront w takes QPR quads per round, rounds QSTRIDE quads apart.
+    // Lane l describes the (l % QPR)-th quad of the (l / QPR)-th of the next
+    // RPD rounds (one segment search per lane), and each round reads its
+    // quads' position, remaining length and A value from those lanes.  The
+    // four loads of a quad share one wave-uniform base address; lanes past
+    // the row's end read the next entries of the pool (or its padding) and
+    // are masked.
+    constexpr int QPR = UNR / 4;
+    constexpr int RPD = 64 / QPR;  // rounds per description
+    constexpr int QSTRIDE = NWV * QPR;
+    static_assert(UNR % 4 == 0 && 4 * 64 <= POOL_PAD, "quads of four tiles within the pool padding");
     const int nl = sp.nlong;
-    const int ntiles = sp.tpre[nl];
-    for (int tb0 = wv * UNR; tb0 < ntiles; tb0 += TSTRIDE * RPD) {
-      const int my = tb0 + (ln / UNR) * TSTRIDE + (ln % UNR);
+    const int nquads = sp.tpre[nl];
+    const uint32_t lane_c = (uint32_t)ln * 4u;
+    const uint32_t lane_v = (uint32_t)ln * (uint32_t)sizeof(V);
+    for (int qb0 = wv * QPR; qb0 < nquads; qb0 += QSTRIDE * RPD) {
+      const int my = qb0 + (ln / QPR) * QSTRIDE + (ln % QPR);
       int64_t mpos = 0;
       V ma = V(0);
       int32_t mrem = 0;
-      if (my < ntiles) {
+      if (my < nquads) {
         const int e = find_seg(sp.tpre, nl, my);
         const int t = sp.lidx[e];
-        const int32_t x0 = (my - sp.tpre[e]) << 6;
-        mrem = min(64, ch.so[t] - x0);
+        const int32_t x0 = (my - sp.tpre[e]) << 8;
+        mrem = ch.so[t] - x0;
         mpos = ch.b[t] + x0;
         ma = ch.a[t];
       }
-      for (int r = 0; r < RPD && tb0 + r * TSTRIDE < ntiles; ++r) {
-        int64_t pos[UNR];
+      for (int r = 0; r < RPD && qb0 + r * QSTRIDE < nquads; ++r) {
+        const int32_t* jp[UNR];
+        const V* vp[UNR];
         V av[UNR];
         bool ok[UNR];
-  #pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int src = r * UNR + u;
-          ok[u] = ln < __builtin_amdgcn_readlane(mrem, src);
-          pos[u] = lane64(mpos, src) + ln;
-          av[u] = lanev<V>(ma, src);
+#pragma unroll
+        for (int g = 0; g < QPR; ++g) {
+          const int src = r * QPR + g;
+          const int32_t rem = __builtin_amdgcn_readlane(mrem, src);
+          const int64_t q0 = lane64(mpos, src);
+          const V a = lanev<V>(ma, src);
+          const char* cb = (const char*)(bcol + q0);
+          const char* vb = (const char*)((const V*)bval + q0);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const int u = g * 4 + t;
+            jp[u] = (const int32_t*)(cb + lane_c + t * 256);
+            vp[u] = (const V*)(vb + lane_v + t * 64 * (int)sizeof(V));
+            av[u] = a;
+            ok[u] = t * 64 + ln < rem;
+          }
         }
-        round(pos, av, ok);
+        round(jp, vp, av, ok);
       }
     }
     // short B rows: 8-lane sub-groups, each streaming 4 rows at once (no
-    // search; 4 gathers in flight per lane)
+    // search; lanes past a row's end re-read its last entry)
     const int ns = sp.nshort;
     constexpr int NSG = DENSE_WG / 8;
     const int sg = tid >> 3, l8 = tid & 7;
@@ -786,7 +807,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       int32_t bl[4];
       V ba[4];
       int32_t mx = 0;
-  #pragma unroll
+#pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int e = eb + u * NSG;
         bl[u] = 0;
@@ -801,18 +822,21 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
         }
       }
       for (int32_t x = l8; x < mx; x += 2 * UNR) {
-        int64_t pos[UNR];
+        const int32_t* jp[UNR];
+        const V* vp[UNR];
         V av[UNR];
         bool ok[UNR];
-  #pragma unroll
+#pragma unroll
         for (int u = 0; u < UNR; ++u) {
           const int r = u & 3;
           const int32_t xx = x + (u >> 2) * 8;
           ok[u] = xx < bl[r];
-          pos[u] = bo[r] + xx;
+          const int64_t pp = bo[r] + min(xx, max(bl[r] - 1, 0));
+          jp[u] = bcol + pp;
+          vp[u] = (const V*)bval + pp;
           av[u] = ba[r];
         }
-        round(pos, av, ok);
+        round(jp, vp, av, ok);
       }
     }
   };
@@ -834,14 +858,17 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
     const int32_t expect = olen > 0 ? olen + (olen >> 3) + 64 : stage_n;
     if (expect <= HFILL) {
       bool over = false;
-      auto hash_round = [&](const int64_t* pos, const V* av, const bool* ok) {
+      auto hash_round = [&](const int32_t* const* jp, const V* const* vp, const V* av, const bool* ok) {
         int32_t j[UNR];
         V bv[UNR];
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
-          j[u] = ok[u] ? R.b_col[pos[u]] : -1;
-          bv[u] = ok[u] ? ldv<V>(R.b_val, pos[u]) : V(0);
+          j[u] = *jp[u];
+          bv[u] = *vp[u];
         }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u)
+          if (!ok[u]) j[u] = -1;
         uint32_t h[UNR];
         int32_t k[UNR];
 #pragma unroll
@@ -860,7 +887,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       };
       for (int32_t cbase = 0; cbase < d; cbase += DENSE_ACHUNK) {
         stage_split(cbase, false, 0);
-        for_rounds(hash_round);
+        for_rounds(hash_round, R.b_col, R.b_val);
         grp.sync();
       }
       if (grp.any(over, wscr)) {
@@ -987,14 +1014,17 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   for (int pc = 0; pc < passes; ++pc) {
     const int32_t c0 = pc * CH;
     const int32_t c1 = min(c0 + CH, R.ncols);
-    auto accumulate_round = [&](const int64_t* pos, const V* av, const bool* ok) {
+    auto accumulate_round = [&](const int32_t* const* jp, const V* const* vp, const V* av, const bool* ok) {
       int32_t j[UNR];
       V bv[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        j[u] = ok[u] ? bcol[pos[u]] : -1;
-        bv[u] = ok[u] ? ldv<V>(bval, pos[u]) : V(0);
+        j[u] = *jp[u];
+        bv[u] = *vp[u];
       }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+        if (!ok[u]) j[u] = -1;
       if constexpr (S::order_free) {
 #pragma unroll
         for (int u = 0; u < UNR; ++u) {
@@ -1010,7 +1040,7 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       const int cnt = min(DENSE_ACHUNK, d - cbase);
       if constexpr (S::order_free) {
         stage_split(cbase, split, pc);
-        for_rounds(accumulate_round);
+        for_rounds(accumulate_round, bcol, bval);
       } else {
         stage_chunk<V>(R, aoff, d, cbase, ch, grp, wscr, true, split ? pc : -1);
         for (int y = 0; y < cnt; ++y) {
@@ -1993,7 +2023,9 @@ void build_bsplit(DProd* p) {
   const int64_t cap = std::max<int64_t>(B->h_top_ub, 1);  // every row's slots lie below the pool top
   const size_t col_off = round256((size_t)nps * 8);
   const size_t val_off = col_off + round256((size_t)cap * 4);
-  const size_t bytes = val_off + round256((size_t)cap * vsz);
+  // (padded like the entry pools: windows of POOL_PAD entries may be read
+  // from any position inside a row)
+  const size_t bytes = val_off + round256((size_t)cap * vsz) + (size_t)POOL_PAD * 8;
   if (bytes > p->bsp_bytes) {
     if (p->bsp) ctx_free(c, p->bsp, p->bsp_bytes);
     p->bsp = nullptr;
