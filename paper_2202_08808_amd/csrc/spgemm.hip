@@ -620,24 +620,8 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
   // between chunks and rows: the drain that reads a chunk out clears it.
   __shared__ Acc acc[CH];
   __shared__ uint32_t bits[NW32];
-  // The A chunk and its split are dead while a chunk is drained, so their
-  // space doubles as the wavefronts' output buffers.
-  constexpr int OBN = sizeof(V) == 4 ? 256 : 192;  // buffered entries per wavefront
-  struct OutBuf {
-    int32_t col[NWV][OBN];
-    V val[NWV][OBN];
-  };
-  struct InBuf {
-    AChunk<V> ch;
-    ChunkSplit sp;
-  };
-  union Stage {
-    InBuf in;
-    OutBuf out;
-  };
-  __shared__ Stage st;
-  AChunk<V>& ch = st.in.ch;
-  ChunkSplit& sp = st.in.sp;
+  __shared__ AChunk<V> ch;
+  __shared__ ChunkSplit sp;
   __shared__ int wscr[16];
   __shared__ uint64_t wscr64[NWV];
   __shared__ int64_t bslot;
@@ -954,20 +938,30 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
         // read the table out (slot order) and clear it
         const bool write = changed && !parked;
         int32_t o = before;
-        for (int r = 0; r < HSEG; r += 64) {
-          const int sl = wv * HSEG + r + ln;
-          const int32_t kk = hk[sl];
-          const uint64_t b = __ballot(kk != -1);
-          if (kk != -1) {
-            if (write) {
+        constexpr int HU = 4;  // slot blocks of 64 read together per step
+        static_assert(HSEG % (64 * HU) == 0, "readout steps");
+        for (int r = 0; r < HSEG; r += 64 * HU) {
+          int32_t kk[HU];
+          Acc vv[HU];
+#pragma unroll
+          for (int u = 0; u < HU; ++u) {
+            const int sl = wv * HSEG + r + u * 64 + ln;
+            kk[u] = hk[sl];
+            vv[u] = hv[sl];
+          }
+#pragma unroll
+          for (int u = 0; u < HU; ++u) {
+            const int sl = wv * HSEG + r + u * 64 + ln;
+            const uint64_t b = __ballot(kk[u] != -1);
+            if (write && kk[u] != -1) {
               const int64_t pos = dest + o + __popcll(b & lt);
-              R.c_col[pos] = kk;
-              ((V*)R.c_val)[pos] = S::from_acc(hv[sl]);
+              R.c_col[pos] = kk[u];
+              ((V*)R.c_val)[pos] = S::from_acc(vv[u]);
             }
             hk[sl] = -1;
             hv[sl] = S::identity();
+            o += __popcll(b);
           }
-          o += __popcll(b);
         }
         if (write && tid == 0) {
           R.c_len[i] = nnew;
@@ -1108,62 +1102,38 @@ __global__ __launch_bounds__(DENSE_WG) void k_rows_dense(RowArgs R, const int32_
       if (grp.any(bad, wscr) || itot != ctot) changed = true;
       old_read = olen;
     }
-    // Read the chunk out 64 columns at a time in ascending column order and
-    // clear what was read.  When writing, each wavefront packs its entries
-    // into its LDS buffer and stores them to out[base + ...] in full runs.
+    // Read the chunk out in ascending column order and clear it: each step
+    // reads the bitmap words and accumulator slots of DU blocks of 64 columns
+    // together, and the touched columns of a block are stored straight to
+    // out[base + ...] at consecutive positions (one coalesced run per block;
+    // the cache merges the runs of consecutive blocks).
     auto drain = [&](int32_t* ocol, V* oval, int64_t base, int32_t limit, bool write) {
-      int32_t* bc = st.out.col[wv];
-      V* bv = st.out.val[wv];
-      int32_t o = before;  // row position of the first buffered entry
-      int32_t nb = 0;
-      auto flush = [&]() {
-        wave_sync();
-        for (int e = ln; e < nb; e += 64) {
-          const int64_t pos = base + o + e;
-          if (pos < limit) {
-            ocol[pos] = bc[e];
-            oval[pos] = bv[e];
-          }
-        }
-        wave_sync();
-        o += nb;
-        nb = 0;
-      };
-      // DU blocks of 64 columns per step: their bitmap words and touched
-      // accumulator slots are read together
-      constexpr int DU = OBN >= 256 ? 4 : 2;
-      static_assert(SEG % (64 * DU) == 0 && 64 * DU <= OBN, "drain steps");
+      int32_t o = before;  // row position of the wavefront's next entry
+      constexpr int DU = 4;
+      static_assert(SEG % (64 * DU) == 0, "drain steps");
       for (int r = 0; r < SEG; r += 64 * DU) {
         uint64_t b[DU];
         Acc a[DU];
-        int cnt = 0;
 #pragma unroll
         for (int u = 0; u < DU; ++u) {
           const int w0 = (wv * SEG + r + u * 64) >> 5;
           b[u] = (uint64_t)bits[w0] | ((uint64_t)bits[w0 + 1] << 32);
-          cnt += __popcll(b[u]);
+          a[u] = acc[wv * SEG + r + u * 64 + ln];
         }
 #pragma unroll
         for (int u = 0; u < DU; ++u) {
           const int x = wv * SEG + r + u * 64 + ln;
-          a[u] = ((b[u] >> ln) & 1ull) ? acc[x] : S::identity();
-        }
-        if (write && nb + cnt > OBN) flush();
-#pragma unroll
-        for (int u = 0; u < DU; ++u) {
-          if ((b[u] >> ln) & 1ull) {
-            const int x = wv * SEG + r + u * 64 + ln;
-            if (write) {
-              const int k = nb + __popcll(b[u] & lt);
-              bc[k] = c0 + x;
-              bv[k] = S::from_acc(a[u]);
+          if (write && ((b[u] >> ln) & 1ull)) {
+            const int64_t pos = base + o + __popcll(b[u] & lt);
+            if (pos < limit) {
+              ocol[pos] = c0 + x;
+              oval[pos] = S::from_acc(a[u]);
             }
-            acc[x] = S::identity();
           }
-          nb += __popcll(b[u]);
+          acc[x] = S::identity();
+          o += __popcll(b[u]);
         }
       }
-      if (write) flush();
       for (int w = ln; w < SEGW; w += 64) bits[wv * SEGW + w] = 0u;
     };
     // cnt entries from (sc, sv) to (dc, dv), 8 loads in flight per lane
