@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdsg.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["prims.hip", "matrix.hip", "ingest.hip", "spgemm.hip", "entry.hip", "general.hip", "batch.hip", "server.hip", "scale_add.hip", "noalloc.hip", "api.hip"]
+SOURCES = ["prims.hip", "matrix.hip", "ingest.hip", "rowindex.hip", "spgemm.hip", "entry.hip", "general.hip", "batch.hip", "server.hip", "scale_add.hip", "noalloc.hip", "api.hip"]
 ARCH = os.environ.get("DSG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -335,6 +335,8 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   if (ng > 0) {
     DSG_HIP(hipEventRecord(b->ev_ready, main));
     DSG_HIP(hipStreamWaitEvent(b->replay_stream, b->ev_ready, 0));
+    // the graph's applies and row writes keep no column index
+    for (DMat* m : gmats) mat_index_invalidate(m);
     DSG_HIP(hipGraphLaunch(b->exec, b->replay_stream));
     b->replays++;
   }

@@ -17,9 +17,11 @@
 //                 recomputed.  Using the stored minimum as a witness this way
 //                 is this library's addition.
 //
-// A recomputed entry takes the minimum (or sum) of a'_ik * a'_kj over k.  A'
-// row i goes into an LDS hash; column j of A' is read from the valued
-// transpose.
+// A recomputed entry takes the minimum (or sum) of a'_ik * a'_kj over k, from
+// the shorter of row i and column j of A': each k of that list is looked up
+// in the per-row column index of A' (rowindex.h), and column j comes from the
+// valued transpose.  C keeps a column index too, so the apply of step 4
+// finds each entry of C in constant time instead of streaming its row.
 //
 // Steps (all on the device, a few host reads of counts in between):
 //   1. per changed entry (r, c) of A, count its products: as a left factor
@@ -31,8 +33,8 @@
 //      (min or sum of the changes), with a guard for the witness test;
 //   4. apply those updates to C in place (ingest.hip: mat_apply_sorted_add),
 //      which lists the lost entries with their slots;
-//   5. recompute the lost entries; entries left without any product are
-//      deleted;
+//   5. recompute the lost entries from the cheaper side; entries left
+//      without any product are deleted;
 //   6. report the rows whose stored content changed (row epochs of C).
 #include <algorithm>
 
@@ -119,9 +121,46 @@ __global__ void k_term_counts(Log L, int cbits, const int32_t* a_len, const int3
   cnt[u] = c;
 }
 
+// The changed keys of the log in a hash set (open addressing, all ones when
+// empty): the right-factor pass asks for each product whether (i, r)
+// changed too.
+struct KeySet {
+  uint64_t* tab;
+  uint32_t mask;
+};
+
+__device__ inline uint32_t key_hash(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  return (uint32_t)k;
+}
+
+__global__ void k_keyset_clear(KeySet H) {
+  for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x <= H.mask; x += gridDim.x * blockDim.x) H.tab[x] = ~0ull;
+}
+
+__global__ void k_keyset_fill(Log L, KeySet H) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= L.n || L.code[u] == UPD_NOP || L.code[u] == UPD_LOST) return;
+  const uint64_t k = L.key[u];
+  uint32_t h = key_hash(k) & H.mask;
+  while (atomicCAS((unsigned long long*)&H.tab[h], ~0ull, (unsigned long long)k) != ~0ull) h = (h + 1) & H.mask;
+}
+
+__device__ inline bool keyset_has(const KeySet& H, uint64_t k) {
+  uint32_t h = key_hash(k) & H.mask;
+  for (;;) {
+    const uint64_t e = H.tab[h];
+    if (e == k) return true;
+    if (e == ~0ull) return false;
+    h = (h + 1) & H.mask;
+  }
+}
+
 // ---- 2. write the products: one wavefront per changed entry ----
 template <int SR>
-__global__ __launch_bounds__(256) void k_term_write(Log L, int cbits, Mat A, Mat T, const int64_t* base,
+__global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, Mat A, Mat T, const int64_t* base,
                                                     uint64_t* tkey, uint64_t* told, uint64_t* tnew, uint8_t* tfl,
                                                     uint64_t sentinel) {
   using S = Sem<SR>;
@@ -184,8 +223,7 @@ __global__ __launch_bounds__(256) void k_term_write(Log L, int cbits, Mat A, Mat
   for (int32_t t = lane; t < tl; t += 64) {
     const int32_t i = T.col[tc + t];
     const V a = ldv<V>(T.val, tc + t);
-    const int64_t e = log_index(L.key, 0, L.n, ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)r);
-    if (e >= 0 && L.code[e] != UPD_NOP) {
+    if (keyset_has(H, ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)r)) {
       // (i, r) changed too: that entry's left-factor products include this one
       tkey[o + t] = sentinel;
       tfl[o + t] = 0;
@@ -205,18 +243,12 @@ __global__ void k_iota_u32(uint32_t* p, int64_t n) {
 }
 
 // ---- 3. segments of equal keys ----
-__global__ void k_seg_heads(const uint64_t* key, int64_t n, uint64_t sentinel, int cbits, int64_t* head,
-                            unsigned long long* nrows) {
+__global__ void k_seg_heads(const uint64_t* key, int64_t n, uint64_t sentinel, int64_t* head) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bool newrow = false;
   if (t < n) {
     const uint64_t k = key[t];
-    const bool h = k != sentinel && (t == 0 || key[t - 1] != k);
-    head[t] = h ? 1 : 0;
-    newrow = h && (t == 0 || (key[t - 1] >> cbits) != (k >> cbits));
+    head[t] = (k != sentinel && (t == 0 || key[t - 1] != k)) ? 1 : 0;
   }
-  const int c = __syncthreads_count(newrow);  // one atomic per workgroup
-  if (threadIdx.x == 0 && c) atomicAdd(nrows, (unsigned long long)c);
 }
 
 __global__ void k_seg_scatter(const uint64_t* key, int64_t n, uint64_t sentinel, const int64_t* head,
@@ -279,82 +311,24 @@ __global__ void k_seg_reduce(const uint64_t* key, const uint32_t* idx, const uin
 }
 
 // ---- 5. lost entries ----
-__global__ void k_lost_heads(const uint64_t* key, int64_t n, int cbits, int64_t* head) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) head[t] = (t == 0 || (key[t - 1] >> cbits) != (key[t] >> cbits)) ? 1 : 0;
-}
-
-// row segments of the sorted lost list, split by the length of A' row i
-__global__ void k_lost_rows(const uint64_t* key, int64_t n, int cbits, const int64_t* head, const int64_t* rid,
-                            const int64_t* d_nrow, int64_t* row_start, const int32_t* a_len, int32_t small_max,
-                            uint8_t* is_small, uint8_t* is_big) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n) return;
-  if (head[t]) {
-    const int64_t r = rid[t];
-    row_start[r] = t;
-    const int32_t d = a_len[(int32_t)(key[t] >> cbits)];
-    is_small[r] = d <= small_max ? 1 : 0;
-    is_big[r] = d <= small_max ? 0 : 1;
-  }
-  if (t == n - 1) row_start[*d_nrow] = n;
-}
-
-// A lost entry (i, j) is recomputed from the cheaper side: column j of A'
-// (probing an LDS hash of A' row i), or A' row i (a binary search of j in the
-// column-sorted copy of each row k).  Costs in probes: len(column j) against
-// d_i searches of ~8 steps.
-__device__ inline bool row_side(int32_t d, int32_t lj) { return (int64_t)d * 8 < (int64_t)lj; }
-
-// work items: each row segment of lost entries in runs of epw entries
-__global__ void k_item_counts(const int64_t* row_start, const int64_t* d_nrow, const uint8_t* is_small,
-                              int32_t epw_small, int32_t epw_big, int64_t* cs, int64_t* cb) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= *d_nrow) return;
-  const int64_t len = row_start[r + 1] - row_start[r];
-  cs[r] = is_small[r] ? (len + epw_small - 1) / epw_small : 0;
-  cb[r] = is_small[r] ? 0 : (len + epw_big - 1) / epw_big;
-}
-
-__global__ void k_item_fill(const int64_t* row_start, const int64_t* d_nrow, const uint8_t* is_small,
-                            int32_t epw_small, int32_t epw_big, const int64_t* os, const int64_t* ob,
-                            int32_t* srow, int32_t* spart, int32_t* brow, int32_t* bpart) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= *d_nrow) return;
-  const int64_t len = row_start[r + 1] - row_start[r];
-  const bool sm = is_small[r] != 0;
-  const int32_t epw = sm ? epw_small : epw_big;
-  const int64_t cnt = (len + epw - 1) / epw;
-  const int64_t o = sm ? os[r] : ob[r];
-  int32_t* ir = sm ? srow : brow;
-  int32_t* ip = sm ? spart : bpart;
-  for (int64_t q = 0; q < cnt; ++q) {
-    ir[o + q] = (int32_t)r;
-    ip[o + q] = (int32_t)q;
-  }
-}
+// A lost entry (i, j) takes the minimum (or sum) of a'_ik * a'_kj over k from
+// the shorter of two lists: row i of A' (each k probed for column j in row
+// k's column index) or column j of A' (each k probed for column k in row i's
+// column index).  Entries are split by that length: up to LOST_NARROW_MAX
+// probes take 8 lanes, longer ones a whole wavefront.
+constexpr int32_t LOST_NARROW_MAX = 64;
 
 struct LostArgs {
   const uint64_t* key;
   const int32_t* slot;
-  const int64_t* row_start;
-  const int32_t* item_row;   // work items of this launch: a row segment ...
-  const int32_t* item_part;  // ... and which run of epw of its entries
-  int32_t epw;
   int cbits;
   Mat A, T;
+  RowIx X;  // column index of A' (every row built)
   int64_t* c_off;
   void* c_val;
   uint32_t* c_epoch;
   const uint32_t* c_cur_epoch;
-  unsigned long long* part_acc;  // big rows: running result per lost entry
-  uint32_t* part_hits;
-  uint64_t* del_key;
-  unsigned long long* ndel;
-  int use_rowside;      // 0: every lost entry from the column side
-  const int64_t* s_rp;  // column-sorted copy of A' (row side only)
-  const int32_t* s_col;
-  const void* s_val;
+  uint8_t* del_flag;  // per lost entry: no product left, delete it
 };
 
 template <int SR>
@@ -368,68 +342,26 @@ __device__ inline unsigned long long acc_comb(unsigned long long a, unsigned lon
   else return a + b;
 }
 
-template <int SR>
-__device__ inline unsigned long long wave_comb(unsigned long long x) {
-  for (int d = 32; d > 0; d >>= 1) x = acc_comb<SR>(x, __shfl_xor(x, d, 64));
-  return x;
+// position of column c in row r of A' (its table, or a scan of the row when
+// the index pool had no room for it)
+__device__ inline int32_t a_find(const LostArgs& L, int32_t r, int32_t c) {
+  if (ix_valid(L.X, r)) return ix_lookup(L.X, r, c);
+  const int64_t o = L.A.off[r];
+  const int32_t n = L.A.len[r];
+  for (int32_t t = 0; t < n; ++t)
+    if (L.A.col[o + t] == c) return t;
+  return -1;
 }
 
-__device__ inline uint32_t wave_sum(uint32_t x) {
-  for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
-}
-
-// LDS hash of the k's of A' row i (entries [k0, k1)): key k -> position in the row
-template <int SLOTS>
-__device__ inline void build_hash(int32_t* hk, int32_t* hp, const Mat& A, int64_t aoff, int32_t k0, int32_t k1,
-                                  int tid, int nthr) {
-  for (int x = tid; x < SLOTS; x += nthr) hk[x] = -1;
-  __syncthreads();
-  for (int32_t t = k0 + tid; t < k1; t += nthr) {
-    const int32_t k = A.col[aoff + t];
-    uint32_t h = hash_col(k) & (SLOTS - 1);
-    while (atomicCAS(&hk[h], -1, k) != -1) h = (h + 1) & (SLOTS - 1);
-    hp[h] = t;
-  }
-  __syncthreads();
-}
-
-template <int SLOTS>
-__device__ inline int32_t probe(const int32_t* hk, const int32_t* hp, int32_t k) {
-  uint32_t h = hash_col(k) & (SLOTS - 1);
-  for (;;) {
-    const int32_t x = hk[h];
-    if (x == k) return hp[h];
-    if (x == -1) return -1;
-    h = (h + 1) & (SLOTS - 1);
-  }
-}
-
-// a wavefront's share of one lost entry over the hashed part of A' row i
-template <int SR, int SLOTS>
-__device__ inline void column_pass(const LostArgs& L, const int32_t* hk, const int32_t* hp, int64_t aoff, int32_t j,
-                                   unsigned long long& acc, uint32_t& hits, int lane) {
-  using V = typename Sem<SR>::V;
-  const int64_t toff = L.T.off[j];
-  const int32_t tl = L.T.len[j];
-  for (int32_t t = lane; t < tl; t += 64) {
-    const int32_t k = L.T.col[toff + t];
-    const int32_t pos = probe<SLOTS>(hk, hp, k);
-    if (pos >= 0) {
-      const V a = ldv<V>(L.A.val, aoff + pos), b = ldv<V>(L.T.val, toff + t);
-      acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
-      ++hits;
-    }
-  }
-}
-
-// write the recomputed entry (lane 0): overwrite at its slot, or list it for deletion
+// write the recomputed entry (one lane): overwrite at its slot, or flag it
+// for deletion when no product is left
 template <int SR>
 __device__ inline void finish_entry(const LostArgs& L, int64_t e, unsigned long long acc, uint32_t hits) {
   using S = Sem<SR>;
   using V = typename S::V;
   const uint64_t key = L.key[e];
   const int32_t i = (int32_t)(key >> L.cbits);
+  L.del_flag[e] = hits == 0 ? 1 : 0;
   if (hits > 0) {
     const V nv = S::from_acc((typename S::Acc)acc);
     const int64_t p = L.c_off[i] + L.slot[e];
@@ -438,177 +370,85 @@ __device__ inline void finish_entry(const LostArgs& L, int64_t e, unsigned long 
       ((V*)L.c_val)[p] = nv;
       L.c_epoch[i] = *L.c_cur_epoch;
     }
-  } else {
-    const unsigned long long q = atomicAdd(L.ndel, 1ull);
-    L.del_key[q] = key;
   }
 }
 
-template <int SR>
-__device__ inline unsigned long long group8_comb(unsigned long long x) {
-  for (int d = 4; d > 0; d >>= 1) x = acc_comb<SR>(x, __shfl_xor(x, d, 64));
-  return x;
+// flags of the lost entries by probe count: up to LOST_NARROW_MAX, or more
+__global__ void k_lost_classes(const uint64_t* key, int64_t n, int cbits, const int32_t* a_len, const int32_t* t_len,
+                               uint8_t* narrow, uint8_t* wide) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const uint64_t k = key[e];
+  const int32_t d = a_len[(int32_t)(k >> cbits)];
+  const int32_t lj = t_len[(int32_t)(k & ((1ull << cbits) - 1))];
+  const bool nar = (d < lj ? d : lj) <= LOST_NARROW_MAX;
+  narrow[e] = nar ? 1 : 0;
+  wide[e] = nar ? 0 : 1;
 }
 
-__device__ inline uint32_t group8_sum(uint32_t x) {
-  for (int d = 4; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
-  return x;
-}
-
-// rows whose A' row fits one LDS hash: one workgroup per work item; 8 lanes
-// per lost entry, so a wavefront works on 8 entries at once
-template <int SR, int SLOTS, int WG>
-__global__ __launch_bounds__(WG) void k_lost_small(LostArgs L) {
+// G lanes per lost entry; the listed entries taken in turn
+template <int SR, int G>
+__global__ __launch_bounds__(256) void k_lost_recompute(LostArgs L, const int32_t* list, const int32_t* d_count) {
   using V = typename Sem<SR>::V;
-  __shared__ int32_t hk[SLOTS];
-  __shared__ int32_t hp[SLOTS];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int sub = lane >> 3, l8 = lane & 7;
-  const int32_t r = L.item_row[blockIdx.x];
-  const int64_t e0 = L.row_start[r] + (int64_t)L.item_part[blockIdx.x] * L.epw;
-  const int64_t e1 = min(L.row_start[r + 1], e0 + L.epw);
-  const int32_t i = (int32_t)(L.key[e0] >> L.cbits);
-  const int64_t aoff = L.A.off[i];
-  build_hash<SLOTS>(hk, hp, L.A, aoff, 0, L.A.len[i], tid, WG);
+  const int64_t n = *d_count;
+  const int l = threadIdx.x & (G - 1);
+  const int64_t ng = ((int64_t)gridDim.x * blockDim.x) / G;
   const uint64_t cmask = (1ull << L.cbits) - 1;
-  const int32_t d = L.A.len[i];
-  constexpr int PER_ROUND = (WG / 64) * 8;
-  for (int64_t eb = e0; eb < e1; eb += PER_ROUND) {
-    const int64_t e = eb + wv * 8 + sub;
-    bool act = e < e1;
-    int32_t j = 0, lj = 0;
-    int64_t toff = 0;
-    if (act) {
-      j = (int32_t)(L.key[e] & cmask);
-      lj = L.T.len[j];
-      toff = L.T.off[j];
-      act = !(L.use_rowside && row_side(d, lj));
-    }
+  // (the G lanes of a group share q0, so each group runs its rounds together
+  // and its shuffles see all of its lanes)
+  for (int64_t q0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; q0 < n; q0 += ng) {
+    const bool act = true;
+    const int64_t e = list[q0];
+    const int32_t i = (int32_t)(L.key[e] >> L.cbits);
+    const int32_t j = (int32_t)(L.key[e] & cmask);
+    const int32_t d = L.A.len[i];
+    const int32_t lj = L.T.len[j];
     unsigned long long acc = acc_id<SR>();
     uint32_t hits = 0;
     if (act) {
-      for (int32_t t = l8; t < lj; t += 8) {
-        const int32_t pos = probe<SLOTS>(hk, hp, L.T.col[toff + t]);
-        if (pos >= 0) {
-          const V a = ldv<V>(L.A.val, aoff + pos), b = ldv<V>(L.T.val, toff + t);
-          acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
-          ++hits;
+      const int64_t aoff = L.A.off[i];
+      if (d <= lj) {
+        // row i of A': is column j in row k?
+        for (int32_t t = l; t < d; t += G) {
+          const int32_t k = L.A.col[aoff + t];
+          const int32_t pos = a_find(L, k, j);
+          if (pos >= 0) {
+            const V a = ldv<V>(L.A.val, aoff + t), b = ldv<V>(L.A.val, L.A.off[k] + pos);
+            acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
+            ++hits;
+          }
+        }
+      } else {
+        // column j of A': is column k in row i?
+        const int64_t toff = L.T.off[j];
+        for (int32_t t = l; t < lj; t += G) {
+          const int32_t k = L.T.col[toff + t];
+          const int32_t pos = a_find(L, i, k);
+          if (pos >= 0) {
+            const V a = ldv<V>(L.A.val, aoff + pos), b = ldv<V>(L.T.val, toff + t);
+            acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
+            ++hits;
+          }
         }
       }
     }
-    acc = group8_comb<SR>(acc);
-    hits = group8_sum(hits);
-    if (act && l8 == 0) finish_entry<SR>(L, e, acc, hits);
-  }
-}
-
-// rows too long for one hash: A' row i in chunks, partial results per entry
-template <int SR, int SLOTS, int WG>
-__global__ __launch_bounds__(WG) void k_lost_big(LostArgs L) {
-  __shared__ int32_t hk[SLOTS];
-  __shared__ int32_t hp[SLOTS];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int32_t r = L.item_row[blockIdx.x];
-  const int64_t e0 = L.row_start[r] + (int64_t)L.item_part[blockIdx.x] * L.epw;
-  const int64_t e1 = min(L.row_start[r + 1], e0 + L.epw);
-  const int32_t i = (int32_t)(L.key[e0] >> L.cbits);
-  const int64_t aoff = L.A.off[i];
-  const int32_t d = L.A.len[i];
-  const uint64_t cmask = (1ull << L.cbits) - 1;
-  constexpr int32_t CHUNK = SLOTS / 2;
-  for (int32_t k0 = 0; k0 < d; k0 += CHUNK) {
-    build_hash<SLOTS>(hk, hp, L.A, aoff, k0, min(d, k0 + CHUNK), tid, WG);
-    for (int64_t e = e0 + wv; e < e1; e += WG / 64) {
-      const int32_t j = (int32_t)(L.key[e] & cmask);
-      if (L.use_rowside && row_side(d, L.T.len[j])) continue;
-      unsigned long long acc = acc_id<SR>();
-      uint32_t hits = 0;
-      column_pass<SR, SLOTS>(L, hk, hp, aoff, j, acc, hits, lane);
-      acc = wave_comb<SR>(acc);
-      hits = wave_sum(hits);
-      if (lane == 0) {
-        if (k0 > 0) {
-          acc = acc_comb<SR>(acc, L.part_acc[e]);
-          hits += L.part_hits[e];
-        }
-        L.part_acc[e] = acc;
-        L.part_hits[e] = hits;
-      }
+#pragma unroll
+    for (int x = G / 2; x > 0; x >>= 1) {
+      acc = acc_comb<SR>(acc, __shfl_xor(acc, x, 64));
+      hits += __shfl_xor(hits, x, 64);
     }
-    __syncthreads();
-  }
-  for (int64_t e = e0 + tid; e < e1; e += WG)
-    if (!(L.use_rowside && row_side(d, L.T.len[(int32_t)(L.key[e] & cmask)])))
-      finish_entry<SR>(L, e, L.part_acc[e], L.part_hits[e]);
-}
-
-// lost entries recomputed from the row side: 8 lanes per entry
-template <int SR>
-__global__ __launch_bounds__(256) void k_lost_rowside(LostArgs L, int64_t nlost) {
-  using V = typename Sem<SR>::V;
-  const int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
-  const int l8 = threadIdx.x & 7;
-  bool act = e < nlost;
-  const uint64_t cmask = (1ull << L.cbits) - 1;
-  int32_t i = 0, j = 0, d = 0;
-  if (act) {
-    i = (int32_t)(L.key[e] >> L.cbits);
-    j = (int32_t)(L.key[e] & cmask);
-    d = L.A.len[i];
-    act = L.use_rowside && row_side(d, L.T.len[j]);
-  }
-  unsigned long long acc = acc_id<SR>();
-  uint32_t hits = 0;
-  if (act) {
-    const int64_t aoff = L.A.off[i];
-    for (int32_t t = l8; t < d; t += 8) {
-      const int32_t k = L.A.col[aoff + t];
-      const int64_t end = L.s_rp[k + 1];
-      int64_t lo = L.s_rp[k], hi = end;
-      while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (L.s_col[mid] < j) lo = mid + 1;
-        else hi = mid;
-      }
-      if (lo < end && L.s_col[lo] == j) {
-        const V a = ldv<V>(L.A.val, aoff + t), b = ldv<V>(L.s_val, lo);
-        acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
-        ++hits;
-      }
-    }
-  }
-  acc = group8_comb<SR>(acc);
-  hits = group8_sum(hits);
-  if (act && l8 == 0) finish_entry<SR>(L, e, acc, hits);
-}
-
-// row-side entries: their count and the column lengths they would stream
-__global__ void k_count_rowside(const uint64_t* key, int64_t n, int cbits, const int32_t* a_len,
-                                const int32_t* t_len, unsigned long long* cnt) {
-  __shared__ unsigned long long sum;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t cmask = (1ull << cbits) - 1;
-  if (threadIdx.x == 0) sum = 0;
-  __syncthreads();
-  int32_t lj = 0;
-  bool rs = false;
-  if (e < n) {
-    lj = t_len[(int32_t)(key[e] & cmask)];
-    rs = row_side(a_len[(int32_t)(key[e] >> cbits)], lj);
-  }
-  if (rs) atomicAdd(&sum, (unsigned long long)lj);
-  const int c = __syncthreads_count(rs);  // one atomic per counter and workgroup
-  if (threadIdx.x == 0 && c) {
-    atomicAdd(cnt, (unsigned long long)c);
-    atomicAdd(cnt + 1, sum);
+    if (act && l == 0) finish_entry<SR>(L, e, acc, hits);
   }
 }
 
-__global__ void k_del_batch(const uint64_t* key, int64_t n, int cbits, int32_t* rows, int32_t* cols, uint8_t* ops) {
+// the flagged lost entries as a DELETE batch
+__global__ void k_del_batch(const uint64_t* key, const int32_t* list, int64_t n, int cbits, int32_t* rows,
+                            int32_t* cols, uint8_t* ops) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < n) {
-    rows[t] = (int32_t)(key[t] >> cbits);
-    cols[t] = (int32_t)(key[t] & ((1ull << cbits) - 1));
+    const uint64_t k = key[list[t]];
+    rows[t] = (int32_t)(k >> cbits);
+    cols[t] = (int32_t)(k & ((1ull << cbits) - 1));
     ops[t] = DSG_OP_DELETE;
   }
 }
@@ -715,6 +555,10 @@ int32_t entry_update(DProd* p) {
   dsg_update_stats& st = p->stats;
   st = dsg_update_stats{};
   st.path = 1;
+  // column indexes of C (the apply of its updates looks entries up in
+  // them) and of A' (the lost entries' probes); built on first use
+  mat_index_enable(C);
+  mat_index_enable(A);
 
   // the counts of step 1 (count_terms), still in the second scratch
   Log L{A->log_key, A->log_old, A->log_new, A->log_code, p->entry_nU};
@@ -726,9 +570,8 @@ int32_t entry_update(DProd* p) {
   (void)cv1.take<char>(scan_scratch_bytes(nU + 1) + 64);
   int64_t* d_total = cv1.take<int64_t>(8);
   const int64_t nterm = p->entry_nterm;
-  // counters: [0] rows of C with changes, [1] lost deletions, [3] lost count,
-  // [5..6] work items, [12] reported rows, [14..15] row-side entries and the
-  // column lengths they would stream
+  // counters: [0] rows of C with changed products, [3] lost entries, [12]
+  // reported rows
   st.terms = nterm;
 
   // ---- workspace for the products, the entry updates and the lost entries ----
@@ -736,13 +579,14 @@ int32_t entry_update(DProd* p) {
   const size_t terms_b = Carve::need({(size_t)NT * 8, (size_t)NT * 4, (size_t)NT * 8, (size_t)NT * 8, (size_t)NT,
                                       radix_scratch_bytes(NT), (size_t)NT * 8, (size_t)NT * 8,
                                       scan_scratch_bytes(NT) + 64, (size_t)(NT + 1) * 8});
-  const size_t lost_b = Carve::need({(size_t)NT * 8, (size_t)NT * 4, radix_scratch_bytes(NT), (size_t)NT * 8,
-                                     (size_t)NT * 8, scan_scratch_bytes(NT) + 64, (size_t)(NT + 1) * 8,
-                                     (size_t)NT, (size_t)NT, (size_t)NT * 4, (size_t)NT * 4, (size_t)NT * 4,
-                                     (size_t)NT * 4, (size_t)NT * 8,
-                                     (size_t)NT * 4, (size_t)NT * 8, (size_t)NT * 4, (size_t)NT * 4, (size_t)NT});
+  const size_t lost_b = Carve::need({(size_t)NT * 8, (size_t)NT * 4, (size_t)NT, (size_t)NT, (size_t)NT * 4,
+                                     (size_t)NT * 4, (size_t)NT, (size_t)NT * 4, (size_t)NT * 4, (size_t)NT * 4,
+                                     (size_t)NT, compact_scratch_bytes(NT) + 64, 64});
+  uint32_t hs = 64;
+  while (hs < 2 * (uint64_t)std::max<int64_t>(nU, 1)) hs <<= 1;
   const size_t segs_b = Carve::need({(size_t)NT * 8, (size_t)NT * 8, (size_t)NT * 8, (size_t)NT, 256, (size_t)n + 64,
-                                     compact_scratch_bytes(std::max<int32_t>(n, 1)) + 64, 256});
+                                     compact_scratch_bytes(std::max<int32_t>(n, 1)) + 64, 256,
+                                     sorted_add_scratch_bytes(NT), (size_t)hs * 8});
   const size_t total_b = std::max(terms_b, lost_b) + segs_b;
   char* region = (char*)ensure_ws(p, total_b);
   Carve cs(region + std::max(terms_b, lost_b), segs_b);
@@ -754,6 +598,8 @@ int32_t entry_update(DProd* p) {
   uint8_t* rflags = cs.take<uint8_t>((size_t)n + 64);
   void* cscr = cs.take<char>(compact_scratch_bytes(std::max<int32_t>(n, 1)) + 64);
   uint32_t* ep_before = (uint32_t*)cs.take<uint64_t>(8);
+  void* sa_scr = cs.take<char>(sorted_add_scratch_bytes(NT));
+  KeySet H{cs.take<uint64_t>(hs), hs - 1};
   hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, s, ctr, 16);
   hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, (const uint32_t*)C->d_epoch, ep_before);
 
@@ -773,7 +619,9 @@ int32_t entry_update(DProd* p) {
     int64_t* seg_start = ct.take<int64_t>(NT + 1);
     {
       Phase ph(c, "entry_terms");
-      hipLaunchKernelGGL((k_term_write<SR>), dim3(blocks_for(nU * 64, 256)), dim3(256), 0, s, L, cbits, view(A),
+      hipLaunchKernelGGL(k_keyset_clear, dim3(std::min<unsigned>(blocks_for(hs, 256), 1024)), dim3(256), 0, s, H);
+      hipLaunchKernelGGL(k_keyset_fill, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, H);
+      hipLaunchKernelGGL((k_term_write<SR>), dim3(blocks_for(nU * 64, 256)), dim3(256), 0, s, L, H, cbits, view(A),
                          view(T), (const int64_t*)off, tkey, told, tnew, tfl, sentinel);
       hipLaunchKernelGGL(k_iota_u32, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tidx, nterm);
     }
@@ -783,8 +631,7 @@ int32_t entry_update(DProd* p) {
       radix_sort_pairs(tkey, tidx, nterm, kbits + 1, rscr, s);
     }
     Phase ph(c, "entry_reduce");
-    hipLaunchKernelGGL(k_seg_heads, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tkey, nterm, sentinel, cbits,
-                       head, ctr + 0);
+    hipLaunchKernelGGL(k_seg_heads, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tkey, nterm, sentinel, head);
     exclusive_scan_i64(head, segid, nterm, d_total, scan2, s);
     hipLaunchKernelGGL(k_seg_scatter, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tkey, nterm, sentinel,
                        (const int64_t*)head, (const int64_t*)segid, (const int64_t*)d_total, seg_start);
@@ -799,126 +646,68 @@ int32_t entry_update(DProd* p) {
   Carve cl(region, lost_b);
   uint64_t* lkey = cl.take<uint64_t>(NT);
   int32_t* lslot = cl.take<int32_t>(NT);
-  void* lrscr = cl.take<char>(radix_scratch_bytes(NT));
-  int64_t* lhead = cl.take<int64_t>(NT);
-  int64_t* lrid = cl.take<int64_t>(NT);
-  void* lscan = cl.take<char>(scan_scratch_bytes(NT) + 64);
-  int64_t* lrow_start = cl.take<int64_t>(NT + 1);
-  uint8_t* is_small = cl.take<uint8_t>(NT);
-  uint8_t* is_big = cl.take<uint8_t>(NT);
-  int32_t* s_item_r = cl.take<int32_t>(NT);
-  int32_t* s_item_p = cl.take<int32_t>(NT);
-  int32_t* b_item_r = cl.take<int32_t>(NT);
-  int32_t* b_item_p = cl.take<int32_t>(NT);
-  unsigned long long* part_acc = cl.take<unsigned long long>(NT);
-  uint32_t* part_hits = cl.take<uint32_t>(NT);
-  uint64_t* dkey = cl.take<uint64_t>(NT);
+  uint8_t* fnarrow = cl.take<uint8_t>(NT);
+  uint8_t* fwide = cl.take<uint8_t>(NT);
+  int32_t* lnarrow = cl.take<int32_t>(NT);
+  int32_t* lwide = cl.take<int32_t>(NT);
+  uint8_t* fdel = cl.take<uint8_t>(NT);
+  int32_t* ldel = cl.take<int32_t>(NT);
   int32_t* drows = cl.take<int32_t>(NT);
   int32_t* dcols = cl.take<int32_t>(NT);
   uint8_t* dops = cl.take<uint8_t>(NT);
+  void* lscr = cl.take<char>(compact_scratch_bytes(NT) + 64);
+  int32_t* lcnt = cl.take<int32_t>(16);  // [0] narrow, [1] wide, [2] deletions
   int64_t nlost = 0;
   {
     Phase ph(c, "entry_apply_c");
-    nlost = mat_apply_sorted_add(C, ckey, cval, cguard, cflag, nseg, lkey, lslot, NT, ctr + 3);
+    // (ctr[0]: the rows of C with changed products)
+    nlost = mat_apply_sorted_add(C, ckey, cval, cguard, cflag, nseg, lkey, lslot, NT, ctr + 3, (int64_t*)ctr,
+                                 sa_scr);
   }
   st.lost = nlost;
 
   // ---- 5. recompute the lost entries ----
   if (nlost > 0) {
-    Phase* ph = new Phase(c, "entry_lost_prep");
-    radix_sort_pairs(lkey, (uint32_t*)lslot, nlost, kbits, lrscr, s);
-    hipLaunchKernelGGL(k_lost_heads, dim3(blocks_for(nlost, 256)), dim3(256), 0, s, lkey, nlost, cbits, lhead);
-    exclusive_scan_i64(lhead, lrid, nlost, d_total, lscan, s);
-    constexpr int SMALL_SLOTS = 2048, BIG_SLOTS = 16384;
-    hipLaunchKernelGGL(k_lost_rows, dim3(blocks_for(nlost, 256)), dim3(256), 0, s, lkey, nlost, cbits,
-                       (const int64_t*)lhead, (const int64_t*)lrid, (const int64_t*)d_total, lrow_start,
-                       (const int32_t*)A->row_len, SMALL_SLOTS / 2, is_small, is_big);
-    const int64_t nrow = read_count(c, d_total);
-    // work items: runs of EPW_S / EPW_B lost entries of one row (a hub row's
-    // entries spread over many workgroups); lhead / lrid are free again
-    constexpr int32_t EPW_S = 32, EPW_B = 64;
-    int64_t* d_ntot = (int64_t*)(ctr + 5);
-    hipLaunchKernelGGL(k_item_counts, dim3(blocks_for(nrow, 256)), dim3(256), 0, s, (const int64_t*)lrow_start,
-                       (const int64_t*)d_total, (const uint8_t*)is_small, EPW_S, EPW_B, lhead, lrid);
-    exclusive_scan_i64(lhead, lhead, nrow, d_ntot, lscan, s);
-    exclusive_scan_i64(lrid, lrid, nrow, d_ntot + 1, lscan, s);
-    hipLaunchKernelGGL(k_item_fill, dim3(blocks_for(nrow, 256)), dim3(256), 0, s, (const int64_t*)lrow_start,
-                       (const int64_t*)d_total, (const uint8_t*)is_small, EPW_S, EPW_B, (const int64_t*)lhead,
-                       (const int64_t*)lrid, s_item_r, s_item_p, b_item_r, b_item_p);
-    int64_t* hc = (int64_t*)((char*)c->pinned + 3072);
-    DSG_HIP(hipMemcpyAsync(hc, d_ntot, 16, hipMemcpyDeviceToHost, s));
+    {
+      Phase ph(c, "entry_lost");
+      // every row of A' needs its column table (the apply dropped the tables
+      // of rows it could not keep them for)
+      mat_index_build(A, nullptr, nullptr, A->nrows);
+      LostArgs la;
+      la.key = lkey;
+      la.slot = lslot;
+      la.cbits = cbits;
+      la.A = view(A);
+      la.T = view(T);
+      la.X = mat_index_view(A);
+      la.c_off = C->row_off;
+      la.c_val = C->val;
+      la.c_epoch = C->row_epoch;
+      la.c_cur_epoch = C->d_epoch;
+      la.del_flag = fdel;
+      hipLaunchKernelGGL(k_lost_classes, dim3(blocks_for(nlost, 256)), dim3(256), 0, s, (const uint64_t*)lkey, nlost,
+                         cbits, (const int32_t*)A->row_len, (const int32_t*)T->row_len, fnarrow, fwide);
+      compact_flags(fnarrow, nlost, lnarrow, lcnt, lscr, s);
+      compact_flags(fwide, nlost, lwide, lcnt + 1, lscr, s);
+      // bounded grids over the device counts
+      const unsigned g8 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(nlost * 8, 256),
+                                                                           32 * (int64_t)c->num_cus));
+      const unsigned g64 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(nlost * 64, 256),
+                                                                            32 * (int64_t)c->num_cus));
+      hipLaunchKernelGGL((k_lost_recompute<SR, 8>), dim3(g8), dim3(256), 0, s, la, (const int32_t*)lnarrow,
+                         (const int32_t*)lcnt);
+      hipLaunchKernelGGL((k_lost_recompute<SR, 64>), dim3(g64), dim3(256), 0, s, la, (const int32_t*)lwide,
+                         (const int32_t*)(lcnt + 1));
+      compact_flags(fdel, nlost, ldel, lcnt + 2, lscr, s);
+      DSG_HIP(hipGetLastError());
+    }
+    int32_t* hd = (int32_t*)((char*)c->pinned + 3072);
+    DSG_HIP(hipMemcpyAsync(hd, lcnt + 2, 4, hipMemcpyDeviceToHost, s));
     DSG_HIP(hipStreamSynchronize(s));
-    const int64_t nsmall = hc[0], nbig = hc[1];
-    LostArgs la;
-    la.key = lkey;
-    la.slot = lslot;
-    la.row_start = lrow_start;
-    la.cbits = cbits;
-    la.A = view(A);
-    la.T = view(T);
-    la.c_off = C->row_off;
-    la.c_val = C->val;
-    la.c_epoch = C->row_epoch;
-    la.c_cur_epoch = C->d_epoch;
-    la.part_acc = part_acc;
-    la.part_hits = part_hits;
-    la.del_key = dkey;
-    la.ndel = ctr + 1;
-    la.s_rp = nullptr;
-    la.s_col = nullptr;
-    la.s_val = nullptr;
-    hipLaunchKernelGGL(k_count_rowside, dim3(blocks_for(nlost, 256)), dim3(256), 0, s, lkey, nlost, cbits,
-                       (const int32_t*)A->row_len, (const int32_t*)T->row_len, ctr + 14);
-    unsigned long long* hrs = (unsigned long long*)((char*)c->pinned + 3072);
-    DSG_HIP(hipMemcpyAsync(hrs, ctr + 14, 16, hipMemcpyDeviceToHost, s));
-    DSG_HIP(hipStreamSynchronize(s));
-    // the sorted copy costs a sort of all of A': only worth it when the
-    // row-side entries would otherwise stream a good part of that
-    la.use_rowside = hrs[0] > 0 && hrs[1] > (unsigned long long)(A->h_top_ub / 4);
-    if (la.use_rowside) {
-      // column-sorted copy of A' for the row-side searches
-      const int64_t annz = A->h_top_ub;  // bound on nnz(A')
-      const size_t sb = Carve::need({(size_t)(n + 1) * 8, (size_t)std::max<int64_t>(annz, 1) * 4,
-                                     (size_t)std::max<int64_t>(annz, 1) * A->vsz});
-      if (p->srt_bytes < sb) {
-        ctx_free(c, p->srt, p->srt_bytes);
-        p->srt = nullptr;
-        p->srt_bytes = 0;
-        p->srt = ctx_alloc(c, sb + sb / 4);
-        p->srt_bytes = sb + sb / 4;
-      }
-      Carve cq(p->srt, sb);
-      int64_t* s_rp = cq.take<int64_t>(n + 1);
-      int32_t* s_col = cq.take<int32_t>(std::max<int64_t>(annz, 1));
-      void* s_val = cq.take<char>((size_t)std::max<int64_t>(annz, 1) * A->vsz);
-      mat_export_device(A, s_rp, s_col, s_val, nullptr, s);
-      delete ph;
-      ph = new Phase(c, "entry_lost_rowside");
-      la.s_rp = s_rp;
-      la.s_col = s_col;
-      la.s_val = s_val;
-      hipLaunchKernelGGL((k_lost_rowside<SR>), dim3(blocks_for(nlost * 8, 256)), dim3(256), 0, s, la, nlost);
-    }
-    delete ph;
-    ph = new Phase(c, "entry_lost_column");
-    if (nsmall > 0) {
-      la.item_row = s_item_r;
-      la.item_part = s_item_p;
-      la.epw = EPW_S;
-      hipLaunchKernelGGL((k_lost_small<SR, SMALL_SLOTS, 128>), dim3((unsigned)nsmall), dim3(128), 0, s, la);
-    }
-    if (nbig > 0) {
-      la.item_row = b_item_r;
-      la.item_part = b_item_p;
-      la.epw = EPW_B;
-      hipLaunchKernelGGL((k_lost_big<SR, BIG_SLOTS, 256>), dim3((unsigned)nbig), dim3(256), 0, s, la);
-    }
-    DSG_HIP(hipGetLastError());
-    delete ph;
-    const int64_t ndel = read_count(c, (const int64_t*)(ctr + 1));
+    const int64_t ndel = hd[0];
     if (ndel > 0) {
-      hipLaunchKernelGGL(k_del_batch, dim3(blocks_for(ndel, 256)), dim3(256), 0, s, dkey, ndel, cbits, drows, dcols,
-                         dops);
+      hipLaunchKernelGGL(k_del_batch, dim3(blocks_for(ndel, 256)), dim3(256), 0, s, (const uint64_t*)lkey,
+                         (const int32_t*)ldel, ndel, cbits, drows, dcols, dops);
       mat_apply_device(C, drows, dcols, nullptr, dops, ndel);
     }
   }
@@ -941,13 +730,19 @@ int32_t entry_update(DProd* p) {
   hipLaunchKernelGGL(k_sync_both, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)A->d_epoch);
   struct Tail {
     unsigned long long ctr[4];
+    unsigned long long ix_top[2];  // index pool tops of C and A
     int32_t nchg;
   };
   Tail* ht = (Tail*)((char*)c->pinned + 3072);
   DSG_HIP(hipMemcpyAsync(ht->ctr, ctr, 32, hipMemcpyDeviceToHost, s));
+  ht->ix_top[0] = ht->ix_top[1] = 0;
+  if (C->ix_top) DSG_HIP(hipMemcpyAsync(&ht->ix_top[0], C->ix_top, 8, hipMemcpyDeviceToHost, s));
+  if (A->ix_top) DSG_HIP(hipMemcpyAsync(&ht->ix_top[1], A->ix_top, 8, hipMemcpyDeviceToHost, s));
   ht->nchg = 0;
   if (n > 0) DSG_HIP(hipMemcpyAsync(&ht->nchg, d_nchg, 4, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));
+  mat_index_note_top(C, ht->ix_top[0]);
+  mat_index_note_top(A, ht->ix_top[1]);
   st.affected_rows = (int64_t)ht->ctr[0];
   st.flops = nterm;
   st.changed_rows = ht->nchg;

@@ -608,6 +608,7 @@ int32_t general_update(DProd* p) {
   DMat* C = p->C;
   DMat* T = A->tidx;
   DSG_REQUIRE(T && p->F, DSG_E_STATE, "internal: Bloom product without transpose index or F");
+  mat_index_invalidate(C);  // the masked merges rewrite rows of C
   const int32_t n = C->nrows;
   const int cb = bits_for(C->ncols);
   const int rb = bits_for(n);

@@ -34,6 +34,7 @@ constexpr uint8_t OP_GUARD_ONLY = 3;  // internal op of mat_apply_sorted_add: no
 constexpr int PLAN_LDS = 1024;        // update columns of a row held in LDS by the plan
 constexpr uint8_t PL_DEL = 1;         // plan flags of a touched row
 constexpr uint8_t PL_HEAVY = 2;
+constexpr uint8_t PL_FLAT = 4;        // heavy row planned update by update through its column index
 constexpr int HEAVY_LEN = 2048;       // rows longer than this are planned by a whole workgroup
 constexpr uint8_t C_NOP = UPD_NOP, C_INS = UPD_INS, C_DEL = UPD_DEL, C_OVR = UPD_OVR, C_LOST = UPD_LOST;
 // the outcomes that change the operand, so the transpose index too
@@ -100,7 +101,9 @@ struct Uniq {
   uint8_t* pdel;  // plan flags: PL_DEL the row loses entries, PL_HEAVY planned by the workgroup kernel
   int32_t* holes;
   int32_t* mv_src;
-  int32_t* mv_u;
+  int32_t* ur;      // per unique update: its row's index r
+  int32_t* pcnt;    // per row r: deletions, inserts, overwrites, insert cursor (rows planned flat)
+  uint8_t* pix;     // per row r planned flat: 1 when its column index takes the inserts
 };
 
 template <int VSZ>
@@ -165,6 +168,7 @@ __global__ void k_fold(const uint64_t* keys, const uint32_t* idx, int64_t n, int
     U.urow[r] = (int32_t)(k >> cbits);
     U.row_first[r] = (int32_t)u;
   }
+  U.ur[u] = (int32_t)(urpos[t] + rh[t] - 1);
 }
 
 // position of column c among the unique updates [u0, u1) of a row, or -1
@@ -180,22 +184,19 @@ __device__ inline int32_t find_update(const uint64_t* ukey, int32_t u0, int32_t 
 }
 
 // Optional guard of an update (sorted ADD updates of a product, see
-// mat_apply_sorted_add): entries it marks are listed as lost, not changed.
+// mat_apply_sorted_add): entries it marks are left unchanged and get the
+// outcome UPD_LOST (listed afterwards).
 struct Guard {
   const uint64_t* key = nullptr;  // ordered key of the guarded value, per unique update
   const uint8_t* flag = nullptr;  // 2: guarded by key; 4: always lost when present
-  uint64_t* lost_key = nullptr;
-  int32_t* lost_slot = nullptr;
-  unsigned long long* nlost = nullptr;
-  int64_t cap = 0;
 };
 
 // The outcome of unique update u of a row whose slot (or -1) the plan found:
 // fold its chain onto the stored value, record code / final / previous
-// value, and apply the guard (listed as lost: lost_slot set).
+// value, and apply the guard (outcome UPD_LOST, the slot kept in U.slot).
 template <int SR, int VSZ>
 __device__ inline uint8_t plan_update(const DMat& m, int64_t off, const uint32_t* idx, const void* vals,
-                                      const Uniq& U, const Guard& G, int32_t u, int32_t& lost_slot) {
+                                      const Uniq& U, const Guard& G, int32_t u) {
   using S = typename SemOf<SR>::S;
   using V = typename S::V;
   const int32_t s = U.slot[u];
@@ -234,7 +235,6 @@ __device__ inline uint8_t plan_update(const DMat& m, int64_t off, const uint32_t
       if (lost) {
         code = C_LOST;
         v = old;
-        lost_slot = s;
       }
     }
   }
@@ -244,41 +244,30 @@ __device__ inline uint8_t plan_update(const DMat& m, int64_t off, const uint32_t
   return code;
 }
 
-// list this wavefront's lost entries with one atomic (all lanes call it)
-__device__ inline void emit_lost(const Uniq& U, const Guard& G, int32_t u, uint8_t code, int32_t lost_slot,
-                                 int lane) {
-  if (!G.flag) return;
-  const bool l = code == C_LOST;
-  const uint64_t lb = __ballot(l);
-  if (!lb) return;
-  unsigned long long p0 = 0;
-  if (lane == 0) p0 = atomicAdd(G.nlost, (unsigned long long)__popcll(lb));
-  p0 = __shfl(p0, 0, 64);
-  if (l) {
-    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-    const unsigned long long p = p0 + __popcll(lb & lt);
-    if ((int64_t)p < G.cap) {
-      G.lost_key[p] = U.key[u];
-      G.lost_slot[p] = lost_slot;
-    }
-  }
-}
-
 template <int SR, int VSZ>
 __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint64_t cmask, const uint32_t* idx,
-                                              const void* vals, Uniq U, unsigned long long* demand, Guard G) {
+                                              const void* vals, Uniq U, unsigned long long* demand, Guard G,
+                                              RowIx X) {
   // the row's update columns (sorted) in LDS, per wavefront, when they fit
   __shared__ int32_t lcol[4][PLAN_LDS];
-  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (r >= *d_nR) return;
   int32_t* lk = lcol[(threadIdx.x >> 6) & 3];
+  // one wavefront per touched row, rows taken in turn
+  const int64_t nR = *d_nR;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < nR; r += nw) {
   const int32_t i = U.urow[r];
   const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
   const int32_t nu = u1 - u0;
   const int64_t off = m.row_off[i];
   const int32_t len = m.row_len[i], cap = m.row_cap[i];
-  if (nu > PLAN_LDS || len > HEAVY_LEN) return;  // k_plan_heavy takes this row
+  if (nu > PLAN_LDS || len > HEAVY_LEN) continue;  // k_plan_heavy takes this row
+  if (ix_valid(X, i)) {
+    // the row's column index gives each update's slot
+    const uint64_t* t = X.tab + X.off[i];
+    const uint32_t mask = (uint32_t)X.sz[i] - 1;
+    for (int32_t u = u0 + lane; u < u1; u += 64) U.slot[u] = ix_find(t, mask, (int32_t)(U.key[u] & cmask));
+  } else {
   const bool in_lds = true;
   for (int32_t u = u0 + lane; u < u1; u += 64) {
     U.slot[u] = -1;
@@ -310,14 +299,13 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
       if (u >= 0) U.slot[u] = s0 + v * 64;
     }
   }
+  }
   __threadfence_block();
   __builtin_amdgcn_wave_barrier();
   int32_t n_del = 0, n_ins = 0, n_ovr = 0;
   for (int32_t base = u0; base < u1; base += 64) {
     const int32_t u = base + lane;
-    int32_t lost_slot = -1;
-    const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u, lost_slot) : C_NOP;
-    emit_lost(U, G, u, code, lost_slot, lane);
+    const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u) : C_NOP;
     n_del += __popcll(__ballot(code == C_DEL));
     n_ins += __popcll(__ballot(code == C_INS));
     n_ovr += __popcll(__ballot(code == C_OVR));
@@ -332,17 +320,20 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
     U.pcap[r] = reloc ? slack_cap(nl) : 0;
     if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
   }
+  }
 }
 
 template <int SR, int VSZ>
 __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uint64_t cmask, int cbits,
                                                 Uniq U, const uint32_t* d_epoch, int tbits, uint64_t* dkey,
                                                 uint8_t* dop, void* dval,
-                                                int64_t dcap, int* err) {
-  const int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+                                                int64_t dcap, int* err, RowIx X) {
   const int lane = threadIdx.x & 63;
-  if (r >= *d_nR) return;
-  if (!U.pchg[r]) return;
+  // one wavefront per touched row, rows taken in turn
+  const int64_t nR = *d_nR;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < nR; r += nw) {
+  if (!U.pchg[r]) continue;
   const int32_t i = U.urow[r];
   const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
   const int64_t off = m.row_off[i];
@@ -350,12 +341,11 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
   const int32_t nl = U.plen[r];
   const int32_t ncap = U.pcap[r];
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  // rows that lose no entry take the ordered paths; the heavy ones of those
-  // (as the plan recorded them: many updates or a long row) belong to
-  // k_commit_heavy, which runs after this kernel.  (The split goes by the
-  // plan's flags: a row's length changes here.)
+  // heavy rows (as the plan recorded them: many updates or a long row)
+  // belong to k_commit_heavy, which runs after this kernel.  (The split goes
+  // by the plan's flags: a row's length changes here.)
+  if (U.pdel[r] & PL_HEAVY) continue;
   const bool nodel = !(U.pdel[r] & PL_DEL);
-  if (nodel && (U.pdel[r] & PL_HEAVY)) return;
   if (nodel) {
     // ---- nothing deleted: the entries keep their order (moved as a block
     // when the row outgrows its space), overwrites go to the planned slots,
@@ -367,7 +357,7 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
       no = __shfl(no, 0, 64);
       if ((int64_t)no + ncap > m.pool_cap) {
         if (lane == 0) atomicOr(err, 1);
-        return;
+        continue;
       }
       dest = (int64_t)no;
       for (int32_t s0 = lane; s0 < len; s0 += 256) {
@@ -389,6 +379,12 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
         }
       }
     }
+    // the row's column index keeps its positions; the inserts join it
+    // unless they would fill it past 3/4 (then it is dropped)
+    const bool ixv = ix_valid(X, i);
+    const bool ixk = ixv && ix_fits(X, i, nl - len);
+    uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
+    const uint32_t ixm = ixk ? (uint32_t)X.sz[i] - 1 : 0u;
     int32_t k = 0;
     for (int32_t base = u0; base < u1; base += 64) {
       const int32_t u = base + lane;
@@ -397,9 +393,11 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
       const bool ins = code == C_INS;
       const uint64_t ib = __ballot(ins);
       if (ins) {
-        const int64_t dst = dest + len + k + __popcll(ib & lt);
+        const int32_t pos = len + k + __popcll(ib & lt);
+        const int64_t dst = dest + pos;
         m.col[dst] = (int32_t)(U.key[u] & cmask);
         store_raw<VSZ>(m.val, dst, U.fin[u]);
+        if (ixk) ix_put(ixt, ixm, (int32_t)(U.key[u] & cmask), pos);
       }
       k += __popcll(ib);
     }
@@ -407,16 +405,38 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
       m.row_off[i] = dest;
       m.row_cap[i] = ncap;
     }
+    if (ixv && lane == 0) {
+      if (ixk) X.used[i] += nl - len;
+      else X.stamp[i] = 0;
+    }
   } else {
     // ---- the row loses entries: mark the deleted slots (column -1) and
     // apply the overwrites where they stand ----
+    const bool ixv = ix_valid(X, i);
+    int32_t n_del = 0;
     for (int32_t base = u0; base < u1; base += 64) {
       const int32_t u = base + lane;
-      if (u < u1) {
-        const uint8_t code = U.code[u];
-        if (code == C_DEL) m.col[off + U.slot[u]] = -1;
-        else if (code == C_OVR) store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
-      }
+      const uint8_t code = u < u1 ? U.code[u] : C_NOP;
+      if (code == C_DEL) m.col[off + U.slot[u]] = -1;
+      else if (code == C_OVR) store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
+      n_del += __popcll(__ballot(code == C_DEL));
+    }
+    // in place, the column index follows the entries (deleted ones leave
+    // tombstones, moved ones get their new slot, inserts are recorded) while
+    // it has room; a row moved to new space, or a full table, drops it
+    const bool ixk = ixv && ncap == 0 && ix_fits(X, i, nl - len + n_del);
+    uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
+    const uint32_t ixm = ixk ? (uint32_t)X.sz[i] - 1 : 0u;
+    if (ixk) {
+      for (int32_t u = u0 + lane; u < u1; u += 64)
+        if (U.code[u] == C_DEL) {
+          const int32_t h = ix_slot(ixt, ixm, (int32_t)(U.key[u] & cmask));
+          if (h >= 0) ixt[h] = IX_TOMB;
+        }
+    }
+    if (ixv && lane == 0) {
+      if (ixk) X.used[i] += nl - len + n_del;
+      else X.stamp[i] = 0;
     }
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
@@ -452,8 +472,13 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
       __builtin_amdgcn_wave_barrier();
       for (int32_t q = lane; q < Mc; q += 64) {
         const int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q];
-        m.col[off + dst] = m.col[off + src];
+        const int32_t cm = m.col[off + src];
+        m.col[off + dst] = cm;
         store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
+        if (ixk) {
+          const int32_t h = ix_slot(ixt, ixm, cm);
+          if (h >= 0) ixt[h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
+        }
       }
       int32_t k = 0;
       for (int32_t base = u0; base < u1; base += 64) {
@@ -465,6 +490,7 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
           const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
           m.col[off + dst] = (int32_t)(U.key[u] & cmask);
           store_raw<VSZ>(m.val, off + dst, U.fin[u]);
+          if (ixk) ix_put(ixt, ixm, (int32_t)(U.key[u] & cmask), dst);
         }
         k += __popcll(ib);
       }
@@ -475,7 +501,7 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
       no = __shfl(no, 0, 64);
       if ((int64_t)no + ncap > m.pool_cap) {
         if (lane == 0) atomicOr(err, 1);
-        return;
+        continue;
       }
       int32_t kept = 0;
       for (int32_t base = 0; base < len; base += 256) {  // 4 loads in flight per lane
@@ -536,6 +562,61 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
       store_raw<VSZ>(dval, u, U.fin[u]);
     }
   }
+  }
+}
+
+// per-row counts of the rows planned flat, cleared before each plan
+__global__ void k_zero_pcnt(int32_t* pcnt, const int64_t* d_nR) {
+  const int64_t n = 4 * *d_nR;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+    pcnt[x] = 0;
+}
+
+// Heavy rows (more than PLAN_LDS updates or longer than HEAVY_LEN) whose
+// column index is usable, planned update by update: each thread looks its
+// update's entry up and decides the outcome; the counts of deletions,
+// inserts and overwrites go to the row (one atomic per counter and
+// wavefront for the lanes of the wavefront's first row, one per lane for
+// the few others).  A hub row's updates thus spread over the whole grid.
+template <int SR, int VSZ>
+__global__ __launch_bounds__(256) void k_plan_flat(DMat m, const int64_t* d_nU, uint64_t cmask, const uint32_t* idx,
+                                                   const void* vals, Uniq U, Guard G, RowIx X) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nU = *d_nU;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // (every lane of a wavefront runs the same number of rounds)
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); b0 < nU; b0 += stride) {
+    const int64_t u = b0 + lane;
+    int32_t r = -1;
+    uint8_t code = C_NOP;
+    if (u < nU) {
+      r = U.ur[u];
+      const int32_t i = U.urow[r];
+      const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+      const int32_t len = m.row_len[i];
+      if ((u1 - u0 > PLAN_LDS || len > HEAVY_LEN) && ix_valid(X, i)) {
+        U.slot[u] = ix_lookup(X, i, (int32_t)(U.key[u] & cmask));
+        code = plan_update<SR, VSZ>(m, m.row_off[i], idx, vals, U, G, (int32_t)u);
+      } else {
+        r = -1;  // planned by k_plan / k_plan_heavy
+      }
+    }
+    const int32_t r0 = __shfl(r, 0, 64);
+    const bool mine = r >= 0 && r == r0;
+    const int32_t cd = __popcll(__ballot(mine && code == C_DEL));
+    const int32_t ci = __popcll(__ballot(mine && code == C_INS));
+    const int32_t co = __popcll(__ballot(mine && code == C_OVR));
+    if (lane == 0 && r0 >= 0) {
+      if (cd) atomicAdd(&U.pcnt[4 * r0], cd);
+      if (ci) atomicAdd(&U.pcnt[4 * r0 + 1], ci);
+      if (co) atomicAdd(&U.pcnt[4 * r0 + 2], co);
+    }
+    if (r >= 0 && !mine) {
+      if (code == C_DEL) atomicAdd(&U.pcnt[4 * r], 1);
+      else if (code == C_INS) atomicAdd(&U.pcnt[4 * r + 1], 1);
+      else if (code == C_OVR) atomicAdd(&U.pcnt[4 * r + 2], 1);
+    }
+  }
 }
 
 // Heavy rows (more than PLAN_LDS updates): one 512-lane workgroup per row,
@@ -552,20 +633,56 @@ constexpr int HEAVY_PLAN_PER_CU = 4;
 template <int SR, int VSZ>
 __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* d_nR, uint64_t cmask,
                                                          const uint32_t* idx, const void* vals, Uniq U,
-                                                         unsigned long long* demand, Guard G) {
+                                                         unsigned long long* demand, Guard G, RowIx X) {
   __shared__ int32_t hk[HEAVY_SLOTS];
   __shared__ int32_t hu[HEAVY_SLOTS];
   __shared__ int32_t cnt[3];
+  __shared__ int32_t wc[HEAVY_WG / 64];
+  __shared__ int32_t picked[HEAVY_WG];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t nR = *d_nR;
-  for (int64_t r = blockIdx.x; r < nR; r += gridDim.x) {
+  // this workgroup's share of the touched rows, scanned HEAVY_WG at a time by
+  // every thread at once; the heavy ones are then taken in turn
+  const int64_t per = (nR + gridDim.x - 1) / gridDim.x;
+  const int64_t rb = (int64_t)blockIdx.x * per, re = min(nR, rb + per);
+  for (int64_t c0 = rb; c0 < re; c0 += HEAVY_WG) {
+  int32_t npick;
+  {
+    const int64_t rr = c0 + tid;
+    bool f = false;
+    if (rr < re) {
+      const int32_t nu = U.row_first[rr + 1] - U.row_first[rr];
+      f = nu > PLAN_LDS || m.row_len[U.urow[rr]] > HEAVY_LEN;
+    }
+    const int32_t q = block_flag_prefix<HEAVY_WG>(f, wc, npick);
+    if (f) picked[q] = (int32_t)rr;
+    __syncthreads();
+  }
+  for (int32_t pq = 0; pq < npick; ++pq) {
+    const int64_t r = picked[pq];
     const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
     const int32_t i = U.urow[r];
     const int64_t off = m.row_off[i];
     const int32_t len = m.row_len[i], cap = m.row_cap[i];
     if (u1 - u0 <= PLAN_LDS && len <= HEAVY_LEN) continue;
-    for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) U.slot[u] = -1;
+    if (ix_valid(X, i)) {
+      // (the same for every thread: no stamp changes during the plan)
+      // k_plan_flat planned its updates; the row's outcome from its counts
+      if (tid == 0) {
+        const int32_t nd = U.pcnt[4 * r], ni = U.pcnt[4 * r + 1], no = U.pcnt[4 * r + 2];
+        const int32_t nl = len - nd + ni;
+        const bool reloc = nl > cap;
+        U.plen[r] = nl;
+        U.pchg[r] = (nd + ni + no) > 0 ? 1 : 0;
+        U.pdel[r] = (nd > 0 ? PL_DEL : 0) | PL_HEAVY | PL_FLAT;
+        U.pcap[r] = reloc ? slack_cap(nl) : 0;
+        if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
+      }
+      continue;
+    }
     if (tid < 3) cnt[tid] = 0;
+    {
+    for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) U.slot[u] = -1;
     for (int32_t c0 = u0; c0 < u1; c0 += HEAVY_SLOTS / 2) {
       const int32_t c1 = min(u1, c0 + HEAVY_SLOTS / 2);
       // a table of twice this pass's updates (load <= 1/2): a long row with
@@ -604,12 +721,11 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
       }
       __syncthreads();
     }
+    }
     int32_t nd = 0, ni = 0, no = 0;
     for (int32_t base = u0 + wv * 64; base < u1; base += HEAVY_WG) {
       const int32_t u = base + lane;
-      int32_t lost_slot = -1;
-      const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u, lost_slot) : C_NOP;
-      emit_lost(U, G, u, code, lost_slot, lane);
+      const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u) : C_NOP;
       nd += __popcll(__ballot(code == C_DEL));
       ni += __popcll(__ballot(code == C_INS));
       no += __popcll(__ballot(code == C_OVR));
@@ -632,85 +748,225 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
     }
     __syncthreads();
   }
+  __syncthreads();  // before the next share overwrites the picked rows
+  }
 }
 
-// Commit of heavy rows (more than PLAN_LDS updates or longer than HEAVY_LEN)
-// without deletions (k_commit takes the rows with deletions): move as a
-// block if needed (4 loads in flight per lane), overwrite at the planned
-// slots, append the inserts, emit the transpose changes.
+// Commit of heavy rows (more than PLAN_LDS updates or longer than HEAVY_LEN),
+// one workgroup per row, rows taken in turn:
+//   - planned flat, no deletions: only the move to fresh space (when the row
+//     outgrows it) and the row's bookkeeping; k_commit_flat then writes the
+//     overwrites and inserts update by update;
+//   - no deletions: move as a block if needed (4 loads in flight per lane),
+//     overwrite at the planned slots, append the inserts;
+//   - with deletions: overwrite and mark the deleted slots, then in place
+//     fill the holes below the new length with the entries above it and the
+//     inserts (the column index follows), or compact into fresh space when
+//     the row outgrows its space (the column index is dropped).
+// The transpose changes of every row but the flat ones are emitted here.
 template <int SR, int VSZ>
 __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t* d_nR, uint64_t cmask, Uniq U,
                                                            const uint32_t* d_epoch, int tbits, uint64_t* dkey,
                                                            uint8_t* dop, void* dval,
-                                                           int64_t dcap, int* err) {
+                                                           int64_t dcap, int* err, RowIx X) {
   __shared__ int32_t wc[HEAVY_WG / 64];
+  __shared__ int32_t picked[HEAVY_WG];
   __shared__ unsigned long long dest_s;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int tid = threadIdx.x;
   const int64_t nR = *d_nR;
-  for (int64_t r = blockIdx.x; r < nR; r += gridDim.x) {
+  // this workgroup's share of the touched rows, scanned HEAVY_WG at a time by
+  // every thread at once; the changed heavy ones are then taken in turn
+  const int64_t per = (nR + gridDim.x - 1) / gridDim.x;
+  const int64_t rb = (int64_t)blockIdx.x * per, re = min(nR, rb + per);
+  for (int64_t c0 = rb; c0 < re; c0 += HEAVY_WG) {
+  int32_t npick;
+  {
+    const int64_t rr = c0 + tid;
+    const bool f = rr < re && U.pchg[rr] && (U.pdel[rr] & PL_HEAVY);
+    const int32_t q = block_flag_prefix<HEAVY_WG>(f, wc, npick);
+    if (f) picked[q] = (int32_t)rr;
+    __syncthreads();
+  }
+  for (int32_t pq = 0; pq < npick; ++pq) {
+    const int64_t r = picked[pq];
     const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
-    // unchanged, losing entries or light: k_commit did it
-    if (!U.pchg[r] || U.pdel[r] != PL_HEAVY) continue;
+    const uint8_t pf = U.pdel[r];
+    // unchanged or light: k_commit did it
+    if (!U.pchg[r] || !(pf & PL_HEAVY)) continue;
+    const bool nodel = !(pf & PL_DEL);
+    const bool flat = (pf & PL_FLAT) != 0;
     const int32_t i = U.urow[r];
     const int64_t off = m.row_off[i];
     const int32_t len = m.row_len[i];
     const int32_t nl = U.plen[r];
     const int32_t ncap = U.pcap[r];
+    const bool ixv = ix_valid(X, i);  // read by every thread before anyone changes it
     int64_t dest = off;
     if (ncap) {
       if (tid == 0) dest_s = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
       __syncthreads();
-      if ((int64_t)dest_s + ncap > m.pool_cap) {
+      dest = (int64_t)dest_s;
+      __syncthreads();
+      if (dest + ncap > m.pool_cap) {
         if (tid == 0) atomicOr(err, 1);
-        __syncthreads();
         continue;
       }
-      dest = (int64_t)dest_s;
-      for (int32_t t0 = tid; t0 < len; t0 += 4 * HEAVY_WG) {
-        int32_t cc[4];
-        uint64_t vv[4];
+    }
+    bool ixk = false;  // the column index stays usable
+    if (nodel) {
+      if (ncap) {
+        for (int32_t t0 = tid; t0 < len; t0 += 4 * HEAVY_WG) {
+          int32_t cc[4];
+          uint64_t vv[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int32_t t = t0 + v * HEAVY_WG;
-          cc[v] = t < len ? m.col[off + t] : 0;
-          vv[v] = t < len ? load_raw<VSZ>(m.val, off + t) : 0;
-        }
+          for (int v = 0; v < 4; ++v) {
+            const int32_t t = t0 + v * HEAVY_WG;
+            cc[v] = t < len ? m.col[off + t] : 0;
+            vv[v] = t < len ? load_raw<VSZ>(m.val, off + t) : 0;
+          }
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int32_t t = t0 + v * HEAVY_WG;
-          if (t < len) {
-            m.col[dest + t] = cc[v];
-            store_raw<VSZ>(m.val, dest + t, vv[v]);
+          for (int v = 0; v < 4; ++v) {
+            const int32_t t = t0 + v * HEAVY_WG;
+            if (t < len) {
+              m.col[dest + t] = cc[v];
+              store_raw<VSZ>(m.val, dest + t, vv[v]);
+            }
           }
         }
       }
-      __syncthreads();
-    }
-    for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG)
-      if (U.code[u] == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
-    // inserts after the row's entries, in update order
-    int32_t k = 0;
-    for (int32_t base = u0; base < u1; base += HEAVY_WG) {
-      const int32_t u = base + tid;
-      const bool ins = u < u1 && U.code[u] == C_INS;
-      const uint64_t ib = __ballot(ins);
-      if (lane == 0) wc[wv] = __popcll(ib);
-      __syncthreads();
-      int32_t before = 0, tot = 0;
-      for (int x = 0; x < HEAVY_WG / 64; ++x) {
-        if (x < wv) before += wc[x];
-        tot += wc[x];
+      // the inserts join the column index unless it would be past 3/4 full
+      ixk = ixv && ix_fits(X, i, nl - len);
+      if (!flat) {
+        uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
+        const uint32_t ixm = ixk ? (uint32_t)X.sz[i] - 1 : 0u;
+        for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG)
+          if (U.code[u] == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
+        // inserts after the row's entries, in update order
+        int32_t k = 0;
+        for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+          const int32_t u = base + tid;
+          const bool ins = u < u1 && U.code[u] == C_INS;
+          int32_t tot;
+          const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
+          if (ins) {
+            const int32_t pos = len + k + q;
+            m.col[dest + pos] = (int32_t)(U.key[u] & cmask);
+            store_raw<VSZ>(m.val, dest + pos, U.fin[u]);
+            if (ixk) ix_put(ixt, ixm, (int32_t)(U.key[u] & cmask), pos);
+          }
+          k += tot;
+        }
+      } else if (tid == 0) {
+        U.pix[r] = ixk ? 1 : 0;
       }
-      if (ins) {
-        const int64_t dst = dest + len + k + before + __popcll(ib & lt);
-        m.col[dst] = (int32_t)(U.key[u] & cmask);
-        store_raw<VSZ>(m.val, dst, U.fin[u]);
+    } else {
+      // overwrites and deletion marks at the planned slots
+      int32_t nd = 0;
+      for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+        const int32_t u = base + tid;
+        const uint8_t code = u < u1 ? U.code[u] : C_NOP;
+        if (code == C_DEL) m.col[off + U.slot[u]] = -1;
+        else if (code == C_OVR) store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
+        int32_t tot;
+        (void)block_flag_prefix<HEAVY_WG>(code == C_DEL, wc, tot);
+        nd += tot;
       }
-      k += tot;
+      const int32_t ni = nl - len + nd;
+      __threadfence_block();
       __syncthreads();
+      if (ncap == 0) {
+        ixk = ixv && ix_fits(X, i, ni);
+        uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
+        const uint32_t ixm = ixk ? (uint32_t)X.sz[i] - 1 : 0u;
+        // holes: deleted slots below the new length (their columns leave
+        // tombstones in the index)
+        int32_t H = 0;
+        for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+          const int32_t u = base + tid;
+          const bool del = u < u1 && U.code[u] == C_DEL;
+          if (del && ixk) {
+            const int32_t h = ix_slot(ixt, ixm, (int32_t)(U.key[u] & cmask));
+            if (h >= 0) ixt[h] = IX_TOMB;
+          }
+          const bool hole = del && U.slot[u] < nl;
+          int32_t tot;
+          const int32_t q = block_flag_prefix<HEAVY_WG>(hole, wc, tot);
+          if (hole) U.holes[u0 + H + q] = U.slot[u];
+          H += tot;
+        }
+        // movers: entries left at or above the new length
+        int32_t Mc = 0;
+        for (int32_t s0 = nl; s0 < len; s0 += HEAVY_WG) {
+          const int32_t sl = s0 + tid;
+          const bool mover = sl < len && m.col[off + sl] != -1;
+          int32_t tot;
+          const int32_t q = block_flag_prefix<HEAVY_WG>(mover, wc, tot);
+          if (mover) U.mv_src[u0 + Mc + q] = sl;
+          Mc += tot;
+        }
+        __threadfence_block();
+        __syncthreads();
+        for (int32_t q = tid; q < Mc; q += HEAVY_WG) {
+          const int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q];
+          const int32_t cm = m.col[off + src];
+          m.col[off + dst] = cm;
+          store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
+          if (ixk) {
+            const int32_t h = ix_slot(ixt, ixm, cm);
+            if (h >= 0) ixt[h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
+          }
+        }
+        // inserts: the remaining holes, then the space after the old length
+        int32_t k = 0;
+        for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+          const int32_t u = base + tid;
+          const bool ins = u < u1 && U.code[u] == C_INS;
+          int32_t tot;
+          const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
+          if (ins) {
+            const int32_t mm = Mc + k + q;
+            const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
+            m.col[off + dst] = (int32_t)(U.key[u] & cmask);
+            store_raw<VSZ>(m.val, off + dst, U.fin[u]);
+            if (ixk) ix_put(ixt, ixm, (int32_t)(U.key[u] & cmask), dst);
+          }
+          k += tot;
+        }
+      } else {
+        // compact into fresh space, then append the inserts
+        int32_t kept = 0;
+        for (int32_t s0 = 0; s0 < len; s0 += HEAVY_WG) {
+          const int32_t sl = s0 + tid;
+          const int32_t cc = sl < len ? m.col[off + sl] : -1;
+          const uint64_t vv = sl < len ? load_raw<VSZ>(m.val, off + sl) : 0;
+          int32_t tot;
+          const int32_t q = block_flag_prefix<HEAVY_WG>(cc != -1, wc, tot);
+          if (cc != -1) {
+            m.col[dest + kept + q] = cc;
+            store_raw<VSZ>(m.val, dest + kept + q, vv);
+          }
+          kept += tot;
+        }
+        for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+          const int32_t u = base + tid;
+          const bool ins = u < u1 && U.code[u] == C_INS;
+          int32_t tot;
+          const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
+          if (ins) {
+            m.col[dest + kept + q] = (int32_t)(U.key[u] & cmask);
+            store_raw<VSZ>(m.val, dest + kept + q, U.fin[u]);
+          }
+          kept += tot;
+        }
+      }
+      if (ixk && tid == 0) X.used[i] += ni;
     }
+    __syncthreads();  // every thread has used the row's old bookkeeping
     if (tid == 0) {
+      if (ixv) {
+        if (!ixk) X.stamp[i] = 0;
+        else if (nodel) X.used[i] += nl - len;
+      }
       m.row_len[i] = nl;
       m.row_epoch[i] = *d_epoch;
       if (ncap) {
@@ -718,7 +974,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
         m.row_cap[i] = ncap;
       }
     }
-    if (dkey) {  // at the update's own index, as in k_commit
+    if (dkey && !(flat && nodel)) {  // at the update's own index, as in k_commit
       for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) {
         const uint8_t code = U.code[u];
         if (!emits_delta(code)) continue;
@@ -733,6 +989,63 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
       }
     }
     __syncthreads();
+  }
+  __syncthreads();  // before the next share overwrites the picked rows
+  }
+}
+
+// The overwrites and inserts of heavy rows planned flat without deletions,
+// update by update (after k_commit_heavy moved such rows and decided on
+// their column index): inserts take places after the row's old entries
+// from the row's cursor (one atomic per wavefront for the lanes of its
+// first row), in no particular order.
+template <int SR, int VSZ>
+__global__ __launch_bounds__(256) void k_commit_flat(DMat m, const int64_t* d_nU, uint64_t cmask, Uniq U, int tbits,
+                                                     uint64_t* dkey, uint8_t* dop, void* dval, int64_t dcap,
+                                                     int* err, RowIx X) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  const int64_t nU = *d_nU;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); b0 < nU; b0 += stride) {
+    const int64_t u = b0 + lane;
+    int32_t r = -1;
+    uint8_t code = C_NOP;
+    if (u < nU) {
+      r = U.ur[u];
+      if (U.pdel[r] == (PL_HEAVY | PL_FLAT) && U.pchg[r]) code = U.code[u];
+      else r = -1;
+    }
+    const bool ins = code == C_INS;
+    const int32_t r0 = __shfl(r, 0, 64);
+    const bool mine = ins && r == r0;
+    const uint64_t bm = __ballot(mine);
+    int32_t base = 0;
+    if (lane == 0 && bm) base = atomicAdd(&U.pcnt[4 * r0 + 3], (int32_t)__popcll(bm));
+    base = __shfl(base, 0, 64);
+    if (r < 0) continue;
+    const int32_t i = U.urow[r];
+    const int64_t off = m.row_off[i];
+    if (code == C_OVR) {
+      store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
+    } else if (ins) {
+      const int32_t k = mine ? base + __popcll(bm & lt) : atomicAdd(&U.pcnt[4 * r + 3], 1);
+      const int32_t pos = U.plen[r] - U.pcnt[4 * r + 1] + k;  // after the old entries
+      const int32_t c = (int32_t)(U.key[u] & cmask);
+      m.col[off + pos] = c;
+      store_raw<VSZ>(m.val, off + pos, U.fin[u]);
+      if (U.pix[r]) ix_put(X.tab + X.off[i], (uint32_t)X.sz[i] - 1, c, pos);
+    }
+    if (dkey && emits_delta(code)) {
+      if (u >= dcap) {
+        atomicOr(err, 4);
+      } else {
+        const uint64_t j = U.key[u] & cmask;
+        dkey[u] = (j << tbits) | (uint64_t)(uint32_t)i;
+        dop[u] = DSG_OP_SET;
+        store_raw<VSZ>(dval, u, U.fin[u]);
+      }
+    }
   }
 }
 
@@ -781,7 +1094,7 @@ size_t work_bytes(int64_t n, bool deltas) {
   return Carve::need({N * 8, N * 4, radix_scratch_bytes(n), N * 8, N * 8, N * 8, N * 8, 64, 64,
                       scan_scratch_bytes(n), N * 8, N, N * 8, N * 4, N * 4, N * 4, N, N * 8, N * 4,
                       (N + 1) * 4, N * 4, N * 4, N, N * 4, N * 4, N * 4, 64, 64, 64,
-                      deltas ? N * 8 : 0, deltas ? N : 0, deltas ? N * 8 : 0, N * 8, N, N});
+                      deltas ? N * 8 : 0, deltas ? N : 0, deltas ? N * 8 : 0, N * 8, N, N, N * 16, N});
 }
 
 Work carve_work(void* base, int64_t n, bool deltas) {
@@ -813,7 +1126,7 @@ Work carve_work(void* base, int64_t n, bool deltas) {
   w.U.pchg = cv.take<uint8_t>(N);
   w.U.holes = cv.take<int32_t>(N);
   w.U.mv_src = cv.take<int32_t>(N);
-  w.U.mv_u = cv.take<int32_t>(N);
+  w.U.ur = cv.take<int32_t>(N);
   w.demand = cv.take<unsigned long long>(8);
   w.ndelta = cv.take<unsigned long long>(8);
   w.err = cv.take<int>(16);
@@ -823,6 +1136,8 @@ Work carve_work(void* base, int64_t n, bool deltas) {
   w.U.old = cv.take<uint64_t>(N);
   w.allops = cv.take<uint8_t>(N);
   w.U.pdel = cv.take<uint8_t>(N);
+  w.U.pcnt = cv.take<int32_t>(N * 4);
+  w.U.pix = cv.take<uint8_t>(N);
   return w;
 }
 
@@ -875,14 +1190,29 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
                         bool graph, const Guard& G, int phases = PH_PLAN | PH_COMMIT, bool deltas_done = false) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
-  unsigned nb = blocks_for(n * 64, 256);
+  // plan and commit take the touched rows in turn: a grid of at most 32
+  // workgroups per CU, not one wavefront per update
+  unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n * 64, 256), 32 * (int64_t)c->num_cus));
   const unsigned nh = (unsigned)std::max(1, c->num_cus);
   const unsigned nph = nh * HEAVY_PLAN_PER_CU;  // the heavy commit takes the same grid
+  // the column index is used outside graphs only (a captured launch would
+  // keep the index generation of its capture); whoever replays a graph
+  // apply drops the matrix's index
+  const RowIx X = graph ? RowIx() : mat_index_view(m);
+  // the flat kernels: one thread per unique update, bounded grid
+  const unsigned nf = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n, 256), 32 * (int64_t)c->num_cus));
   if (phases & PH_PLAN) {
+  // tables for the touched rows that have none, before the plan looks them up
+  if (X.tab) {
+    mat_index_build(m, w.U.urow, w.nR, n);
+    hipLaunchKernelGGL(k_zero_pcnt, dim3(nf), dim3(256), 0, s, w.U.pcnt, (const int64_t*)w.nR);
+    hipLaunchKernelGGL((k_plan_flat<SR, VSZ>), dim3(nf), dim3(256), 0, s, *m, (const int64_t*)w.nU, cmask, w.idx,
+                       vals, w.U, G, X);
+  }
   hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
-                     w.demand, G);
+                     w.demand, G, X);
   hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
-                     w.demand, G);
+                     w.demand, G, X);
   if (!graph) {
     // the one host round trip: how much pool space moved rows need
     unsigned long long* h = (unsigned long long*)c->pinned;
@@ -901,11 +1231,15 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
       // of its length: a row planned to grow in place may no longer fit, so
       // plan again against the new capacities
       hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, w.demand);
-      if (G.nlost) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, G.nlost);
+      if (X.tab) {
+        hipLaunchKernelGGL(k_zero_pcnt, dim3(nf), dim3(256), 0, s, w.U.pcnt, (const int64_t*)w.nR);
+        hipLaunchKernelGGL((k_plan_flat<SR, VSZ>), dim3(nf), dim3(256), 0, s, *m, (const int64_t*)w.nU, cmask,
+                           w.idx, vals, w.U, G, X);
+      }
       hipLaunchKernelGGL((k_plan<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
-                         w.demand, G);
+                         w.demand, G, X);
       hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals,
-                         w.U, w.demand, G);
+                         w.U, w.demand, G, X);
     }
   }
   }
@@ -913,9 +1247,12 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
   // (graph mode: the caller reserved the worst case, see apply_headroom)
   uint64_t* dk = deltas_done ? nullptr : w.dkey;
   hipLaunchKernelGGL((k_commit<SR, VSZ>), dim3(nb), dim3(256), 0, s, *m, w.nR, cmask, cbits, w.U,
-                     (const uint32_t*)m->d_epoch, tbits, dk, w.dop, w.dval, n, w.err);
+                     (const uint32_t*)m->d_epoch, tbits, dk, w.dop, w.dval, n, w.err, X);
   hipLaunchKernelGGL((k_commit_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.U,
-                     (const uint32_t*)m->d_epoch, tbits, dk, w.dop, w.dval, n, w.err);
+                     (const uint32_t*)m->d_epoch, tbits, dk, w.dop, w.dval, n, w.err, X);
+  if (X.tab)
+    hipLaunchKernelGGL((k_commit_flat<SR, VSZ>), dim3(nf), dim3(256), 0, s, *m, (const int64_t*)w.nU, cmask, w.U,
+                       tbits, dk, w.dop, w.dval, n, w.err, X);
 }
 
 // Steps 2-6 on keys/idx already filled (n entries, sentinel-padded allowed);
@@ -1055,6 +1392,26 @@ void keep_log(DMat* m, Work& w, int64_t n) {
   DSG_HIP(hipMemcpyAsync(m->d_log_n, w.nU, 8, hipMemcpyDeviceToDevice, s));
 }
 
+__global__ void k_lost_flags(const uint8_t* code, const int64_t* d_nU, int64_t n, uint8_t* flag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) flag[t] = (t < *d_nU && code[t] == C_LOST) ? 1 : 0;
+}
+
+__global__ void k_lost_gather(const int32_t* li, const int32_t* d_cnt, int64_t n, const uint64_t* key,
+                              const int32_t* slot, uint64_t* lost_key, int32_t* lost_slot,
+                              unsigned long long* d_nlost, const int64_t* d_nR, int64_t* d_nrows) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q == 0) {
+    *d_nlost = (unsigned long long)*d_cnt;
+    if (d_nrows) *d_nrows = *d_nR;
+  }
+  if (q < n && q < *d_cnt) {
+    const int32_t u = li[q];
+    lost_key[q] = key[u];
+    lost_slot[q] = slot[u];
+  }
+}
+
 __global__ void k_ops_from_flags(const uint8_t* flag, int64_t n, uint8_t* ops, const uint64_t* keys,
                                  uint64_t* wkeys, uint32_t* idx) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1067,33 +1424,50 @@ __global__ void k_ops_from_flags(const uint8_t* flag, int64_t n, uint8_t* ops, c
 
 }  // namespace
 
+size_t sorted_add_scratch_bytes(int64_t n) {
+  const size_t N = (size_t)std::max<int64_t>(n, 1);
+  return Carve::need({N, N * 4, compact_scratch_bytes(N), 64});
+}
+
 int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, const uint64_t* guard,
                              const uint8_t* flag, int64_t n, uint64_t* lost_key, int32_t* lost_slot,
-                             int64_t lost_cap, unsigned long long* d_nlost) {
+                             int64_t lost_cap, unsigned long long* d_nlost, int64_t* d_nrows, void* scratch) {
   DSG_REQUIRE(!m->tidx, DSG_E_STATE, "internal: sorted ADD apply on a matrix with a transpose");
+  DSG_REQUIRE(lost_cap >= n, DSG_E_STATE, "internal: lost-entry list shorter than the updates");
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_nlost);
-  if (n == 0) return 0;
+  if (n == 0) {
+    if (d_nrows) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, (unsigned long long*)d_nrows);
+    return 0;
+  }
   Work w = carve_work(ctx_scratch(c, work_bytes(n, false)), n, false);
   hipLaunchKernelGGL(k_ops_from_flags, dim3(blocks_for(n, 256)), dim3(256), 0, s, flag, n, w.allops, keys, w.keys,
                      w.idx);
   Guard G;
   G.key = guard;
   G.flag = flag;
-  G.lost_key = lost_key;
-  G.lost_slot = lost_slot;
-  G.nlost = d_nlost;
-  G.cap = lost_cap;
   const int kbits = bits_for(m->ncols) + bits_for(m->nrows);
   run_core(m, w, n, kbits, false, w.allops, vals, false, true, G);
+  // the lost entries, in key order: a compaction of the outcomes (no
+  // contended counter)
+  Carve cv(scratch, sorted_add_scratch_bytes(n));
+  uint8_t* lf = cv.take<uint8_t>((size_t)n);
+  int32_t* li = cv.take<int32_t>((size_t)n);
+  void* cscr = cv.take<char>(compact_scratch_bytes(n));
+  int32_t* d_cnt = cv.take<int32_t>(16);
+  hipLaunchKernelGGL(k_lost_flags, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const uint8_t*)w.U.code,
+                     (const int64_t*)w.nU, n, lf);
+  compact_flags(lf, n, li, d_cnt, cscr, s);
+  hipLaunchKernelGGL(k_lost_gather, dim3(blocks_for(n, 256)), dim3(256), 0, s, (const int32_t*)li,
+                     (const int32_t*)d_cnt, n, (const uint64_t*)w.U.key, (const int32_t*)w.U.slot, lost_key, lost_slot,
+                     d_nlost, (const int64_t*)w.nR, d_nrows);
   unsigned long long* h = (unsigned long long*)c->pinned;
   int* he = (int*)((char*)c->pinned + 64);
   DSG_HIP(hipMemcpyAsync(h, d_nlost, 8, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipMemcpyAsync(he, w.err, 4, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(he[0] == 0, DSG_E_DEVICE, "internal: pool overflow while applying product updates");
-  DSG_REQUIRE((int64_t)h[0] <= lost_cap, DSG_E_DEVICE, "internal: lost-entry list overflow");
   return (int64_t)h[0];
 }
 

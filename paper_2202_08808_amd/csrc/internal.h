@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/dsg.h"
+#include "rowindex.h"
 
 // ---------------------------------------------------------------------------
 // host-side error plumbing
@@ -89,6 +90,16 @@ struct DMat {
   int64_t log_cap = 0;
   uint64_t apply_seq = 0;         // applies so far
   uint64_t log_seq = 0;           // the apply whose log is held (0: none)
+  // per-row column index (rowindex.h); ix_tab == nullptr: none
+  uint64_t* ix_tab = nullptr;
+  int64_t* ix_off = nullptr;
+  int32_t* ix_sz = nullptr;
+  int32_t* ix_used = nullptr;
+  uint32_t* ix_stamp = nullptr;
+  unsigned long long* ix_top = nullptr;  // device: first free slot of ix_tab
+  int64_t ix_cap = 0;
+  uint32_t ix_gen = 1;            // a row's table is usable while its stamp equals this
+  bool ix_refused = false;        // no room for an index: the matrix runs without one
 };
 
 // Per-kernel timing record.
@@ -212,6 +223,21 @@ void mat_export_device(DMat* m, int64_t* d_row_ptr, int32_t* d_col, void* d_val,
 // Build the structure-only transpose index of m.
 void mat_build_transpose(DMat* m);
 
+// Per-row column index (rowindex.hip).  mat_index_enable allocates it (false
+// when there is no room: the matrix then goes on without one); every table
+// starts invalid.  mat_index_invalidate drops every table at once (any
+// writer that may reorder rows of m without maintaining the tables calls
+// it).  mat_index_build makes the tables of the listed rows (*d_n of them,
+// at most n_max; all rows when d_rows is null, then d_n may be null too)
+// usable, as far as the pool has room.  mat_index_note_top takes a host
+// copy of the pool top and resets the pool when most of it is taken.
+RowIx mat_index_view(const DMat* m);
+bool mat_index_enable(DMat* m);
+void mat_index_free(DMat* m);
+void mat_index_invalidate(DMat* m);
+void mat_index_build(DMat* m, const int32_t* d_rows, const int64_t* d_n, int64_t n_max);
+void mat_index_note_top(DMat* m, uint64_t top);
+
 // Listed rows of a matrix, copied to the host with each row sorted by column.
 struct RowsHost {
   std::vector<int64_t> row_ptr;  // n + 1
@@ -269,13 +295,17 @@ void mat_apply_graph(DMat* m, const int32_t* d_rows, const int32_t* d_cols, cons
 // Apply n unique keys (row << colbits | col), sorted ascending, to m as ADD
 // updates: vals[u] is folded in with the semiring addition when flag[u] & 1
 // (else the key only carries a guard).  An entry present in m is left
-// unchanged and listed as lost -- (key, row-relative slot), at most lost_cap,
-// count in *d_nlost -- when flag[u] & 4, or when flag[u] & 2 and its stored
-// value has the ordered key guard[u] while vals[u] (if any) is strictly
-// larger.  Returns the number of lost entries.  m must have no transpose.
+// unchanged and listed as lost -- (key, row-relative slot) in key order, at
+// most lost_cap >= n, count in *d_nlost -- when flag[u] & 4, or when
+// flag[u] & 2 and its stored value has the ordered key guard[u] while
+// vals[u] (if any) is strictly larger.  *d_nrows (when not null) receives
+// the number of distinct rows among the keys.  scratch holds
+// sorted_add_scratch_bytes(n) bytes.  Returns the number of lost entries.
+// m must have no transpose.
+size_t sorted_add_scratch_bytes(int64_t n);
 int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, const uint64_t* guard,
                              const uint8_t* flag, int64_t n, uint64_t* lost_key, int32_t* lost_slot,
-                             int64_t lost_cap, unsigned long long* d_nlost);
+                             int64_t lost_cap, unsigned long long* d_nlost, int64_t* d_nrows, void* scratch);
 // Device validation of a batch: returns dsg_status.
 dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols,
                                  const uint8_t* d_ops, int64_t n);
@@ -310,8 +340,6 @@ struct DProd {
   uint64_t a_seq = 0, b_seq = 0;  // applies of A and B that C reflects
   void* ews = nullptr;            // workspace of the entry-granular path
   size_t ews_bytes = 0;
-  void* srt = nullptr;            // column-sorted copy of A (entry-granular path)
-  size_t srt_bytes = 0;
   void* bsp = nullptr;            // B with each row's entries grouped by dense column chunk
   size_t bsp_bytes = 0;
   size_t bsp_col_off = 0, bsp_val_off = 0;

@@ -96,3 +96,24 @@ __device__ inline bool same_bits(T a, T b) {
 }
 
 __device__ inline uint32_t hash_col(int32_t c) { return (uint32_t)c * 2654435761u; }
+
+// Exclusive prefix of a flag over a workgroup of NT lanes, and its total.
+// Every thread of the workgroup calls it (it holds two barriers); wsum holds
+// NT/64 ints of LDS.
+template <int NT>
+__device__ inline int32_t block_flag_prefix(bool f, int32_t* wsum, int32_t& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint64_t b = __ballot(f);
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  if (lane == 0) wsum[wv] = __popcll(b);
+  __syncthreads();
+  int32_t before = 0, tot = 0;
+  for (int x = 0; x < NT / 64; ++x) {
+    const int32_t c = wsum[x];
+    if (x < wv) before += c;
+    tot += c;
+  }
+  __syncthreads();
+  total = tot;
+  return before + __popcll(b & lt);
+}

@@ -233,6 +233,7 @@ void mat_destroy(DMat* m) {
   ctx_free(c, m->log_new, (size_t)m->log_cap * 8);
   ctx_free(c, m->log_code, (size_t)m->log_cap);
   ctx_free(c, m->d_log_n, 64);
+  mat_index_free(m);
   if (m->counted) c->objects--;
   delete m;
 }

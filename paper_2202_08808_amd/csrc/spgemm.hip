@@ -2167,6 +2167,7 @@ constexpr int SIDE_BINS = 6;
 void launch_rows(DProd* p, const RowArgs& R, ProdWork& w, const Plan* hplan,
                  std::vector<std::pair<int, size_t>>& timed) {
   Ctx* c = p->ctx;
+  mat_index_invalidate(p->C);  // recomputed rows are written in a new order
   zero_arena_top(p);
   if (side_split(c, hplan, SIDE_BINS)) {
     fork_side(p, R, w, hplan, timed, SIDE_BINS);
@@ -2394,7 +2395,6 @@ void prod_destroy(DProd* p) {
   if (p->arena_top) ctx_free(c, p->arena_top, 64);
   if (p->d_sync) ctx_free(c, p->d_sync, 16);
   if (p->ews) ctx_free(c, p->ews, p->ews_bytes);
-  if (p->srt) ctx_free(c, p->srt, p->srt_bytes);
   if (p->bsp) ctx_free(c, p->bsp, p->bsp_bytes);
   if (p->gws) ctx_free(c, p->gws, p->gws_bytes);
   if (p->F) mat_destroy(p->F);
