@@ -441,18 +441,6 @@ __global__ __launch_bounds__(256) void k_lost_recompute(LostArgs L, const int32_
   }
 }
 
-// the flagged lost entries as a DELETE batch
-__global__ void k_del_batch(const uint64_t* key, const int32_t* list, int64_t n, int cbits, int32_t* rows,
-                            int32_t* cols, uint8_t* ops) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) {
-    const uint64_t k = key[list[t]];
-    rows[t] = (int32_t)(k >> cbits);
-    cols[t] = (int32_t)(k & ((1ull << cbits) - 1));
-    ops[t] = DSG_OP_DELETE;
-  }
-}
-
 __global__ void k_copy_u32(const uint32_t* src, uint32_t* dst) { *dst = *src; }
 
 __global__ void k_rows_after(int32_t n, const uint32_t* epoch, const uint32_t* since, uint8_t* flags) {
@@ -580,8 +568,7 @@ int32_t entry_update(DProd* p) {
                                       radix_scratch_bytes(NT), (size_t)NT * 8, (size_t)NT * 8,
                                       scan_scratch_bytes(NT) + 64, (size_t)(NT + 1) * 8});
   const size_t lost_b = Carve::need({(size_t)NT * 8, (size_t)NT * 4, (size_t)NT, (size_t)NT, (size_t)NT * 4,
-                                     (size_t)NT * 4, (size_t)NT, (size_t)NT * 4, (size_t)NT * 4, (size_t)NT * 4,
-                                     (size_t)NT, compact_scratch_bytes(NT) + 64, 64});
+                                     (size_t)NT * 4, (size_t)NT, (size_t)NT * 4, compact_scratch_bytes(NT) + 64, 64});
   uint32_t hs = 64;
   while (hs < 2 * (uint64_t)std::max<int64_t>(nU, 1)) hs <<= 1;
   const size_t segs_b = Carve::need({(size_t)NT * 8, (size_t)NT * 8, (size_t)NT * 8, (size_t)NT, 256, (size_t)n + 64,
@@ -652,9 +639,6 @@ int32_t entry_update(DProd* p) {
   int32_t* lwide = cl.take<int32_t>(NT);
   uint8_t* fdel = cl.take<uint8_t>(NT);
   int32_t* ldel = cl.take<int32_t>(NT);
-  int32_t* drows = cl.take<int32_t>(NT);
-  int32_t* dcols = cl.take<int32_t>(NT);
-  uint8_t* dops = cl.take<uint8_t>(NT);
   void* lscr = cl.take<char>(compact_scratch_bytes(NT) + 64);
   int32_t* lcnt = cl.take<int32_t>(16);  // [0] narrow, [1] wide, [2] deletions
   int64_t nlost = 0;
@@ -706,9 +690,8 @@ int32_t entry_update(DProd* p) {
     DSG_HIP(hipStreamSynchronize(s));
     const int64_t ndel = hd[0];
     if (ndel > 0) {
-      hipLaunchKernelGGL(k_del_batch, dim3(blocks_for(ndel, 256)), dim3(256), 0, s, (const uint64_t*)lkey,
-                         (const int32_t*)ldel, ndel, cbits, drows, dcols, dops);
-      mat_apply_device(C, drows, dcols, nullptr, dops, ndel);
+      Phase ph(c, "entry_delete");
+      mat_apply_sorted_delete(C, lkey, ldel, ndel);
     }
   }
 

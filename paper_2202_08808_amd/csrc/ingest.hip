@@ -1380,16 +1380,29 @@ void reserve_log(DMat* m, int64_t n) {
   if (!m->d_log_n) m->d_log_n = (int64_t*)ctx_alloc(c, 64);
 }
 
+// the log of an apply in one launch: its unique keys, values before and
+// after and outcomes, and their count
+__global__ void k_keep_log(const Uniq U, const int64_t* d_nU, uint64_t* key, uint64_t* old, uint64_t* nw,
+                           uint8_t* code, int64_t* d_n) {
+  const int64_t n = *d_nU;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t0 == 0) *d_n = n;
+  for (int64_t u = t0; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+    key[u] = U.key[u];
+    old[u] = U.old[u];
+    nw[u] = U.fin[u];
+    code[u] = U.code[u];
+  }
+}
+
 // Keep the unique keys of this apply with their values before and after and
 // their outcomes: the entry-granular and general-update product paths read
 // them.  reserve_log(m, n) must have run.
 void keep_log(DMat* m, Work& w, int64_t n) {
   hipStream_t s = m->ctx->stream;
-  DSG_HIP(hipMemcpyAsync(m->log_key, w.U.key, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-  DSG_HIP(hipMemcpyAsync(m->log_old, w.U.old, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-  DSG_HIP(hipMemcpyAsync(m->log_new, w.U.fin, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-  DSG_HIP(hipMemcpyAsync(m->log_code, w.U.code, (size_t)n, hipMemcpyDeviceToDevice, s));
-  DSG_HIP(hipMemcpyAsync(m->d_log_n, w.nU, 8, hipMemcpyDeviceToDevice, s));
+  const unsigned nb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n, 256), 4096));
+  hipLaunchKernelGGL(k_keep_log, dim3(nb), dim3(256), 0, s, (const Uniq)w.U, (const int64_t*)w.nU, m->log_key,
+                     m->log_old, m->log_new, m->log_code, m->d_log_n);
 }
 
 __global__ void k_lost_flags(const uint8_t* code, const int64_t* d_nU, int64_t n, uint8_t* flag) {
@@ -1409,6 +1422,17 @@ __global__ void k_lost_gather(const int32_t* li, const int32_t* d_cnt, int64_t n
     const int32_t u = li[q];
     lost_key[q] = key[u];
     lost_slot[q] = slot[u];
+  }
+}
+
+// sorted unique keys keys[list[t]] as DELETE updates
+__global__ void k_delete_keys(const uint64_t* keys, const int32_t* list, int64_t n, uint64_t* wkeys, uint32_t* idx,
+                              uint8_t* ops) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) {
+    wkeys[t] = keys[list ? list[t] : t];
+    idx[t] = (uint32_t)t;
+    ops[t] = DSG_OP_DELETE;
   }
 }
 
@@ -1469,6 +1493,22 @@ int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, co
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(he[0] == 0, DSG_E_DEVICE, "internal: pool overflow while applying product updates");
   return (int64_t)h[0];
+}
+
+void mat_apply_sorted_delete(DMat* m, const uint64_t* keys, const int32_t* list, int64_t n) {
+  DSG_REQUIRE(!m->tidx, DSG_E_STATE, "internal: sorted delete on a matrix with a transpose");
+  if (n == 0) return;
+  Ctx* c = m->ctx;
+  hipStream_t s = c->stream;
+  Work w = carve_work(ctx_scratch(c, work_bytes(n, false)), n, false);
+  hipLaunchKernelGGL(k_delete_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, list, n, w.keys, w.idx,
+                     w.allops);
+  const int kbits = bits_for(m->ncols) + bits_for(m->nrows);
+  run_core(m, w, n, kbits, false, w.allops, nullptr, false, true);
+  int* he = (int*)((char*)c->pinned + 64);
+  DSG_HIP(hipMemcpyAsync(he, w.err, 4, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  DSG_REQUIRE(he[0] == 0, DSG_E_DEVICE, "internal: pool overflow while deleting product entries");
 }
 
 size_t apply_work_bytes(int64_t n, bool deltas) { return work_bytes(n, deltas); }

@@ -102,10 +102,42 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_single(const In* in, int64_t* 
   if (threadIdx.x == 0 && total) *total = tot;
 }
 
+// up to SCAN_WG_MAX entries: one workgroup walks the tiles in order,
+// carrying the running sum (one launch instead of three)
+constexpr int64_t SCAN_WG_MAX = 4 * SCAN_TILE;
+
+template <class In>
+__global__ __launch_bounds__(SCAN_NT) void k_scan_wg(const In* in, int64_t* out, int64_t n, int64_t* total) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += SCAN_TILE) {
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+      const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+      v[t] = i < n ? (int64_t)in[i] : 0;
+      s += v[t];
+    }
+    int64_t tot;
+    int64_t run = carry + block_exclusive_scan<int64_t>(s, lds, tot);
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+      const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+      if (i < n) out[i] = run;
+      run += v[t];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
 template <class In>
 void scan_impl(const In* in, int64_t* out, int64_t n, int64_t* d_total, void* scratch, hipStream_t s) {
   if (n <= SCAN_TILE) {
     hipLaunchKernelGGL(k_scan_single<In>, dim3(1), dim3(SCAN_NT), 0, s, in, out, n, d_total);
+    return;
+  }
+  if (n <= SCAN_WG_MAX) {
+    hipLaunchKernelGGL(k_scan_wg<In>, dim3(1), dim3(SCAN_NT), 0, s, in, out, n, d_total);
     return;
   }
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
@@ -155,6 +187,32 @@ __global__ __launch_bounds__(SCAN_NT) void k_flag_write(const uint8_t* flags, co
 }
 
 __global__ void k_store_count(const int64_t* total, int32_t* d_count) { *d_count = (int32_t)*total; }
+
+// up to SCAN_WG_MAX flags: the whole compaction in one workgroup (one
+// launch instead of four)
+__global__ __launch_bounds__(SCAN_NT) void k_compact_wg(const uint8_t* flags, const int32_t* list, int64_t n,
+                                                        int32_t* out, const int32_t* d_n, int32_t* d_count) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  if (d_n) n = *d_n;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += SCAN_TILE) {
+    uint8_t f[SCAN_ITEMS];
+    int64_t c = 0;
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+      const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+      f[t] = (i < n && flags[i]) ? 1 : 0;
+      c += f[t];
+    }
+    int64_t tot;
+    int64_t pos = carry + block_exclusive_scan<int64_t>(c, lds, tot);
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+      const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+      if (f[t]) out[pos++] = list ? list[i] : (int32_t)i;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) *d_count = (int32_t)carry;
+}
 
 // ---- radix sort ----
 
@@ -269,6 +327,11 @@ size_t compact_scratch_bytes(int64_t n) { return scan_scratch_bytes(n) + 256; }
 
 void compact_flags(const uint8_t* flags, int64_t n, int32_t* out, int32_t* d_count, void* scratch,
                    hipStream_t s) {
+  if (n <= SCAN_WG_MAX) {
+    hipLaunchKernelGGL(k_compact_wg, dim3(1), dim3(SCAN_NT), 0, s, flags, (const int32_t*)nullptr, n, out,
+                       (const int32_t*)nullptr, d_count);
+    return;
+  }
   int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
   if (tiles == 0) tiles = 1;
   int64_t* sums = (int64_t*)scratch;
@@ -283,6 +346,10 @@ void compact_flags(const uint8_t* flags, int64_t n, int32_t* out, int32_t* d_cou
 
 void compact_list_by_flags(const int32_t* list, const uint8_t* flags, const int32_t* d_n, int64_t n_max,
                            int32_t* out, int32_t* d_count, void* scratch, hipStream_t s) {
+  if (n_max <= SCAN_WG_MAX) {
+    hipLaunchKernelGGL(k_compact_wg, dim3(1), dim3(SCAN_NT), 0, s, flags, list, n_max, out, d_n, d_count);
+    return;
+  }
   int64_t tiles = (n_max + SCAN_TILE - 1) / SCAN_TILE;
   if (tiles == 0) tiles = 1;
   int64_t* sums = (int64_t*)scratch;
