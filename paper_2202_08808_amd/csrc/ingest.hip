@@ -35,6 +35,7 @@ constexpr int PLAN_LDS = 1024;        // update columns of a row held in LDS by 
 constexpr uint8_t PL_DEL = 1;         // plan flags of a touched row
 constexpr uint8_t PL_HEAVY = 2;
 constexpr uint8_t PL_FLAT = 4;        // heavy row planned update by update through its column index
+constexpr uint8_t PL_PURE_DEL = 8;    // ... whose updates all delete: committed update by update too
 constexpr int HEAVY_LEN = 2048;       // rows longer than this are planned by a whole workgroup
 constexpr uint8_t C_NOP = UPD_NOP, C_INS = UPD_INS, C_DEL = UPD_DEL, C_OVR = UPD_OVR, C_LOST = UPD_LOST;
 // the outcomes that change the operand, so the transpose index too
@@ -674,7 +675,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
         const bool reloc = nl > cap;
         U.plen[r] = nl;
         U.pchg[r] = (nd + ni + no) > 0 ? 1 : 0;
-        U.pdel[r] = (nd > 0 ? PL_DEL : 0) | PL_HEAVY | PL_FLAT;
+        U.pdel[r] = (nd > 0 ? PL_DEL : 0) | PL_HEAVY | PL_FLAT | (nd == u1 - u0 ? PL_PURE_DEL : 0);
         U.pcap[r] = reloc ? slack_cap(nl) : 0;
         if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
       }
@@ -796,6 +797,14 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
     const bool nodel = !(pf & PL_DEL);
     const bool flat = (pf & PL_FLAT) != 0;
     const int32_t i = U.urow[r];
+    if (pf & PL_PURE_DEL) {
+      // k_delete_flat moves the entries; the row keeps its space and index
+      if (tid == 0) {
+        m.row_len[i] = U.plen[r];
+        m.row_epoch[i] = *d_epoch;
+      }
+      continue;
+    }
     const int64_t off = m.row_off[i];
     const int32_t len = m.row_len[i];
     const int32_t nl = U.plen[r];
@@ -991,6 +1000,96 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
     __syncthreads();
   }
   __syncthreads();  // before the next share overwrites the picked rows
+  }
+}
+
+// Heavy rows planned flat whose updates all delete (nd of them, new length
+// nl = len - nd, always in place), update by update in three launches:
+//   1. mark each deleted slot, leave a tombstone in the column index, emit
+//      the transpose change; a deleted slot below nl is a hole (ticket from
+//      the row's hole counter);
+//   2. update q of the row looks at slot nl + q of the old tail: a live
+//      entry there is a mover (ticket from the row's mover counter);
+//   3. mover t goes to hole t (its index slot follows).
+// Holes and movers are equally many; which hole a mover fills does not
+// matter.  Counters are taken once per wavefront for the lanes of its first
+// row.
+__device__ inline int32_t row_ticket(int32_t* ctr, int32_t r, bool take, int lane) {
+  const int32_t r0 = __shfl(r, 0, 64);
+  const bool mine = take && r == r0;
+  const uint64_t bm = __ballot(mine);
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int32_t base = 0;
+  if (lane == 0 && bm) base = atomicAdd(&ctr[4 * r0], (int32_t)__popcll(bm));
+  base = __shfl(base, 0, 64);
+  if (!take) return -1;
+  return mine ? base + __popcll(bm & lt) : atomicAdd(&ctr[4 * r], 1);
+}
+
+template <int VSZ>
+__global__ __launch_bounds__(256) void k_delete_flat(DMat m, const int64_t* d_nU, uint64_t cmask, Uniq U,
+                                                     int stage, int tbits, uint64_t* dkey, uint8_t* dop,
+                                                     void* dval, int64_t dcap, int* err, RowIx X) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nU = *d_nU;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); b0 < nU; b0 += stride) {
+    const int64_t u = b0 + lane;
+    int32_t r = -1;
+    if (u < nU) {
+      r = U.ur[u];
+      if (!(U.pdel[r] & PL_PURE_DEL)) r = -1;
+    }
+    const int32_t i = r >= 0 ? U.urow[r] : 0;
+    const int64_t off = r >= 0 ? m.row_off[i] : 0;
+    const int32_t nl = r >= 0 ? U.plen[r] : 0;
+    const bool ixk = r >= 0 && ix_valid(X, i);
+    if (stage == 1) {
+      bool hole = false;
+      int32_t sl = 0;
+      if (r >= 0) {
+        sl = U.slot[u];
+        const int32_t c = (int32_t)(U.key[u] & cmask);
+        m.col[off + sl] = -1;
+        if (ixk) {
+          const int32_t h = ix_slot(X.tab + X.off[i], (uint32_t)X.sz[i] - 1, c);
+          if (h >= 0) X.tab[X.off[i] + h] = IX_TOMB;
+        }
+        hole = sl < nl;
+        if (dkey) {
+          if (u >= dcap) {
+            atomicOr(err, 4);
+          } else {
+            dkey[u] = ((uint64_t)(uint32_t)c << tbits) | (uint64_t)(uint32_t)i;
+            dop[u] = DSG_OP_DELETE;
+            store_raw<VSZ>(dval, u, U.fin[u]);
+          }
+        }
+      }
+      const int32_t t = row_ticket(U.pcnt + 1, r, hole, lane);
+      if (hole) U.holes[U.row_first[r] + t] = sl;
+    } else if (stage == 2) {
+      bool mover = false;
+      int32_t p = 0;
+      if (r >= 0) {
+        p = nl + (int32_t)(u - U.row_first[r]);
+        mover = m.col[off + p] != -1;
+      }
+      const int32_t t = row_ticket(U.pcnt + 2, r, mover, lane);
+      if (mover) U.mv_src[U.row_first[r] + t] = p;
+    } else if (r >= 0) {
+      const int32_t t = (int32_t)(u - U.row_first[r]);
+      if (t < U.pcnt[4 * r + 2]) {
+        const int32_t src = U.mv_src[U.row_first[r] + t], dst = U.holes[U.row_first[r] + t];
+        const int32_t cm = m.col[off + src];
+        m.col[off + dst] = cm;
+        store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
+        if (ixk) {
+          const int32_t h = ix_slot(X.tab + X.off[i], (uint32_t)X.sz[i] - 1, cm);
+          if (h >= 0) X.tab[X.off[i] + h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
+        }
+      }
+    }
   }
 }
 
@@ -1250,9 +1349,13 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
                      (const uint32_t*)m->d_epoch, tbits, dk, w.dop, w.dval, n, w.err, X);
   hipLaunchKernelGGL((k_commit_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.U,
                      (const uint32_t*)m->d_epoch, tbits, dk, w.dop, w.dval, n, w.err, X);
-  if (X.tab)
+  if (X.tab) {
     hipLaunchKernelGGL((k_commit_flat<SR, VSZ>), dim3(nf), dim3(256), 0, s, *m, (const int64_t*)w.nU, cmask, w.U,
                        tbits, dk, w.dop, w.dval, n, w.err, X);
+    for (int stage = 1; stage <= 3; ++stage)
+      hipLaunchKernelGGL((k_delete_flat<VSZ>), dim3(nf), dim3(256), 0, s, *m, (const int64_t*)w.nU, cmask, w.U,
+                         stage, tbits, dk, w.dop, w.dval, n, w.err, X);
+  }
 }
 
 // Steps 2-6 on keys/idx already filled (n entries, sentinel-padded allowed);
