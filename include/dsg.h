@@ -162,7 +162,7 @@ typedef struct {
                               plain path beside the graph replay (default 24; 0..62) */
   /* Automatic choice: the entry-granular path runs when the products of the
    * affected rows exceed entry_fixed + entry_per_term * (the changed
-   * products).  Defaults 2e8 and 500 (fitted on MI355X); both finite, >= 0. */
+   * products).  Defaults 1e8 and 70 (fitted on MI355X); both finite, >= 0. */
   double entry_fixed;
   double entry_per_term;
 } dsg_tuning;

@@ -186,8 +186,8 @@ static void default_tuning(dsg_tuning* t) {
   t->force_bin = -1;
   t->update_path = 0;
   t->batch_direct_log2 = 24;
-  t->entry_fixed = 2e8;
-  t->entry_per_term = 500.0;
+  t->entry_fixed = 1e8;
+  t->entry_per_term = 70.0;
 }
 
 // host-side check of a CSR: row_ptr monotone from 0, columns in range, no

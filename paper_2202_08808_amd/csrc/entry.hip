@@ -314,9 +314,10 @@ __global__ void k_seg_reduce(const uint64_t* key, const uint32_t* idx, const uin
 // A lost entry (i, j) takes the minimum (or sum) of a'_ik * a'_kj over k from
 // the shorter of two lists: row i of A' (each k probed for column j in row
 // k's column index) or column j of A' (each k probed for column k in row i's
-// column index).  Entries are split by that length: up to LOST_NARROW_MAX
-// probes take 8 lanes, longer ones a whole wavefront.
-constexpr int32_t LOST_NARROW_MAX = 64;
+// column index).  Entries are split into three classes by that length (up
+// to LOST_C0_MAX, up to LOST_C1_MAX, longer), taken by groups of 8, 32 and 64
+// lanes, so that a group needs about one round of probes.
+constexpr int32_t LOST_C0_MAX = 8, LOST_C1_MAX = 32;
 
 struct LostArgs {
   const uint64_t* key;
@@ -345,7 +346,10 @@ __device__ inline unsigned long long acc_comb(unsigned long long a, unsigned lon
 // position of column c in row r of A' (its table, or a scan of the row when
 // the index pool had no room for it)
 __device__ inline int32_t a_find(const LostArgs& L, int32_t r, int32_t c) {
-  if (ix_valid(L.X, r)) return ix_lookup(L.X, r, c);
+  // (the table's place is read before its stamp is checked: independent loads)
+  const int64_t to = L.X.off[r];
+  const uint32_t mask = (uint32_t)L.X.sz[r] - 1;
+  if (L.X.stamp[r] == L.X.gen) return ix_find(L.X.tab + to, mask, c);
   const int64_t o = L.A.off[r];
   const int32_t n = L.A.len[r];
   for (int32_t t = 0; t < n; ++t)
@@ -373,17 +377,18 @@ __device__ inline void finish_entry(const LostArgs& L, int64_t e, unsigned long 
   }
 }
 
-// flags of the lost entries by probe count: up to LOST_NARROW_MAX, or more
+// class flags of the lost entries by probe count
 __global__ void k_lost_classes(const uint64_t* key, int64_t n, int cbits, const int32_t* a_len, const int32_t* t_len,
-                               uint8_t* narrow, uint8_t* wide) {
+                               uint8_t* c0, uint8_t* c1, uint8_t* c2) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const uint64_t k = key[e];
   const int32_t d = a_len[(int32_t)(k >> cbits)];
   const int32_t lj = t_len[(int32_t)(k & ((1ull << cbits) - 1))];
-  const bool nar = (d < lj ? d : lj) <= LOST_NARROW_MAX;
-  narrow[e] = nar ? 1 : 0;
-  wide[e] = nar ? 0 : 1;
+  const int32_t cost = d < lj ? d : lj;
+  c0[e] = cost <= LOST_C0_MAX ? 1 : 0;
+  c1[e] = (cost > LOST_C0_MAX && cost <= LOST_C1_MAX) ? 1 : 0;
+  c2[e] = cost > LOST_C1_MAX ? 1 : 0;
 }
 
 // G lanes per lost entry; the listed entries taken in turn
@@ -567,8 +572,9 @@ int32_t entry_update(DProd* p) {
   const size_t terms_b = Carve::need({(size_t)NT * 8, (size_t)NT * 4, (size_t)NT * 8, (size_t)NT * 8, (size_t)NT,
                                       radix_scratch_bytes(NT), (size_t)NT * 8, (size_t)NT * 8,
                                       scan_scratch_bytes(NT) + 64, (size_t)(NT + 1) * 8});
-  const size_t lost_b = Carve::need({(size_t)NT * 8, (size_t)NT * 4, (size_t)NT, (size_t)NT, (size_t)NT * 4,
-                                     (size_t)NT * 4, (size_t)NT, (size_t)NT * 4, compact_scratch_bytes(NT) + 64, 64});
+  const size_t lost_b = Carve::need({(size_t)NT * 8, (size_t)NT * 4, (size_t)NT, (size_t)NT, (size_t)NT,
+                                     (size_t)NT * 4, (size_t)NT * 4, (size_t)NT * 4, (size_t)NT, (size_t)NT * 4,
+                                     compact_scratch_bytes(NT) + 64, 64});
   uint32_t hs = 64;
   while (hs < 2 * (uint64_t)std::max<int64_t>(nU, 1)) hs <<= 1;
   const size_t segs_b = Carve::need({(size_t)NT * 8, (size_t)NT * 8, (size_t)NT * 8, (size_t)NT, 256, (size_t)n + 64,
@@ -633,14 +639,12 @@ int32_t entry_update(DProd* p) {
   Carve cl(region, lost_b);
   uint64_t* lkey = cl.take<uint64_t>(NT);
   int32_t* lslot = cl.take<int32_t>(NT);
-  uint8_t* fnarrow = cl.take<uint8_t>(NT);
-  uint8_t* fwide = cl.take<uint8_t>(NT);
-  int32_t* lnarrow = cl.take<int32_t>(NT);
-  int32_t* lwide = cl.take<int32_t>(NT);
+  uint8_t* fcls[3] = {cl.take<uint8_t>(NT), cl.take<uint8_t>(NT), cl.take<uint8_t>(NT)};
+  int32_t* lcls[3] = {cl.take<int32_t>(NT), cl.take<int32_t>(NT), cl.take<int32_t>(NT)};
   uint8_t* fdel = cl.take<uint8_t>(NT);
   int32_t* ldel = cl.take<int32_t>(NT);
   void* lscr = cl.take<char>(compact_scratch_bytes(NT) + 64);
-  int32_t* lcnt = cl.take<int32_t>(16);  // [0] narrow, [1] wide, [2] deletions
+  int32_t* lcnt = cl.take<int32_t>(16);  // [0..2] the classes, [3] deletions
   int64_t nlost = 0;
   {
     Phase ph(c, "entry_apply_c");
@@ -670,23 +674,23 @@ int32_t entry_update(DProd* p) {
       la.c_cur_epoch = C->d_epoch;
       la.del_flag = fdel;
       hipLaunchKernelGGL(k_lost_classes, dim3(blocks_for(nlost, 256)), dim3(256), 0, s, (const uint64_t*)lkey, nlost,
-                         cbits, (const int32_t*)A->row_len, (const int32_t*)T->row_len, fnarrow, fwide);
-      compact_flags(fnarrow, nlost, lnarrow, lcnt, lscr, s);
-      compact_flags(fwide, nlost, lwide, lcnt + 1, lscr, s);
+                         cbits, (const int32_t*)A->row_len, (const int32_t*)T->row_len, fcls[0], fcls[1], fcls[2]);
+      for (int k = 0; k < 3; ++k) compact_flags(fcls[k], nlost, lcls[k], lcnt + k, lscr, s);
       // bounded grids over the device counts
-      const unsigned g8 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(nlost * 8, 256),
-                                                                           32 * (int64_t)c->num_cus));
-      const unsigned g64 = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(nlost * 64, 256),
-                                                                            32 * (int64_t)c->num_cus));
-      hipLaunchKernelGGL((k_lost_recompute<SR, 8>), dim3(g8), dim3(256), 0, s, la, (const int32_t*)lnarrow,
+      auto grid = [&](int g) {
+        return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(nlost * g, 256), 32 * (int64_t)c->num_cus));
+      };
+      hipLaunchKernelGGL((k_lost_recompute<SR, 8>), dim3(grid(8)), dim3(256), 0, s, la, (const int32_t*)lcls[0],
                          (const int32_t*)lcnt);
-      hipLaunchKernelGGL((k_lost_recompute<SR, 64>), dim3(g64), dim3(256), 0, s, la, (const int32_t*)lwide,
+      hipLaunchKernelGGL((k_lost_recompute<SR, 32>), dim3(grid(32)), dim3(256), 0, s, la, (const int32_t*)lcls[1],
                          (const int32_t*)(lcnt + 1));
-      compact_flags(fdel, nlost, ldel, lcnt + 2, lscr, s);
+      hipLaunchKernelGGL((k_lost_recompute<SR, 64>), dim3(grid(64)), dim3(256), 0, s, la, (const int32_t*)lcls[2],
+                         (const int32_t*)(lcnt + 2));
+      compact_flags(fdel, nlost, ldel, lcnt + 3, lscr, s);
       DSG_HIP(hipGetLastError());
     }
     int32_t* hd = (int32_t*)((char*)c->pinned + 3072);
-    DSG_HIP(hipMemcpyAsync(hd, lcnt + 2, 4, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipMemcpyAsync(hd, lcnt + 3, 4, hipMemcpyDeviceToHost, s));
     DSG_HIP(hipStreamSynchronize(s));
     const int64_t ndel = hd[0];
     if (ndel > 0) {

@@ -176,7 +176,7 @@ def test_automatic_path_choice(ctx, sr):
     to the row path."""
     say(f"automatic path {SR_ID[sr]}")
     d = ctx.get_tuning()
-    assert (d.entry_fixed, d.entry_per_term) == (2e8, 500.0)
+    assert (d.entry_fixed, d.entry_per_term) == (1e8, 70.0)
     hi = 9 if sr == I.PLUS_TIMES_I64 else 100
     A = I.rmat_csr(15, 16, sr, stream=821, lo=1, hi=hi)
     bs = I.disjoint_batches(A, sr, [200, 30000], stream=822, value_lo=1, value_hi=hi)
