@@ -165,6 +165,13 @@ typedef struct {
    * products).  Defaults 1e8 and 70 (fitted on MI355X); both finite, >= 0. */
   double entry_fixed;
   double entry_per_term;
+  int32_t row_index;       /* 1 (default): the entry-granular path gives C and A a per-row column
+                              index (Section 4's per-row hash; about 20 bytes per entry of C).  The
+                              index pools of a context take at most 1/8 of the device, and only
+                              memory that stays free beyond a reserve (and at most half of what a
+                              budget leaves); without room for A's index the row path runs.
+                              0: never (applies stream the touched rows; the entry path's lost
+                              entries scan rows of A') */
 } dsg_tuning;
 dsg_status dsg_ctx_get_tuning(const dsg_ctx* ctx, dsg_tuning* t);
 /* t == NULL restores the defaults.  DSG_E_ARG for thresholds outside the

@@ -188,6 +188,7 @@ static void default_tuning(dsg_tuning* t) {
   t->batch_direct_log2 = 24;
   t->entry_fixed = 1e8;
   t->entry_per_term = 70.0;
+  t->row_index = 1;
 }
 
 // host-side check of a CSR: row_ptr monotone from 0, columns in range, no
@@ -400,6 +401,7 @@ extern "C" dsg_status dsg_ctx_set_tuning(dsg_ctx* ctx, const dsg_tuning* t) {
     return fail(ctx, DSG_E_ARG, "batch_direct_log2 outside [0, 62]");
   if (!(t->entry_fixed >= 0.0 && t->entry_fixed < 1e300) || !(t->entry_per_term >= 0.0 && t->entry_per_term < 1e300))
     return fail(ctx, DSG_E_ARG, "entry_fixed and entry_per_term must be finite and >= 0");
+  if (t->row_index != 0 && t->row_index != 1) return fail(ctx, DSG_E_ARG, "row_index must be 0 or 1");
   ctx->c.tuning = *t;
   return DSG_OK;
 }
@@ -805,6 +807,7 @@ extern "C" dsg_status dsg_prod_autotune(dsg_prod* ph, int32_t reps, dsg_tuning* 
       t.update_path = saved.update_path;
       t.entry_fixed = saved.entry_fixed;
       t.entry_per_term = saved.entry_per_term;
+      t.row_index = saved.row_index;
       c->tuning = t;
       prod_run(ph->p, 1, true);  // warm: sizes the pools and the arena for this setting
       std::vector<float> ms;

@@ -346,10 +346,12 @@ __device__ inline unsigned long long acc_comb(unsigned long long a, unsigned lon
 // position of column c in row r of A' (its table, or a scan of the row when
 // the index pool had no room for it)
 __device__ inline int32_t a_find(const LostArgs& L, int32_t r, int32_t c) {
-  // (the table's place is read before its stamp is checked: independent loads)
-  const int64_t to = L.X.off[r];
-  const uint32_t mask = (uint32_t)L.X.sz[r] - 1;
-  if (L.X.stamp[r] == L.X.gen) return ix_find(L.X.tab + to, mask, c);
+  if (L.X.tab) {  // A' may have no index (refused for room, or switched off)
+    // (the table's place is read before its stamp is checked: independent loads)
+    const int64_t to = L.X.off[r];
+    const uint32_t tn = (uint32_t)L.X.sz[r];
+    if (L.X.stamp[r] == L.X.gen) return ix_find(L.X.tab + to, tn, c);
+  }
   const int64_t o = L.A.off[r];
   const int32_t n = L.A.len[r];
   for (int32_t t = 0; t < n; ++t)
@@ -548,10 +550,9 @@ int32_t entry_update(DProd* p) {
   dsg_update_stats& st = p->stats;
   st = dsg_update_stats{};
   st.path = 1;
-  // column indexes of C (the apply of its updates looks entries up in
-  // them) and of A' (the lost entries' probes); built on first use
-  mat_index_enable(C);
-  mat_index_enable(A);
+  // column index of C: the apply of its updates looks entries up in it
+  // (A' got its own at eligibility); built on first use
+  if (c->tuning.row_index) mat_index_enable(C);
 
   // the counts of step 1 (count_terms), still in the second scratch
   Log L{A->log_key, A->log_old, A->log_new, A->log_code, p->entry_nU};
@@ -738,7 +739,13 @@ int32_t entry_update(DProd* p) {
 
 }  // namespace
 
-bool entry_eligible(const DProd* p) { return eligible(p); }
+bool entry_eligible(DProd* p) {
+  if (!eligible(p)) return false;
+  // the lost entries probe rows of A' through its column index: without
+  // one (no room for it) the row path runs instead; with the index switched
+  // off the probes scan the rows
+  return !p->ctx->tuning.row_index || mat_index_enable(p->A);
+}
 
 const int64_t* entry_count(DProd* p) { return count_terms(p); }
 

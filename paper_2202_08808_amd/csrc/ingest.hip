@@ -266,8 +266,8 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
   if (ix_valid(X, i)) {
     // the row's column index gives each update's slot
     const uint64_t* t = X.tab + X.off[i];
-    const uint32_t mask = (uint32_t)X.sz[i] - 1;
-    for (int32_t u = u0 + lane; u < u1; u += 64) U.slot[u] = ix_find(t, mask, (int32_t)(U.key[u] & cmask));
+    const uint32_t tn = (uint32_t)X.sz[i];
+    for (int32_t u = u0 + lane; u < u1; u += 64) U.slot[u] = ix_find(t, tn, (int32_t)(U.key[u] & cmask));
   } else {
   const bool in_lds = true;
   for (int32_t u = u0 + lane; u < u1; u += 64) {
@@ -385,7 +385,7 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
     const bool ixv = ix_valid(X, i);
     const bool ixk = ixv && ix_fits(X, i, nl - len);
     uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
-    const uint32_t ixm = ixk ? (uint32_t)X.sz[i] - 1 : 0u;
+    const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
     int32_t k = 0;
     for (int32_t base = u0; base < u1; base += 64) {
       const int32_t u = base + lane;
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
         const int64_t dst = dest + pos;
         m.col[dst] = (int32_t)(U.key[u] & cmask);
         store_raw<VSZ>(m.val, dst, U.fin[u]);
-        if (ixk) ix_put(ixt, ixm, (int32_t)(U.key[u] & cmask), pos);
+        if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), pos);
       }
       k += __popcll(ib);
     }
@@ -427,11 +427,11 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
     // it has room; a row moved to new space, or a full table, drops it
     const bool ixk = ixv && ncap == 0 && ix_fits(X, i, nl - len + n_del);
     uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
-    const uint32_t ixm = ixk ? (uint32_t)X.sz[i] - 1 : 0u;
+    const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
     if (ixk) {
       for (int32_t u = u0 + lane; u < u1; u += 64)
         if (U.code[u] == C_DEL) {
-          const int32_t h = ix_slot(ixt, ixm, (int32_t)(U.key[u] & cmask));
+          const int32_t h = ix_slot(ixt, ixn, (int32_t)(U.key[u] & cmask));
           if (h >= 0) ixt[h] = IX_TOMB;
         }
     }
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
         m.col[off + dst] = cm;
         store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
         if (ixk) {
-          const int32_t h = ix_slot(ixt, ixm, cm);
+          const int32_t h = ix_slot(ixt, ixn, cm);
           if (h >= 0) ixt[h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
         }
       }
@@ -491,7 +491,7 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
           const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
           m.col[off + dst] = (int32_t)(U.key[u] & cmask);
           store_raw<VSZ>(m.val, off + dst, U.fin[u]);
-          if (ixk) ix_put(ixt, ixm, (int32_t)(U.key[u] & cmask), dst);
+          if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), dst);
         }
         k += __popcll(ib);
       }
@@ -847,7 +847,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
       ixk = ixv && ix_fits(X, i, nl - len);
       if (!flat) {
         uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
-        const uint32_t ixm = ixk ? (uint32_t)X.sz[i] - 1 : 0u;
+        const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
         for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG)
           if (U.code[u] == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
         // inserts after the row's entries, in update order
@@ -861,7 +861,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
             const int32_t pos = len + k + q;
             m.col[dest + pos] = (int32_t)(U.key[u] & cmask);
             store_raw<VSZ>(m.val, dest + pos, U.fin[u]);
-            if (ixk) ix_put(ixt, ixm, (int32_t)(U.key[u] & cmask), pos);
+            if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), pos);
           }
           k += tot;
         }
@@ -886,7 +886,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
       if (ncap == 0) {
         ixk = ixv && ix_fits(X, i, ni);
         uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
-        const uint32_t ixm = ixk ? (uint32_t)X.sz[i] - 1 : 0u;
+        const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
         // holes: deleted slots below the new length (their columns leave
         // tombstones in the index)
         int32_t H = 0;
@@ -894,7 +894,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
           const int32_t u = base + tid;
           const bool del = u < u1 && U.code[u] == C_DEL;
           if (del && ixk) {
-            const int32_t h = ix_slot(ixt, ixm, (int32_t)(U.key[u] & cmask));
+            const int32_t h = ix_slot(ixt, ixn, (int32_t)(U.key[u] & cmask));
             if (h >= 0) ixt[h] = IX_TOMB;
           }
           const bool hole = del && U.slot[u] < nl;
@@ -921,7 +921,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
           m.col[off + dst] = cm;
           store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
           if (ixk) {
-            const int32_t h = ix_slot(ixt, ixm, cm);
+            const int32_t h = ix_slot(ixt, ixn, cm);
             if (h >= 0) ixt[h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
           }
         }
@@ -937,7 +937,7 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
             const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
             m.col[off + dst] = (int32_t)(U.key[u] & cmask);
             store_raw<VSZ>(m.val, off + dst, U.fin[u]);
-            if (ixk) ix_put(ixt, ixm, (int32_t)(U.key[u] & cmask), dst);
+            if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), dst);
           }
           k += tot;
         }
@@ -1052,7 +1052,7 @@ __global__ __launch_bounds__(256) void k_delete_flat(DMat m, const int64_t* d_nU
         const int32_t c = (int32_t)(U.key[u] & cmask);
         m.col[off + sl] = -1;
         if (ixk) {
-          const int32_t h = ix_slot(X.tab + X.off[i], (uint32_t)X.sz[i] - 1, c);
+          const int32_t h = ix_slot(X.tab + X.off[i], (uint32_t)X.sz[i], c);
           if (h >= 0) X.tab[X.off[i] + h] = IX_TOMB;
         }
         hole = sl < nl;
@@ -1085,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_delete_flat(DMat m, const int64_t* d_nU
         m.col[off + dst] = cm;
         store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
         if (ixk) {
-          const int32_t h = ix_slot(X.tab + X.off[i], (uint32_t)X.sz[i] - 1, cm);
+          const int32_t h = ix_slot(X.tab + X.off[i], (uint32_t)X.sz[i], cm);
           if (h >= 0) X.tab[X.off[i] + h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
         }
       }
@@ -1112,8 +1112,13 @@ __global__ __launch_bounds__(256) void k_commit_flat(DMat m, const int64_t* d_nU
     uint8_t code = C_NOP;
     if (u < nU) {
       r = U.ur[u];
-      if (U.pdel[r] == (PL_HEAVY | PL_FLAT) && U.pchg[r]) code = U.code[u];
-      else r = -1;
+      // (a row that had to move but found no room is left alone: the
+      // commit reported the error)
+      if (U.pdel[r] == (PL_HEAVY | PL_FLAT) && U.pchg[r] &&
+          !(U.pcap[r] && m.row_cap[U.urow[r]] != U.pcap[r]))
+        code = U.code[u];
+      else
+        r = -1;
     }
     const bool ins = code == C_INS;
     const int32_t r0 = __shfl(r, 0, 64);
@@ -1133,7 +1138,7 @@ __global__ __launch_bounds__(256) void k_commit_flat(DMat m, const int64_t* d_nU
       const int32_t c = (int32_t)(U.key[u] & cmask);
       m.col[off + pos] = c;
       store_raw<VSZ>(m.val, off + pos, U.fin[u]);
-      if (U.pix[r]) ix_put(X.tab + X.off[i], (uint32_t)X.sz[i] - 1, c, pos);
+      if (U.pix[r]) ix_put(X.tab + X.off[i], (uint32_t)X.sz[i], c, pos);
     }
     if (dkey && emits_delta(code)) {
       if (u >= dcap) {

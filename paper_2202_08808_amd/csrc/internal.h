@@ -115,6 +115,7 @@ struct Ctx {
   bool own_stream = false;
   size_t budget = 0;
   size_t held = 0;
+  size_t ix_held = 0;  // bytes of the per-row column index pools of all matrices
   dsg_allocator allocator{};   // the caller's allocator (alloc == nullptr: hipMalloc / hipFree)
   std::mutex alloc_mu;  // ctx_alloc / ctx_free may run on a server's threads
   std::string last_error = "";
@@ -375,7 +376,7 @@ int32_t prod_run(DProd* p, int mode, bool report_affected);
 // last apply changed (kept in the context's second scratch); entry_finish,
 // called next with nothing else on that scratch in between, updates C and
 // returns the reported-row count.
-bool entry_eligible(const DProd* p);
+bool entry_eligible(DProd* p);
 // Queues the count; its total lands in *entry_count's result (device) and is
 // read back by the caller's next synchronisation into p->entry_nterm.
 const int64_t* entry_count(DProd* p);

@@ -85,19 +85,20 @@ __global__ void k_sum_len(int32_t n, const int32_t* len, unsigned long long* out
   if ((threadIdx.x & 63) == 0 && v) atomicAdd(out, v);
 }
 
-// export: one wavefront per row writes (row,col) keys and compact values
+// export of rows [r0, r1): one wavefront per row writes (row - r0, col) keys
+// and compact values at the row's place relative to the first row's
 template <int VSZ>
-__global__ __launch_bounds__(256) void k_export_keys(int32_t n, const int64_t* off, const int32_t* len,
+__global__ __launch_bounds__(256) void k_export_keys(int32_t r0, int32_t r1, const int64_t* off, const int32_t* len,
                                                      const int32_t* col, const char* val,
                                                      const int64_t* rp, int cbits, uint64_t* keys,
                                                      uint32_t* pos, char* vtmp) {
-  int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  int64_t i = r0 + (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   int lane = threadIdx.x & 63;
-  if (i >= n) return;
-  int64_t o = off[i], d = rp[i];
+  if (i >= r1) return;
+  int64_t o = off[i], d = rp[i] - rp[r0];
   int32_t l = len[i];
   for (int32_t t = lane; t < l; t += 64) {
-    keys[d + t] = ((uint64_t)i << cbits) | (uint64_t)(uint32_t)col[o + t];
+    keys[d + t] = ((uint64_t)(i - r0) << cbits) | (uint64_t)(uint32_t)col[o + t];
     pos[d + t] = (uint32_t)(d + t);
     if constexpr (VSZ == 8) ((uint64_t*)vtmp)[d + t] = ((const uint64_t*)val)[o + t];
     if constexpr (VSZ == 4) ((uint32_t*)vtmp)[d + t] = ((const uint32_t*)val)[o + t];
@@ -329,37 +330,55 @@ void mat_export_device(DMat* m, int64_t* d_rp, int32_t* d_col, void* d_val, void
   }
   int64_t nnz = read_i64(c, d_rp + n);
   if (!d_col || nnz == 0) return;
+  // rows in chunks of at most EXPORT_CHUNK entries (a longer row is a chunk
+  // of its own), each sorted by (row, column) on its own: the scratch stays
+  // bounded whatever the matrix's size
+  constexpr int64_t EXPORT_CHUNK = int64_t(1) << 25;
+  std::vector<int64_t> hrp((size_t)n + 1);
+  DSG_HIP(hipMemcpyAsync(hrp.data(), d_rp, ((size_t)n + 1) * 8, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  int64_t most = 0;
+  for (int32_t i = 0; i < n; ++i) most = std::max<int64_t>(most, hrp[i + 1] - hrp[i]);
+  const int64_t cap = std::max<int64_t>(std::min<int64_t>(nnz, EXPORT_CHUNK), most);
   int cbits = bits_for(m->ncols);
-  int rbits = bits_for(n);
   size_t vs = (size_t)(m->vsz ? m->vsz : 4);
-  size_t need = Carve::need({(size_t)nnz * 8, (size_t)nnz * 4, (size_t)nnz * vs, radix_scratch_bytes(nnz)});
+  size_t need = Carve::need({(size_t)cap * 8, (size_t)cap * 4, (size_t)cap * vs, radix_scratch_bytes(cap)});
   Carve cv(ctx_scratch(c, need), need);
-  uint64_t* keys = cv.take<uint64_t>(nnz);
-  uint32_t* pos = cv.take<uint32_t>(nnz);
-  char* vtmp = cv.take<char>((size_t)nnz * vs);
-  void* rs = cv.take<char>(radix_scratch_bytes(nnz));
-  unsigned nb = blocks_for((int64_t)n * 64, 256);
-  if (m->vsz == 8)
-    hipLaunchKernelGGL(k_export_keys<8>, dim3(nb), dim3(256), 0, s, n, m->row_off, m->row_len, m->col,
-                       (const char*)m->val, d_rp, cbits, keys, pos, vtmp);
-  else if (m->vsz == 4)
-    hipLaunchKernelGGL(k_export_keys<4>, dim3(nb), dim3(256), 0, s, n, m->row_off, m->row_len, m->col,
-                       (const char*)m->val, d_rp, cbits, keys, pos, vtmp);
-  else
-    hipLaunchKernelGGL(k_export_keys<0>, dim3(nb), dim3(256), 0, s, n, m->row_off, m->row_len, m->col,
-                       (const char*)m->val, d_rp, cbits, keys, pos, vtmp);
-  radix_sort_pairs(keys, pos, nnz, cbits + rbits, rs, s);
+  uint64_t* keys = cv.take<uint64_t>(cap);
+  uint32_t* pos = cv.take<uint32_t>(cap);
+  char* vtmp = cv.take<char>((size_t)cap * vs);
+  void* rs = cv.take<char>(radix_scratch_bytes(cap));
   uint64_t cmask = cbits >= 64 ? ~0ull : ((1ull << cbits) - 1);
-  unsigned gb = blocks_for(nnz, 256);
-  if (m->vsz == 8)
-    hipLaunchKernelGGL(k_export_gather<8>, dim3(gb), dim3(256), 0, s, nnz, keys, pos, vtmp, cmask, d_col,
-                       (char*)d_val);
-  else if (m->vsz == 4)
-    hipLaunchKernelGGL(k_export_gather<4>, dim3(gb), dim3(256), 0, s, nnz, keys, pos, vtmp, cmask, d_col,
-                       (char*)d_val);
-  else
-    hipLaunchKernelGGL(k_export_gather<0>, dim3(gb), dim3(256), 0, s, nnz, keys, pos, vtmp, cmask, d_col,
-                       (char*)d_val);
+  for (int32_t r0 = 0; r0 < n;) {
+    int32_t r1 = r0 + 1;
+    while (r1 < n && hrp[r1 + 1] - hrp[r0] <= cap) ++r1;
+    const int64_t base = hrp[r0], e = hrp[r1] - base;
+    if (e > 0) {
+      unsigned nb = blocks_for((int64_t)(r1 - r0) * 64, 256);
+      if (m->vsz == 8)
+        hipLaunchKernelGGL(k_export_keys<8>, dim3(nb), dim3(256), 0, s, r0, r1, m->row_off, m->row_len, m->col,
+                           (const char*)m->val, d_rp, cbits, keys, pos, vtmp);
+      else if (m->vsz == 4)
+        hipLaunchKernelGGL(k_export_keys<4>, dim3(nb), dim3(256), 0, s, r0, r1, m->row_off, m->row_len, m->col,
+                           (const char*)m->val, d_rp, cbits, keys, pos, vtmp);
+      else
+        hipLaunchKernelGGL(k_export_keys<0>, dim3(nb), dim3(256), 0, s, r0, r1, m->row_off, m->row_len, m->col,
+                           (const char*)m->val, d_rp, cbits, keys, pos, vtmp);
+      radix_sort_pairs(keys, pos, e, cbits + bits_for(r1 - r0), rs, s);
+      unsigned gb = blocks_for(e, 256);
+      char* ov = d_val ? (char*)d_val + (size_t)base * vs : nullptr;
+      if (m->vsz == 8)
+        hipLaunchKernelGGL(k_export_gather<8>, dim3(gb), dim3(256), 0, s, e, keys, pos, vtmp, cmask, d_col + base,
+                           ov);
+      else if (m->vsz == 4)
+        hipLaunchKernelGGL(k_export_gather<4>, dim3(gb), dim3(256), 0, s, e, keys, pos, vtmp, cmask, d_col + base,
+                           ov);
+      else
+        hipLaunchKernelGGL(k_export_gather<0>, dim3(gb), dim3(256), 0, s, e, keys, pos, vtmp, cmask, d_col + base,
+                           ov);
+    }
+    r0 = r1;
+  }
   DSG_HIP(hipGetLastError());
 }
 

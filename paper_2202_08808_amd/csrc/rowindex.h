@@ -3,11 +3,11 @@
 // Section 4 gives every row of the dynamic structure a hash table from
 // column to position, so that an update finds its entry in constant time.
 // Rows here are slot ranges in no column order; the index adds, per row, an
-// open-addressing table (linear probing, a power-of-two size at least twice
-// the row's length when built) whose slots hold (position in the row << 32 |
-// column), all ones when empty; a deleted entry leaves a tombstone (column
-// field 0xfffffffe) that lookups pass over.  Tables live in one pool per
-// matrix and are taken from its top.
+// open-addressing table (linear probing, 2 * length + 16 slots when built,
+// a column's first slot by multiplying its hash into the table size) whose
+// slots hold (position in the row << 32 | column), all ones when empty; a
+// deleted entry leaves a tombstone (column field 0xfffffffe) that lookups
+// pass over.  Tables live in one pool per matrix and are taken from its top.
 //
 // A row's table is usable only while stamp[i] == gen.  The apply keeps it:
 // overwrites in place change nothing, inserts are recorded, deletions leave
@@ -29,7 +29,7 @@ constexpr uint64_t IX_TOMB = ~0ull - 1;
 struct RowIx {
   uint64_t* tab = nullptr;  // null: the matrix has no index
   int64_t* off = nullptr;   // per row: first slot of its table
-  int32_t* sz = nullptr;    // per row: table size (power of two)
+  int32_t* sz = nullptr;    // per row: table size
   int32_t* used = nullptr;  // per row: slots taken (entries and tombstones)
   uint32_t* stamp = nullptr;
   unsigned long long* top = nullptr;  // device: first free slot of the pool
@@ -49,38 +49,44 @@ __device__ inline uint32_t ix_hash(int32_t c) {
 
 __device__ inline bool ix_valid(const RowIx& X, int32_t i) { return X.tab && X.stamp[i] == X.gen; }
 
-// position of column c in a row whose table is t (size mask + 1), or -1
-__device__ inline int32_t ix_find(const uint64_t* t, uint32_t mask, int32_t c) {
-  uint32_t h = ix_hash(c) & mask;
+// first slot of column c in a table of n slots, and the slot after h
+__device__ inline uint32_t ix_home(int32_t c, uint32_t n) {
+  return (uint32_t)(((uint64_t)ix_hash(c) * n) >> 32);
+}
+__device__ inline uint32_t ix_next(uint32_t h, uint32_t n) { return h + 1 == n ? 0u : h + 1; }
+
+// position of column c in a row whose table is t (n slots), or -1
+__device__ inline int32_t ix_find(const uint64_t* t, uint32_t n, int32_t c) {
+  uint32_t h = ix_home(c, n);
   for (;;) {
     const uint64_t e = t[h];
     if ((uint32_t)e == (uint32_t)c) return (int32_t)(e >> 32);
     if (e == IX_EMPTY) return -1;
-    h = (h + 1) & mask;
+    h = ix_next(h, n);
   }
 }
 
 __device__ inline int32_t ix_lookup(const RowIx& X, int32_t i, int32_t c) {
-  return ix_find(X.tab + X.off[i], (uint32_t)X.sz[i] - 1, c);
+  return ix_find(X.tab + X.off[i], (uint32_t)X.sz[i], c);
 }
 
 // record (column c at position p); the column must not be in the table
-__device__ inline void ix_put(uint64_t* t, uint32_t mask, int32_t c, int32_t p) {
+__device__ inline void ix_put(uint64_t* t, uint32_t n, int32_t c, int32_t p) {
   const uint64_t v = ((uint64_t)(uint32_t)p << 32) | (uint64_t)(uint32_t)c;
-  uint32_t h = ix_hash(c) & mask;
+  uint32_t h = ix_home(c, n);
   while (atomicCAS((unsigned long long*)&t[h], (unsigned long long)IX_EMPTY, (unsigned long long)v) !=
          (unsigned long long)IX_EMPTY)
-    h = (h + 1) & mask;
+    h = ix_next(h, n);
 }
 
 // table slot holding column c, or -1
-__device__ inline int32_t ix_slot(const uint64_t* t, uint32_t mask, int32_t c) {
-  uint32_t h = ix_hash(c) & mask;
+__device__ inline int32_t ix_slot(const uint64_t* t, uint32_t n, int32_t c) {
+  uint32_t h = ix_home(c, n);
   for (;;) {
     const uint64_t e = t[h];
     if ((uint32_t)e == (uint32_t)c) return (int32_t)h;
     if (e == IX_EMPTY) return -1;
-    h = (h + 1) & mask;
+    h = ix_next(h, n);
   }
 }
 

@@ -18,11 +18,7 @@ unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per)
 constexpr int32_t IX_LIGHT_MAX = 2048;  // longer rows are built by a whole workgroup
 constexpr int IX_HEAVY_WG = 512;
 
-__device__ inline int32_t table_size(int32_t len) {
-  int32_t s = 16;
-  while (s < 2 * len) s <<= 1;
-  return s;
-}
+__device__ inline int32_t table_size(int32_t len) { return 2 * len + 16; }
 
 // one wavefront per listed row of at most IX_LIGHT_MAX entries without a
 // usable table (rows taken in turn): take a table from the pool top, clear
@@ -54,7 +50,7 @@ __global__ __launch_bounds__(256) void k_ix_build_light(const int64_t* row_off, 
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     const int64_t off = row_off[i];
-    for (int32_t p = lane; p < len; p += 64) ix_put(t, (uint32_t)sz - 1, col[off + p], p);
+    for (int32_t p = lane; p < len; p += 64) ix_put(t, (uint32_t)sz, col[off + p], p);
     __threadfence_block();
     __builtin_amdgcn_wave_barrier();
     if (lane == 0) {
@@ -114,7 +110,7 @@ __global__ __launch_bounds__(IX_HEAVY_WG) void k_ix_build_heavy(const int64_t* r
     __threadfence_block();
     __syncthreads();
     const int64_t off = row_off[i];
-    for (int32_t p = tid; p < len; p += IX_HEAVY_WG) ix_put(t, (uint32_t)sz - 1, col[off + p], p);
+    for (int32_t p = tid; p < len; p += IX_HEAVY_WG) ix_put(t, (uint32_t)sz, col[off + p], p);
     __threadfence_block();
     __syncthreads();
     if (tid == 0) {
@@ -145,6 +141,7 @@ void free_index(DMat* m) {
   Ctx* c = m->ctx;
   const size_t n = (size_t)std::max<int32_t>(m->nrows, 1);
   ctx_free(c, m->ix_tab, (size_t)m->ix_cap * 8);
+  c->ix_held -= std::min(c->ix_held, (size_t)m->ix_cap * 8);
   ctx_free(c, m->ix_off, n * 8);
   ctx_free(c, m->ix_sz, n * 4);
   ctx_free(c, m->ix_used, n * 4);
@@ -177,8 +174,28 @@ RowIx mat_index_view(const DMat* m) {
 
 namespace {
 
+// Whether an index pool of `bytes` (replacing one of `old` bytes) may be
+// taken: under a memory budget at most half of what is left; the pools of a
+// context together at most 1/8 of the device; and of the device memory free
+// now, a small pool (up to 1/256 of the device) at most half, a larger one
+// at most a quarter of what lies beyond a reserve of a quarter of the
+// device.  Indexes are an accelerator: they never crowd out the matrices,
+// workspaces and exports.
+bool room_for(Ctx* c, size_t bytes, size_t old) {
+  if (c->budget && c->held - std::min(c->held, old) + 2 * bytes > c->budget) return false;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (c->ix_held - std::min(c->ix_held, old) + bytes > total_b / 8) return false;
+  const size_t avail = free_b + old, reserve = total_b / 4;
+  if (bytes <= total_b / 256) return bytes <= avail / 2;
+  return avail > reserve && bytes <= (avail - reserve) / 4;
+}
+
 // Every row's table at once: sizes, offsets by a scan (no contended
-// counter), a pool of 3/2 of their sum (grown if needed), then every row
+// counter), a pool of 5/4 of their sum (grown if needed), then every row
 // built.  Returns false when the pool cannot be had.
 bool build_all(DMat* m) {
   Ctx* c = m->ctx;
@@ -204,13 +221,12 @@ bool build_all(DMat* m) {
   }
   ctx_free(c, scr, sb);
   // room for rebuilt tables until the pool is rebuilt as a whole
-  const int64_t want = total + total / 2 + 65536;
-  if (m->ix_cap < total + total / 4) {
+  const int64_t want = total + total / 4 + 65536;
+  if (m->ix_cap < total + total / 8) {
     const size_t bytes = (size_t)want * 8;
-    // under a memory budget the pool takes at most half of what is left
-    const size_t old = (size_t)m->ix_cap * 8;
-    if (c->budget && c->held - std::min(c->held, old) + 2 * bytes > c->budget) return false;
+    if (!room_for(c, bytes, (size_t)m->ix_cap * 8)) return false;
     ctx_free(c, m->ix_tab, (size_t)m->ix_cap * 8);
+    c->ix_held -= std::min(c->ix_held, (size_t)m->ix_cap * 8);
     m->ix_tab = nullptr;
     m->ix_cap = 0;
     try {
@@ -220,6 +236,7 @@ bool build_all(DMat* m) {
       return false;
     }
     m->ix_cap = want;
+    c->ix_held += bytes;
   }
   const RowIx X = mat_index_view(m);
   const unsigned nl = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for((int64_t)n * 64, 256),
@@ -242,9 +259,8 @@ bool mat_index_enable(DMat* m) {
   if (m->ix_refused) return false;
   Ctx* c = m->ctx;
   const size_t n = (size_t)std::max<int32_t>(m->nrows, 1);
-  // tables take about three times the entries (under a budget the index
-  // takes at most half of what is left)
-  if (c->budget && (c->held + 2 * ((size_t)(5 * m->h_top_ub) * 8 + n * 20) > c->budget)) {
+  // tables take about twice the entries, and the pool a quarter more
+  if (!room_for(c, (size_t)(2 * m->h_top_ub + 16 * (int64_t)n) * 10 + n * 20, 0)) {
     m->ix_refused = true;
     return false;
   }

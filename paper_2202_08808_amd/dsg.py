@@ -44,7 +44,8 @@ class Rows(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("group_ub", ctypes.c_int32 * 8), ("dense_max_passes", ctypes.c_int32),
                 ("force_bin", ctypes.c_int32), ("update_path", ctypes.c_int32), ("batch_direct_log2", ctypes.c_int32),
-                ("entry_fixed", ctypes.c_double), ("entry_per_term", ctypes.c_double)]
+                ("entry_fixed", ctypes.c_double), ("entry_per_term", ctypes.c_double),
+                ("row_index", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):

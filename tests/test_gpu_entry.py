@@ -37,13 +37,17 @@ def row_path(ctx, on):
     ctx.set_tuning(t)
 
 
-def run(ctx, sr, A, batches, use_row_path=False, expect_entry=True, auto=False):
+def run(ctx, sr, A, batches, use_row_path=False, expect_entry=True, auto=False, row_index=1):
     """Apply each batch then update; check C and the reported rows against
-    the oracle after every step (auto: the library chooses the path)."""
+    the oracle after every step (auto: the library chooses the path;
+    row_index 0: no per-row column index on C and A)."""
     if auto:
         ctx.set_tuning(None)
     else:
         row_path(ctx, use_row_path)
+    t = ctx.get_tuning()
+    t.row_index = row_index
+    ctx.set_tuning(t)
     m = dsg.Matrix.from_csr(ctx, A, sr)
     P = dsg.Product(ctx, m, m)
     a = oracle.Csr.of(A)
@@ -76,6 +80,29 @@ def test_entry_matches_oracle(ctx, sr):
     st = run(ctx, sr, A, bs)
     assert sum(s["lost"] for s in st) > 0  # deletions hit stored minima / contributors
     run(ctx, sr, A, bs, use_row_path=True)
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_entry_without_row_index(ctx, sr):
+    """Regression: the entry path on C and A without their per-row column
+    indexes (as when there is no room for them): the applies stream the
+    touched rows and the lost entries scan rows of A'.  R-MAT s12 with rows
+    over 2048 entries in C, batches up to 3000 updates, against the oracle."""
+    say(f"entry path without row index {SR_ID[sr]}")
+    hi = 9 if sr == I.PLUS_TIMES_I64 else 100
+    A = I.rmat_csr(12, 16, sr, stream=811, lo=1, hi=hi)
+    bs = I.disjoint_batches(A, sr, [10, 300, 3000], stream=812, value_lo=1, value_hi=hi)
+    st = run(ctx, sr, A, bs, row_index=0)
+    assert sum(s["lost"] for s in st) > 0
+
+
+def test_row_index_switch_is_checked(ctx):
+    t = ctx.get_tuning()
+    assert t.row_index == 1
+    t.row_index = 2
+    with pytest.raises(dsg.DsgError):
+        ctx.set_tuning(t)
+    ctx.set_tuning(None)
 
 
 @pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
