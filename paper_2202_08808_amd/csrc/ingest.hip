@@ -257,70 +257,70 @@ __global__ __launch_bounds__(256) void k_plan(DMat m, const int64_t* d_nR, uint6
   const int64_t nR = *d_nR;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < nR; r += nw) {
-  const int32_t i = U.urow[r];
-  const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
-  const int32_t nu = u1 - u0;
-  const int64_t off = m.row_off[i];
-  const int32_t len = m.row_len[i], cap = m.row_cap[i];
-  if (nu > PLAN_LDS || len > HEAVY_LEN) continue;  // k_plan_heavy takes this row
-  if (ix_valid(X, i)) {
-    // the row's column index gives each update's slot
-    const uint64_t* t = X.tab + X.off[i];
-    const uint32_t tn = (uint32_t)X.sz[i];
-    for (int32_t u = u0 + lane; u < u1; u += 64) U.slot[u] = ix_find(t, tn, (int32_t)(U.key[u] & cmask));
-  } else {
-  const bool in_lds = true;
-  for (int32_t u = u0 + lane; u < u1; u += 64) {
-    U.slot[u] = -1;
-    if (in_lds) lk[u - u0] = (int32_t)(U.key[u] & cmask);
-  }
-  __threadfence_block();
-  __builtin_amdgcn_wave_barrier();
-  // stream the row once (PU loads in flight per lane) and find each slot's update
-  constexpr int PU = 8;
-  for (int32_t s0 = lane; s0 < len; s0 += 64 * PU) {
-    int32_t cc[PU];
-#pragma unroll
-    for (int v = 0; v < PU; ++v) cc[v] = s0 + v * 64 < len ? m.col[off + s0 + v * 64] : -1;
-#pragma unroll
-    for (int v = 0; v < PU; ++v) {
-      if (cc[v] < 0) continue;
-      int32_t u;
-      if (in_lds) {
-        int32_t lo = 0, hi = nu;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if (lk[mid] < cc[v]) lo = mid + 1;
-          else hi = mid;
-        }
-        u = (lo < nu && lk[lo] == cc[v]) ? u0 + lo : -1;
-      } else {
-        u = find_update(U.key, u0, u1, cmask, cc[v]);
+    const int32_t i = U.urow[r];
+    const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+    const int32_t nu = u1 - u0;
+    const int64_t off = m.row_off[i];
+    const int32_t len = m.row_len[i], cap = m.row_cap[i];
+    if (nu > PLAN_LDS || len > HEAVY_LEN) continue;  // k_plan_heavy takes this row
+    if (ix_valid(X, i)) {
+      // the row's column index gives each update's slot
+      const uint64_t* t = X.tab + X.off[i];
+      const uint32_t tn = (uint32_t)X.sz[i];
+      for (int32_t u = u0 + lane; u < u1; u += 64) U.slot[u] = ix_find(t, tn, (int32_t)(U.key[u] & cmask));
+    } else {
+      const bool in_lds = true;
+      for (int32_t u = u0 + lane; u < u1; u += 64) {
+        U.slot[u] = -1;
+        if (in_lds) lk[u - u0] = (int32_t)(U.key[u] & cmask);
       }
-      if (u >= 0) U.slot[u] = s0 + v * 64;
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      // stream the row once (PU loads in flight per lane) and find each slot's update
+      constexpr int PU = 8;
+      for (int32_t s0 = lane; s0 < len; s0 += 64 * PU) {
+        int32_t cc[PU];
+#pragma unroll
+        for (int v = 0; v < PU; ++v) cc[v] = s0 + v * 64 < len ? m.col[off + s0 + v * 64] : -1;
+#pragma unroll
+        for (int v = 0; v < PU; ++v) {
+          if (cc[v] < 0) continue;
+          int32_t u;
+          if (in_lds) {
+            int32_t lo = 0, hi = nu;
+            while (lo < hi) {
+              const int32_t mid = (lo + hi) >> 1;
+              if (lk[mid] < cc[v]) lo = mid + 1;
+              else hi = mid;
+            }
+            u = (lo < nu && lk[lo] == cc[v]) ? u0 + lo : -1;
+          } else {
+            u = find_update(U.key, u0, u1, cmask, cc[v]);
+          }
+          if (u >= 0) U.slot[u] = s0 + v * 64;
+        }
+      }
     }
-  }
-  }
-  __threadfence_block();
-  __builtin_amdgcn_wave_barrier();
-  int32_t n_del = 0, n_ins = 0, n_ovr = 0;
-  for (int32_t base = u0; base < u1; base += 64) {
-    const int32_t u = base + lane;
-    const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u) : C_NOP;
-    n_del += __popcll(__ballot(code == C_DEL));
-    n_ins += __popcll(__ballot(code == C_INS));
-    n_ovr += __popcll(__ballot(code == C_OVR));
-  }
-  if (lane == 0) {
-    int32_t nl = len - n_del + n_ins;
-    bool chg = (n_del + n_ins + n_ovr) > 0;
-    bool reloc = nl > cap;
-    U.plen[r] = nl;
-    U.pchg[r] = chg ? 1 : 0;
-    U.pdel[r] = n_del > 0 ? PL_DEL : 0;
-    U.pcap[r] = reloc ? slack_cap(nl) : 0;
-    if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
-  }
+    __threadfence_block();
+    __builtin_amdgcn_wave_barrier();
+    int32_t n_del = 0, n_ins = 0, n_ovr = 0;
+    for (int32_t base = u0; base < u1; base += 64) {
+      const int32_t u = base + lane;
+      const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u) : C_NOP;
+      n_del += __popcll(__ballot(code == C_DEL));
+      n_ins += __popcll(__ballot(code == C_INS));
+      n_ovr += __popcll(__ballot(code == C_OVR));
+    }
+    if (lane == 0) {
+      int32_t nl = len - n_del + n_ins;
+      bool chg = (n_del + n_ins + n_ovr) > 0;
+      bool reloc = nl > cap;
+      U.plen[r] = nl;
+      U.pchg[r] = chg ? 1 : 0;
+      U.pdel[r] = n_del > 0 ? PL_DEL : 0;
+      U.pcap[r] = reloc ? slack_cap(nl) : 0;
+      if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
+    }
   }
 }
 
@@ -334,235 +334,235 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
   const int64_t nR = *d_nR;
   const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < nR; r += nw) {
-  if (!U.pchg[r]) continue;
-  const int32_t i = U.urow[r];
-  const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
-  const int64_t off = m.row_off[i];
-  const int32_t len = m.row_len[i];
-  const int32_t nl = U.plen[r];
-  const int32_t ncap = U.pcap[r];
-  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  // heavy rows (as the plan recorded them: many updates or a long row)
-  // belong to k_commit_heavy, which runs after this kernel.  (The split goes
-  // by the plan's flags: a row's length changes here.)
-  if (U.pdel[r] & PL_HEAVY) continue;
-  const bool nodel = !(U.pdel[r] & PL_DEL);
-  if (nodel) {
-    // ---- nothing deleted: the entries keep their order (moved as a block
-    // when the row outgrows its space), overwrites go to the planned slots,
-    // inserts after the row's entries ----
-    int64_t dest = off;
-    if (ncap) {
-      unsigned long long no = 0;
-      if (lane == 0) no = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
-      no = __shfl(no, 0, 64);
-      if ((int64_t)no + ncap > m.pool_cap) {
-        if (lane == 0) atomicOr(err, 1);
-        continue;
-      }
-      dest = (int64_t)no;
-      for (int32_t s0 = lane; s0 < len; s0 += 256) {
-        int32_t cc[4];
-        uint64_t vv[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int32_t t = s0 + v * 64;
-          cc[v] = t < len ? m.col[off + t] : 0;
-          vv[v] = t < len ? load_raw<VSZ>(m.val, off + t) : 0;
+    if (!U.pchg[r]) continue;
+    const int32_t i = U.urow[r];
+    const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+    const int64_t off = m.row_off[i];
+    const int32_t len = m.row_len[i];
+    const int32_t nl = U.plen[r];
+    const int32_t ncap = U.pcap[r];
+    const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    // heavy rows (as the plan recorded them: many updates or a long row)
+    // belong to k_commit_heavy, which runs after this kernel.  (The split goes
+    // by the plan's flags: a row's length changes here.)
+    if (U.pdel[r] & PL_HEAVY) continue;
+    const bool nodel = !(U.pdel[r] & PL_DEL);
+    if (nodel) {
+      // ---- nothing deleted: the entries keep their order (moved as a block
+      // when the row outgrows its space), overwrites go to the planned slots,
+      // inserts after the row's entries ----
+      int64_t dest = off;
+      if (ncap) {
+        unsigned long long no = 0;
+        if (lane == 0) no = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
+        no = __shfl(no, 0, 64);
+        if ((int64_t)no + ncap > m.pool_cap) {
+          if (lane == 0) atomicOr(err, 1);
+          continue;
         }
+        dest = (int64_t)no;
+        for (int32_t s0 = lane; s0 < len; s0 += 256) {
+          int32_t cc[4];
+          uint64_t vv[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int32_t t = s0 + v * 64;
-          if (t < len) {
-            m.col[dest + t] = cc[v];
-            store_raw<VSZ>(m.val, dest + t, vv[v]);
+          for (int v = 0; v < 4; ++v) {
+            const int32_t t = s0 + v * 64;
+            cc[v] = t < len ? m.col[off + t] : 0;
+            vv[v] = t < len ? load_raw<VSZ>(m.val, off + t) : 0;
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int32_t t = s0 + v * 64;
+            if (t < len) {
+              m.col[dest + t] = cc[v];
+              store_raw<VSZ>(m.val, dest + t, vv[v]);
+            }
           }
         }
       }
-    }
-    // the row's column index keeps its positions; the inserts join it
-    // unless they would fill it past 3/4 (then it is dropped)
-    const bool ixv = ix_valid(X, i);
-    const bool ixk = ixv && ix_fits(X, i, nl - len);
-    uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
-    const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
-    int32_t k = 0;
-    for (int32_t base = u0; base < u1; base += 64) {
-      const int32_t u = base + lane;
-      const uint8_t code = u < u1 ? U.code[u] : C_NOP;
-      if (code == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
-      const bool ins = code == C_INS;
-      const uint64_t ib = __ballot(ins);
-      if (ins) {
-        const int32_t pos = len + k + __popcll(ib & lt);
-        const int64_t dst = dest + pos;
-        m.col[dst] = (int32_t)(U.key[u] & cmask);
-        store_raw<VSZ>(m.val, dst, U.fin[u]);
-        if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), pos);
-      }
-      k += __popcll(ib);
-    }
-    if (ncap && lane == 0) {
-      m.row_off[i] = dest;
-      m.row_cap[i] = ncap;
-    }
-    if (ixv && lane == 0) {
-      if (ixk) X.used[i] += nl - len;
-      else X.stamp[i] = 0;
-    }
-  } else {
-    // ---- the row loses entries: mark the deleted slots (column -1) and
-    // apply the overwrites where they stand ----
-    const bool ixv = ix_valid(X, i);
-    int32_t n_del = 0;
-    for (int32_t base = u0; base < u1; base += 64) {
-      const int32_t u = base + lane;
-      const uint8_t code = u < u1 ? U.code[u] : C_NOP;
-      if (code == C_DEL) m.col[off + U.slot[u]] = -1;
-      else if (code == C_OVR) store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
-      n_del += __popcll(__ballot(code == C_DEL));
-    }
-    // in place, the column index follows the entries (deleted ones leave
-    // tombstones, moved ones get their new slot, inserts are recorded) while
-    // it has room; a row moved to new space, or a full table, drops it
-    const bool ixk = ixv && ncap == 0 && ix_fits(X, i, nl - len + n_del);
-    uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
-    const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
-    if (ixk) {
-      for (int32_t u = u0 + lane; u < u1; u += 64)
-        if (U.code[u] == C_DEL) {
-          const int32_t h = ix_slot(ixt, ixn, (int32_t)(U.key[u] & cmask));
-          if (h >= 0) ixt[h] = IX_TOMB;
-        }
-    }
-    if (ixv && lane == 0) {
-      if (ixk) X.used[i] += nl - len + n_del;
-      else X.stamp[i] = 0;
-    }
-    __threadfence_block();
-    __builtin_amdgcn_wave_barrier();
-    if (ncap == 0) {
-      // in place: holes are the deleted slots below the new length, movers
-      // the entries left at or above it; inserts fill the remaining holes,
-      // then the space after the old length
-      int32_t H = 0;
-      for (int32_t base = u0; base < u1; base += 64) {
-        const int32_t u = base + lane;
-        const bool hole = u < u1 && U.code[u] == C_DEL && U.slot[u] < nl;
-        const uint64_t hb = __ballot(hole);
-        if (hole) U.holes[u0 + H + __popcll(hb & lt)] = U.slot[u];
-        H += __popcll(hb);
-      }
-      int32_t Mc = 0;
-      for (int32_t s0 = nl; s0 < len; s0 += 256) {  // 4 loads in flight per lane
-        int32_t cc[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int32_t sl = s0 + v * 64 + lane;
-          cc[v] = sl < len ? m.col[off + sl] : -1;
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const bool mover = cc[v] != -1;
-          const uint64_t mb = __ballot(mover);
-          if (mover) U.mv_src[u0 + Mc + __popcll(mb & lt)] = s0 + v * 64 + lane;
-          Mc += __popcll(mb);
-        }
-      }
-      __threadfence_block();
-      __builtin_amdgcn_wave_barrier();
-      for (int32_t q = lane; q < Mc; q += 64) {
-        const int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q];
-        const int32_t cm = m.col[off + src];
-        m.col[off + dst] = cm;
-        store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
-        if (ixk) {
-          const int32_t h = ix_slot(ixt, ixn, cm);
-          if (h >= 0) ixt[h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
-        }
-      }
+      // the row's column index keeps its positions; the inserts join it
+      // unless they would fill it past 3/4 (then it is dropped)
+      const bool ixv = ix_valid(X, i);
+      const bool ixk = ixv && ix_fits(X, i, nl - len);
+      uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
+      const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
       int32_t k = 0;
       for (int32_t base = u0; base < u1; base += 64) {
         const int32_t u = base + lane;
-        const bool ins = u < u1 && U.code[u] == C_INS;
+        const uint8_t code = u < u1 ? U.code[u] : C_NOP;
+        if (code == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
+        const bool ins = code == C_INS;
         const uint64_t ib = __ballot(ins);
         if (ins) {
-          const int32_t mm = Mc + k + __popcll(ib & lt);
-          const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
-          m.col[off + dst] = (int32_t)(U.key[u] & cmask);
-          store_raw<VSZ>(m.val, off + dst, U.fin[u]);
-          if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), dst);
+          const int32_t pos = len + k + __popcll(ib & lt);
+          const int64_t dst = dest + pos;
+          m.col[dst] = (int32_t)(U.key[u] & cmask);
+          store_raw<VSZ>(m.val, dst, U.fin[u]);
+          if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), pos);
         }
         k += __popcll(ib);
       }
-    } else {
-      // move the row to fresh space, dropping the marked slots
-      unsigned long long no = 0;
-      if (lane == 0) no = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
-      no = __shfl(no, 0, 64);
-      if ((int64_t)no + ncap > m.pool_cap) {
-        if (lane == 0) atomicOr(err, 1);
-        continue;
-      }
-      int32_t kept = 0;
-      for (int32_t base = 0; base < len; base += 256) {  // 4 loads in flight per lane
-        int32_t cc[4];
-        uint64_t vv[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int32_t sl = base + v * 64 + lane;
-          cc[v] = sl < len ? m.col[off + sl] : -1;
-          vv[v] = sl < len ? load_raw<VSZ>(m.val, off + sl) : 0;
-        }
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const bool keep = cc[v] != -1;
-          const uint64_t kb = __ballot(keep);
-          if (keep) {
-            const int64_t dst = (int64_t)no + kept + __popcll(kb & lt);
-            m.col[dst] = cc[v];
-            store_raw<VSZ>(m.val, dst, vv[v]);
-          }
-          kept += __popcll(kb);
-        }
-      }
-      for (int32_t base = u0; base < u1; base += 64) {
-        const int32_t u = base + lane;
-        const bool ins = u < u1 && U.code[u] == C_INS;
-        const uint64_t ib = __ballot(ins);
-        if (ins) {
-          const int64_t dst = (int64_t)no + kept + __popcll(ib & lt);
-          m.col[dst] = (int32_t)(U.key[u] & cmask);
-          store_raw<VSZ>(m.val, dst, U.fin[u]);
-        }
-        kept += __popcll(ib);
-      }
-      if (lane == 0) {
-        m.row_off[i] = (int64_t)no;
+      if (ncap && lane == 0) {
+        m.row_off[i] = dest;
         m.row_cap[i] = ncap;
       }
-    }
-  }
-  if (lane == 0) {
-    m.row_len[i] = nl;
-    m.row_epoch[i] = *d_epoch;
-  }
-  // changes for the transpose index at the update's own index: key
-  // (col << tbits) | row, with the value (k_delta_keys reads the codes)
-  if (dkey) {
-    for (int32_t u = u0 + lane; u < u1; u += 64) {
-      const uint8_t code = U.code[u];
-      if (!emits_delta(code)) continue;
-      if (u >= dcap) {  // an internal error, never written past the list
-        atomicOr(err, 4);
-        continue;
+      if (ixv && lane == 0) {
+        if (ixk) X.used[i] += nl - len;
+        else X.stamp[i] = 0;
       }
-      const uint64_t j = U.key[u] & cmask;
-      dkey[u] = (j << tbits) | (uint64_t)(uint32_t)i;
-      dop[u] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
-      store_raw<VSZ>(dval, u, U.fin[u]);
+    } else {
+      // ---- the row loses entries: mark the deleted slots (column -1) and
+      // apply the overwrites where they stand ----
+      const bool ixv = ix_valid(X, i);
+      int32_t n_del = 0;
+      for (int32_t base = u0; base < u1; base += 64) {
+        const int32_t u = base + lane;
+        const uint8_t code = u < u1 ? U.code[u] : C_NOP;
+        if (code == C_DEL) m.col[off + U.slot[u]] = -1;
+        else if (code == C_OVR) store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
+        n_del += __popcll(__ballot(code == C_DEL));
+      }
+      // in place, the column index follows the entries (deleted ones leave
+      // tombstones, moved ones get their new slot, inserts are recorded) while
+      // it has room; a row moved to new space, or a full table, drops it
+      const bool ixk = ixv && ncap == 0 && ix_fits(X, i, nl - len + n_del);
+      uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
+      const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
+      if (ixk) {
+        for (int32_t u = u0 + lane; u < u1; u += 64)
+          if (U.code[u] == C_DEL) {
+            const int32_t h = ix_slot(ixt, ixn, (int32_t)(U.key[u] & cmask));
+            if (h >= 0) ixt[h] = IX_TOMB;
+          }
+      }
+      if (ixv && lane == 0) {
+        if (ixk) X.used[i] += nl - len + n_del;
+        else X.stamp[i] = 0;
+      }
+      __threadfence_block();
+      __builtin_amdgcn_wave_barrier();
+      if (ncap == 0) {
+        // in place: holes are the deleted slots below the new length, movers
+        // the entries left at or above it; inserts fill the remaining holes,
+        // then the space after the old length
+        int32_t H = 0;
+        for (int32_t base = u0; base < u1; base += 64) {
+          const int32_t u = base + lane;
+          const bool hole = u < u1 && U.code[u] == C_DEL && U.slot[u] < nl;
+          const uint64_t hb = __ballot(hole);
+          if (hole) U.holes[u0 + H + __popcll(hb & lt)] = U.slot[u];
+          H += __popcll(hb);
+        }
+        int32_t Mc = 0;
+        for (int32_t s0 = nl; s0 < len; s0 += 256) {  // 4 loads in flight per lane
+          int32_t cc[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int32_t sl = s0 + v * 64 + lane;
+            cc[v] = sl < len ? m.col[off + sl] : -1;
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool mover = cc[v] != -1;
+            const uint64_t mb = __ballot(mover);
+            if (mover) U.mv_src[u0 + Mc + __popcll(mb & lt)] = s0 + v * 64 + lane;
+            Mc += __popcll(mb);
+          }
+        }
+        __threadfence_block();
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t q = lane; q < Mc; q += 64) {
+          const int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q];
+          const int32_t cm = m.col[off + src];
+          m.col[off + dst] = cm;
+          store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
+          if (ixk) {
+            const int32_t h = ix_slot(ixt, ixn, cm);
+            if (h >= 0) ixt[h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
+          }
+        }
+        int32_t k = 0;
+        for (int32_t base = u0; base < u1; base += 64) {
+          const int32_t u = base + lane;
+          const bool ins = u < u1 && U.code[u] == C_INS;
+          const uint64_t ib = __ballot(ins);
+          if (ins) {
+            const int32_t mm = Mc + k + __popcll(ib & lt);
+            const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
+            m.col[off + dst] = (int32_t)(U.key[u] & cmask);
+            store_raw<VSZ>(m.val, off + dst, U.fin[u]);
+            if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), dst);
+          }
+          k += __popcll(ib);
+        }
+      } else {
+        // move the row to fresh space, dropping the marked slots
+        unsigned long long no = 0;
+        if (lane == 0) no = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
+        no = __shfl(no, 0, 64);
+        if ((int64_t)no + ncap > m.pool_cap) {
+          if (lane == 0) atomicOr(err, 1);
+          continue;
+        }
+        int32_t kept = 0;
+        for (int32_t base = 0; base < len; base += 256) {  // 4 loads in flight per lane
+          int32_t cc[4];
+          uint64_t vv[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int32_t sl = base + v * 64 + lane;
+            cc[v] = sl < len ? m.col[off + sl] : -1;
+            vv[v] = sl < len ? load_raw<VSZ>(m.val, off + sl) : 0;
+          }
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const bool keep = cc[v] != -1;
+            const uint64_t kb = __ballot(keep);
+            if (keep) {
+              const int64_t dst = (int64_t)no + kept + __popcll(kb & lt);
+              m.col[dst] = cc[v];
+              store_raw<VSZ>(m.val, dst, vv[v]);
+            }
+            kept += __popcll(kb);
+          }
+        }
+        for (int32_t base = u0; base < u1; base += 64) {
+          const int32_t u = base + lane;
+          const bool ins = u < u1 && U.code[u] == C_INS;
+          const uint64_t ib = __ballot(ins);
+          if (ins) {
+            const int64_t dst = (int64_t)no + kept + __popcll(ib & lt);
+            m.col[dst] = (int32_t)(U.key[u] & cmask);
+            store_raw<VSZ>(m.val, dst, U.fin[u]);
+          }
+          kept += __popcll(ib);
+        }
+        if (lane == 0) {
+          m.row_off[i] = (int64_t)no;
+          m.row_cap[i] = ncap;
+        }
+      }
     }
-  }
+    if (lane == 0) {
+      m.row_len[i] = nl;
+      m.row_epoch[i] = *d_epoch;
+    }
+    // changes for the transpose index at the update's own index: key
+    // (col << tbits) | row, with the value (k_delta_keys reads the codes)
+    if (dkey) {
+      for (int32_t u = u0 + lane; u < u1; u += 64) {
+        const uint8_t code = U.code[u];
+        if (!emits_delta(code)) continue;
+        if (u >= dcap) {  // an internal error, never written past the list
+          atomicOr(err, 4);
+          continue;
+        }
+        const uint64_t j = U.key[u] & cmask;
+        dkey[u] = (j << tbits) | (uint64_t)(uint32_t)i;
+        dop[u] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
+        store_raw<VSZ>(dval, u, U.fin[u]);
+      }
+    }
   }
 }
 
@@ -647,109 +647,107 @@ __global__ __launch_bounds__(HEAVY_WG) void k_plan_heavy(DMat m, const int64_t* 
   const int64_t per = (nR + gridDim.x - 1) / gridDim.x;
   const int64_t rb = (int64_t)blockIdx.x * per, re = min(nR, rb + per);
   for (int64_t c0 = rb; c0 < re; c0 += HEAVY_WG) {
-  int32_t npick;
-  {
-    const int64_t rr = c0 + tid;
-    bool f = false;
-    if (rr < re) {
-      const int32_t nu = U.row_first[rr + 1] - U.row_first[rr];
-      f = nu > PLAN_LDS || m.row_len[U.urow[rr]] > HEAVY_LEN;
+    int32_t npick;
+    {
+      const int64_t rr = c0 + tid;
+      bool f = false;
+      if (rr < re) {
+        const int32_t nu = U.row_first[rr + 1] - U.row_first[rr];
+        f = nu > PLAN_LDS || m.row_len[U.urow[rr]] > HEAVY_LEN;
+      }
+      const int32_t q = block_flag_prefix<HEAVY_WG>(f, wc, npick);
+      if (f) picked[q] = (int32_t)rr;
+      __syncthreads();
     }
-    const int32_t q = block_flag_prefix<HEAVY_WG>(f, wc, npick);
-    if (f) picked[q] = (int32_t)rr;
-    __syncthreads();
-  }
-  for (int32_t pq = 0; pq < npick; ++pq) {
-    const int64_t r = picked[pq];
-    const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
-    const int32_t i = U.urow[r];
-    const int64_t off = m.row_off[i];
-    const int32_t len = m.row_len[i], cap = m.row_cap[i];
-    if (u1 - u0 <= PLAN_LDS && len <= HEAVY_LEN) continue;
-    if (ix_valid(X, i)) {
-      // (the same for every thread: no stamp changes during the plan)
-      // k_plan_flat planned its updates; the row's outcome from its counts
+    for (int32_t pq = 0; pq < npick; ++pq) {
+      const int64_t r = picked[pq];
+      const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+      const int32_t i = U.urow[r];
+      const int64_t off = m.row_off[i];
+      const int32_t len = m.row_len[i], cap = m.row_cap[i];
+      if (u1 - u0 <= PLAN_LDS && len <= HEAVY_LEN) continue;
+      if (ix_valid(X, i)) {
+        // (the same for every thread: no stamp changes during the plan)
+        // k_plan_flat planned its updates; the row's outcome from its counts
+        if (tid == 0) {
+          const int32_t nd = U.pcnt[4 * r], ni = U.pcnt[4 * r + 1], no = U.pcnt[4 * r + 2];
+          const int32_t nl = len - nd + ni;
+          const bool reloc = nl > cap;
+          U.plen[r] = nl;
+          U.pchg[r] = (nd + ni + no) > 0 ? 1 : 0;
+          U.pdel[r] = (nd > 0 ? PL_DEL : 0) | PL_HEAVY | PL_FLAT | (nd == u1 - u0 ? PL_PURE_DEL : 0);
+          U.pcap[r] = reloc ? slack_cap(nl) : 0;
+          if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
+        }
+        continue;
+      }
+      if (tid < 3) cnt[tid] = 0;
+      for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) U.slot[u] = -1;
+      for (int32_t c0 = u0; c0 < u1; c0 += HEAVY_SLOTS / 2) {
+        const int32_t c1 = min(u1, c0 + HEAVY_SLOTS / 2);
+        // a table of twice this pass's updates (load <= 1/2): a long row with
+        // few updates clears a few hundred slots, not all of them
+        int32_t S = 256;
+        while (S < 2 * (c1 - c0)) S <<= 1;
+        const uint32_t hm = (uint32_t)S - 1;
+        for (int x = tid; x < S; x += HEAVY_WG) hk[x] = -1;
+        __syncthreads();
+        for (int32_t u = c0 + tid; u < c1; u += HEAVY_WG) {
+          const int32_t col = (int32_t)(U.key[u] & cmask);
+          uint32_t h = hash_col(col) & hm;
+          while (atomicCAS(&hk[h], -1, col) != -1) h = (h + 1) & hm;
+          hu[h] = u;
+        }
+        __syncthreads();
+        constexpr int SU = 8;  // row loads in flight per lane
+        for (int32_t s0 = tid; s0 < len; s0 += SU * HEAVY_WG) {
+          int32_t cc[SU];
+#pragma unroll
+          for (int v = 0; v < SU; ++v) cc[v] = s0 + v * HEAVY_WG < len ? m.col[off + s0 + v * HEAVY_WG] : -1;
+#pragma unroll
+          for (int v = 0; v < SU; ++v) {
+            if (cc[v] < 0) continue;
+            uint32_t h = hash_col(cc[v]) & hm;
+            for (;;) {
+              const int32_t x = hk[h];
+              if (x == cc[v]) {
+                U.slot[hu[h]] = s0 + v * HEAVY_WG;
+                break;
+              }
+              if (x == -1) break;
+              h = (h + 1) & hm;
+            }
+          }
+        }
+        __syncthreads();
+      }
+      int32_t nd = 0, ni = 0, no = 0;
+      for (int32_t base = u0 + wv * 64; base < u1; base += HEAVY_WG) {
+        const int32_t u = base + lane;
+        const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u) : C_NOP;
+        nd += __popcll(__ballot(code == C_DEL));
+        ni += __popcll(__ballot(code == C_INS));
+        no += __popcll(__ballot(code == C_OVR));
+      }
+      if (lane == 0) {
+        atomicAdd(&cnt[0], nd);
+        atomicAdd(&cnt[1], ni);
+        atomicAdd(&cnt[2], no);
+      }
+      __syncthreads();
       if (tid == 0) {
-        const int32_t nd = U.pcnt[4 * r], ni = U.pcnt[4 * r + 1], no = U.pcnt[4 * r + 2];
-        const int32_t nl = len - nd + ni;
+        const int32_t nl = len - cnt[0] + cnt[1];
+        const bool chg = (cnt[0] + cnt[1] + cnt[2]) > 0;
         const bool reloc = nl > cap;
         U.plen[r] = nl;
-        U.pchg[r] = (nd + ni + no) > 0 ? 1 : 0;
-        U.pdel[r] = (nd > 0 ? PL_DEL : 0) | PL_HEAVY | PL_FLAT | (nd == u1 - u0 ? PL_PURE_DEL : 0);
+        U.pchg[r] = chg ? 1 : 0;
+        U.pdel[r] = (cnt[0] > 0 ? PL_DEL : 0) | PL_HEAVY;
         U.pcap[r] = reloc ? slack_cap(nl) : 0;
         if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
       }
-      continue;
-    }
-    if (tid < 3) cnt[tid] = 0;
-    {
-    for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) U.slot[u] = -1;
-    for (int32_t c0 = u0; c0 < u1; c0 += HEAVY_SLOTS / 2) {
-      const int32_t c1 = min(u1, c0 + HEAVY_SLOTS / 2);
-      // a table of twice this pass's updates (load <= 1/2): a long row with
-      // few updates clears a few hundred slots, not all of them
-      int32_t S = 256;
-      while (S < 2 * (c1 - c0)) S <<= 1;
-      const uint32_t hm = (uint32_t)S - 1;
-      for (int x = tid; x < S; x += HEAVY_WG) hk[x] = -1;
-      __syncthreads();
-      for (int32_t u = c0 + tid; u < c1; u += HEAVY_WG) {
-        const int32_t col = (int32_t)(U.key[u] & cmask);
-        uint32_t h = hash_col(col) & hm;
-        while (atomicCAS(&hk[h], -1, col) != -1) h = (h + 1) & hm;
-        hu[h] = u;
-      }
-      __syncthreads();
-      constexpr int SU = 8;  // row loads in flight per lane
-      for (int32_t s0 = tid; s0 < len; s0 += SU * HEAVY_WG) {
-        int32_t cc[SU];
-#pragma unroll
-        for (int v = 0; v < SU; ++v) cc[v] = s0 + v * HEAVY_WG < len ? m.col[off + s0 + v * HEAVY_WG] : -1;
-#pragma unroll
-        for (int v = 0; v < SU; ++v) {
-          if (cc[v] < 0) continue;
-          uint32_t h = hash_col(cc[v]) & hm;
-          for (;;) {
-            const int32_t x = hk[h];
-            if (x == cc[v]) {
-              U.slot[hu[h]] = s0 + v * HEAVY_WG;
-              break;
-            }
-            if (x == -1) break;
-            h = (h + 1) & hm;
-          }
-        }
-      }
       __syncthreads();
     }
-    }
-    int32_t nd = 0, ni = 0, no = 0;
-    for (int32_t base = u0 + wv * 64; base < u1; base += HEAVY_WG) {
-      const int32_t u = base + lane;
-      const uint8_t code = u < u1 ? plan_update<SR, VSZ>(m, off, idx, vals, U, G, u) : C_NOP;
-      nd += __popcll(__ballot(code == C_DEL));
-      ni += __popcll(__ballot(code == C_INS));
-      no += __popcll(__ballot(code == C_OVR));
-    }
-    if (lane == 0) {
-      atomicAdd(&cnt[0], nd);
-      atomicAdd(&cnt[1], ni);
-      atomicAdd(&cnt[2], no);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const int32_t nl = len - cnt[0] + cnt[1];
-      const bool chg = (cnt[0] + cnt[1] + cnt[2]) > 0;
-      const bool reloc = nl > cap;
-      U.plen[r] = nl;
-      U.pchg[r] = chg ? 1 : 0;
-      U.pdel[r] = (cnt[0] > 0 ? PL_DEL : 0) | PL_HEAVY;
-      U.pcap[r] = reloc ? slack_cap(nl) : 0;
-      if (reloc) atomicAdd(demand, (unsigned long long)slack_cap(nl));
-    }
-    __syncthreads();
-  }
-  __syncthreads();  // before the next share overwrites the picked rows
+    __syncthreads();  // before the next share overwrites the picked rows
   }
 }
 
@@ -780,226 +778,226 @@ __global__ __launch_bounds__(HEAVY_WG) void k_commit_heavy(DMat m, const int64_t
   const int64_t per = (nR + gridDim.x - 1) / gridDim.x;
   const int64_t rb = (int64_t)blockIdx.x * per, re = min(nR, rb + per);
   for (int64_t c0 = rb; c0 < re; c0 += HEAVY_WG) {
-  int32_t npick;
-  {
-    const int64_t rr = c0 + tid;
-    const bool f = rr < re && U.pchg[rr] && (U.pdel[rr] & PL_HEAVY);
-    const int32_t q = block_flag_prefix<HEAVY_WG>(f, wc, npick);
-    if (f) picked[q] = (int32_t)rr;
-    __syncthreads();
-  }
-  for (int32_t pq = 0; pq < npick; ++pq) {
-    const int64_t r = picked[pq];
-    const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
-    const uint8_t pf = U.pdel[r];
-    // unchanged or light: k_commit did it
-    if (!U.pchg[r] || !(pf & PL_HEAVY)) continue;
-    const bool nodel = !(pf & PL_DEL);
-    const bool flat = (pf & PL_FLAT) != 0;
-    const int32_t i = U.urow[r];
-    if (pf & PL_PURE_DEL) {
-      // k_delete_flat moves the entries; the row keeps its space and index
-      if (tid == 0) {
-        m.row_len[i] = U.plen[r];
-        m.row_epoch[i] = *d_epoch;
-      }
-      continue;
+    int32_t npick;
+    {
+      const int64_t rr = c0 + tid;
+      const bool f = rr < re && U.pchg[rr] && (U.pdel[rr] & PL_HEAVY);
+      const int32_t q = block_flag_prefix<HEAVY_WG>(f, wc, npick);
+      if (f) picked[q] = (int32_t)rr;
+      __syncthreads();
     }
-    const int64_t off = m.row_off[i];
-    const int32_t len = m.row_len[i];
-    const int32_t nl = U.plen[r];
-    const int32_t ncap = U.pcap[r];
-    const bool ixv = ix_valid(X, i);  // read by every thread before anyone changes it
-    int64_t dest = off;
-    if (ncap) {
-      if (tid == 0) dest_s = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
-      __syncthreads();
-      dest = (int64_t)dest_s;
-      __syncthreads();
-      if (dest + ncap > m.pool_cap) {
-        if (tid == 0) atomicOr(err, 1);
+    for (int32_t pq = 0; pq < npick; ++pq) {
+      const int64_t r = picked[pq];
+      const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+      const uint8_t pf = U.pdel[r];
+      // unchanged or light: k_commit did it
+      if (!U.pchg[r] || !(pf & PL_HEAVY)) continue;
+      const bool nodel = !(pf & PL_DEL);
+      const bool flat = (pf & PL_FLAT) != 0;
+      const int32_t i = U.urow[r];
+      if (pf & PL_PURE_DEL) {
+        // k_delete_flat moves the entries; the row keeps its space and index
+        if (tid == 0) {
+          m.row_len[i] = U.plen[r];
+          m.row_epoch[i] = *d_epoch;
+        }
         continue;
       }
-    }
-    bool ixk = false;  // the column index stays usable
-    if (nodel) {
+      const int64_t off = m.row_off[i];
+      const int32_t len = m.row_len[i];
+      const int32_t nl = U.plen[r];
+      const int32_t ncap = U.pcap[r];
+      const bool ixv = ix_valid(X, i);  // read by every thread before anyone changes it
+      int64_t dest = off;
       if (ncap) {
-        for (int32_t t0 = tid; t0 < len; t0 += 4 * HEAVY_WG) {
-          int32_t cc[4];
-          uint64_t vv[4];
+        if (tid == 0) dest_s = atomicAdd((unsigned long long*)m.d_top, (unsigned long long)ncap);
+        __syncthreads();
+        dest = (int64_t)dest_s;
+        __syncthreads();
+        if (dest + ncap > m.pool_cap) {
+          if (tid == 0) atomicOr(err, 1);
+          continue;
+        }
+      }
+      bool ixk = false;  // the column index stays usable
+      if (nodel) {
+        if (ncap) {
+          for (int32_t t0 = tid; t0 < len; t0 += 4 * HEAVY_WG) {
+            int32_t cc[4];
+            uint64_t vv[4];
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int32_t t = t0 + v * HEAVY_WG;
-            cc[v] = t < len ? m.col[off + t] : 0;
-            vv[v] = t < len ? load_raw<VSZ>(m.val, off + t) : 0;
-          }
+            for (int v = 0; v < 4; ++v) {
+              const int32_t t = t0 + v * HEAVY_WG;
+              cc[v] = t < len ? m.col[off + t] : 0;
+              vv[v] = t < len ? load_raw<VSZ>(m.val, off + t) : 0;
+            }
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int32_t t = t0 + v * HEAVY_WG;
-            if (t < len) {
-              m.col[dest + t] = cc[v];
-              store_raw<VSZ>(m.val, dest + t, vv[v]);
+            for (int v = 0; v < 4; ++v) {
+              const int32_t t = t0 + v * HEAVY_WG;
+              if (t < len) {
+                m.col[dest + t] = cc[v];
+                store_raw<VSZ>(m.val, dest + t, vv[v]);
+              }
             }
           }
         }
-      }
-      // the inserts join the column index unless it would be past 3/4 full
-      ixk = ixv && ix_fits(X, i, nl - len);
-      if (!flat) {
-        uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
-        const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
-        for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG)
-          if (U.code[u] == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
-        // inserts after the row's entries, in update order
-        int32_t k = 0;
-        for (int32_t base = u0; base < u1; base += HEAVY_WG) {
-          const int32_t u = base + tid;
-          const bool ins = u < u1 && U.code[u] == C_INS;
-          int32_t tot;
-          const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
-          if (ins) {
-            const int32_t pos = len + k + q;
-            m.col[dest + pos] = (int32_t)(U.key[u] & cmask);
-            store_raw<VSZ>(m.val, dest + pos, U.fin[u]);
-            if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), pos);
+        // the inserts join the column index unless it would be past 3/4 full
+        ixk = ixv && ix_fits(X, i, nl - len);
+        if (!flat) {
+          uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
+          const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
+          for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG)
+            if (U.code[u] == C_OVR) store_raw<VSZ>(m.val, dest + U.slot[u], U.fin[u]);
+          // inserts after the row's entries, in update order
+          int32_t k = 0;
+          for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+            const int32_t u = base + tid;
+            const bool ins = u < u1 && U.code[u] == C_INS;
+            int32_t tot;
+            const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
+            if (ins) {
+              const int32_t pos = len + k + q;
+              m.col[dest + pos] = (int32_t)(U.key[u] & cmask);
+              store_raw<VSZ>(m.val, dest + pos, U.fin[u]);
+              if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), pos);
+            }
+            k += tot;
           }
-          k += tot;
-        }
-      } else if (tid == 0) {
-        U.pix[r] = ixk ? 1 : 0;
-      }
-    } else {
-      // overwrites and deletion marks at the planned slots
-      int32_t nd = 0;
-      for (int32_t base = u0; base < u1; base += HEAVY_WG) {
-        const int32_t u = base + tid;
-        const uint8_t code = u < u1 ? U.code[u] : C_NOP;
-        if (code == C_DEL) m.col[off + U.slot[u]] = -1;
-        else if (code == C_OVR) store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
-        int32_t tot;
-        (void)block_flag_prefix<HEAVY_WG>(code == C_DEL, wc, tot);
-        nd += tot;
-      }
-      const int32_t ni = nl - len + nd;
-      __threadfence_block();
-      __syncthreads();
-      if (ncap == 0) {
-        ixk = ixv && ix_fits(X, i, ni);
-        uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
-        const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
-        // holes: deleted slots below the new length (their columns leave
-        // tombstones in the index)
-        int32_t H = 0;
-        for (int32_t base = u0; base < u1; base += HEAVY_WG) {
-          const int32_t u = base + tid;
-          const bool del = u < u1 && U.code[u] == C_DEL;
-          if (del && ixk) {
-            const int32_t h = ix_slot(ixt, ixn, (int32_t)(U.key[u] & cmask));
-            if (h >= 0) ixt[h] = IX_TOMB;
-          }
-          const bool hole = del && U.slot[u] < nl;
-          int32_t tot;
-          const int32_t q = block_flag_prefix<HEAVY_WG>(hole, wc, tot);
-          if (hole) U.holes[u0 + H + q] = U.slot[u];
-          H += tot;
-        }
-        // movers: entries left at or above the new length
-        int32_t Mc = 0;
-        for (int32_t s0 = nl; s0 < len; s0 += HEAVY_WG) {
-          const int32_t sl = s0 + tid;
-          const bool mover = sl < len && m.col[off + sl] != -1;
-          int32_t tot;
-          const int32_t q = block_flag_prefix<HEAVY_WG>(mover, wc, tot);
-          if (mover) U.mv_src[u0 + Mc + q] = sl;
-          Mc += tot;
-        }
-        __threadfence_block();
-        __syncthreads();
-        for (int32_t q = tid; q < Mc; q += HEAVY_WG) {
-          const int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q];
-          const int32_t cm = m.col[off + src];
-          m.col[off + dst] = cm;
-          store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
-          if (ixk) {
-            const int32_t h = ix_slot(ixt, ixn, cm);
-            if (h >= 0) ixt[h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
-          }
-        }
-        // inserts: the remaining holes, then the space after the old length
-        int32_t k = 0;
-        for (int32_t base = u0; base < u1; base += HEAVY_WG) {
-          const int32_t u = base + tid;
-          const bool ins = u < u1 && U.code[u] == C_INS;
-          int32_t tot;
-          const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
-          if (ins) {
-            const int32_t mm = Mc + k + q;
-            const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
-            m.col[off + dst] = (int32_t)(U.key[u] & cmask);
-            store_raw<VSZ>(m.val, off + dst, U.fin[u]);
-            if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), dst);
-          }
-          k += tot;
+        } else if (tid == 0) {
+          U.pix[r] = ixk ? 1 : 0;
         }
       } else {
-        // compact into fresh space, then append the inserts
-        int32_t kept = 0;
-        for (int32_t s0 = 0; s0 < len; s0 += HEAVY_WG) {
-          const int32_t sl = s0 + tid;
-          const int32_t cc = sl < len ? m.col[off + sl] : -1;
-          const uint64_t vv = sl < len ? load_raw<VSZ>(m.val, off + sl) : 0;
-          int32_t tot;
-          const int32_t q = block_flag_prefix<HEAVY_WG>(cc != -1, wc, tot);
-          if (cc != -1) {
-            m.col[dest + kept + q] = cc;
-            store_raw<VSZ>(m.val, dest + kept + q, vv);
-          }
-          kept += tot;
-        }
+        // overwrites and deletion marks at the planned slots
+        int32_t nd = 0;
         for (int32_t base = u0; base < u1; base += HEAVY_WG) {
           const int32_t u = base + tid;
-          const bool ins = u < u1 && U.code[u] == C_INS;
+          const uint8_t code = u < u1 ? U.code[u] : C_NOP;
+          if (code == C_DEL) m.col[off + U.slot[u]] = -1;
+          else if (code == C_OVR) store_raw<VSZ>(m.val, off + U.slot[u], U.fin[u]);
           int32_t tot;
-          const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
-          if (ins) {
-            m.col[dest + kept + q] = (int32_t)(U.key[u] & cmask);
-            store_raw<VSZ>(m.val, dest + kept + q, U.fin[u]);
+          (void)block_flag_prefix<HEAVY_WG>(code == C_DEL, wc, tot);
+          nd += tot;
+        }
+        const int32_t ni = nl - len + nd;
+        __threadfence_block();
+        __syncthreads();
+        if (ncap == 0) {
+          ixk = ixv && ix_fits(X, i, ni);
+          uint64_t* ixt = ixk ? X.tab + X.off[i] : nullptr;
+          const uint32_t ixn = ixk ? (uint32_t)X.sz[i] : 0u;
+          // holes: deleted slots below the new length (their columns leave
+          // tombstones in the index)
+          int32_t H = 0;
+          for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+            const int32_t u = base + tid;
+            const bool del = u < u1 && U.code[u] == C_DEL;
+            if (del && ixk) {
+              const int32_t h = ix_slot(ixt, ixn, (int32_t)(U.key[u] & cmask));
+              if (h >= 0) ixt[h] = IX_TOMB;
+            }
+            const bool hole = del && U.slot[u] < nl;
+            int32_t tot;
+            const int32_t q = block_flag_prefix<HEAVY_WG>(hole, wc, tot);
+            if (hole) U.holes[u0 + H + q] = U.slot[u];
+            H += tot;
           }
-          kept += tot;
+          // movers: entries left at or above the new length
+          int32_t Mc = 0;
+          for (int32_t s0 = nl; s0 < len; s0 += HEAVY_WG) {
+            const int32_t sl = s0 + tid;
+            const bool mover = sl < len && m.col[off + sl] != -1;
+            int32_t tot;
+            const int32_t q = block_flag_prefix<HEAVY_WG>(mover, wc, tot);
+            if (mover) U.mv_src[u0 + Mc + q] = sl;
+            Mc += tot;
+          }
+          __threadfence_block();
+          __syncthreads();
+          for (int32_t q = tid; q < Mc; q += HEAVY_WG) {
+            const int32_t src = U.mv_src[u0 + q], dst = U.holes[u0 + q];
+            const int32_t cm = m.col[off + src];
+            m.col[off + dst] = cm;
+            store_raw<VSZ>(m.val, off + dst, load_raw<VSZ>(m.val, off + src));
+            if (ixk) {
+              const int32_t h = ix_slot(ixt, ixn, cm);
+              if (h >= 0) ixt[h] = ((uint64_t)(uint32_t)dst << 32) | (uint64_t)(uint32_t)cm;
+            }
+          }
+          // inserts: the remaining holes, then the space after the old length
+          int32_t k = 0;
+          for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+            const int32_t u = base + tid;
+            const bool ins = u < u1 && U.code[u] == C_INS;
+            int32_t tot;
+            const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
+            if (ins) {
+              const int32_t mm = Mc + k + q;
+              const int32_t dst = mm < H ? U.holes[u0 + mm] : len + (mm - H);
+              m.col[off + dst] = (int32_t)(U.key[u] & cmask);
+              store_raw<VSZ>(m.val, off + dst, U.fin[u]);
+              if (ixk) ix_put(ixt, ixn, (int32_t)(U.key[u] & cmask), dst);
+            }
+            k += tot;
+          }
+        } else {
+          // compact into fresh space, then append the inserts
+          int32_t kept = 0;
+          for (int32_t s0 = 0; s0 < len; s0 += HEAVY_WG) {
+            const int32_t sl = s0 + tid;
+            const int32_t cc = sl < len ? m.col[off + sl] : -1;
+            const uint64_t vv = sl < len ? load_raw<VSZ>(m.val, off + sl) : 0;
+            int32_t tot;
+            const int32_t q = block_flag_prefix<HEAVY_WG>(cc != -1, wc, tot);
+            if (cc != -1) {
+              m.col[dest + kept + q] = cc;
+              store_raw<VSZ>(m.val, dest + kept + q, vv);
+            }
+            kept += tot;
+          }
+          for (int32_t base = u0; base < u1; base += HEAVY_WG) {
+            const int32_t u = base + tid;
+            const bool ins = u < u1 && U.code[u] == C_INS;
+            int32_t tot;
+            const int32_t q = block_flag_prefix<HEAVY_WG>(ins, wc, tot);
+            if (ins) {
+              m.col[dest + kept + q] = (int32_t)(U.key[u] & cmask);
+              store_raw<VSZ>(m.val, dest + kept + q, U.fin[u]);
+            }
+            kept += tot;
+          }
+        }
+        if (ixk && tid == 0) X.used[i] += ni;
+      }
+      __syncthreads();  // every thread has used the row's old bookkeeping
+      if (tid == 0) {
+        if (ixv) {
+          if (!ixk) X.stamp[i] = 0;
+          else if (nodel) X.used[i] += nl - len;
+        }
+        m.row_len[i] = nl;
+        m.row_epoch[i] = *d_epoch;
+        if (ncap) {
+          m.row_off[i] = dest;
+          m.row_cap[i] = ncap;
         }
       }
-      if (ixk && tid == 0) X.used[i] += ni;
-    }
-    __syncthreads();  // every thread has used the row's old bookkeeping
-    if (tid == 0) {
-      if (ixv) {
-        if (!ixk) X.stamp[i] = 0;
-        else if (nodel) X.used[i] += nl - len;
-      }
-      m.row_len[i] = nl;
-      m.row_epoch[i] = *d_epoch;
-      if (ncap) {
-        m.row_off[i] = dest;
-        m.row_cap[i] = ncap;
-      }
-    }
-    if (dkey && !(flat && nodel)) {  // at the update's own index, as in k_commit
-      for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) {
-        const uint8_t code = U.code[u];
-        if (!emits_delta(code)) continue;
-        if (u >= dcap) {
-          atomicOr(err, 4);
-          continue;
+      if (dkey && !(flat && nodel)) {  // at the update's own index, as in k_commit
+        for (int32_t u = u0 + tid; u < u1; u += HEAVY_WG) {
+          const uint8_t code = U.code[u];
+          if (!emits_delta(code)) continue;
+          if (u >= dcap) {
+            atomicOr(err, 4);
+            continue;
+          }
+          const uint64_t j = U.key[u] & cmask;
+          dkey[u] = (j << tbits) | (uint64_t)(uint32_t)i;
+          dop[u] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
+          store_raw<VSZ>(dval, u, U.fin[u]);
         }
-        const uint64_t j = U.key[u] & cmask;
-        dkey[u] = (j << tbits) | (uint64_t)(uint32_t)i;
-        dop[u] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
-        store_raw<VSZ>(dval, u, U.fin[u]);
       }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  __syncthreads();  // before the next share overwrites the picked rows
+    __syncthreads();  // before the next share overwrites the picked rows
   }
 }
 

@@ -77,50 +77,50 @@ __global__ __launch_bounds__(IX_HEAVY_WG) void k_ix_build_heavy(const int64_t* r
   const int64_t per = (n + gridDim.x - 1) / gridDim.x;
   const int64_t rb = (int64_t)blockIdx.x * per, re = min(n, rb + per);
   for (int64_t c0 = rb; c0 < re; c0 += IX_HEAVY_WG) {
-  int32_t npick;
-  {
-    const int64_t rr = c0 + tid;
-    bool f = false;
-    if (rr < re) {
-      const int32_t ii = rows ? rows[rr] : (int32_t)rr;
-      f = row_len[ii] > IX_LIGHT_MAX && (fresh || X.stamp[ii] != X.gen);
-    }
-    const int32_t q = block_flag_prefix<IX_HEAVY_WG>(f, wc, npick);
-    if (f) picked[q] = rows ? rows[rr] : (int32_t)rr;
-    __syncthreads();
-  }
-  for (int32_t pq = 0; pq < npick; ++pq) {
-    const int32_t i = picked[pq];
-    const int32_t len = row_len[i];
-    int32_t sz;
-    unsigned long long base;
-    if (fresh) {
-      sz = X.sz[i];
-      base = (unsigned long long)X.off[i];
-    } else {
-      sz = table_size(len);
-      if (tid == 0) base_s = atomicAdd(X.top, (unsigned long long)sz);
-      __syncthreads();
-      base = base_s;
+    int32_t npick;
+    {
+      const int64_t rr = c0 + tid;
+      bool f = false;
+      if (rr < re) {
+        const int32_t ii = rows ? rows[rr] : (int32_t)rr;
+        f = row_len[ii] > IX_LIGHT_MAX && (fresh || X.stamp[ii] != X.gen);
+      }
+      const int32_t q = block_flag_prefix<IX_HEAVY_WG>(f, wc, npick);
+      if (f) picked[q] = rows ? rows[rr] : (int32_t)rr;
       __syncthreads();
     }
-    if ((int64_t)base + sz > X.cap) continue;
-    uint64_t* t = X.tab + base;
-    for (int32_t x = tid; x < sz; x += IX_HEAVY_WG) t[x] = IX_EMPTY;
-    __threadfence_block();
-    __syncthreads();
-    const int64_t off = row_off[i];
-    for (int32_t p = tid; p < len; p += IX_HEAVY_WG) ix_put(t, (uint32_t)sz, col[off + p], p);
-    __threadfence_block();
-    __syncthreads();
-    if (tid == 0) {
-      X.off[i] = (int64_t)base;
-      X.sz[i] = sz;
-      X.used[i] = len;
-      X.stamp[i] = X.gen;
+    for (int32_t pq = 0; pq < npick; ++pq) {
+      const int32_t i = picked[pq];
+      const int32_t len = row_len[i];
+      int32_t sz;
+      unsigned long long base;
+      if (fresh) {
+        sz = X.sz[i];
+        base = (unsigned long long)X.off[i];
+      } else {
+        sz = table_size(len);
+        if (tid == 0) base_s = atomicAdd(X.top, (unsigned long long)sz);
+        __syncthreads();
+        base = base_s;
+        __syncthreads();
+      }
+      if ((int64_t)base + sz > X.cap) continue;
+      uint64_t* t = X.tab + base;
+      for (int32_t x = tid; x < sz; x += IX_HEAVY_WG) t[x] = IX_EMPTY;
+      __threadfence_block();
+      __syncthreads();
+      const int64_t off = row_off[i];
+      for (int32_t p = tid; p < len; p += IX_HEAVY_WG) ix_put(t, (uint32_t)sz, col[off + p], p);
+      __threadfence_block();
+      __syncthreads();
+      if (tid == 0) {
+        X.off[i] = (int64_t)base;
+        X.sz[i] = sz;
+        X.used[i] = len;
+        X.stamp[i] = X.gen;
+      }
     }
-  }
-  __syncthreads();  // before the next share overwrites the picked rows
+    __syncthreads();  // before the next share overwrites the picked rows
   }
 }
 
