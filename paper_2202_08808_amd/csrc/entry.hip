@@ -161,8 +161,7 @@ __device__ inline bool keyset_has(const KeySet& H, uint64_t k) {
 // ---- 2. write the products: one wavefront per changed entry ----
 template <int SR>
 __global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, Mat A, Mat T, const int64_t* base,
-                                                    uint64_t* tkey, uint64_t* told, uint64_t* tnew, uint8_t* tfl,
-                                                    uint64_t sentinel) {
+                                                    uint64_t* tkey, uint64_t* told, uint64_t* tnew, uint8_t* tfl) {
   using S = Sem<SR>;
   using V = typename S::V;
   const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -223,16 +222,14 @@ __global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, 
   for (int32_t t = lane; t < tl; t += 64) {
     const int32_t i = T.col[tc + t];
     const V a = ldv<V>(T.val, tc + t);
-    if (keyset_has(H, ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)r)) {
-      // (i, r) changed too: that entry's left-factor products include this one
-      tkey[o + t] = sentinel;
-      tfl[o + t] = 0;
-      continue;
-    }
-    const uint8_t f = (op ? F_OLD : 0) | (np ? F_NEW : 0);
+    // (i, r) changed too: that entry's left-factor products include this
+    // one, which stays in the list with no effect (its key (i, c) is among
+    // those products' keys, so it adds no entry of C)
+    const bool dup = keyset_has(H, ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)r);
+    const uint8_t f = dup ? 0 : (op ? F_OLD : 0) | (np ? F_NEW : 0);
     tkey[o + t] = ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)c;
-    told[o + t] = op ? (uint64_t)S::mul(a, vo) : 0ull;
-    tnew[o + t] = np ? (uint64_t)S::mul(a, vn) : 0ull;
+    told[o + t] = (f & F_OLD) ? (uint64_t)S::mul(a, vo) : 0ull;
+    tnew[o + t] = (f & F_NEW) ? (uint64_t)S::mul(a, vn) : 0ull;
     tfl[o + t] = f;
   }
 }
@@ -243,21 +240,17 @@ __global__ void k_iota_u32(uint32_t* p, int64_t n) {
 }
 
 // ---- 3. segments of equal keys ----
-__global__ void k_seg_heads(const uint64_t* key, int64_t n, uint64_t sentinel, int64_t* head) {
+__global__ void k_seg_heads(const uint64_t* key, int64_t n, int64_t* head) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) {
-    const uint64_t k = key[t];
-    head[t] = (k != sentinel && (t == 0 || key[t - 1] != k)) ? 1 : 0;
-  }
+  if (t < n) head[t] = (t == 0 || key[t - 1] != key[t]) ? 1 : 0;
 }
 
-__global__ void k_seg_scatter(const uint64_t* key, int64_t n, uint64_t sentinel, const int64_t* head,
-                              const int64_t* segid, const int64_t* d_nseg, int64_t* seg_start) {
+__global__ void k_seg_scatter(int64_t n, const int64_t* head, const int64_t* segid, const int64_t* d_nseg,
+                              int64_t* seg_start) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   if (head[t]) seg_start[segid[t]] = t;
-  const bool valid = key[t] != sentinel;
-  if (valid && (t + 1 == n || key[t + 1] == sentinel)) seg_start[*d_nseg] = t + 1;
+  if (t + 1 == n) seg_start[*d_nseg] = n;
 }
 
 // one thread per segment: fold the changed products of one entry of C
@@ -546,7 +539,6 @@ int32_t entry_update(DProd* p) {
   const int32_t n = A->nrows;
   const int cbits = bits_for(A->ncols);
   const int kbits = 2 * cbits;
-  const uint64_t sentinel = 1ull << kbits;
   dsg_update_stats& st = p->stats;
   st = dsg_update_stats{};
   st.path = 1;
@@ -616,19 +608,19 @@ int32_t entry_update(DProd* p) {
       hipLaunchKernelGGL(k_keyset_clear, dim3(std::min<unsigned>(blocks_for(hs, 256), 1024)), dim3(256), 0, s, H);
       hipLaunchKernelGGL(k_keyset_fill, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, H);
       hipLaunchKernelGGL((k_term_write<SR>), dim3(blocks_for(nU * 64, 256)), dim3(256), 0, s, L, H, cbits, view(A),
-                         view(T), (const int64_t*)off, tkey, told, tnew, tfl, sentinel);
+                         view(T), (const int64_t*)off, tkey, told, tnew, tfl);
       hipLaunchKernelGGL(k_iota_u32, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tidx, nterm);
     }
     // ---- 3. sort, segments, one update per entry of C ----
     {
       Phase ph(c, "entry_sort");
-      radix_sort_pairs(tkey, tidx, nterm, kbits + 1, rscr, s);
+      radix_sort_pairs(tkey, tidx, nterm, kbits, rscr, s);
     }
     Phase ph(c, "entry_reduce");
-    hipLaunchKernelGGL(k_seg_heads, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tkey, nterm, sentinel, head);
+    hipLaunchKernelGGL(k_seg_heads, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tkey, nterm, head);
     exclusive_scan_i64(head, segid, nterm, d_total, scan2, s);
-    hipLaunchKernelGGL(k_seg_scatter, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tkey, nterm, sentinel,
-                       (const int64_t*)head, (const int64_t*)segid, (const int64_t*)d_total, seg_start);
+    hipLaunchKernelGGL(k_seg_scatter, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, nterm, (const int64_t*)head,
+                       (const int64_t*)segid, (const int64_t*)d_total, seg_start);
     nseg = read_count(c, d_total);
     if (nseg > 0)
       hipLaunchKernelGGL((k_seg_reduce<SR>), dim3(blocks_for(nseg, 256)), dim3(256), 0, s, tkey, tidx, told, tnew,
@@ -696,7 +688,7 @@ int32_t entry_update(DProd* p) {
     const int64_t ndel = hd[0];
     if (ndel > 0) {
       Phase ph(c, "entry_delete");
-      mat_apply_sorted_delete(C, lkey, ldel, ndel);
+      mat_apply_sorted_delete(C, lkey, lslot, ldel, ndel);
     }
   }
 

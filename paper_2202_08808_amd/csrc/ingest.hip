@@ -190,6 +190,11 @@ __device__ inline int32_t find_update(const uint64_t* ukey, int32_t u0, int32_t 
 struct Guard {
   const uint64_t* key = nullptr;  // ordered key of the guarded value, per unique update
   const uint8_t* flag = nullptr;  // 2: guarded by key; 4: always lost when present
+  // deletions of present entries whose slots are known (unique update u
+  // deletes the entry at row-relative slot known_slot[known_list[u]]): no
+  // plan, no row streamed (mat_apply_sorted_delete)
+  const int32_t* known_slot = nullptr;
+  const int32_t* known_list = nullptr;
 };
 
 // The outcome of unique update u of a row whose slot (or -1) the plan found:
@@ -562,6 +567,35 @@ __global__ __launch_bounds__(256) void k_commit(DMat m, const int64_t* d_nR, uin
         dop[u] = code == C_DEL ? DSG_OP_DELETE : DSG_OP_SET;
         store_raw<VSZ>(dval, u, U.fin[u]);
       }
+    }
+  }
+}
+
+// The plan of deletions at known slots: one wavefront per touched row
+// records each update's slot and outcome and the row's new length; a heavy
+// row with a usable column index is committed update by update
+// (k_delete_flat), the others by k_commit / k_commit_heavy.
+__global__ __launch_bounds__(256) void k_plan_known(DMat m, const int64_t* d_nR, Uniq U, Guard G, RowIx X) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nR = *d_nR;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < nR; r += nw) {
+    const int32_t i = U.urow[r];
+    const int32_t u0 = U.row_first[r], u1 = U.row_first[r + 1];
+    for (int32_t u = u0 + lane; u < u1; u += 64) {
+      U.slot[u] = G.known_slot[G.known_list ? G.known_list[u] : u];
+      U.code[u] = C_DEL;
+      U.fin[u] = 0;
+      U.old[u] = 0;
+    }
+    if (lane == 0) {
+      const int32_t len = m.row_len[i], nd = u1 - u0;
+      const bool heavy = nd > PLAN_LDS || len > HEAVY_LEN;
+      U.plen[r] = len - nd;
+      U.pchg[r] = 1;
+      U.pcap[r] = 0;
+      U.pdel[r] = PL_DEL | (heavy ? PL_HEAVY | (ix_valid(X, i) ? PL_FLAT | PL_PURE_DEL : 0) : 0);
+      for (int x = 0; x < 4; ++x) U.pcnt[4 * r + x] = 0;
     }
   }
 }
@@ -1303,7 +1337,10 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
   const RowIx X = graph ? RowIx() : mat_index_view(m);
   // the flat kernels: one thread per unique update, bounded grid
   const unsigned nf = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n, 256), 32 * (int64_t)c->num_cus));
-  if (phases & PH_PLAN) {
+  if ((phases & PH_PLAN) && G.known_slot) {
+    // deletions at known slots: nothing to look up, no row moves
+    hipLaunchKernelGGL(k_plan_known, dim3(nb), dim3(256), 0, s, *m, w.nR, w.U, G, X);
+  } else if (phases & PH_PLAN) {
   // tables for the touched rows that have none, before the plan looks them up
   if (X.tab) {
     mat_index_build(m, w.U.urow, w.nR, n);
@@ -1601,7 +1638,7 @@ int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, co
   return (int64_t)h[0];
 }
 
-void mat_apply_sorted_delete(DMat* m, const uint64_t* keys, const int32_t* list, int64_t n) {
+void mat_apply_sorted_delete(DMat* m, const uint64_t* keys, const int32_t* slots, const int32_t* list, int64_t n) {
   DSG_REQUIRE(!m->tidx, DSG_E_STATE, "internal: sorted delete on a matrix with a transpose");
   if (n == 0) return;
   Ctx* c = m->ctx;
@@ -1610,7 +1647,10 @@ void mat_apply_sorted_delete(DMat* m, const uint64_t* keys, const int32_t* list,
   hipLaunchKernelGGL(k_delete_keys, dim3(blocks_for(n, 256)), dim3(256), 0, s, keys, list, n, w.keys, w.idx,
                      w.allops);
   const int kbits = bits_for(m->ncols) + bits_for(m->nrows);
-  run_core(m, w, n, kbits, false, w.allops, nullptr, false, true);
+  Guard G;
+  G.known_slot = slots;
+  G.known_list = list;
+  run_core(m, w, n, kbits, false, w.allops, nullptr, false, true, G);
   int* he = (int*)((char*)c->pinned + 64);
   DSG_HIP(hipMemcpyAsync(he, w.err, 4, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));

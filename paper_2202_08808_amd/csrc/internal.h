@@ -308,9 +308,10 @@ int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, co
                              const uint8_t* flag, int64_t n, uint64_t* lost_key, int32_t* lost_slot,
                              int64_t lost_cap, unsigned long long* d_nlost, int64_t* d_nrows, void* scratch);
 // Delete the n present entries whose keys (row << colbits | col) are
-// keys[list[t]] (list null: keys[t]), sorted ascending and unique.  m must
-// have no transpose.
-void mat_apply_sorted_delete(DMat* m, const uint64_t* keys, const int32_t* list, int64_t n);
+// keys[list[t]] (list null: keys[t]), sorted ascending and unique, and
+// which sit at the row-relative slots slots[list[t]] (nothing is looked up
+// or streamed).  m must have no transpose.
+void mat_apply_sorted_delete(DMat* m, const uint64_t* keys, const int32_t* slots, const int32_t* list, int64_t n);
 // Device validation of a batch: returns dsg_status.
 dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols,
                                  const uint8_t* d_ops, int64_t n);
