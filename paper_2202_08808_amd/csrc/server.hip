@@ -8,10 +8,15 @@
 // within a batch, later entries of a key win or fold after earlier ones.  It
 // also merges consecutive queries into one gather.  Each group is packed into
 // pinned host memory and copied to the device on a stream of its own.  The
-// executor runs the groups in order on the context's stream: ingest plus the
-// dynamic update for an update group, a row gather for a query group.  The copy
-// of the next group overlaps the device work of the current one, and requests
-// that arrive meanwhile join the next group.
+// executor takes the groups in order: ingest plus the dynamic update for an
+// update group (context's stream), a row gather for a query group (a query
+// stream).  Results are those of the arrival order, and device work overlaps:
+//   - the copy of the next group overlaps the device work of the current one;
+//   - a query's gather overlaps the ingest of the update after it (which
+//     changes only the operand): the gather starts after the update before
+//     it (an event), and the next update's product step waits for the gather
+//     (another event), since only that step changes C.
+// Requests that arrive meanwhile join the next group.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -101,6 +106,13 @@ struct DServer {
   dsg_status failed = DSG_OK;
   std::string failure;
   hipStream_t copy = nullptr;
+  hipStream_t qstream = nullptr;  // query gathers
+  hipEvent_t c_ready = nullptr;   // on the context's stream: C after the last update
+  hipEvent_t q_done = nullptr;    // on the query stream: the gather in flight read C
+  void* q_col_h = nullptr;        // pinned: the gathered entries
+  size_t q_col_bytes = 0;
+  void* q_val_h = nullptr;
+  size_t q_val_bytes = 0;
   std::thread stager, executor;
   GatherBufs gather;
   // admission estimates, refreshed by the executor after each group
@@ -301,19 +313,167 @@ void stager_main(DServer* s) {
   s->cv_ready.notify_all();
 }
 
+// A query group whose gather is in flight on the query stream.
+struct PendingQuery {
+  Group* g = nullptr;
+  std::vector<int64_t> row_ptr;  // the gathered rows' pointers
+  int64_t nnz = 0;
+  int status = DSG_OK;
+  std::string msg;
+};
+
+void ensure_dev(Ctx* c, void*& p, size_t& have, size_t bytes) {
+  if (have >= bytes) return;
+  ctx_free(c, p, have);
+  p = nullptr;
+  have = 0;
+  const size_t nb = bytes + bytes / 2 + 4096;
+  p = ctx_alloc(c, nb);
+  have = nb;
+}
+
+void ensure_pinned(void*& p, size_t& have, size_t bytes) {
+  if (have >= bytes) return;
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  have = 0;
+  const size_t nb = bytes + bytes / 2 + 4096;
+  DSG_HIP(hipHostMalloc(&p, nb, hipHostMallocDefault));
+  have = nb;
+}
+
+// Start a query group's gather on the query stream, after its rows are
+// staged and after the last update: row lengths and pointers (read back),
+// then the entries into pinned memory; q_done marks the end.
+void query_begin(DServer* s, Group* g, PendingQuery& pq) {
+  Ctx* c = s->c;
+  DMat* C = s->p->C;
+  hipStream_t q = s->qstream;
+  pq = PendingQuery();
+  pq.g = g;
+  const int32_t n = (int32_t)g->n;
+  DSG_HIP(hipStreamWaitEvent(q, s->slots[(size_t)g->slot].copied, 0));
+  DSG_HIP(hipStreamWaitEvent(q, s->c_ready, 0));
+  GatherBufs& b = s->gather;
+  ensure_dev(c, b.lens, b.lens_bytes, ((size_t)n + 1) * 8);
+  ensure_dev(c, b.rp, b.rp_bytes, ((size_t)n + 1) * 8);
+  ensure_dev(c, b.scan, b.scan_bytes, scan_scratch_bytes(n) + 64);
+  gather_row_ptr(C, g->d_rows, n, (int64_t*)b.lens, (int64_t*)b.rp, b.scan, q);
+  pq.row_ptr.assign((size_t)n + 1, 0);
+  DSG_HIP(hipMemcpyAsync(pq.row_ptr.data(), b.rp, pq.row_ptr.size() * 8, hipMemcpyDeviceToHost, q));
+  DSG_HIP(hipStreamSynchronize(q));
+  pq.nnz = pq.row_ptr[(size_t)n];
+  const size_t vs = (size_t)C->vsz;
+  if (pq.nnz > 0) {
+    ensure_dev(c, b.col, b.col_bytes, (size_t)pq.nnz * 4);
+    ensure_dev(c, b.val, b.val_bytes, (size_t)pq.nnz * (vs ? vs : 1));
+    ensure_pinned(s->q_col_h, s->q_col_bytes, (size_t)pq.nnz * 4);
+    if (vs) ensure_pinned(s->q_val_h, s->q_val_bytes, (size_t)pq.nnz * vs);
+    gather_row_entries(C, g->d_rows, n, (const int64_t*)b.rp, (int32_t*)b.col, b.val, q);
+    DSG_HIP(hipMemcpyAsync(s->q_col_h, b.col, (size_t)pq.nnz * 4, hipMemcpyDeviceToHost, q));
+    if (vs) DSG_HIP(hipMemcpyAsync(s->q_val_h, b.val, (size_t)pq.nnz * vs, hipMemcpyDeviceToHost, q));
+  }
+  DSG_HIP(hipEventRecord(s->q_done, q));
+}
+
+// Complete the query in flight: wait for its gather, sort each row by column,
+// split the answer per request, release its slot.
+void query_finish(DServer* s, PendingQuery& pq) {
+  Group* g = pq.g;
+  int st = pq.status;
+  std::string msg = pq.msg;
+  if (st == DSG_OK) {
+    try {
+      DSG_HIP(hipEventSynchronize(s->q_done));
+      const size_t vs = (size_t)s->p->C->vsz;
+      const int32_t* hc = (const int32_t*)s->q_col_h;
+      const char* hv = (const char*)s->q_val_h;
+      std::vector<int64_t> perm;
+      size_t q0 = 0;
+      for (SReq* r : g->reqs) {
+        const size_t nq = r->rows.size();
+        const int64_t e0 = pq.row_ptr[q0], e1 = pq.row_ptr[q0 + nq];
+        r->answer.row_ptr.resize(nq + 1);
+        for (size_t q = 0; q <= nq; ++q) r->answer.row_ptr[q] = pq.row_ptr[q0 + q] - e0;
+        r->answer.col.resize((size_t)(e1 - e0));
+        r->answer.val.resize((size_t)(e1 - e0) * vs);
+        // rows are stored in no particular column order: sort each one
+        for (size_t q = 0; q < nq; ++q) {
+          const int64_t a = pq.row_ptr[q0 + q], b = pq.row_ptr[q0 + q + 1];
+          perm.resize((size_t)(b - a));
+          for (int64_t e = a; e < b; ++e) perm[(size_t)(e - a)] = e;
+          std::sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return hc[x] < hc[y]; });
+          for (int64_t e = a; e < b; ++e) {
+            const int64_t src = perm[(size_t)(e - a)];
+            r->answer.col[(size_t)(e - e0)] = hc[src];
+            if (vs) memcpy(r->answer.val.data() + (size_t)(e - e0) * vs, hv + (size_t)src * vs, vs);
+          }
+        }
+        q0 += nq;
+      }
+    } catch (const DsgError& e) {
+      st = e.code;
+      msg = e.msg;
+    }
+  }
+  const double t = now_ms();
+  std::lock_guard<std::mutex> lk(s->mu);
+  for (SReq* r : g->reqs) {
+    r->group = g->id;
+    r->group_requests = (int32_t)g->reqs.size();
+    finish(s, r, st, t);
+  }
+  if (st == DSG_OK) s->query_groups++;
+  else if (s->failed == DSG_OK) {
+    s->failed = (dsg_status)st;
+    s->failure = msg;
+  }
+  s->slots[(size_t)g->slot].busy = false;
+  s->inflight -= g->est;
+  delete g;
+  pq.g = nullptr;
+  s->cv_free.notify_all();
+  s->cv_done.notify_all();
+  if (s->failed != DSG_OK) s->cv_arrive.notify_all();
+}
+
 void executor_main(DServer* s) {
   (void)hipSetDevice(s->c->device);
   Ctx* c = s->c;
+  PendingQuery pq;
   for (;;) {
     Group* g = nullptr;
     dsg_status failed;
     {
       std::unique_lock<std::mutex> lk(s->mu);
+      if (pq.g && s->ready.empty()) {
+        // nothing to overlap the gather with: complete the query now
+        lk.unlock();
+        query_finish(s, pq);
+        continue;
+      }
       s->cv_ready.wait(lk, [&] { return !s->ready.empty() || s->stager_done; });
       if (s->ready.empty()) break;
       g = s->ready.front();
       s->ready.pop_front();
       failed = s->failed;
+    }
+    if (g->kind == 1) {
+      if (pq.g) query_finish(s, pq);  // one gather in flight at a time
+      PendingQuery next;
+      next.g = g;
+      next.status = failed;
+      if (failed == DSG_OK) {
+        try {
+          query_begin(s, g, next);
+        } catch (const DsgError& e) {
+          next.g = g;
+          next.status = e.code;
+          next.msg = e.msg;
+        }
+      }
+      pq = std::move(next);
+      continue;
     }
     int st = failed;
     std::string msg;
@@ -322,35 +482,24 @@ void executor_main(DServer* s) {
     if (st == DSG_OK) {
       try {
         DSG_HIP(hipStreamWaitEvent(c->stream, s->slots[(size_t)g->slot].copied, 0));
-        if (g->kind == 0) {
-          if (g->n > 0) mat_apply_device(g->target, g->d_rows, g->d_cols, g->d_vals, g->d_ops, g->n);
-          changed = prod_run(s->p, 0, false);
-          if (g->n > 0) {
-            // workspace the update took: products and entry updates on the
-            // entry-granular path, staging and new C space on the row path
-            const dsg_update_stats& st = s->p->stats;
-            const double sz = 4.0 + (double)s->p->C->vsz;
-            const double bytes = st.path == 1 ? 32.0 * (double)st.terms + 64.0 * (double)st.entries
-                                              : (double)s->p->last_arena_demand + sz * (double)s->p->last_c_demand;
-            ws = std::min(std::max(bytes / (double)g->n, 16.0), 65536.0);
-          }
-          rb = (4.0 + (double)s->p->C->vsz) * (double)s->p->C->h_top_ub / (double)std::max<int32_t>(s->p->C->nrows, 1);
-        } else {
-          RowsHost all;
-          mat_gather_rows(s->p->C, g->d_rows, (int32_t)g->n, s->gather, all, c->stream);
-          // split the answer per query
-          const size_t vsz = (size_t)s->p->C->vsz;
-          size_t q0 = 0;
-          for (SReq* r : g->reqs) {
-            const size_t nq = r->rows.size();
-            const int64_t e0 = all.row_ptr[q0], e1 = all.row_ptr[q0 + nq];
-            r->answer.row_ptr.resize(nq + 1);
-            for (size_t q = 0; q <= nq; ++q) r->answer.row_ptr[q] = all.row_ptr[q0 + q] - e0;
-            r->answer.col.assign(all.col.begin() + e0, all.col.begin() + e1);
-            r->answer.val.assign(all.val.begin() + (size_t)e0 * vsz, all.val.begin() + (size_t)e1 * vsz);
-            q0 += nq;
-          }
+        if (g->n > 0) mat_apply_device(g->target, g->d_rows, g->d_cols, g->d_vals, g->d_ops, g->n);
+        if (pq.g) {
+          // the product step changes C: after the gather before it
+          DSG_HIP(hipStreamWaitEvent(c->stream, s->q_done, 0));
+          query_finish(s, pq);
         }
+        changed = prod_run(s->p, 0, false);
+        DSG_HIP(hipEventRecord(s->c_ready, c->stream));
+        if (g->n > 0) {
+          // workspace the update took: products and entry updates on the
+          // entry-granular path, staging and new C space on the row path
+          const dsg_update_stats& st = s->p->stats;
+          const double sz = 4.0 + (double)s->p->C->vsz;
+          const double bytes = st.path == 1 ? 32.0 * (double)st.terms + 64.0 * (double)st.entries
+                                            : (double)s->p->last_arena_demand + sz * (double)s->p->last_c_demand;
+          ws = std::min(std::max(bytes / (double)g->n, 16.0), 65536.0);
+        }
+        rb = (4.0 + (double)s->p->C->vsz) * (double)s->p->C->h_top_ub / (double)std::max<int32_t>(s->p->C->nrows, 1);
       } catch (const DsgError& e) {
         st = e.code;
         msg = e.msg;
@@ -359,6 +508,7 @@ void executor_main(DServer* s) {
         msg = "unexpected internal error";
       }
     }
+    if (pq.g) query_finish(s, pq);  // (an update that failed before its product step)
     const double t = now_ms();
     std::lock_guard<std::mutex> lk(s->mu);
     for (SReq* r : g->reqs) {
@@ -368,13 +518,9 @@ void executor_main(DServer* s) {
       finish(s, r, st, t);
     }
     if (st == DSG_OK) {
-      if (g->kind == 0) {
-        s->update_groups++;
-        if (ws >= 0) s->ws_per_entry = 0.5 * s->ws_per_entry + 0.5 * ws;
-        if (rb >= 0) s->row_bytes = rb;
-      } else {
-        s->query_groups++;
-      }
+      s->update_groups++;
+      if (ws >= 0) s->ws_per_entry = 0.5 * s->ws_per_entry + 0.5 * ws;
+      if (rb >= 0) s->row_bytes = rb;
     } else if (s->failed == DSG_OK) {
       s->failed = (dsg_status)st;
       s->failure = msg;
@@ -386,6 +532,7 @@ void executor_main(DServer* s) {
     s->cv_done.notify_all();
     if (s->failed != DSG_OK) s->cv_arrive.notify_all();
   }
+  if (pq.g) query_finish(s, pq);
 }
 
 void check_entries(const DMat* m, const int32_t* rows, const int32_t* cols, const uint8_t* ops, int64_t n) {
@@ -432,6 +579,10 @@ DServer* server_create(Ctx* c, DProd* p, const dsg_server_cfg* cfg) {
   s->cfg.slots = std::min(s->cfg.slots, 8);
   try {
     DSG_HIP(hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking));
+    DSG_HIP(hipStreamCreateWithFlags(&s->qstream, hipStreamNonBlocking));
+    DSG_HIP(hipEventCreateWithFlags(&s->c_ready, hipEventDisableTiming));
+    DSG_HIP(hipEventCreateWithFlags(&s->q_done, hipEventDisableTiming));
+    DSG_HIP(hipEventRecord(s->c_ready, c->stream));
     s->slots.resize((size_t)s->cfg.slots);
     for (Slot& sl : s->slots) DSG_HIP(hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming));
     // the product's workspaces at their largest before requests arrive
@@ -443,6 +594,9 @@ DServer* server_create(Ctx* c, DProd* p, const dsg_server_cfg* cfg) {
     for (Slot& sl : s->slots)
       if (sl.copied) (void)hipEventDestroy(sl.copied);
     if (s->copy) (void)hipStreamDestroy(s->copy);
+    if (s->qstream) (void)hipStreamDestroy(s->qstream);
+    if (s->c_ready) (void)hipEventDestroy(s->c_ready);
+    if (s->q_done) (void)hipEventDestroy(s->q_done);
     delete s;
     throw;
   }
@@ -461,13 +615,19 @@ void server_destroy(DServer* s) {
   s->executor.join();
   (void)hipStreamSynchronize(s->c->stream);
   (void)hipStreamSynchronize(s->copy);
+  (void)hipStreamSynchronize(s->qstream);
   for (Slot& sl : s->slots) {
     if (sl.host) (void)hipHostFree(sl.host);
     ctx_free(s->c, sl.dev, sl.dev_bytes);
     if (sl.copied) (void)hipEventDestroy(sl.copied);
   }
   gather_bufs_free(s->c, s->gather);
+  if (s->q_col_h) (void)hipHostFree(s->q_col_h);
+  if (s->q_val_h) (void)hipHostFree(s->q_val_h);
   (void)hipStreamDestroy(s->copy);
+  (void)hipStreamDestroy(s->qstream);
+  (void)hipEventDestroy(s->c_ready);
+  (void)hipEventDestroy(s->q_done);
   for (auto& kv : s->reqs) delete kv.second;
   s->p->refs--;
   delete s;
