@@ -104,21 +104,31 @@ __device__ inline int64_t log_index(const uint64_t* key, int64_t lo, int64_t hi,
 }
 
 // ---- 1. product counts per changed entry ----
-__global__ void k_term_counts(Log L, int cbits, const int32_t* a_len, const int32_t* t_len, int64_t* cnt) {
+// Per changed entry u = (r, c): its products are, in this order, the a_cj of
+// row c of A', the entries (c, j) the batch deleted, and the a_ir of column r
+// of A'.  rng[u] keeps the log range of row c and the count of its deletions
+// for the products' writer.
+__global__ void k_term_counts(Log L, int cbits, const int32_t* a_len, const int32_t* t_len, int64_t* cnt,
+                              int4* rng) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= L.n) return;
   int64_t c = 0;
+  int4 g = make_int4(0, 0, 0, 0);
   if (L.code[u] != UPD_NOP && L.code[u] != UPD_LOST) {
     const uint64_t cmask = (1ull << cbits) - 1;
     const int32_t r = (int32_t)(L.key[u] >> cbits), col = (int32_t)(L.key[u] & cmask);
     // left factor: row col of A', plus its deleted entries
     const uint64_t k0 = (uint64_t)col << cbits;
     int64_t e = log_lower(L.key, L.n, k0);
+    g.x = (int32_t)e;
     int64_t ndel = 0;
     for (; e < L.n && (L.key[e] >> cbits) == (uint64_t)col; ++e) ndel += L.code[e] == UPD_DEL;
+    g.y = (int32_t)e;
+    g.z = (int32_t)ndel;
     c = (int64_t)a_len[col] + ndel + (int64_t)t_len[r];
   }
   cnt[u] = c;
+  rng[u] = g;
 }
 
 // The changed keys of the log in a hash set (open addressing, all ones when
@@ -158,36 +168,56 @@ __device__ inline bool keyset_has(const KeySet& H, uint64_t k) {
   }
 }
 
-// ---- 2. write the products: one wavefront per changed entry ----
+// ---- 2. write the products: one thread per product ----
+// Product t belongs to the last entry u with off[u] <= t (entries without
+// products have none of them).  A wavefront's 64 products mostly share one
+// entry, so the wavefront first finds the entries of its first and last
+// product (same addresses in every lane) and a lane searches further only
+// between those two.  Work is even however long the rows and columns of the
+// changed entries are.
+__device__ inline int64_t entry_of(const int64_t* off, int64_t lo, int64_t hi, int64_t t) {
+  // last u in [lo, hi) with off[u] <= t (off[lo] <= t holds)
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 template <int SR>
-__global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, Mat A, Mat T, const int64_t* base,
-                                                    uint64_t* tkey, uint64_t* told, uint64_t* tnew, uint8_t* tfl) {
+__global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, Mat A, Mat T, const int64_t* off,
+                                                    const int4* rng, int64_t nterm, uint64_t* tkey, uint64_t* told,
+                                                    uint64_t* tnew, uint8_t* tfl) {
   using S = Sem<SR>;
   using V = typename S::V;
-  const int64_t u = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
-  if (u >= L.n) return;
+  const int64_t t0 = t - lane;
+  if (t0 >= nterm) return;
+  const int64_t t1 = std::min<int64_t>(t0 + 63, nterm - 1);
+  const int64_t u0 = entry_of(off, 0, L.n, t0);
+  const int64_t u1 = entry_of(off, u0, L.n, t1);
+  if (t >= nterm) return;
+  const int64_t u = u0 == u1 ? u0 : entry_of(off, u0, u1 + 1, t);
   const uint8_t code = L.code[u];
-  if (code == UPD_NOP || code == UPD_LOST) return;
   const uint64_t cmask = (1ull << cbits) - 1;
   const uint64_t dk = L.key[u];
   const int32_t r = (int32_t)(dk >> cbits), c = (int32_t)(dk & cmask);
   const bool op = code != UPD_INS, np = code != UPD_DEL;  // entry present before / after
   const V vo = rawv<V>(L.old[u]), vn = rawv<V>(L.nw[u]);
-  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
-  int64_t o = base[u];
-  // left factor (i = r, k = c): products a_rc * a_cj
-  const int64_t lo = log_lower(L.key, L.n, (uint64_t)c << cbits);
-  const int64_t hi = log_lower(L.key, L.n, ((uint64_t)c + 1) << cbits);
-  const int64_t ac = A.off[c];
+  const int64_t q = t - off[u];
   const int32_t al = A.len[c];
-  for (int32_t t = lane; t < al; t += 64) {
-    const int32_t j = A.col[ac + t];
-    const V bn = ldv<V>(A.val, ac + t);
+  const int4 g = rng[u];
+  if (q < al) {
+    // left factor (i = r, k = c): a_rc * a_cj
+    const int64_t ac = A.off[c] + q;
+    const int32_t j = A.col[ac];
+    const V bn = ldv<V>(A.val, ac);
     bool bop = true;
     V bo = bn;
-    if (hi > lo) {
-      const int64_t e = log_index(L.key, lo, hi, ((uint64_t)c << cbits) | (uint64_t)(uint32_t)j);
+    if (g.y > g.x) {
+      const int64_t e = log_index(L.key, g.x, g.y, ((uint64_t)c << cbits) | (uint64_t)(uint32_t)j);
       if (e >= 0) {
         const uint8_t ce = L.code[e];
         if (ce == UPD_INS) bop = false;
@@ -195,42 +225,38 @@ __global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, 
       }
     }
     const uint8_t f = (op && bop ? F_OLD : 0) | (np ? F_NEW : 0);
-    tkey[o + t] = ((uint64_t)(uint32_t)r << cbits) | (uint64_t)(uint32_t)j;
-    told[o + t] = (f & F_OLD) ? (uint64_t)S::mul(vo, bo) : 0ull;
-    tnew[o + t] = (f & F_NEW) ? (uint64_t)S::mul(vn, bn) : 0ull;
-    tfl[o + t] = f;
-  }
-  o += al;
-  // entries (c, j) this batch deleted: a_rc * a_cj existed only before
-  for (int64_t e0 = lo; e0 < hi; e0 += 64) {
-    const int64_t e = e0 + lane;
-    const bool del = e < hi && L.code[e] == UPD_DEL;
-    const uint64_t b = __ballot(del);
-    if (del) {
-      const int64_t q = o + __popcll(b & lt);
+    tkey[t] = ((uint64_t)(uint32_t)r << cbits) | (uint64_t)(uint32_t)j;
+    told[t] = (f & F_OLD) ? (uint64_t)S::mul(vo, bo) : 0ull;
+    tnew[t] = (f & F_NEW) ? (uint64_t)S::mul(vn, bn) : 0ull;
+    tfl[t] = f;
+  } else if (q < (int64_t)al + g.z) {
+    // entries (c, j) this batch deleted: a_rc * a_cj existed only before.
+    // The first of these products writes them all, in log order.
+    if (q != al) return;
+    int64_t w = t;
+    for (int64_t e = g.x; e < g.y; ++e) {
+      if (L.code[e] != UPD_DEL) continue;
       const int32_t j = (int32_t)(L.key[e] & cmask);
-      tkey[q] = ((uint64_t)(uint32_t)r << cbits) | (uint64_t)(uint32_t)j;
-      told[q] = op ? (uint64_t)S::mul(vo, rawv<V>(L.old[e])) : 0ull;
-      tnew[q] = 0ull;
-      tfl[q] = op ? F_OLD : 0;
+      tkey[w] = ((uint64_t)(uint32_t)r << cbits) | (uint64_t)(uint32_t)j;
+      told[w] = op ? (uint64_t)S::mul(vo, rawv<V>(L.old[e])) : 0ull;
+      tnew[w] = 0ull;
+      tfl[w] = op ? F_OLD : 0;
+      ++w;
     }
-    o += __popcll(b);
-  }
-  // right factor (k = r, j = c): products a_ir * a_rc over column r of A'
-  const int64_t tc = T.off[r];
-  const int32_t tl = T.len[r];
-  for (int32_t t = lane; t < tl; t += 64) {
-    const int32_t i = T.col[tc + t];
-    const V a = ldv<V>(T.val, tc + t);
+  } else {
+    // right factor (k = r, j = c): a_ir * a_rc over column r of A'
+    const int64_t tc = T.off[r] + (q - al - g.z);
+    const int32_t i = T.col[tc];
+    const V a = ldv<V>(T.val, tc);
     // (i, r) changed too: that entry's left-factor products include this
     // one, which stays in the list with no effect (its key (i, c) is among
     // those products' keys, so it adds no entry of C)
     const bool dup = keyset_has(H, ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)r);
     const uint8_t f = dup ? 0 : (op ? F_OLD : 0) | (np ? F_NEW : 0);
-    tkey[o + t] = ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)c;
-    told[o + t] = (f & F_OLD) ? (uint64_t)S::mul(a, vo) : 0ull;
-    tnew[o + t] = (f & F_NEW) ? (uint64_t)S::mul(a, vn) : 0ull;
-    tfl[o + t] = f;
+    tkey[t] = ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)c;
+    told[t] = (f & F_OLD) ? (uint64_t)S::mul(a, vo) : 0ull;
+    tnew[t] = (f & F_NEW) ? (uint64_t)S::mul(a, vn) : 0ull;
+    tfl[t] = f;
   }
 }
 
@@ -509,16 +535,18 @@ const int64_t* count_terms(DProd* p) {
   const int cbits = bits_for(A->ncols);
   Log L{A->log_key, A->log_old, A->log_new, A->log_code, A->h_log_n};
   const int64_t nU = L.n;
-  const size_t b1 = Carve::need({(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64});
+  const size_t b1 = Carve::need(
+      {(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64, (size_t)(nU + 1) * 16});
   Carve cv1(ctx_scratch2(c, b1), b1);
   int64_t* cnt = cv1.take<int64_t>(nU + 1);
   int64_t* off = cv1.take<int64_t>(nU + 1);
   void* scan1 = cv1.take<char>(scan_scratch_bytes(nU + 1) + 64);
   int64_t* d_total = cv1.take<int64_t>(8);
+  int4* rng = cv1.take<int4>(nU + 1);
   if (nU > 0) {
     Phase ph(c, "entry_count");
     hipLaunchKernelGGL(k_term_counts, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, cbits, (const int32_t*)A->row_len,
-                       (const int32_t*)T->row_len, cnt);
+                       (const int32_t*)T->row_len, cnt, rng);
     exclusive_scan_i64(cnt, off, nU, d_total, scan1, s);
   } else {
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, d_total);
@@ -549,12 +577,14 @@ int32_t entry_update(DProd* p) {
   // the counts of step 1 (count_terms), still in the second scratch
   Log L{A->log_key, A->log_old, A->log_new, A->log_code, p->entry_nU};
   const int64_t nU = L.n;
-  const size_t b1 = Carve::need({(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64});
+  const size_t b1 = Carve::need(
+      {(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64, (size_t)(nU + 1) * 16});
   Carve cv1(ctx_scratch2(c, b1), b1);
   (void)cv1.take<int64_t>(nU + 1);
   int64_t* off = cv1.take<int64_t>(nU + 1);
   (void)cv1.take<char>(scan_scratch_bytes(nU + 1) + 64);
   int64_t* d_total = cv1.take<int64_t>(8);
+  const int4* rng = cv1.take<int4>(nU + 1);
   const int64_t nterm = p->entry_nterm;
   // counters: [0] rows of C with changed products, [3] lost entries, [12]
   // reported rows
@@ -607,8 +637,8 @@ int32_t entry_update(DProd* p) {
       Phase ph(c, "entry_terms");
       hipLaunchKernelGGL(k_keyset_clear, dim3(std::min<unsigned>(blocks_for(hs, 256), 1024)), dim3(256), 0, s, H);
       hipLaunchKernelGGL(k_keyset_fill, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, H);
-      hipLaunchKernelGGL((k_term_write<SR>), dim3(blocks_for(nU * 64, 256)), dim3(256), 0, s, L, H, cbits, view(A),
-                         view(T), (const int64_t*)off, tkey, told, tnew, tfl);
+      hipLaunchKernelGGL((k_term_write<SR>), dim3(blocks_for(nterm, 256)), dim3(256), 0, s, L, H, cbits, view(A),
+                         view(T), (const int64_t*)off, rng, nterm, tkey, told, tnew, tfl);
       hipLaunchKernelGGL(k_iota_u32, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tidx, nterm);
     }
     // ---- 3. sort, segments, one update per entry of C ----
