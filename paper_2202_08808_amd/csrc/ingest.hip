@@ -1277,8 +1277,6 @@ Work carve_work(void* base, int64_t n, bool deltas) {
   return w;
 }
 
-__global__ void k_bump_epoch(uint32_t* e) { *e += 1; }
-
 // Entries of the rows an apply touches, before it changes them (the rows its
 // plan streams): one atomic per workgroup.
 __global__ __launch_bounds__(256) void k_touched_len(const int32_t* urow, const int64_t* d_nR, const int32_t* row_len,
@@ -1292,10 +1290,12 @@ __global__ __launch_bounds__(256) void k_touched_len(const int32_t* urow, const 
   if (threadIdx.x == 0 && sum) atomicAdd(acc, sum);
 }
 __global__ void k_zero_u64(unsigned long long* a) { *a = 0; }
-__global__ void k_zero_counters(unsigned long long* a, unsigned long long* b, int* c) {
+// The apply's counters cleared and the matrix's epoch advanced, in one launch.
+__global__ void k_zero_counters(unsigned long long* a, unsigned long long* b, int* c, uint32_t* epoch) {
   *a = 0;
   *b = 0;
   *c = 0;
+  *epoch += 1;
 }
 
 // The transpose deltas of a planned apply (what k_commit / k_commit_heavy
@@ -1421,13 +1421,12 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
     DSG_HIP(hipGetLastError());
     return;
   }
-  if (!presorted) radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s);
+  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(1), 0, s, w.demand, w.ndelta, w.err, m->d_epoch);
+  if (!presorted) radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s, w.err);
   unsigned nb = blocks_for(n, 256);
   hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, s, w.keys, n, cbits, sentinel, w.kh, w.rh);
   exclusive_scan_i64(w.kh, w.ukpos, n, w.nU, w.scan, s);
   exclusive_scan_i64(w.rh, w.urpos, n, w.nR, w.scan, s);
-  hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(1), 0, s, w.demand, w.ndelta, w.err);
-  hipLaunchKernelGGL(k_bump_epoch, dim3(1), dim3(1), 0, s, m->d_epoch);
   int vsz = m->vsz;
   if (vsz == 8)
     hipLaunchKernelGGL(k_fold<8>, dim3(nb), dim3(256), 0, s, w.keys, w.idx, n, cbits, ops, vals, w.kh,

@@ -3,7 +3,12 @@
 // Block-level scans use 64-wide wavefront shuffles plus one LDS slot per
 // wave.  Radix sort ranks keys inside a tile with a wavefront multi-split
 // (8 ballots build the set of lanes holding the same digit), which keeps the
-// sort stable without per-digit loops.
+// sort stable without per-digit loops.  The digit histograms of every pass
+// are counted in one launch up front; each pass is then one launch whose
+// tiles find the keys of their digit in the tiles before them by a
+// decoupled look-back (each tile publishes its count, then its inclusive
+// prefix, per digit, in one status word), so a sort of p passes takes p + 2
+// launches instead of three per pass.
 #include "internal.h"
 #include "kernel_common.h"
 
@@ -289,6 +294,139 @@ __global__ __launch_bounds__(RS_NT) void k_rs_scatter(const uint64_t* kin, const
   }
 }
 
+// ---- single-sweep passes ----
+// Status word of (tile, digit): 0 while unknown, LB_AGG | the tile's own count
+// of the digit, then LB_PRE | the count over this tile and all before it.
+constexpr uint32_t LB_AGG = 1u << 30, LB_PRE = 2u << 30, LB_CNT = LB_AGG - 1;
+constexpr int RS_MAX_PASSES = 8;
+constexpr int64_t RS_SWEEP_MAX = (int64_t)LB_CNT;  // counts fit the status word's 30 bits
+// polls of a predecessor's status before the sort gives up (tiles start in
+// ticket order, so a predecessor is running and publishes within microseconds)
+constexpr uint32_t RS_SPIN_MAX = 1u << 24;
+
+__global__ void k_rs_zero(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// digit histograms of every pass, summed over the whole input into g[pass][256]
+__global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const uint64_t* keys, int64_t n, int passes, uint32_t* g) {
+  __shared__ uint32_t h[RS_MAX_PASSES][256];
+  for (int p = 0; p < passes; ++p) h[p][threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  for (int t = 0; t < RS_ITEMS; ++t) {
+    const int64_t i = base + t * RS_NT + threadIdx.x;
+    if (i < n) {
+      const uint64_t k = keys[i];
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255], 1u);
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p)
+    if (h[p][threadIdx.x]) atomicAdd(&g[p * 256 + threadIdx.x], h[p][threadIdx.x]);
+}
+
+// One pass: tile t (taken from a ticket, so tiles start in input order)
+// ranks its keys by digit, publishes its per-digit counts, adds those of the
+// tiles before it, and scatters.  It also clears the status words of the
+// pass before it (`clr`, n_clr words) for the pass after it.
+__global__ __launch_bounds__(RS_NT) void k_rs_sweep(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                     uint32_t* vout, int64_t n, int shift, const uint32_t* ghist,
+                                                     uint32_t* ticket, uint32_t* st, uint32_t* clr, int64_t n_clr,
+                                                     int64_t ntiles, int* err) {
+  __shared__ int32_t wcount[RS_WAVES][256];
+  __shared__ uint32_t base_of[256];
+  __shared__ uint32_t lds_scan[RS_WAVES];
+  __shared__ uint32_t tile_s;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int d0 = threadIdx.x;  // RS_NT == 256 digits
+  if (threadIdx.x == 0) tile_s = atomicAdd(ticket, 1u);
+  for (int d = threadIdx.x; d < RS_WAVES * 256; d += RS_NT) (&wcount[0][0])[d] = 0;
+  __syncthreads();
+  const int64_t t = tile_s;
+  for (int64_t x = t * RS_NT + threadIdx.x; x < n_clr; x += ntiles * RS_NT) clr[x] = 0u;
+  const int64_t seg = t * RS_TILE + (int64_t)w * (64 * RS_ITEMS);
+  uint64_t k[RS_ITEMS];
+  uint32_t v[RS_ITEMS];
+  int32_t rank[RS_ITEMS];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const int64_t i = seg + r * 64 + lane;
+    const bool act = i < n;
+    k[r] = act ? kin[i] : 0;
+    v[r] = act ? vin[i] : 0;
+    const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+    uint64_t peers = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(act && bit);
+      peers &= bit ? m : ~m;
+    }
+    const int before = __popcll(peers & lt);
+    const int32_t base = act ? wcount[w][d] : 0;
+    __builtin_amdgcn_wave_barrier();
+    if (act && before == 0) wcount[w][d] = base + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    rank[r] = base + before;
+  }
+  __syncthreads();
+  // this tile's count of digit d0, and the waves' offsets inside the tile
+  uint32_t mine = 0;
+  for (int ww = 0; ww < RS_WAVES; ++ww) {
+    const int32_t c = wcount[ww][d0];
+    wcount[ww][d0] = (int32_t)mine;
+    mine += (uint32_t)c;
+  }
+  // keys of digit d0 in the tiles before this one (decoupled look-back)
+  uint32_t* my = st + t * 256 + d0;
+  uint32_t excl = 0;
+  if (t == 0) {
+    __hip_atomic_store(my, LB_PRE | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(my, LB_AGG | mine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int64_t j = t - 1; j >= 0; --j) {
+      const uint32_t* q = st + j * 256 + d0;
+      uint32_t sv = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint32_t spins = 0;
+      while (sv == 0u && ++spins < RS_SPIN_MAX) {
+        __builtin_amdgcn_s_sleep(1);
+        sv = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (sv == 0u) {  // never published: report it, and end the walk
+        if (err) atomicOr(err, 16);
+        break;
+      }
+      excl += sv & LB_CNT;
+      if (sv & LB_PRE) break;
+    }
+    __hip_atomic_store(my, LB_PRE | (excl + mine), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // first output position of digit d0 over the whole input
+  const uint32_t gc = ghist[d0];
+  uint32_t x = gc;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds_scan[w] = x;
+  __syncthreads();
+  uint32_t wbase = 0;
+  for (int ww = 0; ww < w; ++ww) wbase += lds_scan[ww];
+  base_of[d0] = wbase + x - gc + excl;
+  __syncthreads();
+  for (int r = 0; r < RS_ITEMS; ++r) {
+    const int64_t i = seg + r * 64 + lane;
+    if (i < n) {
+      const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+      const int64_t pos = (int64_t)base_of[d] + wcount[w][d] + rank[r];
+      kout[pos] = k[r];
+      vout[pos] = v[r];
+    }
+  }
+}
+
 __global__ void k_copy_pairs(const uint64_t* ks, const uint32_t* vs, uint64_t* kd, uint32_t* vd, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -466,12 +604,15 @@ __global__ __launch_bounds__(MID_NT) void k_mid_sort(uint64_t* keys, uint32_t* v
 
 size_t radix_scratch_bytes(int64_t n) {
   int64_t ntiles = (n + RS_TILE - 1) / RS_TILE + 1;
-  return Carve::need({(size_t)n * 8, (size_t)n * 4, (size_t)(256 * ntiles) * 8,
-                      scan_scratch_bytes(256 * ntiles)});
+  // ping-pong pairs; the multi-launch passes' tile counts and their scan, or
+  // the single-sweep histograms, tickets and two status regions
+  return Carve::need({(size_t)n * 8, (size_t)n * 4,
+                      std::max((size_t)(256 * ntiles) * 8 + scan_scratch_bytes(256 * ntiles) + 256,
+                               (size_t)(RS_MAX_PASSES * 256 + 64 + 2 * 256 * ntiles) * 4 + 256)});
 }
 
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, void* scratch,
-                      hipStream_t s) {
+                      hipStream_t s, int* err) {
   if (n <= 1 || key_bits <= 0) return;
   if (n <= MID_SORT && key_bits <= MID_KEY_BITS) {
     hipLaunchKernelGGL(k_mid_sort, dim3(1), dim3(MID_NT), 0, s, keys, vals, (int)n);
@@ -487,13 +628,37 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, v
   Carve cv(scratch, radix_scratch_bytes(n));
   uint64_t* k2 = cv.take<uint64_t>(n);
   uint32_t* v2 = cv.take<uint32_t>(n);
-  int64_t* counts = cv.take<int64_t>(256 * ntiles + 1);
-  void* sscr = cv.take<char>(scan_scratch_bytes(256 * ntiles));
   uint64_t* ka = keys;
   uint32_t* va = vals;
   uint64_t* kb = k2;
   uint32_t* vb = v2;
   int passes = (key_bits + 7) / 8;
+  if (n <= RS_SWEEP_MAX && passes <= RS_MAX_PASSES) {
+    uint32_t* ghist = cv.take<uint32_t>(RS_MAX_PASSES * 256);
+    uint32_t* tickets = cv.take<uint32_t>(64);
+    uint32_t* st[2] = {cv.take<uint32_t>(256 * ntiles), cv.take<uint32_t>(256 * ntiles)};
+    // the four takes are whole multiples of 256 bytes, so they lie end to end
+    const int64_t nz = (int64_t)(RS_MAX_PASSES * 256 + 64) + 2 * 256 * ntiles;
+    DSG_REQUIRE((char*)(st[1] + 256 * ntiles) == (char*)(ghist + nz), DSG_E_DEVICE, "internal: sort scratch layout");
+    hipLaunchKernelGGL(k_rs_zero, dim3((unsigned)std::min<int64_t>((nz + 255) / 256, 1024)), dim3(256), 0, s,
+                       ghist, nz);
+    hipLaunchKernelGGL(k_rs_hist_all, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, n, passes, ghist);
+    for (int p = 0; p < passes; ++p) {
+      // pass p uses region p % 2 and clears the other one, which pass p - 1
+      // used, for pass p + 1 (both start cleared)
+      uint32_t* clr = p >= 1 ? st[(p + 1) & 1] : nullptr;
+      hipLaunchKernelGGL(k_rs_sweep, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, va, kb, vb, n, 8 * p,
+                         ghist + 256 * p, tickets + p, st[p & 1], clr, clr ? 256 * ntiles : (int64_t)0, ntiles,
+                         err);
+      uint64_t* tk = ka; ka = kb; kb = tk;
+      uint32_t* tv = va; va = vb; vb = tv;
+    }
+    if (ka != keys)
+      hipLaunchKernelGGL(k_copy_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, ka, va, keys, vals, n);
+    return;
+  }
+  int64_t* counts = cv.take<int64_t>(256 * ntiles + 1);
+  void* sscr = cv.take<char>(scan_scratch_bytes(256 * ntiles));
   for (int p = 0; p < passes; ++p) {
     int shift = 8 * p;
     hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, n, shift, counts, ntiles);
