@@ -146,7 +146,15 @@ __device__ inline uint32_t key_hash(uint64_t k) {
   return (uint32_t)k;
 }
 
-__global__ void k_keyset_clear(KeySet H) {
+// The step's counters cleared and C's epoch noted, and (clear) the key set
+// emptied, in one launch.
+__global__ void k_entry_start(unsigned long long* ctr, int nctr, const uint32_t* epoch, uint32_t* ep_before,
+                              KeySet H, bool clear) {
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < nctr) ctr[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) *ep_before = *epoch;
+  }
+  if (!clear) return;
   for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x <= H.mask; x += gridDim.x * blockDim.x) H.tab[x] = ~0ull;
 }
 
@@ -188,7 +196,7 @@ __device__ inline int64_t entry_of(const int64_t* off, int64_t lo, int64_t hi, i
 template <int SR>
 __global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, Mat A, Mat T, const int64_t* off,
                                                     const int4* rng, int64_t nterm, uint64_t* tkey, uint64_t* told,
-                                                    uint64_t* tnew, uint8_t* tfl) {
+                                                    uint64_t* tnew, uint8_t* tfl, uint32_t* tidx) {
   using S = Sem<SR>;
   using V = typename S::V;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -199,6 +207,7 @@ __global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, 
   const int64_t u0 = entry_of(off, 0, L.n, t0);
   const int64_t u1 = entry_of(off, u0, L.n, t1);
   if (t >= nterm) return;
+  tidx[t] = (uint32_t)t;  // the sort's values: the products' positions
   const int64_t u = u0 == u1 ? u0 : entry_of(off, u0, u1 + 1, t);
   const uint8_t code = L.code[u];
   const uint64_t cmask = (1ull << cbits) - 1;
@@ -258,11 +267,6 @@ __global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, 
     tnew[t] = (f & F_NEW) ? (uint64_t)S::mul(a, vn) : 0ull;
     tfl[t] = f;
   }
-}
-
-__global__ void k_iota_u32(uint32_t* p, int64_t n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < n) p[t] = (uint32_t)t;
 }
 
 // ---- 3. segments of equal keys ----
@@ -467,8 +471,6 @@ __global__ __launch_bounds__(256) void k_lost_recompute(LostArgs L, const int32_
   }
 }
 
-__global__ void k_copy_u32(const uint32_t* src, uint32_t* dst) { *dst = *src; }
-
 __global__ void k_rows_after(int32_t n, const uint32_t* epoch, const uint32_t* since, uint8_t* flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) flags[i] = epoch[i] > *since ? 1 : 0;
@@ -480,10 +482,6 @@ __global__ void k_sync_both(uint32_t* sync, const uint32_t* e) {
 }
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
-
-__global__ void k_zero_n(unsigned long long* p, int n) {
-  for (int x = threadIdx.x; x < n; x += blockDim.x) p[x] = 0ull;
-}
 
 // phase timing (when the context records kernel times)
 struct Phase {
@@ -616,8 +614,8 @@ int32_t entry_update(DProd* p) {
   uint32_t* ep_before = (uint32_t*)cs.take<uint64_t>(8);
   void* sa_scr = cs.take<char>(sorted_add_scratch_bytes(NT));
   KeySet H{cs.take<uint64_t>(hs), hs - 1};
-  hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, s, ctr, 16);
-  hipLaunchKernelGGL(k_copy_u32, dim3(1), dim3(1), 0, s, (const uint32_t*)C->d_epoch, ep_before);
+  hipLaunchKernelGGL(k_entry_start, dim3(nterm > 0 ? std::min<unsigned>(blocks_for(hs, 256), 1024) : 1u), dim3(256),
+                     0, s, ctr, 16, (const uint32_t*)C->d_epoch, ep_before, H, nterm > 0);
 
   int64_t nseg = 0;
   if (nterm > 0) {
@@ -635,11 +633,9 @@ int32_t entry_update(DProd* p) {
     int64_t* seg_start = ct.take<int64_t>(NT + 1);
     {
       Phase ph(c, "entry_terms");
-      hipLaunchKernelGGL(k_keyset_clear, dim3(std::min<unsigned>(blocks_for(hs, 256), 1024)), dim3(256), 0, s, H);
       hipLaunchKernelGGL(k_keyset_fill, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, H);
       hipLaunchKernelGGL((k_term_write<SR>), dim3(blocks_for(nterm, 256)), dim3(256), 0, s, L, H, cbits, view(A),
-                         view(T), (const int64_t*)off, rng, nterm, tkey, told, tnew, tfl);
-      hipLaunchKernelGGL(k_iota_u32, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tidx, nterm);
+                         view(T), (const int64_t*)off, rng, nterm, tkey, told, tnew, tfl, tidx);
     }
     // ---- 3. sort, segments, one update per entry of C ----
     {

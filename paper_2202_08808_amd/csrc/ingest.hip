@@ -137,6 +137,8 @@ __global__ void k_fold(const uint64_t* keys, const uint32_t* idx, int64_t n, int
                        const int64_t* urpos, const int64_t* d_nU, const int64_t* d_nR, Uniq U) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) U.row_first[*d_nR] = (int32_t)*d_nU;
+  // the flat plan's per-row counts start at zero (at most n rows)
+  if (t < n) reinterpret_cast<int4*>(U.pcnt)[t] = make_int4(0, 0, 0, 0);
   if (t >= n || !kh[t]) return;
   uint64_t k = keys[t];
   int64_t u = ukpos[t];
@@ -1315,15 +1317,17 @@ __global__ void k_plan_deltas(Uniq U, const int64_t* d_nU, uint64_t cmask, int c
   store_raw<VSZ>(dval, u, U.fin[u]);
 }
 
-// Phases of one matrix's apply: PH_PLAN plans the unique updates (and, outside
-// graphs, reserves the room moved rows need, re-planning after a compaction);
-// PH_COMMIT commits them, writing the transpose deltas too unless they were
-// taken from the plan already (deltas_done).
-constexpr int PH_PLAN = 1, PH_COMMIT = 2;
+// Phases of one matrix's apply: PH_PLAN plans the unique updates; PH_ROOM
+// (outside graphs) reserves the room moved rows need, re-planning after a
+// compaction -- from the demand the caller already read back (demand0 >= 0)
+// or after reading it; PH_COMMIT commits them, writing the transpose deltas
+// too unless they were taken from the plan already (deltas_done).
+constexpr int PH_PLAN = 1, PH_COMMIT = 2, PH_ROOM = 4;
 
 template <int SR, int VSZ>
 void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, const void* vals, int tbits,
-                        bool graph, const Guard& G, int phases = PH_PLAN | PH_COMMIT, bool deltas_done = false) {
+                        bool graph, const Guard& G, int phases = PH_PLAN | PH_ROOM | PH_COMMIT,
+                        bool deltas_done = false, int64_t demand0 = -1) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   // plan and commit take the touched rows in turn: a grid of at most 32
@@ -1343,8 +1347,8 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
   } else if (phases & PH_PLAN) {
   // tables for the touched rows that have none, before the plan looks them up
   if (X.tab) {
+    // (the fold cleared the per-row counts)
     mat_index_build(m, w.U.urow, w.nR, n);
-    hipLaunchKernelGGL(k_zero_pcnt, dim3(nf), dim3(256), 0, s, w.U.pcnt, (const int64_t*)w.nR);
     hipLaunchKernelGGL((k_plan_flat<SR, VSZ>), dim3(nf), dim3(256), 0, s, *m, (const int64_t*)w.nU, cmask, w.idx,
                        vals, w.U, G, X);
   }
@@ -1352,12 +1356,18 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
                      w.demand, G, X);
   hipLaunchKernelGGL((k_plan_heavy<SR, VSZ>), dim3(nph), dim3(HEAVY_WG), 0, s, *m, w.nR, cmask, w.idx, vals, w.U,
                      w.demand, G, X);
-  if (!graph) {
+  }
+  if ((phases & PH_ROOM) && !graph && !G.known_slot) {
     // the one host round trip: how much pool space moved rows need
     unsigned long long* h = (unsigned long long*)c->pinned;
     for (;;) {
-      DSG_HIP(hipMemcpyAsync(h, w.demand, 8, hipMemcpyDeviceToHost, s));
-      DSG_HIP(hipStreamSynchronize(s));
+      if (demand0 >= 0) {
+        h[0] = (unsigned long long)demand0;
+        demand0 = -1;
+      } else {
+        DSG_HIP(hipMemcpyAsync(h, w.demand, 8, hipMemcpyDeviceToHost, s));
+        DSG_HIP(hipStreamSynchronize(s));
+      }
       const int64_t demand = (int64_t)h[0];
       if (demand == 0) break;
       const uint64_t version = m->version;
@@ -1381,7 +1391,6 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
                          w.U, w.demand, G, X);
     }
   }
-  }
   if (!(phases & PH_COMMIT)) return;
   // (graph mode: the caller reserved the worst case, see apply_headroom)
   uint64_t* dk = deltas_done ? nullptr : w.dkey;
@@ -1402,8 +1411,8 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
 // phases as launch_plan_commit (sorting, folding and the epoch bump belong to
 // the plan).
 void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint8_t* ops, const void* vals,
-              bool graph, bool presorted = false, const Guard& G = Guard(), int phases = PH_PLAN | PH_COMMIT,
-              bool deltas_done = false) {
+              bool graph, bool presorted = false, const Guard& G = Guard(),
+              int phases = PH_PLAN | PH_ROOM | PH_COMMIT, bool deltas_done = false, int64_t demand0 = -1) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   int cbits = bits_for(m->ncols);
@@ -1411,12 +1420,15 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
   uint64_t cmask = (1ull << cbits) - 1;
   int tbits = bits_for(m->nrows);
   if (!(phases & PH_PLAN)) {
+    const int ph = phases;
+    const bool dd = deltas_done;
+    const int64_t d0 = demand0;
     switch (m->sr) {
-      case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
-      case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
-      case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
-      case 3: launch_plan_commit<3, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
-      default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph, G, PH_COMMIT, deltas_done); break;
+      case 0: launch_plan_commit<0, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G, ph, dd, d0); break;
+      case 1: launch_plan_commit<1, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G, ph, dd, d0); break;
+      case 2: launch_plan_commit<2, 8>(m, w, n, cmask, cbits, vals, tbits, graph, G, ph, dd, d0); break;
+      case 3: launch_plan_commit<3, 4>(m, w, n, cmask, cbits, vals, tbits, graph, G, ph, dd, d0); break;
+      default: launch_plan_commit<-1, 0>(m, w, n, cmask, cbits, vals, tbits, graph, G, ph, dd, d0); break;
     }
     DSG_HIP(hipGetLastError());
     return;
@@ -1425,8 +1437,7 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
   if (!presorted) radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s, w.err);
   unsigned nb = blocks_for(n, 256);
   hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, s, w.keys, n, cbits, sentinel, w.kh, w.rh);
-  exclusive_scan_i64(w.kh, w.ukpos, n, w.nU, w.scan, s);
-  exclusive_scan_i64(w.rh, w.urpos, n, w.nR, w.scan, s);
+  exclusive_scan_i64_pair(w.kh, w.ukpos, w.nU, w.rh, w.urpos, w.nR, n, w.scan, s);
   int vsz = m->vsz;
   if (vsz == 8)
     hipLaunchKernelGGL(k_fold<8>, dim3(nb), dim3(256), 0, s, w.keys, w.idx, n, cbits, ops, vals, w.kh,
@@ -1494,7 +1505,16 @@ void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const
   if (count_touched)
     hipLaunchKernelGGL(k_touched_len, dim3(nb), dim3(256), 0, s, (const int32_t*)wt->U.urow, (const int64_t*)wt->nR,
                        (const int32_t*)t->row_len, wt->demand + 2);
-  // a compaction of the transpose does not move the matrix: its plan stands
+  // one round trip for the room both plans need; then a compaction of either
+  // pool re-plans that matrix alone (the transpose's deltas do not depend on
+  // where the matrix's rows sit)
+  int64_t* hd = (int64_t*)((char*)m->ctx->pinned + 512);
+  DSG_HIP(hipMemcpyAsync(hd, w.demand, 8, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipMemcpyAsync(hd + 1, wt->demand, 8, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  const int64_t dm = hd[0], dt = hd[1];
+  run_core(m, w, n, kbits, false, d_ops, d_vals, false, false, Guard(), PH_ROOM, false, dm);
+  run_core(t, *wt, n, tk, true, w.dop, tvals, false, false, Guard(), PH_ROOM, false, dt);
   run_core(m, w, n, kbits, false, d_ops, d_vals, false, false, Guard(), PH_COMMIT, true);
   run_core(t, *wt, n, tk, true, w.dop, tvals, false, false, Guard(), PH_COMMIT);
 }

@@ -181,6 +181,10 @@ struct Carve {
 // Exclusive scan of n int64 values (in place allowed); total written to
 // *d_total (device) if not null.  Scratch: scan_scratch_bytes(n).
 size_t scan_scratch_bytes(int64_t n);
+// Two such scans of n values each (one launch when n is small; one scratch,
+// used by each in turn).
+void exclusive_scan_i64_pair(const int64_t* in0, int64_t* out0, int64_t* tot0, const int64_t* in1, int64_t* out1,
+                             int64_t* tot1, int64_t n, void* scratch, hipStream_t s);
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* d_total, void* scratch,
                         hipStream_t s);
 // Exclusive scan of int32 counts into int64 offsets.

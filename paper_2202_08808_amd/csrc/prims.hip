@@ -135,6 +135,35 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_wg(const In* in, int64_t* out,
   if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// two scans of the same length, one per workgroup, in one launch
+__global__ __launch_bounds__(SCAN_NT) void k_scan_wg_pair(const int64_t* in0, int64_t* out0, int64_t* tot0,
+                                                          const int64_t* in1, int64_t* out1, int64_t* tot1,
+                                                          int64_t n) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  const int64_t* in = blockIdx.x ? in1 : in0;
+  int64_t* out = blockIdx.x ? out1 : out0;
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += SCAN_TILE) {
+    int64_t v[SCAN_ITEMS];
+    int64_t s = 0;
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+      const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+      v[t] = i < n ? in[i] : 0;
+      s += v[t];
+    }
+    int64_t tot;
+    int64_t run = carry + block_exclusive_scan<int64_t>(s, lds, tot);
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+      const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+      if (i < n) out[i] = run;
+      run += v[t];
+    }
+    carry += tot;
+  }
+  int64_t* total = blockIdx.x ? tot1 : tot0;
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
 template <class In>
 void scan_impl(const In* in, int64_t* out, int64_t n, int64_t* d_total, void* scratch, hipStream_t s) {
   if (n <= SCAN_TILE) {
@@ -454,6 +483,16 @@ size_t scan_scratch_bytes(int64_t n) {
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* d_total, void* scratch,
                         hipStream_t s) {
   scan_impl<int64_t>(in, out, n, d_total, scratch, s);
+}
+
+void exclusive_scan_i64_pair(const int64_t* in0, int64_t* out0, int64_t* tot0, const int64_t* in1, int64_t* out1,
+                             int64_t* tot1, int64_t n, void* scratch, hipStream_t s) {
+  if (n <= SCAN_WG_MAX) {
+    hipLaunchKernelGGL(k_scan_wg_pair, dim3(2), dim3(SCAN_NT), 0, s, in0, out0, tot0, in1, out1, tot1, n);
+    return;
+  }
+  scan_impl<int64_t>(in0, out0, n, tot0, scratch, s);
+  scan_impl<int64_t>(in1, out1, n, tot1, scratch, s);
 }
 
 void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* d_total,
