@@ -252,6 +252,7 @@ extern "C" dsg_status dsg_ctx_create(int device, void* hip_stream, size_t mem_bu
       c.own_stream = true;
     }
     DSG_HIP(hipHostMalloc(&c.pinned, 4096, hipHostMallocDefault));
+    DSG_HIP(hipHostGetDevicePointer(&c.pinned_dev, c.pinned, 0));
     noalloc_init(device);  // the allocation-free row export's staging array on this device
   } catch (const DsgError& e) {
     if (ctx) {

@@ -740,12 +740,12 @@ int32_t entry_update(DProd* p) {
     int32_t nchg;
   };
   Tail* ht = (Tail*)((char*)c->pinned + 3072);
-  DSG_HIP(hipMemcpyAsync(ht->ctr, ctr, 32, hipMemcpyDeviceToHost, s));
-  ht->ix_top[0] = ht->ix_top[1] = 0;
-  if (C->ix_top) DSG_HIP(hipMemcpyAsync(&ht->ix_top[0], C->ix_top, 8, hipMemcpyDeviceToHost, s));
-  if (A->ix_top) DSG_HIP(hipMemcpyAsync(&ht->ix_top[1], A->ix_top, 8, hipMemcpyDeviceToHost, s));
-  ht->nchg = 0;
-  if (n > 0) DSG_HIP(hipMemcpyAsync(&ht->nchg, d_nchg, 4, hipMemcpyDeviceToHost, s));
+  FetchList F;
+  F.add(ctr, 32, 3072 + (int32_t)offsetof(Tail, ctr));
+  F.add(C->ix_top, 8, 3072 + (int32_t)offsetof(Tail, ix_top));
+  F.add(A->ix_top, 8, 3072 + (int32_t)offsetof(Tail, ix_top) + 8);
+  F.add(n > 0 ? (const void*)d_nchg : nullptr, 4, 3072 + (int32_t)offsetof(Tail, nchg));
+  fetch_to_pinned(c, F, s);
   DSG_HIP(hipStreamSynchronize(s));
   mat_index_note_top(C, ht->ix_top[0]);
   mat_index_note_top(A, ht->ix_top[1]);

@@ -1650,8 +1650,10 @@ int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, co
                      d_nlost, (const int64_t*)w.nR, d_nrows);
   unsigned long long* h = (unsigned long long*)c->pinned;
   int* he = (int*)((char*)c->pinned + 64);
-  DSG_HIP(hipMemcpyAsync(h, d_nlost, 8, hipMemcpyDeviceToHost, s));
-  DSG_HIP(hipMemcpyAsync(he, w.err, 4, hipMemcpyDeviceToHost, s));
+  FetchList F;
+  F.add(d_nlost, 8, 0);
+  F.add(w.err, 4, 64);
+  fetch_to_pinned(c, F, s);
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(he[0] == 0, DSG_E_DEVICE, "internal: pool overflow while applying product updates");
   return (int64_t)h[0];
@@ -1705,6 +1707,13 @@ dsg_status validate_batch_device(DMat* m, const int32_t* d_rows, const int32_t* 
                                  int64_t n) {
   if (n == 0) return DSG_OK;
   Ctx* c = m->ctx;
+  if (validate_to_pinned(d_rows, d_cols, d_ops, n, m->nrows, m->ncols, c, 0)) {
+    DSG_HIP(hipStreamSynchronize(c->stream));
+    const int v = *(volatile int*)c->pinned;
+    if (v & 1) return DSG_E_RANGE;
+    if (v & 2) return DSG_E_ARG;
+    return DSG_OK;
+  }
   int* flags = (int*)ctx_scratch(c, 64);
   DSG_HIP(hipMemsetAsync(flags, 0, 4, c->stream));
   hipLaunchKernelGGL(k_validate, dim3(blocks_for(n, 256)), dim3(256), 0, c->stream, d_rows, d_cols, d_ops, n,
@@ -1746,11 +1755,13 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   }
   int* h = (int*)c->pinned;
   int64_t* hn = (int64_t*)((char*)c->pinned + 64);
-  h[1] = 0;
-  if (deltas) DSG_HIP(hipMemcpyAsync(h + 1, wt.err, 4, hipMemcpyDeviceToHost, s));
-  // a failed move (pool exhausted) would leave the batch half applied: report it loudly
-  DSG_HIP(hipMemcpyAsync(h, w.err, 4, hipMemcpyDeviceToHost, s));
-  DSG_HIP(hipMemcpyAsync(hn, w.nU, 8, hipMemcpyDeviceToHost, s));  // the log's length, in the same wait
+  // a failed move (pool exhausted) would leave the batch half applied: report
+  // it loudly; the log's length comes in the same wait
+  FetchList F;
+  F.add(w.err, 4, 0);
+  F.add(deltas ? (const void*)wt.err : nullptr, 4, 4);
+  F.add(w.nU, 8, 64);
+  fetch_to_pinned(c, F, s);
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(h[0] == 0 && h[1] == 0, DSG_E_DEVICE, "internal: pool overflow while applying a batch");
   m->h_log_n = *hn;

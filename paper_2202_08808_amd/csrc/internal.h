@@ -127,8 +127,10 @@ struct Ctx {
   std::string timing_phase;  // when not empty, only phases of this name are timed
   std::vector<KernelTiming> timings;
   std::vector<hipEvent_t> event_pool;
-  // pinned host staging block for small device->host reads
+  // pinned host staging block for small device->host reads (4 KB), and its
+  // device address, which kernels write to directly
   void* pinned = nullptr;
+  void* pinned_dev = nullptr;
   // reusable device scratch, grown on demand
   void* scratch = nullptr;
   size_t scratch_bytes = 0;
@@ -181,6 +183,30 @@ struct Carve {
 // Exclusive scan of n int64 values (in place allowed); total written to
 // *d_total (device) if not null.  Scratch: scan_scratch_bytes(n).
 size_t scan_scratch_bytes(int64_t n);
+// Small device values copied into the context's pinned block by one kernel
+// (in place of one copy each): up to 8 sources of 4-byte multiples, each to
+// its byte offset in the block; a null source writes zeros.  Read them after
+// the stream is synchronized.
+struct FetchList {
+  const void* src[8] = {};
+  int32_t bytes[8] = {};
+  int32_t off[8] = {};
+  int32_t n = 0;
+  void add(const void* p, int32_t nbytes, int32_t offset) {
+    src[n] = p;
+    bytes[n] = nbytes;
+    off[n] = offset;
+    ++n;
+  }
+};
+void fetch_to_pinned(Ctx* c, const FetchList& F, hipStream_t s);
+// Validity of a batch on the device (bit 0: an index out of range, bit 1: an
+// unknown op) written into the pinned block at byte offset `off` (n small:
+// one launch), or -1 when n is too large for that (the caller checks the
+// usual way).
+bool validate_to_pinned(const int32_t* rows, const int32_t* cols, const uint8_t* ops, int64_t n, int32_t nrows,
+                        int32_t ncols, Ctx* c, int32_t off);
+
 // Two such scans of n values each (one launch when n is small; one scratch,
 // used by each in turn).
 void exclusive_scan_i64_pair(const int64_t* in0, int64_t* out0, int64_t* tot0, const int64_t* in1, int64_t* out1,

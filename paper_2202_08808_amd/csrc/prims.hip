@@ -495,6 +495,45 @@ void exclusive_scan_i64_pair(const int64_t* in0, int64_t* out0, int64_t* tot0, c
   scan_impl<int64_t>(in1, out1, n, tot1, scratch, s);
 }
 
+__global__ void k_fetch(FetchList F, char* dst) {
+  const int i = threadIdx.x;
+  if (i >= F.n) return;
+  uint32_t* d = (uint32_t*)(dst + F.off[i]);
+  const uint32_t* p = (const uint32_t*)F.src[i];
+  for (int w = 0; w < F.bytes[i] / 4; ++w) d[w] = p ? p[w] : 0u;
+}
+
+void fetch_to_pinned(Ctx* c, const FetchList& F, hipStream_t s) {
+  if (F.n == 0) return;
+  hipLaunchKernelGGL(k_fetch, dim3(1), dim3(64), 0, s, F, (char*)c->pinned_dev);
+}
+
+constexpr int64_t VALIDATE_ONE_MAX = 1 << 16;
+
+// one workgroup checks the whole batch and writes the result itself
+__global__ __launch_bounds__(1024) void k_validate_one(const int32_t* rows, const int32_t* cols, const uint8_t* ops,
+                                                       int64_t n, int32_t nrows, int32_t ncols, int* out) {
+  __shared__ int bits;
+  if (threadIdx.x == 0) bits = 0;
+  __syncthreads();
+  int b = 0;
+  for (int64_t t = threadIdx.x; t < n; t += 1024) {
+    if (rows[t] < 0 || rows[t] >= nrows || cols[t] < 0 || cols[t] >= ncols) b |= 1;
+    if (ops[t] > DSG_OP_ADD) b |= 2;
+  }
+  if (b) atomicOr(&bits, b);
+  __syncthreads();
+  if (threadIdx.x == 0) *out = bits;
+}
+
+bool validate_to_pinned(const int32_t* rows, const int32_t* cols, const uint8_t* ops, int64_t n, int32_t nrows,
+                        int32_t ncols, Ctx* c, int32_t off) {
+  if (n > VALIDATE_ONE_MAX) return false;
+  hipLaunchKernelGGL(k_validate_one, dim3(1), dim3(1024), 0, c->stream, rows, cols, ops, n, nrows, ncols,
+                     (int*)((char*)c->pinned_dev + off));
+  return true;
+}
+
 void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64_t* d_total,
                                void* scratch, hipStream_t s) {
   scan_impl<int32_t>(in, out, n, d_total, scratch, s);
