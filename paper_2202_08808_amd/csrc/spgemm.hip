@@ -2202,16 +2202,21 @@ void launch_tail(DProd* p, ProdWork& w, int64_t nmax, bool set_sync = true) {
 // row kernels advance on the device (and, when given, one more device count
 // in the same wait).
 Plan read_plan(Ctx* c, ProdWork& w, DMat* C, const int64_t* d_extra = nullptr, int64_t* h_extra = nullptr) {
+  static_assert(sizeof(Plan) % 4 == 0 && sizeof(Plan) <= 2048, "pinned staging");
   Plan* hp = (Plan*)c->pinned;
   int64_t* htop = (int64_t*)((char*)c->pinned + 2048);
-  DSG_HIP(hipMemcpyAsync(hp, w.plan, sizeof(Plan), hipMemcpyDeviceToHost, c->stream));
-  DSG_HIP(hipMemcpyAsync(&hp->count, w.d_count, 4, hipMemcpyDeviceToHost, c->stream));
-  DSG_HIP(hipMemcpyAsync(htop, C->d_top, 8, hipMemcpyDeviceToHost, c->stream));
-  if (d_extra) DSG_HIP(hipMemcpyAsync(htop + 1, d_extra, 8, hipMemcpyDeviceToHost, c->stream));
+  FetchList F;
+  F.add(w.plan, (int32_t)sizeof(Plan), 0);
+  F.add(C->d_top, 8, 2048);
+  F.add(d_extra, 8, 2048 + 8);
+  F.add(w.d_count, 4, 2048 + 16);
+  fetch_to_pinned(c, F, c->stream);
   DSG_HIP(hipStreamSynchronize(c->stream));
   C->h_top_ub = *htop;
   if (h_extra) *h_extra = htop[1];
-  return *hp;
+  Plan plan = *hp;
+  plan.count = *(const int32_t*)(htop + 2);
+  return plan;
 }
 
 // Recompute the rows flagged for retry after growing C and the arena by
@@ -2303,11 +2308,13 @@ int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, con
   static_assert(1024 + sizeof(Tail) <= 4096, "pinned staging");
   auto read_tail = [&]() {
     launch_tail(p, w, std::max<int32_t>(plan.count, 1), false);
-    DSG_HIP(hipMemcpyAsync(&ht->nchg, w.d_nchg, 4, hipMemcpyDeviceToHost, s));
-    DSG_HIP(hipMemcpyAsync(&ht->err, w.err, 4, hipMemcpyDeviceToHost, s));
-    DSG_HIP(hipMemcpyAsync(&ht->c_short, &w.plan->c_short, 16, hipMemcpyDeviceToHost, s));
-    DSG_HIP(hipMemcpyAsync(&ht->c_top, C->d_top, 8, hipMemcpyDeviceToHost, s));
-    DSG_HIP(hipMemcpyAsync(ht->stats, w.stats, sizeof(ht->stats), hipMemcpyDeviceToHost, s));
+    FetchList F;
+    F.add(w.d_nchg, 4, 1024 + (int32_t)offsetof(Tail, nchg));
+    F.add(w.err, 4, 1024 + (int32_t)offsetof(Tail, err));
+    F.add(&w.plan->c_short, 16, 1024 + (int32_t)offsetof(Tail, c_short));
+    F.add(C->d_top, 8, 1024 + (int32_t)offsetof(Tail, c_top));
+    F.add(w.stats, (int32_t)sizeof(ht->stats), 1024 + (int32_t)offsetof(Tail, stats));
+    fetch_to_pinned(c, F, s);
     DSG_HIP(hipStreamSynchronize(s));
     C->h_top_ub = ht->c_top;
     return *ht;
