@@ -23,6 +23,11 @@
 namespace {
 
 constexpr int OUT_WORDS = 8;  // per product: k_publish's 6 words, apply error flags, spare
+// Rounds of worst-case growth a compaction of a graphed product's pools
+// leaves room for.  Graphed products are the small ones (C below
+// 2^batch_direct_log2 slots), so the room costs little memory, and fewer
+// compactions mean fewer captures.
+constexpr int64_t ROOM_ROUNDS = 16;
 
 __global__ void k_or_flags(const int* a, const int* b, int64_t* out) {
   int v = a ? *a : 0;
@@ -221,13 +226,13 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   for (size_t k = 0; k < sets.size(); ++k) {
     if (!graphed[(size_t)owner[k]]) continue;
     DMat* m = sets[k].m;
-    // (a compaction makes room for about four rounds: each one changes the
-    // pools the graph bakes in)
+    // (a compaction makes room for about ROOM_ROUNDS rounds: each one
+    // changes the pools the graph bakes in, and so forces a new capture)
     const int64_t hm = apply_headroom(m, sets[k].n);
-    mat_reserve(m, hm, 4 * hm);
+    mat_reserve(m, hm, ROOM_ROUNDS * hm);
     if (m->tidx) {
       const int64_t ht = apply_headroom(m->tidx, sets[k].n);
-      mat_reserve(m->tidx, ht, 4 * ht);
+      mat_reserve(m->tidx, ht, ROOM_ROUNDS * ht);
     }
     ensure_ws(c, b->aw, b->aw_bytes, k, apply_work_bytes(sets[k].n, m->tidx != nullptr), ws_changed);
     ensure_ws(c, b->awt, b->awt_bytes, k, apply_work_bytes(sets[k].n, false), ws_changed);
@@ -243,7 +248,7 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
     // dozen rounds.)
     const int64_t c_room = std::max<int64_t>(p->C->h_top_ub / 64, 2 * p->last_c_growth) + 4096;
     const size_t arena = std::max<size_t>(p->arena_bytes, (size_t)1 << 20);
-    prod_prepare_graph(p, c_room, arena, 4 * c_room);
+    prod_prepare_graph(p, c_room, arena, ROOM_ROUNDS * c_room);
     ensure_ws(c, b->pw, b->pw_bytes, j, prod_graph_work_bytes(p), ws_changed);
     c_top_before[j] = p->C->h_top_ub;
   }
