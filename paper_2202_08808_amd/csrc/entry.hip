@@ -584,8 +584,8 @@ int32_t entry_update(DProd* p) {
   int64_t* d_total = cv1.take<int64_t>(8);
   const int4* rng = cv1.take<int4>(nU + 1);
   const int64_t nterm = p->entry_nterm;
-  // counters: [0] rows of C with changed products, [3] lost entries, [12]
-  // reported rows
+  // counters: [0] rows of C with changed products, [3] lost entries, [5]
+  // the product sort's error flag, [12] reported rows
   st.terms = nterm;
 
   // ---- workspace for the products, the entry updates and the lost entries ----
@@ -640,7 +640,7 @@ int32_t entry_update(DProd* p) {
     // ---- 3. sort, segments, one update per entry of C ----
     {
       Phase ph(c, "entry_sort");
-      radix_sort_pairs(tkey, tidx, nterm, kbits, rscr, s);
+      radix_sort_pairs(tkey, tidx, nterm, kbits, rscr, s, (int*)(ctr + 5));
     }
     Phase ph(c, "entry_reduce");
     hipLaunchKernelGGL(k_seg_heads, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, tkey, nterm, head);
@@ -735,13 +735,13 @@ int32_t entry_update(DProd* p) {
   }
   hipLaunchKernelGGL(k_sync_both, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)A->d_epoch);
   struct Tail {
-    unsigned long long ctr[4];
+    unsigned long long ctr[6];
     unsigned long long ix_top[2];  // index pool tops of C and A
     int32_t nchg;
   };
   Tail* ht = (Tail*)((char*)c->pinned + 3072);
   FetchList F;
-  F.add(ctr, 32, 3072 + (int32_t)offsetof(Tail, ctr));
+  F.add(ctr, 48, 3072 + (int32_t)offsetof(Tail, ctr));
   F.add(C->ix_top, 8, 3072 + (int32_t)offsetof(Tail, ix_top));
   F.add(A->ix_top, 8, 3072 + (int32_t)offsetof(Tail, ix_top) + 8);
   F.add(n > 0 ? (const void*)d_nchg : nullptr, 4, 3072 + (int32_t)offsetof(Tail, nchg));
@@ -749,6 +749,7 @@ int32_t entry_update(DProd* p) {
   DSG_HIP(hipStreamSynchronize(s));
   mat_index_note_top(C, ht->ix_top[0]);
   mat_index_note_top(A, ht->ix_top[1]);
+  DSG_REQUIRE(ht->ctr[5] == 0, DSG_E_DEVICE, "internal: the product sort could not complete");
   st.affected_rows = (int64_t)ht->ctr[0];
   st.flops = nterm;
   st.changed_rows = ht->nchg;

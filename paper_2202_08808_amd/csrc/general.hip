@@ -682,7 +682,7 @@ int32_t general_update(DProd* p) {
     hipLaunchKernelGGL(k_pat_write, dim3(blocks_for(nL * 64, 256)), dim3(256), 0, s, LA, LB, rows_of(B), rows_of(T),
                        (const int64_t*)off, cb, keys);
     hipLaunchKernelGGL(k_iota_u32, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, idx, nterm);
-    radix_sort_pairs(keys, idx, nterm, rb + cb + 6, rscr, s);
+    radix_sort_pairs(keys, idx, nterm, rb + cb + 6, rscr, s, err);
     // C* and F*
     hipLaunchKernelGGL(k_pat_heads, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, keys, nterm, head);
     exclusive_scan_i64(head, segid, nterm, d_total, scan2, s);

@@ -342,12 +342,14 @@ void mat_export_device(DMat* m, int64_t* d_rp, int32_t* d_col, void* d_val, void
   const int64_t cap = std::max<int64_t>(std::min<int64_t>(nnz, EXPORT_CHUNK), most);
   int cbits = bits_for(m->ncols);
   size_t vs = (size_t)(m->vsz ? m->vsz : 4);
-  size_t need = Carve::need({(size_t)cap * 8, (size_t)cap * 4, (size_t)cap * vs, radix_scratch_bytes(cap)});
+  size_t need = Carve::need({(size_t)cap * 8, (size_t)cap * 4, (size_t)cap * vs, radix_scratch_bytes(cap), 64});
   Carve cv(ctx_scratch(c, need), need);
   uint64_t* keys = cv.take<uint64_t>(cap);
   uint32_t* pos = cv.take<uint32_t>(cap);
   char* vtmp = cv.take<char>((size_t)cap * vs);
   void* rs = cv.take<char>(radix_scratch_bytes(cap));
+  int* d_err = cv.take<int>(16);  // the sorts' error flag
+  DSG_HIP(hipMemsetAsync(d_err, 0, 4, s));
   uint64_t cmask = cbits >= 64 ? ~0ull : ((1ull << cbits) - 1);
   for (int32_t r0 = 0; r0 < n;) {
     int32_t r1 = r0 + 1;
@@ -364,7 +366,7 @@ void mat_export_device(DMat* m, int64_t* d_rp, int32_t* d_col, void* d_val, void
       else
         hipLaunchKernelGGL(k_export_keys<0>, dim3(nb), dim3(256), 0, s, r0, r1, m->row_off, m->row_len, m->col,
                            (const char*)m->val, d_rp, cbits, keys, pos, vtmp);
-      radix_sort_pairs(keys, pos, e, cbits + bits_for(r1 - r0), rs, s);
+      radix_sort_pairs(keys, pos, e, cbits + bits_for(r1 - r0), rs, s, d_err);
       unsigned gb = blocks_for(e, 256);
       char* ov = d_val ? (char*)d_val + (size_t)base * vs : nullptr;
       if (m->vsz == 8)
@@ -380,6 +382,10 @@ void mat_export_device(DMat* m, int64_t* d_rp, int32_t* d_col, void* d_val, void
     r0 = r1;
   }
   DSG_HIP(hipGetLastError());
+  int* h = (int*)c->pinned;
+  DSG_HIP(hipMemcpyAsync(h, d_err, 4, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipStreamSynchronize(s));
+  DSG_REQUIRE(h[0] == 0, DSG_E_DEVICE, "internal: the export's sort could not complete");
 }
 
 void mat_build_transpose(DMat* m) {

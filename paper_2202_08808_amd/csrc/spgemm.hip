@@ -2291,7 +2291,7 @@ int32_t prod_sequence(DProd* p, int mode, bool report_affected, ProdWork& w, con
     void* rs = dc.take<char>(radix_scratch_bytes(ndense));
     hipLaunchKernelGGL(k_flop_keys, dim3(blocks_for(ndense, 256)), dim3(256), 0, s, dl, (int32_t)ndense, w.flq, keys,
                        vals);
-    radix_sort_pairs(keys, vals, ndense, FLOP_KEY_BITS, rs, s);
+    radix_sort_pairs(keys, vals, ndense, FLOP_KEY_BITS, rs, s, w.err);
     DSG_HIP(hipMemcpyAsync(dl, vals, (size_t)ndense * 4, hipMemcpyDeviceToDevice, s));
   }
   std::vector<std::pair<int, size_t>> timed;
