@@ -402,31 +402,30 @@ __device__ inline void finish_entry(const LostArgs& L, int64_t e, unsigned long 
   }
 }
 
-// class flags of the lost entries by probe count
+// class of each lost entry by probe count: 0 (at most LOST_C0_MAX), 1 (at
+// most LOST_C1_MAX), 2 (more)
 __global__ void k_lost_classes(const uint64_t* key, int64_t n, int cbits, const int32_t* a_len, const int32_t* t_len,
-                               uint8_t* c0, uint8_t* c1, uint8_t* c2) {
+                               uint8_t* cls) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const uint64_t k = key[e];
   const int32_t d = a_len[(int32_t)(k >> cbits)];
   const int32_t lj = t_len[(int32_t)(k & ((1ull << cbits) - 1))];
   const int32_t cost = d < lj ? d : lj;
-  c0[e] = cost <= LOST_C0_MAX ? 1 : 0;
-  c1[e] = (cost > LOST_C0_MAX && cost <= LOST_C1_MAX) ? 1 : 0;
-  c2[e] = cost > LOST_C1_MAX ? 1 : 0;
+  cls[e] = cost <= LOST_C0_MAX ? 0 : cost <= LOST_C1_MAX ? 1 : 2;
 }
 
-// G lanes per lost entry; the listed entries taken in turn
+// G lanes per lost entry; the listed entries taken in turn by the nb blocks
+// of this part of the grid (b is the block's index within the part)
 template <int SR, int G>
-__global__ __launch_bounds__(256) void k_lost_recompute(LostArgs L, const int32_t* list, const int32_t* d_count) {
+__device__ inline void lost_recompute(const LostArgs& L, const int32_t* list, int64_t n, int64_t b, int64_t nb) {
   using V = typename Sem<SR>::V;
-  const int64_t n = *d_count;
   const int l = threadIdx.x & (G - 1);
-  const int64_t ng = ((int64_t)gridDim.x * blockDim.x) / G;
+  const int64_t ng = (nb * blockDim.x) / G;
   const uint64_t cmask = (1ull << L.cbits) - 1;
   // (the G lanes of a group share q0, so each group runs its rounds together
   // and its shuffles see all of its lanes)
-  for (int64_t q0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; q0 < n; q0 += ng) {
+  for (int64_t q0 = (b * blockDim.x + threadIdx.x) / G; q0 < n; q0 += ng) {
     const bool act = true;
     const int64_t e = list[q0];
     const int32_t i = (int32_t)(L.key[e] >> L.cbits);
@@ -469,6 +468,19 @@ __global__ __launch_bounds__(256) void k_lost_recompute(LostArgs L, const int32_
     }
     if (act && l == 0) finish_entry<SR>(L, e, acc, hits);
   }
+}
+
+// the three classes in one launch: blocks [0, nb0) take class 0 by groups of
+// 8 lanes, [nb0, nb0 + nb1) class 1 by groups of 32, the rest class 2 by
+// groups of 64
+template <int SR>
+__global__ __launch_bounds__(256) void k_lost_recompute(LostArgs L, const int32_t* l0, const int32_t* l1,
+                                                        const int32_t* l2, const int32_t* cnt, int64_t nb0,
+                                                        int64_t nb1) {
+  const int64_t b = blockIdx.x;
+  if (b < nb0) lost_recompute<SR, 8>(L, l0, cnt[0], b, nb0);
+  else if (b < nb0 + nb1) lost_recompute<SR, 32>(L, l1, cnt[1], b - nb0, nb1);
+  else lost_recompute<SR, 64>(L, l2, cnt[2], b - nb0 - nb1, (int64_t)gridDim.x - nb0 - nb1);
 }
 
 __global__ void k_rows_after(int32_t n, const uint32_t* epoch, const uint32_t* since, uint8_t* flags) {
@@ -658,7 +670,7 @@ int32_t entry_update(DProd* p) {
   Carve cl(region, lost_b);
   uint64_t* lkey = cl.take<uint64_t>(NT);
   int32_t* lslot = cl.take<int32_t>(NT);
-  uint8_t* fcls[3] = {cl.take<uint8_t>(NT), cl.take<uint8_t>(NT), cl.take<uint8_t>(NT)};
+  uint8_t* fcls = cl.take<uint8_t>(NT);
   int32_t* lcls[3] = {cl.take<int32_t>(NT), cl.take<int32_t>(NT), cl.take<int32_t>(NT)};
   uint8_t* fdel = cl.take<uint8_t>(NT);
   int32_t* ldel = cl.take<int32_t>(NT);
@@ -693,18 +705,16 @@ int32_t entry_update(DProd* p) {
       la.c_cur_epoch = C->d_epoch;
       la.del_flag = fdel;
       hipLaunchKernelGGL(k_lost_classes, dim3(blocks_for(nlost, 256)), dim3(256), 0, s, (const uint64_t*)lkey, nlost,
-                         cbits, (const int32_t*)A->row_len, (const int32_t*)T->row_len, fcls[0], fcls[1], fcls[2]);
-      for (int k = 0; k < 3; ++k) compact_flags(fcls[k], nlost, lcls[k], lcnt + k, lscr, s);
+                         cbits, (const int32_t*)A->row_len, (const int32_t*)T->row_len, fcls);
+      compact_classes3(fcls, nlost, lcls[0], lcls[1], lcls[2], lcnt, lscr, s);
       // bounded grids over the device counts
       auto grid = [&](int g) {
-        return (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(nlost * g, 256), 32 * (int64_t)c->num_cus));
+        return std::max<int64_t>(1, std::min<int64_t>(blocks_for(nlost * g, 256), 32 * (int64_t)c->num_cus));
       };
-      hipLaunchKernelGGL((k_lost_recompute<SR, 8>), dim3(grid(8)), dim3(256), 0, s, la, (const int32_t*)lcls[0],
-                         (const int32_t*)lcnt);
-      hipLaunchKernelGGL((k_lost_recompute<SR, 32>), dim3(grid(32)), dim3(256), 0, s, la, (const int32_t*)lcls[1],
-                         (const int32_t*)(lcnt + 1));
-      hipLaunchKernelGGL((k_lost_recompute<SR, 64>), dim3(grid(64)), dim3(256), 0, s, la, (const int32_t*)lcls[2],
-                         (const int32_t*)(lcnt + 2));
+      const int64_t nb0 = grid(8), nb1 = grid(32), nb2 = grid(64);
+      hipLaunchKernelGGL((k_lost_recompute<SR>), dim3((unsigned)(nb0 + nb1 + nb2)), dim3(256), 0, s, la,
+                         (const int32_t*)lcls[0], (const int32_t*)lcls[1], (const int32_t*)lcls[2],
+                         (const int32_t*)lcnt, nb0, nb1);
       compact_flags(fdel, nlost, ldel, lcnt + 3, lscr, s);
       DSG_HIP(hipGetLastError());
     }

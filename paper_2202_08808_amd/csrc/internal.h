@@ -219,6 +219,12 @@ void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64
 
 // Indices i < n with flags[i] != 0, ascending, into out; count into *d_count.
 size_t compact_scratch_bytes(int64_t n);
+// Positions of the entries of each class 0, 1, 2 of cls[0..n) (every value
+// one of those), in order, into out0/out1/out2; their counts to
+// d_count[0..2].
+// Scratch: compact_scratch_bytes(n).
+void compact_classes3(const uint8_t* cls, int64_t n, int32_t* out0, int32_t* out1, int32_t* out2, int32_t* d_count,
+                      void* scratch, hipStream_t s);
 void compact_flags(const uint8_t* flags, int64_t n, int32_t* out, int32_t* d_count, void* scratch,
                    hipStream_t s);
 // Entries list[q], q < *d_n, with flags[q] != 0, in order, into out; count into *d_count.

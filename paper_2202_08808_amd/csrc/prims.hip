@@ -541,6 +541,95 @@ void exclusive_scan_i32_to_i64(const int32_t* in, int64_t* out, int64_t n, int64
 
 size_t compact_scratch_bytes(int64_t n) { return scan_scratch_bytes(n) + 256; }
 
+// ---- three-class compaction ----
+// A position's class as packed counts: class 0 in the low 32 bits, class 1
+// in the high 32; class 2's count before a position is the position minus
+// the other two.
+
+__device__ inline int64_t cls_pack(uint8_t c) { return c == 0 ? 1ll : c == 1 ? (1ll << 32) : 0ll; }
+
+__device__ inline void cls_place(uint8_t c, int64_t i, int64_t pre, int32_t* o0, int32_t* o1, int32_t* o2) {
+  const int64_t p0 = pre & 0xffffffffll, p1 = (int64_t)((uint64_t)pre >> 32);
+  if (c == 0) o0[p0] = (int32_t)i;
+  else if (c == 1) o1[p1] = (int32_t)i;
+  else o2[i - p0 - p1] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(SCAN_NT) void k_cls_counts(const uint8_t* cls, int64_t n, int64_t* sums) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  int64_t c = 0;
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    if (i < n) c += cls_pack(cls[i]);
+  }
+  int64_t total;
+  block_exclusive_scan<int64_t>(c, lds, total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_NT) void k_cls_write(const uint8_t* cls, int64_t n, const int64_t* sums,
+                                                       int32_t* o0, int32_t* o1, int32_t* o2) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  uint8_t f[SCAN_ITEMS];
+  int64_t c = 0;
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    f[t] = i < n ? cls[i] : 3;
+    if (i < n) c += cls_pack(f[t]);
+  }
+  int64_t total;
+  int64_t pre = sums[blockIdx.x] + block_exclusive_scan<int64_t>(c, lds, total);
+  for (int t = 0; t < SCAN_ITEMS; ++t) {
+    const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+    if (i < n) {
+      cls_place(f[t], i, pre, o0, o1, o2);
+      pre += cls_pack(f[t]);
+    }
+  }
+}
+
+__global__ void k_cls_store(const int64_t* total, int64_t n, int32_t* d_count) {
+  const int64_t t = *total;
+  const int64_t c0 = t & 0xffffffffll, c1 = (int64_t)((uint64_t)t >> 32);
+  d_count[0] = (int32_t)c0;
+  d_count[1] = (int32_t)c1;
+  d_count[2] = (int32_t)(n - c0 - c1);
+}
+
+// up to SCAN_WG_MAX entries in one workgroup
+__global__ __launch_bounds__(SCAN_NT) void k_cls_wg(const uint8_t* cls, int64_t n, int32_t* o0, int32_t* o1,
+                                                    int32_t* o2, int32_t* d_count) {
+  __shared__ int64_t lds[SCAN_NT / 64];
+  int64_t carry = 0;
+  for (int64_t base = 0; base < n; base += SCAN_TILE) {
+    uint8_t f[SCAN_ITEMS];
+    int64_t c = 0;
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+      const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+      f[t] = i < n ? cls[i] : 3;
+      if (i < n) c += cls_pack(f[t]);
+    }
+    int64_t tot;
+    int64_t pre = carry + block_exclusive_scan<int64_t>(c, lds, tot);
+    for (int t = 0; t < SCAN_ITEMS; ++t) {
+      const int64_t i = base + (int64_t)threadIdx.x * SCAN_ITEMS + t;
+      if (i < n) {
+        cls_place(f[t], i, pre, o0, o1, o2);
+        pre += cls_pack(f[t]);
+      }
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    const int64_t c0 = carry & 0xffffffffll, c1 = (int64_t)((uint64_t)carry >> 32);
+    d_count[0] = (int32_t)c0;
+    d_count[1] = (int32_t)c1;
+    d_count[2] = (int32_t)(n - c0 - c1);
+  }
+}
+
 void compact_flags(const uint8_t* flags, int64_t n, int32_t* out, int32_t* d_count, void* scratch,
                    hipStream_t s) {
   if (n <= SCAN_WG_MAX) {
@@ -558,6 +647,22 @@ void compact_flags(const uint8_t* flags, int64_t n, int32_t* out, int32_t* d_cou
   hipLaunchKernelGGL(k_flag_write, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, flags,
                      (const int32_t*)nullptr, n, sums, out, (const int32_t*)nullptr);
   hipLaunchKernelGGL(k_store_count, dim3(1), dim3(1), 0, s, total, d_count);
+}
+
+void compact_classes3(const uint8_t* cls, int64_t n, int32_t* out0, int32_t* out1, int32_t* out2, int32_t* d_count,
+                      void* scratch, hipStream_t s) {
+  if (n <= SCAN_WG_MAX) {
+    hipLaunchKernelGGL(k_cls_wg, dim3(1), dim3(SCAN_NT), 0, s, cls, n, out0, out1, out2, d_count);
+    return;
+  }
+  const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+  int64_t* sums = (int64_t*)scratch;
+  int64_t* total = sums + tiles + 1;
+  hipLaunchKernelGGL(k_cls_counts, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, cls, n, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(SCAN_NT), 0, s, sums, tiles, total);
+  hipLaunchKernelGGL(k_cls_write, dim3((unsigned)tiles), dim3(SCAN_NT), 0, s, cls, n, (const int64_t*)sums, out0,
+                     out1, out2);
+  hipLaunchKernelGGL(k_cls_store, dim3(1), dim3(1), 0, s, (const int64_t*)total, n, d_count);
 }
 
 void compact_list_by_flags(const int32_t* list, const uint8_t* flags, const int32_t* d_n, int64_t n_max,
