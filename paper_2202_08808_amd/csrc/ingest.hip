@@ -1622,11 +1622,12 @@ int64_t mat_apply_sorted_add(DMat* m, const uint64_t* keys, const void* vals, co
   DSG_REQUIRE(lost_cap >= n, DSG_E_STATE, "internal: lost-entry list shorter than the updates");
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_nlost);
   if (n == 0) {
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, d_nlost);
     if (d_nrows) hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, (unsigned long long*)d_nrows);
     return 0;
   }
+  // (k_lost_gather sets *d_nlost and *d_nrows below)
   Work w = carve_work(ctx_scratch(c, work_bytes(n, false)), n, false);
   hipLaunchKernelGGL(k_ops_from_flags, dim3(blocks_for(n, 256)), dim3(256), 0, s, flag, n, w.allops, keys, w.keys,
                      w.idx);

@@ -23,13 +23,13 @@ __device__ inline int32_t table_size(int32_t len) { return 2 * len + 16; }
 // one wavefront per listed row of at most IX_LIGHT_MAX entries without a
 // usable table (rows taken in turn): take a table from the pool top, clear
 // it, record every entry
-__global__ __launch_bounds__(256) void k_ix_build_light(const int64_t* row_off, const int32_t* row_len,
-                                                        const int32_t* col, RowIx X, const int32_t* rows,
-                                                        const int64_t* d_n, int64_t n_all, int fresh) {
+// (b: the block's index among the nb blocks that build light rows)
+__device__ inline void ix_build_light(const int64_t* row_off, const int32_t* row_len, const int32_t* col,
+                                      const RowIx& X, const int32_t* rows, int64_t n, int fresh, int64_t b,
+                                      int64_t nb) {
   const int lane = threadIdx.x & 63;
-  const int64_t n = d_n ? *d_n : n_all;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < n; r += nw) {
+  const int64_t nw = (nb * blockDim.x) >> 6;
+  for (int64_t r = (b * blockDim.x + threadIdx.x) >> 6; r < n; r += nw) {
     const int32_t i = rows ? rows[r] : (int32_t)r;
     if (!fresh && X.stamp[i] == X.gen) continue;
     const int32_t len = row_len[i];
@@ -62,20 +62,20 @@ __global__ __launch_bounds__(256) void k_ix_build_light(const int64_t* row_off, 
   }
 }
 
-// the longer rows: one workgroup per row, rows taken in turn
-__global__ __launch_bounds__(IX_HEAVY_WG) void k_ix_build_heavy(const int64_t* row_off, const int32_t* row_len,
-                                                                const int32_t* col, RowIx X, const int32_t* rows,
-                                                                const int64_t* d_n, int64_t n_all, int fresh) {
+// the longer rows: one workgroup per row, rows taken in turn (b: the block's
+// index among the nb blocks that build them)
+__device__ inline void ix_build_heavy(const int64_t* row_off, const int32_t* row_len, const int32_t* col,
+                                      const RowIx& X, const int32_t* rows, int64_t n, int fresh, int64_t b,
+                                      int64_t nb) {
   __shared__ unsigned long long base_s;
   __shared__ int32_t wc[IX_HEAVY_WG / 64];
   __shared__ int32_t picked[IX_HEAVY_WG];
   const int tid = threadIdx.x;
-  const int64_t n = d_n ? *d_n : n_all;
   // this workgroup's share of the listed rows, scanned IX_HEAVY_WG at a time
   // by every thread at once; the long rows without a table are then built in
   // turn
-  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
-  const int64_t rb = (int64_t)blockIdx.x * per, re = min(n, rb + per);
+  const int64_t per = (n + nb - 1) / nb;
+  const int64_t rb = b * per, re = min(n, rb + per);
   for (int64_t c0 = rb; c0 < re; c0 += IX_HEAVY_WG) {
     int32_t npick;
     {
@@ -122,6 +122,24 @@ __global__ __launch_bounds__(IX_HEAVY_WG) void k_ix_build_heavy(const int64_t* r
     }
     __syncthreads();  // before the next share overwrites the picked rows
   }
+}
+
+// Tables of the listed rows (all rows when rows is null; their count on the
+// device, or n_all) that have none: blocks [0, nl) take the short rows a
+// wavefront each, the others the long rows a workgroup each.
+__global__ __launch_bounds__(IX_HEAVY_WG) void k_ix_build(const int64_t* row_off, const int32_t* row_len,
+                                                          const int32_t* col, RowIx X, const int32_t* rows,
+                                                          const int64_t* d_n, int64_t n_all, int fresh, int64_t nl) {
+  const int64_t n = d_n ? *d_n : n_all;
+  const int64_t b = blockIdx.x;
+  if (b < nl) ix_build_light(row_off, row_len, col, X, rows, n, fresh, b, nl);
+  else ix_build_heavy(row_off, row_len, col, X, rows, n, fresh, b - nl, (int64_t)gridDim.x - nl);
+}
+
+// block counts of k_ix_build for n listed rows
+void ix_build_grid(Ctx* c, int64_t n, int64_t& nl, int64_t& nh) {
+  nl = std::max<int64_t>(1, std::min<int64_t>(blocks_for(n * 64, IX_HEAVY_WG), 8 * (int64_t)c->num_cus));
+  nh = std::max<int64_t>(1, std::min<int64_t>(n, 2 * (int64_t)c->num_cus));
 }
 
 // table sizes of every row (a fresh build: offsets by a scan of these)
@@ -239,15 +257,11 @@ bool build_all(DMat* m) {
     c->ix_held += bytes;
   }
   const RowIx X = mat_index_view(m);
-  const unsigned nl = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for((int64_t)n * 64, 256),
-                                                                        16 * (int64_t)c->num_cus));
-  hipLaunchKernelGGL(k_ix_build_light, dim3(nl), dim3(256), 0, s, (const int64_t*)m->row_off,
+  int64_t nl, nh;
+  ix_build_grid(c, n, nl, nh);
+  hipLaunchKernelGGL(k_ix_build, dim3((unsigned)(nl + nh)), dim3(IX_HEAVY_WG), 0, s, (const int64_t*)m->row_off,
                      (const int32_t*)m->row_len, (const int32_t*)m->col, X, (const int32_t*)nullptr,
-                     (const int64_t*)nullptr, (int64_t)n, 1);
-  const unsigned nh = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 2 * (int64_t)c->num_cus));
-  hipLaunchKernelGGL(k_ix_build_heavy, dim3(nh), dim3(IX_HEAVY_WG), 0, s, (const int64_t*)m->row_off,
-                     (const int32_t*)m->row_len, (const int32_t*)m->col, X, (const int32_t*)nullptr,
-                     (const int64_t*)nullptr, (int64_t)n, 1);
+                     (const int64_t*)nullptr, (int64_t)n, 1, nl);
   DSG_HIP(hipGetLastError());
   return true;
 }
@@ -306,14 +320,10 @@ void mat_index_build(DMat* m, const int32_t* d_rows, const int64_t* d_n, int64_t
   hipStream_t s = c->stream;
   const RowIx X = mat_index_view(m);
   // a bounded grid: the listed rows are taken in turn
-  const unsigned nl = (unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks_for(n_max * 64, 256),
-                                                                        16 * (int64_t)c->num_cus));
-  hipLaunchKernelGGL(k_ix_build_light, dim3(nl), dim3(256), 0, s,
-                     (const int64_t*)m->row_off, (const int32_t*)m->row_len, (const int32_t*)m->col, X, d_rows,
-                     d_n, n_max, 0);
-  const unsigned nh = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_max, 2 * (int64_t)c->num_cus));
-  hipLaunchKernelGGL(k_ix_build_heavy, dim3(nh), dim3(IX_HEAVY_WG), 0, s, (const int64_t*)m->row_off,
-                     (const int32_t*)m->row_len, (const int32_t*)m->col, X, d_rows, d_n, n_max, 0);
+  int64_t nl, nh;
+  ix_build_grid(c, n_max, nl, nh);
+  hipLaunchKernelGGL(k_ix_build, dim3((unsigned)(nl + nh)), dim3(IX_HEAVY_WG), 0, s, (const int64_t*)m->row_off,
+                     (const int32_t*)m->row_len, (const int32_t*)m->col, X, d_rows, d_n, n_max, 0, nl);
   DSG_HIP(hipGetLastError());
 }
 
