@@ -416,6 +416,8 @@ void query_finish(DServer* s, PendingQuery& pq) {
       msg = e.msg;
     }
   }
+  // (a gather that failed part way may still be reading the slot)
+  if (st != DSG_OK) (void)hipStreamSynchronize(s->qstream);
   const double t = now_ms();
   std::lock_guard<std::mutex> lk(s->mu);
   for (SReq* r : g->reqs) {
