@@ -1412,7 +1412,8 @@ void launch_plan_commit(DMat* m, Work& w, int64_t n, uint64_t cmask, int cbits, 
 // the plan).
 void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint8_t* ops, const void* vals,
               bool graph, bool presorted = false, const Guard& G = Guard(),
-              int phases = PH_PLAN | PH_ROOM | PH_COMMIT, bool deltas_done = false, int64_t demand0 = -1) {
+              int phases = PH_PLAN | PH_ROOM | PH_COMMIT, bool deltas_done = false, int64_t demand0 = -1,
+              int key_lo = 0) {
   Ctx* c = m->ctx;
   hipStream_t s = c->stream;
   int cbits = bits_for(m->ncols);
@@ -1434,7 +1435,7 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
     return;
   }
   hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(1), 0, s, w.demand, w.ndelta, w.err, m->d_epoch);
-  if (!presorted) radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s, w.err);
+  if (!presorted) radix_sort_pairs(w.keys, w.idx, n, key_bits + (padded ? 1 : 0), w.radix, s, w.err, key_lo);
   unsigned nb = blocks_for(n, 256);
   hipLaunchKernelGGL(k_heads, dim3(nb), dim3(256), 0, s, w.keys, n, cbits, sentinel, w.kh, w.rh);
   exclusive_scan_i64_pair(w.kh, w.ukpos, w.nU, w.rh, w.urpos, w.nR, n, w.scan, s);
@@ -1458,6 +1459,13 @@ void run_core(DMat* m, Work& w, int64_t n, int key_bits, bool padded, const uint
   DSG_HIP(hipGetLastError());
 }
 
+// The transpose's deltas come in the order of the matrix's unique updates,
+// by (row, column): for each column of the matrix -- a row of the transpose
+// -- already by row.  Sorting them by the transpose's row bits alone (a
+// stable sort) therefore gives their full order: the passes skip the low
+// bits(t->ncols) bits.
+int delta_key_lo(const DMat* t) { return bits_for(t->ncols); }
+
 // Everything of mat_apply_device.  In a graph (no host round trips, on
 // caller-owned workspaces, error flags left on the device) the matrix is
 // planned and committed, then its transpose index.  Outside graphs both are
@@ -1478,7 +1486,8 @@ void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const
       int tk = bits_for(t->ncols) + bits_for(t->nrows);
       hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, (const uint8_t*)w.U.code,
                          (const int64_t*)w.nU, 1ull << tk, wt->keys, wt->idx, n);
-      run_core(t, *wt, n, tk, true, w.dop, t->vsz ? w.dval : nullptr, graph);
+      run_core(t, *wt, n, tk, true, w.dop, t->vsz ? w.dval : nullptr, graph, false, Guard(),
+               PH_PLAN | PH_ROOM | PH_COMMIT, false, -1, delta_key_lo(t));
     }
     return;
   }
@@ -1501,7 +1510,7 @@ void apply_pipeline(DMat* m, const int32_t* d_rows, const int32_t* d_cols, const
   hipLaunchKernelGGL(k_delta_keys, dim3(nb), dim3(256), 0, s, w.dkey, (const uint8_t*)w.U.code,
                      (const int64_t*)w.nU, 1ull << tk, wt->keys, wt->idx, n);
   const void* tvals = t->vsz ? (const void*)w.dval : nullptr;
-  run_core(t, *wt, n, tk, true, w.dop, tvals, false, false, Guard(), PH_PLAN);
+  run_core(t, *wt, n, tk, true, w.dop, tvals, false, false, Guard(), PH_PLAN, false, -1, delta_key_lo(t));
   if (count_touched)
     hipLaunchKernelGGL(k_touched_len, dim3(nb), dim3(256), 0, s, (const int32_t*)wt->U.urow, (const int64_t*)wt->nR,
                        (const int32_t*)t->row_len, wt->demand + 2);

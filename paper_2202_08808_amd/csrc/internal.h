@@ -234,9 +234,12 @@ void compact_list_by_flags(const int32_t* list, const uint8_t* flags, const int3
 // Stable LSD radix sort of (key, value) pairs on the low key_bits bits.
 size_t radix_scratch_bytes(int64_t n);
 // Sorts keys/vals in place (using the scratch as ping-pong buffers).  err,
-// when given, gets bit 16 if a pass could not complete its look-back.
+// when given, gets bit 16 if a pass could not complete its look-back.  When
+// the input is already in order on the bits below key_lo among keys equal
+// above it, key_lo > 0 lets the radix passes start there (the order is the
+// same, with fewer passes).
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, void* scratch,
-                      hipStream_t s, int* err = nullptr);
+                      hipStream_t s, int* err = nullptr, int key_lo = 0);
 
 void fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 void iota_i32(int32_t* p, int64_t n, hipStream_t s);

@@ -338,8 +338,10 @@ __global__ void k_rs_zero(uint32_t* p, int64_t n) {
     p[i] = 0u;
 }
 
-// digit histograms of every pass, summed over the whole input into g[pass][256]
-__global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const uint64_t* keys, int64_t n, int passes, uint32_t* g) {
+// digit histograms of every pass (pass p: bits lo + 8p and up), summed over
+// the whole input into g[pass][256]
+__global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const uint64_t* keys, int64_t n, int lo, int passes,
+                                                       uint32_t* g) {
   __shared__ uint32_t h[RS_MAX_PASSES][256];
   for (int p = 0; p < passes; ++p) h[p][threadIdx.x] = 0u;
   __syncthreads();
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(RS_NT) void k_rs_hist_all(const uint64_t* keys, int
     const int64_t i = base + t * RS_NT + threadIdx.x;
     if (i < n) {
       const uint64_t k = keys[i];
-      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (8 * p)) & 255], 1u);
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(k >> (lo + 8 * p)) & 255], 1u);
     }
   }
   __syncthreads();
@@ -795,7 +797,7 @@ size_t radix_scratch_bytes(int64_t n) {
 }
 
 void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, void* scratch,
-                      hipStream_t s, int* err) {
+                      hipStream_t s, int* err, int key_lo) {
   if (n <= 1 || key_bits <= 0) return;
   if (n <= MID_SORT && key_bits <= MID_KEY_BITS) {
     hipLaunchKernelGGL(k_mid_sort, dim3(1), dim3(MID_NT), 0, s, keys, vals, (int)n);
@@ -815,7 +817,9 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, v
   uint32_t* va = vals;
   uint64_t* kb = k2;
   uint32_t* vb = v2;
-  int passes = (key_bits + 7) / 8;
+  // (bits below key_lo already ordered: the passes start there)
+  if (key_lo < 0 || key_lo >= key_bits) key_lo = 0;
+  int passes = (key_bits - key_lo + 7) / 8;
   if (n <= RS_SWEEP_MAX && passes <= RS_MAX_PASSES) {
     uint32_t* ghist = cv.take<uint32_t>(RS_MAX_PASSES * 256);
     uint32_t* tickets = cv.take<uint32_t>(64);
@@ -825,12 +829,12 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, v
     DSG_REQUIRE((char*)(st[1] + 256 * ntiles) == (char*)(ghist + nz), DSG_E_DEVICE, "internal: sort scratch layout");
     hipLaunchKernelGGL(k_rs_zero, dim3((unsigned)std::min<int64_t>((nz + 255) / 256, 1024)), dim3(256), 0, s,
                        ghist, nz);
-    hipLaunchKernelGGL(k_rs_hist_all, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, n, passes, ghist);
+    hipLaunchKernelGGL(k_rs_hist_all, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, n, key_lo, passes, ghist);
     for (int p = 0; p < passes; ++p) {
       // pass p uses region p % 2 and clears the other one, which pass p - 1
       // used, for pass p + 1 (both start cleared)
       uint32_t* clr = p >= 1 ? st[(p + 1) & 1] : nullptr;
-      hipLaunchKernelGGL(k_rs_sweep, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, va, kb, vb, n, 8 * p,
+      hipLaunchKernelGGL(k_rs_sweep, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, va, kb, vb, n, key_lo + 8 * p,
                          ghist + 256 * p, tickets + p, st[p & 1], clr, clr ? 256 * ntiles : (int64_t)0, ntiles,
                          err);
       uint64_t* tk = ka; ka = kb; kb = tk;
@@ -843,7 +847,7 @@ void radix_sort_pairs(uint64_t* keys, uint32_t* vals, int64_t n, int key_bits, v
   int64_t* counts = cv.take<int64_t>(256 * ntiles + 1);
   void* sscr = cv.take<char>(scan_scratch_bytes(256 * ntiles));
   for (int p = 0; p < passes; ++p) {
-    int shift = 8 * p;
+    int shift = key_lo + 8 * p;
     hipLaunchKernelGGL(k_rs_hist, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, n, shift, counts, ntiles);
     exclusive_scan_i64(counts, counts, 256 * ntiles, nullptr, sscr, s);
     hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)ntiles), dim3(RS_NT), 0, s, ka, va, kb, vb, n, shift,
