@@ -1,11 +1,12 @@
-// Entry-granular dynamic update of C = A*A over (min,+) fp32 and (+,x) int64.
+// Entry-granular dynamic update of C = A*B (and A*A) over (min,+) fp32 and
+// (+,x) int64.
 //
 // Section 5 writes the new product as the old one combined with the products
 // that involve changed entries (Eq. 1), and observes that C can change only
 // where that change pattern is non-zero.  The row path recomputes every row
 // the pattern reaches.  This path works one level finer: it lists every
-// product a_ik * a_kj the last batch changed, with its value before and after,
-// and folds those values into the stored entries of C.
+// product a_ik * b_kj the last batches changed, with its value before and
+// after, and folds those values into the stored entries of C.
 //
 //   (+,x) int64   c' = c + sum(new - old) over the entry's changed products
 //                 (two's-complement ring, so the subtraction is exact).  An
@@ -17,17 +18,19 @@
 //                 recomputed.  Using the stored minimum as a witness this way
 //                 is this library's addition.
 //
-// A recomputed entry takes the minimum (or sum) of a'_ik * a'_kj over k, from
-// the shorter of row i and column j of A': each k of that list is looked up
-// in the per-row column index of A' (rowindex.h), and column j comes from the
-// valued transpose.  C keeps a column index too, so the apply of step 4
-// finds each entry of C in constant time instead of streaming its row.
+// A recomputed entry takes the minimum (or sum) of a'_ik * b'_kj over k, from
+// the shorter of row i of A' and column j of B': each k of that list is
+// looked up in the per-row column index (rowindex.h) of B' or A', and column
+// j comes from B's valued transpose.  C keeps a column index too, so the
+// apply of step 4 finds each entry of C in constant time instead of
+// streaming its row.
 //
 // Steps (all on the device, a few host reads of counts in between):
-//   1. per changed entry (r, c) of A, count its products: as a left factor
-//      (i = r, k = c) over row c of A' plus row c's deleted entries, and as a
-//      right factor (k = r, j = c) over column r of A' (rows i whose entry
-//      (i, r) did not change -- the others are covered as left factors);
+//   1. count the products of each changed entry: (i, k) of A as a left
+//      factor, over row k of B' plus the entries the batch deleted from it;
+//      (k, j) of B as a right factor, over column k of A' (rows i whose entry
+//      (i, k) did not change -- the others are covered as left factors).  For
+//      C = A*A every changed entry is both;
 //   2. write the products (key i<<bits | j, old value, new value, presence);
 //   3. sort them by key, and reduce each key to one ADD update of C
 //      (min or sum of the changes), with a guard for the witness test;
@@ -104,35 +107,40 @@ __device__ inline int64_t log_index(const uint64_t* key, int64_t lo, int64_t hi,
 }
 
 // ---- 1. product counts per changed entry ----
-// Per changed entry u = (r, c): its products are, in this order, the a_cj of
-// row c of A', the entries (c, j) the batch deleted, and the a_ir of column r
-// of A'.  rng[u] keeps the log range of row c and the count of its deletions
-// for the products' writer.
-__global__ void k_term_counts(Log L, int cbits, const int32_t* a_len, const int32_t* t_len, int64_t* cnt,
-                              int4* rng) {
+// The changed entries are those of A's log, then those of B's log (for
+// C = A*A both are A's).  A changed entry (i, k) of A is a left factor: its
+// products are the b_kj of row k of B', then the entries (k, j) the batch
+// deleted from B (rng[u] keeps that log range of B and its count of
+// deletions for the products' writer).  A changed entry (k, j) of B is a
+// right factor: its products are the a_ik of column k of A' (rows i whose
+// entry (i, k) changed too are covered as left factors).
+__global__ void k_term_counts(Log LA, Log LB, int abits, int bbits, const int32_t* b_len, const int32_t* ta_len,
+                              int64_t* cnt, int4* rng) {
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= L.n) return;
+  if (u >= LA.n + LB.n) return;
   int64_t c = 0;
   int4 g = make_int4(0, 0, 0, 0);
-  if (L.code[u] != UPD_NOP && L.code[u] != UPD_LOST) {
-    const uint64_t cmask = (1ull << cbits) - 1;
-    const int32_t r = (int32_t)(L.key[u] >> cbits), col = (int32_t)(L.key[u] & cmask);
-    // left factor: row col of A', plus its deleted entries
-    const uint64_t k0 = (uint64_t)col << cbits;
-    int64_t e = log_lower(L.key, L.n, k0);
-    g.x = (int32_t)e;
-    int64_t ndel = 0;
-    for (; e < L.n && (L.key[e] >> cbits) == (uint64_t)col; ++e) ndel += L.code[e] == UPD_DEL;
-    g.y = (int32_t)e;
-    g.z = (int32_t)ndel;
-    c = (int64_t)a_len[col] + ndel + (int64_t)t_len[r];
+  if (u < LA.n) {
+    if (LA.code[u] != UPD_NOP && LA.code[u] != UPD_LOST) {
+      const int32_t k = (int32_t)(LA.key[u] & ((1ull << abits) - 1));
+      int64_t e = log_lower(LB.key, LB.n, (uint64_t)k << bbits);
+      g.x = (int32_t)e;
+      int64_t ndel = 0;
+      for (; e < LB.n && (LB.key[e] >> bbits) == (uint64_t)k; ++e) ndel += LB.code[e] == UPD_DEL;
+      g.y = (int32_t)e;
+      g.z = (int32_t)ndel;
+      c = (int64_t)b_len[k] + ndel;
+    }
+  } else {
+    const int64_t v = u - LA.n;
+    if (LB.code[v] != UPD_NOP && LB.code[v] != UPD_LOST) c = ta_len[(int32_t)(LB.key[v] >> bbits)];
   }
   cnt[u] = c;
   rng[u] = g;
 }
 
-// The changed keys of the log in a hash set (open addressing, all ones when
-// empty): the right-factor pass asks for each product whether (i, r)
+// The changed keys of A's log in a hash set (open addressing, all ones when
+// empty): the right-factor pass asks for each product whether (i, k)
 // changed too.
 struct KeySet {
   uint64_t* tab;
@@ -194,75 +202,84 @@ __device__ inline int64_t entry_of(const int64_t* off, int64_t lo, int64_t hi, i
 }
 
 template <int SR>
-__global__ __launch_bounds__(256) void k_term_write(Log L, KeySet H, int cbits, Mat A, Mat T, const int64_t* off,
-                                                    const int4* rng, int64_t nterm, uint64_t* tkey, uint64_t* told,
-                                                    uint64_t* tnew, uint8_t* tfl, uint32_t* tidx) {
+__global__ __launch_bounds__(256) void k_term_write(Log LA, Log LB, KeySet H, int abits, int bbits, Mat B, Mat TA,
+                                                    const int64_t* off, const int4* rng, int64_t nterm,
+                                                    uint64_t* tkey, uint64_t* told, uint64_t* tnew, uint8_t* tfl,
+                                                    uint32_t* tidx) {
   using S = Sem<SR>;
   using V = typename S::V;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lane = threadIdx.x & 63;
   const int64_t t0 = t - lane;
   if (t0 >= nterm) return;
+  const int64_t nu = LA.n + LB.n;
   const int64_t t1 = std::min<int64_t>(t0 + 63, nterm - 1);
-  const int64_t u0 = entry_of(off, 0, L.n, t0);
-  const int64_t u1 = entry_of(off, u0, L.n, t1);
+  const int64_t u0 = entry_of(off, 0, nu, t0);
+  const int64_t u1 = entry_of(off, u0, nu, t1);
   if (t >= nterm) return;
   tidx[t] = (uint32_t)t;  // the sort's values: the products' positions
   const int64_t u = u0 == u1 ? u0 : entry_of(off, u0, u1 + 1, t);
-  const uint8_t code = L.code[u];
-  const uint64_t cmask = (1ull << cbits) - 1;
-  const uint64_t dk = L.key[u];
-  const int32_t r = (int32_t)(dk >> cbits), c = (int32_t)(dk & cmask);
-  const bool op = code != UPD_INS, np = code != UPD_DEL;  // entry present before / after
-  const V vo = rawv<V>(L.old[u]), vn = rawv<V>(L.nw[u]);
   const int64_t q = t - off[u];
-  const int32_t al = A.len[c];
-  const int4 g = rng[u];
-  if (q < al) {
-    // left factor (i = r, k = c): a_rc * a_cj
-    const int64_t ac = A.off[c] + q;
-    const int32_t j = A.col[ac];
-    const V bn = ldv<V>(A.val, ac);
-    bool bop = true;
-    V bo = bn;
-    if (g.y > g.x) {
-      const int64_t e = log_index(L.key, g.x, g.y, ((uint64_t)c << cbits) | (uint64_t)(uint32_t)j);
-      if (e >= 0) {
-        const uint8_t ce = L.code[e];
-        if (ce == UPD_INS) bop = false;
-        else if (ce == UPD_OVR) bo = rawv<V>(L.old[e]);
+  const uint64_t amask = (1ull << abits) - 1, bmask = (1ull << bbits) - 1;
+  if (u < LA.n) {
+    // left factor (i, k) of A: a_ik * b_kj
+    const uint8_t code = LA.code[u];
+    const uint64_t dk = LA.key[u];
+    const int32_t i = (int32_t)(dk >> abits), k = (int32_t)(dk & amask);
+    const bool op = code != UPD_INS, np = code != UPD_DEL;  // entry present before / after
+    const V vo = rawv<V>(LA.old[u]), vn = rawv<V>(LA.nw[u]);
+    const int32_t bl = B.len[k];
+    const int4 g = rng[u];
+    if (q < bl) {
+      const int64_t bo = B.off[k] + q;
+      const int32_t j = B.col[bo];
+      const V bn = ldv<V>(B.val, bo);
+      bool bop = true;
+      V bold = bn;
+      if (g.y > g.x) {  // (k, j) changed in B too: its value before
+        const int64_t e = log_index(LB.key, g.x, g.y, ((uint64_t)k << bbits) | (uint64_t)(uint32_t)j);
+        if (e >= 0) {
+          const uint8_t ce = LB.code[e];
+          if (ce == UPD_INS) bop = false;
+          else if (ce == UPD_OVR) bold = rawv<V>(LB.old[e]);
+        }
+      }
+      const uint8_t f = (op && bop ? F_OLD : 0) | (np ? F_NEW : 0);
+      tkey[t] = ((uint64_t)(uint32_t)i << bbits) | (uint64_t)(uint32_t)j;
+      told[t] = (f & F_OLD) ? (uint64_t)S::mul(vo, bold) : 0ull;
+      tnew[t] = (f & F_NEW) ? (uint64_t)S::mul(vn, bn) : 0ull;
+      tfl[t] = f;
+    } else if (q == bl) {
+      // entries (k, j) this batch deleted from B: a_ik * b_kj existed only
+      // before.  The first of these products writes them all, in log order.
+      int64_t w = t;
+      for (int64_t e = g.x; e < g.y; ++e) {
+        if (LB.code[e] != UPD_DEL) continue;
+        const int32_t j = (int32_t)(LB.key[e] & bmask);
+        tkey[w] = ((uint64_t)(uint32_t)i << bbits) | (uint64_t)(uint32_t)j;
+        told[w] = op ? (uint64_t)S::mul(vo, rawv<V>(LB.old[e])) : 0ull;
+        tnew[w] = 0ull;
+        tfl[w] = op ? F_OLD : 0;
+        ++w;
       }
     }
-    const uint8_t f = (op && bop ? F_OLD : 0) | (np ? F_NEW : 0);
-    tkey[t] = ((uint64_t)(uint32_t)r << cbits) | (uint64_t)(uint32_t)j;
-    told[t] = (f & F_OLD) ? (uint64_t)S::mul(vo, bo) : 0ull;
-    tnew[t] = (f & F_NEW) ? (uint64_t)S::mul(vn, bn) : 0ull;
-    tfl[t] = f;
-  } else if (q < (int64_t)al + g.z) {
-    // entries (c, j) this batch deleted: a_rc * a_cj existed only before.
-    // The first of these products writes them all, in log order.
-    if (q != al) return;
-    int64_t w = t;
-    for (int64_t e = g.x; e < g.y; ++e) {
-      if (L.code[e] != UPD_DEL) continue;
-      const int32_t j = (int32_t)(L.key[e] & cmask);
-      tkey[w] = ((uint64_t)(uint32_t)r << cbits) | (uint64_t)(uint32_t)j;
-      told[w] = op ? (uint64_t)S::mul(vo, rawv<V>(L.old[e])) : 0ull;
-      tnew[w] = 0ull;
-      tfl[w] = op ? F_OLD : 0;
-      ++w;
-    }
   } else {
-    // right factor (k = r, j = c): a_ir * a_rc over column r of A'
-    const int64_t tc = T.off[r] + (q - al - g.z);
-    const int32_t i = T.col[tc];
-    const V a = ldv<V>(T.val, tc);
-    // (i, r) changed too: that entry's left-factor products include this
-    // one, which stays in the list with no effect (its key (i, c) is among
+    // right factor (k, j) of B: a_ik * b_kj over column k of A'
+    const int64_t v = u - LA.n;
+    const uint8_t code = LB.code[v];
+    const uint64_t dk = LB.key[v];
+    const int32_t k = (int32_t)(dk >> bbits), j = (int32_t)(dk & bmask);
+    const bool op = code != UPD_INS, np = code != UPD_DEL;
+    const V vo = rawv<V>(LB.old[v]), vn = rawv<V>(LB.nw[v]);
+    const int64_t tc = TA.off[k] + q;
+    const int32_t i = TA.col[tc];
+    const V a = ldv<V>(TA.val, tc);
+    // (i, k) changed too: that entry's left-factor products include this
+    // one, which stays in the list with no effect (its key (i, j) is among
     // those products' keys, so it adds no entry of C)
-    const bool dup = keyset_has(H, ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)r);
+    const bool dup = keyset_has(H, ((uint64_t)(uint32_t)i << abits) | (uint64_t)(uint32_t)k);
     const uint8_t f = dup ? 0 : (op ? F_OLD : 0) | (np ? F_NEW : 0);
-    tkey[t] = ((uint64_t)(uint32_t)i << cbits) | (uint64_t)(uint32_t)c;
+    tkey[t] = ((uint64_t)(uint32_t)i << bbits) | (uint64_t)(uint32_t)j;
     told[t] = (f & F_OLD) ? (uint64_t)S::mul(a, vo) : 0ull;
     tnew[t] = (f & F_NEW) ? (uint64_t)S::mul(a, vn) : 0ull;
     tfl[t] = f;
@@ -334,10 +351,10 @@ __global__ void k_seg_reduce(const uint64_t* key, const uint32_t* idx, const uin
 }
 
 // ---- 5. lost entries ----
-// A lost entry (i, j) takes the minimum (or sum) of a'_ik * a'_kj over k from
-// the shorter of two lists: row i of A' (each k probed for column j in row
-// k's column index) or column j of A' (each k probed for column k in row i's
-// column index).  Entries are split into three classes by that length (up
+// A lost entry (i, j) takes the minimum (or sum) of a'_ik * b'_kj over k from
+// the shorter of two lists: row i of A' (each k probed for column j in the
+// column index of row k of B') or column j of B' (each k probed for column k
+// in the column index of row i of A').  Entries are split into three classes by that length (up
 // to LOST_C0_MAX, up to LOST_C1_MAX, longer), taken by groups of 8, 32 and 64
 // lanes, so that a group needs about one round of probes.
 constexpr int32_t LOST_C0_MAX = 8, LOST_C1_MAX = 32;
@@ -345,9 +362,9 @@ constexpr int32_t LOST_C0_MAX = 8, LOST_C1_MAX = 32;
 struct LostArgs {
   const uint64_t* key;
   const int32_t* slot;
-  int cbits;
-  Mat A, T;
-  RowIx X;  // column index of A' (every row built)
+  int cbits;     // column bits of C's keys
+  Mat A, B, TB;  // rows of A' and B', columns of B' (B's valued transpose)
+  RowIx XA, XB;  // column indexes of A' and B' (every row built)
   int64_t* c_off;
   void* c_val;
   uint32_t* c_epoch;
@@ -366,19 +383,19 @@ __device__ inline unsigned long long acc_comb(unsigned long long a, unsigned lon
   else return a + b;
 }
 
-// position of column c in row r of A' (its table, or a scan of the row when
-// the index pool had no room for it)
-__device__ inline int32_t a_find(const LostArgs& L, int32_t r, int32_t c) {
-  if (L.X.tab) {  // A' may have no index (refused for room, or switched off)
+// position of column c in row r of M (its table in X, or a scan of the row
+// when the index pool had no room for it)
+__device__ inline int32_t a_find(const RowIx& X, const Mat& M, int32_t r, int32_t c) {
+  if (X.tab) {  // M may have no index (refused for room, or switched off)
     // (the table's place is read before its stamp is checked: independent loads)
-    const int64_t to = L.X.off[r];
-    const uint32_t tn = (uint32_t)L.X.sz[r];
-    if (L.X.stamp[r] == L.X.gen) return ix_find(L.X.tab + to, tn, c);
+    const int64_t to = X.off[r];
+    const uint32_t tn = (uint32_t)X.sz[r];
+    if (X.stamp[r] == X.gen) return ix_find(X.tab + to, tn, c);
   }
-  const int64_t o = L.A.off[r];
-  const int32_t n = L.A.len[r];
+  const int64_t o = M.off[r];
+  const int32_t n = M.len[r];
   for (int32_t t = 0; t < n; ++t)
-    if (L.A.col[o + t] == c) return t;
+    if (M.col[o + t] == c) return t;
   return -1;
 }
 
@@ -404,13 +421,13 @@ __device__ inline void finish_entry(const LostArgs& L, int64_t e, unsigned long 
 
 // class of each lost entry by probe count: 0 (at most LOST_C0_MAX), 1 (at
 // most LOST_C1_MAX), 2 (more)
-__global__ void k_lost_classes(const uint64_t* key, int64_t n, int cbits, const int32_t* a_len, const int32_t* t_len,
+__global__ void k_lost_classes(const uint64_t* key, int64_t n, int cbits, const int32_t* a_len, const int32_t* tb_len,
                                uint8_t* cls) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const uint64_t k = key[e];
   const int32_t d = a_len[(int32_t)(k >> cbits)];
-  const int32_t lj = t_len[(int32_t)(k & ((1ull << cbits) - 1))];
+  const int32_t lj = tb_len[(int32_t)(k & ((1ull << cbits) - 1))];
   const int32_t cost = d < lj ? d : lj;
   cls[e] = cost <= LOST_C0_MAX ? 0 : cost <= LOST_C1_MAX ? 1 : 2;
 }
@@ -431,30 +448,30 @@ __device__ inline void lost_recompute(const LostArgs& L, const int32_t* list, in
     const int32_t i = (int32_t)(L.key[e] >> L.cbits);
     const int32_t j = (int32_t)(L.key[e] & cmask);
     const int32_t d = L.A.len[i];
-    const int32_t lj = L.T.len[j];
+    const int32_t lj = L.TB.len[j];
     unsigned long long acc = acc_id<SR>();
     uint32_t hits = 0;
     if (act) {
       const int64_t aoff = L.A.off[i];
       if (d <= lj) {
-        // row i of A': is column j in row k?
+        // row i of A': is column j in row k of B'?
         for (int32_t t = l; t < d; t += G) {
           const int32_t k = L.A.col[aoff + t];
-          const int32_t pos = a_find(L, k, j);
+          const int32_t pos = a_find(L.XB, L.B, k, j);
           if (pos >= 0) {
-            const V a = ldv<V>(L.A.val, aoff + t), b = ldv<V>(L.A.val, L.A.off[k] + pos);
+            const V a = ldv<V>(L.A.val, aoff + t), b = ldv<V>(L.B.val, L.B.off[k] + pos);
             acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
             ++hits;
           }
         }
       } else {
-        // column j of A': is column k in row i?
-        const int64_t toff = L.T.off[j];
+        // column j of B': is column k in row i of A'?
+        const int64_t toff = L.TB.off[j];
         for (int32_t t = l; t < lj; t += G) {
-          const int32_t k = L.T.col[toff + t];
-          const int32_t pos = a_find(L, i, k);
+          const int32_t k = L.TB.col[toff + t];
+          const int32_t pos = a_find(L.XA, L.A, i, k);
           if (pos >= 0) {
-            const V a = ldv<V>(L.A.val, aoff + pos), b = ldv<V>(L.T.val, toff + t);
+            const V a = ldv<V>(L.A.val, aoff + pos), b = ldv<V>(L.TB.val, toff + t);
             acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
             ++hits;
           }
@@ -488,9 +505,9 @@ __global__ void k_rows_after(int32_t n, const uint32_t* epoch, const uint32_t* s
   if (i < n) flags[i] = epoch[i] > *since ? 1 : 0;
 }
 
-__global__ void k_sync_both(uint32_t* sync, const uint32_t* e) {
-  sync[0] = *e;
-  sync[1] = *e;
+__global__ void k_sync_ab(uint32_t* sync, const uint32_t* ea, const uint32_t* eb) {
+  sync[0] = *ea;
+  sync[1] = *eb;
 }
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
@@ -527,24 +544,53 @@ int64_t read_count(Ctx* c, const int64_t* d) {
   return *h;
 }
 
-bool eligible(const DProd* p) {
-  const DMat* A = p->A;
-  if (p->ops || p->B != A || (A->sr != 0 && A->sr != 1)) return false;
-  if (p->ctx->tuning.update_path == 1) return false;
-  if (!A->tidx || A->tidx->vsz != A->vsz) return false;
-  return A->log_seq != 0 && A->log_seq == A->apply_seq && A->apply_seq == p->a_seq + 1;
+// An operand applied once since the last update, with the log of that
+// apply; or not applied since.
+bool changed_once(const DMat* m, uint64_t seq) {
+  return m->log_seq != 0 && m->log_seq == m->apply_seq && m->apply_seq == seq + 1;
 }
 
-// Step 1, on its own: count the products the last apply changed (the
+bool eligible(const DProd* p) {
+  const DMat* A = p->A;
+  const DMat* B = p->B;
+  if (p->ops || (A->sr != 0 && A->sr != 1) || B->sr != A->sr) return false;
+  if (p->ctx->tuning.update_path == 1) return false;
+  if (B == A) return changed_once(A, p->a_seq);
+  const bool ca = changed_once(A, p->a_seq), cb = changed_once(B, p->b_seq);
+  const bool ua = A->apply_seq == p->a_seq, ub = B->apply_seq == p->b_seq;
+  return (ca || ua) && (cb || ub) && (ca || cb);
+}
+
+// The two logs of the pending update: A's changed entries (left factors) and
+// B's (right factors); an operand not applied since the last update has an
+// empty one.  For C = A*A both are A's log.
+struct EntryLogs {
+  Log LA, LB;
+  int abits, bbits;  // column bits of A's and B's keys (B's are C's too)
+};
+
+EntryLogs entry_logs(const DProd* p) {
+  const DMat* A = p->A;
+  const DMat* B = p->B;
+  const bool ca = B == A || A->apply_seq != p->a_seq;
+  const bool cb = B == A || B->apply_seq != p->b_seq;
+  EntryLogs g;
+  g.LA = Log{A->log_key, A->log_old, A->log_new, A->log_code, ca ? A->h_log_n : 0};
+  g.LB = Log{B->log_key, B->log_old, B->log_new, B->log_code, cb ? B->h_log_n : 0};
+  g.abits = bits_for(A->ncols);
+  g.bbits = bits_for(B->ncols);
+  return g;
+}
+
+// Step 1, on its own: count the products the last applies changed (the
 // offsets stay in the context's second scratch for entry_finish).
 const int64_t* count_terms(DProd* p) {
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
   DMat* A = p->A;
-  DMat* T = A->tidx;
-  const int cbits = bits_for(A->ncols);
-  Log L{A->log_key, A->log_old, A->log_new, A->log_code, A->h_log_n};
-  const int64_t nU = L.n;
+  DMat* B = p->B;
+  const EntryLogs g = entry_logs(p);
+  const int64_t nU = g.LA.n + g.LB.n;
   const size_t b1 = Carve::need(
       {(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64, (size_t)(nU + 1) * 16});
   Carve cv1(ctx_scratch2(c, b1), b1);
@@ -555,8 +601,8 @@ const int64_t* count_terms(DProd* p) {
   int4* rng = cv1.take<int4>(nU + 1);
   if (nU > 0) {
     Phase ph(c, "entry_count");
-    hipLaunchKernelGGL(k_term_counts, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, cbits, (const int32_t*)A->row_len,
-                       (const int32_t*)T->row_len, cnt, rng);
+    hipLaunchKernelGGL(k_term_counts, dim3(blocks_for(nU, 256)), dim3(256), 0, s, g.LA, g.LB, g.abits, g.bbits,
+                       (const int32_t*)B->row_len, (const int32_t*)A->tidx->row_len, cnt, rng);
     exclusive_scan_i64(cnt, off, nU, d_total, scan1, s);
   } else {
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, d_total);
@@ -572,21 +618,24 @@ int32_t entry_update(DProd* p) {
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
   DMat* A = p->A;
-  DMat* T = A->tidx;
+  DMat* B = p->B;
+  DMat* TA = A->tidx;  // columns of A'
+  DMat* TB = B->tidx;  // columns of B'
   DMat* C = p->C;
   const int32_t n = A->nrows;
-  const int cbits = bits_for(A->ncols);
-  const int kbits = 2 * cbits;
+  const EntryLogs g = entry_logs(p);
+  const int cbits = g.bbits;  // C's keys: (row << cbits) | column
+  const int kbits = bits_for(C->nrows) + cbits;
   dsg_update_stats& st = p->stats;
   st = dsg_update_stats{};
   st.path = 1;
   // column index of C: the apply of its updates looks entries up in it
-  // (A' got its own at eligibility); built on first use
+  // (A' and B' got theirs at eligibility); built on first use
   if (c->tuning.row_index) mat_index_enable(C);
 
   // the counts of step 1 (count_terms), still in the second scratch
-  Log L{A->log_key, A->log_old, A->log_new, A->log_code, p->entry_nU};
-  const int64_t nU = L.n;
+  const int64_t nU = g.LA.n + g.LB.n;
+  DSG_REQUIRE(nU == p->entry_nU, DSG_E_STATE, "internal: the logs changed between counting and updating");
   const size_t b1 = Carve::need(
       {(size_t)(nU + 1) * 8, (size_t)(nU + 1) * 8, scan_scratch_bytes(nU + 1) + 64, 64, (size_t)(nU + 1) * 16});
   Carve cv1(ctx_scratch2(c, b1), b1);
@@ -608,8 +657,8 @@ int32_t entry_update(DProd* p) {
   const size_t lost_b = Carve::need({(size_t)NT * 8, (size_t)NT * 4, (size_t)NT, (size_t)NT, (size_t)NT,
                                      (size_t)NT * 4, (size_t)NT * 4, (size_t)NT * 4, (size_t)NT, (size_t)NT * 4,
                                      compact_scratch_bytes(NT) + 64, 64});
-  uint32_t hs = 64;
-  while (hs < 2 * (uint64_t)std::max<int64_t>(nU, 1)) hs <<= 1;
+  uint32_t hs = 64;  // the key set of A's changed entries
+  while (hs < 2 * (uint64_t)std::max<int64_t>(g.LA.n, 1)) hs <<= 1;
   const size_t segs_b = Carve::need({(size_t)NT * 8, (size_t)NT * 8, (size_t)NT * 8, (size_t)NT, 256, (size_t)n + 64,
                                      compact_scratch_bytes(std::max<int32_t>(n, 1)) + 64, 256,
                                      sorted_add_scratch_bytes(NT), (size_t)hs * 8});
@@ -645,9 +694,10 @@ int32_t entry_update(DProd* p) {
     int64_t* seg_start = ct.take<int64_t>(NT + 1);
     {
       Phase ph(c, "entry_terms");
-      hipLaunchKernelGGL(k_keyset_fill, dim3(blocks_for(nU, 256)), dim3(256), 0, s, L, H);
-      hipLaunchKernelGGL((k_term_write<SR>), dim3(blocks_for(nterm, 256)), dim3(256), 0, s, L, H, cbits, view(A),
-                         view(T), (const int64_t*)off, rng, nterm, tkey, told, tnew, tfl, tidx);
+      if (g.LA.n > 0)
+        hipLaunchKernelGGL(k_keyset_fill, dim3(blocks_for(g.LA.n, 256)), dim3(256), 0, s, g.LA, H);
+      hipLaunchKernelGGL((k_term_write<SR>), dim3(blocks_for(nterm, 256)), dim3(256), 0, s, g.LA, g.LB, H, g.abits,
+                         g.bbits, view(B), view(TA), (const int64_t*)off, rng, nterm, tkey, told, tnew, tfl, tidx);
     }
     // ---- 3. sort, segments, one update per entry of C ----
     {
@@ -689,23 +739,26 @@ int32_t entry_update(DProd* p) {
   if (nlost > 0) {
     {
       Phase ph(c, "entry_lost");
-      // every row of A' needs its column table (the apply dropped the tables
-      // of rows it could not keep them for)
+      // every row of A' and B' needs its column table (the applies dropped
+      // the tables of rows they could not keep them for)
       mat_index_build(A, nullptr, nullptr, A->nrows);
+      if (B != A) mat_index_build(B, nullptr, nullptr, B->nrows);
       LostArgs la;
       la.key = lkey;
       la.slot = lslot;
       la.cbits = cbits;
       la.A = view(A);
-      la.T = view(T);
-      la.X = mat_index_view(A);
+      la.B = view(B);
+      la.TB = view(TB);
+      la.XA = mat_index_view(A);
+      la.XB = mat_index_view(B);
       la.c_off = C->row_off;
       la.c_val = C->val;
       la.c_epoch = C->row_epoch;
       la.c_cur_epoch = C->d_epoch;
       la.del_flag = fdel;
       hipLaunchKernelGGL(k_lost_classes, dim3(blocks_for(nlost, 256)), dim3(256), 0, s, (const uint64_t*)lkey, nlost,
-                         cbits, (const int32_t*)A->row_len, (const int32_t*)T->row_len, fcls);
+                         cbits, (const int32_t*)A->row_len, (const int32_t*)TB->row_len, fcls);
       compact_classes3(fcls, nlost, lcls[0], lcls[1], lcls[2], lcnt, lscr, s);
       // bounded grids over the device counts
       auto grid = [&](int g) {
@@ -728,7 +781,7 @@ int32_t entry_update(DProd* p) {
     }
   }
 
-  // ---- 6. rows whose content changed, and C now reflects A's epoch ----
+  // ---- 6. rows whose content changed, and C now reflects A's and B's epochs ----
   if (p->changed_cap < n) {
     ctx_free(c, p->changed_rows, (size_t)p->changed_cap * 4);
     p->changed_rows = nullptr;
@@ -743,10 +796,11 @@ int32_t entry_update(DProd* p) {
                        (const uint32_t*)ep_before, rflags);
     compact_flags(rflags, n, p->changed_rows, d_nchg, cscr, s);
   }
-  hipLaunchKernelGGL(k_sync_both, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)A->d_epoch);
+  hipLaunchKernelGGL(k_sync_ab, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)A->d_epoch,
+                     (const uint32_t*)B->d_epoch);
   struct Tail {
     unsigned long long ctr[6];
-    unsigned long long ix_top[2];  // index pool tops of C and A
+    unsigned long long ix_top[3];  // index pool tops of C, A and B
     int32_t nchg;
   };
   Tail* ht = (Tail*)((char*)c->pinned + 3072);
@@ -754,11 +808,13 @@ int32_t entry_update(DProd* p) {
   F.add(ctr, 48, 3072 + (int32_t)offsetof(Tail, ctr));
   F.add(C->ix_top, 8, 3072 + (int32_t)offsetof(Tail, ix_top));
   F.add(A->ix_top, 8, 3072 + (int32_t)offsetof(Tail, ix_top) + 8);
+  F.add(B != A ? (const void*)B->ix_top : nullptr, 8, 3072 + (int32_t)offsetof(Tail, ix_top) + 16);
   F.add(n > 0 ? (const void*)d_nchg : nullptr, 4, 3072 + (int32_t)offsetof(Tail, nchg));
   fetch_to_pinned(c, F, s);
   DSG_HIP(hipStreamSynchronize(s));
   mat_index_note_top(C, ht->ix_top[0]);
   mat_index_note_top(A, ht->ix_top[1]);
+  if (B != A) mat_index_note_top(B, ht->ix_top[2]);
   DSG_REQUIRE(ht->ctr[5] == 0, DSG_E_DEVICE, "internal: the product sort could not complete");
   st.affected_rows = (int64_t)ht->ctr[0];
   st.flops = nterm;
@@ -770,10 +826,26 @@ int32_t entry_update(DProd* p) {
 
 bool entry_eligible(DProd* p) {
   if (!eligible(p)) return false;
-  // the lost entries probe rows of A' through its column index: without
-  // one (no room for it) the row path runs instead; with the index switched
-  // off the probes scan the rows
-  return !p->ctx->tuning.row_index || mat_index_enable(p->A);
+  // the products of B's changed entries run over columns of A', and the lost
+  // entries over columns of B': both need the operand's valued transpose
+  // (A's exists for the discovery; B's is built here on first use, and every
+  // later apply of B keeps it)
+  for (DMat* m : {p->A, p->B}) {
+    if (!m->tidx) {
+      try {
+        mat_build_transpose(m);
+      } catch (const DsgError& e) {
+        if (e.code != DSG_E_OOM) throw;
+        return false;
+      }
+    }
+    if (!m->tidx || m->tidx->vsz != m->vsz) return false;
+  }
+  // the lost entries probe rows of A' and B' through their column indexes:
+  // without them (no room) the row path runs instead; with the index
+  // switched off the probes scan the rows
+  if (!p->ctx->tuning.row_index) return true;
+  return mat_index_enable(p->A) && (p->B == p->A || mat_index_enable(p->B));
 }
 
 const int64_t* entry_count(DProd* p) { return count_terms(p); }

@@ -243,3 +243,57 @@ def test_automatic_path_choice(ctx, sr):
             assert np.array_equal(x.row_ptr, y.row_ptr) and np.array_equal(x.col, y.col)
             assert np.asarray(x.val).tobytes() == np.asarray(y.val).tobytes(), f"batch {k}"
     assert chosen == [1, 0]
+
+
+def run_ab(ctx, sr, A, B, steps, use_row_path=False):
+    """C = A*B: each step applies a batch to A, to B or to both, then
+    updates; C and the reported rows against the oracle after every step."""
+    row_path(ctx, use_row_path)
+    ma = dsg.Matrix.from_csr(ctx, A, sr)
+    mb = dsg.Matrix.from_csr(ctx, B, sr)
+    P = dsg.Product(ctx, ma, mb)
+    a, b = oracle.Csr.of(A), oracle.Csr.of(B)
+    C = oracle.spgemm(sr, a, b, nthreads=THREADS)
+    stats = []
+    for t, (ba, bb) in enumerate(steps):
+        if ba is not None:
+            ma.apply_batch(ba)
+            a, _ = oracle.apply(sr, a, ba.rows, ba.cols, ba.vals, ba.ops)
+        if bb is not None:
+            mb.apply_batch(bb)
+            b, _ = oracle.apply(sr, b, bb.rows, bb.cols, bb.vals, bb.ops)
+        rs = P.update()
+        want = oracle.spgemm(sr, a, b, nthreads=THREADS)
+        assert_same_csr(sr, P.export(), want, f"step {t}")
+        assert np.array_equal(rs.row_ids(), changed_rows(C, want)), f"step {t}: reported rows"
+        st = P.stats()
+        stats.append(st)
+        if not use_row_path:
+            assert st["path"] == 1, f"step {t}: row path taken"
+        C = want
+    P.destroy()
+    ma.destroy()
+    mb.destroy()
+    ctx.set_tuning(None)
+    return stats
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_entry_a_times_b(ctx, sr):
+    """C = A*B on the entry path (Eq. 1 with both operands changing): batches
+    to A alone, to B alone and to both, on R-MAT operands of different shapes
+    (B's valued transpose and both column indexes built on first use), and
+    the same steps on the row path."""
+    say(f"entry path A*B {SR_ID[sr]}")
+    hi = 9 if sr == I.PLUS_TIMES_I64 else 100
+    A = I.rmat_csr(11, 8, sr, stream=821, lo=1, hi=hi)
+    rng = np.random.default_rng(822)
+    n, m = A.nrows, A.nrows + A.nrows // 2  # B is n x 1.5n: its keys take one more column bit than A's
+    keys = np.unique(rng.integers(0, n, 12 * n, dtype=np.int64) * m + rng.integers(0, m, 12 * n, dtype=np.int64))
+    B = I.csr_from_keys(n, m, keys, I.draw_values(sr, keys.size, rng, 1, hi))
+    ba = I.disjoint_batches(A, sr, [10, 300, 2000, 50], stream=823, value_lo=1, value_hi=hi)
+    bb = I.disjoint_batches(B, sr, [20, 500, 40, 1500], stream=824, value_lo=1, value_hi=hi)
+    steps = [(ba[0], None), (None, bb[0]), (ba[1], bb[1]), (ba[2], None), (None, bb[2]), (ba[3], bb[3])]
+    st = run_ab(ctx, sr, A, B, steps)
+    assert sum(s["lost"] for s in st) > 0
+    run_ab(ctx, sr, A, B, steps, use_row_path=True)
