@@ -155,9 +155,10 @@ typedef struct {
                               it needs at most this many column passes, else a global-memory hash */
   int32_t force_bin;       /* -1: automatic; 0..7 group bin; 8 dense; 9 global hash (for tests;
                               a group bin is only used for rows that fit it) */
-  int32_t update_path;     /* dynamic updates of C = A*A over (min,+) or int64 (+,x):
-                              0 automatic (see below); 1 always whole rows; 2 entry-granular
-                              whenever it applies.  Same results every way. */
+  int32_t update_path;     /* dynamic updates of C = A*A or A*B (no transposed operand) over (min,+)
+                              or int64 (+,x), each operand applied at most once since the last
+                              update: 0 automatic (see below); 1 always whole rows; 2
+                              entry-granular whenever it applies.  Same results every way. */
   int32_t batch_direct_log2; /* batched form: products whose C holds at least 2^this slots take the
                               plain path beside the graph replay (default 24; 0..62) */
   /* Automatic choice: the entry-granular path runs when the products of the
@@ -165,13 +166,13 @@ typedef struct {
    * products).  Defaults 1e8 and 70 (fitted on MI355X); both finite, >= 0. */
   double entry_fixed;
   double entry_per_term;
-  int32_t row_index;       /* 1 (default): the entry-granular path gives C and A a per-row column
+  int32_t row_index;       /* 1 (default): the entry-granular path gives C, A and B a per-row column
                               index (Section 4's per-row hash; about 20 bytes per entry of C).  The
                               index pools of a context take at most 1/8 of the device, and only
                               memory that stays free beyond a reserve (and at most half of what a
-                              budget leaves); without room for A's index the row path runs.
-                              0: never (applies stream the touched rows; the entry path's lost
-                              entries scan rows of A') */
+                              budget leaves); without room for the operands' indexes the row path
+                              runs.  0: never (applies stream the touched rows; the entry path's
+                              lost entries scan rows of A' and B') */
 } dsg_tuning;
 dsg_status dsg_ctx_get_tuning(const dsg_ctx* ctx, dsg_tuning* t);
 /* t == NULL restores the defaults.  DSG_E_ARG for thresholds outside the
