@@ -1,5 +1,5 @@
-// Entry-granular dynamic update of C = A*B (and A*A) over (min,+) fp32 and
-// (+,x) int64.
+// Entry-granular dynamic update of C = A*B (and A*A) over (min,+) fp32,
+// (+,x) int64 and (or, and) on 32-bit words.
 //
 // Section 5 writes the new product as the old one combined with the products
 // that involve changed entries (Eq. 1), and observes that C can change only
@@ -17,8 +17,10 @@
 //                 minimum and no new value reaches it.  Then the entry is
 //                 recomputed.  Using the stored minimum as a witness this way
 //                 is this library's addition.
+//   (or, and)     c' = c | (OR of the changed products' new words), unless a
+//                 product vanished or lost bits: then the entry is recomputed.
 //
-// A recomputed entry takes the minimum (or sum) of a'_ik * b'_kj over k, from
+// A recomputed entry takes the minimum (sum, OR) of a'_ik * b'_kj over k, from
 // the shorter of row i of A' and column j of B': each k of that list is
 // looked up in the per-row column index (rowindex.h) of B' or A', and column
 // j comes from B's valued transpose.  C keeps a column index too, so the
@@ -332,6 +334,23 @@ __global__ void k_seg_reduce(const uint64_t* key, const uint32_t* idx, const uin
     ((V*)cval)[s] = has_new ? f32_unkey(nmin) : 0.0f;
     cguard[s] = wmin;
     cflag[s] = (has_new ? 1 : 0) | (has_w ? 2 : 0);
+  } else if constexpr (SR == 3) {
+    // (or, and) on words: the OR of the new products; a product that vanished
+    // or lost bits makes the entry lost (those bits may have come from it
+    // alone)
+    uint32_t orw = 0;
+    bool any = false, lost = false;
+    for (int64_t t = t0; t < t1; ++t) {
+      const uint32_t q = idx[t];
+      const uint8_t f = tfl[q];
+      const uint32_t o = (uint32_t)told[q], w = (uint32_t)tnew[q];
+      if (f & F_NEW) orw |= w;
+      any = any || f != 0;
+      lost = lost || ((f & F_OLD) && (!(f & F_NEW) || (o & ~w) != 0u));
+    }
+    ((V*)cval)[s] = (V)orw;
+    cguard[s] = 0;
+    cflag[s] = (any ? 1 : 0) | (lost ? 4 : 0);
   } else {
     // (+,x) int64: the sum of the changes; a vanished product makes the entry lost
     unsigned long long delta = 0;
@@ -351,7 +370,7 @@ __global__ void k_seg_reduce(const uint64_t* key, const uint32_t* idx, const uin
 }
 
 // ---- 5. lost entries ----
-// A lost entry (i, j) takes the minimum (or sum) of a'_ik * b'_kj over k from
+// A lost entry (i, j) takes the minimum (sum, OR) of a'_ik * b'_kj over k from
 // the shorter of two lists: row i of A' (each k probed for column j in the
 // column index of row k of B') or column j of B' (each k probed for column k
 // in the column index of row i of A').  Entries are split into three classes by that length (up
@@ -380,6 +399,7 @@ __device__ inline unsigned long long acc_id() {
 template <int SR>
 __device__ inline unsigned long long acc_comb(unsigned long long a, unsigned long long b) {
   if constexpr (SR == 1) return a < b ? a : b;
+  else if constexpr (SR == 3) return a | b;
   else return a + b;
 }
 
@@ -553,7 +573,7 @@ bool changed_once(const DMat* m, uint64_t seq) {
 bool eligible(const DProd* p) {
   const DMat* A = p->A;
   const DMat* B = p->B;
-  if (p->ops || (A->sr != 0 && A->sr != 1) || B->sr != A->sr) return false;
+  if (p->ops || (A->sr != 0 && A->sr != 1 && A->sr != 3) || B->sr != A->sr) return false;
   if (p->ctx->tuning.update_path == 1) return false;
   if (B == A) return changed_once(A, p->a_seq);
   const bool ca = changed_once(A, p->a_seq), cb = changed_once(B, p->b_seq);
@@ -850,4 +870,10 @@ bool entry_eligible(DProd* p) {
 
 const int64_t* entry_count(DProd* p) { return count_terms(p); }
 
-int32_t entry_finish(DProd* p) { return p->A->sr == 1 ? entry_update<1>(p) : entry_update<0>(p); }
+int32_t entry_finish(DProd* p) {
+  switch (p->A->sr) {
+    case 1: return entry_update<1>(p);
+    case 3: return entry_update<3>(p);
+    default: return entry_update<0>(p);
+  }
+}

@@ -1,5 +1,5 @@
-"""GPU: the entry-granular dynamic update of C = A*A ((min,+) fp32 and int64
-(+,x)) gives the oracle's C bit for bit and reports exactly the rows whose
+"""GPU: the entry-granular dynamic update of C = A*A and A*B ((min,+) fp32,
+int64 (+,x) and bitwise (or, and)) gives the oracle's C bit for bit and reports exactly the rows whose
 content changed, like the row path; it takes over only when C reflects
 every apply but the last one."""
 import sys
@@ -14,8 +14,8 @@ from paper_2202_08808_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-SRS = [I.PLUS_TIMES_I64, I.MIN_PLUS_F32]
-SR_ID = {I.PLUS_TIMES_I64: "i64", I.MIN_PLUS_F32: "minplus"}
+SRS = [I.PLUS_TIMES_I64, I.MIN_PLUS_F32, I.OR_AND_U32]
+SR_ID = {I.PLUS_TIMES_I64: "i64", I.MIN_PLUS_F32: "minplus", I.OR_AND_U32: "orand"}
 
 
 def say(msg):
@@ -127,7 +127,7 @@ def test_entry_vanishing_entries(ctx, sr):
     # 0->1->2 (one path), 3->4->5 and 3->6->5 (two paths)
     edges = {(0, 1): 2, (1, 2): 3, (3, 4): 1, (4, 5): 1, (3, 6): 5, (6, 5): 5}
     keys = np.array(sorted(i * n + j for i, j in edges), np.int64)
-    vdt = np.int64 if sr == I.PLUS_TIMES_I64 else np.float32
+    vdt = I.VALUE_DTYPE[sr]
     vals = np.array([edges[(int(k) // n, int(k) % n)] for k in keys]).astype(vdt)
     A = I.csr_from_keys(n, n, keys, vals)
     dels = I.Batch(np.array([0, 4], np.int32), np.array([1, 5], np.int32),
