@@ -155,7 +155,7 @@ typedef struct {
                               it needs at most this many column passes, else a global-memory hash */
   int32_t force_bin;       /* -1: automatic; 0..7 group bin; 8 dense; 9 global hash (for tests;
                               a group bin is only used for rows that fit it) */
-  int32_t update_path;     /* dynamic updates of C = A*A or A*B (no transposed operand) over (min,+),
+  int32_t update_path;     /* dynamic updates of C = op(A)*op(B) (no Bloom matrix) over (min,+),
                               int64 (+,x) or (or, and), each operand applied at most once since the last
                               update: 0 automatic (see below); 1 always whole rows; 2
                               entry-granular whenever it applies.  Same results every way. */

@@ -1,5 +1,8 @@
-// Entry-granular dynamic update of C = A*B (and A*A) over (min,+) fp32,
-// (+,x) int64 and (or, and) on 32-bit words.
+// Entry-granular dynamic update of C = op(A)*op(B) (B may be A, either may be
+// transposed) over (min,+) fp32, (+,x) int64 and (or, and) on 32-bit words.
+// Below, A and B name op(A) and op(B): a transposed operand reads its rows
+// from the matrix's transpose index, its columns from the matrix, and its
+// changes from the transpose index's log.
 //
 // Section 5 writes the new product as the old one combined with the products
 // that involve changed entries (Eq. 1), and observes that C can change only
@@ -564,41 +567,70 @@ int64_t read_count(Ctx* c, const int64_t* d) {
   return *h;
 }
 
-// An operand applied once since the last update, with the log of that
-// apply; or not applied since.
-bool changed_once(const DMat* m, uint64_t seq) {
-  return m->log_seq != 0 && m->log_seq == m->apply_seq && m->apply_seq == seq + 1;
+// One operand of the product as the entry path sees it: the matrix whose
+// rows it reads (op(X): X, or X's transpose index), the matrix holding its
+// columns as rows (X's transpose index, or X itself), the matrix whose log
+// lists its changes in its own coordinates (the transpose index keeps the
+// transposed log of every apply), the source matrix that counts applies, and
+// the apply count the product last reflected.
+struct OpView {
+  DMat* rows;
+  DMat* cols;
+  const DMat* logm;
+  const DMat* src;
+  uint64_t seq;
+};
+
+OpView op_view(const DProd* p, bool left) {
+  const bool trans = (p->ops & (left ? DSG_TRANS_A : DSG_TRANS_B)) != 0;
+  DMat* src = left ? p->src_a : p->src_b;
+  OpView v;
+  v.rows = left ? p->A : p->B;
+  v.cols = trans ? src : src->tidx;
+  v.logm = trans ? src->tidx : src;
+  v.src = src;
+  v.seq = left ? p->a_seq : p->b_seq;
+  return v;
 }
+
+// An operand applied once since the last update, with the log of that apply
+// (in its own coordinates); or not applied since.
+bool changed_once(const OpView& v) {
+  return v.logm && v.src->log_seq != 0 && v.src->log_seq == v.src->apply_seq && v.logm->log_seq == v.src->apply_seq &&
+         v.src->apply_seq == v.seq + 1;
+}
+bool unchanged(const OpView& v) { return v.src->apply_seq == v.seq; }
 
 bool eligible(const DProd* p) {
   const DMat* A = p->A;
   const DMat* B = p->B;
-  if (p->ops || (A->sr != 0 && A->sr != 1 && A->sr != 3) || B->sr != A->sr) return false;
+  if (p->bloom || (A->sr != 0 && A->sr != 1 && A->sr != 3) || B->sr != A->sr) return false;
   if (p->ctx->tuning.update_path == 1) return false;
-  if (B == A) return changed_once(A, p->a_seq);
-  const bool ca = changed_once(A, p->a_seq), cb = changed_once(B, p->b_seq);
-  const bool ua = A->apply_seq == p->a_seq, ub = B->apply_seq == p->b_seq;
-  return (ca || ua) && (cb || ub) && (ca || cb);
+  const OpView l = op_view(p, true), r = op_view(p, false);
+  if (B == A) return changed_once(l);
+  return (changed_once(l) || unchanged(l)) && (changed_once(r) || unchanged(r)) && (changed_once(l) || changed_once(r));
 }
 
-// The two logs of the pending update: A's changed entries (left factors) and
-// B's (right factors); an operand not applied since the last update has an
-// empty one.  For C = A*A both are A's log.
+// The two logs of the pending update: op(A)'s changed entries (left factors)
+// and op(B)'s (right factors); an operand not applied since the last update
+// has an empty one.  For C = A*A both are A's log.
 struct EntryLogs {
   Log LA, LB;
-  int abits, bbits;  // column bits of A's and B's keys (B's are C's too)
+  int abits, bbits;  // column bits of op(A)'s and op(B)'s keys (op(B)'s are C's too)
 };
 
 EntryLogs entry_logs(const DProd* p) {
-  const DMat* A = p->A;
-  const DMat* B = p->B;
-  const bool ca = B == A || A->apply_seq != p->a_seq;
-  const bool cb = B == A || B->apply_seq != p->b_seq;
+  const OpView l = op_view(p, true), r = op_view(p, false);
+  const bool same = p->B == p->A;
+  const bool ca = same || !unchanged(l);
+  const bool cb = same || !unchanged(r);
+  const DMat* la = l.logm;
+  const DMat* lb = r.logm;
   EntryLogs g;
-  g.LA = Log{A->log_key, A->log_old, A->log_new, A->log_code, ca ? A->h_log_n : 0};
-  g.LB = Log{B->log_key, B->log_old, B->log_new, B->log_code, cb ? B->h_log_n : 0};
-  g.abits = bits_for(A->ncols);
-  g.bbits = bits_for(B->ncols);
+  g.LA = Log{la->log_key, la->log_old, la->log_new, la->log_code, ca ? la->h_log_n : 0};
+  g.LB = Log{lb->log_key, lb->log_old, lb->log_new, lb->log_code, cb ? lb->h_log_n : 0};
+  g.abits = bits_for(p->A->ncols);
+  g.bbits = bits_for(p->B->ncols);
   return g;
 }
 
@@ -607,8 +639,8 @@ EntryLogs entry_logs(const DProd* p) {
 const int64_t* count_terms(DProd* p) {
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
-  DMat* A = p->A;
   DMat* B = p->B;
+  DMat* TA = op_view(p, true).cols;  // columns of op(A)'
   const EntryLogs g = entry_logs(p);
   const int64_t nU = g.LA.n + g.LB.n;
   const size_t b1 = Carve::need(
@@ -622,7 +654,7 @@ const int64_t* count_terms(DProd* p) {
   if (nU > 0) {
     Phase ph(c, "entry_count");
     hipLaunchKernelGGL(k_term_counts, dim3(blocks_for(nU, 256)), dim3(256), 0, s, g.LA, g.LB, g.abits, g.bbits,
-                       (const int32_t*)B->row_len, (const int32_t*)A->tidx->row_len, cnt, rng);
+                       (const int32_t*)B->row_len, (const int32_t*)TA->row_len, cnt, rng);
     exclusive_scan_i64(cnt, off, nU, d_total, scan1, s);
   } else {
     hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, s, d_total);
@@ -637,10 +669,10 @@ int32_t entry_update(DProd* p) {
   using V = typename Sem<SR>::V;
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
-  DMat* A = p->A;
+  DMat* A = p->A;  // op(A), op(B): rows
   DMat* B = p->B;
-  DMat* TA = A->tidx;  // columns of A'
-  DMat* TB = B->tidx;  // columns of B'
+  DMat* TA = op_view(p, true).cols;   // columns of op(A)'
+  DMat* TB = op_view(p, false).cols;  // columns of op(B)'
   DMat* C = p->C;
   const int32_t n = A->nrows;
   const EntryLogs g = entry_logs(p);
@@ -845,13 +877,14 @@ int32_t entry_update(DProd* p) {
 }  // namespace
 
 bool entry_eligible(DProd* p) {
-  if (!eligible(p)) return false;
-  // the products of B's changed entries run over columns of A', and the lost
-  // entries over columns of B': both need the operand's valued transpose
-  // (A's exists for the discovery; B's is built here on first use, and every
-  // later apply of B keeps it)
-  for (DMat* m : {p->A, p->B}) {
+  // the products of op(B)'s changed entries run over columns of op(A)', and
+  // the lost entries over columns of op(B)': both need that operand's columns
+  // as rows, with values -- the matrix itself for a transposed operand, else
+  // its valued transpose index (A's exists for the discovery; B's is built
+  // here on first use, and every later apply of B keeps it, with its log)
+  for (DMat* m : {p->src_a, p->src_b}) {
     if (!m->tidx) {
+      if (!eligible(p)) return false;
       try {
         mat_build_transpose(m);
       } catch (const DsgError& e) {
@@ -861,6 +894,7 @@ bool entry_eligible(DProd* p) {
     }
     if (!m->tidx || m->tidx->vsz != m->vsz) return false;
   }
+  if (!eligible(p)) return false;
   // the lost entries probe rows of A' and B' through their column indexes:
   // without them (no room) the row path runs instead; with the index
   // switched off the probes scan the rows

@@ -1746,6 +1746,7 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   Work wt;
   if (deltas) wt = carve_work(ctx_scratch2(c, work_bytes(n, false)), n, false);
   reserve_log(m, n);
+  if (deltas) reserve_log(m->tidx, n);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool timed = c->timing && ctx_timing_begin(c, "apply", 0.0, &e0, &e1);
   const size_t tslot = c->timings.size() - (timed ? 1 : 0);
@@ -1757,6 +1758,9 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   }
   apply_pipeline(m, d_rows, d_cols, d_vals, d_ops, n, w, deltas ? &wt : nullptr, false, timed);
   keep_log(m, w, n);
+  // (and the transpose index's own: the same changes keyed by column, for a
+  // product that uses the matrix transposed)
+  if (deltas) keep_log(m->tidx, wt, n);
   if (c->timing) ctx_timing_end(c, e1);
   if (timed) {
     DSG_HIP(hipMemcpyAsync(touched, w.demand + 2, 8, hipMemcpyDeviceToHost, s));
@@ -1771,10 +1775,12 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   F.add(w.err, 4, 0);
   F.add(deltas ? (const void*)wt.err : nullptr, 4, 4);
   F.add(w.nU, 8, 64);
+  F.add(deltas ? (const void*)wt.nU : nullptr, 8, 72);
   fetch_to_pinned(c, F, s);
   DSG_HIP(hipStreamSynchronize(s));
   DSG_REQUIRE(h[0] == 0 && h[1] == 0, DSG_E_DEVICE, "internal: pool overflow while applying a batch");
-  m->h_log_n = *hn;
+  m->h_log_n = hn[0];
+  if (deltas) m->tidx->h_log_n = hn[1];
   if (timed && tslot < c->timings.size()) {
     // algorithmic bytes: the batch read (row, column, value, op), the touched
     // rows streamed by the plan, the unique updates written; for the
@@ -1789,4 +1795,5 @@ void mat_apply_device(DMat* m, const int32_t* d_rows, const int32_t* d_cols, con
   }
   m->apply_seq++;
   m->log_seq = m->apply_seq;
+  if (deltas) m->tidx->log_seq = m->apply_seq;  // (its own apply count is not kept: the matrix's stands for it)
 }

@@ -245,15 +245,22 @@ def test_automatic_path_choice(ctx, sr):
     assert chosen == [1, 0]
 
 
-def run_ab(ctx, sr, A, B, steps, use_row_path=False):
-    """C = A*B: each step applies a batch to A, to B or to both, then
-    updates; C and the reported rows against the oracle after every step."""
+def run_ab(ctx, sr, A, B, steps, use_row_path=False, trans_a=False, trans_b=False, same=False):
+    """C = op(A)*op(B) (same: B is A, one matrix): each step applies a batch
+    to A, to B or to both, then updates; C and the reported rows against the
+    oracle after every step."""
     row_path(ctx, use_row_path)
     ma = dsg.Matrix.from_csr(ctx, A, sr)
-    mb = dsg.Matrix.from_csr(ctx, B, sr)
-    P = dsg.Product(ctx, ma, mb)
+    mb = ma if same else dsg.Matrix.from_csr(ctx, B, sr)
+    P = dsg.Product(ctx, ma, mb, trans_a=trans_a, trans_b=trans_b)
     a, b = oracle.Csr.of(A), oracle.Csr.of(B)
-    C = oracle.spgemm(sr, a, b, nthreads=THREADS)
+
+    def want_of(a, b):
+        x = oracle.transpose(a) if trans_a else a
+        y = oracle.transpose(b) if trans_b else b
+        return oracle.spgemm(sr, x, y, nthreads=THREADS)
+
+    C = want_of(a, a if same else b)
     stats = []
     for t, (ba, bb) in enumerate(steps):
         if ba is not None:
@@ -263,7 +270,7 @@ def run_ab(ctx, sr, A, B, steps, use_row_path=False):
             mb.apply_batch(bb)
             b, _ = oracle.apply(sr, b, bb.rows, bb.cols, bb.vals, bb.ops)
         rs = P.update()
-        want = oracle.spgemm(sr, a, b, nthreads=THREADS)
+        want = want_of(a, a if same else b)
         assert_same_csr(sr, P.export(), want, f"step {t}")
         assert np.array_equal(rs.row_ids(), changed_rows(C, want)), f"step {t}: reported rows"
         st = P.stats()
@@ -273,7 +280,8 @@ def run_ab(ctx, sr, A, B, steps, use_row_path=False):
         C = want
     P.destroy()
     ma.destroy()
-    mb.destroy()
+    if not same:
+        mb.destroy()
     ctx.set_tuning(None)
     return stats
 
@@ -297,3 +305,27 @@ def test_entry_a_times_b(ctx, sr):
     st = run_ab(ctx, sr, A, B, steps)
     assert sum(s["lost"] for s in st) > 0
     run_ab(ctx, sr, A, B, steps, use_row_path=True)
+
+
+@pytest.mark.parametrize("sr", SRS, ids=lambda s: SR_ID[s])
+def test_entry_transposed_operands(ctx, sr):
+    """The entry path on transposed operands (each operand's changes read
+    from its transpose index's log): C = A^T*B with batches to A alone, B
+    alone and both; C = A*A^T and C = A^T*A^T with batches to A; the row path
+    on the first for comparison."""
+    say(f"entry path transposed {SR_ID[sr]}")
+    hi = 9 if sr == I.PLUS_TIMES_I64 else 100
+    A = I.rmat_csr(10, 8, sr, stream=831, lo=1, hi=hi)
+    rng = np.random.default_rng(832)
+    n, m = A.nrows, A.nrows + A.nrows // 2
+    keys = np.unique(rng.integers(0, n, 10 * n, dtype=np.int64) * m + rng.integers(0, m, 10 * n, dtype=np.int64))
+    B = I.csr_from_keys(n, m, keys, I.draw_values(sr, keys.size, rng, 1, hi))
+    ba = I.disjoint_batches(A, sr, [20, 400, 1500, 60], stream=833, value_lo=1, value_hi=hi)
+    bb = I.disjoint_batches(B, sr, [30, 300, 50, 900], stream=834, value_lo=1, value_hi=hi)
+    steps = [(ba[0], None), (None, bb[0]), (ba[1], bb[1]), (ba[2], None), (None, bb[2]), (ba[3], bb[3])]
+    st = run_ab(ctx, sr, A, B, steps, trans_a=True)
+    assert sum(s["lost"] for s in st) > 0
+    run_ab(ctx, sr, A, B, steps, trans_a=True, use_row_path=True)
+    only_a = [(b, None) for b in ba]
+    run_ab(ctx, sr, A, A, only_a, trans_b=True, same=True)
+    run_ab(ctx, sr, A, A, only_a, trans_a=True, trans_b=True, same=True)
