@@ -466,7 +466,6 @@ __device__ inline void lost_recompute(const LostArgs& L, const int32_t* list, in
   // (the G lanes of a group share q0, so each group runs its rounds together
   // and its shuffles see all of its lanes)
   for (int64_t q0 = (b * blockDim.x + threadIdx.x) / G; q0 < n; q0 += ng) {
-    const bool act = true;
     const int64_t e = list[q0];
     const int32_t i = (int32_t)(L.key[e] >> L.cbits);
     const int32_t j = (int32_t)(L.key[e] & cmask);
@@ -474,30 +473,28 @@ __device__ inline void lost_recompute(const LostArgs& L, const int32_t* list, in
     const int32_t lj = L.TB.len[j];
     unsigned long long acc = acc_id<SR>();
     uint32_t hits = 0;
-    if (act) {
-      const int64_t aoff = L.A.off[i];
-      if (d <= lj) {
-        // row i of A': is column j in row k of B'?
-        for (int32_t t = l; t < d; t += G) {
-          const int32_t k = L.A.col[aoff + t];
-          const int32_t pos = a_find(L.XB, L.B, k, j);
-          if (pos >= 0) {
-            const V a = ldv<V>(L.A.val, aoff + t), b = ldv<V>(L.B.val, L.B.off[k] + pos);
-            acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
-            ++hits;
-          }
+    const int64_t aoff = L.A.off[i];
+    if (d <= lj) {
+      // row i of A': is column j in row k of B'?
+      for (int32_t t = l; t < d; t += G) {
+        const int32_t k = L.A.col[aoff + t];
+        const int32_t pos = a_find(L.XB, L.B, k, j);
+        if (pos >= 0) {
+          const V a = ldv<V>(L.A.val, aoff + t), b = ldv<V>(L.B.val, L.B.off[k] + pos);
+          acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
+          ++hits;
         }
-      } else {
-        // column j of B': is column k in row i of A'?
-        const int64_t toff = L.TB.off[j];
-        for (int32_t t = l; t < lj; t += G) {
-          const int32_t k = L.TB.col[toff + t];
-          const int32_t pos = a_find(L.XA, L.A, i, k);
-          if (pos >= 0) {
-            const V a = ldv<V>(L.A.val, aoff + pos), b = ldv<V>(L.TB.val, toff + t);
-            acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
-            ++hits;
-          }
+      }
+    } else {
+      // column j of B': is column k in row i of A'?
+      const int64_t toff = L.TB.off[j];
+      for (int32_t t = l; t < lj; t += G) {
+        const int32_t k = L.TB.col[toff + t];
+        const int32_t pos = a_find(L.XA, L.A, i, k);
+        if (pos >= 0) {
+          const V a = ldv<V>(L.A.val, aoff + pos), b = ldv<V>(L.TB.val, toff + t);
+          acc = acc_comb<SR>(acc, (unsigned long long)Sem<SR>::mul(a, b));
+          ++hits;
         }
       }
     }
@@ -506,7 +503,7 @@ __device__ inline void lost_recompute(const LostArgs& L, const int32_t* list, in
       acc = acc_comb<SR>(acc, __shfl_xor(acc, x, 64));
       hits += __shfl_xor(hits, x, 64);
     }
-    if (act && l == 0) finish_entry<SR>(L, e, acc, hits);
+    if (l == 0) finish_entry<SR>(L, e, acc, hits);
   }
 }
 
