@@ -496,9 +496,10 @@ FORMS = [("minplus", False, False), ("minplus", True, False), ("minplus", False,
 def bench_forms(args):
     """Operand forms and semirings on one R-MAT graph (scale 16, edge factor
     16, the default workload's structure and batch recipe): per batch size,
-    ms per step of the dynamic update (apply + update, row path) and of a
-    static recompute, for C = A A, A^T A and A A^T over (min,+) and the
-    bitwise (or, and) semiring on 32-bit words."""
+    ms per step of the dynamic update (apply + update) on the row path and
+    with the automatic path choice (entry-granular where the cost rule takes
+    it), and of a static recompute, for C = A A, A^T A and A A^T over (min,+)
+    and the bitwise (or, and) semiring on 32-bit words."""
     import torch
     from paper_2202_08808_amd import dsg
     from paper_2202_08808_amd import inputs as I
@@ -513,39 +514,46 @@ def bench_forms(args):
                                     value_lo=lo, value_hi=hi)
             batches = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in (q.rows, q.cols, q.vals, q.ops))
                        for q in bs]
-            ctx = dsg.Context(0, stream=torch.cuda.current_stream(dev))
-            t = ctx.get_tuning()
-            t.update_path = 1
-            ctx.set_tuning(t)
-            A = dsg.Matrix.from_csr(ctx, A0, sr)
-            P = dsg.Product(ctx, A, A, trans_a=ta, trans_b=tb)
-            ts = []
-            for k in range(args.warmup + args.steps):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                A.apply(*batches[k])
-                P.update()
-                torch.cuda.synchronize()
-                if k >= args.warmup:
-                    ts.append(time.perf_counter() - t0)
-            st = P.stats()
-            rec = {"batch": b, "semiring": name, "form": ("At" if ta else "A") + ("At" if tb else "A"),
-                   "ms": round(float(np.median(ts)) * 1e3, 4), "updates_per_s": round(b / float(np.median(ts)), 1),
-                   "affected_rows": st["affected_rows"], "flops": st["flops"], "nnz_c": P.nnz()}
-            ts = []
-            for _ in range(3):
-                torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                P.recompute_static()
-                torch.cuda.synchronize()
-                ts.append(time.perf_counter() - t0)
-            rec["static_ms"] = round(float(np.median(ts)) * 1e3, 4)
+            rec = {"batch": b, "semiring": name, "form": ("At" if ta else "A") + ("At" if tb else "A")}
+            for mode, key in ((1, "ms"), (0, "auto_ms")):
+                ctx = dsg.Context(0, stream=torch.cuda.current_stream(dev))
+                t = ctx.get_tuning()
+                t.update_path = mode
+                ctx.set_tuning(t)
+                A = dsg.Matrix.from_csr(ctx, A0, sr)
+                P = dsg.Product(ctx, A, A, trans_a=ta, trans_b=tb)
+                ts, paths = [], []
+                for k in range(args.warmup + args.steps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    A.apply(*batches[k])
+                    P.update()
+                    torch.cuda.synchronize()
+                    if k >= args.warmup:
+                        ts.append(time.perf_counter() - t0)
+                        paths.append(P.stats()["path"])
+                rec[key] = round(float(np.median(ts)) * 1e3, 4)
+                if mode == 1:
+                    st = P.stats()
+                    rec.update({"updates_per_s": round(b / float(np.median(ts)), 1),
+                                "affected_rows": st["affected_rows"], "flops": st["flops"], "nnz_c": P.nnz()})
+                    ts = []
+                    for _ in range(3):
+                        torch.cuda.synchronize()
+                        t0 = time.perf_counter()
+                        P.recompute_static()
+                        torch.cuda.synchronize()
+                        ts.append(time.perf_counter() - t0)
+                    rec["static_ms"] = round(float(np.median(ts)) * 1e3, 4)
+                else:
+                    rec["auto_entry_steps"] = int(sum(1 for x in paths if x == 1))
+                P.destroy()
+                A.destroy()
+                ctx.close()
             rec["speedup"] = round(rec["static_ms"] / rec["ms"], 3)
+            rec["speedup_auto"] = round(rec["static_ms"] / rec["auto_ms"], 3)
             log(f"[forms] {json.dumps(rec)}")
             out.append(rec)
-            P.destroy()
-            A.destroy()
-            ctx.close()
     print(json.dumps({"workload": "forms", "sweep": out}), flush=True)
 
 
