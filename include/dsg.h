@@ -240,20 +240,19 @@ dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod
  * the entries of C* from the columns k of A' that R lets through, and merges
  * the new entries and bits into C and F.  When an operand took more than one
  * apply since the last update (the change logs hold one apply), the row path
- * runs and F is rebuilt.  Not with DSG_TRANS_A / DSG_TRANS_B
- * (DSG_E_UNSUPPORTED), nor in the batched form.  Results equal those of the
- * other paths. */
+ * runs and F is rebuilt.  Combines with DSG_TRANS_A / DSG_TRANS_B (then A
+ * and B above are op(A) and op(B)); not in the batched form.  Results equal
+ * those of the other paths. */
 #define DSG_GENERAL_BLOOM 0x4u
 
 /* Create C = op(A) op(B), op(X) = X^T when ops holds X's flag, and compute
  * it from scratch.  A transposed operand is read from its transpose index,
  * which every apply of the matrix keeps current (the index is built here if
  * the matrix has none), so updates are applied to A and B as usual and
- * dsg_prod_update recomputes the rows that op(A)'s changed rows and op(B)'s
- * changed rows reach.  Products with a transposed operand always take the
- * row path (never the entry-granular one).  Errors: DSG_E_ARG (unknown flag),
- * DSG_E_STATE (semiring mismatch, inner dimensions of op(A) and op(B)
- * differ). */
+ * dsg_prod_update brings C up to date from op(A)'s and op(B)'s changes by
+ * any of the update paths (dsg_tuning.update_path).  Errors: DSG_E_ARG
+ * (unknown flag), DSG_E_STATE (semiring mismatch, inner dimensions of op(A)
+ * and op(B) differ). */
 dsg_status dsg_prod_create(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, uint32_t ops, dsg_prod** out);
 
 /* Canonical host CSR of a DSG_GENERAL_BLOOM product's Bloom matrix F (same

@@ -591,8 +591,6 @@ extern "C" dsg_status dsg_prod_create(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, uint
   if (!out || !A || !B || !A->alive || !B->alive) return fail(ctx, DSG_E_ARG, "NULL or destroyed argument");
   *out = nullptr;
   if (ops & ~(uint32_t)(DSG_TRANS_A | DSG_TRANS_B | DSG_GENERAL_BLOOM)) return fail(ctx, DSG_E_ARG, "unknown operand flag");
-  if ((ops & DSG_GENERAL_BLOOM) && (ops & (DSG_TRANS_A | DSG_TRANS_B)))
-    return fail(ctx, DSG_E_UNSUPPORTED, "general updates with the Bloom matrix take untransposed operands");
   if (A->owner != ctx || B->owner != ctx) return fail(ctx, DSG_E_STATE, "operands belong to another context");
   if (A->m->sr != B->m->sr) return fail(ctx, DSG_E_STATE, "semiring mismatch");
   const int32_t inner_a = (ops & DSG_TRANS_A) ? A->m->nrows : A->m->ncols;

@@ -564,39 +564,6 @@ int64_t read_count(Ctx* c, const int64_t* d) {
   return *h;
 }
 
-// One operand of the product as the entry path sees it: the matrix whose
-// rows it reads (op(X): X, or X's transpose index), the matrix holding its
-// columns as rows (X's transpose index, or X itself), the matrix whose log
-// lists its changes in its own coordinates (the transpose index keeps the
-// transposed log of every apply), the source matrix that counts applies, and
-// the apply count the product last reflected.
-struct OpView {
-  DMat* rows;
-  DMat* cols;
-  const DMat* logm;
-  const DMat* src;
-  uint64_t seq;
-};
-
-OpView op_view(const DProd* p, bool left) {
-  const bool trans = (p->ops & (left ? DSG_TRANS_A : DSG_TRANS_B)) != 0;
-  DMat* src = left ? p->src_a : p->src_b;
-  OpView v;
-  v.rows = left ? p->A : p->B;
-  v.cols = trans ? src : src->tidx;
-  v.logm = trans ? src->tidx : src;
-  v.src = src;
-  v.seq = left ? p->a_seq : p->b_seq;
-  return v;
-}
-
-// An operand applied once since the last update, with the log of that apply
-// (in its own coordinates); or not applied since.
-bool changed_once(const OpView& v) {
-  return v.logm && v.src->log_seq != 0 && v.src->log_seq == v.src->apply_seq && v.logm->log_seq == v.src->apply_seq &&
-         v.src->apply_seq == v.seq + 1;
-}
-bool unchanged(const OpView& v) { return v.src->apply_seq == v.seq; }
 
 bool eligible(const DProd* p) {
   const DMat* A = p->A;

@@ -10,7 +10,8 @@
 //                   (i, j) and reduced to C* and F*.  A* holds the entries the
 //                   last apply of A changed (deletions included), B* those of
 //                   B; B's old row k is B' row k plus the entries of row k that
-//                   apply deleted, A' column k is a row of A's transpose index.
+//                   apply deleted, A' column k is a row of A's transpose index
+//                   (of A itself when the product reads A^T).
 //                   Entries of B' row k that the apply inserted make the pattern
 //                   a superset, which the masked product below resolves.
 //   E, R            r_i = the bitwise or over (i, j) in C* of f*_ij | f_ij
@@ -23,6 +24,10 @@
 //                   entries checked before each addition), H the new bits.
 //   merges          Z into C and H into F at C*: SET where a term exists,
 //                   DELETE where none does, through the ordinary apply.
+// A and B above stand for op(A) and op(B) (Section 5, transposition): a
+// transposed operand's rows are its transpose index's, its log is the one
+// that index keeps of every apply, in the transposed coordinates, and its
+// columns as rows are the source matrix itself.
 // Semiring additions that are exactly associative combine with atomics in
 // any order; fp64 sums take the kept k of a row one at a time in ascending k,
 // so every c'_ij is summed in the order of its definition.
@@ -544,23 +549,21 @@ void check_err(Ctx* c, const int* d_err) {
   DSG_REQUIRE(h[0] == 0, DSG_E_DEVICE, "internal: masked product error " + std::to_string(h[0]));
 }
 
-// The log of X's applies since the product last saw it: its last apply's log,
-// or nothing when X was not applied since.
-bool fresh_log(const DMat* X, uint64_t seen) {
-  return X->apply_seq == seen || (X->log_seq != 0 && X->log_seq == X->apply_seq && X->apply_seq == seen + 1);
-}
+// op(X)'s log since the product last saw X: the log of X's last apply in
+// op(X)'s coordinates (X's own, or its transpose index's), or nothing when X
+// was not applied since.
+bool fresh_log(const OpView& v) { return unchanged(v) || changed_once(v); }
 
-LogView log_since(const DMat* X, uint64_t seen) {
-  LogView L{X->log_key, X->log_code, X->apply_seq == seen ? 0 : X->h_log_n, bits_for(X->ncols)};
+LogView log_since(const OpView& v) {
+  LogView L{v.logm->log_key, v.logm->log_code, unchanged(v) ? 0 : v.logm->h_log_n, bits_for(v.logm->ncols)};
   return L;
 }
 
 }  // namespace
 
 bool general_eligible(const DProd* p) {
-  if (!p->F || p->ops) return false;
-  if (p->A == p->B) return fresh_log(p->A, p->a_seq);
-  return fresh_log(p->A, p->a_seq) && fresh_log(p->B, p->b_seq);
+  if (!p->F) return false;
+  return fresh_log(op_view(p, true)) && fresh_log(op_view(p, false));
 }
 
 // F from scratch: the masked product over C's whole structure with every k
@@ -606,7 +609,8 @@ int32_t general_update(DProd* p) {
   DMat* A = p->A;
   DMat* B = p->B;
   DMat* C = p->C;
-  DMat* T = A->tidx;
+  const OpView l = op_view(p, true), r = op_view(p, false);
+  DMat* T = l.cols;  // columns of op(A)' as rows
   DSG_REQUIRE(T && p->F, DSG_E_STATE, "internal: Bloom product without transpose index or F");
   mat_index_invalidate(C);  // the masked merges rewrite rows of C
   const int32_t n = C->nrows;
@@ -615,8 +619,8 @@ int32_t general_update(DProd* p) {
   dsg_update_stats& st = p->stats;
   st = dsg_update_stats{};
   st.path = 2;
-  const LogView LA = log_since(A, p->a_seq);
-  const LogView LB = A == B ? LA : log_since(B, p->b_seq);
+  const LogView LA = log_since(l);
+  const LogView LB = A == B ? LA : log_since(r);
   const int64_t nL = LA.n + LB.n;
 
   // ---- computePattern: count and write the terms ----

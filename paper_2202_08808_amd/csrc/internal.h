@@ -261,7 +261,8 @@ int64_t mat_nnz(DMat* m);
 // Canonical (column-sorted) CSR copy on the device: row_ptr[nrows+1], col, val.
 void mat_export_device(DMat* m, int64_t* d_row_ptr, int32_t* d_col, void* d_val, void* scratch,
                        hipStream_t s);
-// Build the structure-only transpose index of m.
+// Build the valued transpose index of m (its columns as rows, with their
+// values); every later apply of m keeps it current.
 void mat_build_transpose(DMat* m);
 
 // Per-row column index (rowindex.hip).  mat_index_enable allocates it (false
@@ -411,12 +412,46 @@ void prod_destroy(DProd* p);
 // mode 0: dynamic update; 1: recompute every row (static); with report_affected.
 int32_t prod_run(DProd* p, int mode, bool report_affected);
 
-// Entry-granular dynamic update (entry.hip): for C = A*A over (min,+) or
-// int64 (+,x) when C reflects every apply but the last and A holds that
-// apply's log (entry_eligible).  entry_count lists how many products the
-// last apply changed (kept in the context's second scratch); entry_finish,
-// called next with nothing else on that scratch in between, updates C and
-// returns the reported-row count.
+// One operand of a product as the dynamic paths see it: the matrix whose
+// rows they read (op(X): X, or X's transpose index), the matrix holding its
+// columns as rows (X's transpose index, or X itself), the matrix whose log
+// lists its changes in its own coordinates (the transpose index keeps the
+// transposed log of every apply), the source matrix that counts applies, and
+// the apply count the product last reflected.
+struct OpView {
+  DMat* rows;
+  DMat* cols;
+  const DMat* logm;
+  const DMat* src;
+  uint64_t seq;
+};
+
+inline OpView op_view(const DProd* p, bool left) {
+  const bool trans = (p->ops & (left ? DSG_TRANS_A : DSG_TRANS_B)) != 0;
+  DMat* src = left ? p->src_a : p->src_b;
+  OpView v;
+  v.rows = left ? p->A : p->B;
+  v.cols = trans ? src : src->tidx;
+  v.logm = trans ? src->tidx : src;
+  v.src = src;
+  v.seq = left ? p->a_seq : p->b_seq;
+  return v;
+}
+
+// An operand applied once since the last update, with the log of that apply
+// (in its own coordinates); or not applied since.
+inline bool changed_once(const OpView& v) {
+  return v.logm && v.src->log_seq != 0 && v.src->log_seq == v.src->apply_seq && v.logm->log_seq == v.src->apply_seq &&
+         v.src->apply_seq == v.seq + 1;
+}
+inline bool unchanged(const OpView& v) { return v.src->apply_seq == v.seq; }
+
+// Entry-granular dynamic update (entry.hip): for C = op(A) op(B) over
+// (min,+), int64 (+,x) or (or, and) when C reflects every apply but the last
+// and the operands hold that apply's logs (entry_eligible).  entry_count
+// lists how many products the last applies changed (kept in the context's
+// second scratch); entry_finish, called next with nothing else on that
+// scratch in between, updates C and returns the reported-row count.
 bool entry_eligible(DProd* p);
 // Queues the count; its total lands in *entry_count's result (device) and is
 // read back by the caller's next synchronisation into p->entry_nterm.
@@ -424,9 +459,9 @@ const int64_t* entry_count(DProd* p);
 int32_t entry_finish(DProd* p);
 
 // General updates with the Bloom matrix (general.hip, Section 5.2,
-// Algorithm 2).  bloom_build computes F from the current C, A and B;
-// general_eligible tells whether the logs of the operands cover every apply
-// since the product last saw them (then general_update brings C and F up to
+// Algorithm 2), for C = op(A) op(B).  bloom_build computes F from the
+// current C, op(A) and op(B); general_eligible tells whether the logs of the
+// operands cover every apply since the product last saw them (then general_update brings C and F up to
 // date and returns the reported-row count).
 void bloom_build(DProd* p);
 bool general_eligible(const DProd* p);
