@@ -241,8 +241,9 @@ dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod
  * the new entries and bits into C and F.  When an operand took more than one
  * apply since the last update (the change logs hold one apply), the row path
  * runs and F is rebuilt.  Combines with DSG_TRANS_A / DSG_TRANS_B (then A
- * and B above are op(A) and op(B)); not in the batched form.  Results equal
- * those of the other paths. */
+ * and B above are op(A) and op(B)); in the batched form such a product takes
+ * the plain path beside the graph replay.  Results equal those of the other
+ * paths. */
 #define DSG_GENERAL_BLOOM 0x4u
 
 /* Create C = op(A) op(B), op(X) = X^T when ops holds X's flag, and compute
@@ -393,8 +394,9 @@ dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int32_t nprod,
  * products whose C holds fewer than 2^batch_direct_log2 slots (tuning) are one hipGraph replay, with
  * one host round trip before it (validation of every set) and one after it
  * (results); the replay runs on a stream of its own while the products with a
- * larger C take the plain path (apply and update, with their round trips) on
- * the context's stream.  The graph is captured on the first run and replayed
+ * larger C, and those with the Bloom matrix (DSG_GENERAL_BLOOM), take the
+ * plain path (apply and update, with their round trips) on the context's
+ * stream.  The graph is captured on the first run and replayed
  * while the set arrays, their sizes and the storage of every object it
  * touches stay the same (a run with other arrays or after storage grew
  * captures again).  Rows of C that find no room in C's pool or in the staging
@@ -417,7 +419,7 @@ typedef struct {
   double capture_ms;  /* capture and instantiation */
   double replay_ms;   /* launch until the results were read back (the direct products run meanwhile) */
   double finish_ms;   /* completion of rows that waited for room */
-  int64_t direct;     /* product updates that took the plain path (C of at least 2^24 slots) */
+  int64_t direct;     /* product updates that took the plain path (a large C, or a Bloom matrix) */
   double direct_ms;   /* their time (apply and update), beside the replay */
 } dsg_batch_stats;
 dsg_status dsg_batch_info(const dsg_batch* b, dsg_batch_stats* out);

@@ -871,8 +871,6 @@ extern "C" dsg_status dsg_batch_create(dsg_ctx* ctx, dsg_prod* const* prods, int
   std::vector<DMat*> seen;
   for (int32_t i = 0; i < nprod; ++i) {
     if (!prods[i] || prods[i]->owner != ctx) return fail(ctx, DSG_E_STATE, "product of another context");
-    if (prods[i]->p->bloom)
-      return fail(ctx, DSG_E_UNSUPPORTED, "products with the Bloom matrix are not taken by the batched form");
     DMat* mine[2] = {prods[i]->p->src_a, prods[i]->p->src_b};
     for (DMat* m : mine)
       if (std::find(seen.begin(), seen.end(), m) != seen.end())

@@ -3,8 +3,9 @@
 // 2^batch_direct_log2 slots, a tuning field) take the plain path on the context's stream, with its host
 // round trips, which their kernel time hides, and with everything it offers
 // (the split copy of B, the entry-granular choice, room sized from the
-// plan); the others are brought up to date by one hipGraph replay on a
-// stream of its own, which runs meanwhile.
+// plan); so do products with the Bloom matrix, whose general update sizes
+// its pattern on the host.  The others are brought up to date by one
+// hipGraph replay on a stream of its own, which runs meanwhile.
 //
 // Each product's chain (apply its operands' sets, then the dynamic update)
 // is captured on a stream of its own, forked from and joined to the
@@ -215,7 +216,7 @@ dsg_status batch_run(DBatch* b, const std::vector<DBatchSet>& sets, std::vector<
   size_t ng = 0;
   for (size_t j = 0; j < np; ++j) {
     DProd* p = b->prods[j];
-    graphed[j] = p->C->h_top_ub < (int64_t(1) << c->tuning.batch_direct_log2) ? 1 : 0;
+    graphed[j] = !p->bloom && p->C->h_top_ub < (int64_t(1) << c->tuning.batch_direct_log2) ? 1 : 0;
     if (!graphed[j]) continue;
     ++ng;
     for (DMat* m : prod_matrices(p))

@@ -286,15 +286,81 @@ def test_general_transposed_operands(ctx, sr, form):
     a.destroy()
 
 
+def test_general_in_batched_form(ctx):
+    """Products with the Bloom matrix in the batched form (A A over (min,+),
+    A^T B over int64) beside a product the graph replays: each run takes Alg.
+    2 on the plain path for the first two; C', F' and the reported rows
+    against the oracle after every run."""
+    say("general update in the batched form")
+    specs = [(I.MIN_PLUS_F32, False, True, True), (I.PLUS_TIMES_I64, True, False, True),
+             (I.PLUS_TIMES_I64, False, True, False)]  # (semiring, trans_a, one matrix, Bloom)
+    objs, host = [], []
+    for t, (sr, ta, same, bloom) in enumerate(specs):
+        lo, hi = vrange(sr)
+        A = I.rmat_csr(10, 8, sr, stream=1220 + t, lo=lo, hi=hi)
+        B = A if same else I.rmat_csr(10, 8, sr, stream=1230 + t, lo=lo, hi=hi)
+        a = dsg.Matrix.from_csr(ctx, A, sr)
+        b = a if same else dsg.Matrix.from_csr(ctx, B, sr)
+        objs.append((a, b, dsg.Product(ctx, a, b, trans_a=ta, bloom=bloom)))
+        bas = I.disjoint_batches(A, sr, [25, 250, 700], stream=1240 + t, value_lo=lo, value_hi=hi)
+        bbs = None if same else I.disjoint_batches(B, sr, [35, 350, 300], stream=1250 + t, value_lo=lo, value_hi=hi)
+        ha = oracle.Csr.of(A)
+        host.append({"a": ha, "b": ha if same else oracle.Csr.of(B), "bas": bas, "bbs": bbs})
+    def ops(j):
+        sr, ta, same, _ = specs[j]
+        h = host[j]
+        return (oracle.transpose(h["a"]) if ta else h["a"]), (h["a"] if same else h["b"])
+    for j, (sr, _, _, _) in enumerate(specs):
+        host[j]["C"] = oracle.spgemm(sr, *ops(j), nthreads=THREADS)
+    bx = dsg.Batch(ctx, [p for _, _, p in objs])
+    for rnd in range(3):
+        sets, keep = [], []
+        for j, (sr, ta, same, bloom) in enumerate(specs):
+            a, b, _ = objs[j]
+            h = host[j]
+            ba = h["bas"][rnd]
+            dev = to_dev(ba)
+            keep.append(dev)
+            sets.append((a, *dev))
+            h["a"], _ = oracle.apply(sr, h["a"], ba.rows, ba.cols, ba.vals, ba.ops)
+            if not same:
+                bb = h["bbs"][rnd]
+                dev = to_dev(bb)
+                keep.append(dev)
+                sets.append((b, *dev))
+                h["b"], _ = oracle.apply(sr, h["b"], bb.rows, bb.cols, bb.vals, bb.ops)
+        counts = bx.run(sets)
+        for j, (sr, ta, same, bloom) in enumerate(specs):
+            P = objs[j][2]
+            x, y = ops(j)
+            want = oracle.spgemm(sr, x, y, nthreads=THREADS)
+            got = P.export()
+            assert_same_csr(sr, got, want, f"run {rnd} product {j}: C'")
+            assert got.val.tobytes() == want.val.tobytes(), f"run {rnd} product {j}: C' values not bit for bit"
+            truth = changed_rows(host[j]["C"], want)
+            assert counts[j] == len(truth), f"run {rnd} product {j}: row count"
+            assert np.array_equal(bx.rows(j).row_ids(), truth), f"run {rnd} product {j}: reported rows"
+            if bloom:
+                assert P.stats()["path"] == 2, f"run {rnd} product {j}: the general path did not run"
+                same_bloom(P.export_bloom(), oracle.bloom(x, y), f"run {rnd} product {j}: F'")
+            host[j]["C"] = want
+    info = bx.info()
+    assert info["direct"] == 6 and info["replays"] == 3, info
+    bx.destroy()
+    for a, b, p in objs:
+        p.destroy()
+    for a, b, p in objs:
+        if b is not a:
+            b.destroy()
+        a.destroy()
+
+
 def test_general_argument_errors(ctx):
     say("general update errors")
     sr = I.MIN_PLUS_F32
     A = I.rmat_csr(8, 4, sr, stream=1170, lo=1, hi=100)
     a = dsg.Matrix.from_csr(ctx, A, sr)
     P = dsg.Product(ctx, a, a, bloom=True)
-    with pytest.raises(dsg.DsgError) as e:
-        dsg.Batch(ctx, [P])
-    assert e.value.status == dsg.E_UNSUPPORTED
     Q = dsg.Product(ctx, a, a)
     with pytest.raises(dsg.DsgError) as e:
         Q.export_bloom()
