@@ -342,7 +342,10 @@ typedef struct {
   int32_t path;         /* 0: affected rows recomputed; 1: entry-granular; 2: general updates with the
                            Bloom filter (affected_rows: rows of C*, entries: entries of C*, terms: terms
                            of the pattern, a_entries: columns of A' kept by the filter, flops: products
-                           of the masked multiply tried) */
+                           of the masked multiply tried or, in rows that probe, lookups of b'_kj;
+                           bin_rows[0] / [1]: parts of rows of C* (a row's kept k in up to 32 parts;
+                           fp64 rows whole) that walked rows of B' / probed them through B's column
+                           index) */
   int32_t pad;
   int64_t terms;        /* entry-granular: changed products a_ik * b_kj enumerated */
   int64_t entries;      /* entry-granular: entries of C with changed products */

@@ -281,75 +281,190 @@ struct MaskedArgs {
   Mask M;
   const uint64_t* rbits;  // per mask row; null: keep every k
   RowsView A, B;
+  RowIx XB;               // B's per-row column index (tab null: no probing)
   void* z;                // accumulator word per mask entry (Sem::Acc)
   unsigned long long* h;  // Bloom bits per mask entry
-  unsigned long long* stats;  // [0] kept A entries, [1] products tried
+  unsigned long long* stats;  // [0] kept A entries, [1] products tried (walk) or probes,
+                              // [2] rows that walked, [3] rows that probed
   int* err;
 };
 
-// Z and H: one workgroup per mask row; A' row i read with the filter r_i;
-// each wavefront takes one kept k at a time and its lanes walk B' row k,
-// adding a term only where (i, j) is in the mask.
+// A mask row is computed by probing (for each kept k and each masked column
+// j, b'_kj looked up in B' row k's column table) instead of walking B' row k
+// when its probes cost less than the walk: kept * len * PROBE_COST < the
+// summed lengths of the kept rows of B'.  A probe is a few dependent global
+// reads, an element of the walk one coalesced read and an LDS lookup.
+constexpr unsigned long long PROBE_COST = 8;
+
+// position of column c in row r of B' (its table, or a scan of the row when
+// the table is not usable), or -1
+__device__ inline int32_t row_find(const RowIx& X, const RowsView& M, int32_t r, int32_t c) {
+  if (X.tab && X.stamp[r] == X.gen) return ix_find(X.tab + X.off[r], (uint32_t)X.sz[r], c);
+  const int64_t o = M.off[r];
+  const int32_t n = M.len[r];
+  for (int32_t t = 0; t < n; ++t)
+    if (M.col[o + t] == c) return t;
+  return -1;
+}
+
+// Z and H: a mask row's entries of A' (row i, read with the filter r_i) are
+// cut into up to MSPLIT parts of at least MIN_SLICE entries, so that the few
+// rows of C* that reach hub rows of B' do not leave one workgroup with most
+// of the work; the parts combine their terms with atomics.  The parts are
+// listed first ((row << 5) | part), and a bounded grid takes them in turn.
+// In a part each wavefront takes one kept k at a time and its lanes walk B'
+// row k, adding a term only where (i, j) is in the mask; a part whose probes
+// cost less (PROBE_COST) takes every (kept k, masked j) pair to B' row k's
+// column table instead.
+constexpr int MSPLIT = 32;  // (the part index takes 5 bits of a list word)
+constexpr int MIN_SLICE = 64;
+constexpr int MASK_GRID = 8192;
+
+__device__ inline int32_t n_parts(int32_t al) { return min(MSPLIT, max(1, (al + MIN_SLICE - 1) / MIN_SLICE)); }
+
+// parts per mask row: none when no term can reach it
+__global__ void k_part_counts(Mask M, const uint64_t* rbits, RowsView A, int64_t nrow, int64_t* cnt) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrow) return;
+  const int64_t len = M.start[r + 1] - M.start[r];
+  const uint64_t R = rbits ? rbits[r] : ~0ull;
+  const int32_t al = A.len[M.row[r]];
+  cnt[r] = (len == 0 || R == 0 || al == 0) ? 0 : n_parts(al);
+}
+
+__global__ void k_part_items(const int64_t* cnt, const int64_t* off, int64_t nrow, int64_t* items) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nrow) return;
+  for (int64_t y = 0; y < cnt[r]; ++y) items[off[r] + y] = (r << 5) | y;
+}
+
 template <int SR>
-__global__ __launch_bounds__(MW) void k_masked(MaskedArgs P) {
+__global__ __launch_bounds__(MW) void k_masked(MaskedArgs P, const int64_t* items, const int64_t* d_nitems) {
   using S = Sem<SR>;
   using V = typename S::V;
   using Acc = typename S::Acc;
   __shared__ int32_t hk[MSLOTS];
   __shared__ int32_t hv[MSLOTS];
   __shared__ unsigned long long cnt[2];
-  const int64_t r = blockIdx.x;
-  const int32_t i = P.M.row[r];
-  const int64_t s0 = P.M.start[r], s1 = P.M.start[r + 1];
-  const int32_t len = (int32_t)(s1 - s0);
-  if (len == 0) return;
-  const uint64_t R = P.rbits ? P.rbits[r] : ~0ull;
-  if (R == 0) return;  // no term can reach the row's masked entries
-  const bool tab = len <= MSLOTS / 2;
-  if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
-  if (tab) table_build(hk, hv, P.M.col, s0, len);
-  else __syncthreads();
+  __shared__ unsigned long long pre[2];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t ao = P.A.off[i];
-  const int32_t al = P.A.len[i];
   Acc* z = (Acc*)P.z;
-  unsigned long long kept = 0, tried = 0;
-  for (int32_t t = wv; t < al; t += MW / 64) {
-    const int32_t k = P.A.col[ao + t];
-    if (!(R & bloom_bit(k))) continue;  // not in A^R
-    const V a = ((const V*)P.A.val)[ao + t];
-    const int64_t bo = P.B.off[k];
-    const int32_t bl = P.B.len[k];
-    const unsigned long long bit = (unsigned long long)bloom_bit(k);
-    ++kept;
-    tried += (unsigned long long)bl;
-    for (int32_t u = lane; u < bl; u += 64) {
-      const int32_t j = P.B.col[bo + u];
-      const int64_t e = tab ? (int64_t)table_find(hk, hv, j) : run_find(P.M.col, s0, s1, j) - s0;
-      if (e < 0) continue;  // (i, j) is not in the mask
-      S::atomic_combine(&z[s0 + e], S::mul(a, ((const V*)P.B.val)[bo + u]));
-      atomicOr(&P.h[s0 + e], bit);
+  const int64_t ni = *d_nitems;
+  unsigned long long sum_kept = 0, sum_tried = 0, n_walk = 0, n_probe = 0;  // (thread 0)
+  for (int64_t it = blockIdx.x; it < ni; it += gridDim.x) {
+    const int64_t w = items[it];
+    const int64_t r = w >> 5;
+    const int32_t part = (int32_t)(w & 31);
+    const int32_t i = P.M.row[r];
+    const int64_t s0 = P.M.start[r], s1 = P.M.start[r + 1];
+    const int32_t len = (int32_t)(s1 - s0);
+    const uint64_t R = P.rbits ? P.rbits[r] : ~0ull;
+    const int64_t ao = P.A.off[i];
+    const int32_t al = P.A.len[i];
+    // this part [t0, t1) of A' row i
+    const int32_t np = n_parts(al);
+    const int32_t t0 = (int32_t)((int64_t)al * part / np);
+    const int32_t t1 = (int32_t)((int64_t)al * (part + 1) / np);
+    if (threadIdx.x < 2) {
+      cnt[threadIdx.x] = 0;
+      pre[threadIdx.x] = 0;
     }
+    __syncthreads();
+    bool probe = false;
+    if (P.XB.tab) {
+      // the walk's length: the rows of B' the part's kept k name
+      unsigned long long nk = 0, walk = 0;
+      for (int32_t t = t0 + threadIdx.x; t < t1; t += MW) {
+        const int32_t k = P.A.col[ao + t];
+        if (R & bloom_bit(k)) {
+          ++nk;
+          walk += (unsigned long long)P.B.len[k];
+        }
+      }
+      for (int d = 32; d > 0; d >>= 1) {
+        nk += __shfl_xor(nk, d, 64);
+        walk += __shfl_xor(walk, d, 64);
+      }
+      if (lane == 0) {
+        atomicAdd(&pre[0], nk);
+        atomicAdd(&pre[1], walk);
+      }
+      __syncthreads();
+      probe = pre[0] * (unsigned long long)len * PROBE_COST < pre[1];
+    }
+    unsigned long long kept = 0, tried = 0;
+    if (probe) {
+      const int64_t npair = (int64_t)(t1 - t0) * len;
+      for (int64_t q = threadIdx.x; q < npair; q += MW) {
+        const int32_t t = t0 + (int32_t)(q / len);
+        const int32_t e = (int32_t)(q - (int64_t)(t - t0) * len);
+        const int32_t k = P.A.col[ao + t];
+        if (!(R & bloom_bit(k))) continue;  // not in A^R
+        kept += e == 0;
+        ++tried;
+        const int32_t pos = row_find(P.XB, P.B, k, P.M.col[s0 + e]);
+        if (pos < 0) continue;  // no b'_kj
+        const V a = ((const V*)P.A.val)[ao + t];
+        S::atomic_combine(&z[s0 + e], S::mul(a, ((const V*)P.B.val)[P.B.off[k] + pos]));
+        atomicOr(&P.h[s0 + e], (unsigned long long)bloom_bit(k));
+      }
+      for (int d = 32; d > 0; d >>= 1) {
+        kept += __shfl_xor(kept, d, 64);
+        tried += __shfl_xor(tried, d, 64);
+      }
+    } else {
+      const bool tab = len <= MSLOTS / 2;
+      if (tab) table_build(hk, hv, P.M.col, s0, len);
+      for (int32_t t = t0 + wv; t < t1; t += MW / 64) {
+        const int32_t k = P.A.col[ao + t];
+        if (!(R & bloom_bit(k))) continue;  // not in A^R
+        const V a = ((const V*)P.A.val)[ao + t];
+        const int64_t bo = P.B.off[k];
+        const int32_t bl = P.B.len[k];
+        const unsigned long long bit = (unsigned long long)bloom_bit(k);
+        ++kept;
+        tried += (unsigned long long)bl;
+        for (int32_t u = lane; u < bl; u += 64) {
+          const int32_t j = P.B.col[bo + u];
+          const int64_t e = tab ? (int64_t)table_find(hk, hv, j) : run_find(P.M.col, s0, s1, j) - s0;
+          if (e < 0) continue;  // (i, j) is not in the mask
+          S::atomic_combine(&z[s0 + e], S::mul(a, ((const V*)P.B.val)[bo + u]));
+          atomicOr(&P.h[s0 + e], bit);
+        }
+      }
+    }
+    if (lane == 0) {
+      atomicAdd(&cnt[0], kept);
+      atomicAdd(&cnt[1], tried);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      sum_kept += cnt[0];
+      sum_tried += cnt[1];
+      if (probe) ++n_probe;
+      else ++n_walk;
+    }
+    __syncthreads();  // the next part resets cnt and pre and rebuilds the table
   }
-  if (lane == 0) {
-    atomicAdd(&cnt[0], kept);
-    atomicAdd(&cnt[1], tried);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    atomicAdd(&P.stats[0], cnt[0]);
-    atomicAdd(&P.stats[1], cnt[1]);
+  if (threadIdx.x == 0 && (n_walk | n_probe)) {
+    atomicAdd(&P.stats[0], sum_kept);
+    atomicAdd(&P.stats[1], sum_tried);
+    atomicAdd(&P.stats[2], n_walk);
+    atomicAdd(&P.stats[3], n_probe);
   }
 }
 
 // fp64: the row's kept k sorted in LDS, then one k at a time in ascending
 // order; the workgroup's lanes share B' row k, whose columns are distinct, so
-// each masked entry takes its terms in ascending k without atomics.
+// each masked entry takes its terms in ascending k without atomics.  Rows
+// whose probes cost less give each masked entry one lane, which probes the
+// kept k in ascending order.
 __global__ __launch_bounds__(MW) void k_masked_f64(MaskedArgs P) {
   __shared__ int32_t hk[MSLOTS / 2];
   __shared__ int32_t hv[MSLOTS / 2];
   __shared__ uint64_t ks[FP64_KCAP];
   __shared__ int nk;
+  __shared__ unsigned long long walk;
   const int64_t r = blockIdx.x;
   const int32_t i = P.M.row[r];
   const int64_t s0 = P.M.start[r], s1 = P.M.start[r + 1];
@@ -359,7 +474,10 @@ __global__ __launch_bounds__(MW) void k_masked_f64(MaskedArgs P) {
   if (R == 0) return;
   constexpr int SL = MSLOTS / 2;
   const bool tab = len <= SL / 2;
-  if (threadIdx.x == 0) nk = 0;
+  if (threadIdx.x == 0) {
+    nk = 0;
+    walk = 0;
+  }
   if (tab) {
     for (int x = threadIdx.x; x < SL; x += MW) hk[x] = -1;
     __syncthreads();
@@ -373,19 +491,24 @@ __global__ __launch_bounds__(MW) void k_masked_f64(MaskedArgs P) {
   __syncthreads();
   const int64_t ao = P.A.off[i];
   const int32_t al = P.A.len[i];
+  unsigned long long wl = 0;
   for (int32_t t = threadIdx.x; t < al; t += MW) {
     const int32_t k = P.A.col[ao + t];
     if (R & bloom_bit(k)) {
       const int q = atomicAdd(&nk, 1);
       if (q < FP64_KCAP) ks[q] = ((uint64_t)(uint32_t)k << 32) | (uint32_t)t;
+      wl += (unsigned long long)P.B.len[k];
     }
   }
+  for (int d = 32; d > 0; d >>= 1) wl += __shfl_xor(wl, d, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(&walk, wl);
   __syncthreads();
   const int n = nk;
   if (n > FP64_KCAP) {
     if (threadIdx.x == 0) atomicOr(P.err, 16);
     return;
   }
+  const bool probe = P.XB.tab && (unsigned long long)n * (unsigned long long)len * PROBE_COST < walk;
   int np2 = 1;
   while (np2 < n) np2 <<= 1;
   for (int x = n + threadIdx.x; x < np2; x += MW) ks[x] = ~0ull;
@@ -408,6 +531,32 @@ __global__ __launch_bounds__(MW) void k_masked_f64(MaskedArgs P) {
     }
   }
   double* z = (double*)P.z;
+  if (probe) {
+    for (int32_t e = threadIdx.x; e < len; e += MW) {
+      const int32_t j = P.M.col[s0 + e];
+      double acc = 0.0;
+      unsigned long long hb = 0;
+      for (int q = 0; q < n; ++q) {
+        const int32_t k = (int32_t)(ks[q] >> 32);
+        const int32_t pos = row_find(P.XB, P.B, k, j);
+        if (pos < 0) continue;
+        const int32_t t = (int32_t)(uint32_t)ks[q];
+        const double p = __dmul_rn(((const double*)P.A.val)[ao + t], ((const double*)P.B.val)[P.B.off[k] + pos]);
+        acc = hb ? __dadd_rn(acc, p) : p;  // the first term as it is, then ascending k
+        hb |= (unsigned long long)bloom_bit(k);
+      }
+      if (hb) {
+        z[s0 + e] = acc;
+        P.h[s0 + e] = hb;
+      }
+    }
+    if (threadIdx.x == 0) {
+      atomicAdd(&P.stats[0], (unsigned long long)n);
+      atomicAdd(&P.stats[1], (unsigned long long)n * (unsigned long long)len);
+      atomicAdd(&P.stats[3], 1ull);
+    }
+    return;
+  }
   unsigned long long tried = 0;
   for (int q = 0; q < n; ++q) {
     const int32_t k = (int32_t)(ks[q] >> 32);
@@ -447,6 +596,7 @@ __global__ __launch_bounds__(MW) void k_masked_f64(MaskedArgs P) {
   if (threadIdx.x == 0) {
     atomicAdd(&P.stats[0], (unsigned long long)n);
     atomicAdd(&P.stats[1], tried);
+    atomicAdd(&P.stats[2], 1ull);
   }
 }
 
@@ -509,7 +659,7 @@ int64_t read_i64(Ctx* c, const int64_t* d) {
 
 // Z and H over a mask (z / h filled here first).
 void launch_masked(DProd* p, const Mask& M, int64_t nrow, int64_t nmask, const uint64_t* rbits, void* z,
-                   unsigned long long* h, unsigned long long* stats, int* err) {
+                   unsigned long long* h, unsigned long long* stats, int* err, const RowIx& XB = RowIx()) {
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
   const int sr = p->C->sr;
@@ -526,16 +676,37 @@ void launch_masked(DProd* p, const Mask& M, int64_t nrow, int64_t nmask, const u
   P.rbits = rbits;
   P.A = rows_of(p->A);
   P.B = rows_of(p->B);
+  P.XB = XB;
   P.z = z;
   P.h = h;
   P.stats = stats;
   P.err = err;
-  const dim3 g((unsigned)nrow);
+  if (sr == 2) {
+    // fp64 keeps a row whole (its terms in ascending k)
+    hipLaunchKernelGGL(k_masked_f64, dim3((unsigned)nrow), dim3(MW), 0, s, P);
+    DSG_HIP(hipGetLastError());
+    return;
+  }
+  // the list of parts (in the context's scratch, free while this runs)
+  const size_t pb = Carve::need({(size_t)nrow * 8, (size_t)nrow * 8, (size_t)nrow * MSPLIT * 8,
+                                 scan_scratch_bytes(nrow) + 64, 64});
+  Carve cv(ctx_scratch(c, pb), pb);
+  int64_t* pcnt = cv.take<int64_t>(nrow);
+  int64_t* poff = cv.take<int64_t>(nrow);
+  int64_t* items = cv.take<int64_t>(nrow * MSPLIT);
+  void* pscan = cv.take<char>(scan_scratch_bytes(nrow) + 64);
+  int64_t* d_nitems = cv.take<int64_t>(8);
+  const unsigned rb = blocks_for(nrow, 256);
+  hipLaunchKernelGGL(k_part_counts, dim3(rb), dim3(256), 0, s, M, rbits, P.A, nrow, pcnt);
+  exclusive_scan_i64(pcnt, poff, nrow, d_nitems, pscan, s);
+  hipLaunchKernelGGL(k_part_items, dim3(rb), dim3(256), 0, s, (const int64_t*)pcnt, (const int64_t*)poff, nrow, items);
+  const dim3 g((unsigned)std::min<int64_t>(nrow * MSPLIT, MASK_GRID));
+  const int64_t* it = items;
+  const int64_t* ni = d_nitems;
   switch (sr) {
-    case 0: hipLaunchKernelGGL(k_masked<0>, g, dim3(MW), 0, s, P); break;
-    case 1: hipLaunchKernelGGL(k_masked<1>, g, dim3(MW), 0, s, P); break;
-    case 2: hipLaunchKernelGGL(k_masked_f64, g, dim3(MW), 0, s, P); break;
-    default: hipLaunchKernelGGL(k_masked<3>, g, dim3(MW), 0, s, P); break;
+    case 0: hipLaunchKernelGGL(k_masked<0>, g, dim3(MW), 0, s, P, it, ni); break;
+    case 1: hipLaunchKernelGGL(k_masked<1>, g, dim3(MW), 0, s, P, it, ni); break;
+    default: hipLaunchKernelGGL(k_masked<3>, g, dim3(MW), 0, s, P, it, ni); break;
   }
   DSG_HIP(hipGetLastError());
 }
@@ -706,12 +877,18 @@ int32_t general_update(DProd* p) {
   st.entries = ncs;
   st.affected_rows = nrow;
   const Mask M{row_id, row_start, cs_col};
+  RowIx XB;
   if (nrow > 0) {
     // E and R
     hipLaunchKernelGGL(k_row_filter, dim3((unsigned)nrow), dim3(MW), 0, s, M, (const unsigned long long*)fstar,
                        rows_of(p->F), rbits);
-    // Z and H
-    launch_masked(p, M, nrow, ncs, rbits, z, h, stats, err);
+    // Z and H (rows with few masked entries probe B' through its column
+    // index: every row's table made usable first)
+    if (c->tuning.row_index && mat_index_enable(B)) {
+      mat_index_build(B, nullptr, nullptr, B->nrows);
+      XB = mat_index_view(B);
+    }
+    launch_masked(p, M, nrow, ncs, rbits, z, h, stats, err, XB);
     check_err(c, err);
     // the merges, masked at C*
     const unsigned gb = blocks_for(ncs, 256);
@@ -742,16 +919,21 @@ int32_t general_update(DProd* p) {
   hipLaunchKernelGGL(k_set_sync2, dim3(1), dim3(1), 0, s, p->d_sync, (const uint32_t*)A->d_epoch,
                      (const uint32_t*)B->d_epoch);
   struct Tail {
-    unsigned long long st[2];
+    unsigned long long st[4];
+    unsigned long long ix_top;  // B's index pool top
     int32_t nchg;
   };
   Tail* ht = (Tail*)((char*)c->pinned + 3072);
   ht->nchg = 0;
-  DSG_HIP(hipMemcpyAsync(ht->st, stats, 16, hipMemcpyDeviceToHost, s));
+  DSG_HIP(hipMemcpyAsync(ht->st, stats, 32, hipMemcpyDeviceToHost, s));
   if (n > 0) DSG_HIP(hipMemcpyAsync(&ht->nchg, d_nchg, 4, hipMemcpyDeviceToHost, s));
+  if (XB.tab) DSG_HIP(hipMemcpyAsync(&ht->ix_top, B->ix_top, 8, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));
+  if (XB.tab) mat_index_note_top(B, ht->ix_top);
   st.a_entries = (int64_t)ht->st[0];
   st.flops = (int64_t)ht->st[1];
+  st.bin_rows[0] = (int64_t)ht->st[2];
+  st.bin_rows[1] = (int64_t)ht->st[3];
   st.changed_rows = ht->nchg;
   return ht->nchg;
 }

@@ -186,6 +186,49 @@ def test_general_long_mask_rows(ctx, sr):
     a.destroy()
 
 
+@pytest.mark.parametrize("sr", SEMIRINGS, ids=[NAMES[s] for s in SEMIRINGS])
+def test_general_probe_and_walk(ctx, sr):
+    """The masked product's two ways through a row of C*: with B's column
+    index (rows of few masked entries probe b'_kj for each kept k) and
+    without it (every row walks the kept rows of B'), on R-MAT scale 12, edge
+    factor 16: both give the oracle's C' bit for bit and its Bloom matrix,
+    and the first run probes rows while the second probes none."""
+    say(f"general update probe and walk {NAMES[sr]}")
+    lo, hi = vrange(sr)
+    A = I.rmat_csr(12, 16, sr, stream=1260 + sr, lo=lo, hi=hi)
+    bas = I.disjoint_batches(A, sr, [40, 400], stream=1270 + sr, value_lo=lo, value_hi=hi)
+    rows = {}
+    try:
+        for ix in (1, 0):
+            t = ctx.get_tuning()
+            t.row_index = ix
+            ctx.set_tuning(t)
+            a = dsg.Matrix.from_csr(ctx, A, sr)
+            P = dsg.Product(ctx, a, a, bloom=True)
+            ha = oracle.Csr.of(A)
+            walked = probed = 0
+            for q, ba in enumerate(bas):
+                a.apply(*to_dev(ba))
+                ha, _ = oracle.apply(sr, ha, ba.rows, ba.cols, ba.vals, ba.ops)
+                P.update()
+                st = P.stats()
+                assert st["path"] == 2
+                walked += st["bin_rows"][0]
+                probed += st["bin_rows"][1]
+                want = oracle.spgemm(sr, ha, ha, nthreads=THREADS)
+                got = P.export()
+                assert_same_csr(sr, got, want, f"index {ix} batch {q}: C'")
+                assert got.val.tobytes() == want.val.tobytes(), f"index {ix} batch {q}: C' values not bit for bit"
+                same_bloom(P.export_bloom(), oracle.bloom(ha, ha), f"index {ix} batch {q}: F'")
+            rows[ix] = (walked, probed)
+            P.destroy()
+            a.destroy()
+    finally:
+        ctx.set_tuning(None)
+    assert rows[1][1] > 0, rows
+    assert rows[0][1] == 0 and rows[0][0] > 0, rows
+
+
 def test_general_several_applies_fall_back(ctx):
     """Two applies before one update: the change log holds one apply, so the
     row path runs and F is built again -- same C and F as the oracle."""
@@ -387,7 +430,13 @@ def test_general_rmat16_full_size(ctx, batch):
     a.apply(*to_dev(ba))
     ha2, _ = oracle.apply(sr, ha, ba.rows, ba.cols, ba.vals, ba.ops)
     rs = P.update()
-    assert P.stats()["path"] == 2
+    st = P.stats()
+    assert st["path"] == 2
+    # hub rows of B' are long and the rows of a small batch's C* short: most
+    # parts of those rows probe (a row of C* takes up to 32 parts)
+    if batch == 100:
+        assert st["bin_rows"][1] > st["bin_rows"][0], st["bin_rows"][:2]
+    assert 0 < st["bin_rows"][0] + st["bin_rows"][1] <= 32 * st["affected_rows"]
     want = oracle.spgemm(sr, ha2, ha2, nthreads=THREADS)
     assert_same_csr(sr, P.export(), want, "C'")
     same_bloom(P.export_bloom(), oracle.bloom(ha2, ha2), "F'")
