@@ -240,9 +240,19 @@ __device__ inline uint64_t wg_or(uint64_t x, uint64_t* red) {
   return r;
 }
 
+// A probe (a lookup in a row's column table: a few dependent global reads)
+// is taken to cost PROBE_COST elements of a streamed row (one coalesced read
+// and an LDS lookup each).  The row filter and the masked product probe where
+// that costs less than streaming, e.g. a mask row with kept k's probes every
+// b'_kj when kept * len * PROBE_COST < the summed lengths of the kept rows
+// of B'.
+constexpr unsigned long long PROBE_COST = 8;
+
 // E and R: r = OR over the row's C* entries of f*_ij | f_ij, with f_ij read
-// from F's row i (stored entries whose column is in the row's C*).
-__global__ __launch_bounds__(MW) void k_row_filter(Mask M, const unsigned long long* fstar, RowsView F,
+// from F's row i (stored entries whose column is in the row's C*): found
+// through F's column index when the row's C* entries are few against F's
+// row (PROBE_COST), else by streaming F's row against a table of them.
+__global__ __launch_bounds__(MW) void k_row_filter(Mask M, const unsigned long long* fstar, RowsView F, RowIx XF,
                                                    uint64_t* rbits) {
   __shared__ int32_t hk[MSLOTS];
   __shared__ int32_t hv[MSLOTS];
@@ -256,7 +266,14 @@ __global__ __launch_bounds__(MW) void k_row_filter(Mask M, const unsigned long l
   const int64_t fo = F.off[i];
   const int32_t fl = F.len[i];
   const uint64_t* fval = (const uint64_t*)F.val;
-  if (len <= MSLOTS / 2) {
+  if (XF.tab && XF.stamp[i] == XF.gen && (uint64_t)len * PROBE_COST < (uint64_t)fl) {
+    const uint64_t* ft = XF.tab + XF.off[i];
+    const uint32_t fn = (uint32_t)XF.sz[i];
+    for (int32_t t = threadIdx.x; t < len; t += MW) {
+      const int32_t pos = ix_find(ft, fn, M.col[s0 + t]);
+      if (pos >= 0) acc |= fval[fo + pos];
+    }
+  } else if (len <= MSLOTS / 2) {
     table_build(hk, hv, M.col, s0, len);
     for (int32_t t = threadIdx.x; t < fl; t += MW)
       if (table_find(hk, hv, F.col[fo + t]) >= 0) acc |= fval[fo + t];
@@ -289,12 +306,6 @@ struct MaskedArgs {
   int* err;
 };
 
-// A mask row is computed by probing (for each kept k and each masked column
-// j, b'_kj looked up in B' row k's column table) instead of walking B' row k
-// when its probes cost less than the walk: kept * len * PROBE_COST < the
-// summed lengths of the kept rows of B'.  A probe is a few dependent global
-// reads, an element of the walk one coalesced read and an LDS lookup.
-constexpr unsigned long long PROBE_COST = 8;
 
 // position of column c in row r of B' (its table, or a scan of the row when
 // the table is not usable), or -1
@@ -783,7 +794,13 @@ int32_t general_update(DProd* p) {
   const OpView l = op_view(p, true), r = op_view(p, false);
   DMat* T = l.cols;  // columns of op(A)' as rows
   DSG_REQUIRE(T && p->F, DSG_E_STATE, "internal: Bloom product without transpose index or F");
-  mat_index_invalidate(C);  // the masked merges rewrite rows of C
+  // C and F take per-row column indexes, which the merges (ordinary applies)
+  // keep current: the merges then place their entries by lookup, and R finds
+  // f_ij by lookup where that is cheaper
+  if (c->tuning.row_index) {
+    mat_index_enable(C);
+    mat_index_enable(p->F);
+  }
   const int32_t n = C->nrows;
   const int cb = bits_for(C->ncols);
   const int rb = bits_for(n);
@@ -880,8 +897,13 @@ int32_t general_update(DProd* p) {
   RowIx XB;
   if (nrow > 0) {
     // E and R
+    RowIx XF;
+    if (p->F->ix_tab) {
+      mat_index_build(p->F, nullptr, nullptr, p->F->nrows);
+      XF = mat_index_view(p->F);
+    }
     hipLaunchKernelGGL(k_row_filter, dim3((unsigned)nrow), dim3(MW), 0, s, M, (const unsigned long long*)fstar,
-                       rows_of(p->F), rbits);
+                       rows_of(p->F), XF, rbits);
     // Z and H (rows with few masked entries probe B' through its column
     // index: every row's table made usable first)
     if (c->tuning.row_index && mat_index_enable(B)) {
@@ -920,16 +942,19 @@ int32_t general_update(DProd* p) {
                      (const uint32_t*)B->d_epoch);
   struct Tail {
     unsigned long long st[4];
-    unsigned long long ix_top;  // B's index pool top
+    unsigned long long ix_top[3];  // index pool tops of B, C and F
     int32_t nchg;
   };
   Tail* ht = (Tail*)((char*)c->pinned + 3072);
   ht->nchg = 0;
   DSG_HIP(hipMemcpyAsync(ht->st, stats, 32, hipMemcpyDeviceToHost, s));
   if (n > 0) DSG_HIP(hipMemcpyAsync(&ht->nchg, d_nchg, 4, hipMemcpyDeviceToHost, s));
-  if (XB.tab) DSG_HIP(hipMemcpyAsync(&ht->ix_top, B->ix_top, 8, hipMemcpyDeviceToHost, s));
+  DMat* ixm[3] = {XB.tab ? B : nullptr, C, p->F};
+  for (int q = 0; q < 3; ++q)
+    if (ixm[q] && ixm[q]->ix_tab) DSG_HIP(hipMemcpyAsync(&ht->ix_top[q], ixm[q]->ix_top, 8, hipMemcpyDeviceToHost, s));
   DSG_HIP(hipStreamSynchronize(s));
-  if (XB.tab) mat_index_note_top(B, ht->ix_top);
+  for (int q = 0; q < 3; ++q)
+    if (ixm[q] && ixm[q]->ix_tab) mat_index_note_top(ixm[q], ht->ix_top[q]);
   st.a_entries = (int64_t)ht->st[0];
   st.flops = (int64_t)ht->st[1];
   st.bin_rows[0] = (int64_t)ht->st[2];
