@@ -796,8 +796,11 @@ int32_t general_update(DProd* p) {
   DSG_REQUIRE(T && p->F, DSG_E_STATE, "internal: Bloom product without transpose index or F");
   // C and F take per-row column indexes, which the merges (ordinary applies)
   // keep current: the merges then place their entries by lookup, and R finds
-  // f_ij by lookup where that is cheaper
-  if (c->tuning.row_index) {
+  // f_ij by lookup where that is cheaper.  Where C's rows are short (under
+  // IX_MIN_ROW slots on average) streaming a row costs less than keeping the
+  // tables, and they go without.
+  constexpr int64_t IX_MIN_ROW = 128;
+  if (c->tuning.row_index && C->h_top_ub >= IX_MIN_ROW * (int64_t)C->nrows) {
     mat_index_enable(C);
     mat_index_enable(p->F);
   }
