@@ -454,13 +454,15 @@ def bench_sweep(args):
             if path == "auto":
                 rec["auto_took_entry"] = bool(st["path"] == 1)
             if path == "bloom":
-                # Algorithm 2: entries of C*, and the columns of A' the row
-                # filter kept against those its rows hold
+                # Algorithm 2: entries and rows of C*, the columns of A' the
+                # row filter kept, the products the masked multiply walked
+                # plus the b'_kj it probed, and its parts that walked / probed
                 rec["bloom_taken"] = bool(st["path"] == 2)
                 rec["bloom_cstar_entries"] = st["entries"]
                 rec["bloom_cstar_rows"] = st["affected_rows"]
                 rec["bloom_kept_a_entries"] = st["a_entries"]
                 rec["bloom_masked_products"] = st["flops"]
+                rec["bloom_parts_walked"], rec["bloom_parts_probed"] = st["bin_rows"][0], st["bin_rows"][1]
             if path == "entry":
                 rec["entry_taken"] = bool(st["path"] == 1)
                 rec["lost_per_batch"] = st["lost"]
