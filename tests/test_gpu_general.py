@@ -229,6 +229,50 @@ def test_general_probe_and_walk(ctx, sr):
     assert rows[0][1] == 0 and rows[0][0] > 0, rows
 
 
+@pytest.mark.parametrize("sr", [I.PLUS_TIMES_I64, I.MIN_PLUS_F32], ids=["i64", "minplus"])
+def test_general_bloom_build_long_row(ctx, sr):
+    """A row of C with 140,000 entries, far longer than the masked
+    product's LDS table of a row's columns (found by binary search in C's
+    sorted row instead): F built from scratch equals the oracle's Bloom
+    matrix, and the general path then updates C and F exactly."""
+    say(f"general update bloom build long row {NAMES[sr]}")
+    lo, hi = vrange(sr)
+    rng = np.random.default_rng(1280 + sr)
+    m = 150000
+    ka = np.array([0 * 2 + 0, 0 * 2 + 1, 1 * 2 + 0, 2 * 2 + 1, 3 * 2 + 0], np.int64)  # A: 4 x 2
+    A = I.csr_from_keys(4, 2, ka, I.draw_values(sr, ka.size, rng, lo, hi))
+    kb = np.concatenate([np.arange(0, 70000, dtype=np.int64), m + np.arange(70000, 140000, dtype=np.int64)])
+    B = I.csr_from_keys(2, m, kb, I.draw_values(sr, kb.size, rng, lo, hi))
+    a = dsg.Matrix.from_csr(ctx, A, sr)
+    b = dsg.Matrix.from_csr(ctx, B, sr)
+    P = dsg.Product(ctx, a, b, bloom=True)
+    ha, hb = oracle.Csr.of(A), oracle.Csr.of(B)
+    C = oracle.spgemm(sr, ha, hb)
+    assert int(np.diff(C.row_ptr).max()) == 140000
+    assert_same_csr(sr, P.export(), C, "static C")
+    same_bloom(P.export_bloom(), oracle.bloom(ha, hb), "static F")
+    # change B row 1 (deletions and value changes) and A row 0: the general path
+    rows = np.array([1] * 40 + [0], np.int32)
+    cols = np.concatenate([rng.choice(np.arange(70000, 140000), 40, replace=False), [60000]]).astype(np.int32)
+    vals = I.draw_values(sr, 41, rng, lo, hi)
+    ops = np.where(np.arange(41) % 2 == 0, 1, 0).astype(np.uint8)
+    bat = I.Batch(rows, cols, vals, ops)
+    b.apply(*to_dev(bat))
+    hb2, _ = oracle.apply(sr, hb, rows, cols, vals, ops)
+    rs = P.update()
+    assert P.stats()["path"] == 2
+    want = oracle.spgemm(sr, ha, hb2)
+    assert_same_csr(sr, P.export(), want, "C'")
+    same_bloom(P.export_bloom(), oracle.bloom(ha, hb2), "F'")
+    assert np.array_equal(rs.row_ids(), changed_rows(C, want))
+    # a static recompute builds F again the same way
+    P.recompute_static()
+    same_bloom(P.export_bloom(), oracle.bloom(ha, hb2), "F after a static recompute")
+    P.destroy()
+    b.destroy()
+    a.destroy()
+
+
 def test_general_several_applies_fall_back(ctx):
     """Two applies before one update: the change log holds one apply, so the
     row path runs and F is built again -- same C and F as the oracle."""
