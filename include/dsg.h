@@ -168,9 +168,9 @@ typedef struct {
   double entry_per_term;
   int32_t row_index;       /* 1 (default): the entry-granular path gives C, A and B a per-row column
                               index (Section 4's per-row hash; about 20 bytes per entry of C), and
-                              the general path with the Bloom matrix gives one to B (its masked
-                              product probes B' rows) and, where C's rows average at least 128
-                              slots, to C and F.  The index pools of a context take at most 1/8 of
+                              the general path with the Bloom matrix, where C's rows average at
+                              least 128 slots, gives one to B (its masked product probes B' rows),
+                              C and F.  The index pools of a context take at most 1/8 of
                               the device, and only memory that stays free beyond a reserve (and at
                               most half of what a budget leaves); without room for the operands'
                               indexes the row path runs.  0: never (applies stream the touched

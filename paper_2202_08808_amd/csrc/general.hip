@@ -796,11 +796,13 @@ int32_t general_update(DProd* p) {
   DSG_REQUIRE(T && p->F, DSG_E_STATE, "internal: Bloom product without transpose index or F");
   // C and F take per-row column indexes, which the merges (ordinary applies)
   // keep current: the merges then place their entries by lookup, and R finds
-  // f_ij by lookup where that is cheaper.  Where C's rows are short (under
-  // IX_MIN_ROW slots on average) streaming a row costs less than keeping the
-  // tables, and they go without.
+  // f_ij by lookup where that is cheaper; B takes one for the masked
+  // product's probes.  Where C's rows are short (under IX_MIN_ROW slots on
+  // average) streaming and walking rows cost less than keeping the tables,
+  // and they go without (B keeps an index some other path gave it).
   constexpr int64_t IX_MIN_ROW = 128;
-  if (c->tuning.row_index && C->h_top_ub >= IX_MIN_ROW * (int64_t)C->nrows) {
+  const bool long_rows = C->h_top_ub >= IX_MIN_ROW * (int64_t)C->nrows;
+  if (c->tuning.row_index && long_rows) {
     mat_index_enable(C);
     mat_index_enable(p->F);
   }
@@ -909,7 +911,7 @@ int32_t general_update(DProd* p) {
                        rows_of(p->F), XF, rbits);
     // Z and H (rows with few masked entries probe B' through its column
     // index: every row's table made usable first)
-    if (c->tuning.row_index && mat_index_enable(B)) {
+    if (c->tuning.row_index && (B->ix_tab || (long_rows && mat_index_enable(B)))) {
       mat_index_build(B, nullptr, nullptr, B->nrows);
       XB = mat_index_view(B);
     }
