@@ -242,8 +242,9 @@ dsg_status dsg_prod_create_static(dsg_ctx* ctx, dsg_mat* A, dsg_mat* B, dsg_prod
  * bits F*, ors F and F* over each row of C* into a filter R, recomputes only
  * the entries of C* from the columns k of A' that R lets through, and merges
  * the new entries and bits into C and F.  When an operand took more than one
- * apply since the last update (the change logs hold one apply), the row path
- * runs and F is rebuilt.  Combines with DSG_TRANS_A / DSG_TRANS_B (then A
+ * apply since the last update (the change logs hold one apply), or an fp64
+ * row of A' keeps more than 4096 columns after the filter, the row path runs
+ * and F is rebuilt.  Combines with DSG_TRANS_A / DSG_TRANS_B (then A
  * and B above are op(A) and op(B)); in the batched form such a product takes
  * the plain path beside the graph replay.  Results equal those of the other
  * paths. */

@@ -668,9 +668,12 @@ int64_t read_i64(Ctx* c, const int64_t* d) {
   return *h;
 }
 
-// Z and H over a mask (z / h filled here first).
+// Z and H over a mask (z / h filled here first).  bits_only: only h is
+// wanted (F from scratch), so fp64 too takes the kernel that combines in any
+// order (its z is then left meaningless).
 void launch_masked(DProd* p, const Mask& M, int64_t nrow, int64_t nmask, const uint64_t* rbits, void* z,
-                   unsigned long long* h, unsigned long long* stats, int* err, const RowIx& XB = RowIx()) {
+                   unsigned long long* h, unsigned long long* stats, int* err, const RowIx& XB = RowIx(),
+                   bool bits_only = false) {
   Ctx* c = p->ctx;
   hipStream_t s = c->stream;
   const int sr = p->C->sr;
@@ -692,7 +695,7 @@ void launch_masked(DProd* p, const Mask& M, int64_t nrow, int64_t nmask, const u
   P.h = h;
   P.stats = stats;
   P.err = err;
-  if (sr == 2) {
+  if (sr == 2 && !bits_only) {
     // fp64 keeps a row whole (its terms in ascending k)
     hipLaunchKernelGGL(k_masked_f64, dim3((unsigned)nrow), dim3(MW), 0, s, P);
     DSG_HIP(hipGetLastError());
@@ -715,20 +718,23 @@ void launch_masked(DProd* p, const Mask& M, int64_t nrow, int64_t nmask, const u
   const int64_t* it = items;
   const int64_t* ni = d_nitems;
   switch (sr) {
-    case 0: hipLaunchKernelGGL(k_masked<0>, g, dim3(MW), 0, s, P, it, ni); break;
+    case 0:
+    case 2: hipLaunchKernelGGL(k_masked<0>, g, dim3(MW), 0, s, P, it, ni); break;  // (fp64: bits only, 8-byte words)
     case 1: hipLaunchKernelGGL(k_masked<1>, g, dim3(MW), 0, s, P, it, ni); break;
     default: hipLaunchKernelGGL(k_masked<3>, g, dim3(MW), 0, s, P, it, ni); break;
   }
   DSG_HIP(hipGetLastError());
 }
 
-void check_err(Ctx* c, const int* d_err) {
+// The masked product's flags: 16 when an fp64 row kept more columns of A'
+// than its ascending-k sum takes (FP64_KCAP); anything else is an internal
+// error.
+int read_err(Ctx* c, const int* d_err) {
   int* h = (int*)((char*)c->pinned + 3328);
   DSG_HIP(hipMemcpyAsync(h, d_err, 4, hipMemcpyDeviceToHost, c->stream));
   DSG_HIP(hipStreamSynchronize(c->stream));
-  DSG_REQUIRE(!(h[0] & 16), DSG_E_UNSUPPORTED,
-              "fp64 Bloom product: a row of A keeps more than 4096 entries after the filter");
-  DSG_REQUIRE(h[0] == 0, DSG_E_DEVICE, "internal: masked product error " + std::to_string(h[0]));
+  DSG_REQUIRE((h[0] & ~16) == 0, DSG_E_DEVICE, "internal: masked product error " + std::to_string(h[0]));
+  return h[0];
 }
 
 // op(X)'s log since the product last saw X: the log of X's last apply in
@@ -778,8 +784,8 @@ void bloom_build(DProd* p) {
   hipLaunchKernelGGL(k_zero_n, dim3(1), dim3(64), 0, s, (unsigned long long*)err, 8);
   if (n > 0) hipLaunchKernelGGL(k_iota_i32, dim3(blocks_for(n, 256)), dim3(256), 0, s, rid, (int64_t)n);
   Mask M{rid, rp, col};
-  if (nnz > 0) launch_masked(p, M, n, nnz, nullptr, z, h, stats, err);
-  check_err(c, err);
+  if (nnz > 0) launch_masked(p, M, n, nnz, nullptr, z, h, stats, err, RowIx(), true);
+  (void)read_err(c, err);
   DMat* F = mat_create(c, n, C->ncols, 0, rp, col, h);
   if (p->F) mat_destroy(p->F);
   p->F = F;
@@ -916,7 +922,22 @@ int32_t general_update(DProd* p) {
       XB = mat_index_view(B);
     }
     launch_masked(p, M, nrow, ncs, rbits, z, h, stats, err, XB);
-    check_err(c, err);
+    if (read_err(c, err) & 16) {
+      // an fp64 row kept more columns of A' than its ascending-k sum takes:
+      // nothing is merged; the row path brings C up to date and F is built
+      // again, as after several applies
+      p->bloom = false;
+      int32_t nchg = 0;
+      try {
+        nchg = prod_run(p, 0, false);
+      } catch (...) {
+        p->bloom = true;
+        throw;
+      }
+      p->bloom = true;
+      bloom_build(p);
+      return nchg;
+    }
     // the merges, masked at C*
     const unsigned gb = blocks_for(ncs, 256);
     switch (C->sr) {

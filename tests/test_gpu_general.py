@@ -273,6 +273,46 @@ def test_general_bloom_build_long_row(ctx, sr):
     a.destroy()
 
 
+def test_general_fp64_long_row_falls_back(ctx):
+    """fp64 with a row of A' of 5000 entries, more than the ascending-k
+    masked product keeps (4096): F is still built (its bits need no order),
+    and an update whose filter keeps that row whole takes the row path and
+    builds F again -- C' and F' equal the oracle's."""
+    say("general update fp64 long row fallback")
+    sr = I.PLUS_TIMES_F64
+    rng = np.random.default_rng(1290)
+    kdim, m = 5000, 64
+    ka = np.concatenate([np.arange(kdim, dtype=np.int64), kdim + rng.choice(kdim, 20, replace=False)])
+    A = I.csr_from_keys(2, kdim, np.unique(ka), I.draw_values(sr, np.unique(ka).size, rng, 1, 9))
+    kb = np.unique(np.repeat(np.arange(kdim, dtype=np.int64), 2) * m + rng.integers(0, m, 2 * kdim))
+    B = I.csr_from_keys(kdim, m, kb, I.draw_values(sr, kb.size, rng, 1, 9))
+    a = dsg.Matrix.from_csr(ctx, A, sr)
+    b = dsg.Matrix.from_csr(ctx, B, sr)
+    P = dsg.Product(ctx, a, b, bloom=True)
+    ha, hb = oracle.Csr.of(A), oracle.Csr.of(B)
+    C = oracle.spgemm(sr, ha, hb)
+    assert_same_csr(sr, P.export(), C, "static C")
+    same_bloom(P.export_bloom(), oracle.bloom(ha, hb), "static F")
+    for t in range(2):
+        rows = rng.choice(kdim, 30, replace=False).astype(np.int32)
+        cols = rng.integers(0, m, 30).astype(np.int32)
+        vals = I.draw_values(sr, 30, rng, 1, 9)
+        ops = np.zeros(30, np.uint8)
+        bat = I.Batch(rows, cols, vals, ops)
+        b.apply(*to_dev(bat))
+        hb, _ = oracle.apply(sr, hb, rows, cols, vals, ops)
+        rs = P.update()
+        assert P.stats()["path"] == 0, f"update {t}: the row path did not take over"
+        want = oracle.spgemm(sr, ha, hb)
+        assert_same_csr(sr, P.export(), want, f"update {t}: C'")
+        same_bloom(P.export_bloom(), oracle.bloom(ha, hb), f"update {t}: F'")
+        assert np.array_equal(rs.row_ids(), changed_rows(C, want)), f"update {t}: reported rows"
+        C = want
+    P.destroy()
+    b.destroy()
+    a.destroy()
+
+
 def test_general_several_applies_fall_back(ctx):
     """Two applies before one update: the change log holds one apply, so the
     row path runs and F is built again -- same C and F as the oracle."""
