@@ -166,17 +166,25 @@ __global__ void k_pat_reduce(const uint64_t* keys, int64_t n, const int64_t* hea
   atomicOr(&fstar[s], (unsigned long long)bloom_bit((int32_t)(keys[t] & 63u)));
 }
 
-// columns of C* and the heads of its rows
-__global__ void k_cs_rows_heads(const uint64_t* cs_key, int64_t n, int cb, int32_t* cs_col, int64_t* rhead) {
+// columns of C* and the heads of its rows (*d_n entries of C*, a grid over
+// cap >= *d_n: the heads past the entries are zero, so a scan over cap
+// counts the rows)
+__global__ void k_cs_rows_heads(const uint64_t* cs_key, const int64_t* d_n, int64_t cap, int cb, int32_t* cs_col,
+                                int64_t* rhead) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+  if (s >= cap) return;
+  if (s >= *d_n) {
+    rhead[s] = 0;
+    return;
+  }
   cs_col[s] = (int32_t)(cs_key[s] & ((1ull << cb) - 1));
   rhead[s] = (s == 0 || (cs_key[s] >> cb) != (cs_key[s - 1] >> cb)) ? 1 : 0;
 }
 
-__global__ void k_cs_rows(const uint64_t* cs_key, int64_t n, int cb, const int64_t* rhead, const int64_t* rid,
+__global__ void k_cs_rows(const uint64_t* cs_key, const int64_t* d_n, int cb, const int64_t* rhead, const int64_t* rid,
                           int32_t* row_id, int64_t* row_start) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = *d_n;
   if (s >= n) return;
   if (rhead[s]) {
     row_id[rid[s]] = (int32_t)(cs_key[s] >> cb);
@@ -888,19 +896,26 @@ int32_t general_update(DProd* p) {
     radix_sort_pairs(keys, idx, nterm, rb + cb + 6, rscr, s, err);
     // C* and F*
     hipLaunchKernelGGL(k_pat_heads, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, keys, nterm, head);
-    exclusive_scan_i64(head, segid, nterm, d_total, scan2, s);
-    ncs = read_i64(c, d_total);
-    hipLaunchKernelGGL(k_fill_acc<uint64_t>, dim3(blocks_for(ncs, 256)), dim3(256), 0, s, (uint64_t*)cs_key,
-                       fstar, ncs, 0ull);
+    // (the entry count stays on the device until the rows are counted too:
+    // one round trip for both; grids over the terms, an upper bound)
+    int64_t* d_ncs = d_total;
+    int64_t* d_nrow = d_total + 1;
+    exclusive_scan_i64(head, segid, nterm, d_ncs, scan2, s);
+    hipLaunchKernelGGL(k_fill_acc<uint64_t>, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, (uint64_t*)cs_key,
+                       fstar, nterm, 0ull);
     hipLaunchKernelGGL(k_pat_reduce, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, keys, nterm,
                        (const int64_t*)head, (const int64_t*)segid, cs_key, fstar);
     // the rows of C*
-    hipLaunchKernelGGL(k_cs_rows_heads, dim3(blocks_for(ncs, 256)), dim3(256), 0, s, (const uint64_t*)cs_key, ncs, cb,
-                       cs_col, rhead);
-    exclusive_scan_i64(rhead, rid, ncs, d_total, scan2, s);
-    hipLaunchKernelGGL(k_cs_rows, dim3(blocks_for(ncs, 256)), dim3(256), 0, s, (const uint64_t*)cs_key, ncs, cb,
-                       (const int64_t*)rhead, (const int64_t*)rid, row_id, row_start);
-    nrow = read_i64(c, d_total);
+    hipLaunchKernelGGL(k_cs_rows_heads, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, (const uint64_t*)cs_key,
+                       (const int64_t*)d_ncs, nterm, cb, cs_col, rhead);
+    exclusive_scan_i64(rhead, rid, nterm, d_nrow, scan2, s);
+    hipLaunchKernelGGL(k_cs_rows, dim3(blocks_for(nterm, 256)), dim3(256), 0, s, (const uint64_t*)cs_key,
+                       (const int64_t*)d_ncs, cb, (const int64_t*)rhead, (const int64_t*)rid, row_id, row_start);
+    int64_t* hn = (int64_t*)((char*)c->pinned + 3072);
+    DSG_HIP(hipMemcpyAsync(hn, d_total, 16, hipMemcpyDeviceToHost, s));
+    DSG_HIP(hipStreamSynchronize(s));
+    ncs = hn[0];
+    nrow = hn[1];
   }
   st.entries = ncs;
   st.affected_rows = nrow;
